@@ -1,0 +1,984 @@
+/*
+ * Plain, slow, obviously correct CPU reference of the RNSM merge path.
+ *
+ * TEST INFRASTRUCTURE ONLY. The product library never links, calls or
+ * executes this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark do. It shares no code with the HIP path.
+ *
+ * All distances are computed in double precision from the original float32
+ * values. Everything is single-threaded and deterministic. Functions follow
+ * the paper (arXiv 2602.17099) in its own order and notation:
+ *
+ *   beam search ............ Algorithm 1 (Section 2.2)
+ *   edge selection prune ... RNG / heuristic edge selection (Section 2.2,
+ *                            Section 4.2 "UpdateGraph", Section 5 execution)
+ *   RNSM pairwise merge .... Algorithm 2 (Section 4.2): neighbor expansion,
+ *                            reverse inversion, lazy greedy pivots, naive
+ *                            search, local sliding, graph update with
+ *                            reverse edges
+ *   MOS .................... Algorithm 3 (Section 5)
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   - key order is (distance, global id), ascending, everywhere;
+ *   - the prune drops v when some kept w has alpha*d(w,v) < d(p,v) (strict),
+ *     stops at R kept, never backfills; alpha is rounded to float32 first and
+ *     the product is formed in double;
+ *   - searches keep a visited set (Algorithm 1 says "unexpanded neighbor");
+ *   - a follower is seeded with every id of its pivot's final beam;
+ *   - searches of every operation read only the input sub-index graphs;
+ *   - the source of an operation is the smaller sub-index (ties: lower index).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "rnsm_oracle.h"
+
+/* ------------------------------------------------------------------ */
+/* distances (the paper's delta; L2 is its default, Section 2.1)       */
+/* ------------------------------------------------------------------ */
+
+double orc_dist_vec(const float* a, const float* b, int dim, int metric,
+                    double na, double nb) {
+    if (metric == ORC_L2SQ) {
+        double s = 0.0;
+        for (int j = 0; j < dim; ++j) {
+            double t = (double)a[j] - (double)b[j];
+            s += t * t;
+        }
+        return s;
+    }
+    double dot = 0.0;
+    for (int j = 0; j < dim; ++j) dot += (double)a[j] * (double)b[j];
+    if (metric == ORC_IP) return 1.0 - dot;
+    /* cosine */
+    return 1.0 - dot / (na * nb);
+}
+
+void orc_norms(const float* X, int64_t n, int dim, double* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < dim; ++j) s += (double)X[i * dim + j] * (double)X[i * dim + j];
+        out[i] = sqrt(s);
+    }
+}
+
+typedef struct {
+    const float* X;      /* global rows [N x dim] */
+    int dim;
+    int metric;
+    const double* norms; /* [N], used for cosine only (may be NULL otherwise) */
+} space_t;
+
+static double dist_ids(const space_t* S, int64_t a, int64_t b) {
+    double na = S->norms ? S->norms[a] : 1.0, nb = S->norms ? S->norms[b] : 1.0;
+    return orc_dist_vec(S->X + a * S->dim, S->X + b * S->dim, S->dim, S->metric, na, nb);
+}
+
+/* (d, id) ascending */
+static int key_less(double da, int64_t ia, double db, int64_t ib) {
+    return da < db || (da == db && ia < ib);
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 1: beam search                                            */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double d;
+    int32_t id;      /* local id in the searched graph */
+    int expanded;
+} cand_t;
+
+/* visited set with a generation counter, reusable across searches */
+typedef struct {
+    uint32_t* stamp;
+    uint32_t gen;
+    int64_t n;
+} visited_t;
+
+static int visited_init(visited_t* v, int64_t n) {
+    v->stamp = (uint32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
+    v->gen = 0;
+    v->n = n;
+    return v->stamp != NULL;
+}
+static void visited_next(visited_t* v) {
+    if (++v->gen == 0) {
+        memset(v->stamp, 0, sizeof(uint32_t) * (size_t)v->n);
+        v->gen = 1;
+    }
+}
+
+/* insert keeping C sorted by (d, global id); C has room for cap entries */
+static void cand_insert(cand_t* C, int* size, double d, int32_t id, int64_t base) {
+    int i = *size;
+    while (i > 0 && key_less(d, base + id, C[i - 1].d, base + C[i - 1].id)) {
+        C[i] = C[i - 1];
+        --i;
+    }
+    C[i].d = d;
+    C[i].id = id;
+    C[i].expanded = 0;
+    ++*size;
+}
+
+/*
+ * Beam search on one graph (Algorithm 1).
+ * G: n vertices, CSR (offsets, nbrs) with local ids; vertex v is global row
+ * base + v of S->X. The query is the vector q (with norm qn for cosine).
+ * C starts from the seeds (deduplicated, truncated to the ef best); the loop
+ * expands the nearest unexpanded entry, inserts its not-yet-visited
+ * out-neighbours, and truncates C back to ef, until every entry of C is
+ * expanded. Returns |C| and writes C in key order.
+ */
+static int beam_search(const space_t* S, int64_t n, const int64_t* offsets, const int32_t* nbrs,
+                       int64_t base, const float* q, double qn, const int32_t* seeds, int nseeds,
+                       int ef, visited_t* vis, int32_t* out_ids, double* out_d, int64_t* ndc,
+                       int64_t* n_expand) {
+    int maxdeg = 0;
+    (void)n;
+    /* capacity: ef + largest degree met; grow on demand */
+    int cap = ef + nseeds + 64;
+    cand_t* C = (cand_t*)malloc(sizeof(cand_t) * (size_t)cap);
+    int size = 0;
+    visited_next(vis);
+    int64_t nd = 0, ne = 0;
+
+    for (int i = 0; i < nseeds; ++i) {
+        int32_t s = seeds[i];
+        if (s < 0) continue;
+        if (vis->stamp[s] == vis->gen) continue; /* dedupe seeds */
+        vis->stamp[s] = vis->gen;
+        const float* x = S->X + (base + s) * S->dim;
+        double xn = S->norms ? S->norms[base + s] : 1.0;
+        double d = orc_dist_vec(q, x, S->dim, S->metric, qn, xn);
+        ++nd;
+        cand_insert(C, &size, d, s, base);
+    }
+    if (size > ef) size = ef;
+
+    for (;;) {
+        int u = -1;
+        for (int i = 0; i < size; ++i)
+            if (!C[i].expanded) { u = i; break; }
+        if (u < 0) break;
+        C[u].expanded = 1;
+        ++ne;
+        int32_t uid = C[u].id;
+        int64_t b = offsets[uid], e = offsets[uid + 1];
+        int deg = (int)(e - b);
+        if (deg > maxdeg) maxdeg = deg;
+        if (size + deg > cap) {
+            cap = size + deg + 64;
+            C = (cand_t*)realloc(C, sizeof(cand_t) * (size_t)cap);
+        }
+        for (int64_t j = b; j < e; ++j) {
+            int32_t v = nbrs[j];
+            if (vis->stamp[v] == vis->gen) continue;
+            vis->stamp[v] = vis->gen;
+            const float* x = S->X + (base + v) * S->dim;
+            double xn = S->norms ? S->norms[base + v] : 1.0;
+            double d = orc_dist_vec(q, x, S->dim, S->metric, qn, xn);
+            ++nd;
+            cand_insert(C, &size, d, v, base);
+        }
+        if (size > ef) size = ef;
+    }
+    for (int i = 0; i < size; ++i) {
+        out_ids[i] = C[i].id;
+        out_d[i] = C[i].d;
+    }
+    free(C);
+    if (ndc) *ndc += nd;
+    if (n_expand) *n_expand += ne;
+    return size;
+}
+
+int orc_beam_search(int64_t n, const int64_t* offsets, const int32_t* nbrs, int64_t base,
+                    const float* X, int dim, int metric, const double* norms,
+                    const float* q, const int32_t* seeds, int nseeds, int ef,
+                    int32_t* out_ids, double* out_d, int64_t* ndc) {
+    space_t S = {X, dim, metric, norms};
+    visited_t vis;
+    if (!visited_init(&vis, n)) return -1;
+    double qn = 1.0;
+    if (metric == ORC_COSINE) {
+        double s = 0.0;
+        for (int j = 0; j < dim; ++j) s += (double)q[j] * (double)q[j];
+        qn = sqrt(s);
+    }
+    int r = beam_search(&S, n, offsets, nbrs, base, q, qn, seeds, nseeds, ef, &vis, out_ids, out_d,
+                        ndc, NULL);
+    free(vis.stamp);
+    return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* Edge selection (RNG rule with alpha)                                */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double d;
+    int32_t id; /* global */
+} wkey_t;
+
+static int wkey_cmp(const void* a, const void* b) {
+    const wkey_t* x = (const wkey_t*)a;
+    const wkey_t* y = (const wkey_t*)b;
+    if (key_less(x->d, x->id, y->d, y->id)) return -1;
+    if (key_less(y->d, y->id, x->d, x->id)) return 1;
+    return 0;
+}
+
+/*
+ * Prune(p, W): sort the candidates by (d(p,.), id); walk them in order and
+ * keep v unless some already kept w satisfies alpha * d(w, v) < d(p, v);
+ * stop once R are kept. Duplicates and p itself are removed first.
+ */
+static int prune(const space_t* S, int64_t p, const int32_t* W, int nW, float alpha, int R,
+                 int32_t* out_ids, double* out_d) {
+    wkey_t* c = (wkey_t*)malloc(sizeof(wkey_t) * (size_t)(nW > 0 ? nW : 1));
+    int nc = 0;
+    for (int i = 0; i < nW; ++i) {
+        int32_t v = W[i];
+        if (v < 0 || v == p) continue;
+        int dup = 0;
+        for (int j = 0; j < nc; ++j)
+            if (c[j].id == v) { dup = 1; break; }
+        if (dup) continue;
+        c[nc].id = v;
+        c[nc].d = dist_ids(S, p, v);
+        ++nc;
+    }
+    qsort(c, (size_t)nc, sizeof(wkey_t), wkey_cmp);
+    const double a = (double)alpha; /* alpha already float32 */
+    int nk = 0;
+    for (int i = 0; i < nc && nk < R; ++i) {
+        int dominated = 0;
+        for (int j = 0; j < nk; ++j) {
+            double dwv = dist_ids(S, out_ids[j], c[i].id);
+            if (a * dwv < c[i].d) { dominated = 1; break; }
+        }
+        if (!dominated) {
+            out_ids[nk] = c[i].id;
+            out_d[nk] = c[i].d;
+            ++nk;
+        }
+    }
+    free(c);
+    return nk;
+}
+
+int orc_prune(int64_t p, const int32_t* W, int nW, const float* X, int dim, int metric,
+              const double* norms, float alpha, int R, int32_t* out_ids, double* out_d) {
+    space_t S = {X, dim, metric, norms};
+    return prune(&S, p, W, nW, alpha, R, out_ids, out_d);
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 2, phase 1: neighbor expansion and reverse inversion      */
+/* ------------------------------------------------------------------ */
+
+/*
+ * N_k(v): beam search in the source graph from v itself with effort k+,
+ * keep the first k results other than v. nk_out is [n x k], -1 padded.
+ */
+static int expand_neighbors(const space_t* S, int64_t n, const int64_t* offsets,
+                            const int32_t* nbrs, int64_t base, int k, int kplus,
+                            int32_t* nk_out, int64_t* ndc) {
+    visited_t vis;
+    if (!visited_init(&vis, n)) return -1;
+    int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)kplus);
+    double* ds = (double*)malloc(sizeof(double) * (size_t)kplus);
+    for (int64_t v = 0; v < n; ++v) {
+        int32_t seed = (int32_t)v;
+        const float* q = S->X + (base + v) * S->dim;
+        double qn = S->norms ? S->norms[base + v] : 1.0;
+        int c = beam_search(S, n, offsets, nbrs, base, q, qn, &seed, 1, kplus, &vis, ids, ds, ndc,
+                            NULL);
+        int t = 0;
+        for (int i = 0; i < c && t < k; ++i)
+            if (ids[i] != v) nk_out[v * k + t++] = ids[i];
+        for (; t < k; ++t) nk_out[v * k + t] = -1;
+    }
+    free(ids);
+    free(ds);
+    free(vis.stamp);
+    return 0;
+}
+
+int orc_expand(int64_t n, const int64_t* offsets, const int32_t* nbrs, int64_t base,
+               const float* X, int dim, int metric, const double* norms, int k, int kplus,
+               int32_t* nk_out) {
+    space_t S = {X, dim, metric, norms};
+    return expand_neighbors(&S, n, offsets, nbrs, base, k, kplus, nk_out, NULL);
+}
+
+/* R_k(x) = { y : x in N_k(y) }, each list in ascending id order. */
+int orc_invert(int64_t n, const int32_t* nk, int k, int64_t* rk_off, int32_t* rk_ids) {
+    for (int64_t i = 0; i <= n; ++i) rk_off[i] = 0;
+    for (int64_t y = 0; y < n; ++y)
+        for (int j = 0; j < k; ++j) {
+            int32_t x = nk[y * k + j];
+            if (x >= 0) rk_off[x + 1]++;
+        }
+    for (int64_t i = 0; i < n; ++i) rk_off[i + 1] += rk_off[i];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) fill[i] = rk_off[i];
+    for (int64_t y = 0; y < n; ++y) /* y ascending => every list sorted */
+        for (int j = 0; j < k; ++j) {
+            int32_t x = nk[y * k + j];
+            if (x >= 0) rk_ids[fill[x]++] = (int32_t)y;
+        }
+    free(fill);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 2, phase 2: lazy greedy pivot selection                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t g;
+    int32_t x;
+} hent_t;
+
+/* max-heap on gain, ties: smaller id first */
+static int hent_above(hent_t a, hent_t b) { return a.g > b.g || (a.g == b.g && a.x < b.x); }
+
+static void heap_push(hent_t* h, int64_t* n, hent_t e) {
+    int64_t i = (*n)++;
+    h[i] = e;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (!hent_above(h[i], h[p])) break;
+        hent_t t = h[i]; h[i] = h[p]; h[p] = t;
+        i = p;
+    }
+}
+
+static hent_t heap_pop(hent_t* h, int64_t* n) {
+    hent_t top = h[0];
+    h[0] = h[--*n];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < *n && hent_above(h[l], h[m])) m = l;
+        if (r < *n && hent_above(h[r], h[m])) m = r;
+        if (m == i) break;
+        hent_t t = h[i]; h[i] = h[m]; h[m] = t;
+        i = m;
+    }
+    return top;
+}
+
+/*
+ * Heap of (|R_k(x)|, x). Pop the top; drop it when x is covered; when the
+ * gain |R_k(x) \ Covered| fell below the stored key, push it back with the
+ * new gain; otherwise x becomes a pivot with followers F_x = R_k(x) \ Covered
+ * and Covered grows by {x} and R_k(x).
+ * pivot_of[y] = x for a follower y of x, -1 for a pivot.
+ * order[0..*n_piv) lists the pivots in selection order.
+ */
+int orc_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivot_of,
+               int32_t* order, int64_t* n_piv) {
+    hent_t* h = (hent_t*)malloc(sizeof(hent_t) * (size_t)(n > 0 ? n : 1));
+    char* covered = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t hn = 0, np = 0;
+    for (int64_t x = 0; x < n; ++x) {
+        hent_t e = {rk_off[x + 1] - rk_off[x], (int32_t)x};
+        heap_push(h, &hn, e);
+    }
+    for (int64_t i = 0; i < n; ++i) pivot_of[i] = -2; /* unassigned */
+    while (hn > 0) {
+        hent_t e = heap_pop(h, &hn);
+        int32_t x = e.x;
+        if (covered[x]) continue;
+        int64_t g = 0;
+        for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j)
+            if (!covered[rk_ids[j]]) ++g;
+        if (g < e.g) {
+            hent_t r = {g, x};
+            heap_push(h, &hn, r);
+            continue;
+        }
+        for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) {
+            int32_t y = rk_ids[j];
+            if (!covered[y]) pivot_of[y] = x;
+        }
+        pivot_of[x] = -1;
+        order[np++] = x;
+        covered[x] = 1;
+        for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) covered[rk_ids[j]] = 1;
+    }
+    *n_piv = np;
+    free(h);
+    free(covered);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 3: merge order selection                                  */
+/* ------------------------------------------------------------------ */
+
+#define HOP_INF 0x3fffffff
+
+static void mos_hops(int m, const char* adj, int* H) {
+    int* q = (int*)malloc(sizeof(int) * (size_t)m);
+    for (int s = 0; s < m; ++s) {
+        for (int t = 0; t < m; ++t) H[s * m + t] = HOP_INF;
+        H[s * m + s] = 0;
+        int qh = 0, qt = 0;
+        q[qt++] = s;
+        while (qh < qt) {
+            int u = q[qh++];
+            for (int v = 0; v < m; ++v)
+                if (adj[u * m + v] && H[s * m + v] == HOP_INF) {
+                    H[s * m + v] = H[s * m + u] + 1;
+                    q[qt++] = v;
+                }
+        }
+    }
+    free(q);
+}
+
+/* cost matrix: Euclidean distance of centroids, or 1 for every pair when
+ * centroids is NULL (random partitions) */
+void orc_mos_cost(int m, const double* centroids, int dim, double* C) {
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            if (i == j) { C[i * m + j] = 0.0; continue; }
+            if (!centroids) { C[i * m + j] = 1.0; continue; }
+            double s = 0.0;
+            for (int t = 0; t < dim; ++t) {
+                double d = centroids[i * dim + t] - centroids[j * dim + t];
+                s += d * d;
+            }
+            C[i * m + j] = sqrt(s);
+        }
+}
+
+/*
+ * Vertices are visited in ascending order of their mean cost to their
+ * min(R, m-1) nearest others (ties: index). For each v, while some x lies
+ * more than delta hops away, take the cheapest such x (ties: index):
+ * both below the degree bound -> edge (v,x); x saturated -> relay to the
+ * cheapest unsaturated neighbour x' of x, edge (v,x'); v saturated -> relay
+ * from the cheapest unsaturated neighbour v' of v, edge (v',x); otherwise, or
+ * when no relay exists, edge (v,x) as a counted fallback. Hops are recomputed
+ * by BFS after each edge. Edges are written in insertion order.
+ * Requires delta >= 2 (a relay puts x within two hops of v).
+ */
+int orc_mos(int m, const double* C, int R, int delta, int32_t* out_edges, int cap,
+            int* n_edges, int* n_fallback) {
+    if (m < 1 || R < 1 || delta < 2) return -1;
+    char* adj = (char*)calloc((size_t)m * m, 1);
+    int* H = (int*)malloc(sizeof(int) * (size_t)m * m);
+    int* deg = (int*)calloc((size_t)m, sizeof(int));
+    int* order = (int*)malloc(sizeof(int) * (size_t)m);
+    double* avg = (double*)malloc(sizeof(double) * (size_t)m);
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)m);
+    int ne = 0, nf = 0;
+    int r = R < m - 1 ? R : m - 1;
+    for (int i = 0; i < m; ++i) {
+        int t = 0;
+        for (int j = 0; j < m; ++j)
+            if (j != i) tmp[t++] = C[i * m + j];
+        /* partial selection sort of the r smallest */
+        double s = 0.0;
+        for (int a = 0; a < r; ++a) {
+            int best = a;
+            for (int b = a + 1; b < t; ++b)
+                if (tmp[b] < tmp[best]) best = b;
+            double x = tmp[a]; tmp[a] = tmp[best]; tmp[best] = x;
+            s += tmp[a];
+        }
+        avg[i] = r > 0 ? s / r : 0.0;
+        order[i] = i;
+    }
+    for (int a = 1; a < m; ++a) { /* stable insertion sort by (avg, index) */
+        int v = order[a], b = a;
+        while (b > 0 && avg[order[b - 1]] > avg[v]) { order[b] = order[b - 1]; --b; }
+        order[b] = v;
+    }
+    mos_hops(m, adj, H);
+    for (int oi = 0; oi < m; ++oi) {
+        int v = order[oi];
+        for (;;) {
+            int x = -1;
+            for (int c = 0; c < m; ++c) {
+                if (c == v || H[v * m + c] <= delta) continue;
+                if (x < 0 || C[v * m + c] < C[v * m + x]) x = c;
+            }
+            if (x < 0) break;
+            int a = v, b = x, fallback = 0;
+            if (deg[v] < R && deg[x] < R) {
+                /* direct edge */
+            } else if (deg[v] < R && deg[x] >= R) {
+                int best = -1;
+                for (int c = 0; c < m; ++c)
+                    if (adj[x * m + c] && c != v && deg[c] < R &&
+                        (best < 0 || C[c * m + v] < C[best * m + v]))
+                        best = c;
+                if (best >= 0) b = best; else fallback = 1;
+            } else if (deg[v] >= R && deg[x] < R) {
+                int best = -1;
+                for (int c = 0; c < m; ++c)
+                    if (adj[v * m + c] && c != x && deg[c] < R &&
+                        (best < 0 || C[c * m + x] < C[best * m + x]))
+                        best = c;
+                if (best >= 0) a = best; else fallback = 1;
+            } else {
+                fallback = 1;
+            }
+            if (ne >= cap) { ne = -1; break; }
+            adj[a * m + b] = adj[b * m + a] = 1;
+            deg[a]++; deg[b]++;
+            out_edges[2 * ne] = a;
+            out_edges[2 * ne + 1] = b;
+            ++ne;
+            nf += fallback;
+            mos_hops(m, adj, H);
+        }
+        if (ne < 0) break;
+    }
+    *n_edges = ne;
+    *n_fallback = nf;
+    free(adj); free(H); free(deg); free(order); free(avg); free(tmp);
+    return ne < 0 ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 2, phase 3 + graph update, for one operation s -> t        */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n, base;
+    const int64_t* offsets;
+    const int32_t* nbrs;
+    int32_t entry;
+} sub_t;
+
+typedef struct {
+    int32_t* rows;  /* [N x R] global ids */
+    double* dists;  /* [N x R] */
+    int32_t* deg;   /* [N] */
+    int R;
+} rows_t;
+
+static int64_t g_ndc_expand, g_ndc_naive, g_ndc_slide;
+
+static int pair_op(const space_t* S, const sub_t* s, const sub_t* t, const rows_t* rows,
+                   const orc_params_t* P, const int32_t* pivot_of, const int32_t* piv_order,
+                   int64_t n_piv, int32_t* trace_res_ids, double* trace_res_d) {
+    const int L = P->ef_naive, EL = P->ef_slide, R = P->R;
+    const int RES = L > EL ? L : EL;
+    int32_t* res_ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->n * RES));
+    double* res_d = (double*)malloc(sizeof(double) * (size_t)(s->n * RES));
+    int* res_n = (int*)calloc((size_t)s->n, sizeof(int));
+    visited_t vis;
+    if (!res_ids || !res_d || !res_n || !visited_init(&vis, t->n)) return -1;
+
+    /* naive search of every pivot from the target's default entry point */
+    for (int64_t i = 0; i < n_piv; ++i) {
+        int64_t p = piv_order[i];
+        const float* q = S->X + (s->base + p) * S->dim;
+        double qn = S->norms ? S->norms[s->base + p] : 1.0;
+        res_n[p] = beam_search(S, t->n, t->offsets, t->nbrs, t->base, q, qn, &t->entry, 1, L, &vis,
+                               res_ids + p * RES, res_d + p * RES, &g_ndc_naive, NULL);
+    }
+    /* local sliding of every follower from its pivot's results */
+    for (int64_t y = 0; y < s->n; ++y) {
+        int32_t p = pivot_of[y];
+        if (p < 0) continue;
+        const float* q = S->X + (s->base + y) * S->dim;
+        double qn = S->norms ? S->norms[s->base + y] : 1.0;
+        res_n[y] = beam_search(S, t->n, t->offsets, t->nbrs, t->base, q, qn, res_ids + (int64_t)p * RES,
+                               res_n[p], EL, &vis, res_ids + y * RES, res_d + y * RES,
+                               &g_ndc_slide, NULL);
+    }
+    if (trace_res_ids) {
+        for (int64_t y = 0; y < s->n; ++y)
+            for (int j = 0; j < RES; ++j) {
+                trace_res_ids[y * RES + j] = j < res_n[y] ? res_ids[y * RES + j] : -1;
+                trace_res_d[y * RES + j] = j < res_n[y] ? res_d[y * RES + j] : INFINITY;
+            }
+    }
+
+    /* source update: concatenate with the current row, prune to R */
+    int32_t* W = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + RES + 1));
+    for (int64_t u = 0; u < s->n; ++u) {
+        int64_t gu = s->base + u;
+        int nw = 0;
+        for (int j = 0; j < rows->deg[gu]; ++j) W[nw++] = rows->rows[gu * R + j];
+        for (int j = 0; j < res_n[u]; ++j) W[nw++] = (int32_t)(t->base + res_ids[u * RES + j]);
+        rows->deg[gu] = prune(S, gu, W, nw, P->alpha, R, rows->rows + gu * R, rows->dists + gu * R);
+    }
+    free(W);
+
+    /* reverse edges: every kept u -> v with v in the target */
+    int64_t* rcnt = (int64_t*)calloc((size_t)(t->n + 1), sizeof(int64_t));
+    for (int64_t u = 0; u < s->n; ++u) {
+        int64_t gu = s->base + u;
+        for (int j = 0; j < rows->deg[gu]; ++j) {
+            int64_t v = rows->rows[gu * R + j] - t->base;
+            if (v >= 0 && v < t->n) rcnt[v + 1]++;
+        }
+    }
+    for (int64_t v = 0; v < t->n; ++v) rcnt[v + 1] += rcnt[v];
+    int32_t* rev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(rcnt[t->n] > 0 ? rcnt[t->n] : 1));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(t->n > 0 ? t->n : 1));
+    for (int64_t v = 0; v < t->n; ++v) fill[v] = rcnt[v];
+    for (int64_t u = 0; u < s->n; ++u) {
+        int64_t gu = s->base + u;
+        for (int j = 0; j < rows->deg[gu]; ++j) {
+            int64_t v = rows->rows[gu * R + j] - t->base;
+            if (v >= 0 && v < t->n) rev[fill[v]++] = (int32_t)gu;
+        }
+    }
+    int maxrev = 0;
+    for (int64_t v = 0; v < t->n; ++v)
+        if (rcnt[v + 1] - rcnt[v] > maxrev) maxrev = (int)(rcnt[v + 1] - rcnt[v]);
+    int32_t* W2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + maxrev + 1));
+    for (int64_t v = 0; v < t->n; ++v) {
+        if (rcnt[v + 1] == rcnt[v]) continue;
+        int64_t gv = t->base + v;
+        int nw = 0;
+        for (int j = 0; j < rows->deg[gv]; ++j) W2[nw++] = rows->rows[gv * R + j];
+        for (int64_t j = rcnt[v]; j < rcnt[v + 1]; ++j) W2[nw++] = rev[j];
+        rows->deg[gv] = prune(S, gv, W2, nw, P->alpha, R, rows->rows + gv * R, rows->dists + gv * R);
+    }
+    free(W2); free(rev); free(fill); free(rcnt);
+    free(res_ids); free(res_d); free(res_n); free(vis.stamp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Whole merge: MOS plan, operation order, sequential operations        */
+/* ------------------------------------------------------------------ */
+
+int orc_merge(int m, const int64_t* sizes, const int64_t* offsets_cat, const int32_t* nbrs_cat,
+              const int32_t* entries, const float* X, int dim, const orc_params_t* P,
+              int32_t* out_rows, double* out_dists, int32_t* out_deg, int32_t* out_entry,
+              int32_t* out_ops, int* out_nops, orc_trace_t* trace) {
+    if (m < 1 || P->R < 1 || P->ef_naive < 1 || P->ef_slide < 1 || P->k < 1 || P->kplus < P->k)
+        return -1;
+    const int R = P->R;
+    int64_t N = 0;
+    sub_t* subs = (sub_t*)malloc(sizeof(sub_t) * (size_t)m);
+    int64_t ooff = 0, noff = 0;
+    for (int i = 0; i < m; ++i) {
+        subs[i].n = sizes[i];
+        subs[i].base = N;
+        subs[i].offsets = offsets_cat + ooff;
+        subs[i].nbrs = nbrs_cat + noff;
+        subs[i].entry = entries[i];
+        noff += subs[i].offsets[sizes[i]];
+        ooff += sizes[i] + 1;
+        N += sizes[i];
+    }
+    double* norms = NULL;
+    if (P->metric == ORC_COSINE) {
+        norms = (double*)malloc(sizeof(double) * (size_t)N);
+        orc_norms(X, N, dim, norms);
+    }
+    space_t S = {X, dim, P->metric, norms};
+    rows_t rows = {out_rows, out_dists, out_deg, R};
+    /* rows start as the input rows in global ids */
+    for (int i = 0; i < m; ++i)
+        for (int64_t v = 0; v < subs[i].n; ++v) {
+            int64_t g = subs[i].base + v;
+            int64_t b = subs[i].offsets[v], e = subs[i].offsets[v + 1];
+            if (e - b > R) { free(subs); free(norms); return -2; }
+            out_deg[g] = (int32_t)(e - b);
+            for (int64_t j = b; j < e; ++j) {
+                out_rows[g * R + (j - b)] = (int32_t)(subs[i].base + subs[i].nbrs[j]);
+                out_dists[g * R + (j - b)] = dist_ids(&S, g, subs[i].base + subs[i].nbrs[j]);
+            }
+        }
+
+    /* plan */
+    double* C = (double*)malloc(sizeof(double) * (size_t)m * m);
+    double* cent = NULL;
+    if (P->use_centroids) {
+        cent = (double*)calloc((size_t)m * dim, sizeof(double));
+        for (int i = 0; i < m; ++i) {
+            for (int64_t v = 0; v < subs[i].n; ++v)
+                for (int t = 0; t < dim; ++t)
+                    cent[i * dim + t] += (double)X[(subs[i].base + v) * dim + t];
+            for (int t = 0; t < dim; ++t) cent[i * dim + t] /= (double)subs[i].n;
+        }
+    }
+    orc_mos_cost(m, cent, dim, C);
+    int rmos = P->mos_degree;
+    if (rmos <= 0) {
+        rmos = (int)ceil(sqrt((double)m));
+        if (rmos < 2) rmos = 2;
+    }
+    int cap = m * m, ne = 0, nf = 0;
+    int32_t* edges = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)cap);
+    if (m >= 2) {
+        if (orc_mos(m, C, rmos, P->mos_diameter, edges, cap, &ne, &nf) != 0) {
+            free(subs); free(norms); free(C); free(cent); free(edges);
+            return -3;
+        }
+    }
+    /* execution order: ascending (cost, min index, max index) */
+    for (int a = 1; a < ne; ++a) {
+        int32_t e0 = edges[2 * a], e1 = edges[2 * a + 1];
+        int i0 = e0 < e1 ? e0 : e1, j0 = e0 < e1 ? e1 : e0;
+        int b = a;
+        while (b > 0) {
+            int32_t f0 = edges[2 * (b - 1)], f1 = edges[2 * (b - 1) + 1];
+            int i1 = f0 < f1 ? f0 : f1, j1 = f0 < f1 ? f1 : f0;
+            double c0 = C[i0 * m + j0], c1 = C[i1 * m + j1];
+            int later = c1 > c0 || (c1 == c0 && (i1 > i0 || (i1 == i0 && j1 > j0)));
+            if (!later) break;
+            edges[2 * b] = edges[2 * (b - 1)];
+            edges[2 * b + 1] = edges[2 * (b - 1) + 1];
+            --b;
+        }
+        edges[2 * b] = i0;
+        edges[2 * b + 1] = j0;
+    }
+    /* normalise every edge to (min, max) for the first element too */
+    for (int a = 0; a < ne; ++a) {
+        int32_t e0 = edges[2 * a], e1 = edges[2 * a + 1];
+        edges[2 * a] = e0 < e1 ? e0 : e1;
+        edges[2 * a + 1] = e0 < e1 ? e1 : e0;
+    }
+    /* direction: the smaller sub-index is the source; ties: lower index */
+    for (int a = 0; a < ne; ++a) {
+        int i = edges[2 * a], j = edges[2 * a + 1];
+        int src = (sizes[j] < sizes[i]) ? j : i;
+        int dst = src == i ? j : i;
+        out_ops[2 * a] = src;
+        out_ops[2 * a + 1] = dst;
+    }
+    *out_nops = ne;
+
+    /* expansion, inversion and pivots, once per source sub-index, from its
+     * input graph */
+    int32_t** piv_of = (int32_t**)calloc((size_t)m, sizeof(int32_t*));
+    int32_t** piv_ord = (int32_t**)calloc((size_t)m, sizeof(int32_t*));
+    int64_t* npiv = (int64_t*)calloc((size_t)m, sizeof(int64_t));
+    g_ndc_expand = g_ndc_naive = g_ndc_slide = 0;
+    int rc = 0;
+    for (int a = 0; a < ne && rc == 0; ++a) {
+        int si = out_ops[2 * a];
+        if (piv_of[si]) continue;
+        const sub_t* s = &subs[si];
+        int32_t* nk = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->n * P->k));
+        int64_t* rko = (int64_t*)malloc(sizeof(int64_t) * (size_t)(s->n + 1));
+        int32_t* rki = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->n * P->k + 1));
+        piv_of[si] = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->n > 0 ? s->n : 1));
+        piv_ord[si] = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->n > 0 ? s->n : 1));
+        if (expand_neighbors(&S, s->n, s->offsets, s->nbrs, s->base, P->k, P->kplus, nk,
+                             &g_ndc_expand) != 0)
+            rc = -4;
+        orc_invert(s->n, nk, P->k, rko, rki);
+        if (P->all_pivots) {
+            for (int64_t v = 0; v < s->n; ++v) { piv_of[si][v] = -1; piv_ord[si][v] = (int32_t)v; }
+            npiv[si] = s->n;
+        } else {
+            orc_pivots(s->n, rko, rki, piv_of[si], piv_ord[si], &npiv[si]);
+        }
+        if (trace && a == 0) {
+            if (trace->nk) memcpy(trace->nk, nk, sizeof(int32_t) * (size_t)(s->n * P->k));
+            if (trace->pivot_of) memcpy(trace->pivot_of, piv_of[si], sizeof(int32_t) * (size_t)s->n);
+        }
+        free(nk); free(rko); free(rki);
+    }
+    for (int a = 0; a < ne && rc == 0; ++a) {
+        int si = out_ops[2 * a], ti = out_ops[2 * a + 1];
+        int32_t* tri = (trace && a == 0) ? trace->res_ids : NULL;
+        double* trd = (trace && a == 0) ? trace->res_d : NULL;
+        if (pair_op(&S, &subs[si], &subs[ti], &rows, P, piv_of[si], piv_ord[si], npiv[si], tri,
+                    trd) != 0)
+            rc = -5;
+    }
+    /* merged entry: the entry of the largest sub-index (ties: lowest index) */
+    int big = 0;
+    for (int i = 1; i < m; ++i)
+        if (sizes[i] > sizes[big]) big = i;
+    *out_entry = (int32_t)(subs[big].base + subs[big].entry);
+    if (trace) {
+        trace->ndc_expand = g_ndc_expand;
+        trace->ndc_naive = g_ndc_naive;
+        trace->ndc_slide = g_ndc_slide;
+        trace->n_pivots = ne > 0 ? npiv[out_ops[0]] : 0;
+    }
+    for (int i = 0; i < m; ++i) { free(piv_of[i]); free(piv_ord[i]); }
+    free(piv_of); free(piv_ord); free(npiv);
+    free(subs); free(norms); free(C); free(cent); free(edges);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sub-index builder (inputs) and exact k-NN                            */
+/* ------------------------------------------------------------------ */
+
+/* exact K nearest neighbours of every row of X (excluding itself) by
+ * (d, id), brute force. out [n x K] local ids, -1 padded when n-1 < K */
+int orc_knn(int64_t n, const float* X, int dim, int metric, int K, int32_t* out) {
+    double* norms = NULL;
+    if (metric == ORC_COSINE) {
+        norms = (double*)malloc(sizeof(double) * (size_t)n);
+        orc_norms(X, n, dim, norms);
+    }
+    space_t S = {X, dim, metric, norms};
+    wkey_t* c = (wkey_t*)malloc(sizeof(wkey_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t v = 0; v < n; ++v) {
+        int nc = 0;
+        for (int64_t u = 0; u < n; ++u) {
+            if (u == v) continue;
+            c[nc].id = (int32_t)u;
+            c[nc].d = dist_ids(&S, v, u);
+            ++nc;
+        }
+        qsort(c, (size_t)nc, sizeof(wkey_t), wkey_cmp);
+        for (int j = 0; j < K; ++j) out[v * K + j] = j < nc ? c[j].id : -1;
+    }
+    free(c);
+    free(norms);
+    return 0;
+}
+
+/* exact top-K of the rows of X for external queries Q, by (d, id) */
+int orc_knn_queries(int64_t n, const float* X, int64_t nq, const float* Q, int dim, int metric,
+                    int K, int32_t* out_ids, double* out_d) {
+    wkey_t* c = (wkey_t*)malloc(sizeof(wkey_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < nq; ++i) {
+        const float* q = Q + i * dim;
+        double qn = 1.0;
+        if (metric == ORC_COSINE) {
+            double s = 0.0;
+            for (int j = 0; j < dim; ++j) s += (double)q[j] * (double)q[j];
+            qn = sqrt(s);
+        }
+        for (int64_t u = 0; u < n; ++u) {
+            double un = 1.0;
+            if (metric == ORC_COSINE) {
+                double s = 0.0;
+                for (int j = 0; j < dim; ++j) s += (double)X[u * dim + j] * (double)X[u * dim + j];
+                un = sqrt(s);
+            }
+            c[u].id = (int32_t)u;
+            c[u].d = orc_dist_vec(q, X + u * dim, dim, metric, qn, un);
+        }
+        qsort(c, (size_t)n, sizeof(wkey_t), wkey_cmp);
+        for (int j = 0; j < K; ++j) {
+            out_ids[i * K + j] = j < n ? c[j].id : -1;
+            out_d[i * K + j] = j < n ? c[j].d : INFINITY;
+        }
+    }
+    free(c);
+    return 0;
+}
+
+/*
+ * Builder: row(v) = Prune(v, kNN(v), alpha, R). With reverse != 0, every
+ * kept edge v -> w also offers v to w, and every w that received an offer is
+ * pruned again over row(w) + offers, with alpha_rev. Entry: the vertex closest
+ * to the centroid (exact integer criterion sum_j (n x_j - S_j)^2 when every
+ * value is an integer, double precision otherwise), ties by id.
+ * out_nbrs has room for n x R ids; out_offsets n+1.
+ */
+int orc_build(int64_t n, const float* X, int dim, int metric, const int32_t* knn, int K, int R,
+              float alpha, int reverse, float alpha_rev, int64_t* out_offsets, int32_t* out_nbrs,
+              int32_t* out_entry) {
+    double* norms = NULL;
+    if (metric == ORC_COSINE) {
+        norms = (double*)malloc(sizeof(double) * (size_t)n);
+        orc_norms(X, n, dim, norms);
+    }
+    space_t S = {X, dim, metric, norms};
+    int32_t* rows = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n * R + 1));
+    double* rd = (double*)malloc(sizeof(double) * (size_t)(n * R + 1));
+    int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t* W = (int32_t*)malloc(sizeof(int32_t) * (size_t)(K + 1));
+    for (int64_t v = 0; v < n; ++v) {
+        int nw = 0;
+        for (int j = 0; j < K; ++j)
+            if (knn[v * K + j] >= 0) W[nw++] = knn[v * K + j];
+        deg[v] = prune(&S, v, W, nw, alpha, R, rows + v * R, rd + v * R);
+    }
+    free(W);
+    if (reverse) {
+        int64_t* cnt = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
+        for (int64_t v = 0; v < n; ++v)
+            for (int j = 0; j < deg[v]; ++j) cnt[rows[v * R + j] + 1]++;
+        for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+        int32_t* rev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(cnt[n] + 1));
+        int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        for (int64_t v = 0; v < n; ++v) fill[v] = cnt[v];
+        for (int64_t v = 0; v < n; ++v)
+            for (int j = 0; j < deg[v]; ++j) rev[fill[rows[v * R + j]]++] = (int32_t)v;
+        int maxr = 0;
+        for (int64_t v = 0; v < n; ++v)
+            if (cnt[v + 1] - cnt[v] > maxr) maxr = (int)(cnt[v + 1] - cnt[v]);
+        /* every offer is read from the rows of the first pass */
+        int32_t* rows2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n * R + 1));
+        int32_t* deg2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+        int32_t* W2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + maxr + 1));
+        for (int64_t w = 0; w < n; ++w) {
+            if (cnt[w + 1] == cnt[w]) {
+                deg2[w] = deg[w];
+                memcpy(rows2 + w * R, rows + w * R, sizeof(int32_t) * (size_t)deg[w]);
+                continue;
+            }
+            int nw = 0;
+            for (int j = 0; j < deg[w]; ++j) W2[nw++] = rows[w * R + j];
+            for (int64_t j = cnt[w]; j < cnt[w + 1]; ++j) W2[nw++] = rev[j];
+            deg2[w] = prune(&S, w, W2, nw, alpha_rev, R, rows2 + w * R, rd + w * R);
+        }
+        memcpy(rows, rows2, sizeof(int32_t) * (size_t)(n * R));
+        memcpy(deg, deg2, sizeof(int32_t) * (size_t)n);
+        free(rows2); free(deg2); free(W2); free(rev); free(fill); free(cnt);
+    }
+    out_offsets[0] = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        out_offsets[v + 1] = out_offsets[v] + deg[v];
+        memcpy(out_nbrs + out_offsets[v], rows + v * R, sizeof(int32_t) * (size_t)deg[v]);
+    }
+    /* entry */
+    int integral = 1;
+    for (int64_t i = 0; i < n * dim && integral; ++i)
+        if (X[i] != floor(X[i]) || fabs(X[i]) > 1e6) integral = 0;
+    int64_t best = 0;
+    if (integral) {
+        int64_t* Ssum = (int64_t*)calloc((size_t)dim, sizeof(int64_t));
+        for (int64_t v = 0; v < n; ++v)
+            for (int j = 0; j < dim; ++j) Ssum[j] += (int64_t)X[v * dim + j];
+        __int128 bestc = 0;
+        for (int64_t v = 0; v < n; ++v) {
+            __int128 c = 0;
+            for (int j = 0; j < dim; ++j) {
+                __int128 t = (__int128)n * (int64_t)X[v * dim + j] - Ssum[j];
+                c += t * t;
+            }
+            if (v == 0 || c < bestc) { bestc = c; best = v; }
+        }
+        free(Ssum);
+    } else {
+        double* mean = (double*)calloc((size_t)dim, sizeof(double));
+        for (int64_t v = 0; v < n; ++v)
+            for (int j = 0; j < dim; ++j) mean[j] += (double)X[v * dim + j];
+        for (int j = 0; j < dim; ++j) mean[j] /= (double)n;
+        double bestc = 0.0;
+        for (int64_t v = 0; v < n; ++v) {
+            double c = 0.0;
+            for (int j = 0; j < dim; ++j) {
+                double t = (double)X[v * dim + j] - mean[j];
+                c += t * t;
+            }
+            if (v == 0 || c < bestc) { bestc = c; best = v; }
+        }
+        free(mean);
+    }
+    *out_entry = (int32_t)best;
+    free(rows); free(rd); free(deg); free(norms);
+    return 0;
+}

@@ -1,0 +1,126 @@
+"""Seeded synthetic inputs shared by the oracle side and the HIP side.
+
+This module only draws random numbers (numpy PCG64): vectors shaped like the
+paper's workloads (dataset table, Section 6.1) and small random graphs for
+tests. It holds none of the method's arithmetic: no distances, no search, no
+pruning. Every workload is fully determined by its seed.
+
+Recipes (the paper's datasets are not available; these stand in for them):
+
+* ``tiny_int``: i.i.d. integers uniform in [-8, 8], dim 32, stored as float32.
+  Squared-L2 distances between such vectors are exact small integers.
+* ``mixture_u8``: 0..255 integers drawn from an equal-weight Gaussian mixture
+  (SIFT-like, 128-d). Component centres are 128 + ``center_sd`` * N(0, I),
+  points are centre + ``sigma`` * N(0, I), rounded and clipped to [0, 255],
+  stored as float32. The centre spread is chosen so that components overlap:
+  with well separated components no exact k-NN edge crosses a component and a
+  flat graph built from k-NN lists cannot be navigated between them.
+* ``mixture_unit``: L2-normalised Gaussian mixture (DEEP-like / embedding-like),
+  optional per-dimension scale decaying as 1/sqrt(i).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEED_BASE = 0x524E534D  # "RNSM"
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.PCG64(seed))
+
+
+def tiny_int(n: int, dim: int = 32, seed: int = SEED_BASE + 1, lo: int = -8, hi: int = 8) -> np.ndarray:
+    """Integers uniform in [lo, hi] stored as float32, shape (n, dim)."""
+    g = rng(seed)
+    return g.integers(lo, hi + 1, size=(n, dim)).astype(np.float32)
+
+
+def mixture_u8(n: int, dim: int = 128, comps: int = 64, sigma: float = 30.0,
+               center_sd: float = 20.0, seed: int = SEED_BASE + 2,
+               stream: int = 0) -> np.ndarray:
+    """Gaussian-mixture integers in [0, 255] stored as float32, shape (n, dim).
+
+    ``stream`` selects an independent draw (0: base vectors, 1: queries) from
+    the same mixture: the centres depend on ``seed`` only.
+    """
+    gc = rng(seed)
+    centres = 128.0 + center_sd * gc.standard_normal((comps, dim))
+    g = rng(seed * 1000003 + 17 + stream)
+    out = np.empty((n, dim), dtype=np.float32)
+    chunk = 1 << 16
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        lab = g.integers(0, comps, size=e - s)
+        x = centres[lab] + sigma * g.standard_normal((e - s, dim))
+        out[s:e] = np.clip(np.rint(x), 0, 255)
+    return out
+
+
+def mixture_unit(n: int, dim: int = 96, comps: int = 256, noise: float = 0.5,
+                 decay: bool = False, seed: int = SEED_BASE + 3,
+                 stream: int = 0) -> np.ndarray:
+    """L2-normalised Gaussian-mixture vectors, float32, shape (n, dim)."""
+    gc = rng(seed)
+    scale = (1.0 / np.sqrt(np.arange(1, dim + 1))) if decay else np.ones(dim)
+    centres = gc.standard_normal((comps, dim)) * scale
+    g = rng(seed * 1000003 + 29 + stream)
+    out = np.empty((n, dim), dtype=np.float32)
+    chunk = 1 << 16
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        lab = g.integers(0, comps, size=e - s)
+        x = centres[lab] + noise * scale * g.standard_normal((e - s, dim))
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+        out[s:e] = x
+    return out
+
+
+def uneven_sizes(m: int, lo: int, hi: int, total: int, seed: int) -> list[int]:
+    """m sizes drawn log-uniform on [lo, hi], then scaled by a common factor
+    (clamped to [lo, hi], water-filling) so that they sum to ``total``."""
+    g = rng(seed)
+    s = np.exp(g.uniform(np.log(lo), np.log(hi), size=m))
+    fa, fb = 1e-6, 1e6
+    for _ in range(200):
+        f = np.sqrt(fa * fb)
+        t = np.clip(s * f, lo, hi).sum()
+        if t < total:
+            fa = f
+        else:
+            fb = f
+    sizes = np.floor(np.clip(s * fb, lo, hi)).astype(np.int64)
+    # hand the rounding remainder to the largest sizes below the cap
+    rem = int(total - sizes.sum())
+    order = np.argsort(-sizes, kind="stable")
+    i = 0
+    while rem != 0 and i < 10 * m:
+        j = order[i % m]
+        step = 1 if rem > 0 else -1
+        if lo <= sizes[j] + step <= hi:
+            sizes[j] += step
+            rem -= step
+        i += 1
+    return [int(v) for v in sizes]
+
+
+def random_graph(n: int, deg: int, seed: int, ring: bool = True) -> tuple[np.ndarray, np.ndarray]:
+    """Random directed graph as CSR (int64 offsets, int32 local ids).
+
+    Every row has ``deg`` distinct out-neighbours, no self-loop. With ``ring``
+    the first neighbour of v is (v + 1) mod n, so the graph is strongly
+    connected. Requires deg < n.
+    """
+    assert 0 < deg < n
+    g = rng(seed)
+    nbrs = np.empty((n, deg), dtype=np.int32)
+    for v in range(n):
+        row = []
+        if ring:
+            row.append((v + 1) % n)
+        while len(row) < deg:
+            c = int(g.integers(0, n))
+            if c != v and c not in row:
+                row.append(c)
+        nbrs[v] = row
+    offsets = np.arange(0, n * deg + 1, deg, dtype=np.int64)
+    return offsets, nbrs.reshape(-1)

@@ -1,0 +1,55 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a private copy of the oracle's C source (a
+flipped comparison, a dropped step, a swapped operand), builds it on the CPU,
+and runs the pin suite against it: the suite must fail. No GPU involved.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "rnsm_oracle.c")
+
+MUTANTS = {
+    "distance_not_squared": ("s += t * t;", "s += fabs(t);"),
+    "key_tie_reversed": ("(da == db && ia < ib)", "(da == db && ia > ib)"),
+    "beam_no_truncation": ("        if (size > ef) size = ef;\n    }\n    for (int i = 0; i < size; ++i) {",
+                           "    }\n    for (int i = 0; i < size; ++i) {"),
+    "beam_expands_farthest": ("if (!C[i].expanded) { u = i; break; }", "if (!C[i].expanded) { u = i; }"),
+    "prune_not_strict": ("if (a * dwv < c[i].d)", "if (a * dwv <= c[i].d)"),
+    "prune_alpha_wrong_side": ("if (a * dwv < c[i].d)", "if (dwv < a * c[i].d)"),
+    "pivot_tie_reversed": ("(a.g == b.g && a.x < b.x)", "(a.g == b.g && a.x > b.x)"),
+    "mos_relay_costliest": ("(best < 0 || C[c * m + v] < C[best * m + v])",
+                            "(best < 0 || C[c * m + v] > C[best * m + v])"),
+    "no_reverse_prune": ("        if (rcnt[v + 1] == rcnt[v]) continue;", "        continue;"),
+    "ops_order_reversed": ("(c1 == c0 && (i1 > i0 || (i1 == i0 && j1 > j0)))",
+                           "(c1 == c0 && (i1 < i0 || (i1 == i0 && j1 < j0)))"),
+    "larger_is_source": ("int src = (sizes[j] < sizes[i]) ? j : i;",
+                         "int src = (sizes[j] > sizes[i]) ? j : i;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    with tempfile.TemporaryDirectory() as td:
+        csrc = os.path.join(td, "rnsm_oracle.c")
+        with open(csrc, "w") as f:
+            f.write(src.replace(old, new))
+        hdr = os.path.join(ROOT, "oracle", "rnsm_oracle.h")
+        with open(os.path.join(td, "rnsm_oracle.h"), "w") as f:
+            f.write(open(hdr).read())
+        so = os.path.join(td, "libmutant.so")
+        subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-o", so, csrc, "-lm"],
+                       check=True)
+        env = dict(os.environ, RNSM_ORACLE_LIB=so)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                           env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+        assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

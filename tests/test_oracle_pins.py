@@ -1,0 +1,424 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each check ties one oracle function to something other than itself: a hand
+traced example (tests/golden), a closed form, a brute-force definition on a
+tiny input, or an invariant the paper states. None of these tests needs a GPU.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2602_17099_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _csr(adj):
+    offs = np.zeros(len(adj) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum([len(a) for a in adj])
+    nb = np.array([v for a in adj for v in a] or [0], dtype=np.int32)
+    return offs, nb
+
+
+def _exact_l2(a, b):
+    return sum((int(x) - int(y)) ** 2 for x, y in zip(a, b))
+
+
+# ---------------------------------------------------------------- distances
+
+def test_distance_exact_on_integers(orc):
+    X = inputs.tiny_int(50, 32, seed=11)
+    for i in range(0, 50, 7):
+        for j in range(0, 50, 5):
+            assert orc.dist(X[i], X[j]) == _exact_l2(X[i], X[j])
+
+
+def test_distance_ip_cosine_closed_forms(orc):
+    e0 = np.array([1, 0, 0, 0], np.float32)
+    e1 = np.array([0, 1, 0, 0], np.float32)
+    assert orc.dist(e0, e1, orc.IP) == 1.0          # orthogonal unit vectors
+    assert orc.dist(e0, e0, orc.IP) == 0.0
+    assert orc.dist(e0, -e0, orc.IP) == 2.0         # opposite unit vectors
+    a = np.array([3, 4, 0, 0], np.float32)          # |a| = 5
+    b = np.array([6, 8, 0, 0], np.float32)          # parallel, |b| = 10
+    assert abs(orc.dist(a, b, orc.COSINE)) < 1e-15
+    c = np.array([0, 0, 2, 0], np.float32)
+    assert orc.dist(a, c, orc.COSINE) == 1.0
+    # cosine = 1 - <a,d>/(|a||d|) = 1 - 24/(5*5) for d = (0, 5, 0, 0)... use (4, 3)
+    d = np.array([4, 3, 0, 0], np.float32)
+    assert abs(orc.dist(a, d, orc.COSINE) - (1.0 - 24.0 / 25.0)) < 1e-15
+
+
+# ------------------------------------------------------------- beam search
+
+@pytest.mark.parametrize("case", _gold("beam_path.json")["cases"], ids=lambda c: c["name"])
+def test_beam_search_hand_traced(orc, case):
+    X = np.array(case["points"], np.float32)
+    offs, nb = _csr(case["adjacency"])
+    ids, ds, ndc = orc.beam_search(offs, nb, X, np.array(case["query"], np.float32),
+                                   case["seeds"], case["ef"])
+    assert ids.tolist() == case["ids"]
+    assert ds.tolist() == case["dists"]
+    assert ndc == case["ndc"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_beam_search_exhaustive_equals_brute_force(orc, seed):
+    # a strongly connected graph searched with ef >= n visits every vertex,
+    # so the result is the exact top-ef by (d, id)
+    n = 70
+    X = inputs.tiny_int(n, 6, seed=seed, lo=-3, hi=3)  # many distance ties
+    offs, nb = inputs.random_graph(n, 4, seed=seed + 100)
+    q = inputs.tiny_int(1, 6, seed=seed + 7, lo=-3, hi=3)[0]
+    ids, ds, _ = orc.beam_search(offs, nb, X, q, [0], n + 5)
+    truth = sorted(range(n), key=lambda v: (_exact_l2(q, X[v]), v))
+    assert ids.tolist() == truth
+    assert ds.tolist() == [_exact_l2(q, X[v]) for v in truth]
+
+
+def test_beam_search_result_is_sorted_and_bounded(orc):
+    n = 300
+    X = inputs.tiny_int(n, 8, seed=5)
+    offs, nb = inputs.random_graph(n, 6, seed=9)
+    for ef in (1, 3, 16, 40):
+        q = inputs.tiny_int(1, 8, seed=ef)[0]
+        ids, ds, _ = orc.beam_search(offs, nb, X, q, [0, 5], ef)
+        assert len(ids) == ef
+        keys = list(zip(ds.tolist(), ids.tolist()))
+        assert keys == sorted(keys)
+        assert len(set(ids.tolist())) == len(ids)
+
+
+# ------------------------------------------------------------------- prune
+
+def test_prune_collinear_one_side(orc):
+    X = np.array([[0], [1], [2], [3], [4]], np.float32)
+    ids, ds = orc.prune(0, [1, 2, 3, 4], X, 1.2, 10)
+    assert ids.tolist() == [1]          # 1 dominates 2, 3, 4; no backfill
+    assert ds.tolist() == [1.0]
+
+
+def test_prune_two_sides(orc):
+    X = np.array([[0], [-2], [-1], [1], [2]], np.float32)
+    ids, _ = orc.prune(0, [1, 2, 3, 4], X, 1.2, 10)
+    # keys (1,id2) (1,id3) (4,id1) (4,id4); -1 and +1 are 4 apart: both kept
+    assert ids.tolist() == [2, 3]
+
+
+def test_prune_strict_inequality_and_alpha(orc):
+    # p=(0,0) w=(3,0) v=(3,4): d(p,w)=9, d(p,v)=25, d(w,v)=16
+    X = np.array([[0, 0], [3, 0], [3, 4]], np.float32)
+    assert orc.prune(0, [1, 2], X, 1.0, 5)[0].tolist() == [1]      # 16 < 25
+    assert orc.prune(0, [1, 2], X, 1.5, 5)[0].tolist() == [1]      # 24 < 25
+    assert orc.prune(0, [1, 2], X, 1.5625, 5)[0].tolist() == [1, 2]  # 25 < 25 is false
+    assert orc.prune(0, [1, 2], X, 1.6, 5)[0].tolist() == [1, 2]
+    # equidistant from p and w: p=(0,0) w=(2,0) v=(1,3): d(p,v)=d(w,v)=10
+    Y = np.array([[0, 0], [2, 0], [1, 3]], np.float32)
+    assert orc.prune(0, [2, 1], Y, 1.0, 5)[0].tolist() == [1, 2]
+
+
+def test_prune_cap_dedupe_self(orc):
+    X = np.array([[0], [-2], [-1], [1], [2]], np.float32)
+    assert orc.prune(0, [3, 2], X, 1.2, 1)[0].tolist() == [2]       # R=1: nearest, tie by id
+    assert orc.prune(0, [0, 3, 3, 2, 0, 2], X, 1.2, 10)[0].tolist() == [2, 3]
+    assert orc.prune(0, [], X, 1.2, 10)[0].tolist() == []
+
+
+def test_prune_contains_rng_neighbours(orc):
+    # with alpha = 1 and no cap, every edge of the relative neighbourhood graph
+    # of p (no w with max(d(p,w), d(w,v)) < d(p,v)) survives the prune
+    g = np.random.default_rng(3)
+    X = g.standard_normal((60, 2)).astype(np.float32)
+    D = np.array([[orc.dist(X[i], X[j]) for j in range(60)] for i in range(60)])
+    for p in range(0, 60, 6):
+        kept = set(orc.prune(p, list(range(60)), X, 1.0, 1000)[0].tolist())
+        rng_nbrs = {v for v in range(60) if v != p and not any(
+            max(D[p, w], D[w, v]) < D[p, v] for w in range(60) if w not in (p, v))}
+        assert rng_nbrs <= kept
+
+
+@pytest.mark.parametrize("alpha,R", [(1.0, 8), (1.2, 8), (1.2, 100), (2.0, 5)])
+def test_prune_self_consistency_brute_force(orc, alpha, R):
+    X = inputs.tiny_int(120, 8, seed=21, lo=-4, hi=4)
+    a = float(np.float32(alpha))
+    for p in range(0, 120, 11):
+        W = list(range(120))
+        ids, ds = orc.prune(p, W, X, alpha, R)
+        kept = ids.tolist()
+        order = sorted((v for v in W if v != p), key=lambda v: (_exact_l2(X[p], X[v]), v))
+        assert kept == [v for v in order if v in set(kept)]   # kept in (d, id) order
+        K = []
+        for v in order:
+            if len(K) == R:
+                break
+            dom = any(a * _exact_l2(X[w], X[v]) < _exact_l2(X[p], X[v]) for w in K)
+            if v in kept:
+                assert not dom
+                K.append(v)
+            else:
+                assert dom
+        assert K == kept
+
+
+# -------------------------------------------------- expansion and inversion
+
+def test_expansion_exhaustive_is_exact_knn(orc):
+    n, k = 40, 5
+    X = inputs.tiny_int(n, 4, seed=8, lo=-5, hi=5)
+    offs, nb = inputs.random_graph(n, 3, seed=31)
+    nk = orc.expand(offs, nb, X, k, n + 1)
+    for v in range(n):
+        truth = sorted((u for u in range(n) if u != v), key=lambda u: (_exact_l2(X[v], X[u]), u))
+        assert nk[v].tolist() == truth[:k]
+
+
+def test_invert_definition(orc):
+    nk = np.array([[1, 2], [2, -1], [0, 1], [1, 0]], np.int32)
+    off, ids = orc.invert(nk)
+    lists = [ids[off[x]:off[x + 1]].tolist() for x in range(4)]
+    assert lists == [[2, 3], [0, 2, 3], [0, 1], []]
+
+
+# ---------------------------------------------------------- pivot selection
+
+def _eager(rk):
+    """Eager greedy: repeatedly take the uncovered x with the largest
+    |R_k(x) minus covered| (ties: smallest id)."""
+    n = len(rk)
+    cov = [False] * n
+    piv, fol = [], {}
+    while not all(cov):
+        best = None
+        for x in range(n):
+            if cov[x]:
+                continue
+            g = sum(1 for y in rk[x] if not cov[y])
+            if best is None or g > best[0]:
+                best = (g, x)
+        x = best[1]
+        for y in rk[x]:
+            if not cov[y]:
+                fol[y] = x
+        piv.append(x)
+        cov[x] = True
+        for y in rk[x]:
+            cov[y] = True
+    return piv, fol
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_lazy_greedy_equals_eager(orc, seed):
+    g = np.random.default_rng(seed)
+    n, k = 60, 3
+    nk = np.array([g.choice([u for u in range(n) if u != v], k, replace=False) for v in range(n)],
+                  np.int32)
+    off, ids = orc.invert(nk)
+    pivot_of, order = orc.pivots(off, ids)
+    rk = [ids[off[x]:off[x + 1]].tolist() for x in range(n)]
+    piv, fol = _eager(rk)
+    assert order.tolist() == piv
+    for y in range(n):
+        assert pivot_of[y] == (-1 if y in piv else fol[y])
+    # every vertex is a pivot or follows one; a follower's pivot is in its N_k
+    for y in range(n):
+        if pivot_of[y] >= 0:
+            assert pivot_of[y] in nk[y].tolist()
+            assert pivot_of[pivot_of[y]] == -1
+
+
+def test_pivots_dominate(orc):
+    # the pivots dominate the undirected R_k graph, so they are no fewer than a
+    # minimum dominating set (brute force on 12 vertices)
+    g = np.random.default_rng(4)
+    n, k = 12, 2
+    nk = np.array([g.choice([u for u in range(n) if u != v], k, replace=False) for v in range(n)],
+                  np.int32)
+    off, ids = orc.invert(nk)
+    _, order = orc.pivots(off, ids)
+    nb = [set() for _ in range(n)]
+    for y in range(n):
+        for x in nk[y]:
+            nb[x].add(y)
+            nb[y].add(int(x))
+    best = n
+    for r in range(1, n + 1):
+        for S in itertools.combinations(range(n), r):
+            if all(v in S or nb[v] & set(S) for v in range(n)):
+                best = r
+                break
+        if best == r:
+            break
+    assert len(order) >= best
+
+
+# ---------------------------------------------------------------------- MOS
+
+@pytest.mark.parametrize("name", ["mos_relay_5.json", "mos_relay_7.json"])
+def test_mos_hand_traced_relay(orc, name):
+    gd = _gold(name)
+    C = np.array(gd["cost"], np.float64)
+    edges, nf = orc.mos(C, gd["degree_bound"], gd["diameter"])
+    assert [list(e) for e in edges] == gd["edges"]
+    assert nf == gd["fallbacks"]
+
+
+def test_mos_two_and_star(orc):
+    assert orc.mos(orc.mos_cost(2), 2)[0] == [(0, 1)]
+    for m in (3, 4, 5):
+        edges, nf = orc.mos(orc.mos_cost(m), m - 1)
+        assert edges == [(0, j) for j in range(1, m)] and nf == 0
+
+
+@pytest.mark.parametrize("m,R,cent", [(6, 3, False), (10, 4, True), (17, 5, True), (50, 8, False),
+                                      (50, 8, True), (30, 3, True)])
+def test_mos_invariants(orc, m, R, cent):
+    g = np.random.default_rng(m * 7 + R)
+    C = orc.mos_cost(m, g.standard_normal((m, 5)) if cent else None)
+    edges, nf = orc.mos(C, R, 2)
+    adj = [set() for _ in range(m)]
+    for a, b in edges:
+        assert a != b and b not in adj[a]
+        adj[a].add(b)
+        adj[b].add(a)
+    for s in range(m):  # connected with diameter <= 2
+        seen = {s} | adj[s]
+        for x in list(adj[s]):
+            seen |= adj[x]
+        assert len(seen) == m
+    over = sum(max(0, len(adj[v]) - R) for v in range(m))
+    assert over <= 2 * nf
+
+
+# ----------------------------------------------------- whole operation (P6)
+
+def _exact_cm_op(orc, X, rows, s_rng, t_rng, R, alpha):
+    """Reference for one operation when every search is exhaustive: the
+    candidates of a source vertex are the whole target, sorted; no beam search."""
+    rows = {v: list(r) for v, r in rows.items()}
+    for u in range(*s_rng):
+        rows[u] = orc.prune(u, rows[u] + list(range(*t_rng)), X, alpha, R)[0].tolist()
+    rev = {}
+    for u in range(*s_rng):
+        for v in rows[u]:
+            if t_rng[0] <= v < t_rng[1]:
+                rev.setdefault(v, []).append(u)
+    for v, r in rev.items():
+        rows[v] = orc.prune(v, rows[v] + r, X, alpha, R)[0].tolist()
+    return rows
+
+
+def _subs_random(sizes, R_in, seed):
+    subs, rows, base = [], {}, 0
+    for i, n in enumerate(sizes):
+        offs, nb = inputs.random_graph(n, R_in, seed=seed + i)
+        subs.append((offs, nb, 0))
+        for v in range(n):
+            rows[base + v] = [base + int(x) for x in nb[offs[v]:offs[v + 1]]]
+        base += n
+    return subs, rows
+
+
+def test_whole_op_exhaustive_equals_exact_cm(orc):
+    sizes, R, alpha = [45, 60], 8, 1.2
+    X = inputs.tiny_int(sum(sizes), 5, seed=41, lo=-6, hi=6)
+    subs, rows = _subs_random(sizes, 4, 500)
+    out = orc.merge(subs, X, R=R, L=64, alpha=alpha)
+    assert out["ops"] == [(0, 1)]
+    ref = _exact_cm_op(orc, X, rows, (0, 45), (45, 105), R, alpha)
+    for v in range(105):
+        got = out["nbrs"][out["offsets"][v]:out["offsets"][v + 1]].tolist()
+        assert got == ref[v], v
+
+
+def test_multi_op_exhaustive_equals_sequential_cm(orc):
+    sizes, R, alpha = [30, 22, 41, 35], 6, 1.2
+    X = inputs.tiny_int(sum(sizes), 4, seed=43, lo=-6, hi=6)
+    subs, rows = _subs_random(sizes, 3, 700)
+    out = orc.merge(subs, X, R=R, L=48, alpha=alpha, mos_degree=2)
+    bases = np.concatenate([[0], np.cumsum(sizes)])
+    # unit costs: execution order is ascending (min index, max index); the
+    # smaller sub-index is the source
+    mos_edges, _ = orc.mos(orc.mos_cost(4), 2)
+    pairs = sorted(tuple(sorted(e)) for e in mos_edges)
+    assert [tuple(sorted(o)) for o in out["ops"]] == pairs
+    for s, t in out["ops"]:
+        assert sizes[s] < sizes[t] or (sizes[s] == sizes[t] and s < t)
+        rows = _exact_cm_op(orc, X, rows, (bases[s], bases[s + 1]), (bases[t], bases[t + 1]), R,
+                            alpha)
+    for v in range(sum(sizes)):
+        got = out["nbrs"][out["offsets"][v]:out["offsets"][v + 1]].tolist()
+        assert got == rows[v], v
+
+
+def test_merge_output_invariants(orc):
+    X = inputs.tiny_int(800, 32, seed=51)
+    g0 = orc.build_graph(X[:400], 32, 16, alpha=1.0)
+    g1 = orc.build_graph(X[400:], 32, 16, alpha=1.0)
+    out = orc.merge([g0, g1], X, R=16, L=32, alpha=1.2, trace=True)
+    a = float(np.float32(1.2))
+    offs, nb = out["offsets"], out["nbrs"]
+    assert out["entry"] == g0[2]  # equal sizes: the first sub-index's entry
+    for v in range(800):
+        row = nb[offs[v]:offs[v + 1]].tolist()
+        assert len(row) <= 16 and v not in row and len(set(row)) == len(row)
+        assert all(0 <= u < 800 for u in row)
+        if v < 400:  # every source row was pruned: (d, id) order, none dominated
+            keys = [(_exact_l2(X[v], X[u]), u) for u in row]
+            assert keys == sorted(keys)
+            for i, u in enumerate(row):
+                assert not any(a * _exact_l2(X[w], X[u]) < _exact_l2(X[v], X[u]) for w in row[:i])
+            assert any(u >= 400 for u in row)
+    assert out["dists"].tolist() == [_exact_l2(X[v], X[u]) for v in range(800)
+                                     for u in nb[offs[v]:offs[v + 1]]]
+    tr = out["trace"]
+    piv = tr["pivot_of"]
+    assert tr["n_pivots"] == int((piv == -1).sum())
+    for y in np.nonzero(piv >= 0)[0]:
+        assert piv[y] in tr["nk"][y].tolist()
+
+
+def test_all_pivots_mode_is_cross_query(orc):
+    # with every source vertex a pivot there is no local sliding
+    X = inputs.tiny_int(300, 8, seed=61)
+    subs, _ = _subs_random([140, 160], 4, 900)
+    out = orc.merge(subs, X, R=8, L=16, alpha=1.2, all_pivots=True, trace=True)
+    assert out["trace"]["ndc_slide"] == 0 and out["trace"]["n_pivots"] == 140
+
+
+# ------------------------------------------------------- builder and recall
+
+def test_knn_brute_force_and_fast_path(orc):
+    X = inputs.tiny_int(300, 6, seed=71, lo=-3, hi=3)
+    a = orc.knn(X, 12)
+    for v in range(0, 300, 17):
+        truth = sorted((u for u in range(300) if u != v), key=lambda u: (_exact_l2(X[v], X[u]), u))
+        assert a[v].tolist() == truth[:12]
+    assert np.array_equal(orc.knn_fast(X, 12, block=64), a)
+    Y = np.random.default_rng(2).standard_normal((200, 7)).astype(np.float32)
+    assert np.array_equal(orc.knn_fast(Y, 9, block=50), orc.knn(Y, 9))
+
+
+def test_builder_entry_and_rows(orc):
+    X = inputs.tiny_int(500, 8, seed=81)
+    offs, nb, entry = orc.build_graph(X, 20, 10, alpha=1.0)
+    n = 500
+    S = X.astype(np.int64).sum(0)
+    crit = [int(((n * X[v].astype(np.int64) - S) ** 2).sum()) for v in range(n)]
+    assert entry == min(range(n), key=lambda v: (crit[v], v))
+    knn = orc.knn(X, 20)
+    for v in range(0, n, 13):
+        assert nb[offs[v]:offs[v + 1]].tolist() == orc.prune(v, knn[v], X, 1.0, 10)[0].tolist()
+    assert np.diff(offs).max() <= 10
+
+
+def test_recall_definition(orc):
+    assert orc.recall_at_k([[1, 2, 3]], [[1, 2, 4]], k=3) == pytest.approx(2 / 3)
+    assert orc.recall_at_k([[5, 6], [1, 2]], [[6, 5], [3, 4]], k=2) == pytest.approx(0.5)
