@@ -1,0 +1,224 @@
+/*
+ * librnsm: Reverse Neighbor Sliding Merge (RNSM) of proximity-graph indexes
+ * on AMD Instinct MI355X (gfx950), after arXiv 2602.17099.
+ *
+ * The method (Section 4, Algorithm 2): every vertex of the smaller
+ * sub-index (the source) finds neighbours in the larger one (the target) by
+ * greedy beam search (Algorithm 1). Pivot vertices, picked by a lazy greedy
+ * over reverse k-NN lists, start from the target's entry point ("naive
+ * search"); their followers start from the pivot's results ("local
+ * sliding"). Each source vertex's results are concatenated with its current
+ * out-neighbours and pruned by the RNG/alpha edge-selection rule to out-degree
+ * R; the kept cross edges are offered back to the target vertices as reverse
+ * edges, and every target that received some is pruned again. With more than
+ * two sub-indexes, Merge Order Selection (Section 5, Algorithm 3) picks which
+ * pairs to merge and in which order.
+ *
+ * Conventions shared by every entry point:
+ *  - Ids: sub-index i's local id v has global id base_i + v, where base_i is
+ *    the sum of the sizes of sub-indexes 0..i-1 in the order given.
+ *  - Distances: RNSM_L2SQ = sum (x-y)^2, RNSM_IP = 1 - <x,y>,
+ *    RNSM_COSINE = 1 - <x,y>/(|x||y|); all accumulate in float32. Every
+ *    ordering is by (distance, id) ascending.
+ *  - Prune rule: candidates sorted by (d(p,.), id); v is dropped when some
+ *    already kept w has alpha * d(w,v) < d(p,v) (strict; alpha as float32,
+ *    product formed in double); stop at R kept; no backfill.
+ *  - Memory: every pointer marked "device" is HIP device memory (for example
+ *    torch.Tensor.data_ptr() of a CUDA/HIP tensor). Inputs are borrowed and
+ *    read only; nothing is retained after a call returns. Outputs are
+ *    caller-allocated. Work runs on `stream` (NULL: the default stream) and
+ *    every call has finished on the device when it returns.
+ *  - Errors: every entry point returns rnsm_status; no exception crosses the
+ *    boundary. On error the outputs are unspecified and nothing leaks;
+ *    rnsm_last_error() describes the failure (thread-local).
+ *  - The library is not reentrant per device: calls that overlap on one
+ *    device are serialised by an internal lock.
+ */
+#ifndef RNSM_H
+#define RNSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RNSM_OK = 0,
+    RNSM_EINVAL = 1,       /* bad argument or malformed input graph */
+    RNSM_ENOMEM = 2,       /* device or host allocation failed */
+    RNSM_EDEVICE = 3,      /* a HIP call failed */
+    RNSM_EUNSUPPORTED = 4, /* valid but outside what the kernels handle */
+    RNSM_EINTERNAL = 5
+} rnsm_status;
+
+typedef enum { RNSM_L2SQ = 0, RNSM_IP = 1, RNSM_COSINE = 2 } rnsm_metric;
+
+/* storage type of the vectors the searches read */
+typedef enum { RNSM_F32 = 0, RNSM_BF16 = 1, RNSM_F16 = 2 } rnsm_dtype;
+
+/* flags of rnsm_params */
+#define RNSM_FLAG_ALL_PIVOTS 1u     /* every source vertex runs a naive search (cross-query merge) */
+#define RNSM_FLAG_CENTROID_COSTS 2u /* MOS costs = centroid distances (default: unit costs) */
+
+/*
+ * One input sub-index: a flat proximity graph (Section 2.2) over n vectors.
+ * CSR in device memory: offsets[n+1] (int64, offsets[0] = 0, non-decreasing),
+ * nbrs[offsets[n]] local ids in [0, n). Rows hold no self-loop and no
+ * duplicate, and at most R entries (rnsm_merge rejects others with
+ * RNSM_EINVAL). entry: local id of the default entry point.
+ */
+typedef struct {
+    int64_t n;
+    const int64_t* offsets;
+    const int32_t* nbrs;
+    int32_t entry;
+} rnsm_graph;
+
+/*
+ * Vectors of all sub-indexes, concatenated in global-id order.
+ * f32: device, row-major [n x dim] float32 original values; the prune, the
+ *      output distances and the cosine norms read these.
+ * search_dtype / search: the copy the beam searches read. RNSM_F32 reads f32
+ *      (search may be NULL). RNSM_BF16 / RNSM_F16 read `search`, a device
+ *      row-major [n x dim] array of 16-bit values (the plain FP32 form versus
+ *      the reduced-precision form).
+ * dim * element size must be a multiple of 16 bytes and dim <= 1024 (f32) or
+ * dim <= 2048 (16-bit); otherwise RNSM_EUNSUPPORTED.
+ */
+typedef struct {
+    int64_t n;
+    int32_t dim;
+    const float* f32;
+    rnsm_dtype search_dtype;
+    const void* search;
+} rnsm_vectors;
+
+/*
+ * Parameters. Zero means "default" where a default is given.
+ * R        max out-degree of the merged graph (1..64)
+ * L        beam width; ef_naive and ef_slide default to L (1..128)
+ * alpha    prune factor (>= 1)
+ * k_reverse (default 5) reverse k-NN size, k_expand (default 16) the
+ *          neighbor-expansion beam width k+ (Section 4.2); k_reverse <= k_expand <= 64
+ * mos_degree   MOS degree bound (default max(2, ceil(sqrt(m))))
+ * mos_diameter MOS diameter bound (default 2, must be >= 2)
+ * flags    RNSM_FLAG_*
+ * stream   hipStream_t or NULL
+ */
+typedef struct {
+    int32_t R, L;
+    float alpha;
+    rnsm_metric metric;
+    int32_t k_reverse, k_expand, ef_naive, ef_slide;
+    int32_t mos_degree, mos_diameter;
+    uint32_t flags;
+    void* stream;
+} rnsm_params;
+
+/*
+ * Merged graph, caller-allocated device buffers:
+ * offsets [N+1] int64; nbrs [N*R] int32 capacity (global ids, first
+ * offsets[N] used); dists [N*R] float32 capacity or NULL (distance of each
+ * edge, recomputed in float32 on the original vectors).
+ * Written by the call: entry (global id of the entry of the largest
+ * sub-index, ties: lowest index) and n_edges.
+ * Pruned rows are in (distance, id) order; rows no operation touched keep the
+ * input order.
+ */
+typedef struct {
+    int64_t* offsets;
+    int32_t* nbrs;
+    float* dists;
+    int32_t entry;
+    int64_t n_edges;
+} rnsm_csr;
+
+/* Counters and event timings of the last rnsm_merge on this thread. */
+typedef struct {
+    double ms_total;        /* host wall time of the call */
+    double ms_expand;       /* neighbor expansion + inversion (device) */
+    double ms_plan;         /* host: MOS + lazy greedy, incl. transfers */
+    double ms_search;       /* naive + sliding search kernels (device events) */
+    double ms_prune;        /* source + target prunes and reverse edges (device) */
+    double ms_compact;
+    int64_t n_ops, n_source_vertices, n_pivots, n_followers, n_reverse_edges;
+    int64_t ndc_expand, ndc_naive, ndc_slide;   /* distance computations */
+    int64_t exp_naive, exp_slide;               /* expansions (vertices popped) */
+    int64_t adj_naive, adj_slide;               /* adjacency entries read */
+    double search_bytes;    /* algorithmic bytes of the naive + sliding searches */
+    int64_t search_launches;
+    int64_t hash_full;      /* neighbours the LDS visited table could not hold */
+} rnsm_stats;
+
+/*
+ * Merge m >= 2 sub-indexes into one graph (Algorithm 2 per operation,
+ * Algorithm 3 for the operation plan; Section 5 for the order: operations
+ * by ascending cost then (min index, max index), the smaller sub-index is the
+ * source, ties: the lower index). Searches of every operation read the input
+ * graphs only; rows start as the input rows and are updated operation by
+ * operation. graphs[m], vecs (N = sum of sizes rows), params, out as above.
+ * RNSM_EINVAL: m < 2, NULL pointers, vecs->n != N, R/L/alpha/k out of range,
+ * an entry out of range, or a malformed input row (offsets not
+ * non-decreasing, id out of range, self-loop, duplicate, degree > R).
+ */
+rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
+                       const rnsm_params* params, rnsm_csr* out);
+
+/* rnsm_merge with L2SQ, float32 search and default k, k+, MOS settings. */
+rnsm_status rnsm_merge_simple(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
+                              int32_t R, int32_t L, float alpha, rnsm_csr* out);
+
+/*
+ * Merge order selection (Algorithm 3) plus the execution order and direction
+ * of Section 5. Host only: deterministic, thread-safe, no device work.
+ * sizes[m]; centroids: NULL for unit costs (random partitions) or host
+ * [m x dim] double centroids (costs = Euclidean distances). degree_bound >= 1,
+ * diameter >= 2. out_ops receives 2*count int32: (source, target) pairs in
+ * execution order; cap = capacity in pairs. out_fallbacks counts edges added
+ * beyond the degree bound when no relay exists.
+ * RNSM_EINVAL on bad arguments or when cap is too small.
+ */
+rnsm_status mos_plan(int32_t m, const int64_t* sizes, const double* centroids, int32_t dim,
+                     int32_t degree_bound, int32_t diameter, int32_t* out_ops, int32_t cap,
+                     int32_t* out_count, int32_t* out_fallbacks);
+
+/*
+ * Beam search (Algorithm 1) of nq queries in one graph.
+ * g: the graph (local ids 0..n-1, device CSR), base: its n vectors
+ * (search_dtype/search/f32 as in rnsm_vectors; base->n == g->n).
+ * queries: device [nq x dim] in the same storage type as the searched copy.
+ * seeds: device [nq x n_seeds] local ids (-1 = none) or NULL to start every
+ * query from g->entry. ef in 1..128, k in 1..ef.
+ * out_ids: device [nq x k] local ids (-1 when fewer than k found);
+ * out_dists: device [nq x k] float32 or NULL.
+ */
+rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const void* queries,
+                        int64_t nq, const int32_t* seeds, int32_t n_seeds, int32_t ef, int32_t k,
+                        rnsm_metric metric, int32_t* out_ids, float* out_dists, void* stream);
+
+/*
+ * Sub-index builder used to make inputs: row(v) = Prune(v, knn(v), alpha, R);
+ * with reverse != 0, every kept v -> w offers v to w, and each w that got
+ * offers is pruned again over row(w) + offers with alpha_rev. Entry: the
+ * vertex closest to the centroid (exact integer criterion when every value
+ * is an integer, float64 otherwise), ties by id.
+ * X: device [n x dim] float32. knn: device [n x K] local ids sorted by
+ * (d, id), -1 padded, no self. out_offsets: device [n+1]; out_nbrs: device
+ * [n x R] capacity. *out_entry written.
+ */
+rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric metric,
+                             const int32_t* knn, int32_t K, int32_t R, float alpha,
+                             int32_t reverse, float alpha_rev, int64_t* out_offsets,
+                             int32_t* out_nbrs, int32_t* out_entry, void* stream);
+
+/* Stats of the last rnsm_merge on the calling thread. */
+rnsm_status rnsm_get_stats(rnsm_stats* out);
+
+/* Thread-local message of the last failure ("" if none). */
+const char* rnsm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RNSM_H */

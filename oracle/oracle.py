@@ -81,6 +81,8 @@ def _setup(L):
     L.orc_mos_cost.argtypes = [C.c_int, P, C.c_int, P]
     L.orc_mos.restype = C.c_int
     L.orc_mos.argtypes = [C.c_int, P, C.c_int, C.c_int, P, C.c_int, P, P]
+    L.orc_plan.restype = C.c_int
+    L.orc_plan.argtypes = [C.c_int, P, P, C.c_int, C.c_int, C.c_int, P, C.c_int, P, P]
     L.orc_merge.restype = C.c_int
     L.orc_merge.argtypes = [C.c_int, P, P, P, P, P, C.c_int, P, P, P, P, P, P, P, P]
     L.orc_knn.restype = C.c_int
@@ -195,6 +197,21 @@ def mos(cost, R, delta=2):
     if rc != 0:
         raise ValueError(f"orc_mos failed: {rc}")
     return [tuple(int(v) for v in e) for e in edges[: ne[0]]], int(nf[0])
+
+
+def plan(sizes, R, delta=2, centroids=None):
+    """Operations (source, target) in execution order and the fallback count."""
+    sizes = _i64(sizes)
+    m = len(sizes)
+    cen = None if centroids is None else np.ascontiguousarray(centroids, dtype=np.float64)
+    ops = np.zeros((max(1, m * m), 2), dtype=np.int32)
+    n = np.zeros(1, dtype=np.int32)
+    nf = np.zeros(1, dtype=np.int32)
+    rc = lib().orc_plan(m, _p(sizes), _p(cen), 0 if cen is None else cen.shape[1], R, delta,
+                        _p(ops), m * m, _p(n), _p(nf))
+    if rc != 0:
+        raise ValueError(f"orc_plan failed: {rc}")
+    return [tuple(int(v) for v in o) for o in ops[: n[0]]], int(nf[0])
 
 
 def merge(subs, X, R, L, alpha, metric=L2SQ, k=5, kplus=16, ef_slide=None, mos_degree=0,

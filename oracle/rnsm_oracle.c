@@ -659,6 +659,58 @@ static int pair_op(const space_t* S, const sub_t* s, const sub_t* t, const rows_
 /* Whole merge: MOS plan, operation order, sequential operations        */
 /* ------------------------------------------------------------------ */
 
+/*
+ * Operation plan: MOS edges (Algorithm 3) executed in ascending order of
+ * (cost, min index, max index); each runs from the smaller sub-index to the
+ * larger one (ties: the lower index is the source). out_ops: 2*cap int32.
+ */
+int orc_plan(int m, const int64_t* sizes, const double* centroids, int dim, int R, int delta,
+             int32_t* out_ops, int cap, int* n_ops, int* n_fallback) {
+    double* C = (double*)malloc(sizeof(double) * (size_t)m * m);
+    orc_mos_cost(m, centroids, dim, C);
+    int ne = 0, nf = 0;
+    int32_t* edges = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(m * m + 1));
+    if (m >= 2 && orc_mos(m, C, R, delta, edges, m * m, &ne, &nf) != 0) {
+        free(C); free(edges);
+        return -1;
+    }
+    if (ne > cap) { free(C); free(edges); return -2; }
+    /* normalise every edge to (min, max) */
+    for (int a = 0; a < ne; ++a) {
+        int32_t e0 = edges[2 * a], e1 = edges[2 * a + 1];
+        edges[2 * a] = e0 < e1 ? e0 : e1;
+        edges[2 * a + 1] = e0 < e1 ? e1 : e0;
+    }
+    /* stable insertion sort by (cost, min index, max index) */
+    for (int a = 1; a < ne; ++a) {
+        int32_t i0 = edges[2 * a], j0 = edges[2 * a + 1];
+        int b = a;
+        while (b > 0) {
+            int32_t i1 = edges[2 * (b - 1)], j1 = edges[2 * (b - 1) + 1];
+            double c0 = C[i0 * m + j0], c1 = C[i1 * m + j1];
+            int later = c1 > c0 || (c1 == c0 && (i1 > i0 || (i1 == i0 && j1 > j0)));
+            if (!later) break;
+            edges[2 * b] = edges[2 * (b - 1)];
+            edges[2 * b + 1] = edges[2 * (b - 1) + 1];
+            --b;
+        }
+        edges[2 * b] = i0;
+        edges[2 * b + 1] = j0;
+    }
+    /* direction: the smaller sub-index is the source; ties: lower index */
+    for (int a = 0; a < ne; ++a) {
+        int i = edges[2 * a], j = edges[2 * a + 1];
+        int src = (sizes[j] < sizes[i]) ? j : i;
+        int dst = src == i ? j : i;
+        out_ops[2 * a] = src;
+        out_ops[2 * a + 1] = dst;
+    }
+    *n_ops = ne;
+    if (n_fallback) *n_fallback = nf;
+    free(C); free(edges);
+    return 0;
+}
+
 int orc_merge(int m, const int64_t* sizes, const int64_t* offsets_cat, const int32_t* nbrs_cat,
               const int32_t* entries, const float* X, int dim, const orc_params_t* P,
               int32_t* out_rows, double* out_dists, int32_t* out_deg, int32_t* out_entry,
@@ -700,7 +752,7 @@ int orc_merge(int m, const int64_t* sizes, const int64_t* offsets_cat, const int
         }
 
     /* plan */
-    double* C = (double*)malloc(sizeof(double) * (size_t)m * m);
+    int cap = m * m, ne = 0;
     double* cent = NULL;
     if (P->use_centroids) {
         cent = (double*)calloc((size_t)m * dim, sizeof(double));
@@ -711,51 +763,15 @@ int orc_merge(int m, const int64_t* sizes, const int64_t* offsets_cat, const int
             for (int t = 0; t < dim; ++t) cent[i * dim + t] /= (double)subs[i].n;
         }
     }
-    orc_mos_cost(m, cent, dim, C);
     int rmos = P->mos_degree;
     if (rmos <= 0) {
         rmos = (int)ceil(sqrt((double)m));
         if (rmos < 2) rmos = 2;
     }
-    int cap = m * m, ne = 0, nf = 0;
-    int32_t* edges = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)cap);
-    if (m >= 2) {
-        if (orc_mos(m, C, rmos, P->mos_diameter, edges, cap, &ne, &nf) != 0) {
-            free(subs); free(norms); free(C); free(cent); free(edges);
-            return -3;
-        }
-    }
-    /* execution order: ascending (cost, min index, max index) */
-    for (int a = 1; a < ne; ++a) {
-        int32_t e0 = edges[2 * a], e1 = edges[2 * a + 1];
-        int i0 = e0 < e1 ? e0 : e1, j0 = e0 < e1 ? e1 : e0;
-        int b = a;
-        while (b > 0) {
-            int32_t f0 = edges[2 * (b - 1)], f1 = edges[2 * (b - 1) + 1];
-            int i1 = f0 < f1 ? f0 : f1, j1 = f0 < f1 ? f1 : f0;
-            double c0 = C[i0 * m + j0], c1 = C[i1 * m + j1];
-            int later = c1 > c0 || (c1 == c0 && (i1 > i0 || (i1 == i0 && j1 > j0)));
-            if (!later) break;
-            edges[2 * b] = edges[2 * (b - 1)];
-            edges[2 * b + 1] = edges[2 * (b - 1) + 1];
-            --b;
-        }
-        edges[2 * b] = i0;
-        edges[2 * b + 1] = j0;
-    }
-    /* normalise every edge to (min, max) for the first element too */
-    for (int a = 0; a < ne; ++a) {
-        int32_t e0 = edges[2 * a], e1 = edges[2 * a + 1];
-        edges[2 * a] = e0 < e1 ? e0 : e1;
-        edges[2 * a + 1] = e0 < e1 ? e1 : e0;
-    }
-    /* direction: the smaller sub-index is the source; ties: lower index */
-    for (int a = 0; a < ne; ++a) {
-        int i = edges[2 * a], j = edges[2 * a + 1];
-        int src = (sizes[j] < sizes[i]) ? j : i;
-        int dst = src == i ? j : i;
-        out_ops[2 * a] = src;
-        out_ops[2 * a + 1] = dst;
+    int nfb = 0;
+    if (orc_plan(m, sizes, cent, dim, rmos, P->mos_diameter, out_ops, cap, &ne, &nfb) != 0) {
+        free(subs); free(norms); free(cent);
+        return -3;
     }
     *out_nops = ne;
 
@@ -812,7 +828,7 @@ int orc_merge(int m, const int64_t* sizes, const int64_t* offsets_cat, const int
     }
     for (int i = 0; i < m; ++i) { free(piv_of[i]); free(piv_ord[i]); }
     free(piv_of); free(piv_ord); free(npiv);
-    free(subs); free(norms); free(C); free(cent); free(edges);
+    free(subs); free(norms); free(cent);
     return rc;
 }
 

@@ -1,0 +1,228 @@
+"""Python binding of librnsm (include/rnsm.h): argument marshalling only.
+
+Every step of the merge runs in the HIP library; PyTorch only provides device
+memory (tensors) and streams. If the library has not been built the calls
+raise: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librnsm.so")
+
+L2SQ, IP, COSINE = 0, 1, 2
+F32, BF16, F16 = 0, 1, 2
+FLAG_ALL_PIVOTS = 1
+FLAG_CENTROID_COSTS = 2
+
+SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_search", "rnsm_build_graph",
+           "rnsm_get_stats", "rnsm_last_error"]
+
+_lib = None
+
+
+class RnsmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"librnsm status {status}: {msg}")
+        self.status = status
+
+
+class Graph(C.Structure):
+    _fields_ = [("n", C.c_int64), ("offsets", C.c_void_p), ("nbrs", C.c_void_p),
+                ("entry", C.c_int32)]
+
+
+class Vectors(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("f32", C.c_void_p),
+                ("search_dtype", C.c_int), ("search", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("R", C.c_int32), ("L", C.c_int32), ("alpha", C.c_float), ("metric", C.c_int),
+                ("k_reverse", C.c_int32), ("k_expand", C.c_int32), ("ef_naive", C.c_int32),
+                ("ef_slide", C.c_int32), ("mos_degree", C.c_int32), ("mos_diameter", C.c_int32),
+                ("flags", C.c_uint32), ("stream", C.c_void_p)]
+
+
+class Csr(C.Structure):
+    _fields_ = [("offsets", C.c_void_p), ("nbrs", C.c_void_p), ("dists", C.c_void_p),
+                ("entry", C.c_int32), ("n_edges", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("ms_total", C.c_double), ("ms_expand", C.c_double), ("ms_plan", C.c_double),
+                ("ms_search", C.c_double), ("ms_prune", C.c_double), ("ms_compact", C.c_double),
+                ("n_ops", C.c_int64), ("n_source_vertices", C.c_int64), ("n_pivots", C.c_int64),
+                ("n_followers", C.c_int64), ("n_reverse_edges", C.c_int64),
+                ("ndc_expand", C.c_int64), ("ndc_naive", C.c_int64), ("ndc_slide", C.c_int64),
+                ("exp_naive", C.c_int64), ("exp_slide", C.c_int64), ("adj_naive", C.c_int64),
+                ("adj_slide", C.c_int64), ("search_bytes", C.c_double),
+                ("search_launches", C.c_int64), ("hash_full", C.c_int64)]
+
+
+def lib():
+    """Load librnsm.so; raises if it is missing (build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_2602_17099_amd/build.py "
+                               "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.rnsm_merge.restype = C.c_int
+        L.rnsm_merge.argtypes = [C.c_int32, P, P, P, P]
+        L.rnsm_merge_simple.restype = C.c_int
+        L.rnsm_merge_simple.argtypes = [C.c_int32, P, P, C.c_int32, C.c_int32, C.c_float, P]
+        L.mos_plan.restype = C.c_int
+        L.mos_plan.argtypes = [C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_int32, P, P]
+        L.rnsm_search.restype = C.c_int
+        L.rnsm_search.argtypes = [P, P, P, C.c_int64, P, C.c_int32, C.c_int32, C.c_int32, C.c_int,
+                                  P, P, P]
+        L.rnsm_build_graph.restype = C.c_int
+        L.rnsm_build_graph.argtypes = [C.c_int64, P, C.c_int32, C.c_int, P, C.c_int32, C.c_int32,
+                                       C.c_float, C.c_int32, C.c_float, P, P, P, P]
+        L.rnsm_get_stats.restype = C.c_int
+        L.rnsm_get_stats.argtypes = [P]
+        L.rnsm_last_error.restype = C.c_char_p
+        L.rnsm_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise RnsmError(st, lib().rnsm_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().rnsm_last_error().decode()
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _vectors(X, search=None):
+    import torch
+    assert X.is_cuda and X.dtype == torch.float32 and X.is_contiguous()
+    v = Vectors(n=X.shape[0], dim=X.shape[1], f32=X.data_ptr(), search_dtype=F32, search=None)
+    if search is not None:
+        assert search.is_cuda and search.is_contiguous() and search.shape == X.shape
+        v.search_dtype = BF16 if search.dtype == torch.bfloat16 else F16
+        assert search.dtype in (torch.bfloat16, torch.float16)
+        v.search = search.data_ptr()
+    return v
+
+
+def merge(subs, X, R, L, alpha, metric=L2SQ, search=None, k=0, kplus=0, ef_naive=0,
+          ef_slide=0, mos_degree=0, mos_diameter=0, flags=0, dists=True, stream=None,
+          out=None):
+    """Merge sub-indexes. subs: list of (offsets int64, nbrs int32, entry) device
+    tensors with local ids, in global-id order over the rows of X (float32
+    device [N, dim]). search: optional bf16/f16 copy of X that the searches
+    read. Returns (offsets, nbrs, dists, entry) device tensors (global ids)."""
+    import torch
+    m = len(subs)
+    gs = (Graph * m)()
+    for i, (o, nb, e) in enumerate(subs):
+        assert o.dtype == torch.int64 and nb.dtype == torch.int32 and o.is_cuda and nb.is_cuda
+        gs[i] = Graph(n=o.shape[0] - 1, offsets=o.data_ptr(), nbrs=nb.data_ptr(), entry=int(e))
+    v = _vectors(X, search)
+    N = X.shape[0]
+    dev = X.device
+    if out is None:
+        out = (torch.empty(N + 1, dtype=torch.int64, device=dev),
+               torch.empty(N * R, dtype=torch.int32, device=dev),
+               torch.empty(N * R, dtype=torch.float32, device=dev) if dists else None)
+    o_off, o_nb, o_d = out
+    csr = Csr(offsets=o_off.data_ptr(), nbrs=o_nb.data_ptr(),
+              dists=None if o_d is None else o_d.data_ptr())
+    p = Params(R=R, L=L, alpha=float(alpha), metric=metric, k_reverse=k, k_expand=kplus,
+               ef_naive=ef_naive, ef_slide=ef_slide, mos_degree=mos_degree,
+               mos_diameter=mos_diameter, flags=flags, stream=_stream(stream))
+    _check(lib().rnsm_merge(m, gs, C.byref(v), C.byref(p), C.byref(csr)))
+    ne = int(csr.n_edges)
+    return o_off, o_nb[:ne], (None if o_d is None else o_d[:ne]), int(csr.entry)
+
+
+def merge_simple(subs, X, R, L, alpha, stream=None):
+    import torch
+    m = len(subs)
+    gs = (Graph * m)()
+    for i, (o, nb, e) in enumerate(subs):
+        gs[i] = Graph(n=o.shape[0] - 1, offsets=o.data_ptr(), nbrs=nb.data_ptr(), entry=int(e))
+    v = _vectors(X)
+    N = X.shape[0]
+    o_off = torch.empty(N + 1, dtype=torch.int64, device=X.device)
+    o_nb = torch.empty(N * R, dtype=torch.int32, device=X.device)
+    csr = Csr(offsets=o_off.data_ptr(), nbrs=o_nb.data_ptr(), dists=None)
+    _check(lib().rnsm_merge_simple(m, gs, C.byref(v), R, L, float(alpha), C.byref(csr)))
+    return o_off, o_nb[: int(csr.n_edges)], int(csr.entry)
+
+
+def stats() -> dict:
+    s = Stats()
+    _check(lib().rnsm_get_stats(C.byref(s)))
+    return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+
+def mos_plan(sizes, degree_bound, diameter=2, centroids=None):
+    """Host-only planner: (source, target) operations in execution order, and
+    the number of fallback edges."""
+    import numpy as np
+    m = len(sizes)
+    sz = np.ascontiguousarray(sizes, dtype=np.int64)
+    cen = None if centroids is None else np.ascontiguousarray(centroids, dtype=np.float64)
+    cap = m * m
+    ops = np.zeros((cap, 2), dtype=np.int32)
+    cnt = C.c_int32(0)
+    fb = C.c_int32(0)
+    _check(lib().mos_plan(m, sz.ctypes.data_as(C.c_void_p),
+                          None if cen is None else cen.ctypes.data_as(C.c_void_p),
+                          0 if cen is None else cen.shape[1], degree_bound, diameter,
+                          ops.ctypes.data_as(C.c_void_p), cap, C.byref(cnt), C.byref(fb)))
+    return [tuple(int(x) for x in o) for o in ops[: cnt.value]], fb.value
+
+
+def search(offsets, nbrs, entry, base, queries, ef, k, seeds=None, metric=L2SQ,
+           base_search=None, stream=None):
+    """Beam search of every query row in one graph (local ids)."""
+    import torch
+    g = Graph(n=offsets.shape[0] - 1, offsets=offsets.data_ptr(), nbrs=nbrs.data_ptr(),
+              entry=int(entry))
+    v = _vectors(base, base_search)
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=base.device)
+    ds = torch.empty((nq, k), dtype=torch.float32, device=base.device)
+    ns = 0
+    if seeds is not None:
+        assert seeds.dtype == torch.int32 and seeds.is_contiguous()
+        ns = seeds.shape[1]
+    _check(lib().rnsm_search(C.byref(g), C.byref(v), C.c_void_p(queries.data_ptr()), nq,
+                             _ptr(seeds), ns, ef, k, metric, C.c_void_p(ids.data_ptr()),
+                             C.c_void_p(ds.data_ptr()), _stream(stream)))
+    return ids, ds
+
+
+def build_graph(X, knn, R, alpha=1.0, reverse=False, alpha_rev=1.2, metric=L2SQ, stream=None):
+    """Sub-index builder from exact k-NN lists (device int32 [n, K])."""
+    import torch
+    n, dim = X.shape
+    K = knn.shape[1]
+    off = torch.empty(n + 1, dtype=torch.int64, device=X.device)
+    nb = torch.empty(n * R, dtype=torch.int32, device=X.device)
+    entry = C.c_int32(0)
+    _check(lib().rnsm_build_graph(n, C.c_void_p(X.data_ptr()), dim, metric,
+                                  C.c_void_p(knn.data_ptr()), K, R, float(alpha), int(reverse),
+                                  float(alpha_rev), C.c_void_p(off.data_ptr()),
+                                  C.c_void_p(nb.data_ptr()), C.byref(entry), _stream(stream)))
+    ne = int(off[-1].item())
+    return off, nb[:ne].clone(), entry.value

@@ -1,0 +1,795 @@
+// C ABI of librnsm (declared in include/rnsm.h): argument checks, device
+// workspace, and the orchestration of the RNSM merge (Algorithm 2 per
+// operation, Algorithm 3 for the plan).
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rnsm.h"
+#include "rnsm_internal.h"
+#include "rnsm_plan.h"
+
+using namespace rnsm;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local rnsm_stats g_stats;
+std::mutex g_lock;
+
+rnsm_status fail(rnsm_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? RNSM_ENOMEM : RNSM_EDEVICE, "%s: %s (%s:%d)", \
+                        #x, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+    } while (0)
+
+// device buffers kept between calls, per device, grown on demand
+struct Workspace {
+    struct Buf {
+        void* p = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::string, Buf> bufs;
+    hipError_t get(const char* name, size_t bytes, void** out) {
+        Buf& b = bufs[name];
+        if (bytes == 0) bytes = 16;
+        if (b.bytes < bytes) {
+            if (b.p) {
+                hipError_t e = hipFree(b.p);
+                if (e != hipSuccess) return e;
+                b.p = nullptr;
+                b.bytes = 0;
+            }
+            hipError_t e = hipMalloc(&b.p, bytes);
+            if (e != hipSuccess) return e;
+            b.bytes = bytes;
+        }
+        *out = b.p;
+        return hipSuccess;
+    }
+};
+std::map<int, Workspace> g_ws;
+
+#define WS(ptr, name, bytes) HIPCHK(ws.get(name, (size_t)(bytes), (void**)&(ptr)))
+
+int elt_size(rnsm_dtype t) { return t == RNSM_F32 ? 4 : 2; }
+
+int ilog2_ceil(int64_t x) {
+    int b = 0;
+    while ((1ll << b) < x) ++b;
+    return b;
+}
+
+// LDS visited-table size and wavefronts per block for a search of beam ef
+// over rows of degree <= maxdeg. RNSM_HASH_BITS / RNSM_WPB override.
+void search_shape(int ef, int maxdeg, int* hbits, int* wpb) {
+    int hb = ilog2_ceil((int64_t)ef * (maxdeg > 0 ? maxdeg : 16) * 2);
+    hb = hb < 8 ? 8 : (hb > 13 ? 13 : hb);
+    const char* e = getenv("RNSM_HASH_BITS");
+    if (e && atoi(e) >= 6 && atoi(e) <= 14) hb = atoi(e);
+    int w = 4;
+    while (w > 1 && (size_t)w * ((1u << hb) + 64) * 4 > 64 * 1024) --w;
+    const char* ew = getenv("RNSM_WPB");
+    if (ew && atoi(ew) >= 1 && atoi(ew) <= 4) w = atoi(ew);
+    while (w > 1 && (size_t)w * ((1u << hb) + 64) * 4 > 64 * 1024) --w;
+    *hbits = hb;
+    *wpb = w;
+}
+
+struct VecInfo {
+    int tt;        // 0 f32, 1 bf16, 2 f16 (search copy)
+    int row_bytes; // search copy
+    int nch;       // chunks of the search copy
+    int G, cpl;
+    int nch32, G32, cpl32;  // float32 originals (prune)
+    const char* search;
+};
+
+rnsm_status vec_info(const rnsm_vectors* v, VecInfo& vi) {
+    if (!v->f32) return fail(RNSM_EINVAL, "vectors: f32 is NULL");
+    if (v->dim < 1) return fail(RNSM_EINVAL, "vectors: dim < 1");
+    if (v->search_dtype != RNSM_F32 && v->search_dtype != RNSM_BF16 &&
+        v->search_dtype != RNSM_F16)
+        return fail(RNSM_EINVAL, "vectors: unknown search dtype %d", (int)v->search_dtype);
+    if (v->search_dtype != RNSM_F32 && !v->search)
+        return fail(RNSM_EINVAL, "vectors: search copy is NULL for a 16-bit search dtype");
+    const int es = elt_size(v->search_dtype);
+    if (((int64_t)v->dim * es) % 16 != 0 || ((int64_t)v->dim * 4) % 16 != 0)
+        return fail(RNSM_EUNSUPPORTED, "vectors: dim %d gives rows that are not a multiple of 16 bytes",
+                    v->dim);
+    vi.tt = v->search_dtype == RNSM_F32 ? 0 : (v->search_dtype == RNSM_BF16 ? 1 : 2);
+    vi.row_bytes = v->dim * es;
+    vi.nch = vi.row_bytes / 16;
+    vi.G = lanes_per_row(vi.nch);
+    vi.nch32 = v->dim / 4;
+    vi.G32 = lanes_per_row(vi.nch32);
+    if (vi.G < 0 || vi.G32 < 0) return fail(RNSM_EUNSUPPORTED, "vectors: dim %d too large", v->dim);
+    vi.cpl = (vi.nch + vi.G - 1) / vi.G;
+    vi.cpl32 = (vi.nch32 + vi.G32 - 1) / vi.G32;
+    vi.search = v->search_dtype == RNSM_F32 ? (const char*)v->f32 : (const char*)v->search;
+    return RNSM_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct Events {
+    std::vector<hipEvent_t> ev;
+    ~Events() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t record(hipStream_t st, int* idx) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+        *idx = (int)ev.size() - 1;
+        return hipEventRecord(e, st);
+    }
+    float between(int a, int b) {
+        float ms = 0.f;
+        if (a >= 0 && b >= 0) (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
+        return ms;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* rnsm_last_error(void) { return g_err.c_str(); }
+
+rnsm_status rnsm_get_stats(rnsm_stats* out) {
+    if (!out) return fail(RNSM_EINVAL, "rnsm_get_stats: NULL");
+    *out = g_stats;
+    return RNSM_OK;
+}
+
+rnsm_status mos_plan(int32_t m, const int64_t* sizes, const double* centroids, int32_t dim,
+                     int32_t degree_bound, int32_t diameter, int32_t* out_ops, int32_t cap,
+                     int32_t* out_count, int32_t* out_fallbacks) {
+    g_err.clear();
+    if (m < 1 || !sizes || !out_ops || !out_count) return fail(RNSM_EINVAL, "mos_plan: bad arguments");
+    if (degree_bound < 1) return fail(RNSM_EINVAL, "mos_plan: degree_bound < 1");
+    if (diameter < 2) return fail(RNSM_EINVAL, "mos_plan: diameter < 2");
+    if (centroids && dim < 1) return fail(RNSM_EINVAL, "mos_plan: dim < 1 with centroids");
+    for (int i = 0; i < m; ++i)
+        if (sizes[i] < 1) return fail(RNSM_EINVAL, "mos_plan: size of sub-index %d < 1", i);
+    std::vector<std::pair<int, int>> ops;
+    int fb = 0;
+    if (plan_ops(m, sizes, centroids, dim, degree_bound, diameter, ops, &fb) != 0)
+        return fail(RNSM_EINTERNAL, "mos_plan: planner failed");
+    if ((int64_t)ops.size() > cap)
+        return fail(RNSM_EINVAL, "mos_plan: %d operations exceed cap %d", (int)ops.size(), cap);
+    for (size_t i = 0; i < ops.size(); ++i) {
+        out_ops[2 * i] = ops[i].first;
+        out_ops[2 * i + 1] = ops[i].second;
+    }
+    *out_count = (int32_t)ops.size();
+    if (out_fallbacks) *out_fallbacks = fb;
+    return RNSM_OK;
+}
+
+rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
+                       const rnsm_params* p, rnsm_csr* out) {
+    const auto t0 = std::chrono::steady_clock::now();
+    g_err.clear();
+    memset(&g_stats, 0, sizeof g_stats);
+    // ---------------------------------------------------- host argument checks
+    if (m < 2) return fail(RNSM_EINVAL, "rnsm_merge: m = %d < 2", m);
+    if (!graphs || !vecs || !p || !out) return fail(RNSM_EINVAL, "rnsm_merge: NULL argument");
+    if (!out->offsets || !out->nbrs) return fail(RNSM_EINVAL, "rnsm_merge: NULL output buffer");
+    const int R = p->R;
+    if (R < 1 || R > 64) return fail(RNSM_EINVAL, "rnsm_merge: R = %d outside 1..64", R);
+    if (p->L < 1 || p->L > 128) return fail(RNSM_EINVAL, "rnsm_merge: L = %d outside 1..128", p->L);
+    if (!(p->alpha >= 1.0f) || !std::isfinite(p->alpha))
+        return fail(RNSM_EINVAL, "rnsm_merge: alpha must be finite and >= 1");
+    if (p->metric < RNSM_L2SQ || p->metric > RNSM_COSINE)
+        return fail(RNSM_EINVAL, "rnsm_merge: unknown metric %d", (int)p->metric);
+    const int k = p->k_reverse ? p->k_reverse : 5;
+    const int kp = p->k_expand ? p->k_expand : 16;
+    if (k < 1 || kp < k || kp > 64)
+        return fail(RNSM_EINVAL, "rnsm_merge: need 1 <= k_reverse <= k_expand <= 64 (got %d, %d)", k, kp);
+    const int efN = p->ef_naive ? p->ef_naive : p->L;
+    const int efS = p->ef_slide ? p->ef_slide : p->L;
+    if (efN < 1 || efN > 128 || efS < 1 || efS > 128)
+        return fail(RNSM_EINVAL, "rnsm_merge: ef_naive / ef_slide outside 1..128");
+    const int diam = p->mos_diameter ? p->mos_diameter : 2;
+    if (diam < 2) return fail(RNSM_EINVAL, "rnsm_merge: mos_diameter < 2");
+    int rmos = p->mos_degree;
+    if (rmos < 0) return fail(RNSM_EINVAL, "rnsm_merge: mos_degree < 0");
+    if (rmos == 0) rmos = std::max(2, (int)std::ceil(std::sqrt((double)m)));
+    VecInfo vi;
+    rnsm_status vs = vec_info(vecs, vi);
+    if (vs != RNSM_OK) return vs;
+    std::vector<int64_t> sizes(m), bases(m);
+    int64_t N = 0;
+    for (int i = 0; i < m; ++i) {
+        const rnsm_graph& g = graphs[i];
+        if (g.n < 1) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d is empty", i);
+        if (!g.offsets || !g.nbrs) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d has a NULL CSR pointer", i);
+        if (g.entry < 0 || g.entry >= g.n)
+            return fail(RNSM_EINVAL, "rnsm_merge: entry %d of sub-index %d out of range", g.entry, i);
+        sizes[i] = g.n;
+        bases[i] = N;
+        N += g.n;
+    }
+    if (N != vecs->n) return fail(RNSM_EINVAL, "rnsm_merge: vectors hold %lld rows, graphs %lld",
+                                  (long long)vecs->n, (long long)N);
+    if (N >= (1ll << 31) - 1) return fail(RNSM_EUNSUPPORTED, "rnsm_merge: more than 2^31-2 vertices");
+
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)p->stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    Workspace& ws = g_ws[dev];
+    Events E;
+
+    // ------------------------------------------------ input graph validation
+    int* vflags;
+    WS(vflags, "vflags", sizeof(int) * m);
+    HIPCHK(hipMemsetAsync(vflags, 0, sizeof(int) * m, st));
+    std::vector<int64_t> nnz(m), first(m);
+    for (int i = 0; i < m; ++i) {
+        HIPCHK(hipMemcpyAsync(&first[i], graphs[i].offsets, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&nnz[i], graphs[i].offsets + graphs[i].n, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < m; ++i) {
+        if (first[i] != 0 || nnz[i] < 0)
+            return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: offsets[0] != 0 or offsets[n] < 0", i);
+        HIPCHK(launch_validate(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, nnz[i], R, vflags + i, st));
+    }
+    std::vector<int> hflags(m);
+    HIPCHK(hipMemcpyAsync(hflags.data(), vflags, sizeof(int) * m, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < m; ++i) {
+        const int f = hflags[i];
+        if (f & 1) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: offsets not non-decreasing", i);
+        if (f & 4) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: neighbour id out of range", i);
+        if (f & 8) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: self-loop", i);
+        if (f & 16) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: duplicate neighbour", i);
+        if (f & 2) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: degree above R = %d", i, R);
+    }
+
+    // ------------------------------------------------------------ workspace
+    int32_t *rows, *deg, *errf;
+    float *rdist, *norms = nullptr;
+    u64* cnt;
+    WS(rows, "rows", sizeof(int32_t) * N * R);
+    WS(deg, "deg", sizeof(int32_t) * N);
+    WS(rdist, "rdist", sizeof(float) * N * R);
+    WS(cnt, "counters", sizeof(u64) * 3 * CNT_N);
+    WS(errf, "errf", sizeof(int));
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * 3 * CNT_N, st));
+    HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
+    if (p->metric == RNSM_COSINE) {
+        WS(norms, "norms", sizeof(float) * N);
+        HIPCHK(launch_norms(vecs->f32, N, vecs->dim, norms, st));
+    }
+    for (int i = 0; i < m; ++i)
+        HIPCHK(launch_init_rows(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, bases[i], R, rows,
+                                deg, rdist, st));
+
+    // ----------------------------------------------------------------- plan
+    const auto tp = std::chrono::steady_clock::now();
+    std::vector<std::pair<int, int>> ops;
+    int fallbacks = 0;
+    std::vector<double> cent;
+    if (p->flags & RNSM_FLAG_CENTROID_COSTS) {
+        // centroids in float64, summed on the device
+        double* cs;
+        unsigned long long* csi;
+        int* flag;
+        u64* bb;
+        WS(cs, "centroid_sums", sizeof(double) * vecs->dim);
+        WS(csi, "centroid_isums", sizeof(unsigned long long) * vecs->dim);
+        WS(flag, "centroid_flag", sizeof(int));
+        WS(bb, "entry_best", sizeof(u64) * 3 * entry_blocks(1));
+        cent.assign((size_t)m * vecs->dim, 0.0);
+        for (int i = 0; i < m; ++i) {
+            const int one = 0;  // force the float64 path
+            HIPCHK(hipMemcpyAsync(flag, &one, sizeof(int), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemsetAsync(cs, 0, sizeof(double) * vecs->dim, st));
+            HIPCHK(launch_entry(vecs->f32 + bases[i] * vecs->dim, sizes[i], vecs->dim, flag, cs, csi,
+                                nullptr, 0, st));
+            HIPCHK(hipMemcpyAsync(cent.data() + (size_t)i * vecs->dim, cs, sizeof(double) * vecs->dim,
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int t = 0; t < vecs->dim; ++t) cent[(size_t)i * vecs->dim + t] /= (double)sizes[i];
+        }
+    }
+    if (plan_ops(m, sizes.data(), cent.empty() ? nullptr : cent.data(), vecs->dim, rmos, diam, ops,
+                 &fallbacks) != 0)
+        return fail(RNSM_EINTERNAL, "rnsm_merge: planner failed");
+    double ms_plan = ms_since(tp);
+
+    // ------------------------------------- expansion, inversion and pivots
+    std::vector<Pivots> piv(m);
+    std::vector<char> have(m, 0);
+    double ms_expand = 0.0, ms_search = 0.0, ms_prune = 0.0;
+    for (auto& op : ops) {
+        const int s = op.first;
+        if (have[s]) continue;
+        have[s] = 1;
+        const int64_t ns = sizes[s];
+        int32_t *nk, *rcnt, *rk_ids;
+        int64_t *rk_off, *stmp;
+        WS(nk, "nk", sizeof(int32_t) * ns * k);
+        WS(rcnt, "rk_cnt", sizeof(int32_t) * ns);
+        WS(rk_off, "rk_off", sizeof(int64_t) * (ns + 1));
+        WS(rk_ids, "rk_ids", sizeof(int32_t) * ns * k);
+        WS(stmp, "scan_tmp", sizeof(int64_t) * scan_tmp_elems(ns));
+        int e0, e1;
+        HIPCHK(E.record(st, &e0));
+        SearchArgs a = {};
+        a.base = vi.search + bases[s] * vi.row_bytes;
+        a.nch = vi.nch;
+        a.row_bytes = vi.row_bytes;
+        a.offs = graphs[s].offsets;
+        a.nbrs = graphs[s].nbrs;
+        a.n = ns;
+        a.qvec = a.base;
+        a.qidx = nullptr;
+        a.nq = ns;
+        a.seed_mode = 1;
+        a.metric = p->metric;
+        a.base_norm = norms ? norms + bases[s] : nullptr;
+        a.q_norm = a.base_norm;
+        a.ef = kp;
+        a.G = vi.G;
+        a.cpl = vi.cpl;
+        int wpb;
+        search_shape(kp, R, &a.hbits, &wpb);
+        a.out_mode = 1;
+        a.out_ids = nk;
+        a.out_stride = k;
+        a.out_k = k;
+        a.counters = cnt + 0 * CNT_N;
+        a.err = errf;
+        HIPCHK(launch_search(vi.tt, a, wpb, st));
+        HIPCHK(launch_invert(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
+        HIPCHK(E.record(st, &e1));
+        std::vector<int64_t> h_off(ns + 1);
+        HIPCHK(hipMemcpyAsync(h_off.data(), rk_off, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<int32_t> h_ids(h_off[ns] > 0 ? h_off[ns] : 1);
+        if (h_off[ns] > 0)
+            HIPCHK(hipMemcpy(h_ids.data(), rk_ids, sizeof(int32_t) * h_off[ns], hipMemcpyDeviceToHost));
+        ms_expand += E.between(e0, e1);
+        const auto tg = std::chrono::steady_clock::now();
+        if (p->flags & RNSM_FLAG_ALL_PIVOTS) {
+            piv[s].pivots.resize(ns);
+            for (int64_t v = 0; v < ns; ++v) piv[s].pivots[v] = (int32_t)v;
+        } else {
+            select_pivots(ns, h_off.data(), h_ids.data(), piv[s]);
+        }
+        ms_plan += ms_since(tg);
+    }
+
+    // ------------------------------------------------------- the operations
+    const int RES = std::max(efN, efS);
+    for (auto& op : ops) {
+        const int s = op.first, t = op.second;
+        const int64_t ns = sizes[s], nt = sizes[t];
+        const Pivots& P = piv[s];
+        const int64_t np = (int64_t)P.pivots.size(), nf = (int64_t)P.followers.size();
+        int32_t *d_piv, *d_fol, *d_folp, *res;
+        WS(d_piv, "pivots", sizeof(int32_t) * std::max<int64_t>(np, 1));
+        WS(d_fol, "followers", sizeof(int32_t) * std::max<int64_t>(nf, 1));
+        WS(d_folp, "follower_pivot", sizeof(int32_t) * std::max<int64_t>(nf, 1));
+        WS(res, "res", sizeof(int32_t) * ns * RES);
+        if (np) HIPCHK(hipMemcpyAsync(d_piv, P.pivots.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
+        if (nf) {
+            HIPCHK(hipMemcpyAsync(d_fol, P.followers.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(d_folp, P.follower_pivot.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, st));
+        }
+        HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));
+        int e0, e1, e2;
+        HIPCHK(E.record(st, &e0));
+        SearchArgs a = {};
+        a.base = vi.search + bases[t] * vi.row_bytes;
+        a.nch = vi.nch;
+        a.row_bytes = vi.row_bytes;
+        a.offs = graphs[t].offsets;
+        a.nbrs = graphs[t].nbrs;
+        a.n = nt;
+        a.qvec = vi.search + bases[s] * vi.row_bytes;
+        a.metric = p->metric;
+        a.base_norm = norms ? norms + bases[t] : nullptr;
+        a.q_norm = norms ? norms + bases[s] : nullptr;
+        a.G = vi.G;
+        a.cpl = vi.cpl;
+        a.out_mode = 0;
+        a.out_ids = res;
+        a.out_stride = RES;
+        a.err = errf;
+        int wpb;
+        // wave A: pivots, naive search from the target's entry point
+        a.qidx = d_piv;
+        a.nq = np;
+        a.seed_mode = 0;
+        a.entry = graphs[t].entry;
+        a.ef = efN;
+        a.out_k = efN;
+        a.out_row = d_piv;
+        a.counters = cnt + 1 * CNT_N;
+        search_shape(efN, R, &a.hbits, &wpb);
+        HIPCHK(launch_search(vi.tt, a, wpb, st));
+        // wave B: followers, local sliding from their pivot's results
+        a.qidx = d_fol;
+        a.nq = nf;
+        a.seed_mode = 2;
+        a.seed_ids = res;
+        a.seed_stride = RES;
+        a.seed_row = d_folp;
+        a.n_seeds = efN;
+        a.ef = efS;
+        a.out_k = efS;
+        a.out_row = d_fol;
+        a.counters = cnt + 2 * CNT_N;
+        search_shape(efS, R, &a.hbits, &wpb);
+        HIPCHK(launch_search(vi.tt, a, wpb, st));
+        HIPCHK(E.record(st, &e1));
+
+        // source rows: current row + search results, pruned to R
+        PruneArgs q = {};
+        q.X = vecs->f32;
+        q.n_total = N;
+        q.nch = vi.nch32;
+        q.G = vi.G32;
+        q.cpl = vi.cpl32;
+        q.metric = p->metric;
+        q.norms = norms;
+        q.n_items = ns;
+        q.item_base = bases[s];
+        q.rows_in = rows;
+        q.deg_in = deg;
+        q.extra_mode = 1;
+        q.extra_ids = res;
+        q.extra_stride = RES;
+        q.extra_cnt = RES;
+        q.extra_index_base = bases[s];
+        q.extra_id_add = bases[t];
+        q.alpha = p->alpha;
+        q.R = R;
+        q.rows_out = rows;
+        q.deg_out = deg;
+        q.dist_out = rdist;
+        q.wcap = R + RES;
+        q.err = errf;
+        HIPCHK(launch_prune(q, st));
+        // reverse edges into the target, then prune every target that got some
+        int32_t *rc, *rcur, *rev;
+        int64_t *roff, *stmp;
+        u64* scratch;
+        WS(rc, "rev_cnt", sizeof(int32_t) * nt);
+        WS(rcur, "rev_cur", sizeof(int32_t) * nt);
+        WS(roff, "rev_off", sizeof(int64_t) * (nt + 1));
+        WS(rev, "rev_ids", sizeof(int32_t) * std::max<int64_t>(ns * R, 1));
+        WS(stmp, "scan_tmp2", sizeof(int64_t) * scan_tmp_elems(nt));
+        WS(scratch, "prune_scratch", sizeof(u64) * (nt * R + ns * R));
+        HIPCHK(hipMemsetAsync(rc, 0, sizeof(int32_t) * nt, st));
+        HIPCHK(hipMemsetAsync(rcur, 0, sizeof(int32_t) * nt, st));
+        HIPCHK(launch_rev_count(rows, deg, bases[s], ns, R, bases[t], nt, rc, st));
+        HIPCHK(launch_scan(rc, nt, roff, stmp, st));
+        HIPCHK(launch_rev_scatter(rows, deg, bases[s], ns, R, bases[t], nt, roff, rcur, rev, st));
+        PruneArgs r = q;
+        r.n_items = nt;
+        r.item_base = bases[t];
+        r.extra_mode = 2;
+        r.extra_ids = rev;
+        r.extra_off = roff;
+        r.extra_index_base = bases[t];
+        r.extra_id_add = 0;
+        r.skip_empty_extra = 1;
+        r.scratch = scratch;
+        r.wcap = 256;
+        HIPCHK(launch_prune(r, st));
+        HIPCHK(E.record(st, &e2));
+        g_stats.n_followers += nf;
+        g_stats.n_pivots += np;
+        g_stats.n_source_vertices += ns;
+        (void)e2;
+        HIPCHK(hipStreamSynchronize(st));  // keeps event timings per operation simple
+        ms_search += E.between(e0, e1);
+        ms_prune += E.between(e1, e2);
+        int64_t nrev = 0;
+        HIPCHK(hipMemcpy(&nrev, roff + nt, sizeof(int64_t), hipMemcpyDeviceToHost));
+        g_stats.n_reverse_edges += nrev;
+    }
+
+    // ----------------------------------------------------------- compaction
+    int c0, c1;
+    HIPCHK(E.record(st, &c0));
+    int64_t* stmp3;
+    WS(stmp3, "scan_tmp3", sizeof(int64_t) * scan_tmp_elems(N));
+    HIPCHK(launch_scan(deg, N, out->offsets, stmp3, st));
+    HIPCHK(launch_compact(rows, deg, rdist, out->offsets, N, R, vecs->f32, vecs->dim, p->metric,
+                          norms, out->nbrs, out->dists, st));
+    HIPCHK(E.record(st, &c1));
+    int64_t nedges = 0;
+    u64 hc[3 * CNT_N];
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&nedges, out->offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (herr & 1) return fail(RNSM_EINTERNAL, "rnsm_merge: a search exceeded its iteration bound");
+    if (herr & 2) return fail(RNSM_EINTERNAL, "rnsm_merge: prune candidate list over capacity");
+
+    // merged entry: entry of the largest sub-index (ties: lowest index)
+    int big = 0;
+    for (int i = 1; i < m; ++i)
+        if (sizes[i] > sizes[big]) big = i;
+    out->entry = (int32_t)(bases[big] + graphs[big].entry);
+    out->n_edges = nedges;
+
+    rnsm_stats& S = g_stats;
+    S.ms_expand = ms_expand;
+    S.ms_plan = ms_plan;
+    S.ms_search = ms_search;
+    S.ms_prune = ms_prune;
+    S.ms_compact = E.between(c0, c1);
+    S.n_ops = (int64_t)ops.size();
+    S.ndc_expand = (int64_t)hc[0 * CNT_N + CNT_NDC];
+    S.ndc_naive = (int64_t)hc[1 * CNT_N + CNT_NDC];
+    S.ndc_slide = (int64_t)hc[2 * CNT_N + CNT_NDC];
+    S.exp_naive = (int64_t)hc[1 * CNT_N + CNT_EXP];
+    S.exp_slide = (int64_t)hc[2 * CNT_N + CNT_EXP];
+    S.adj_naive = (int64_t)hc[1 * CNT_N + CNT_ADJ];
+    S.adj_slide = (int64_t)hc[2 * CNT_N + CNT_ADJ];
+    S.hash_full = (int64_t)(hc[0 * CNT_N + CNT_HFULL] + hc[1 * CNT_N + CNT_HFULL] +
+                            hc[2 * CNT_N + CNT_HFULL]);
+    S.search_launches = 2 * (int64_t)ops.size();
+    // algorithmic bytes of the searches: every distance reads one row, every
+    // expansion reads two offsets and its adjacency, every query reads its
+    // row and writes its beam, followers read their pivot's beam
+    const double rb = vi.row_bytes;
+    S.search_bytes = (double)(S.ndc_naive + S.ndc_slide) * rb +
+                     (double)(S.exp_naive + S.exp_slide) * 16.0 +
+                     (double)(S.adj_naive + S.adj_slide) * 4.0 +
+                     (double)S.n_source_vertices * (rb + 4.0 * RES) +
+                     (double)S.n_followers * 4.0 * efN;
+    S.ms_total = ms_since(t0);
+    (void)fallbacks;
+    return RNSM_OK;
+}
+
+rnsm_status rnsm_merge_simple(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
+                              int32_t R, int32_t L, float alpha, rnsm_csr* out) {
+    rnsm_params p;
+    memset(&p, 0, sizeof p);
+    p.R = R;
+    p.L = L;
+    p.alpha = alpha;
+    p.metric = RNSM_L2SQ;
+    if (!vecs) return fail(RNSM_EINVAL, "rnsm_merge_simple: NULL vectors");
+    rnsm_vectors v = *vecs;
+    v.search_dtype = RNSM_F32;
+    v.search = nullptr;
+    return rnsm_merge(m, graphs, &v, &p, out);
+}
+
+rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const void* queries,
+                        int64_t nq, const int32_t* seeds, int32_t n_seeds, int32_t ef, int32_t k,
+                        rnsm_metric metric, int32_t* out_ids, float* out_dists, void* stream) {
+    g_err.clear();
+    if (!g || !base || !out_ids || (nq > 0 && !queries))
+        return fail(RNSM_EINVAL, "rnsm_search: NULL argument");
+    if (ef < 1 || ef > 128) return fail(RNSM_EINVAL, "rnsm_search: ef outside 1..128");
+    if (k < 1 || k > ef) return fail(RNSM_EINVAL, "rnsm_search: k outside 1..ef");
+    if (metric < RNSM_L2SQ || metric > RNSM_COSINE) return fail(RNSM_EINVAL, "rnsm_search: metric");
+    if (seeds && n_seeds < 1) return fail(RNSM_EINVAL, "rnsm_search: n_seeds < 1");
+    if (g->n < 1 || !g->offsets || !g->nbrs || base->n != g->n)
+        return fail(RNSM_EINVAL, "rnsm_search: graph / base mismatch");
+    if (!seeds && (g->entry < 0 || g->entry >= g->n)) return fail(RNSM_EINVAL, "rnsm_search: entry");
+    VecInfo vi;
+    rnsm_status vs = vec_info(base, vi);
+    if (vs != RNSM_OK) return vs;
+    if (nq == 0) return RNSM_OK;
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    Workspace& ws = g_ws[dev];
+    u64* cnt;
+    int* errf;
+    float *bn = nullptr, *qn = nullptr;
+    WS(cnt, "search_counters", sizeof(u64) * CNT_N);
+    WS(errf, "search_err", sizeof(int));
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * CNT_N, st));
+    HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
+    if (metric == RNSM_COSINE) {
+        if (base->search_dtype != RNSM_F32)
+            return fail(RNSM_EUNSUPPORTED, "rnsm_search: cosine needs a float32 search copy here");
+        WS(bn, "search_bnorm", sizeof(float) * g->n);
+        WS(qn, "search_qnorm", sizeof(float) * nq);
+        HIPCHK(launch_norms(base->f32, g->n, base->dim, bn, st));
+        HIPCHK(launch_norms((const float*)queries, nq, base->dim, qn, st));
+    }
+    SearchArgs a = {};
+    a.base = vi.search;
+    a.nch = vi.nch;
+    a.row_bytes = vi.row_bytes;
+    a.offs = g->offsets;
+    a.nbrs = g->nbrs;
+    a.n = g->n;
+    a.qvec = (const char*)queries;
+    a.nq = nq;
+    a.seed_mode = seeds ? 2 : 0;
+    a.entry = g->entry;
+    a.seed_ids = seeds;
+    a.seed_stride = n_seeds;
+    a.n_seeds = seeds ? n_seeds : 0;
+    a.metric = metric;
+    a.base_norm = bn;
+    a.q_norm = qn;
+    a.ef = ef;
+    a.G = vi.G;
+    a.cpl = vi.cpl;
+    int wpb;
+    search_shape(ef, 32, &a.hbits, &wpb);
+    a.out_mode = 0;
+    a.out_ids = out_ids;
+    a.out_d = out_dists;
+    a.out_stride = k;
+    a.out_k = k;
+    a.counters = cnt;
+    a.err = errf;
+    HIPCHK(launch_search(vi.tt, a, wpb, st));
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (herr) return fail(RNSM_EINTERNAL, "rnsm_search: a search exceeded its iteration bound");
+    return RNSM_OK;
+}
+
+rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric metric,
+                             const int32_t* knn, int32_t K, int32_t R, float alpha,
+                             int32_t reverse, float alpha_rev, int64_t* out_offsets,
+                             int32_t* out_nbrs, int32_t* out_entry, void* stream) {
+    g_err.clear();
+    if (n < 1 || !X || !knn || !out_offsets || !out_nbrs || !out_entry)
+        return fail(RNSM_EINVAL, "rnsm_build_graph: bad argument");
+    if (K < 1 || R < 1 || R > 64) return fail(RNSM_EINVAL, "rnsm_build_graph: K < 1 or R outside 1..64");
+    if (!(alpha >= 1.0f) || (reverse && !(alpha_rev >= 1.0f)))
+        return fail(RNSM_EINVAL, "rnsm_build_graph: alpha < 1");
+    if (metric < RNSM_L2SQ || metric > RNSM_COSINE) return fail(RNSM_EINVAL, "rnsm_build_graph: metric");
+    if (dim < 1 || (dim % 4) != 0) return fail(RNSM_EUNSUPPORTED, "rnsm_build_graph: dim must be a multiple of 4");
+    const int nch = dim / 4, G = lanes_per_row(nch);
+    if (G < 0) return fail(RNSM_EUNSUPPORTED, "rnsm_build_graph: dim too large");
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    Workspace& ws = g_ws[dev];
+    int32_t *rows1, *deg1, *rows2, *deg2, *rc, *rcur, *rev, *errf;
+    float *d1, *d2, *norms = nullptr;
+    int64_t *roff, *stmp;
+    u64* scratch;
+    WS(rows1, "b_rows1", sizeof(int32_t) * n * R);
+    WS(deg1, "b_deg1", sizeof(int32_t) * n);
+    WS(d1, "b_d1", sizeof(float) * n * R);
+    WS(errf, "b_err", sizeof(int));
+    HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
+    if (metric == RNSM_COSINE) {
+        WS(norms, "b_norms", sizeof(float) * n);
+        HIPCHK(launch_norms(X, n, dim, norms, st));
+    }
+    PruneArgs q = {};
+    q.X = X;
+    q.n_total = n;
+    q.nch = nch;
+    q.G = G;
+    q.cpl = (nch + G - 1) / G;
+    q.metric = metric;
+    q.norms = norms;
+    q.n_items = n;
+    q.item_base = 0;
+    q.extra_mode = 1;
+    q.extra_ids = knn;
+    q.extra_stride = K;
+    q.extra_cnt = K;
+    q.alpha = alpha;
+    q.R = R;
+    q.rows_out = rows1;
+    q.deg_out = deg1;
+    q.dist_out = d1;
+    q.wcap = K;
+    q.err = errf;
+    HIPCHK(launch_prune(q, st));
+    int32_t *rows = rows1, *deg = deg1;
+    if (reverse) {
+        WS(rows2, "b_rows2", sizeof(int32_t) * n * R);
+        WS(deg2, "b_deg2", sizeof(int32_t) * n);
+        WS(d2, "b_d2", sizeof(float) * n * R);
+        WS(rc, "b_rc", sizeof(int32_t) * n);
+        WS(rcur, "b_rcur", sizeof(int32_t) * n);
+        WS(roff, "b_roff", sizeof(int64_t) * (n + 1));
+        WS(rev, "b_rev", sizeof(int32_t) * n * R);
+        WS(stmp, "b_stmp", sizeof(int64_t) * scan_tmp_elems(n));
+        WS(scratch, "b_scratch", sizeof(u64) * 2 * n * R);
+        HIPCHK(hipMemsetAsync(rc, 0, sizeof(int32_t) * n, st));
+        HIPCHK(hipMemsetAsync(rcur, 0, sizeof(int32_t) * n, st));
+        HIPCHK(launch_rev_count(rows1, deg1, 0, n, R, 0, n, rc, st));
+        HIPCHK(launch_scan(rc, n, roff, stmp, st));
+        HIPCHK(launch_rev_scatter(rows1, deg1, 0, n, R, 0, n, roff, rcur, rev, st));
+        PruneArgs r = q;
+        r.rows_in = rows1;
+        r.deg_in = deg1;
+        r.extra_mode = 2;
+        r.extra_ids = rev;
+        r.extra_off = roff;
+        r.extra_index_base = 0;
+        r.skip_empty_extra = 1;
+        r.alpha = alpha_rev;
+        r.rows_out = rows2;
+        r.deg_out = deg2;
+        r.dist_out = d2;
+        r.scratch = scratch;
+        r.wcap = 256;
+        HIPCHK(launch_prune(r, st));
+        HIPCHK(launch_copy_rows(rows1, deg1, d1, rc, n, R, rows2, deg2, d2, st));
+        rows = rows2;
+        deg = deg2;
+    }
+    int64_t* stmp3;
+    WS(stmp3, "b_stmp3", sizeof(int64_t) * scan_tmp_elems(n));
+    HIPCHK(launch_scan(deg, n, out_offsets, stmp3, st));
+    HIPCHK(launch_compact(rows, deg, d1, out_offsets, n, R, X, dim, metric, norms, out_nbrs, nullptr, st));
+    // entry: closest to the centroid
+    int* flag;
+    double* cs;
+    unsigned long long* csi;
+    u64* bb;
+    const int64_t nb = entry_blocks(n);
+    WS(flag, "b_flag", sizeof(int));
+    WS(cs, "b_cs", sizeof(double) * dim);
+    WS(csi, "b_csi", sizeof(unsigned long long) * dim);
+    WS(bb, "b_best", sizeof(u64) * 3 * nb);
+    const int one = 1;
+    HIPCHK(hipMemcpyAsync(flag, &one, sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(cs, 0, sizeof(double) * dim, st));
+    HIPCHK(hipMemsetAsync(csi, 0, sizeof(unsigned long long) * dim, st));
+    HIPCHK(launch_entry(X, n, dim, flag, cs, csi, bb, nb, st));
+    std::vector<u64> hb(3 * nb);
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(hb.data(), bb, sizeof(u64) * 3 * nb, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (herr & 4) return fail(RNSM_EINVAL, "rnsm_build_graph: a k-NN id is out of range");
+    if (herr) return fail(RNSM_EINTERNAL, "rnsm_build_graph: prune candidate list over capacity");
+    int64_t best = 0;
+    for (int64_t b = 1; b < nb; ++b) {
+        const u64* x = &hb[3 * b];
+        const u64* y = &hb[3 * best];
+        if (x[0] < y[0] || (x[0] == y[0] && (x[1] < y[1] || (x[1] == y[1] && x[2] < y[2])))) best = b;
+    }
+    *out_entry = (int32_t)hb[3 * best + 2];
+    return RNSM_OK;
+}
+
+}  // extern "C"

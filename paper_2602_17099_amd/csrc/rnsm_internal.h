@@ -1,0 +1,117 @@
+// Internal interface between the host orchestration (rnsm_api.cpp) and the
+// device kernels (rnsm_kernels.hip). Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rnsm {
+
+typedef unsigned long long u64;
+
+// counters the search kernel accumulates (one atomic per wavefront)
+enum { CNT_NDC = 0, CNT_EXP = 1, CNT_ADJ = 2, CNT_HFULL = 3, CNT_N = 4 };
+
+struct SearchArgs {
+    const char* base;         // target rows, search storage type, row r at base + r*row_bytes
+    int nch;                  // 16-byte chunks per row
+    int row_bytes;
+    const int64_t* offs;      // target CSR
+    const int32_t* nbrs;
+    int64_t n;                // target size
+    const char* qvec;         // query rows (same storage type), row u at qvec + u*row_bytes
+    const int32_t* qidx;      // query i uses row qidx[i] (NULL: row i)
+    int64_t nq;
+    int seed_mode;            // 0: entry, 1: the query's own row id, 2: seed rows
+    int32_t entry;
+    const int32_t* seed_ids;  // mode 2: row seed_row[i] (NULL: row i) of seed_stride ids, n_seeds used
+    int64_t seed_stride;
+    const int32_t* seed_row;
+    int n_seeds;
+    int metric;
+    const float* base_norm;   // cosine: norms of target rows
+    const float* q_norm;      // cosine: norms of query rows (indexed like the query row)
+    int ef;
+    int G;                    // lanes per row
+    int cpl;                  // chunks per lane
+    int hbits;                // log2 of the LDS visited-table size per wavefront
+    int out_mode;             // 0: first out_k of the beam, 1: first out_k excluding the query's own id
+    int32_t* out_ids;
+    float* out_d;
+    int64_t out_stride;
+    int out_k;
+    const int32_t* out_row;   // output row of query i (NULL: i)
+    u64* counters;            // CNT_N entries
+    int* err;
+};
+
+struct PruneArgs {
+    const float* X;           // float32 rows of every vertex (global ids)
+    int64_t n_total;          // number of rows of X (ids >= n_total are rejected)
+    int nch;
+    int G;
+    int cpl;
+    int metric;
+    const float* norms;
+    int64_t n_items;
+    const int32_t* items;     // item i -> vertex items[i] (NULL: item_base + i)
+    int64_t item_base;
+    const int32_t* rows_in;   // [* x R] current rows, indexed by vertex (NULL: empty rows)
+    const int32_t* deg_in;
+    int extra_mode;           // 0: none, 1: fixed stride, 2: CSR
+    const int32_t* extra_ids;
+    int64_t extra_stride;
+    int extra_cnt;
+    const int64_t* extra_off;
+    int64_t extra_index_base; // extra row of vertex p is p - extra_index_base
+    int64_t extra_id_add;     // added to every extra id (-1 entries skipped)
+    int skip_empty_extra;     // leave rows without extra candidates untouched
+    float alpha;
+    int R;
+    int32_t* rows_out;
+    int32_t* deg_out;
+    float* dist_out;
+    u64* scratch;             // keys of candidate lists longer than wcap (mode 2)
+    int wcap;
+    int* err;
+};
+
+// launchers (all asynchronous on `st`)
+hipError_t launch_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t nnz,
+                           int R, int* flags, hipStream_t st);
+hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
+                            int R, int32_t* rows, int32_t* deg, float* rdist, hipStream_t st);
+hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st);
+hipError_t launch_search(int tt, const SearchArgs& a, int waves_per_block, hipStream_t st);
+hipError_t launch_prune(const PruneArgs& a, hipStream_t st);
+hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* off, int64_t* tmp_blocks,
+                       hipStream_t st);
+size_t scan_tmp_elems(int64_t n);
+hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int64_t* rk_off,
+                         int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st);
+hipError_t launch_rev_count(const int32_t* rows, const int32_t* deg, int64_t s_base, int64_t n_s,
+                            int R, int64_t t_base, int64_t n_t, int32_t* cnt, hipStream_t st);
+hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, int64_t s_base,
+                              int64_t n_s, int R, int64_t t_base, int64_t n_t,
+                              const int64_t* off, int32_t* cur, int32_t* rev, hipStream_t st);
+hipError_t launch_max_i32(const int32_t* v, int64_t n, int32_t* out, hipStream_t st);
+hipError_t launch_compact(const int32_t* rows, const int32_t* deg, const float* rdist,
+                          const int64_t* off, int64_t N, int R, const float* X, int dim,
+                          int metric, const float* norms, int32_t* out_nbrs, float* out_dists,
+                          hipStream_t st);
+hipError_t launch_copy_rows(const int32_t* rows_a, const int32_t* deg_a, const float* dist_a,
+                            const int32_t* cnt, int64_t n, int R, int32_t* rows_b,
+                            int32_t* deg_b, float* dist_b, hipStream_t st);
+hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* colsum_d,
+                        unsigned long long* colsum_i, u64* block_best, int64_t nblocks,
+                        hipStream_t st);
+int64_t entry_blocks(int64_t n);
+
+// choice of lanes per row for rows of nch 16-byte chunks (chunks per lane <= 4)
+inline int lanes_per_row(int nch) {
+    int need = (nch + 3) / 4;
+    int g = 1;
+    while (g < need) g <<= 1;
+    return g > 64 ? -1 : g;
+}
+
+}  // namespace rnsm

@@ -1,0 +1,1107 @@
+// Device kernels of the RNSM merge path for gfx950 (CDNA4, 64-lane
+// wavefronts).
+//
+//  - k_beam_search: Algorithm 1 (Section 2.2), one wavefront per query. The
+//    beam is a sorted array of 64-bit keys (order-preserving float bits of
+//    the distance << 32 | id) held one or two per lane; the nearest
+//    unexpanded entry is found with a ballot; new entries are placed with a
+//    ballot-count and a one-lane shift. The visited set is an open-addressing
+//    table in LDS; when a probe sequence is full the vertex is evaluated
+//    again and an exact key match in the beam drops the duplicate, which
+//    leaves the final beam unchanged (a re-evaluated vertex that is not in
+//    the beam has a key above the current worst, because the worst key of a
+//    full beam only decreases). Distances: G lanes per row, 16-byte
+//    coalesced loads, float32 accumulation, butterfly reduction.
+//  - k_prune: the edge-selection rule of Section 2.2 as used by UpdateGraph
+//    (Section 4.2): candidates are extracted in (distance, id) order by a
+//    wavefront min-reduction; each one is tested against the kept rows,
+//    which stay in registers.
+//  - reverse-edge count/scatter, reverse k-NN inversion, scans, compaction,
+//    input validation and the builder's entry point.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rnsm_internal.h"
+
+namespace rnsm {
+
+#define WAVE 64
+#define MAXCPL 4
+#define EMPTY_KEY (~0ull)
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ unsigned fkey(float d) {
+    d = d + 0.0f;  // -0 -> +0
+    unsigned u = __float_as_uint(d);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float fval(unsigned k) {
+    unsigned u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+__device__ __forceinline__ u64 make_key(float d, int id) {
+    return ((u64)fkey(d) << 32) | (unsigned)id;
+}
+__device__ __forceinline__ u64 readlane64(u64 x, int l) {
+    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x & 0xffffffffu), l);
+    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+    return ((u64)hi << 32) | lo;
+}
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+__device__ __forceinline__ u64 lanemask_lt(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+__device__ __forceinline__ u64 wave_min_u64(u64 x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        u64 o = __shfl_xor(x, off);
+        x = o < x ? o : x;
+    }
+    return x;
+}
+__device__ __forceinline__ float group_sum(float acc, int G) {
+    for (int off = G >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    return acc;
+}
+
+// blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical blocks so that neighbouring work items share
+// one L2
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t x = b & 7, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// 16-byte chunk -> floats (f32: 4 values, bf16 / f16: 8 values)
+template <int TT>
+struct Elt {
+    static constexpr int EPC = TT == 0 ? 4 : 8;
+};
+
+template <int TT>
+__device__ __forceinline__ void cvt_chunk(const uint4 r, float* f) {
+    if constexpr (TT == 0) {
+        f[0] = __uint_as_float(r.x);
+        f[1] = __uint_as_float(r.y);
+        f[2] = __uint_as_float(r.z);
+        f[3] = __uint_as_float(r.w);
+    } else if constexpr (TT == 1) {
+        const unsigned w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f[2 * i] = __uint_as_float(w[i] << 16);
+            f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+    } else {
+        const unsigned w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            union { unsigned short s; _Float16 h; } lo, hi;
+            lo.s = (unsigned short)(w[i] & 0xffffu);
+            hi.s = (unsigned short)(w[i] >> 16);
+            f[2 * i] = (float)lo.h;
+            f[2 * i + 1] = (float)hi.h;
+        }
+    }
+}
+
+__device__ __forceinline__ float finalize_dist(float acc, int metric, float na, float nb) {
+    if (metric == 0) return acc;
+    if (metric == 1) return 1.0f - acc;
+    return 1.0f - acc / (na * nb);
+}
+
+// ------------------------------------------------------------ beam search
+
+template <int EFS>
+struct Beam {
+    u64 k[EFS];
+    unsigned e[EFS];  // expanded flag
+};
+
+template <int EFS>
+__device__ __forceinline__ u64 beam_worst(const Beam<EFS>& B, int ef) {
+    const int s = ef - 1;
+    if constexpr (EFS == 1) {
+        return readlane64(B.k[0], s);
+    } else {
+        return (s >= 64) ? readlane64(B.k[1], s - 64) : readlane64(B.k[0], s);
+    }
+}
+
+// insert key into the sorted beam of capacity ef; drops exact duplicates
+template <int EFS>
+__device__ __forceinline__ void beam_insert(Beam<EFS>& B, u64 key, int ef, int lane) {
+    u64 lt = __ballot(B.k[0] < key);
+    u64 eq = __ballot(B.k[0] == key);
+    int pos = __popcll(lt);
+    if constexpr (EFS == 2) {
+        lt = __ballot(B.k[1] < key);
+        eq |= __ballot(B.k[1] == key);
+        pos += __popcll(lt);
+    }
+    if (eq != 0ull || pos >= ef) return;
+    if constexpr (EFS == 1) {
+        u64 up = __shfl_up(B.k[0], 1);
+        unsigned eup = __shfl_up(B.e[0], 1);
+        if (lane > pos) {
+            B.k[0] = up;
+            B.e[0] = eup;
+        } else if (lane == pos) {
+            B.k[0] = key;
+            B.e[0] = 0;
+        }
+        if (lane >= ef) {
+            B.k[0] = EMPTY_KEY;
+            B.e[0] = 0;
+        }
+    } else {
+        const u64 a63 = readlane64(B.k[0], 63);
+        const unsigned e63 = (unsigned)__builtin_amdgcn_readlane((int)B.e[0], 63);
+        u64 upa = __shfl_up(B.k[0], 1);
+        unsigned eupa = __shfl_up(B.e[0], 1);
+        u64 upb = __shfl_up(B.k[1], 1);
+        unsigned eupb = __shfl_up(B.e[1], 1);
+        if (lane > pos) {
+            B.k[0] = upa;
+            B.e[0] = eupa;
+        } else if (lane == pos) {
+            B.k[0] = key;
+            B.e[0] = 0;
+        }
+        const int sb = 64 + lane;
+        const u64 pb = lane == 0 ? a63 : upb;
+        const unsigned peb = lane == 0 ? e63 : eupb;
+        if (sb > pos) {
+            B.k[1] = pb;
+            B.e[1] = peb;
+        } else if (sb == pos) {
+            B.k[1] = key;
+            B.e[1] = 0;
+        }
+        if (sb >= ef) {
+            B.k[1] = EMPTY_KEY;
+            B.e[1] = 0;
+        }
+    }
+}
+
+// 0: already visited, 1: newly visited, 2: table full along the probe path
+__device__ __forceinline__ int hash_visit(int* tab, int hbits, int v) {
+    const unsigned mask = (1u << hbits) - 1u;
+    unsigned h = ((unsigned)v * 2654435761u) >> (32 - hbits);
+#pragma unroll 1
+    for (int p = 0; p < 16; ++p) {
+        int old = atomicCAS(&tab[(h + p) & mask], -1, v);
+        if (old == -1) return 1;
+        if (old == v) return 0;
+    }
+    return 2;
+}
+
+template <int TT>
+struct Query {
+    float q[MAXCPL][Elt<TT>::EPC];
+};
+
+// evaluate the per-lane candidates v (-1: none): visited filter, distances,
+// beam insertion
+template <int TT, int EFS>
+__device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS>& B,
+                                                   const Query<TT>& Q, float qn, int* tab,
+                                                   int* cl, int v, int lane, u64& ndc,
+                                                   u64& hfull) {
+    constexpr int EPC = Elt<TT>::EPC;
+    int st = 0;
+    if (v >= a.n) v = -1;  // ids from callers are range-checked
+    if (v >= 0) st = hash_visit(tab, a.hbits, v);
+    const u64 full = __ballot(st == 2);
+    hfull += __popcll(full);
+    const u64 m = __ballot(st != 0);
+    const int nc = __popcll(m);
+    if (nc == 0) return;
+    if (st != 0) cl[__popcll(m & lanemask_lt(lane))] = v;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    ndc += nc;
+    const int G = a.G, RPP = WAVE / G;
+    const int group = lane / G, sub = lane - group * G;
+    constexpr int UNR = 4;
+    for (int c0 = 0; c0 < nc; c0 += RPP * UNR) {
+        uint4 raw[UNR][MAXCPL];
+        int cid[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int c = c0 + u * RPP + group;
+            cid[u] = c < nc ? cl[c] : -1;
+            const char* row = a.base + (int64_t)(cid[u] < 0 ? 0 : cid[u]) * a.row_bytes;
+#pragma unroll
+            for (int j = 0; j < MAXCPL; ++j) {
+                const int ch = sub + j * G;
+                if (cid[u] >= 0 && j < a.cpl && ch < a.nch)
+                    raw[u][j] = *(const uint4*)(row + (int64_t)ch * 16);
+                else
+                    raw[u][j] = make_uint4(0, 0, 0, 0);
+            }
+        }
+        u64 key[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int j = 0; j < MAXCPL; ++j) {
+                float x[EPC];
+                cvt_chunk<TT>(raw[u][j], x);
+                if (a.metric == 0) {
+#pragma unroll
+                    for (int t = 0; t < EPC; ++t) {
+                        const float d = Q.q[j][t] - x[t];
+                        acc = fmaf(d, d, acc);
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < EPC; ++t) acc = fmaf(Q.q[j][t], x[t], acc);
+                }
+            }
+            acc = group_sum(acc, G);
+            float nb = 1.0f;
+            if (a.metric == 2 && cid[u] >= 0) nb = a.base_norm[cid[u]];
+            const float d = finalize_dist(acc, a.metric, qn, nb);
+            key[u] = (cid[u] >= 0 && sub == 0) ? make_key(d, cid[u]) : EMPTY_KEY;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const u64 worst = beam_worst(B, a.ef);
+            u64 mm = __ballot(key[u] < worst);
+            while (mm) {
+                const int l = __ffsll((long long)mm) - 1;
+                mm &= mm - 1;
+                const u64 kk = readlane64(key[u], l);
+                beam_insert(B, kk, a.ef, lane);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int TT, int EFS>
+__global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
+    extern __shared__ int smem[];
+    constexpr int EPC = Elt<TT>::EPC;
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int64_t i = xcd_block() * wpb + wib;
+    if (i >= a.nq) return;
+    const int H = 1 << a.hbits;
+    int* tab = smem + wib * (H + WAVE);
+    int* cl = tab + H;
+    for (int t = lane; t < H; t += WAVE) tab[t] = -1;
+    __builtin_amdgcn_wave_barrier();
+
+    const int u = a.qidx ? a.qidx[i] : (int)i;
+    const char* qrow = a.qvec + (int64_t)u * a.row_bytes;
+    const int G = a.G;
+    const int group = lane / G, sub = lane - group * G;
+    (void)group;
+    Query<TT> Q;
+#pragma unroll
+    for (int j = 0; j < MAXCPL; ++j) {
+        const int ch = sub + j * G;
+        uint4 r = make_uint4(0, 0, 0, 0);
+        if (j < a.cpl && ch < a.nch) r = *(const uint4*)(qrow + (int64_t)ch * 16);
+        cvt_chunk<TT>(r, Q.q[j]);
+    }
+    const float qn = a.metric == 2 ? a.q_norm[u] : 1.0f;
+
+    Beam<EFS> B;
+#pragma unroll
+    for (int s = 0; s < EFS; ++s) {
+        B.k[s] = EMPTY_KEY;
+        B.e[s] = 0;
+    }
+    u64 ndc = 0, nexp = 0, nadj = 0, hfull = 0;
+
+    // seeds
+    if (a.seed_mode == 0 || a.seed_mode == 1) {
+        const int s0 = a.seed_mode == 0 ? a.entry : u;
+        process_candidates<TT, EFS>(a, B, Q, qn, tab, cl, lane == 0 ? s0 : -1, lane, ndc, hfull);
+    } else {
+        const int64_t srow = a.seed_row ? a.seed_row[i] : i;
+        const int32_t* sp = a.seed_ids + srow * a.seed_stride;
+        for (int j0 = 0; j0 < a.n_seeds; j0 += WAVE) {
+            const int j = j0 + lane;
+            const int v = j < a.n_seeds ? sp[j] : -1;
+            process_candidates<TT, EFS>(a, B, Q, qn, tab, cl, v, lane, ndc, hfull);
+        }
+    }
+
+    // expand the nearest unexpanded entry until every entry is expanded
+    const int64_t maxit = a.n + 2;
+    for (int64_t it = 0;; ++it) {
+        u64 m0 = __ballot(B.k[0] != EMPTY_KEY && B.e[0] == 0u);
+        int s;
+        if (m0) {
+            s = __ffsll((long long)m0) - 1;
+        } else {
+            if constexpr (EFS == 2) {
+                u64 m1 = __ballot(B.k[1] != EMPTY_KEY && B.e[1] == 0u);
+                if (!m1) break;
+                s = 64 + __ffsll((long long)m1) - 1;
+            } else {
+                break;
+            }
+        }
+        int uid;
+        if (s < 64) {
+            if (lane == s) B.e[0] = 1u;
+            uid = __builtin_amdgcn_readlane((int)(unsigned)(B.k[0] & 0xffffffffu), s);
+        } else {
+            if constexpr (EFS == 2) {
+                if (lane == s - 64) B.e[1] = 1u;
+                uid = __builtin_amdgcn_readlane((int)(unsigned)(B.k[1] & 0xffffffffu), s - 64);
+            } else {
+                uid = 0;
+            }
+        }
+        ++nexp;
+        const int64_t b = a.offs[uid], en = a.offs[uid + 1];
+        nadj += (u64)(en - b);
+        for (int64_t j0 = b; j0 < en; j0 += WAVE) {
+            const int64_t j = j0 + lane;
+            const int v = j < en ? a.nbrs[j] : -1;
+            process_candidates<TT, EFS>(a, B, Q, qn, tab, cl, v, lane, ndc, hfull);
+        }
+        if (it > maxit) {
+            if (lane == 0) atomicOr(a.err, 1);
+            break;
+        }
+    }
+
+    // write the result
+    const int64_t orow = a.out_row ? a.out_row[i] : i;
+    int32_t* oi = a.out_ids + orow * a.out_stride;
+    float* od = a.out_d ? a.out_d + orow * a.out_stride : nullptr;
+    if (a.out_mode == 0) {
+#pragma unroll
+        for (int s = 0; s < EFS; ++s) {
+            const int slot = s * 64 + lane;
+            if (slot < a.out_k) {
+                const u64 kk = B.k[s];
+                oi[slot] = kk != EMPTY_KEY ? (int)(unsigned)(kk & 0xffffffffu) : -1;
+                if (od) od[slot] = kk != EMPTY_KEY ? fval((unsigned)(kk >> 32)) : INFINITY;
+            }
+        }
+    } else {
+        const u64 kk = B.k[0];
+        const bool valid = kk != EMPTY_KEY;
+        const bool self = valid && (int)(unsigned)(kk & 0xffffffffu) == u;
+        const u64 sm = __ballot(self);
+        const int cnt = __popcll(__ballot(valid && !self));
+        const int pos = lane - __popcll(sm & lanemask_lt(lane));
+        if (valid && !self && pos < a.out_k) {
+            oi[pos] = (int)(unsigned)(kk & 0xffffffffu);
+            if (od) od[pos] = fval((unsigned)(kk >> 32));
+        }
+        if (lane >= cnt && lane < a.out_k) {
+            oi[lane] = -1;
+            if (od) od[lane] = INFINITY;
+        }
+    }
+    if (lane == 0) {
+        atomicAdd(&a.counters[CNT_NDC], ndc);
+        atomicAdd(&a.counters[CNT_EXP], nexp);
+        atomicAdd(&a.counters[CNT_ADJ], nadj);
+        atomicAdd(&a.counters[CNT_HFULL], hfull);
+    }
+}
+
+// ------------------------------------------------------------------ prune
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
+    extern __shared__ unsigned char psm[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int64_t i = xcd_block() * wpb + wib;
+    if (i >= a.n_items) return;
+    u64* lkeys = (u64*)psm + (int64_t)wib * (a.wcap + a.R);
+    int* kept_ids = (int*)(lkeys + a.wcap);
+    const int64_t p = a.items ? (int64_t)a.items[i] : a.item_base + i;
+    const int64_t e = p - a.extra_index_base;
+    const int R = a.R;
+
+    const int nrow = a.rows_in ? a.deg_in[p] : 0;
+    int next = 0;
+    int64_t xo = 0;
+    if (a.extra_mode == 1) {
+        next = a.extra_cnt;
+        xo = e * a.extra_stride;
+    } else if (a.extra_mode == 2) {
+        xo = a.extra_off[e];
+        next = (int)(a.extra_off[e + 1] - xo);
+    }
+    if (a.skip_empty_extra && next == 0) return;
+    const int nW = nrow + next;
+    u64* wk = lkeys;
+    if (nW > a.wcap) {
+        if (a.extra_mode != 2 || !a.scratch) {
+            if (lane == 0) atomicOr(a.err, 2);
+            return;
+        }
+        wk = a.scratch + (int64_t)R * e + xo;
+    }
+    // gather candidate ids
+    for (int t = lane; t < nW; t += WAVE) {
+        int64_t id;
+        if (t < nrow) {
+            id = a.rows_in[p * R + t];
+        } else {
+            const int32_t x = a.extra_ids[xo + (t - nrow)];
+            id = x < 0 ? -1 : (int64_t)x + a.extra_id_add;
+        }
+        if (id >= a.n_total) {  // ids from callers are range-checked
+            atomicOr(a.err, 4);
+            id = -1;
+        }
+        wk[t] = (id < 0 || id == p) ? EMPTY_KEY : (u64)id;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    const int G = a.G, RPP = WAVE / G;
+    const int group = lane / G, sub = lane - group * G;
+    const int rowf = a.nch * 4;  // floats per row
+    float4 pq[MAXCPL];
+    {
+        const float* pr = a.X + p * rowf;
+#pragma unroll
+        for (int j = 0; j < MAXCPL; ++j) {
+            const int ch = sub + j * G;
+            pq[j] = (j < a.cpl && ch < a.nch) ? *(const float4*)(pr + ch * 4)
+                                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    const float pn = a.metric == 2 ? a.norms[p] : 1.0f;
+    // distances d(p, w) -> keys
+    constexpr int UNR = 2;
+    for (int c0 = 0; c0 < nW; c0 += RPP * UNR) {
+        float4 raw[UNR][MAXCPL];
+        int cid[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int c = c0 + u * RPP + group;
+            const u64 kk = c < nW ? wk[c] : EMPTY_KEY;
+            cid[u] = kk == EMPTY_KEY ? -1 : (int)kk;
+            const float* row = a.X + (int64_t)(cid[u] < 0 ? 0 : cid[u]) * rowf;
+#pragma unroll
+            for (int j = 0; j < MAXCPL; ++j) {
+                const int ch = sub + j * G;
+                raw[u][j] = (cid[u] >= 0 && j < a.cpl && ch < a.nch)
+                                ? *(const float4*)(row + ch * 4)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int j = 0; j < MAXCPL; ++j) {
+                const float4 x = raw[u][j], q = pq[j];
+                if (a.metric == 0) {
+                    float d0 = q.x - x.x, d1 = q.y - x.y, d2 = q.z - x.z, d3 = q.w - x.w;
+                    acc = fmaf(d0, d0, acc);
+                    acc = fmaf(d1, d1, acc);
+                    acc = fmaf(d2, d2, acc);
+                    acc = fmaf(d3, d3, acc);
+                } else {
+                    acc = fmaf(q.x, x.x, acc);
+                    acc = fmaf(q.y, x.y, acc);
+                    acc = fmaf(q.z, x.z, acc);
+                    acc = fmaf(q.w, x.w, acc);
+                }
+            }
+            acc = group_sum(acc, G);
+            const int c = c0 + u * RPP + group;
+            if (sub == 0 && cid[u] >= 0) {
+                const float nb = a.metric == 2 ? a.norms[cid[u]] : 1.0f;
+                wk[c] = make_key(finalize_dist(acc, a.metric, pn, nb), cid[u]);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // greedy selection in (d, id) order
+    float4 kept[KS > 0 ? KS : 1][MAXCPL];
+    const double alpha = (double)a.alpha;
+    int nk = 0;
+    bool started = false;
+    u64 lastk = 0;
+    while (nk < R) {
+        u64 mn = EMPTY_KEY;
+        for (int t = lane; t < nW; t += WAVE) {
+            const u64 kk = wk[t];
+            if (kk != EMPTY_KEY && (!started || kk > lastk) && kk < mn) mn = kk;
+        }
+        mn = wave_min_u64(mn);
+        if (mn == EMPTY_KEY) break;
+        started = true;
+        lastk = mn;
+        const int v = (int)(unsigned)(mn & 0xffffffffu);
+        const float dv = fval((unsigned)(mn >> 32));
+        float4 vx[MAXCPL];
+        {
+            const float* vr = a.X + (int64_t)v * rowf;
+#pragma unroll
+            for (int j = 0; j < MAXCPL; ++j) {
+                const int ch = sub + j * G;
+                vx[j] = (j < a.cpl && ch < a.nch) ? *(const float4*)(vr + ch * 4)
+                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+        const float vn = a.metric == 2 ? a.norms[v] : 1.0f;
+        bool dom = false;
+        const int nslots = (nk + RPP - 1) / RPP;
+        for (int s = 0; s < nslots; ++s) {
+            const int jk = s * RPP + group;
+            float4 kx[MAXCPL];
+            if constexpr (KS > 0) {
+#pragma unroll
+                for (int ss = 0; ss < KS; ++ss)
+                    if (ss == s) {
+#pragma unroll
+                        for (int j = 0; j < MAXCPL; ++j) kx[j] = kept[ss][j];
+                    }
+            } else {
+                const int kid = jk < nk ? kept_ids[jk] : v;
+                const float* kr = a.X + (int64_t)kid * rowf;
+#pragma unroll
+                for (int j = 0; j < MAXCPL; ++j) {
+                    const int ch = sub + j * G;
+                    kx[j] = (j < a.cpl && ch < a.nch) ? *(const float4*)(kr + ch * 4)
+                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+            float acc = 0.0f;
+#pragma unroll
+            for (int j = 0; j < MAXCPL; ++j) {
+                const float4 x = vx[j], q = kx[j];
+                if (a.metric == 0) {
+                    float d0 = q.x - x.x, d1 = q.y - x.y, d2 = q.z - x.z, d3 = q.w - x.w;
+                    acc = fmaf(d0, d0, acc);
+                    acc = fmaf(d1, d1, acc);
+                    acc = fmaf(d2, d2, acc);
+                    acc = fmaf(d3, d3, acc);
+                } else {
+                    acc = fmaf(q.x, x.x, acc);
+                    acc = fmaf(q.y, x.y, acc);
+                    acc = fmaf(q.z, x.z, acc);
+                    acc = fmaf(q.w, x.w, acc);
+                }
+            }
+            acc = group_sum(acc, G);
+            if (jk < nk && sub == 0) {
+                const float kn = a.metric == 2 ? a.norms[kept_ids[jk]] : 1.0f;
+                const float dkv = finalize_dist(acc, a.metric, kn, vn);
+                if (alpha * (double)dkv < (double)dv) dom = true;
+            }
+        }
+        if (__ballot(dom) != 0ull) continue;
+        if constexpr (KS > 0) {
+            const int s = nk / RPP, gsel = nk - s * RPP;
+#pragma unroll
+            for (int ss = 0; ss < KS; ++ss)
+                if (ss == s && group == gsel) {
+#pragma unroll
+                    for (int j = 0; j < MAXCPL; ++j) kept[ss][j] = vx[j];
+                }
+        }
+        if (lane == 0) {
+            kept_ids[nk] = v;
+            a.rows_out[p * R + nk] = v;
+            a.dist_out[p * R + nk] = dv;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        ++nk;
+    }
+    if (lane == 0) a.deg_out[p] = nk;
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t nnz,
+                           int R, int* flags) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int64_t b = offs[v], e = offs[v + 1];
+    int f = 0;
+    if (b > e || b < 0 || e > nnz) {
+        atomicOr(flags, 1);
+        return;
+    }
+    if (e - b > R) f |= 2;
+    for (int64_t j = b; j < e; ++j) {
+        const int32_t x = nbrs[j];
+        if (x < 0 || x >= n) f |= 4;
+        if (x == v) f |= 8;
+        for (int64_t t = b; t < j; ++t)
+            if (nbrs[t] == x) f |= 16;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+__global__ void k_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
+                            int R, int32_t* rows, int32_t* deg, float* rdist) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int64_t b = offs[v], e = offs[v + 1];
+    const int64_t g = base + v;
+    deg[g] = (int32_t)(e - b);
+    for (int64_t j = b; j < e; ++j) {
+        rows[g * R + (j - b)] = (int32_t)(base + nbrs[j]);
+        rdist[g * R + (j - b)] = __int_as_float(0x7fc00000);  // NaN: not computed yet
+    }
+}
+
+__global__ void k_norms(const float* X, int64_t n, int dim, float* out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    float s = 0.0f;
+    for (int j = 0; j < dim; ++j) s = fmaf(X[v * dim + j], X[v * dim + j], s);
+    out[v] = sqrtf(s);
+}
+
+// exclusive scan of int32 counts into int64 offsets (n+1 entries)
+#define SCAN_T 256
+#define SCAN_PER 4
+#define SCAN_BLK (SCAN_T * SCAN_PER)
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_block(const int32_t* cnt, int64_t n,
+                                                       int64_t* off, int64_t* bsum) {
+    __shared__ int64_t s[SCAN_T];
+    const int64_t b0 = (int64_t)blockIdx.x * SCAN_BLK;
+    int64_t v[SCAN_PER];
+    int64_t t = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+        const int64_t idx = b0 + threadIdx.x * SCAN_PER + j;
+        v[j] = idx < n ? cnt[idx] : 0;
+        t += v[j];
+    }
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 1; o < SCAN_T; o <<= 1) {
+        int64_t x = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += x;
+        __syncthreads();
+    }
+    int64_t run = s[threadIdx.x] - t;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+        const int64_t idx = b0 + threadIdx.x * SCAN_PER + j;
+        if (idx < n) off[idx] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == SCAN_T - 1) bsum[blockIdx.x] = s[SCAN_T - 1];
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_sums(int64_t* bsum, int64_t nb) {
+    __shared__ int64_t s[SCAN_T];
+    int64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += SCAN_T) {
+        const int64_t idx = c0 + threadIdx.x;
+        const int64_t x = idx < nb ? bsum[idx] : 0;
+        s[threadIdx.x] = x;
+        __syncthreads();
+        for (int o = 1; o < SCAN_T; o <<= 1) {
+            int64_t y = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+            __syncthreads();
+            s[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (idx < nb) bsum[idx] = carry + s[threadIdx.x] - x;
+        const int64_t tot = s[SCAN_T - 1];
+        __syncthreads();
+        carry += tot;
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ void k_scan_add(int64_t* off, int64_t n, const int64_t* bsum, int64_t nb) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) off[idx] += bsum[idx / SCAN_BLK];
+    if (idx == 0) off[n] = bsum[nb];
+}
+
+__global__ void k_count_ids(const int32_t* ids, int64_t total, int32_t* cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int32_t x = ids[t];
+    if (x >= 0) atomicAdd(&cnt[x], 1);
+}
+
+__global__ void k_invert_scatter(const int32_t* nk, int64_t n, int k, const int64_t* off,
+                                 int32_t* cur, int32_t* out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    const int32_t x = nk[t];
+    if (x < 0) return;
+    const int pos = atomicAdd(&cur[x], 1);
+    out[off[x] + pos] = (int32_t)(t / k);
+}
+
+__global__ void k_sort_segments(const int64_t* off, int64_t n, int32_t* ids) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int64_t b = off[x], e = off[x + 1];
+    for (int64_t i = b + 1; i < e; ++i) {
+        const int32_t v = ids[i];
+        int64_t j = i;
+        while (j > b && ids[j - 1] > v) {
+            ids[j] = ids[j - 1];
+            --j;
+        }
+        ids[j] = v;
+    }
+}
+
+__global__ void k_rev_count(const int32_t* rows, const int32_t* deg, int64_t s_base, int64_t n_s,
+                            int R, int64_t t_base, int64_t n_t, int32_t* cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_s * R) return;
+    const int64_t u = t / R;
+    const int j = (int)(t - u * R);
+    const int64_t g = s_base + u;
+    if (j >= deg[g]) return;
+    const int64_t v = (int64_t)rows[g * R + j] - t_base;
+    if (v >= 0 && v < n_t) atomicAdd(&cnt[v], 1);
+}
+
+__global__ void k_rev_scatter(const int32_t* rows, const int32_t* deg, int64_t s_base,
+                              int64_t n_s, int R, int64_t t_base, int64_t n_t, const int64_t* off,
+                              int32_t* cur, int32_t* rev) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_s * R) return;
+    const int64_t u = t / R;
+    const int j = (int)(t - u * R);
+    const int64_t g = s_base + u;
+    if (j >= deg[g]) return;
+    const int64_t v = (int64_t)rows[g * R + j] - t_base;
+    if (v < 0 || v >= n_t) return;
+    const int pos = atomicAdd(&cur[v], 1);
+    rev[off[v] + pos] = (int32_t)g;
+}
+
+__global__ void k_max_i32(const int32_t* v, int64_t n, int32_t* out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) atomicMax(out, v[t]);
+}
+
+__global__ void k_compact(const int32_t* rows, const int32_t* deg, const float* rdist,
+                          const int64_t* off, int64_t N, int R, const float* X, int dim,
+                          int metric, const float* norms, int32_t* out_nbrs, float* out_dists) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * R) return;
+    const int64_t v = t / R;
+    const int j = (int)(t - v * R);
+    if (j >= deg[v]) return;
+    const int32_t u = rows[t];
+    out_nbrs[off[v] + j] = u;
+    if (out_dists) {
+        float d = rdist[t];
+        if (d != d) {  // not computed by a prune: input edge left as it was
+            float acc = 0.0f;
+            for (int c = 0; c < dim; ++c) {
+                const float a = X[v * dim + c], b = X[(int64_t)u * dim + c];
+                if (metric == 0) {
+                    const float x = a - b;
+                    acc = fmaf(x, x, acc);
+                } else {
+                    acc = fmaf(a, b, acc);
+                }
+            }
+            d = finalize_dist(acc, metric, metric == 2 ? norms[v] : 1.0f,
+                              metric == 2 ? norms[u] : 1.0f);
+        }
+        out_dists[off[v] + j] = d;
+    }
+}
+
+__global__ void k_copy_rows(const int32_t* rows_a, const int32_t* deg_a, const float* dist_a,
+                            const int32_t* cnt, int64_t n, int R, int32_t* rows_b, int32_t* deg_b,
+                            float* dist_b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * R) return;
+    const int64_t v = t / R;
+    if (cnt[v] != 0) return;  // pruned again: written by the prune
+    const int j = (int)(t - v * R);
+    if (j == 0) deg_b[v] = deg_a[v];
+    if (j < deg_a[v]) {
+        rows_b[t] = rows_a[t];
+        dist_b[t] = dist_a[t];
+    }
+}
+
+// builder entry point: vertex closest to the centroid
+__global__ void k_check_integral(const float* X, int64_t total, int* flag) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (t < total) {
+        const float x = X[t];
+        bad = x != floorf(x) || fabsf(x) > 1.0e6f;
+    }
+    if (__ballot(bad) != 0ull && lane_id() == 0) atomicAnd(flag, 0);
+}
+
+// column sums; thread t sums column t % dim over a slab of COLSUM_ROWS rows
+#define COLSUM_ROWS 1024
+__global__ void k_colsum(const float* X, int64_t n, int dim, const int* flag, double* cs_d,
+                         unsigned long long* cs_i) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nslab = (n + COLSUM_ROWS - 1) / COLSUM_ROWS;
+    if (t >= nslab * dim) return;
+    const int c = (int)(t % dim);
+    const int64_t r0 = (t / dim) * COLSUM_ROWS;
+    const int64_t r1 = r0 + COLSUM_ROWS < n ? r0 + COLSUM_ROWS : n;
+    if (*flag) {
+        long long s = 0;
+        for (int64_t r = r0; r < r1; ++r) s += (long long)X[r * dim + c];
+        atomicAdd(&cs_i[c], (unsigned long long)s);
+    } else {
+        double s = 0.0;
+        for (int64_t r = r0; r < r1; ++r) s += (double)X[r * dim + c];
+        atomicAdd(&cs_d[c], s);
+    }
+}
+
+#define ENTRY_T 256
+__global__ __launch_bounds__(ENTRY_T) void k_entry_crit(const float* X, int64_t n, int dim,
+                                                        const int* flag, const double* cs_d,
+                                                        const unsigned long long* cs_i,
+                                                        u64* block_best) {
+    // per block: (criterion, id) minimum; integral data -> exact
+    // sum_j (n x_j - S_j)^2 in 128-bit; otherwise float64 sum_j (x_j - mean_j)^2
+    __shared__ unsigned __int128 sc[ENTRY_T];
+    __shared__ double sd[ENTRY_T];
+    __shared__ int64_t sid[ENTRY_T];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool integral = *flag != 0;
+    unsigned __int128 ci = ~(unsigned __int128)0;
+    double cd = INFINITY;
+    if (v < n) {
+        if (integral) {
+            ci = 0;
+            for (int c = 0; c < dim; ++c) {
+                const __int128 d = (__int128)n * (long long)X[v * dim + c] - (__int128)(long long)cs_i[c];
+                ci += (unsigned __int128)(d * d);
+            }
+        } else {
+            cd = 0.0;
+            for (int c = 0; c < dim; ++c) {
+                const double d = (double)X[v * dim + c] - cs_d[c] / (double)n;
+                cd += d * d;
+            }
+        }
+    }
+    sc[threadIdx.x] = ci;
+    sd[threadIdx.x] = cd;
+    sid[threadIdx.x] = v < n ? v : INT64_MAX;
+    __syncthreads();
+    for (int o = ENTRY_T / 2; o >= 1; o >>= 1) {
+        if (threadIdx.x < o) {
+            const int a = threadIdx.x, b = threadIdx.x + o;
+            bool take;
+            if (integral)
+                take = sc[b] < sc[a] || (sc[b] == sc[a] && sid[b] < sid[a]);
+            else
+                take = sd[b] < sd[a] || (sd[b] == sd[a] && sid[b] < sid[a]);
+            if (take) {
+                sc[a] = sc[b];
+                sd[a] = sd[b];
+                sid[a] = sid[b];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        u64* o = block_best + blockIdx.x * 3;
+        if (integral) {
+            o[0] = (u64)(sc[0] >> 64);
+            o[1] = (u64)sc[0];
+        } else {
+            union { double d; u64 u; } c;
+            c.d = sd[0];
+            o[0] = 0;
+            o[1] = c.u;
+        }
+        o[2] = (u64)sid[0];
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t nnz,
+                           int R, int* flags, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_validate, dim3(nblk(n, 256)), dim3(256), 0, st, offs, nbrs, n, nnz, R,
+                       flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
+                            int R, int32_t* rows, int32_t* deg, float* rdist, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_rows, dim3(nblk(n, 256)), dim3(256), 0, st, offs, nbrs, n, base, R,
+                       rows, deg, rdist);
+    return hipGetLastError();
+}
+
+hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_norms, dim3(nblk(n, 256)), dim3(256), 0, st, X, n, dim, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_search(int tt, const SearchArgs& a, int wpb, hipStream_t st) {
+    if (a.nq <= 0) return hipSuccess;
+    const size_t lds = (size_t)wpb * (((size_t)1 << a.hbits) + WAVE) * sizeof(int);
+    const dim3 grid(nblk(a.nq, wpb)), block(wpb * WAVE);
+    const int efs = a.ef > 64 ? 2 : 1;
+#define RNSM_SEARCH(TT, EFS)                                                           \
+    hipLaunchKernelGGL((k_beam_search<TT, EFS>), grid, block, lds, st, a)
+    if (tt == 0) {
+        if (efs == 1) RNSM_SEARCH(0, 1); else RNSM_SEARCH(0, 2);
+    } else if (tt == 1) {
+        if (efs == 1) RNSM_SEARCH(1, 1); else RNSM_SEARCH(1, 2);
+    } else {
+        if (efs == 1) RNSM_SEARCH(2, 1); else RNSM_SEARCH(2, 2);
+    }
+#undef RNSM_SEARCH
+    return hipGetLastError();
+}
+
+hipError_t launch_prune(const PruneArgs& a, hipStream_t st) {
+    if (a.n_items <= 0) return hipSuccess;
+    const int wpb = 4;
+    const size_t lds = (size_t)wpb * ((size_t)(a.wcap + a.R) * sizeof(u64));
+    const dim3 grid(nblk(a.n_items, wpb)), block(wpb * WAVE);
+    const int rpp = WAVE / a.G;
+    const int need = (a.R + rpp - 1) / rpp;
+    if (need <= 1)
+        hipLaunchKernelGGL(k_prune<1>, grid, block, lds, st, a);
+    else if (need <= 2)
+        hipLaunchKernelGGL(k_prune<2>, grid, block, lds, st, a);
+    else if (need <= 4)
+        hipLaunchKernelGGL(k_prune<4>, grid, block, lds, st, a);
+    else if (need <= 8)
+        hipLaunchKernelGGL(k_prune<8>, grid, block, lds, st, a);
+    else
+        hipLaunchKernelGGL(k_prune<0>, grid, block, lds, st, a);
+    return hipGetLastError();
+}
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + SCAN_BLK - 1) / SCAN_BLK) + 2; }
+
+hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* off, int64_t* tmp, hipStream_t st) {
+    const int64_t nb = (n + SCAN_BLK - 1) / SCAN_BLK;
+    if (n > 0)
+        hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(SCAN_T), 0, st, cnt, n, off, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, st, tmp, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, st, off, n, tmp,
+                       nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int64_t* rk_off,
+                         int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)n, st);
+    if (e != hipSuccess) return e;
+    if (n > 0)
+        hipLaunchKernelGGL(k_count_ids, dim3(nblk(n * k, 256)), dim3(256), 0, st, nk, n * k, cnt);
+    e = launch_scan(cnt, n, rk_off, scan_tmp, st);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)n, st);
+    if (e != hipSuccess) return e;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_invert_scatter, dim3(nblk(n * k, 256)), dim3(256), 0, st, nk, n, k,
+                           rk_off, cnt, rk_ids);
+        hipLaunchKernelGGL(k_sort_segments, dim3(nblk(n, 256)), dim3(256), 0, st, rk_off, n,
+                           rk_ids);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rev_count(const int32_t* rows, const int32_t* deg, int64_t s_base, int64_t n_s,
+                            int R, int64_t t_base, int64_t n_t, int32_t* cnt, hipStream_t st) {
+    if (n_s <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rev_count, dim3(nblk(n_s * R, 256)), dim3(256), 0, st, rows, deg, s_base,
+                       n_s, R, t_base, n_t, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, int64_t s_base,
+                              int64_t n_s, int R, int64_t t_base, int64_t n_t,
+                              const int64_t* off, int32_t* cur, int32_t* rev, hipStream_t st) {
+    if (n_s <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rev_scatter, dim3(nblk(n_s * R, 256)), dim3(256), 0, st, rows, deg,
+                       s_base, n_s, R, t_base, n_t, off, cur, rev);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_i32(const int32_t* v, int64_t n, int32_t* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_max_i32, dim3(nblk(n, 256)), dim3(256), 0, st, v, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const int32_t* rows, const int32_t* deg, const float* rdist,
+                          const int64_t* off, int64_t N, int R, const float* X, int dim,
+                          int metric, const float* norms, int32_t* out_nbrs, float* out_dists,
+                          hipStream_t st) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3(nblk(N * R, 256)), dim3(256), 0, st, rows, deg, rdist, off,
+                       N, R, X, dim, metric, norms, out_nbrs, out_dists);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const int32_t* rows_a, const int32_t* deg_a, const float* dist_a,
+                            const int32_t* cnt, int64_t n, int R, int32_t* rows_b,
+                            int32_t* deg_b, float* dist_b, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_rows, dim3(nblk(n * R, 256)), dim3(256), 0, st, rows_a, deg_a,
+                       dist_a, cnt, n, R, rows_b, deg_b, dist_b);
+    return hipGetLastError();
+}
+
+int64_t entry_blocks(int64_t n) { return (n + ENTRY_T - 1) / ENTRY_T; }
+
+hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* cs_d,
+                        unsigned long long* cs_i, u64* block_best, int64_t nblocks,
+                        hipStream_t st) {
+    // flag must hold 1, cs_d / cs_i must hold zeros
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_integral, dim3(nblk(n * dim, 256)), dim3(256), 0, st, X, n * dim,
+                       flag);
+    const int64_t nslab = (n + COLSUM_ROWS - 1) / COLSUM_ROWS;
+    hipLaunchKernelGGL(k_colsum, dim3(nblk(nslab * dim, 256)), dim3(256), 0, st, X, n, dim, flag,
+                       cs_d, cs_i);
+    if (block_best && nblocks > 0)
+        hipLaunchKernelGGL(k_entry_crit, dim3((unsigned)nblocks), dim3(ENTRY_T), 0, st, X, n, dim,
+                           flag, cs_d, cs_i, block_best);
+    return hipGetLastError();
+}
+
+}  // namespace rnsm

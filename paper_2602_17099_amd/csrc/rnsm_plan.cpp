@@ -1,0 +1,198 @@
+// Host-side planning of the RNSM path: merge order selection (Algorithm 3,
+// Section 5) with the execution order and direction rules of Section 5, and
+// the lazy greedy pivot selection of Algorithm 2 (Section 4.2).
+#include "rnsm_plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace rnsm {
+
+// ---------------------------------------------------------------- MOS
+
+namespace {
+
+// hop counts from v in the undirected graph adj (INT32_MAX: unreachable)
+void bfs_from(int v, const std::vector<std::vector<int>>& adj, std::vector<int>& hop) {
+    const int m = (int)adj.size();
+    hop.assign(m, INT32_MAX);
+    std::vector<int> q;
+    q.reserve(m);
+    hop[v] = 0;
+    q.push_back(v);
+    for (size_t h = 0; h < q.size(); ++h) {
+        const int u = q[h];
+        for (int w : adj[u])
+            if (hop[w] == INT32_MAX) {
+                hop[w] = hop[u] + 1;
+                q.push_back(w);
+            }
+    }
+}
+
+bool has_edge(const std::vector<std::vector<int>>& adj, int a, int b) {
+    return std::find(adj[a].begin(), adj[a].end(), b) != adj[a].end();
+}
+
+}  // namespace
+
+int mos_edges(int m, const std::vector<double>& cost, int R, int delta,
+              std::vector<std::pair<int, int>>& edges, int* fallbacks) {
+    edges.clear();
+    *fallbacks = 0;
+    if (m < 1 || R < 1 || delta < 2 || (int)cost.size() != m * m) return -1;
+    auto C = [&](int a, int b) { return cost[(size_t)a * m + b]; };
+    // vertices by ascending mean cost to their min(R, m-1) cheapest others
+    const int r = std::min(R, m - 1);
+    std::vector<double> mean(m, 0.0);
+    for (int i = 0; i < m; ++i) {
+        std::vector<double> c;
+        c.reserve(m);
+        for (int j = 0; j < m; ++j)
+            if (j != i) c.push_back(C(i, j));
+        std::partial_sort(c.begin(), c.begin() + r, c.end());
+        double s = 0.0;
+        for (int t = 0; t < r; ++t) s += c[t];
+        mean[i] = r > 0 ? s / r : 0.0;
+    }
+    std::vector<int> order(m);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mean[a] < mean[b]; });
+
+    std::vector<std::vector<int>> adj(m);
+    std::vector<int> hop;
+    auto deg = [&](int a) { return (int)adj[a].size(); };
+    for (int v : order) {
+        for (;;) {
+            bfs_from(v, adj, hop);
+            int x = -1;
+            for (int c = 0; c < m; ++c) {
+                if (c == v || hop[c] <= delta) continue;
+                if (x < 0 || C(v, c) < C(v, x)) x = c;
+            }
+            if (x < 0) break;
+            int a = v, b = x;
+            bool fb = false;
+            const bool vs = deg(v) >= R, xs = deg(x) >= R;
+            if (!vs && xs) {
+                // relay to the cheapest unsaturated neighbour of x
+                int best = -1;
+                for (int c : adj[x])
+                    if (c != v && deg(c) < R &&
+                        (best < 0 || C(c, v) < C(best, v) || (C(c, v) == C(best, v) && c < best)))
+                        best = c;
+                if (best >= 0) b = best; else fb = true;
+            } else if (vs && !xs) {
+                int best = -1;
+                for (int c : adj[v])
+                    if (c != x && deg(c) < R &&
+                        (best < 0 || C(c, x) < C(best, x) || (C(c, x) == C(best, x) && c < best)))
+                        best = c;
+                if (best >= 0) a = best; else fb = true;
+            } else if (vs && xs) {
+                fb = true;
+            }
+            if (has_edge(adj, a, b)) return -2;  // cannot happen for delta >= 2
+            adj[a].push_back(b);
+            adj[b].push_back(a);
+            edges.emplace_back(a, b);
+            if (fb) ++*fallbacks;
+        }
+    }
+    return 0;
+}
+
+int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int R, int delta,
+             std::vector<std::pair<int, int>>& ops, int* fallbacks) {
+    std::vector<double> cost((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            if (i == j) continue;
+            if (!centroids) {
+                cost[(size_t)i * m + j] = 1.0;
+                continue;
+            }
+            double s = 0.0;
+            for (int t = 0; t < dim; ++t) {
+                const double d = centroids[(size_t)i * dim + t] - centroids[(size_t)j * dim + t];
+                s += d * d;
+            }
+            cost[(size_t)i * m + j] = std::sqrt(s);
+        }
+    std::vector<std::pair<int, int>> e;
+    const int rc = mos_edges(m, cost, R, delta, e, fallbacks);
+    if (rc != 0) return rc;
+    for (auto& p : e)
+        if (p.first > p.second) std::swap(p.first, p.second);
+    std::stable_sort(e.begin(), e.end(), [&](const std::pair<int, int>& a,
+                                             const std::pair<int, int>& b) {
+        const double ca = cost[(size_t)a.first * m + a.second];
+        const double cb = cost[(size_t)b.first * m + b.second];
+        if (ca != cb) return ca < cb;
+        return a < b;
+    });
+    ops.clear();
+    for (auto& p : e) {
+        const int i = p.first, j = p.second;  // i < j
+        if (sizes[j] < sizes[i])
+            ops.emplace_back(j, i);
+        else
+            ops.emplace_back(i, j);
+    }
+    return 0;
+}
+
+// ------------------------------------------------------ lazy greedy pivots
+
+void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, Pivots& out) {
+    out.pivots.clear();
+    out.followers.clear();
+    out.follower_pivot.clear();
+    std::vector<unsigned char> covered((size_t)n, 0);
+    int64_t gmax = 0;
+    for (int64_t x = 0; x < n; ++x) gmax = std::max<int64_t>(gmax, rk_off[x + 1] - rk_off[x]);
+    // bucket g holds the vertices whose stored gain is g: the initial members
+    // in ascending id order plus members moved down later (sorted before the
+    // bucket is processed; a bucket only receives members while a higher one
+    // is processed)
+    std::vector<std::vector<int32_t>> init(gmax + 1), moved(gmax + 1);
+    for (int64_t x = 0; x < n; ++x) init[rk_off[x + 1] - rk_off[x]].push_back((int32_t)x);
+    out.pivots.reserve(n / 4);
+    out.followers.reserve(n);
+    out.follower_pivot.reserve(n);
+    for (int64_t g = gmax; g >= 0; --g) {
+        std::vector<int32_t>& A = init[g];
+        std::vector<int32_t>& B = moved[g];
+        std::sort(B.begin(), B.end());
+        size_t ia = 0, ib = 0;
+        while (ia < A.size() || ib < B.size()) {
+            int32_t x;
+            if (ib >= B.size() || (ia < A.size() && A[ia] < B[ib]))
+                x = A[ia++];
+            else
+                x = B[ib++];
+            if (covered[x]) continue;
+            int64_t cur = 0;
+            for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) cur += !covered[rk_ids[j]];
+            if (cur < g) {
+                moved[cur].push_back(x);
+                continue;
+            }
+            out.pivots.push_back(x);
+            covered[x] = 1;
+            for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) {
+                const int32_t y = rk_ids[j];
+                if (!covered[y]) {
+                    covered[y] = 1;
+                    out.followers.push_back(y);
+                    out.follower_pivot.push_back(x);
+                }
+            }
+        }
+        std::vector<int32_t>().swap(A);
+        std::vector<int32_t>().swap(B);
+    }
+}
+
+}  // namespace rnsm
