@@ -1,0 +1,267 @@
+"""Benchmark: merged vertices/s of the RNSM merge on one MI355X.
+
+Workload (default): two sub-indexes of 500,000 vectors each, dim 128,
+integers 0..255 from a 64-component Gaussian mixture (sigma 30) stored as
+float32, squared L2; each sub-index has out-degree <= 32; merge with R=32,
+L=64, alpha=1.2; 10,000 held-out queries for recall@10. A step is one whole
+merge (expansion, inversion, pivots, naive and sliding searches, prunes,
+reverse edges, compaction) with every input already in HBM.
+
+Prints one JSON line. Options: --steps K, --warmup W, --gpus N (only 1),
+--workload {fp32-2x500k,tiny}, --no-cpu-baseline, --calib-copy (adds a plain
+1 GiB device copy for counter calibration).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "fp32-2x500k": dict(n=500_000, dim=128, R=32, L=64, alpha=1.2, K=64, nq=10_000,
+                        gen="mixture_u8", build_alpha=1.2, reverse=True),
+    "tiny": dict(n=5_000, dim=32, R=16, L=32, alpha=1.2, K=32, nq=500, gen="tiny_int",
+                 build_alpha=1.0, reverse=False),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(wl, seed_off=0):
+    from paper_2602_17099_amd import inputs
+    n2 = 2 * wl["n"]
+    if wl["gen"] == "mixture_u8":
+        X = inputs.mixture_u8(n2, wl["dim"], seed=inputs.SEED_BASE + 2)
+        Q = inputs.mixture_u8(wl["nq"], wl["dim"], seed=inputs.SEED_BASE + 2, stream=1)
+    else:
+        allx = inputs.tiny_int(n2 + wl["nq"], wl["dim"], seed=inputs.SEED_BASE + 1)
+        X, Q = allx[:n2], allx[n2:]
+    return np.ascontiguousarray(X), np.ascontiguousarray(Q)
+
+
+def build_subs(pkg, Xd, wl):
+    from paper_2602_17099_amd.prepare import knn_l2_exact
+    subs = []
+    n = wl["n"]
+    for i in range(2):
+        Xi = Xd[i * n:(i + 1) * n]
+        knn = knn_l2_exact(Xi, None, wl["K"], exclude_self=True)
+        off, nb, entry = pkg.build_graph(Xi, knn, wl["R"], alpha=wl["build_alpha"],
+                                         reverse=wl["reverse"], alpha_rev=1.2)
+        del knn
+        subs.append((off, nb, entry))
+    return subs
+
+
+def recall_at_10(pkg, off, nb, entry, Xd, Qd, gt, ef=64):
+    import torch
+    ids, _ = pkg.search(off, nb, entry, Xd, Qd, ef, 10)
+    ids = ids.to(torch.int64)
+    hit = (ids[:, :, None] == gt[:, None, :].to(torch.int64)).any(2).sum().item()
+    return hit / (10 * Qd.shape[0])
+
+
+PHASES = ("expansion", "naive", "sliding")
+
+
+def time_merges(pkg, subs, Xd, wl, steps, warmup, search=None):
+    """Time `steps` whole merges after `warmup`; per-phase event times and
+    counts are summed over the timed steps."""
+    import torch
+    N = Xd.shape[0]
+    R = wl["R"]
+    out = (torch.empty(N + 1, dtype=torch.int64, device=Xd.device),
+           torch.empty(N * R, dtype=torch.int32, device=Xd.device),
+           torch.empty(N * R, dtype=torch.float32, device=Xd.device))
+    kw = dict(R=R, L=wl["L"], alpha=wl["alpha"], search=search, out=out)
+    for _ in range(warmup):
+        pkg.merge(subs, Xd, **kw)
+    torch.cuda.synchronize()
+    agg = {"ms": [0.0] * 3, "bytes": [0.0] * 3, "ndc": [0] * 3, "launches": [0] * 3}
+    st = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = pkg.merge(subs, Xd, **kw)
+        st = pkg.stats()
+        for ph in range(3):
+            agg["ms"][ph] += st["ms_search"][ph]
+            agg["bytes"][ph] += st["bytes"][ph]
+            agg["ndc"][ph] += st["ndc"][ph]
+            agg["launches"][ph] += st["launches"][ph]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, agg, st, res
+
+
+def exact_ndc(pkg, subs, Xd, wl, search=None):
+    """Distance counts of one merge with the probing visited table, which
+    evaluates every visited vertex exactly once (the method's own count)."""
+    os.environ["RNSM_EXACT_VISITED"] = "1"
+    try:
+        pkg.merge(subs, Xd, R=wl["R"], L=wl["L"], alpha=wl["alpha"], search=search)
+        st = pkg.stats()
+    finally:
+        del os.environ["RNSM_EXACT_VISITED"]
+    assert st["exact_visited"] == 1
+    return st["ndc"]
+
+
+def search_roofline(agg, st, ndc_exact, steps):
+    """Algorithmic bytes of the k_beam_search launches (expansion, naive,
+    sliding) over their event-timed durations; re-evaluations caused by the
+    forgetful visited table are not counted as algorithmic bytes."""
+    rb = st["row_bytes"]
+    tot_b = tot_ms = 0.0
+    per = {}
+    for ph in range(3):
+        extra = agg["ndc"][ph] - steps * ndc_exact[ph]
+        b = agg["bytes"][ph] - extra * rb
+        per[PHASES[ph]] = {"gbs": b / (agg["ms"][ph] * 1e6) if agg["ms"][ph] else None,
+                           "ms_per_launch": agg["ms"][ph] / max(1, agg["launches"][ph]),
+                           "ndc_inflation": agg["ndc"][ph] / max(1, steps * ndc_exact[ph])}
+        tot_b += b
+        tot_ms += agg["ms"][ph]
+    launches = sum(agg["launches"])
+    achieved = tot_b / (tot_ms * 1e6)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "k_beam_search (expansion, naive and sliding launches)",
+            "bytes_per_launch": tot_b / launches, "ms_per_launch": tot_ms / launches,
+            "per_phase": per}
+
+
+def cpu_baseline(wl):
+    """The oracle's full merge on a replica of the workload with 1/20 of the
+    vectors per sub-index (same distribution, dim and parameters; sub-indexes
+    built by the oracle), single-threaded."""
+    from oracle import oracle as O
+    from paper_2602_17099_amd import inputs
+    n = max(1000, wl["n"] // 20)
+    if wl["gen"] == "mixture_u8":
+        X = inputs.mixture_u8(2 * n, wl["dim"], seed=inputs.SEED_BASE + 2)
+    else:
+        X = inputs.tiny_int(2 * n, wl["dim"], seed=inputs.SEED_BASE + 1)
+    subs = [O.build_graph(X[i * n:(i + 1) * n], wl["K"], wl["R"], alpha=wl["build_alpha"],
+                          reverse=wl["reverse"], alpha_rev=1.2) for i in range(2)]
+    t0 = time.perf_counter()
+    O.merge(subs, X, R=wl["R"], L=wl["L"], alpha=wl["alpha"])
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "merged vertices/s", "cores": 1, "kind": "oracle",
+            "sample": f"full oracle merge of a 2 x {n} replica (same distribution, dim "
+                      f"{wl['dim']}, R={wl['R']}, L={wl['L']}, alpha={wl['alpha']}), "
+                      f"{dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fp32-2x500k", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--no-recall", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2602_17099_amd as pkg
+    pkg.lib()
+    wl = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+
+    t = time.perf_counter()
+    X, Q = make_inputs(wl)
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    log(f"inputs {X.shape} in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    subs = build_subs(pkg, Xd, wl)
+    torch.cuda.synchronize()
+    log(f"sub-indexes built in {time.perf_counter() - t:.1f}s "
+        f"(edges {[int(s[0][-1]) for s in subs]}, entries {[s[2] for s in subs]})")
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read, 1 GiB written")
+
+    ndc_x = exact_ndc(pkg, subs, Xd, wl)
+    dt, agg, st, res = time_merges(pkg, subs, Xd, wl, args.steps, args.warmup)
+    n_src = st["n_source_vertices"]
+    value = args.steps * n_src / dt
+    ms_step = 1000.0 * dt / args.steps
+    log(f"fp32: {ms_step:.2f} ms/step, {value / 1e6:.3f} M merged vertices/s; stats {st}")
+    roof = search_roofline(agg, st, ndc_x, args.steps)
+    log(f"fp32 search roofline {roof}")
+    off, nb, ds, entry = res
+    gt = None
+    rec32 = None
+    if wl["nq"] and not args.no_recall:
+        from paper_2602_17099_amd.prepare import knn_l2_exact
+        gt = knn_l2_exact(Xd, Qd, 10)
+        rec32 = recall_at_10(pkg, off, nb, entry, Xd, Qd, gt)
+        log(f"fp32 recall@10 (query ef 64) {rec32:.4f}")
+
+    bf16 = None
+    if not args.no_bf16:
+        Xb = Xd.to(torch.bfloat16)
+        ndc_b = exact_ndc(pkg, subs, Xd, wl, search=Xb)
+        dtb, aggb, stb, resb = time_merges(pkg, subs, Xd, wl, args.steps, args.warmup, search=Xb)
+        vb = args.steps * stb["n_source_vertices"] / dtb
+        recb = recall_at_10(pkg, resb[0], resb[1], resb[3], Xd, Qd, gt) if gt is not None else None
+        same = bool(torch.equal(resb[0], off) and torch.equal(resb[1], nb))
+        rb = search_roofline(aggb, stb, ndc_b, args.steps)
+        bf16 = {"value": vb, "ms_per_step": 1000.0 * dtb / args.steps, "recall_at_10": recb,
+                "speedup_vs_fp32": vb / value, "same_graph_as_fp32": same,
+                "search_ms_per_launch": rb["ms_per_launch"], "search_gbs": rb["achieved"],
+                "search_frac": rb["frac"]}
+        log(f"bf16 search copy: {bf16}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        cpu = cpu_baseline(wl)
+        log(f"cpu baseline in {time.perf_counter() - t:.1f}s: {cpu}")
+
+    line = {
+        "metric": "merged vertices/s at equal recall@10 (BF16 vs FP32); search-kernel HBM GB/s vs peak",
+        "value": value, "unit": "merged vertices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload if args.workload != "fp32-2x500k" else
+                   "plain FP32: 2 x 500,000 vectors, dim 128, u8-valued mixture, L2SQ, "
+                   "R=32, L=64, alpha=1.2",
+                   "sub_index_size": wl["n"], "dim": wl["dim"], "R": wl["R"], "L": wl["L"],
+                   "alpha": wl["alpha"], "parallelism": "single GPU"},
+        "recall_at_10": rec32,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "bf16_form": bf16,
+        "phase_ms": {"expansion_search": st["ms_search"][0], "invert": st["ms_invert"],
+                     "host_plan": st["ms_plan"], "naive_search": st["ms_search"][1],
+                     "sliding_search": st["ms_search"][2], "prune_and_reverse": st["ms_prune"],
+                     "compact": st["ms_compact"], "total": st["ms_total"]},
+        "counts": {"pivots": st["n_pivots"], "followers": st["n_followers"],
+                   "reverse_edges": st["n_reverse_edges"], "ndc_exact": ndc_x,
+                   "ndc_timed": st["ndc"], "visited_table_evictions": st["hash_evictions"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -134,21 +134,31 @@ typedef struct {
     int64_t n_edges;
 } rnsm_csr;
 
-/* Counters and event timings of the last rnsm_merge on this thread. */
+/*
+ * Counters and event timings of the last rnsm_merge on this thread. Arrays
+ * indexed [3] are per search phase: 0 neighbor expansion, 1 pivots' naive
+ * search, 2 followers' local sliding.
+ */
 typedef struct {
     double ms_total;        /* host wall time of the call */
-    double ms_expand;       /* neighbor expansion + inversion (device) */
-    double ms_plan;         /* host: MOS + lazy greedy, incl. transfers */
-    double ms_search;       /* naive + sliding search kernels (device events) */
-    double ms_prune;        /* source + target prunes and reverse edges (device) */
-    double ms_compact;
+    double ms_search[3];    /* search kernels of each phase (device events) */
+    double ms_invert;       /* reverse k-NN inversion (device events) */
+    double ms_plan;         /* host: MOS, reverse k-NN transfer, lazy greedy */
+    double ms_prune;        /* source and target prunes with the reverse edges (device events) */
+    double ms_compact;      /* CSR compaction (device events) */
     int64_t n_ops, n_source_vertices, n_pivots, n_followers, n_reverse_edges;
-    int64_t ndc_expand, ndc_naive, ndc_slide;   /* distance computations */
-    int64_t exp_naive, exp_slide;               /* expansions (vertices popped) */
-    int64_t adj_naive, adj_slide;               /* adjacency entries read */
-    double search_bytes;    /* algorithmic bytes of the naive + sliding searches */
-    int64_t search_launches;
-    int64_t hash_full;      /* neighbours the LDS visited table could not hold */
+    int64_t queries[3];     /* searches run */
+    int64_t ndc[3];         /* distance computations (re-evaluations included) */
+    int64_t expansions[3];  /* vertices expanded */
+    int64_t adjacency[3];   /* adjacency entries read */
+    int64_t launches[3];    /* search kernel launches */
+    double bytes[3];        /* algorithmic bytes from the counts above: every distance reads
+                               one row, every expansion two offsets and its adjacency, every
+                               query its row, its seeds and its output */
+    int64_t hash_evictions; /* visited-table evictions: a forgotten vertex may be evaluated
+                               again, which adds to ndc but never changes a result */
+    int32_t row_bytes;      /* bytes of one row of the searched copy */
+    int32_t exact_visited;  /* 1 when the searches ran with the probing visited table */
 } rnsm_stats;
 
 /*

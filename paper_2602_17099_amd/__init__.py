@@ -52,14 +52,14 @@ class Csr(C.Structure):
 
 
 class Stats(C.Structure):
-    _fields_ = [("ms_total", C.c_double), ("ms_expand", C.c_double), ("ms_plan", C.c_double),
-                ("ms_search", C.c_double), ("ms_prune", C.c_double), ("ms_compact", C.c_double),
+    _fields_ = [("ms_total", C.c_double), ("ms_search", C.c_double * 3), ("ms_invert", C.c_double),
+                ("ms_plan", C.c_double), ("ms_prune", C.c_double), ("ms_compact", C.c_double),
                 ("n_ops", C.c_int64), ("n_source_vertices", C.c_int64), ("n_pivots", C.c_int64),
                 ("n_followers", C.c_int64), ("n_reverse_edges", C.c_int64),
-                ("ndc_expand", C.c_int64), ("ndc_naive", C.c_int64), ("ndc_slide", C.c_int64),
-                ("exp_naive", C.c_int64), ("exp_slide", C.c_int64), ("adj_naive", C.c_int64),
-                ("adj_slide", C.c_int64), ("search_bytes", C.c_double),
-                ("search_launches", C.c_int64), ("hash_full", C.c_int64)]
+                ("queries", C.c_int64 * 3), ("ndc", C.c_int64 * 3), ("expansions", C.c_int64 * 3),
+                ("adjacency", C.c_int64 * 3), ("launches", C.c_int64 * 3), ("bytes", C.c_double * 3),
+                ("hash_evictions", C.c_int64), ("row_bytes", C.c_int32),
+                ("exact_visited", C.c_int32)]
 
 
 def lib():
@@ -169,9 +169,15 @@ def merge_simple(subs, X, R, L, alpha, stream=None):
 
 
 def stats() -> dict:
+    """Counters of the last merge on this thread; per-phase arrays are
+    [expansion, naive search, local sliding]."""
     s = Stats()
     _check(lib().rnsm_get_stats(C.byref(s)))
-    return {name: getattr(s, name) for name, _ in Stats._fields_}
+    out = {}
+    for name, _ in Stats._fields_:
+        v = getattr(s, name)
+        out[name] = list(v) if hasattr(v, "__len__") else v
+    return out
 
 
 def mos_plan(sizes, degree_bound, diameter=2, centroids=None):

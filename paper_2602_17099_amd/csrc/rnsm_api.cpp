@@ -82,18 +82,36 @@ int ilog2_ceil(int64_t x) {
 
 // LDS visited-table size and wavefronts per block for a search of beam ef
 // over rows of degree <= maxdeg. RNSM_HASH_BITS / RNSM_WPB override.
-void search_shape(int ef, int maxdeg, int* hbits, int* wpb) {
-    int hb = ilog2_ceil((int64_t)ef * (maxdeg > 0 ? maxdeg : 16) * 2);
-    hb = hb < 8 ? 8 : (hb > 13 ? 13 : hb);
+// LDS visited-table size, wavefronts per block and table mode of a search of
+// beam ef over rows of degree <= maxdeg. The fast table is lossy (a forgotten
+// vertex is evaluated again and dropped by key), so it is sized for
+// occupancy rather than for the whole visited set: 2048 slots measured best
+// for the L=64, R=32 searches. RNSM_EXACT_VISITED=1 selects an 8192-slot
+// probing table that holds every visited vertex (distance counts then equal
+// the method's own). RNSM_HASH_BITS / RNSM_WPB override the sizes.
+struct SearchShape {
+    int hbits, wpb, mode;
+};
+
+SearchShape search_shape(int ef, int maxdeg) {
+    SearchShape s;
+    int hb = ilog2_ceil((int64_t)ef * (maxdeg > 0 ? maxdeg : 16));
+    hb = hb < 8 ? 8 : (hb > 11 ? 11 : hb);
+    s.mode = 0;
+    const char* x = getenv("RNSM_EXACT_VISITED");
+    if (x && atoi(x) == 1) {
+        s.mode = 1;
+        hb = 13;
+    }
     const char* e = getenv("RNSM_HASH_BITS");
     if (e && atoi(e) >= 6 && atoi(e) <= 14) hb = atoi(e);
-    int w = 4;
-    while (w > 1 && (size_t)w * ((1u << hb) + 64) * 4 > 64 * 1024) --w;
+    int w = 1;
     const char* ew = getenv("RNSM_WPB");
     if (ew && atoi(ew) >= 1 && atoi(ew) <= 4) w = atoi(ew);
-    while (w > 1 && (size_t)w * ((1u << hb) + 64) * 4 > 64 * 1024) --w;
-    *hbits = hb;
-    *wpb = w;
+    while (w > 1 && search_lds_bytes(hb, w) > 64 * 1024) --w;
+    s.hbits = hb;
+    s.wpb = w;
+    return s;
 }
 
 struct VecInfo {
@@ -329,7 +347,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     // ------------------------------------- expansion, inversion and pivots
     std::vector<Pivots> piv(m);
     std::vector<char> have(m, 0);
-    double ms_expand = 0.0, ms_search = 0.0, ms_prune = 0.0;
+    double ms_prune = 0.0;
     for (auto& op : ops) {
         const int s = op.first;
         if (have[s]) continue;
@@ -342,7 +360,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         WS(rk_off, "rk_off", sizeof(int64_t) * (ns + 1));
         WS(rk_ids, "rk_ids", sizeof(int32_t) * ns * k);
         WS(stmp, "scan_tmp", sizeof(int64_t) * scan_tmp_elems(ns));
-        int e0, e1;
+        int e0, e0b, e1;
         HIPCHK(E.record(st, &e0));
         SearchArgs a = {};
         a.base = vi.search + bases[s] * vi.row_bytes;
@@ -361,24 +379,29 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.ef = kp;
         a.G = vi.G;
         a.cpl = vi.cpl;
-        int wpb;
-        search_shape(kp, R, &a.hbits, &wpb);
+        const SearchShape sh = search_shape(kp, R);
+        a.hbits = sh.hbits;
+        a.hash_mode = sh.mode;
         a.out_mode = 1;
         a.out_ids = nk;
         a.out_stride = k;
         a.out_k = k;
         a.counters = cnt + 0 * CNT_N;
         a.err = errf;
-        HIPCHK(launch_search(vi.tt, a, wpb, st));
+        HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
+        HIPCHK(E.record(st, &e0b));
         HIPCHK(launch_invert(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
         HIPCHK(E.record(st, &e1));
+        g_stats.queries[0] += ns;
+        g_stats.launches[0] += 1;
         std::vector<int64_t> h_off(ns + 1);
         HIPCHK(hipMemcpyAsync(h_off.data(), rk_off, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         std::vector<int32_t> h_ids(h_off[ns] > 0 ? h_off[ns] : 1);
         if (h_off[ns] > 0)
             HIPCHK(hipMemcpy(h_ids.data(), rk_ids, sizeof(int32_t) * h_off[ns], hipMemcpyDeviceToHost));
-        ms_expand += E.between(e0, e1);
+        g_stats.ms_search[0] += E.between(e0, e0b);
+        g_stats.ms_invert += E.between(e0b, e1);
         const auto tg = std::chrono::steady_clock::now();
         if (p->flags & RNSM_FLAG_ALL_PIVOTS) {
             piv[s].pivots.resize(ns);
@@ -407,7 +430,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             HIPCHK(hipMemcpyAsync(d_folp, P.follower_pivot.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, st));
         }
         HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));
-        int e0, e1, e2;
+        int e0, e0b, e1, e2;
         HIPCHK(E.record(st, &e0));
         SearchArgs a = {};
         a.base = vi.search + bases[t] * vi.row_bytes;
@@ -426,7 +449,6 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.out_ids = res;
         a.out_stride = RES;
         a.err = errf;
-        int wpb;
         // wave A: pivots, naive search from the target's entry point
         a.qidx = d_piv;
         a.nq = np;
@@ -436,8 +458,11 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.out_k = efN;
         a.out_row = d_piv;
         a.counters = cnt + 1 * CNT_N;
-        search_shape(efN, R, &a.hbits, &wpb);
-        HIPCHK(launch_search(vi.tt, a, wpb, st));
+        const SearchShape shA = search_shape(efN, R);
+        a.hbits = shA.hbits;
+        a.hash_mode = shA.mode;
+        HIPCHK(launch_search(vi.tt, a, shA.wpb, st));
+        HIPCHK(E.record(st, &e0b));
         // wave B: followers, local sliding from their pivot's results
         a.qidx = d_fol;
         a.nq = nf;
@@ -450,9 +475,16 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.out_k = efS;
         a.out_row = d_fol;
         a.counters = cnt + 2 * CNT_N;
-        search_shape(efS, R, &a.hbits, &wpb);
-        HIPCHK(launch_search(vi.tt, a, wpb, st));
+        const SearchShape shB = search_shape(efS, R);
+        a.hbits = shB.hbits;
+        a.hash_mode = shB.mode;
+        HIPCHK(launch_search(vi.tt, a, shB.wpb, st));
         HIPCHK(E.record(st, &e1));
+        g_stats.queries[1] += np;
+        g_stats.queries[2] += nf;
+        g_stats.launches[1] += np > 0;
+        g_stats.launches[2] += nf > 0;
+        g_stats.exact_visited = shB.mode;
 
         // source rows: current row + search results, pruned to R
         PruneArgs q = {};
@@ -490,7 +522,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         WS(roff, "rev_off", sizeof(int64_t) * (nt + 1));
         WS(rev, "rev_ids", sizeof(int32_t) * std::max<int64_t>(ns * R, 1));
         WS(stmp, "scan_tmp2", sizeof(int64_t) * scan_tmp_elems(nt));
-        WS(scratch, "prune_scratch", sizeof(u64) * (nt * R + ns * R));
+        WS(scratch, "prune_scratch", sizeof(u64) * 2 * (nt * R + ns * R));
         HIPCHK(hipMemsetAsync(rc, 0, sizeof(int32_t) * nt, st));
         HIPCHK(hipMemsetAsync(rcur, 0, sizeof(int32_t) * nt, st));
         HIPCHK(launch_rev_count(rows, deg, bases[s], ns, R, bases[t], nt, rc, st));
@@ -514,7 +546,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         g_stats.n_source_vertices += ns;
         (void)e2;
         HIPCHK(hipStreamSynchronize(st));  // keeps event timings per operation simple
-        ms_search += E.between(e0, e1);
+        g_stats.ms_search[1] += E.between(e0, e0b);
+        g_stats.ms_search[2] += E.between(e0b, e1);
         ms_prune += E.between(e1, e2);
         int64_t nrev = 0;
         HIPCHK(hipMemcpy(&nrev, roff + nt, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -548,31 +581,25 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     out->n_edges = nedges;
 
     rnsm_stats& S = g_stats;
-    S.ms_expand = ms_expand;
     S.ms_plan = ms_plan;
-    S.ms_search = ms_search;
     S.ms_prune = ms_prune;
     S.ms_compact = E.between(c0, c1);
     S.n_ops = (int64_t)ops.size();
-    S.ndc_expand = (int64_t)hc[0 * CNT_N + CNT_NDC];
-    S.ndc_naive = (int64_t)hc[1 * CNT_N + CNT_NDC];
-    S.ndc_slide = (int64_t)hc[2 * CNT_N + CNT_NDC];
-    S.exp_naive = (int64_t)hc[1 * CNT_N + CNT_EXP];
-    S.exp_slide = (int64_t)hc[2 * CNT_N + CNT_EXP];
-    S.adj_naive = (int64_t)hc[1 * CNT_N + CNT_ADJ];
-    S.adj_slide = (int64_t)hc[2 * CNT_N + CNT_ADJ];
-    S.hash_full = (int64_t)(hc[0 * CNT_N + CNT_HFULL] + hc[1 * CNT_N + CNT_HFULL] +
-                            hc[2 * CNT_N + CNT_HFULL]);
-    S.search_launches = 2 * (int64_t)ops.size();
-    // algorithmic bytes of the searches: every distance reads one row, every
-    // expansion reads two offsets and its adjacency, every query reads its
-    // row and writes its beam, followers read their pivot's beam
+    S.row_bytes = vi.row_bytes;
     const double rb = vi.row_bytes;
-    S.search_bytes = (double)(S.ndc_naive + S.ndc_slide) * rb +
-                     (double)(S.exp_naive + S.exp_slide) * 16.0 +
-                     (double)(S.adj_naive + S.adj_slide) * 4.0 +
-                     (double)S.n_source_vertices * (rb + 4.0 * RES) +
-                     (double)S.n_followers * 4.0 * efN;
+    for (int ph = 0; ph < 3; ++ph) {
+        S.ndc[ph] = (int64_t)hc[ph * CNT_N + CNT_NDC];
+        S.expansions[ph] = (int64_t)hc[ph * CNT_N + CNT_EXP];
+        S.adjacency[ph] = (int64_t)hc[ph * CNT_N + CNT_ADJ];
+        S.hash_evictions += (int64_t)hc[ph * CNT_N + CNT_HFULL];
+        // every distance reads one row, every expansion reads two offsets and
+        // its adjacency, every query reads its row and writes its result;
+        // followers also read their pivot's beam
+        const double out_w = ph == 0 ? k : (ph == 1 ? efN : efS);
+        S.bytes[ph] = (double)S.ndc[ph] * rb + (double)S.expansions[ph] * 16.0 +
+                      (double)S.adjacency[ph] * 4.0 + (double)S.queries[ph] * (rb + 4.0 * out_w) +
+                      (ph == 2 ? (double)S.queries[ph] * 4.0 * efN : 0.0);
+    }
     S.ms_total = ms_since(t0);
     (void)fallbacks;
     return RNSM_OK;
@@ -650,8 +677,9 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     a.ef = ef;
     a.G = vi.G;
     a.cpl = vi.cpl;
-    int wpb;
-    search_shape(ef, 32, &a.hbits, &wpb);
+    const SearchShape sh = search_shape(ef, 32);
+    a.hbits = sh.hbits;
+    a.hash_mode = sh.mode;
     a.out_mode = 0;
     a.out_ids = out_ids;
     a.out_d = out_dists;
@@ -659,7 +687,7 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     a.out_k = k;
     a.counters = cnt;
     a.err = errf;
-    HIPCHK(launch_search(vi.tt, a, wpb, st));
+    HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
     int herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -731,7 +759,7 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
         WS(roff, "b_roff", sizeof(int64_t) * (n + 1));
         WS(rev, "b_rev", sizeof(int32_t) * n * R);
         WS(stmp, "b_stmp", sizeof(int64_t) * scan_tmp_elems(n));
-        WS(scratch, "b_scratch", sizeof(u64) * 2 * n * R);
+        WS(scratch, "b_scratch", sizeof(u64) * 4 * n * R);
         HIPCHK(hipMemsetAsync(rc, 0, sizeof(int32_t) * n, st));
         HIPCHK(hipMemsetAsync(rcur, 0, sizeof(int32_t) * n, st));
         HIPCHK(launch_rev_count(rows1, deg1, 0, n, R, 0, n, rc, st));

@@ -34,6 +34,7 @@ struct SearchArgs {
     int G;                    // lanes per row
     int cpl;                  // chunks per lane
     int hbits;                // log2 of the LDS visited-table size per wavefront
+    int hash_mode;            // 0: direct-mapped (forgetful), 1: linear probing
     int out_mode;             // 0: first out_k of the beam, 1: first out_k excluding the query's own id
     int32_t* out_ids;
     float* out_d;
@@ -82,6 +83,7 @@ hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n,
                             int R, int32_t* rows, int32_t* deg, float* rdist, hipStream_t st);
 hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st);
 hipError_t launch_search(int tt, const SearchArgs& a, int waves_per_block, hipStream_t st);
+size_t search_lds_bytes(int hbits, int waves_per_block);
 hipError_t launch_prune(const PruneArgs& a, hipStream_t st);
 hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* off, int64_t* tmp_blocks,
                        hipStream_t st);

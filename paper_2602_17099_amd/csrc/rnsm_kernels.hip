@@ -122,6 +122,34 @@ struct Beam {
     unsigned e[EFS];  // expanded flag
 };
 
+// DPP moves (gfx9 controls): the source lane's value, `old` where there is none
+#define DPP_ROW_SHR(n) (0x110 + (n))
+#define DPP_WAVE_SHR1 0x138
+#define DPP_ROW_BCAST15 0x142
+#define DPP_ROW_BCAST31 0x143
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_add_src(float v) {
+    // value of the DPP source lane, 0 where the source is out of range
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ unsigned wave_shr1(unsigned v) {
+    return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_WAVE_SHR1, 0xF, 0xF, false);
+}
+
+// sum over each aligned group of G lanes; the total is valid in the group's
+// last lane (sub == G-1)
+template <int G>
+__device__ __forceinline__ float group_sum_last(float v) {
+    if constexpr (G >= 2) v += dpp_add_src<DPP_ROW_SHR(1)>(v);
+    if constexpr (G >= 4) v += dpp_add_src<DPP_ROW_SHR(2)>(v);
+    if constexpr (G >= 8) v += dpp_add_src<DPP_ROW_SHR(4)>(v);
+    if constexpr (G >= 16) v += dpp_add_src<DPP_ROW_SHR(8)>(v);
+    if constexpr (G >= 32) v += dpp_add_src<DPP_ROW_BCAST15>(v);
+    if constexpr (G >= 64) v += dpp_add_src<DPP_ROW_BCAST31>(v);
+    return v;
+}
+
 template <int EFS>
 __device__ __forceinline__ u64 beam_worst(const Beam<EFS>& B, int ef) {
     const int s = ef - 1;
@@ -132,7 +160,12 @@ __device__ __forceinline__ u64 beam_worst(const Beam<EFS>& B, int ef) {
     }
 }
 
+__device__ __forceinline__ u64 shr1_u64(u64 x) {
+    return ((u64)wave_shr1((unsigned)(x >> 32)) << 32) | wave_shr1((unsigned)(x & 0xffffffffu));
+}
+
 // insert key into the sorted beam of capacity ef; drops exact duplicates
+// (a vertex evaluated again after the visited table forgot it)
 template <int EFS>
 __device__ __forceinline__ void beam_insert(Beam<EFS>& B, u64 key, int ef, int lane) {
     u64 lt = __ballot(B.k[0] < key);
@@ -145,8 +178,8 @@ __device__ __forceinline__ void beam_insert(Beam<EFS>& B, u64 key, int ef, int l
     }
     if (eq != 0ull || pos >= ef) return;
     if constexpr (EFS == 1) {
-        u64 up = __shfl_up(B.k[0], 1);
-        unsigned eup = __shfl_up(B.e[0], 1);
+        const u64 up = shr1_u64(B.k[0]);
+        const unsigned eup = wave_shr1(B.e[0]);
         if (lane > pos) {
             B.k[0] = up;
             B.e[0] = eup;
@@ -161,10 +194,10 @@ __device__ __forceinline__ void beam_insert(Beam<EFS>& B, u64 key, int ef, int l
     } else {
         const u64 a63 = readlane64(B.k[0], 63);
         const unsigned e63 = (unsigned)__builtin_amdgcn_readlane((int)B.e[0], 63);
-        u64 upa = __shfl_up(B.k[0], 1);
-        unsigned eupa = __shfl_up(B.e[0], 1);
-        u64 upb = __shfl_up(B.k[1], 1);
-        unsigned eupb = __shfl_up(B.e[1], 1);
+        const u64 upa = shr1_u64(B.k[0]);
+        const unsigned eupa = wave_shr1(B.e[0]);
+        const u64 upb = shr1_u64(B.k[1]);
+        const unsigned eupb = wave_shr1(B.e[1]);
         if (lane > pos) {
             B.k[0] = upa;
             B.e[0] = eupa;
@@ -189,17 +222,25 @@ __device__ __forceinline__ void beam_insert(Beam<EFS>& B, u64 key, int ef, int l
     }
 }
 
-// 0: already visited, 1: newly visited, 2: table full along the probe path
+// visited table. Mode 0 (fast): direct-mapped, a vertex replaces whatever
+// held its slot. Mode 1 (exact while the table has room): linear probing.
+// 0: seen, 1: not seen, 2: not seen (or forgotten) and another vertex was
+// evicted / the probe path was full
+template <bool EXACT>
 __device__ __forceinline__ int hash_visit(int* tab, int hbits, int v) {
-    const unsigned mask = (1u << hbits) - 1u;
-    unsigned h = ((unsigned)v * 2654435761u) >> (32 - hbits);
-#pragma unroll 1
-    for (int p = 0; p < 16; ++p) {
-        int old = atomicCAS(&tab[(h + p) & mask], -1, v);
-        if (old == -1) return 1;
-        if (old == v) return 0;
+    const unsigned h = ((unsigned)v * 2654435761u) >> (32 - hbits);
+    if constexpr (!EXACT) {
+        const int old = atomicExch(&tab[h], v);
+        return old == v ? 0 : (old == -1 ? 1 : 2);
+    } else {
+        const unsigned mask = (1u << hbits) - 1u;
+        for (int p = 0; p < 64; ++p) {
+            const int old = atomicCAS(&tab[(h + p) & mask], -1, v);
+            if (old == -1) return 1;
+            if (old == v) return 0;
+        }
+        return 2;
     }
-    return 2;
 }
 
 template <int TT>
@@ -207,19 +248,27 @@ struct Query {
     float q[MAXCPL][Elt<TT>::EPC];
 };
 
+__host__ __device__ constexpr int search_lds_words(int hbits) { return (1 << hbits) + 64; }
+
+template <int G>
+struct Grp {
+    static constexpr int RPP = WAVE / G;                               // rows per pass
+    static constexpr int UNR = RPP >= 32 ? 1 : (RPP >= 8 ? 2 : 4);     // passes per batch
+};
+
 // evaluate the per-lane candidates v (-1: none): visited filter, distances,
 // beam insertion
-template <int TT, int EFS>
+template <int TT, int EFS, int G, bool EXACT>
 __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS>& B,
                                                    const Query<TT>& Q, float qn, int* tab,
                                                    int* cl, int v, int lane, u64& ndc,
-                                                   u64& hfull) {
+                                                   u64& nevict) {
     constexpr int EPC = Elt<TT>::EPC;
+    constexpr int RPP = Grp<G>::RPP, UNR = Grp<G>::UNR;
     int st = 0;
     if (v >= a.n) v = -1;  // ids from callers are range-checked
-    if (v >= 0) st = hash_visit(tab, a.hbits, v);
-    const u64 full = __ballot(st == 2);
-    hfull += __popcll(full);
+    if (v >= 0) st = hash_visit<EXACT>(tab, a.hbits, v);
+    nevict += __popcll(__ballot(st == 2));
     const u64 m = __ballot(st != 0);
     const int nc = __popcll(m);
     if (nc == 0) return;
@@ -228,9 +277,7 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     ndc += nc;
-    const int G = a.G, RPP = WAVE / G;
     const int group = lane / G, sub = lane - group * G;
-    constexpr int UNR = 4;
     for (int c0 = 0; c0 < nc; c0 += RPP * UNR) {
         uint4 raw[UNR][MAXCPL];
         int cid[UNR];
@@ -248,10 +295,10 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
                     raw[u][j] = make_uint4(0, 0, 0, 0);
             }
         }
-        u64 key[UNR];
+        float acc[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            float acc = 0.0f;
+            float s = 0.0f;
 #pragma unroll
             for (int j = 0; j < MAXCPL; ++j) {
                 float x[EPC];
@@ -260,54 +307,52 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
 #pragma unroll
                     for (int t = 0; t < EPC; ++t) {
                         const float d = Q.q[j][t] - x[t];
-                        acc = fmaf(d, d, acc);
+                        s = fmaf(d, d, s);
                     }
                 } else {
 #pragma unroll
-                    for (int t = 0; t < EPC; ++t) acc = fmaf(Q.q[j][t], x[t], acc);
+                    for (int t = 0; t < EPC; ++t) s = fmaf(Q.q[j][t], x[t], s);
                 }
             }
-            acc = group_sum(acc, G);
-            float nb = 1.0f;
-            if (a.metric == 2 && cid[u] >= 0) nb = a.base_norm[cid[u]];
-            const float d = finalize_dist(acc, a.metric, qn, nb);
-            key[u] = (cid[u] >= 0 && sub == 0) ? make_key(d, cid[u]) : EMPTY_KEY;
+            acc[u] = group_sum_last<G>(s);
         }
+        const u64 worst = beam_worst(B, a.ef);
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const u64 worst = beam_worst(B, a.ef);
-            u64 mm = __ballot(key[u] < worst);
+            u64 key = EMPTY_KEY;
+            if (sub == G - 1 && cid[u] >= 0) {
+                float nb = 1.0f;
+                if (a.metric == 2) nb = a.base_norm[cid[u]];
+                key = make_key(finalize_dist(acc[u], a.metric, qn, nb), cid[u]);
+            }
+            u64 mm = __ballot(key < worst);
             while (mm) {
                 const int l = __ffsll((long long)mm) - 1;
                 mm &= mm - 1;
-                const u64 kk = readlane64(key[u], l);
-                beam_insert(B, kk, a.ef, lane);
+                beam_insert(B, readlane64(key, l), a.ef, lane);
             }
         }
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int TT, int EFS>
+template <int TT, int EFS, int G, bool EXACT>
 __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     extern __shared__ int smem[];
-    constexpr int EPC = Elt<TT>::EPC;
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     const int64_t i = xcd_block() * wpb + wib;
     if (i >= a.nq) return;
     const int H = 1 << a.hbits;
-    int* tab = smem + wib * (H + WAVE);
+    int* tab = smem + (int64_t)wib * search_lds_words(a.hbits);
     int* cl = tab + H;
     for (int t = lane; t < H; t += WAVE) tab[t] = -1;
     __builtin_amdgcn_wave_barrier();
 
     const int u = a.qidx ? a.qidx[i] : (int)i;
     const char* qrow = a.qvec + (int64_t)u * a.row_bytes;
-    const int G = a.G;
-    const int group = lane / G, sub = lane - group * G;
-    (void)group;
+    const int sub = lane % G;
     Query<TT> Q;
 #pragma unroll
     for (int j = 0; j < MAXCPL; ++j) {
@@ -324,19 +369,20 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
         B.k[s] = EMPTY_KEY;
         B.e[s] = 0;
     }
-    u64 ndc = 0, nexp = 0, nadj = 0, hfull = 0;
+    u64 ndc = 0, nexp = 0, nadj = 0, nevict = 0;
 
     // seeds
     if (a.seed_mode == 0 || a.seed_mode == 1) {
         const int s0 = a.seed_mode == 0 ? a.entry : u;
-        process_candidates<TT, EFS>(a, B, Q, qn, tab, cl, lane == 0 ? s0 : -1, lane, ndc, hfull);
+        process_candidates<TT, EFS, G, EXACT>(a, B, Q, qn, tab, cl, lane == 0 ? s0 : -1, lane, ndc,
+                                       nevict);
     } else {
         const int64_t srow = a.seed_row ? a.seed_row[i] : i;
         const int32_t* sp = a.seed_ids + srow * a.seed_stride;
         for (int j0 = 0; j0 < a.n_seeds; j0 += WAVE) {
             const int j = j0 + lane;
             const int v = j < a.n_seeds ? sp[j] : -1;
-            process_candidates<TT, EFS>(a, B, Q, qn, tab, cl, v, lane, ndc, hfull);
+            process_candidates<TT, EFS, G, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
         }
     }
 
@@ -374,7 +420,7 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
         for (int64_t j0 = b; j0 < en; j0 += WAVE) {
             const int64_t j = j0 + lane;
             const int v = j < en ? a.nbrs[j] : -1;
-            process_candidates<TT, EFS>(a, B, Q, qn, tab, cl, v, lane, ndc, hfull);
+            process_candidates<TT, EFS, G, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
         }
         if (it > maxit) {
             if (lane == 0) atomicOr(a.err, 1);
@@ -416,22 +462,65 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
         atomicAdd(&a.counters[CNT_NDC], ndc);
         atomicAdd(&a.counters[CNT_EXP], nexp);
         atomicAdd(&a.counters[CNT_ADJ], nadj);
-        atomicAdd(&a.counters[CNT_HFULL], hfull);
+        atomicAdd(&a.counters[CNT_HFULL], nevict);
     }
 }
 
 // ------------------------------------------------------------------ prune
 
-template <int KS>
+// float32 distance between the lane-group layouts of two rows (valid in the
+// group's last lane)
+template <int G>
+__device__ __forceinline__ float dist_rows(const float4* a, const float4* b, int metric) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < MAXCPL; ++j) {
+        const float4 x = a[j], q = b[j];
+        if (metric == 0) {
+            const float d0 = q.x - x.x, d1 = q.y - x.y, d2 = q.z - x.z, d3 = q.w - x.w;
+            acc = fmaf(d0, d0, acc);
+            acc = fmaf(d1, d1, acc);
+            acc = fmaf(d2, d2, acc);
+            acc = fmaf(d3, d3, acc);
+        } else {
+            acc = fmaf(q.x, x.x, acc);
+            acc = fmaf(q.y, x.y, acc);
+            acc = fmaf(q.z, x.z, acc);
+            acc = fmaf(q.w, x.w, acc);
+        }
+    }
+    return group_sum_last<G>(acc);
+}
+
+__device__ __forceinline__ void load_row_f32(const float* X, int64_t id, int rowf, int sub, int G,
+                                             int cpl, int nch, float4* out) {
+    const float* r = X + id * rowf;
+#pragma unroll
+    for (int j = 0; j < MAXCPL; ++j) {
+        const int ch = sub + j * G;
+        out[j] = (id >= 0 && j < cpl && ch < nch) ? *(const float4*)(r + ch * 4)
+                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// Prune(p, W): W = current row of p plus the extra candidates; keys (d, id)
+// are computed, sorted by rank, and walked in order; a candidate is kept
+// unless alpha * d(w, v) < d(p, v) for a kept w (strict, in double); stop at
+// R kept. Kept rows stay in registers (KS slots per lane group) or are
+// re-read (KS == 0).
+template <int G, int KS>
 __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     extern __shared__ unsigned char psm[];
+    constexpr int RPP = WAVE / G;
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     const int64_t i = xcd_block() * wpb + wib;
     if (i >= a.n_items) return;
-    u64* lkeys = (u64*)psm + (int64_t)wib * (a.wcap + a.R);
-    int* kept_ids = (int*)(lkeys + a.wcap);
+    // per wavefront: keys[wcap], sorted[wcap], kept ids[R]
+    u64* lkeys = (u64*)psm + (int64_t)wib * (2 * a.wcap + a.R);
+    u64* lsort = lkeys + a.wcap;
+    int* kept_ids = (int*)(lsort + a.wcap);
     const int64_t p = a.items ? (int64_t)a.items[i] : a.item_base + i;
     const int64_t e = p - a.extra_index_base;
     const int R = a.R;
@@ -449,14 +538,16 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     if (a.skip_empty_extra && next == 0) return;
     const int nW = nrow + next;
     u64* wk = lkeys;
+    u64* ws = lsort;
     if (nW > a.wcap) {
         if (a.extra_mode != 2 || !a.scratch) {
             if (lane == 0) atomicOr(a.err, 2);
             return;
         }
-        wk = a.scratch + (int64_t)R * e + xo;
+        wk = a.scratch + 2 * ((int64_t)R * e + xo);
+        ws = wk + nW;
     }
-    // gather candidate ids
+    // candidate ids
     for (int t = lane; t < nW; t += WAVE) {
         int64_t id;
         if (t < nrow) {
@@ -475,22 +566,13 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    const int G = a.G, RPP = WAVE / G;
     const int group = lane / G, sub = lane - group * G;
-    const int rowf = a.nch * 4;  // floats per row
+    const int rowf = a.nch * 4;
     float4 pq[MAXCPL];
-    {
-        const float* pr = a.X + p * rowf;
-#pragma unroll
-        for (int j = 0; j < MAXCPL; ++j) {
-            const int ch = sub + j * G;
-            pq[j] = (j < a.cpl && ch < a.nch) ? *(const float4*)(pr + ch * 4)
-                                              : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-    }
+    load_row_f32(a.X, p, rowf, sub, G, a.cpl, a.nch, pq);
     const float pn = a.metric == 2 ? a.norms[p] : 1.0f;
-    // distances d(p, w) -> keys
-    constexpr int UNR = 2;
+    // keys (d(p, w), w)
+    constexpr int UNR = RPP >= 16 ? 1 : 2;
     for (int c0 = 0; c0 < nW; c0 += RPP * UNR) {
         float4 raw[UNR][MAXCPL];
         int cid[UNR];
@@ -499,37 +581,13 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
             const int c = c0 + u * RPP + group;
             const u64 kk = c < nW ? wk[c] : EMPTY_KEY;
             cid[u] = kk == EMPTY_KEY ? -1 : (int)kk;
-            const float* row = a.X + (int64_t)(cid[u] < 0 ? 0 : cid[u]) * rowf;
-#pragma unroll
-            for (int j = 0; j < MAXCPL; ++j) {
-                const int ch = sub + j * G;
-                raw[u][j] = (cid[u] >= 0 && j < a.cpl && ch < a.nch)
-                                ? *(const float4*)(row + ch * 4)
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+            load_row_f32(a.X, cid[u], rowf, sub, G, a.cpl, a.nch, raw[u]);
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int j = 0; j < MAXCPL; ++j) {
-                const float4 x = raw[u][j], q = pq[j];
-                if (a.metric == 0) {
-                    float d0 = q.x - x.x, d1 = q.y - x.y, d2 = q.z - x.z, d3 = q.w - x.w;
-                    acc = fmaf(d0, d0, acc);
-                    acc = fmaf(d1, d1, acc);
-                    acc = fmaf(d2, d2, acc);
-                    acc = fmaf(d3, d3, acc);
-                } else {
-                    acc = fmaf(q.x, x.x, acc);
-                    acc = fmaf(q.y, x.y, acc);
-                    acc = fmaf(q.z, x.z, acc);
-                    acc = fmaf(q.w, x.w, acc);
-                }
-            }
-            acc = group_sum(acc, G);
+            const float acc = dist_rows<G>(raw[u], pq, a.metric);
             const int c = c0 + u * RPP + group;
-            if (sub == 0 && cid[u] >= 0) {
+            if (sub == G - 1 && cid[u] >= 0) {
                 const float nb = a.metric == 2 ? a.norms[cid[u]] : 1.0f;
                 wk[c] = make_key(finalize_dist(acc, a.metric, pn, nb), cid[u]);
             }
@@ -538,80 +596,69 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // sort by rank: position = #smaller keys + #equal keys earlier
+    for (int t = lane; t < nW; t += WAVE) {
+        const u64 kt = wk[t];
+        int r = 0;
+        for (int s = 0; s < nW; ++s) {
+            const u64 ks = wk[s];
+            r += (ks < kt || (ks == kt && s < t)) ? 1 : 0;
+        }
+        ws[r] = kt;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // greedy selection in (d, id) order
+    // walk the candidates in (d, id) order
     float4 kept[KS > 0 ? KS : 1][MAXCPL];
     const double alpha = (double)a.alpha;
     int nk = 0;
-    bool started = false;
-    u64 lastk = 0;
-    while (nk < R) {
-        u64 mn = EMPTY_KEY;
-        for (int t = lane; t < nW; t += WAVE) {
-            const u64 kk = wk[t];
-            if (kk != EMPTY_KEY && (!started || kk > lastk) && kk < mn) mn = kk;
-        }
-        mn = wave_min_u64(mn);
-        if (mn == EMPTY_KEY) break;
-        started = true;
-        lastk = mn;
-        const int v = (int)(unsigned)(mn & 0xffffffffu);
-        const float dv = fval((unsigned)(mn >> 32));
-        float4 vx[MAXCPL];
-        {
-            const float* vr = a.X + (int64_t)v * rowf;
+    u64 prev = EMPTY_KEY;
+    float4 vx[MAXCPL], nx[MAXCPL];
+    u64 cur = nW > 0 ? ws[0] : EMPTY_KEY;
+    load_row_f32(a.X, cur == EMPTY_KEY ? -1 : (int64_t)(unsigned)(cur & 0xffffffffu), rowf, sub,
+                 G, a.cpl, a.nch, nx);
+    for (int t = 0; t < nW && nk < R; ++t) {
+        if (cur == EMPTY_KEY) break;
 #pragma unroll
-            for (int j = 0; j < MAXCPL; ++j) {
-                const int ch = sub + j * G;
-                vx[j] = (j < a.cpl && ch < a.nch) ? *(const float4*)(vr + ch * 4)
-                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-        }
+        for (int j = 0; j < MAXCPL; ++j) vx[j] = nx[j];
+        const u64 kcur = cur;
+        // prefetch the next candidate's row
+        cur = t + 1 < nW ? ws[t + 1] : EMPTY_KEY;
+        load_row_f32(a.X, cur == EMPTY_KEY ? -1 : (int64_t)(unsigned)(cur & 0xffffffffu), rowf,
+                     sub, G, a.cpl, a.nch, nx);
+        if (kcur == prev) continue;  // the same vertex twice in W
+        prev = kcur;
+        const int v = (int)(unsigned)(kcur & 0xffffffffu);
+        const float dv = fval((unsigned)(kcur >> 32));
         const float vn = a.metric == 2 ? a.norms[v] : 1.0f;
         bool dom = false;
         const int nslots = (nk + RPP - 1) / RPP;
-        for (int s = 0; s < nslots; ++s) {
-            const int jk = s * RPP + group;
-            float4 kx[MAXCPL];
-            if constexpr (KS > 0) {
+        if constexpr (KS > 0) {
 #pragma unroll
-                for (int ss = 0; ss < KS; ++ss)
-                    if (ss == s) {
-#pragma unroll
-                        for (int j = 0; j < MAXCPL; ++j) kx[j] = kept[ss][j];
+            for (int s = 0; s < KS; ++s) {
+                if (s < nslots) {
+                    const float acc = dist_rows<G>(kept[s], vx, a.metric);
+                    const int jk = s * RPP + group;
+                    if (jk < nk && sub == G - 1) {
+                        const float kn = a.metric == 2 ? a.norms[kept_ids[jk]] : 1.0f;
+                        const float dkv = finalize_dist(acc, a.metric, kn, vn);
+                        if (alpha * (double)dkv < (double)dv) dom = true;
                     }
-            } else {
-                const int kid = jk < nk ? kept_ids[jk] : v;
-                const float* kr = a.X + (int64_t)kid * rowf;
-#pragma unroll
-                for (int j = 0; j < MAXCPL; ++j) {
-                    const int ch = sub + j * G;
-                    kx[j] = (j < a.cpl && ch < a.nch) ? *(const float4*)(kr + ch * 4)
-                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             }
-            float acc = 0.0f;
-#pragma unroll
-            for (int j = 0; j < MAXCPL; ++j) {
-                const float4 x = vx[j], q = kx[j];
-                if (a.metric == 0) {
-                    float d0 = q.x - x.x, d1 = q.y - x.y, d2 = q.z - x.z, d3 = q.w - x.w;
-                    acc = fmaf(d0, d0, acc);
-                    acc = fmaf(d1, d1, acc);
-                    acc = fmaf(d2, d2, acc);
-                    acc = fmaf(d3, d3, acc);
-                } else {
-                    acc = fmaf(q.x, x.x, acc);
-                    acc = fmaf(q.y, x.y, acc);
-                    acc = fmaf(q.z, x.z, acc);
-                    acc = fmaf(q.w, x.w, acc);
+        } else {
+            for (int s = 0; s < nslots; ++s) {
+                const int jk = s * RPP + group;
+                float4 kx[MAXCPL];
+                load_row_f32(a.X, jk < nk ? kept_ids[jk] : -1, rowf, sub, G, a.cpl, a.nch, kx);
+                const float acc = dist_rows<G>(kx, vx, a.metric);
+                if (jk < nk && sub == G - 1) {
+                    const float kn = a.metric == 2 ? a.norms[kept_ids[jk]] : 1.0f;
+                    const float dkv = finalize_dist(acc, a.metric, kn, vn);
+                    if (alpha * (double)dkv < (double)dv) dom = true;
                 }
-            }
-            acc = group_sum(acc, G);
-            if (jk < nk && sub == 0) {
-                const float kn = a.metric == 2 ? a.norms[kept_ids[jk]] : 1.0f;
-                const float dkv = finalize_dist(acc, a.metric, kn, vn);
-                if (alpha * (double)dkv < (double)dv) dom = true;
             }
         }
         if (__ballot(dom) != 0ull) continue;
@@ -639,25 +686,42 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
 
 // ------------------------------------------------------------ small kernels
 
-__global__ void k_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t nnz,
-                           int R, int* flags) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// one wavefront per row: offsets, degree, id range, self-loops, duplicates
+__global__ __launch_bounds__(256) void k_validate(const int64_t* offs, const int32_t* nbrs,
+                                                  int64_t n, int64_t nnz, int R, int* flags) {
+    __shared__ int rowbuf[4][WAVE];
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    const int64_t v = (int64_t)blockIdx.x * 4 + w;
     if (v >= n) return;
     const int64_t b = offs[v], e = offs[v + 1];
-    int f = 0;
     if (b > e || b < 0 || e > nnz) {
-        atomicOr(flags, 1);
+        if (lane == 0) atomicOr(flags, 1);
         return;
     }
-    if (e - b > R) f |= 2;
-    for (int64_t j = b; j < e; ++j) {
-        const int32_t x = nbrs[j];
+    const int64_t deg = e - b;
+    if (deg > R || deg > WAVE) {
+        if (lane == 0) atomicOr(flags, 2);
+        return;
+    }
+    const int x = lane < deg ? nbrs[b + lane] : -1;
+    int f = 0;
+    if (lane < deg) {
         if (x < 0 || x >= n) f |= 4;
         if (x == v) f |= 8;
-        for (int64_t t = b; t < j; ++t)
-            if (nbrs[t] == x) f |= 16;
     }
-    if (f) atomicOr(flags, f);
+    rowbuf[w][lane] = x;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < deg)
+        for (int t = 0; t < lane; ++t)
+            if (rowbuf[w][t] == x) f |= 16;
+    int all = 0;
+#pragma unroll
+    for (int bit = 4; bit <= 16; bit <<= 1)
+        if (__ballot((f & bit) != 0) != 0ull) all |= bit;
+    if (lane == 0 && all) atomicOr(flags, all);
 }
 
 __global__ void k_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
@@ -956,8 +1020,7 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / 
 hipError_t launch_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t nnz,
                            int R, int* flags, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_validate, dim3(nblk(n, 256)), dim3(256), 0, st, offs, nbrs, n, nnz, R,
-                       flags);
+    hipLaunchKernelGGL(k_validate, dim3(nblk(n, 4)), dim3(256), 0, st, offs, nbrs, n, nnz, R, flags);
     return hipGetLastError();
 }
 
@@ -975,41 +1038,78 @@ hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStrea
     return hipGetLastError();
 }
 
+template <int TT, int EFS, bool EXACT>
+static void launch_search_g(const SearchArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+    switch (a.G) {
+        case 1: hipLaunchKernelGGL((k_beam_search<TT, EFS, 1, EXACT>), grid, block, lds, st, a); break;
+        case 2: hipLaunchKernelGGL((k_beam_search<TT, EFS, 2, EXACT>), grid, block, lds, st, a); break;
+        case 4: hipLaunchKernelGGL((k_beam_search<TT, EFS, 4, EXACT>), grid, block, lds, st, a); break;
+        case 8: hipLaunchKernelGGL((k_beam_search<TT, EFS, 8, EXACT>), grid, block, lds, st, a); break;
+        case 16: hipLaunchKernelGGL((k_beam_search<TT, EFS, 16, EXACT>), grid, block, lds, st, a); break;
+        case 32: hipLaunchKernelGGL((k_beam_search<TT, EFS, 32, EXACT>), grid, block, lds, st, a); break;
+        default: hipLaunchKernelGGL((k_beam_search<TT, EFS, 64, EXACT>), grid, block, lds, st, a); break;
+    }
+}
+
+template <int TT, int EFS>
+static void launch_search_m(const SearchArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+    if (a.hash_mode)
+        launch_search_g<TT, EFS, true>(a, grid, block, lds, st);
+    else
+        launch_search_g<TT, EFS, false>(a, grid, block, lds, st);
+}
+
+size_t search_lds_bytes(int hbits, int wpb) {
+    return (size_t)wpb * search_lds_words(hbits) * sizeof(int);
+}
+
 hipError_t launch_search(int tt, const SearchArgs& a, int wpb, hipStream_t st) {
     if (a.nq <= 0) return hipSuccess;
-    const size_t lds = (size_t)wpb * (((size_t)1 << a.hbits) + WAVE) * sizeof(int);
+    const size_t lds = search_lds_bytes(a.hbits, wpb);
     const dim3 grid(nblk(a.nq, wpb)), block(wpb * WAVE);
     const int efs = a.ef > 64 ? 2 : 1;
-#define RNSM_SEARCH(TT, EFS)                                                           \
-    hipLaunchKernelGGL((k_beam_search<TT, EFS>), grid, block, lds, st, a)
     if (tt == 0) {
-        if (efs == 1) RNSM_SEARCH(0, 1); else RNSM_SEARCH(0, 2);
+        if (efs == 1) launch_search_m<0, 1>(a, grid, block, lds, st);
+        else launch_search_m<0, 2>(a, grid, block, lds, st);
     } else if (tt == 1) {
-        if (efs == 1) RNSM_SEARCH(1, 1); else RNSM_SEARCH(1, 2);
+        if (efs == 1) launch_search_m<1, 1>(a, grid, block, lds, st);
+        else launch_search_m<1, 2>(a, grid, block, lds, st);
     } else {
-        if (efs == 1) RNSM_SEARCH(2, 1); else RNSM_SEARCH(2, 2);
+        if (efs == 1) launch_search_m<2, 1>(a, grid, block, lds, st);
+        else launch_search_m<2, 2>(a, grid, block, lds, st);
     }
-#undef RNSM_SEARCH
     return hipGetLastError();
+}
+
+template <int G>
+static void launch_prune_g(const PruneArgs& a, int need, dim3 grid, dim3 block, size_t lds,
+                           hipStream_t st) {
+    if (need <= 1)
+        hipLaunchKernelGGL((k_prune<G, 1>), grid, block, lds, st, a);
+    else if (need <= 2)
+        hipLaunchKernelGGL((k_prune<G, 2>), grid, block, lds, st, a);
+    else if (need <= 4)
+        hipLaunchKernelGGL((k_prune<G, 4>), grid, block, lds, st, a);
+    else
+        hipLaunchKernelGGL((k_prune<G, 0>), grid, block, lds, st, a);
 }
 
 hipError_t launch_prune(const PruneArgs& a, hipStream_t st) {
     if (a.n_items <= 0) return hipSuccess;
-    const int wpb = 4;
-    const size_t lds = (size_t)wpb * ((size_t)(a.wcap + a.R) * sizeof(u64));
+    const int wpb = 2;
+    const size_t lds = (size_t)wpb * ((size_t)(2 * a.wcap + a.R) * sizeof(u64));
     const dim3 grid(nblk(a.n_items, wpb)), block(wpb * WAVE);
     const int rpp = WAVE / a.G;
     const int need = (a.R + rpp - 1) / rpp;
-    if (need <= 1)
-        hipLaunchKernelGGL(k_prune<1>, grid, block, lds, st, a);
-    else if (need <= 2)
-        hipLaunchKernelGGL(k_prune<2>, grid, block, lds, st, a);
-    else if (need <= 4)
-        hipLaunchKernelGGL(k_prune<4>, grid, block, lds, st, a);
-    else if (need <= 8)
-        hipLaunchKernelGGL(k_prune<8>, grid, block, lds, st, a);
-    else
-        hipLaunchKernelGGL(k_prune<0>, grid, block, lds, st, a);
+    switch (a.G) {
+        case 1: launch_prune_g<1>(a, need, grid, block, lds, st); break;
+        case 2: launch_prune_g<2>(a, need, grid, block, lds, st); break;
+        case 4: launch_prune_g<4>(a, need, grid, block, lds, st); break;
+        case 8: launch_prune_g<8>(a, need, grid, block, lds, st); break;
+        case 16: launch_prune_g<16>(a, need, grid, block, lds, st); break;
+        case 32: launch_prune_g<32>(a, need, grid, block, lds, st); break;
+        default: launch_prune_g<64>(a, need, grid, block, lds, st); break;
+    }
     return hipGetLastError();
 }
 

@@ -117,6 +117,22 @@ def test_search_tiny_visited_table(dev, orc, pkg, search_case, monkeypatch):
         assert ids[i].tolist() == rid.tolist(), i
 
 
+def test_search_duplicate_seeds_full_table(dev, orc, pkg, search_case, monkeypatch):
+    # with an overflowing visited table both copies of a duplicated seed are
+    # evaluated in the same batch; the beam must hold the vertex once
+    X, Q, off, nb, entry = search_case
+    monkeypatch.setenv("RNSM_HASH_BITS", "6")
+    g = np.random.default_rng(7)
+    seeds = g.integers(0, len(X), size=(len(Q), 120)).astype(np.int32)
+    seeds[:, 60:] = seeds[:, :60]
+    ids, ds = pkg.search(_t(off, dev), _t(nb, dev), entry, _t(X, dev), _t(Q, dev), 100, 100,
+                         seeds=_t(seeds, dev))
+    ids = ids.cpu().numpy()
+    for i in range(0, len(Q), 9):
+        rid, _, _ = orc.beam_search(off, nb, X, Q[i], seeds[i], 100)
+        assert ids[i, :len(rid)].tolist() == rid.tolist(), i
+
+
 # -------------------------------------------------------------- the merge
 
 @pytest.fixture(scope="module")
@@ -154,11 +170,23 @@ def test_merge_tiny_trace_steps(dev, orc, pkg, tiny):
     st = pkg.stats()
     tr = ref["trace"]
     assert st["n_pivots"] == tr["n_pivots"]
-    # visited-table overflow only adds re-evaluations
-    assert st["ndc_naive"] >= tr["ndc_naive"] and st["ndc_slide"] >= tr["ndc_slide"]
-    if st["hash_full"] == 0:
-        assert st["ndc_naive"] == tr["ndc_naive"] and st["ndc_slide"] == tr["ndc_slide"]
-        assert st["ndc_expand"] == tr["ndc_expand"]
+    # a forgetful visited table only adds re-evaluations
+    ref_ndc = [tr["ndc_expand"], tr["ndc_naive"], tr["ndc_slide"]]
+    assert all(g >= r for g, r in zip(st["ndc"], ref_ndc))
+
+
+def test_merge_tiny_exact_visited_counts(dev, orc, pkg, tiny, monkeypatch):
+    # with the probing visited table every vertex is evaluated once: the
+    # distance counts of all three search phases equal the oracle's
+    X, subs = tiny
+    ref = orc.merge(subs, X, R=16, L=32, alpha=1.2, trace=True)
+    monkeypatch.setenv("RNSM_EXACT_VISITED", "1")
+    got = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=16, L=32, alpha=1.2)
+    _assert_same_merge(got, ref)
+    st = pkg.stats()
+    tr = ref["trace"]
+    assert st["exact_visited"] == 1 and st["hash_evictions"] == 0
+    assert st["ndc"] == [tr["ndc_expand"], tr["ndc_naive"], tr["ndc_slide"]]
 
 
 @pytest.mark.parametrize("flags", [0, 1])
