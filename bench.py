@@ -173,11 +173,21 @@ def main():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--calib-only", action="store_true",
+                    help="only copy 1 GiB device to device (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
+    if args.calib_only:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": a.numel() * 4}))
+        return
     import paper_2602_17099_amd as pkg
     pkg.lib()
     wl = WORKLOADS[args.workload]
@@ -257,6 +267,7 @@ def main():
                      "sliding_search": st["ms_search"][2], "prune_and_reverse": st["ms_prune"],
                      "compact": st["ms_compact"], "total": st["ms_total"]},
         "counts": {"pivots": st["n_pivots"], "followers": st["n_followers"],
+                   "expansions": st["expansions"], "queries": st["queries"],
                    "reverse_edges": st["n_reverse_edges"], "ndc_exact": ndc_x,
                    "ndc_timed": st["ndc"], "visited_table_evictions": st["hash_evictions"]},
     }

@@ -83,8 +83,12 @@ typedef struct {
  *      (search may be NULL). RNSM_BF16 / RNSM_F16 read `search`, a device
  *      row-major [n x dim] array of 16-bit values (the plain FP32 form versus
  *      the reduced-precision form).
- * dim * element size must be a multiple of 16 bytes and dim <= 1024 (f32) or
- * dim <= 2048 (16-bit); otherwise RNSM_EUNSUPPORTED.
+ * Rows are read in 16-byte chunks by groups of G lanes, G a power of two,
+ * each lane holding 1 to 4 whole chunks: the number of chunks per row
+ * (dim * element size / 16, for the 16-bit copy and for the float32 rows)
+ * must be 2^k times 1, 2, 3 or 4 and at most 256 (float32: dim 4, 8, 12,
+ * 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024); otherwise
+ * RNSM_EUNSUPPORTED.
  */
 typedef struct {
     int64_t n;

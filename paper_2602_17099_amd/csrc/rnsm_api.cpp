@@ -49,7 +49,25 @@ struct Workspace {
         void* p = nullptr;
         size_t bytes = 0;
     };
-    std::map<std::string, Buf> bufs;
+    std::map<std::string, Buf> bufs, hbufs;
+    // pinned host staging buffers (hipHostMalloc), kept like the device ones
+    hipError_t hget(const char* name, size_t bytes, void** out) {
+        Buf& b = hbufs[name];
+        if (bytes == 0) bytes = 16;
+        if (b.bytes < bytes) {
+            if (b.p) {
+                hipError_t e = hipHostFree(b.p);
+                if (e != hipSuccess) return e;
+                b.p = nullptr;
+                b.bytes = 0;
+            }
+            hipError_t e = hipHostMalloc(&b.p, bytes, hipHostMallocDefault);
+            if (e != hipSuccess) return e;
+            b.bytes = bytes;
+        }
+        *out = b.p;
+        return hipSuccess;
+    }
     hipError_t get(const char* name, size_t bytes, void** out) {
         Buf& b = bufs[name];
         if (bytes == 0) bytes = 16;
@@ -71,6 +89,7 @@ struct Workspace {
 std::map<int, Workspace> g_ws;
 
 #define WS(ptr, name, bytes) HIPCHK(ws.get(name, (size_t)(bytes), (void**)&(ptr)))
+#define HS(ptr, name, bytes) HIPCHK(ws.hget(name, (size_t)(bytes), (void**)&(ptr)))
 
 int elt_size(rnsm_dtype t) { return t == RNSM_F32 ? 4 : 2; }
 
@@ -141,7 +160,10 @@ rnsm_status vec_info(const rnsm_vectors* v, VecInfo& vi) {
     vi.G = lanes_per_row(vi.nch);
     vi.nch32 = v->dim / 4;
     vi.G32 = lanes_per_row(vi.nch32);
-    if (vi.G < 0 || vi.G32 < 0) return fail(RNSM_EUNSUPPORTED, "vectors: dim %d too large", v->dim);
+    if (vi.G < 0 || vi.G32 < 0)
+        return fail(RNSM_EUNSUPPORTED,
+                    "vectors: dim %d does not split into whole 16-byte chunks per lane "
+                    "(supported: chunks per row = 2^k x {1,2,3,4}, up to 256)", v->dim);
     vi.cpl = (vi.nch + vi.G - 1) / vi.G;
     vi.cpl32 = (vi.nch32 + vi.G32 - 1) / vi.G32;
     vi.search = v->search_dtype == RNSM_F32 ? (const char*)v->f32 : (const char*)v->search;
@@ -299,9 +321,9 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     WS(rows, "rows", sizeof(int32_t) * N * R);
     WS(deg, "deg", sizeof(int32_t) * N);
     WS(rdist, "rdist", sizeof(float) * N * R);
-    WS(cnt, "counters", sizeof(u64) * 3 * CNT_N);
+    WS(cnt, "counters", sizeof(u64) * 3 * CNT_SLOTS * CNT_N);
     WS(errf, "errf", sizeof(int));
-    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * 3 * CNT_N, st));
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * 3 * CNT_SLOTS * CNT_N, st));
     HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
     if (p->metric == RNSM_COSINE) {
         WS(norms, "norms", sizeof(float) * N);
@@ -310,6 +332,13 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     for (int i = 0; i < m; ++i)
         HIPCHK(launch_init_rows(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, bases[i], R, rows,
                                 deg, rdist, st));
+    // padded adjacency of every input graph (rows of R ids, -1 filled): the
+    // searches read a vertex's neighbours with one load, no offsets lookup
+    int32_t* padj;
+    WS(padj, "padj", sizeof(int32_t) * N * R);
+    for (int i = 0; i < m; ++i)
+        HIPCHK(launch_pad_adjacency(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, R,
+                                    padj + bases[i] * R, st));
 
     // ----------------------------------------------------------------- plan
     const auto tp = std::chrono::steady_clock::now();
@@ -368,6 +397,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.row_bytes = vi.row_bytes;
         a.offs = graphs[s].offsets;
         a.nbrs = graphs[s].nbrs;
+        a.padj = padj + bases[s] * R;
+        a.rp = R;
         a.n = ns;
         a.qvec = a.base;
         a.qidx = nullptr;
@@ -378,6 +409,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.q_norm = a.base_norm;
         a.ef = kp;
         a.G = vi.G;
+        a.lgG = ilog2i(vi.G);
         a.cpl = vi.cpl;
         const SearchShape sh = search_shape(kp, R);
         a.hbits = sh.hbits;
@@ -386,7 +418,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.out_ids = nk;
         a.out_stride = k;
         a.out_k = k;
-        a.counters = cnt + 0 * CNT_N;
+        a.counters = cnt + 0 * CNT_SLOTS * CNT_N;
         a.err = errf;
         HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
         HIPCHK(E.record(st, &e0b));
@@ -394,20 +426,23 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         HIPCHK(E.record(st, &e1));
         g_stats.queries[0] += ns;
         g_stats.launches[0] += 1;
-        std::vector<int64_t> h_off(ns + 1);
-        HIPCHK(hipMemcpyAsync(h_off.data(), rk_off, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        std::vector<int32_t> h_ids(h_off[ns] > 0 ? h_off[ns] : 1);
-        if (h_off[ns] > 0)
-            HIPCHK(hipMemcpy(h_ids.data(), rk_ids, sizeof(int32_t) * h_off[ns], hipMemcpyDeviceToHost));
         g_stats.ms_search[0] += E.between(e0, e0b);
         g_stats.ms_invert += E.between(e0b, e1);
         const auto tg = std::chrono::steady_clock::now();
+        // R_k to the host through pinned buffers, in one synchronisation
+        int64_t* h_off;
+        int32_t* h_ids;
+        HS(h_off, "h_rk_off", sizeof(int64_t) * (ns + 1));
+        HS(h_ids, "h_rk_ids", sizeof(int32_t) * ns * k);
+        HIPCHK(hipMemcpyAsync(h_off, rk_off, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(h_ids, rk_ids, sizeof(int32_t) * ns * k, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         if (p->flags & RNSM_FLAG_ALL_PIVOTS) {
             piv[s].pivots.resize(ns);
             for (int64_t v = 0; v < ns; ++v) piv[s].pivots[v] = (int32_t)v;
         } else {
-            select_pivots(ns, h_off.data(), h_ids.data(), piv[s]);
+            select_pivots(ns, h_off, h_ids, piv[s]);
         }
         ms_plan += ms_since(tg);
     }
@@ -424,10 +459,20 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         WS(d_fol, "followers", sizeof(int32_t) * std::max<int64_t>(nf, 1));
         WS(d_folp, "follower_pivot", sizeof(int32_t) * std::max<int64_t>(nf, 1));
         WS(res, "res", sizeof(int32_t) * ns * RES);
-        if (np) HIPCHK(hipMemcpyAsync(d_piv, P.pivots.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
-        if (nf) {
-            HIPCHK(hipMemcpyAsync(d_fol, P.followers.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(d_folp, P.follower_pivot.data(), sizeof(int32_t) * nf, hipMemcpyHostToDevice, st));
+        float* res_d;
+        WS(res_d, "res_d", sizeof(float) * ns * RES);
+        {
+            // pivot and follower lists to the device through one pinned buffer
+            int32_t* hl;
+            HS(hl, "h_lists", sizeof(int32_t) * (np + 2 * nf + 1));
+            memcpy(hl, P.pivots.data(), sizeof(int32_t) * np);
+            memcpy(hl + np, P.followers.data(), sizeof(int32_t) * nf);
+            memcpy(hl + np + nf, P.follower_pivot.data(), sizeof(int32_t) * nf);
+            if (np) HIPCHK(hipMemcpyAsync(d_piv, hl, sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
+            if (nf) {
+                HIPCHK(hipMemcpyAsync(d_fol, hl + np, sizeof(int32_t) * nf, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(d_folp, hl + np + nf, sizeof(int32_t) * nf, hipMemcpyHostToDevice, st));
+            }
         }
         HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));
         int e0, e0b, e1, e2;
@@ -438,15 +483,19 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.row_bytes = vi.row_bytes;
         a.offs = graphs[t].offsets;
         a.nbrs = graphs[t].nbrs;
+        a.padj = padj + bases[t] * R;
+        a.rp = R;
         a.n = nt;
         a.qvec = vi.search + bases[s] * vi.row_bytes;
         a.metric = p->metric;
         a.base_norm = norms ? norms + bases[t] : nullptr;
         a.q_norm = norms ? norms + bases[s] : nullptr;
         a.G = vi.G;
+        a.lgG = ilog2i(vi.G);
         a.cpl = vi.cpl;
         a.out_mode = 0;
         a.out_ids = res;
+        a.out_d = res_d;
         a.out_stride = RES;
         a.err = errf;
         // wave A: pivots, naive search from the target's entry point
@@ -457,7 +506,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.ef = efN;
         a.out_k = efN;
         a.out_row = d_piv;
-        a.counters = cnt + 1 * CNT_N;
+        a.counters = cnt + 1 * CNT_SLOTS * CNT_N;
         const SearchShape shA = search_shape(efN, R);
         a.hbits = shA.hbits;
         a.hash_mode = shA.mode;
@@ -474,7 +523,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.ef = efS;
         a.out_k = efS;
         a.out_row = d_fol;
-        a.counters = cnt + 2 * CNT_N;
+        a.counters = cnt + 2 * CNT_SLOTS * CNT_N;
         const SearchShape shB = search_shape(efS, R);
         a.hbits = shB.hbits;
         a.hash_mode = shB.mode;
@@ -492,6 +541,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         q.n_total = N;
         q.nch = vi.nch32;
         q.G = vi.G32;
+        q.lgG = ilog2i(vi.G32);
         q.cpl = vi.cpl32;
         q.metric = p->metric;
         q.norms = norms;
@@ -499,8 +549,12 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         q.item_base = bases[s];
         q.rows_in = rows;
         q.deg_in = deg;
+        q.rows_d = rdist;
         q.extra_mode = 1;
         q.extra_ids = res;
+        // a float32 search copy gives exactly the distances the prune would
+        // compute (same rows, same lane layout and order); a 16-bit copy does not
+        q.extra_d = vi.tt == 0 ? res_d : nullptr;
         q.extra_stride = RES;
         q.extra_cnt = RES;
         q.extra_index_base = bases[s];
@@ -521,18 +575,22 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         WS(rcur, "rev_cur", sizeof(int32_t) * nt);
         WS(roff, "rev_off", sizeof(int64_t) * (nt + 1));
         WS(rev, "rev_ids", sizeof(int32_t) * std::max<int64_t>(ns * R, 1));
+        float* rev_d;
+        WS(rev_d, "rev_d", sizeof(float) * std::max<int64_t>(ns * R, 1));
         WS(stmp, "scan_tmp2", sizeof(int64_t) * scan_tmp_elems(nt));
         WS(scratch, "prune_scratch", sizeof(u64) * 2 * (nt * R + ns * R));
         HIPCHK(hipMemsetAsync(rc, 0, sizeof(int32_t) * nt, st));
         HIPCHK(hipMemsetAsync(rcur, 0, sizeof(int32_t) * nt, st));
         HIPCHK(launch_rev_count(rows, deg, bases[s], ns, R, bases[t], nt, rc, st));
         HIPCHK(launch_scan(rc, nt, roff, stmp, st));
-        HIPCHK(launch_rev_scatter(rows, deg, bases[s], ns, R, bases[t], nt, roff, rcur, rev, st));
+        HIPCHK(launch_rev_scatter(rows, deg, rdist, bases[s], ns, R, bases[t], nt, roff, rcur, rev,
+                                  rev_d, st));
         PruneArgs r = q;
         r.n_items = nt;
         r.item_base = bases[t];
         r.extra_mode = 2;
         r.extra_ids = rev;
+        r.extra_d = rev_d;
         r.extra_off = roff;
         r.extra_index_base = bases[t];
         r.extra_id_add = 0;
@@ -564,12 +622,16 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
                           norms, out->nbrs, out->dists, st));
     HIPCHK(E.record(st, &c1));
     int64_t nedges = 0;
-    u64 hc[3 * CNT_N];
+    std::vector<u64> hslots(3 * CNT_SLOTS * CNT_N);
+    u64 hc[3 * CNT_N] = {};
     int herr = 0;
     HIPCHK(hipMemcpyAsync(&nedges, out->offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hslots.data(), cnt, sizeof(u64) * hslots.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    for (int ph = 0; ph < 3; ++ph)
+        for (int sl = 0; sl < CNT_SLOTS; ++sl)
+            for (int c = 0; c < CNT_N; ++c) hc[ph * CNT_N + c] += hslots[(ph * CNT_SLOTS + sl) * CNT_N + c];
     if (herr & 1) return fail(RNSM_EINTERNAL, "rnsm_merge: a search exceeded its iteration bound");
     if (herr & 2) return fail(RNSM_EINTERNAL, "rnsm_merge: prune candidate list over capacity");
 
@@ -645,9 +707,9 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     u64* cnt;
     int* errf;
     float *bn = nullptr, *qn = nullptr;
-    WS(cnt, "search_counters", sizeof(u64) * CNT_N);
+    WS(cnt, "search_counters", sizeof(u64) * CNT_SLOTS * CNT_N);
     WS(errf, "search_err", sizeof(int));
-    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * CNT_N, st));
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * CNT_SLOTS * CNT_N, st));
     HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
     if (metric == RNSM_COSINE) {
         if (base->search_dtype != RNSM_F32)
@@ -676,6 +738,7 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     a.q_norm = qn;
     a.ef = ef;
     a.G = vi.G;
+    a.lgG = ilog2i(vi.G);
     a.cpl = vi.cpl;
     const SearchShape sh = search_shape(ef, 32);
     a.hbits = sh.hbits;
@@ -708,7 +771,7 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
     if (metric < RNSM_L2SQ || metric > RNSM_COSINE) return fail(RNSM_EINVAL, "rnsm_build_graph: metric");
     if (dim < 1 || (dim % 4) != 0) return fail(RNSM_EUNSUPPORTED, "rnsm_build_graph: dim must be a multiple of 4");
     const int nch = dim / 4, G = lanes_per_row(nch);
-    if (G < 0) return fail(RNSM_EUNSUPPORTED, "rnsm_build_graph: dim too large");
+    if (G < 0) return fail(RNSM_EUNSUPPORTED, "rnsm_build_graph: dim does not split into whole chunks per lane");
     std::lock_guard<std::mutex> lk(g_lock);
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
@@ -732,7 +795,8 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
     q.n_total = n;
     q.nch = nch;
     q.G = G;
-    q.cpl = (nch + G - 1) / G;
+    q.lgG = ilog2i(G);
+    q.cpl = nch / G;
     q.metric = metric;
     q.norms = norms;
     q.n_items = n;
@@ -764,12 +828,16 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
         HIPCHK(hipMemsetAsync(rcur, 0, sizeof(int32_t) * n, st));
         HIPCHK(launch_rev_count(rows1, deg1, 0, n, R, 0, n, rc, st));
         HIPCHK(launch_scan(rc, n, roff, stmp, st));
-        HIPCHK(launch_rev_scatter(rows1, deg1, 0, n, R, 0, n, roff, rcur, rev, st));
+        float* rev_d;
+        WS(rev_d, "b_rev_d", sizeof(float) * n * R);
+        HIPCHK(launch_rev_scatter(rows1, deg1, d1, 0, n, R, 0, n, roff, rcur, rev, rev_d, st));
         PruneArgs r = q;
         r.rows_in = rows1;
         r.deg_in = deg1;
+        r.rows_d = d1;
         r.extra_mode = 2;
         r.extra_ids = rev;
+        r.extra_d = rev_d;
         r.extra_off = roff;
         r.extra_index_base = 0;
         r.skip_empty_extra = 1;

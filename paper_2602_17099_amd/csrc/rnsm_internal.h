@@ -10,6 +10,8 @@ typedef unsigned long long u64;
 
 // counters the search kernel accumulates (one atomic per wavefront)
 enum { CNT_NDC = 0, CNT_EXP = 1, CNT_ADJ = 2, CNT_HFULL = 3, CNT_N = 4 };
+// copies of the counters, summed on the host: CNT_SLOTS * CNT_N entries per launch
+enum { CNT_SLOTS = 64 };
 
 struct SearchArgs {
     const char* base;         // target rows, search storage type, row r at base + r*row_bytes
@@ -17,6 +19,8 @@ struct SearchArgs {
     int row_bytes;
     const int64_t* offs;      // target CSR
     const int32_t* nbrs;
+    const int32_t* padj;      // optional padded adjacency [n x rp], -1 filled (replaces offs/nbrs)
+    int rp;
     int64_t n;                // target size
     const char* qvec;         // query rows (same storage type), row u at qvec + u*row_bytes
     const int32_t* qidx;      // query i uses row qidx[i] (NULL: row i)
@@ -31,8 +35,9 @@ struct SearchArgs {
     const float* base_norm;   // cosine: norms of target rows
     const float* q_norm;      // cosine: norms of query rows (indexed like the query row)
     int ef;
-    int G;                    // lanes per row
-    int cpl;                  // chunks per lane
+    int G;                    // lanes per row (power of two)
+    int lgG;                  // log2(G)
+    int cpl;                  // 16-byte chunks per lane (nch = G * cpl)
     int hbits;                // log2 of the LDS visited-table size per wavefront
     int hash_mode;            // 0: direct-mapped (forgetful), 1: linear probing
     int out_mode;             // 0: first out_k of the beam, 1: first out_k excluding the query's own id
@@ -41,7 +46,7 @@ struct SearchArgs {
     int64_t out_stride;
     int out_k;
     const int32_t* out_row;   // output row of query i (NULL: i)
-    u64* counters;            // CNT_N entries
+    u64* counters;            // CNT_SLOTS x CNT_N entries
     int* err;
 };
 
@@ -49,8 +54,9 @@ struct PruneArgs {
     const float* X;           // float32 rows of every vertex (global ids)
     int64_t n_total;          // number of rows of X (ids >= n_total are rejected)
     int nch;
-    int G;
-    int cpl;
+    int G;                    // lanes per row (power of two)
+    int lgG;
+    int cpl;                  // 16-byte chunks per lane (nch = G * cpl)
     int metric;
     const float* norms;
     int64_t n_items;
@@ -58,8 +64,10 @@ struct PruneArgs {
     int64_t item_base;
     const int32_t* rows_in;   // [* x R] current rows, indexed by vertex (NULL: empty rows)
     const int32_t* deg_in;
+    const float* rows_d;      // their float32 distances (NaN: not known), or NULL
     int extra_mode;           // 0: none, 1: fixed stride, 2: CSR
     const int32_t* extra_ids;
+    const float* extra_d;     // float32 distances d(p, extra) in the extra layout, or NULL
     int64_t extra_stride;
     int extra_cnt;
     const int64_t* extra_off;
@@ -79,6 +87,8 @@ struct PruneArgs {
 // launchers (all asynchronous on `st`)
 hipError_t launch_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t nnz,
                            int R, int* flags, hipStream_t st);
+hipError_t launch_pad_adjacency(const int64_t* offs, const int32_t* nbrs, int64_t n, int rp,
+                                int32_t* out, hipStream_t st);
 hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
                             int R, int32_t* rows, int32_t* deg, float* rdist, hipStream_t st);
 hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st);
@@ -92,9 +102,10 @@ hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int6
                          int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st);
 hipError_t launch_rev_count(const int32_t* rows, const int32_t* deg, int64_t s_base, int64_t n_s,
                             int R, int64_t t_base, int64_t n_t, int32_t* cnt, hipStream_t st);
-hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, int64_t s_base,
-                              int64_t n_s, int R, int64_t t_base, int64_t n_t,
-                              const int64_t* off, int32_t* cur, int32_t* rev, hipStream_t st);
+hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, const float* rdist,
+                              int64_t s_base, int64_t n_s, int R, int64_t t_base, int64_t n_t,
+                              const int64_t* off, int32_t* cur, int32_t* rev, float* rev_d,
+                              hipStream_t st);
 hipError_t launch_max_i32(const int32_t* v, int64_t n, int32_t* out, hipStream_t st);
 hipError_t launch_compact(const int32_t* rows, const int32_t* deg, const float* rdist,
                           const int64_t* off, int64_t N, int R, const float* X, int dim,
@@ -108,12 +119,18 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
                         hipStream_t st);
 int64_t entry_blocks(int64_t n);
 
-// choice of lanes per row for rows of nch 16-byte chunks (chunks per lane <= 4)
+// lanes per row for rows of nch 16-byte chunks: the smallest power of two G
+// with 4*G >= nch that divides nch, so that every lane holds nch/G <= 4 whole
+// chunks; -1 when there is none
 inline int lanes_per_row(int nch) {
-    int need = (nch + 3) / 4;
-    int g = 1;
-    while (g < need) g <<= 1;
-    return g > 64 ? -1 : g;
+    for (int g = 1; g <= 64; g <<= 1)
+        if (4 * g >= nch && nch % g == 0) return g;
+    return -1;
+}
+inline int ilog2i(int g) {
+    int b = 0;
+    while ((1 << b) < g) ++b;
+    return b;
 }
 
 }  // namespace rnsm

@@ -27,7 +27,6 @@
 namespace rnsm {
 
 #define WAVE 64
-#define MAXCPL 4
 #define EMPTY_KEY (~0ull)
 
 // ------------------------------------------------------------------ helpers
@@ -60,10 +59,6 @@ __device__ __forceinline__ u64 wave_min_u64(u64 x) {
         x = o < x ? o : x;
     }
     return x;
-}
-__device__ __forceinline__ float group_sum(float acc, int G) {
-    for (int off = G >> 1; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-    return acc;
 }
 
 // blocks are dispatched round-robin over the 8 XCDs; give each XCD a
@@ -137,16 +132,15 @@ __device__ __forceinline__ unsigned wave_shr1(unsigned v) {
     return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_WAVE_SHR1, 0xF, 0xF, false);
 }
 
-// sum over each aligned group of G lanes; the total is valid in the group's
-// last lane (sub == G-1)
-template <int G>
-__device__ __forceinline__ float group_sum_last(float v) {
-    if constexpr (G >= 2) v += dpp_add_src<DPP_ROW_SHR(1)>(v);
-    if constexpr (G >= 4) v += dpp_add_src<DPP_ROW_SHR(2)>(v);
-    if constexpr (G >= 8) v += dpp_add_src<DPP_ROW_SHR(4)>(v);
-    if constexpr (G >= 16) v += dpp_add_src<DPP_ROW_SHR(8)>(v);
-    if constexpr (G >= 32) v += dpp_add_src<DPP_ROW_BCAST15>(v);
-    if constexpr (G >= 64) v += dpp_add_src<DPP_ROW_BCAST31>(v);
+// sum over each aligned group of G lanes (G a uniform power of two); the
+// total is valid in the group's last lane (sub == G-1)
+__device__ __forceinline__ float group_sum_last(float v, int G) {
+    if (G >= 2) v += dpp_add_src<DPP_ROW_SHR(1)>(v);
+    if (G >= 4) v += dpp_add_src<DPP_ROW_SHR(2)>(v);
+    if (G >= 8) v += dpp_add_src<DPP_ROW_SHR(4)>(v);
+    if (G >= 16) v += dpp_add_src<DPP_ROW_SHR(8)>(v);
+    if (G >= 32) v += dpp_add_src<DPP_ROW_BCAST15>(v);
+    if (G >= 64) v += dpp_add_src<DPP_ROW_BCAST31>(v);
     return v;
 }
 
@@ -243,28 +237,23 @@ __device__ __forceinline__ int hash_visit(int* tab, int hbits, int v) {
     }
 }
 
-template <int TT>
+template <int TT, int CPL>
 struct Query {
-    float q[MAXCPL][Elt<TT>::EPC];
+    float q[CPL][Elt<TT>::EPC];
 };
 
 __host__ __device__ constexpr int search_lds_words(int hbits) { return (1 << hbits) + 64; }
 
-template <int G>
-struct Grp {
-    static constexpr int RPP = WAVE / G;                               // rows per pass
-    static constexpr int UNR = RPP >= 32 ? 1 : (RPP >= 8 ? 2 : 4);     // passes per batch
-};
-
 // evaluate the per-lane candidates v (-1: none): visited filter, distances,
-// beam insertion
-template <int TT, int EFS, int G, bool EXACT>
+// beam insertion. Rows are read by groups of G lanes, CPL 16-byte chunks per
+// lane at a stride of G chunks, UNR rows per group per batch.
+template <int TT, int EFS, int CPL, bool EXACT>
 __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS>& B,
-                                                   const Query<TT>& Q, float qn, int* tab,
+                                                   const Query<TT, CPL>& Q, float qn, int* tab,
                                                    int* cl, int v, int lane, u64& ndc,
                                                    u64& nevict) {
     constexpr int EPC = Elt<TT>::EPC;
-    constexpr int RPP = Grp<G>::RPP, UNR = Grp<G>::UNR;
+    constexpr int UNR = 2;
     int st = 0;
     if (v >= a.n) v = -1;  // ids from callers are range-checked
     if (v >= 0) st = hash_visit<EXACT>(tab, a.hbits, v);
@@ -277,22 +266,20 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     ndc += nc;
-    const int group = lane / G, sub = lane - group * G;
+    const int G = a.G, RPP = WAVE >> a.lgG;
+    const int group = lane >> a.lgG, sub = lane & (G - 1);
+    const int64_t gstride = (int64_t)G * 16;
     for (int c0 = 0; c0 < nc; c0 += RPP * UNR) {
-        uint4 raw[UNR][MAXCPL];
+        uint4 raw[UNR][CPL];
         int cid[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const int c = c0 + u * RPP + group;
             cid[u] = c < nc ? cl[c] : -1;
-            const char* row = a.base + (int64_t)(cid[u] < 0 ? 0 : cid[u]) * a.row_bytes;
+            if (cid[u] >= 0) {
+                const char* rp = a.base + (int64_t)cid[u] * a.row_bytes + sub * 16;
 #pragma unroll
-            for (int j = 0; j < MAXCPL; ++j) {
-                const int ch = sub + j * G;
-                if (cid[u] >= 0 && j < a.cpl && ch < a.nch)
-                    raw[u][j] = *(const uint4*)(row + (int64_t)ch * 16);
-                else
-                    raw[u][j] = make_uint4(0, 0, 0, 0);
+                for (int j = 0; j < CPL; ++j) raw[u][j] = *(const uint4*)(rp + j * gstride);
             }
         }
         float acc[UNR];
@@ -300,7 +287,7 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
         for (int u = 0; u < UNR; ++u) {
             float s = 0.0f;
 #pragma unroll
-            for (int j = 0; j < MAXCPL; ++j) {
+            for (int j = 0; j < CPL; ++j) {
                 float x[EPC];
                 cvt_chunk<TT>(raw[u][j], x);
                 if (a.metric == 0) {
@@ -314,7 +301,7 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
                     for (int t = 0; t < EPC; ++t) s = fmaf(Q.q[j][t], x[t], s);
                 }
             }
-            acc[u] = group_sum_last<G>(s);
+            acc[u] = group_sum_last(s, G);
         }
         const u64 worst = beam_worst(B, a.ef);
 #pragma unroll
@@ -336,7 +323,7 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int TT, int EFS, int G, bool EXACT>
+template <int TT, int EFS, int CPL, bool EXACT>
 __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     extern __shared__ int smem[];
     const int lane = lane_id();
@@ -351,16 +338,12 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     __builtin_amdgcn_wave_barrier();
 
     const int u = a.qidx ? a.qidx[i] : (int)i;
-    const char* qrow = a.qvec + (int64_t)u * a.row_bytes;
-    const int sub = lane % G;
-    Query<TT> Q;
+    const int sub = lane & (a.G - 1);
+    const char* qrow = a.qvec + (int64_t)u * a.row_bytes + sub * 16;
+    Query<TT, CPL> Q;
 #pragma unroll
-    for (int j = 0; j < MAXCPL; ++j) {
-        const int ch = sub + j * G;
-        uint4 r = make_uint4(0, 0, 0, 0);
-        if (j < a.cpl && ch < a.nch) r = *(const uint4*)(qrow + (int64_t)ch * 16);
-        cvt_chunk<TT>(r, Q.q[j]);
-    }
+    for (int j = 0; j < CPL; ++j)
+        cvt_chunk<TT>(*(const uint4*)(qrow + (int64_t)j * a.G * 16), Q.q[j]);
     const float qn = a.metric == 2 ? a.q_norm[u] : 1.0f;
 
     Beam<EFS> B;
@@ -374,7 +357,7 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     // seeds
     if (a.seed_mode == 0 || a.seed_mode == 1) {
         const int s0 = a.seed_mode == 0 ? a.entry : u;
-        process_candidates<TT, EFS, G, EXACT>(a, B, Q, qn, tab, cl, lane == 0 ? s0 : -1, lane, ndc,
+        process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, lane == 0 ? s0 : -1, lane, ndc,
                                        nevict);
     } else {
         const int64_t srow = a.seed_row ? a.seed_row[i] : i;
@@ -382,7 +365,7 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
         for (int j0 = 0; j0 < a.n_seeds; j0 += WAVE) {
             const int j = j0 + lane;
             const int v = j < a.n_seeds ? sp[j] : -1;
-            process_candidates<TT, EFS, G, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
+            process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
         }
     }
 
@@ -415,12 +398,19 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
             }
         }
         ++nexp;
-        const int64_t b = a.offs[uid], en = a.offs[uid + 1];
-        nadj += (u64)(en - b);
-        for (int64_t j0 = b; j0 < en; j0 += WAVE) {
-            const int64_t j = j0 + lane;
-            const int v = j < en ? a.nbrs[j] : -1;
-            process_candidates<TT, EFS, G, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
+        if (a.padj) {
+            // padded adjacency: one load, no offsets lookup
+            const int v = lane < a.rp ? a.padj[(int64_t)uid * a.rp + lane] : -1;
+            nadj += (u64)__popcll(__ballot(v >= 0));
+            process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
+        } else {
+            const int64_t b = a.offs[uid], en = a.offs[uid + 1];
+            nadj += (u64)(en - b);
+            for (int64_t j0 = b; j0 < en; j0 += WAVE) {
+                const int64_t j = j0 + lane;
+                const int v = j < en ? a.nbrs[j] : -1;
+                process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
+            }
         }
         if (it > maxit) {
             if (lane == 0) atomicOr(a.err, 1);
@@ -459,10 +449,13 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
         }
     }
     if (lane == 0) {
-        atomicAdd(&a.counters[CNT_NDC], ndc);
-        atomicAdd(&a.counters[CNT_EXP], nexp);
-        atomicAdd(&a.counters[CNT_ADJ], nadj);
-        atomicAdd(&a.counters[CNT_HFULL], nevict);
+        // counters are spread over CNT_SLOTS copies to keep the atomics of
+        // hundreds of thousands of wavefronts from meeting on one address
+        u64* c = a.counters + (blockIdx.x & (CNT_SLOTS - 1)) * CNT_N;
+        atomicAdd(&c[CNT_NDC], ndc);
+        atomicAdd(&c[CNT_EXP], nexp);
+        atomicAdd(&c[CNT_ADJ], nadj);
+        atomicAdd(&c[CNT_HFULL], nevict);
     }
 }
 
@@ -470,11 +463,11 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
 
 // float32 distance between the lane-group layouts of two rows (valid in the
 // group's last lane)
-template <int G>
-__device__ __forceinline__ float dist_rows(const float4* a, const float4* b, int metric) {
+template <int CPL>
+__device__ __forceinline__ float dist_rows(const float4* a, const float4* b, int metric, int G) {
     float acc = 0.0f;
 #pragma unroll
-    for (int j = 0; j < MAXCPL; ++j) {
+    for (int j = 0; j < CPL; ++j) {
         const float4 x = a[j], q = b[j];
         if (metric == 0) {
             const float d0 = q.x - x.x, d1 = q.y - x.y, d2 = q.z - x.z, d3 = q.w - x.w;
@@ -489,17 +482,17 @@ __device__ __forceinline__ float dist_rows(const float4* a, const float4* b, int
             acc = fmaf(q.w, x.w, acc);
         }
     }
-    return group_sum_last<G>(acc);
+    return group_sum_last(acc, G);
 }
 
+// this lane's CPL chunks of float32 row id (nothing for id < 0)
+template <int CPL>
 __device__ __forceinline__ void load_row_f32(const float* X, int64_t id, int rowf, int sub, int G,
-                                             int cpl, int nch, float4* out) {
-    const float* r = X + id * rowf;
+                                             float4* out) {
+    if (id >= 0) {
+        const float* r = X + id * rowf + sub * 4;
 #pragma unroll
-    for (int j = 0; j < MAXCPL; ++j) {
-        const int ch = sub + j * G;
-        out[j] = (id >= 0 && j < cpl && ch < nch) ? *(const float4*)(r + ch * 4)
-                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int j = 0; j < CPL; ++j) out[j] = *(const float4*)(r + (int64_t)j * G * 4);
     }
 }
 
@@ -508,10 +501,9 @@ __device__ __forceinline__ void load_row_f32(const float* X, int64_t id, int row
 // unless alpha * d(w, v) < d(p, v) for a kept w (strict, in double); stop at
 // R kept. Kept rows stay in registers (KS slots per lane group) or are
 // re-read (KS == 0).
-template <int G, int KS>
+template <int CPL, int KS>
 __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     extern __shared__ unsigned char psm[];
-    constexpr int RPP = WAVE / G;
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
@@ -524,6 +516,7 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     const int64_t p = a.items ? (int64_t)a.items[i] : a.item_base + i;
     const int64_t e = p - a.extra_index_base;
     const int R = a.R;
+    const int G = a.G, RPP = WAVE >> a.lgG;
 
     const int nrow = a.rows_in ? a.deg_in[p] : 0;
     int next = 0;
@@ -547,45 +540,50 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
         wk = a.scratch + 2 * ((int64_t)R * e + xo);
         ws = wk + nW;
     }
-    // candidate ids
+    // candidate ids; a candidate whose float32 distance to p is already known
+    // (its search result, a reverse edge, a pruned row) gets its key now,
+    // the others hold their id (< 2^32) until their distance is computed
     for (int t = lane; t < nW; t += WAVE) {
         int64_t id;
+        float d = __int_as_float(0x7fc00000);
         if (t < nrow) {
             id = a.rows_in[p * R + t];
+            if (a.rows_d) d = a.rows_d[p * R + t];
         } else {
             const int32_t x = a.extra_ids[xo + (t - nrow)];
             id = x < 0 ? -1 : (int64_t)x + a.extra_id_add;
+            if (a.extra_d) d = a.extra_d[xo + (t - nrow)];
         }
         if (id >= a.n_total) {  // ids from callers are range-checked
             atomicOr(a.err, 4);
             id = -1;
         }
-        wk[t] = (id < 0 || id == p) ? EMPTY_KEY : (u64)id;
+        wk[t] = (id < 0 || id == p) ? EMPTY_KEY : (d == d ? make_key(d, (int)id) : (u64)id);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    const int group = lane / G, sub = lane - group * G;
+    const int group = lane >> a.lgG, sub = lane & (G - 1);
     const int rowf = a.nch * 4;
-    float4 pq[MAXCPL];
-    load_row_f32(a.X, p, rowf, sub, G, a.cpl, a.nch, pq);
+    float4 pq[CPL];
+    load_row_f32<CPL>(a.X, p, rowf, sub, G, pq);
     const float pn = a.metric == 2 ? a.norms[p] : 1.0f;
-    // keys (d(p, w), w)
-    constexpr int UNR = RPP >= 16 ? 1 : 2;
+    // keys (d(p, w), w) of the candidates still without one
+    constexpr int UNR = 2;
     for (int c0 = 0; c0 < nW; c0 += RPP * UNR) {
-        float4 raw[UNR][MAXCPL];
+        float4 raw[UNR][CPL];
         int cid[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const int c = c0 + u * RPP + group;
             const u64 kk = c < nW ? wk[c] : EMPTY_KEY;
-            cid[u] = kk == EMPTY_KEY ? -1 : (int)kk;
-            load_row_f32(a.X, cid[u], rowf, sub, G, a.cpl, a.nch, raw[u]);
+            cid[u] = kk < (1ull << 32) ? (int)kk : -1;
+            load_row_f32<CPL>(a.X, cid[u], rowf, sub, G, raw[u]);
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            const float acc = dist_rows<G>(raw[u], pq, a.metric);
+            const float acc = dist_rows<CPL>(raw[u], pq, a.metric, G);
             const int c = c0 + u * RPP + group;
             if (sub == G - 1 && cid[u] >= 0) {
                 const float nb = a.metric == 2 ? a.norms[cid[u]] : 1.0f;
@@ -611,23 +609,23 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     // walk the candidates in (d, id) order
-    float4 kept[KS > 0 ? KS : 1][MAXCPL];
+    float4 kept[KS > 0 ? KS : 1][CPL];
     const double alpha = (double)a.alpha;
     int nk = 0;
     u64 prev = EMPTY_KEY;
-    float4 vx[MAXCPL], nx[MAXCPL];
+    float4 vx[CPL], nx[CPL];
     u64 cur = nW > 0 ? ws[0] : EMPTY_KEY;
-    load_row_f32(a.X, cur == EMPTY_KEY ? -1 : (int64_t)(unsigned)(cur & 0xffffffffu), rowf, sub,
-                 G, a.cpl, a.nch, nx);
+    load_row_f32<CPL>(a.X, cur == EMPTY_KEY ? -1 : (int64_t)(unsigned)(cur & 0xffffffffu), rowf,
+                      sub, G, nx);
     for (int t = 0; t < nW && nk < R; ++t) {
         if (cur == EMPTY_KEY) break;
 #pragma unroll
-        for (int j = 0; j < MAXCPL; ++j) vx[j] = nx[j];
+        for (int j = 0; j < CPL; ++j) vx[j] = nx[j];
         const u64 kcur = cur;
         // prefetch the next candidate's row
         cur = t + 1 < nW ? ws[t + 1] : EMPTY_KEY;
-        load_row_f32(a.X, cur == EMPTY_KEY ? -1 : (int64_t)(unsigned)(cur & 0xffffffffu), rowf,
-                     sub, G, a.cpl, a.nch, nx);
+        load_row_f32<CPL>(a.X, cur == EMPTY_KEY ? -1 : (int64_t)(unsigned)(cur & 0xffffffffu),
+                          rowf, sub, G, nx);
         if (kcur == prev) continue;  // the same vertex twice in W
         prev = kcur;
         const int v = (int)(unsigned)(kcur & 0xffffffffu);
@@ -639,7 +637,7 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 if (s < nslots) {
-                    const float acc = dist_rows<G>(kept[s], vx, a.metric);
+                    const float acc = dist_rows<CPL>(kept[s], vx, a.metric, G);
                     const int jk = s * RPP + group;
                     if (jk < nk && sub == G - 1) {
                         const float kn = a.metric == 2 ? a.norms[kept_ids[jk]] : 1.0f;
@@ -651,9 +649,9 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
         } else {
             for (int s = 0; s < nslots; ++s) {
                 const int jk = s * RPP + group;
-                float4 kx[MAXCPL];
-                load_row_f32(a.X, jk < nk ? kept_ids[jk] : -1, rowf, sub, G, a.cpl, a.nch, kx);
-                const float acc = dist_rows<G>(kx, vx, a.metric);
+                float4 kx[CPL];
+                load_row_f32<CPL>(a.X, jk < nk ? kept_ids[jk] : v, rowf, sub, G, kx);
+                const float acc = dist_rows<CPL>(kx, vx, a.metric, G);
                 if (jk < nk && sub == G - 1) {
                     const float kn = a.metric == 2 ? a.norms[kept_ids[jk]] : 1.0f;
                     const float dkv = finalize_dist(acc, a.metric, kn, vn);
@@ -668,7 +666,7 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
             for (int ss = 0; ss < KS; ++ss)
                 if (ss == s && group == gsel) {
 #pragma unroll
-                    for (int j = 0; j < MAXCPL; ++j) kept[ss][j] = vx[j];
+                    for (int j = 0; j < CPL; ++j) kept[ss][j] = vx[j];
                 }
         }
         if (lane == 0) {
@@ -722,6 +720,16 @@ __global__ __launch_bounds__(256) void k_validate(const int64_t* offs, const int
     for (int bit = 4; bit <= 16; bit <<= 1)
         if (__ballot((f & bit) != 0) != 0ull) all |= bit;
     if (lane == 0 && all) atomicOr(flags, all);
+}
+
+__global__ void k_pad_adjacency(const int64_t* offs, const int32_t* nbrs, int64_t n, int rp,
+                                int32_t* out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * rp) return;
+    const int64_t v = t / rp;
+    const int j = (int)(t - v * rp);
+    const int64_t b = offs[v], e = offs[v + 1];
+    out[t] = j < e - b ? nbrs[b + j] : -1;
 }
 
 __global__ void k_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
@@ -852,9 +860,9 @@ __global__ void k_rev_count(const int32_t* rows, const int32_t* deg, int64_t s_b
     if (v >= 0 && v < n_t) atomicAdd(&cnt[v], 1);
 }
 
-__global__ void k_rev_scatter(const int32_t* rows, const int32_t* deg, int64_t s_base,
-                              int64_t n_s, int R, int64_t t_base, int64_t n_t, const int64_t* off,
-                              int32_t* cur, int32_t* rev) {
+__global__ void k_rev_scatter(const int32_t* rows, const int32_t* deg, const float* rdist,
+                              int64_t s_base, int64_t n_s, int R, int64_t t_base, int64_t n_t,
+                              const int64_t* off, int32_t* cur, int32_t* rev, float* rev_d) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_s * R) return;
     const int64_t u = t / R;
@@ -865,6 +873,7 @@ __global__ void k_rev_scatter(const int32_t* rows, const int32_t* deg, int64_t s
     if (v < 0 || v >= n_t) return;
     const int pos = atomicAdd(&cur[v], 1);
     rev[off[v] + pos] = (int32_t)g;
+    if (rev_d) rev_d[off[v] + pos] = rdist[g * R + j];  // d(u, v) = d(v, u), same arithmetic
 }
 
 __global__ void k_max_i32(const int32_t* v, int64_t n, int32_t* out) {
@@ -1024,6 +1033,14 @@ hipError_t launch_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, 
     return hipGetLastError();
 }
 
+hipError_t launch_pad_adjacency(const int64_t* offs, const int32_t* nbrs, int64_t n, int rp,
+                                int32_t* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pad_adjacency, dim3(nblk(n * rp, 256)), dim3(256), 0, st, offs, nbrs, n, rp,
+                       out);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
                             int R, int32_t* rows, int32_t* deg, float* rdist, hipStream_t st) {
     if (n <= 0) return hipSuccess;
@@ -1039,24 +1056,21 @@ hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStrea
 }
 
 template <int TT, int EFS, bool EXACT>
-static void launch_search_g(const SearchArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
-    switch (a.G) {
+static void launch_search_c(const SearchArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+    switch (a.cpl) {
         case 1: hipLaunchKernelGGL((k_beam_search<TT, EFS, 1, EXACT>), grid, block, lds, st, a); break;
         case 2: hipLaunchKernelGGL((k_beam_search<TT, EFS, 2, EXACT>), grid, block, lds, st, a); break;
-        case 4: hipLaunchKernelGGL((k_beam_search<TT, EFS, 4, EXACT>), grid, block, lds, st, a); break;
-        case 8: hipLaunchKernelGGL((k_beam_search<TT, EFS, 8, EXACT>), grid, block, lds, st, a); break;
-        case 16: hipLaunchKernelGGL((k_beam_search<TT, EFS, 16, EXACT>), grid, block, lds, st, a); break;
-        case 32: hipLaunchKernelGGL((k_beam_search<TT, EFS, 32, EXACT>), grid, block, lds, st, a); break;
-        default: hipLaunchKernelGGL((k_beam_search<TT, EFS, 64, EXACT>), grid, block, lds, st, a); break;
+        case 3: hipLaunchKernelGGL((k_beam_search<TT, EFS, 3, EXACT>), grid, block, lds, st, a); break;
+        default: hipLaunchKernelGGL((k_beam_search<TT, EFS, 4, EXACT>), grid, block, lds, st, a); break;
     }
 }
 
 template <int TT, int EFS>
 static void launch_search_m(const SearchArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
     if (a.hash_mode)
-        launch_search_g<TT, EFS, true>(a, grid, block, lds, st);
+        launch_search_c<TT, EFS, true>(a, grid, block, lds, st);
     else
-        launch_search_g<TT, EFS, false>(a, grid, block, lds, st);
+        launch_search_c<TT, EFS, false>(a, grid, block, lds, st);
 }
 
 size_t search_lds_bytes(int hbits, int wpb) {
@@ -1081,17 +1095,17 @@ hipError_t launch_search(int tt, const SearchArgs& a, int wpb, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int G>
-static void launch_prune_g(const PruneArgs& a, int need, dim3 grid, dim3 block, size_t lds,
+template <int CPL>
+static void launch_prune_c(const PruneArgs& a, int need, dim3 grid, dim3 block, size_t lds,
                            hipStream_t st) {
     if (need <= 1)
-        hipLaunchKernelGGL((k_prune<G, 1>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_prune<CPL, 1>), grid, block, lds, st, a);
     else if (need <= 2)
-        hipLaunchKernelGGL((k_prune<G, 2>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_prune<CPL, 2>), grid, block, lds, st, a);
     else if (need <= 4)
-        hipLaunchKernelGGL((k_prune<G, 4>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_prune<CPL, 4>), grid, block, lds, st, a);
     else
-        hipLaunchKernelGGL((k_prune<G, 0>), grid, block, lds, st, a);
+        hipLaunchKernelGGL((k_prune<CPL, 0>), grid, block, lds, st, a);
 }
 
 hipError_t launch_prune(const PruneArgs& a, hipStream_t st) {
@@ -1101,14 +1115,11 @@ hipError_t launch_prune(const PruneArgs& a, hipStream_t st) {
     const dim3 grid(nblk(a.n_items, wpb)), block(wpb * WAVE);
     const int rpp = WAVE / a.G;
     const int need = (a.R + rpp - 1) / rpp;
-    switch (a.G) {
-        case 1: launch_prune_g<1>(a, need, grid, block, lds, st); break;
-        case 2: launch_prune_g<2>(a, need, grid, block, lds, st); break;
-        case 4: launch_prune_g<4>(a, need, grid, block, lds, st); break;
-        case 8: launch_prune_g<8>(a, need, grid, block, lds, st); break;
-        case 16: launch_prune_g<16>(a, need, grid, block, lds, st); break;
-        case 32: launch_prune_g<32>(a, need, grid, block, lds, st); break;
-        default: launch_prune_g<64>(a, need, grid, block, lds, st); break;
+    switch (a.cpl) {
+        case 1: launch_prune_c<1>(a, need, grid, block, lds, st); break;
+        case 2: launch_prune_c<2>(a, need, grid, block, lds, st); break;
+        case 3: launch_prune_c<3>(a, need, grid, block, lds, st); break;
+        default: launch_prune_c<4>(a, need, grid, block, lds, st); break;
     }
     return hipGetLastError();
 }
@@ -1138,8 +1149,6 @@ hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int6
     if (n > 0) {
         hipLaunchKernelGGL(k_invert_scatter, dim3(nblk(n * k, 256)), dim3(256), 0, st, nk, n, k,
                            rk_off, cnt, rk_ids);
-        hipLaunchKernelGGL(k_sort_segments, dim3(nblk(n, 256)), dim3(256), 0, st, rk_off, n,
-                           rk_ids);
     }
     return hipGetLastError();
 }
@@ -1152,12 +1161,13 @@ hipError_t launch_rev_count(const int32_t* rows, const int32_t* deg, int64_t s_b
     return hipGetLastError();
 }
 
-hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, int64_t s_base,
-                              int64_t n_s, int R, int64_t t_base, int64_t n_t,
-                              const int64_t* off, int32_t* cur, int32_t* rev, hipStream_t st) {
+hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, const float* rdist,
+                              int64_t s_base, int64_t n_s, int R, int64_t t_base, int64_t n_t,
+                              const int64_t* off, int32_t* cur, int32_t* rev, float* rev_d,
+                              hipStream_t st) {
     if (n_s <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rev_scatter, dim3(nblk(n_s * R, 256)), dim3(256), 0, st, rows, deg,
-                       s_base, n_s, R, t_base, n_t, off, cur, rev);
+    hipLaunchKernelGGL(k_rev_scatter, dim3(nblk(n_s * R, 256)), dim3(256), 0, st, rows, deg, rdist,
+                       s_base, n_s, R, t_base, n_t, off, cur, rev, rev_d);
     return hipGetLastError();
 }
 

@@ -145,6 +145,13 @@ int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int 
 
 // ------------------------------------------------------ lazy greedy pivots
 
+// The lazy greedy of Algorithm 2: repeatedly take the vertex with the largest
+// stored gain (ties: smallest id); drop it if covered; if its gain
+// |R_k(x) minus Covered| fell below the stored one, store it under the new
+// gain; otherwise make it a pivot whose followers are its uncovered R_k.
+// A vertex is only ever moved to a lower gain while a higher one is
+// processed, so every gain level is a bitmap over vertex ids scanned once in
+// ascending order.
 void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, Pivots& out) {
     out.pivots.clear();
     out.followers.clear();
@@ -152,46 +159,45 @@ void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, Pivo
     std::vector<unsigned char> covered((size_t)n, 0);
     int64_t gmax = 0;
     for (int64_t x = 0; x < n; ++x) gmax = std::max<int64_t>(gmax, rk_off[x + 1] - rk_off[x]);
-    // bucket g holds the vertices whose stored gain is g: the initial members
-    // in ascending id order plus members moved down later (sorted before the
-    // bucket is processed; a bucket only receives members while a higher one
-    // is processed)
-    std::vector<std::vector<int32_t>> init(gmax + 1), moved(gmax + 1);
-    for (int64_t x = 0; x < n; ++x) init[rk_off[x + 1] - rk_off[x]].push_back((int32_t)x);
+    const int64_t words = (n + 63) / 64;
+    std::vector<std::vector<uint64_t>> level(gmax + 1);
+    auto mark = [&](int64_t g, int64_t x) {
+        std::vector<uint64_t>& b = level[g];
+        if (b.empty()) b.assign((size_t)words, 0ull);
+        b[x >> 6] |= 1ull << (x & 63);
+    };
+    for (int64_t x = 0; x < n; ++x) mark(rk_off[x + 1] - rk_off[x], x);
     out.pivots.reserve(n / 4);
     out.followers.reserve(n);
     out.follower_pivot.reserve(n);
     for (int64_t g = gmax; g >= 0; --g) {
-        std::vector<int32_t>& A = init[g];
-        std::vector<int32_t>& B = moved[g];
-        std::sort(B.begin(), B.end());
-        size_t ia = 0, ib = 0;
-        while (ia < A.size() || ib < B.size()) {
-            int32_t x;
-            if (ib >= B.size() || (ia < A.size() && A[ia] < B[ib]))
-                x = A[ia++];
-            else
-                x = B[ib++];
-            if (covered[x]) continue;
-            int64_t cur = 0;
-            for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) cur += !covered[rk_ids[j]];
-            if (cur < g) {
-                moved[cur].push_back(x);
-                continue;
-            }
-            out.pivots.push_back(x);
-            covered[x] = 1;
-            for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) {
-                const int32_t y = rk_ids[j];
-                if (!covered[y]) {
-                    covered[y] = 1;
-                    out.followers.push_back(y);
-                    out.follower_pivot.push_back(x);
+        std::vector<uint64_t>& b = level[g];
+        if (b.empty()) continue;
+        for (int64_t w = 0; w < words; ++w) {
+            uint64_t bits = b[w];
+            while (bits) {
+                const int32_t x = (int32_t)(w * 64 + __builtin_ctzll(bits));
+                bits &= bits - 1;
+                if (covered[x]) continue;
+                int64_t cur = 0;
+                for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) cur += !covered[rk_ids[j]];
+                if (cur < g) {
+                    mark(cur, x);
+                    continue;
+                }
+                out.pivots.push_back(x);
+                covered[x] = 1;
+                for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) {
+                    const int32_t y = rk_ids[j];
+                    if (!covered[y]) {
+                        covered[y] = 1;
+                        out.followers.push_back(y);
+                        out.follower_pivot.push_back(x);
+                    }
                 }
             }
         }
-        std::vector<int32_t>().swap(A);
-        std::vector<int32_t>().swap(B);
+        std::vector<uint64_t>().swap(b);
     }
 }
 

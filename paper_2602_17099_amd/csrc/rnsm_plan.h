@@ -22,7 +22,8 @@ struct Pivots {
     std::vector<int32_t> follower_pivot;  // pivot of each follower
 };
 
-// lazy greedy over reverse k-NN lists R_k (CSR, lists sorted by id)
+// lazy greedy over reverse k-NN lists R_k (CSR; the order inside a list only
+// changes the order of the follower list, not the pivots or their followers)
 void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, Pivots& out);
 
 }  // namespace rnsm

@@ -92,6 +92,21 @@ def test_search_seeds_bit_exact(dev, orc, pkg, search_case, ef, ns):
         assert ds[i, :len(rid)].astype(np.float64).tolist() == rd.tolist(), i
 
 
+def test_search_out_of_range_seeds_ignored(dev, orc, pkg, search_case):
+    # seed ids outside the graph are skipped like -1
+    X, Q, off, nb, entry = search_case
+    g = np.random.default_rng(5)
+    seeds = g.integers(0, len(X), size=(len(Q), 20)).astype(np.int32)
+    seeds[:, ::3] = len(X) + 7
+    ids, _ = pkg.search(_t(off, dev), _t(nb, dev), entry, _t(X, dev), _t(Q, dev), 24, 24,
+                        seeds=_t(seeds, dev))
+    ids = ids.cpu().numpy()
+    for i in range(0, len(Q), 10):
+        s = np.where(seeds[i] >= len(X), -1, seeds[i])
+        rid, _, _ = orc.beam_search(off, nb, X, Q[i], s, 24)
+        assert ids[i, :len(rid)].tolist() == rid.tolist(), i
+
+
 @pytest.mark.parametrize("dtype", ["bfloat16", "float16"])
 def test_search_16bit_copy_on_integers(dev, orc, pkg, search_case, dtype):
     import torch
