@@ -142,12 +142,12 @@ def search_roofline(agg, st, ndc_exact, steps):
 
 
 def cpu_baseline(wl):
-    """The oracle's full merge on a replica of the workload with 1/20 of the
+    """The oracle's full merge on a replica of the workload with 1/8 of the
     vectors per sub-index (same distribution, dim and parameters; sub-indexes
     built by the oracle), single-threaded."""
     from oracle import oracle as O
     from paper_2602_17099_amd import inputs
-    n = max(1000, wl["n"] // 20)
+    n = max(1000, wl["n"] // 8)
     if wl["gen"] == "mixture_u8":
         X = inputs.mixture_u8(2 * n, wl["dim"], seed=inputs.SEED_BASE + 2)
     else:

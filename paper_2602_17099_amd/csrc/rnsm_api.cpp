@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -50,6 +51,20 @@ struct Workspace {
         size_t bytes = 0;
     };
     std::map<std::string, Buf> bufs, hbufs;
+    // second stream (default priority) for the naive searches of the pivot
+    // chunks, which then overlap the sliding searches of earlier chunks
+    hipStream_t side = nullptr;
+    hipError_t side_stream(hipStream_t* out) {
+        if (!side) {
+            hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                side = nullptr;
+                return e;
+            }
+        }
+        *out = side;
+        return hipSuccess;
+    }
     // pinned host staging buffers (hipHostMalloc), kept like the device ones
     hipError_t hget(const char* name, size_t bytes, void** out) {
         Buf& b = hbufs[name];
@@ -373,110 +388,98 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         return fail(RNSM_EINTERNAL, "rnsm_merge: planner failed");
     double ms_plan = ms_since(tp);
 
-    // ------------------------------------- expansion, inversion and pivots
-    std::vector<Pivots> piv(m);
-    std::vector<char> have(m, 0);
-    double ms_prune = 0.0;
-    for (auto& op : ops) {
-        const int s = op.first;
-        if (have[s]) continue;
-        have[s] = 1;
-        const int64_t ns = sizes[s];
-        int32_t *nk, *rcnt, *rk_ids;
-        int64_t *rk_off, *stmp;
-        WS(nk, "nk", sizeof(int32_t) * ns * k);
-        WS(rcnt, "rk_cnt", sizeof(int32_t) * ns);
-        WS(rk_off, "rk_off", sizeof(int64_t) * (ns + 1));
-        WS(rk_ids, "rk_ids", sizeof(int32_t) * ns * k);
-        WS(stmp, "scan_tmp", sizeof(int64_t) * scan_tmp_elems(ns));
-        int e0, e0b, e1;
-        HIPCHK(E.record(st, &e0));
-        SearchArgs a = {};
-        a.base = vi.search + bases[s] * vi.row_bytes;
-        a.nch = vi.nch;
-        a.row_bytes = vi.row_bytes;
-        a.offs = graphs[s].offsets;
-        a.nbrs = graphs[s].nbrs;
-        a.padj = padj + bases[s] * R;
-        a.rp = R;
-        a.n = ns;
-        a.qvec = a.base;
-        a.qidx = nullptr;
-        a.nq = ns;
-        a.seed_mode = 1;
-        a.metric = p->metric;
-        a.base_norm = norms ? norms + bases[s] : nullptr;
-        a.q_norm = a.base_norm;
-        a.ef = kp;
-        a.G = vi.G;
-        a.lgG = ilog2i(vi.G);
-        a.cpl = vi.cpl;
-        const SearchShape sh = search_shape(kp, R);
-        a.hbits = sh.hbits;
-        a.hash_mode = sh.mode;
-        a.out_mode = 1;
-        a.out_ids = nk;
-        a.out_stride = k;
-        a.out_k = k;
-        a.counters = cnt + 0 * CNT_SLOTS * CNT_N;
-        a.err = errf;
-        HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
-        HIPCHK(E.record(st, &e0b));
-        HIPCHK(launch_invert(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
-        HIPCHK(E.record(st, &e1));
-        g_stats.queries[0] += ns;
-        g_stats.launches[0] += 1;
-        HIPCHK(hipStreamSynchronize(st));
-        g_stats.ms_search[0] += E.between(e0, e0b);
-        g_stats.ms_invert += E.between(e0b, e1);
-        const auto tg = std::chrono::steady_clock::now();
-        // R_k to the host through pinned buffers, in one synchronisation
-        int64_t* h_off;
-        int32_t* h_ids;
-        HS(h_off, "h_rk_off", sizeof(int64_t) * (ns + 1));
-        HS(h_ids, "h_rk_ids", sizeof(int32_t) * ns * k);
-        HIPCHK(hipMemcpyAsync(h_off, rk_off, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_ids, rk_ids, sizeof(int32_t) * ns * k, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (p->flags & RNSM_FLAG_ALL_PIVOTS) {
-            piv[s].pivots.resize(ns);
-            for (int64_t v = 0; v < ns; ++v) piv[s].pivots[v] = (int32_t)v;
-        } else {
-            select_pivots(ns, h_off, h_ids, piv[s]);
-        }
-        ms_plan += ms_since(tg);
-    }
-
     // ------------------------------------------------------- the operations
+    // Per operation (source s into target t): neighbour expansion of s in
+    // its own graph and the reverse k-NN lists (device); R_k to the host and
+    // the lazy greedy there. The greedy hands over pivot groups in chunks;
+    // each chunk's naive search (pivots) and local sliding (their followers)
+    // are queued at once, so the device searches while the host is still
+    // selecting. Then source prune, reverse edges and target prune.
     const int RES = std::max(efN, efS);
-    for (auto& op : ops) {
-        const int s = op.first, t = op.second;
+    double ms_prune = 0.0;
+    std::vector<int> last_use(m, -1);
+    for (size_t oi = 0; oi < ops.size(); ++oi) last_use[ops[oi].first] = (int)oi;
+    std::vector<std::vector<int32_t>> cached(m);  // lists of a source used again later
+    std::vector<int64_t> cached_np(m, 0), cached_nf(m, 0);
+    std::vector<std::array<int, 3>> ev_exp;
+    std::vector<std::array<int, 4>> ev_chunk;
+    std::vector<std::array<int, 2>> ev_prune;
+    int64_t* h_nrev;
+    HS(h_nrev, "h_nrev", sizeof(int64_t) * ops.size());
+    for (size_t oi = 0; oi < ops.size(); ++oi) {
+        const int s = ops[oi].first, t = ops[oi].second;
         const int64_t ns = sizes[s], nt = sizes[t];
-        const Pivots& P = piv[s];
-        const int64_t np = (int64_t)P.pivots.size(), nf = (int64_t)P.followers.size();
-        int32_t *d_piv, *d_fol, *d_folp, *res;
-        WS(d_piv, "pivots", sizeof(int32_t) * std::max<int64_t>(np, 1));
-        WS(d_fol, "followers", sizeof(int32_t) * std::max<int64_t>(nf, 1));
-        WS(d_folp, "follower_pivot", sizeof(int32_t) * std::max<int64_t>(nf, 1));
-        WS(res, "res", sizeof(int32_t) * ns * RES);
+        int32_t *d_piv, *d_fol, *d_folp, *res, *h_lists;
         float* res_d;
+        WS(d_piv, "pivots", sizeof(int32_t) * ns);
+        WS(d_fol, "followers", sizeof(int32_t) * ns);
+        WS(d_folp, "follower_pivot", sizeof(int32_t) * ns);
+        WS(res, "res", sizeof(int32_t) * ns * RES);
         WS(res_d, "res_d", sizeof(float) * ns * RES);
-        {
-            // pivot and follower lists to the device through one pinned buffer
-            int32_t* hl;
-            HS(hl, "h_lists", sizeof(int32_t) * (np + 2 * nf + 1));
-            memcpy(hl, P.pivots.data(), sizeof(int32_t) * np);
-            memcpy(hl + np, P.followers.data(), sizeof(int32_t) * nf);
-            memcpy(hl + np + nf, P.follower_pivot.data(), sizeof(int32_t) * nf);
-            if (np) HIPCHK(hipMemcpyAsync(d_piv, hl, sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
-            if (nf) {
-                HIPCHK(hipMemcpyAsync(d_fol, hl + np, sizeof(int32_t) * nf, hipMemcpyHostToDevice, st));
-                HIPCHK(hipMemcpyAsync(d_folp, hl + np + nf, sizeof(int32_t) * nf, hipMemcpyHostToDevice, st));
-            }
+        HS(h_lists, "h_lists", sizeof(int32_t) * 3 * ns);
+        int32_t* h_piv = h_lists;
+        int32_t* h_fol = h_lists + ns;
+        int32_t* h_folp = h_lists + 2 * ns;
+        int64_t *h_off = nullptr;
+        int32_t* h_ids = nullptr;
+        const bool fresh = cached[s].empty() && !(p->flags & RNSM_FLAG_ALL_PIVOTS);
+        if (fresh) {
+            int32_t *nk, *rcnt, *rk_ids;
+            int64_t *rk_off, *stmp;
+            WS(nk, "nk", sizeof(int32_t) * ns * k);
+            WS(rcnt, "rk_cnt", sizeof(int32_t) * ns);
+            WS(rk_off, "rk_off", sizeof(int64_t) * (ns + 1));
+            WS(rk_ids, "rk_ids", sizeof(int32_t) * ns * k);
+            WS(stmp, "scan_tmp", sizeof(int64_t) * scan_tmp_elems(ns));
+            std::array<int, 3> ex;
+            HIPCHK(E.record(st, &ex[0]));
+            SearchArgs a = {};
+            a.base = vi.search + bases[s] * vi.row_bytes;
+            a.nch = vi.nch;
+            a.row_bytes = vi.row_bytes;
+            a.offs = graphs[s].offsets;
+            a.nbrs = graphs[s].nbrs;
+            a.padj = padj + bases[s] * R;
+            a.rp = R;
+            a.n = ns;
+            a.qvec = a.base;
+            a.qidx = nullptr;
+            a.nq = ns;
+            a.seed_mode = 1;
+            a.metric = p->metric;
+            a.base_norm = norms ? norms + bases[s] : nullptr;
+            a.q_norm = a.base_norm;
+            a.ef = kp;
+            a.G = vi.G;
+            a.lgG = ilog2i(vi.G);
+            a.cpl = vi.cpl;
+            const SearchShape sh = search_shape(kp, R);
+            a.hbits = sh.hbits;
+            a.hash_mode = sh.mode;
+            a.out_mode = 1;
+            a.out_ids = nk;
+            a.out_stride = k;
+            a.out_k = k;
+            a.counters = cnt + 0 * CNT_SLOTS * CNT_N;
+            a.err = errf;
+            HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
+            HIPCHK(E.record(st, &ex[1]));
+            HIPCHK(launch_invert(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
+            HIPCHK(E.record(st, &ex[2]));
+            ev_exp.push_back(ex);
+            g_stats.queries[0] += ns;
+            g_stats.launches[0] += 1;
+            // R_k to the host through pinned buffers
+            HS(h_off, "h_rk_off", sizeof(int64_t) * (ns + 1));
+            HS(h_ids, "h_rk_ids", sizeof(int32_t) * ns * k);
+            HIPCHK(hipMemcpyAsync(h_off, rk_off, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(h_ids, rk_ids, sizeof(int32_t) * ns * k, hipMemcpyDeviceToHost, st));
         }
+        // also drains the previous operation, whose copies read h_lists
+        HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));
-        int e0, e0b, e1, e2;
-        HIPCHK(E.record(st, &e0));
+
+        // search arguments shared by the chunks
         SearchArgs a = {};
         a.base = vi.search + bases[t] * vi.row_bytes;
         a.nch = vi.nch;
@@ -499,42 +502,130 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.out_stride = RES;
         a.err = errf;
         // wave A: pivots, naive search from the target's entry point
-        a.qidx = d_piv;
-        a.nq = np;
-        a.seed_mode = 0;
-        a.entry = graphs[t].entry;
-        a.ef = efN;
-        a.out_k = efN;
-        a.out_row = d_piv;
-        a.counters = cnt + 1 * CNT_SLOTS * CNT_N;
+        SearchArgs aA = a;
+        aA.seed_mode = 0;
+        aA.entry = graphs[t].entry;
+        aA.ef = efN;
+        aA.out_k = efN;
+        aA.counters = cnt + 1 * CNT_SLOTS * CNT_N;
         const SearchShape shA = search_shape(efN, R);
-        a.hbits = shA.hbits;
-        a.hash_mode = shA.mode;
-        HIPCHK(launch_search(vi.tt, a, shA.wpb, st));
-        HIPCHK(E.record(st, &e0b));
+        aA.hbits = shA.hbits;
+        aA.hash_mode = shA.mode;
         // wave B: followers, local sliding from their pivot's results
-        a.qidx = d_fol;
-        a.nq = nf;
-        a.seed_mode = 2;
-        a.seed_ids = res;
-        a.seed_stride = RES;
-        a.seed_row = d_folp;
-        a.n_seeds = efN;
-        a.ef = efS;
-        a.out_k = efS;
-        a.out_row = d_fol;
-        a.counters = cnt + 2 * CNT_SLOTS * CNT_N;
+        SearchArgs aB = a;
+        aB.seed_mode = 2;
+        aB.seed_ids = res;
+        aB.seed_stride = RES;
+        aB.n_seeds = efN;
+        aB.ef = efS;
+        aB.out_k = efS;
+        aB.counters = cnt + 2 * CNT_SLOTS * CNT_N;
         const SearchShape shB = search_shape(efS, R);
-        a.hbits = shB.hbits;
-        a.hash_mode = shB.mode;
-        HIPCHK(launch_search(vi.tt, a, shB.wpb, st));
-        HIPCHK(E.record(st, &e1));
-        g_stats.queries[1] += np;
-        g_stats.queries[2] += nf;
-        g_stats.launches[1] += np > 0;
-        g_stats.launches[2] += nf > 0;
+        aB.hbits = shB.hbits;
+        aB.hash_mode = shB.mode;
         g_stats.exact_visited = shB.mode;
 
+        // chunk c: lists and naive search on the side stream, then the
+        // sliding search on st after the naive one (event wait); the naive
+        // search of chunk c+1 overlaps the sliding search of chunk c
+        hipStream_t sd;
+        HIPCHK(ws.side_stream(&sd));
+        int ev_go;
+        HIPCHK(E.record(st, &ev_go));
+        HIPCHK(hipStreamWaitEvent(sd, E.ev[ev_go], 0));
+        int64_t pa = 0, fa = 0;  // list prefixes already handed to the device
+        hipError_t cerr = hipSuccess;
+        auto emit = [&](int64_t np, int64_t nf) {
+            if (cerr != hipSuccess) return;
+            std::array<int, 4> ce;
+            auto chk = [&](hipError_t e) {
+                if (e != hipSuccess && cerr == hipSuccess) cerr = e;
+                return e == hipSuccess;
+            };
+            if (np > pa && !chk(hipMemcpyAsync(d_piv + pa, h_piv + pa, sizeof(int32_t) * (np - pa),
+                                               hipMemcpyHostToDevice, sd)))
+                return;
+            if (nf > fa) {
+                if (!chk(hipMemcpyAsync(d_fol + fa, h_fol + fa, sizeof(int32_t) * (nf - fa),
+                                        hipMemcpyHostToDevice, sd)) ||
+                    !chk(hipMemcpyAsync(d_folp + fa, h_folp + fa, sizeof(int32_t) * (nf - fa),
+                                        hipMemcpyHostToDevice, sd)))
+                    return;
+            }
+            if (!chk(E.record(sd, &ce[0]))) return;
+            SearchArgs x = aA;
+            x.qidx = d_piv + pa;
+            x.out_row = x.qidx;
+            x.nq = np - pa;
+            if (!chk(launch_search(vi.tt, x, shA.wpb, sd)) || !chk(E.record(sd, &ce[1]))) return;
+            if (!chk(hipStreamWaitEvent(st, E.ev[ce[1]], 0))) return;
+            if (!chk(E.record(st, &ce[2]))) return;
+            SearchArgs y = aB;
+            y.qidx = d_fol + fa;
+            y.out_row = y.qidx;
+            y.seed_row = d_folp + fa;
+            y.nq = nf - fa;
+            if (!chk(launch_search(vi.tt, y, shB.wpb, st)) || !chk(E.record(st, &ce[3]))) return;
+            ev_chunk.push_back(ce);
+            g_stats.launches[1] += np > pa;
+            g_stats.launches[2] += nf > fa;
+            pa = np;
+            fa = nf;
+        };
+        const auto tg = std::chrono::steady_clock::now();
+        int64_t np = 0, nf = 0;
+        if (p->flags & RNSM_FLAG_ALL_PIVOTS) {
+            // every vertex is a pivot (no sliding)
+            for (int64_t v = 0; v < ns; ++v) h_piv[v] = (int32_t)v;
+            np = ns;
+            emit(np, 0);
+        } else if (fresh) {
+            int64_t chunk = std::max<int64_t>(4096, ns / 64);
+            if (const char* c = getenv("RNSM_PIVOT_CHUNK")) chunk = std::max(1ll, atoll(c));
+            select_pivots(ns, h_off, h_ids, h_piv, h_fol, h_folp, chunk,
+                          [&](int64_t a1, int64_t b1) {
+                              np = a1;
+                              nf = b1;
+                              emit(a1, b1);
+                          });
+            if (last_use[s] > (int)oi) {
+                cached[s].assign(h_lists, h_lists + 3 * ns);
+                cached_np[s] = np;
+                cached_nf[s] = nf;
+            }
+        } else {
+            memcpy(h_lists, cached[s].data(), sizeof(int32_t) * 3 * ns);
+            np = cached_np[s];
+            nf = cached_nf[s];
+            emit(np, nf);
+        }
+        ms_plan += ms_since(tg);
+        if (cerr != hipSuccess) {
+            (void)hipStreamSynchronize(sd);
+            return fail(cerr == hipErrorOutOfMemory ? RNSM_ENOMEM : RNSM_EDEVICE,
+                        "rnsm_merge: queueing searches: %s", hipGetErrorString(cerr));
+        }
+        g_stats.queries[1] += np;
+        g_stats.queries[2] += nf;
+        // source prune order: each pivot followed by its followers, so that
+        // neighbouring wavefronts share most candidate rows in L2
+        int32_t *h_order, *d_order;
+        HS(h_order, "h_order", sizeof(int32_t) * ns);
+        WS(d_order, "prune_order", sizeof(int32_t) * ns);
+        {
+            int64_t o = 0, f = 0;
+            for (int64_t i = 0; i < np; ++i) {
+                const int32_t pv = h_piv[i];
+                h_order[o++] = pv;
+                while (f < nf && h_folp[f] == pv) h_order[o++] = h_fol[f++];
+            }
+            if (o != ns || f != nf)
+                return fail(RNSM_EINTERNAL, "rnsm_merge: pivot groups do not cover the source");
+            HIPCHK(hipMemcpyAsync(d_order, h_order, sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+        }
+
+        std::array<int, 2> pe;
+        HIPCHK(E.record(st, &pe[0]));
         // source rows: current row + search results, pruned to R
         PruneArgs q = {};
         q.X = vecs->f32;
@@ -546,6 +637,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         q.metric = p->metric;
         q.norms = norms;
         q.n_items = ns;
+        q.items = d_order;
         q.item_base = bases[s];
         q.rows_in = rows;
         q.deg_in = deg;
@@ -587,6 +679,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
                                   rev_d, st));
         PruneArgs r = q;
         r.n_items = nt;
+        r.items = nullptr;
         r.item_base = bases[t];
         r.extra_mode = 2;
         r.extra_ids = rev;
@@ -598,18 +691,12 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         r.scratch = scratch;
         r.wcap = 256;
         HIPCHK(launch_prune(r, st));
-        HIPCHK(E.record(st, &e2));
+        HIPCHK(E.record(st, &pe[1]));
+        ev_prune.push_back(pe);
+        HIPCHK(hipMemcpyAsync(h_nrev + oi, roff + nt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         g_stats.n_followers += nf;
         g_stats.n_pivots += np;
         g_stats.n_source_vertices += ns;
-        (void)e2;
-        HIPCHK(hipStreamSynchronize(st));  // keeps event timings per operation simple
-        g_stats.ms_search[1] += E.between(e0, e0b);
-        g_stats.ms_search[2] += E.between(e0b, e1);
-        ms_prune += E.between(e1, e2);
-        int64_t nrev = 0;
-        HIPCHK(hipMemcpy(&nrev, roff + nt, sizeof(int64_t), hipMemcpyDeviceToHost));
-        g_stats.n_reverse_edges += nrev;
     }
 
     // ----------------------------------------------------------- compaction
@@ -632,6 +719,16 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     for (int ph = 0; ph < 3; ++ph)
         for (int sl = 0; sl < CNT_SLOTS; ++sl)
             for (int c = 0; c < CNT_N; ++c) hc[ph * CNT_N + c] += hslots[(ph * CNT_SLOTS + sl) * CNT_N + c];
+    for (auto& ex : ev_exp) {
+        g_stats.ms_search[0] += E.between(ex[0], ex[1]);
+        g_stats.ms_invert += E.between(ex[1], ex[2]);
+    }
+    for (auto& ce : ev_chunk) {
+        g_stats.ms_search[1] += E.between(ce[0], ce[1]);
+        g_stats.ms_search[2] += E.between(ce[2], ce[3]);
+    }
+    for (auto& pe : ev_prune) ms_prune += E.between(pe[0], pe[1]);
+    for (size_t oi = 0; oi < ops.size(); ++oi) g_stats.n_reverse_edges += h_nrev[oi];
     if (herr & 1) return fail(RNSM_EINTERNAL, "rnsm_merge: a search exceeded its iteration bound");
     if (herr & 2) return fail(RNSM_EINTERNAL, "rnsm_merge: prune candidate list over capacity");
 

@@ -60,7 +60,7 @@ struct PruneArgs {
     int metric;
     const float* norms;
     int64_t n_items;
-    const int32_t* items;     // item i -> vertex items[i] (NULL: item_base + i)
+    const int32_t* items;     // item i -> vertex item_base + items[i] (NULL: item_base + i)
     int64_t item_base;
     const int32_t* rows_in;   // [* x R] current rows, indexed by vertex (NULL: empty rows)
     const int32_t* deg_in;

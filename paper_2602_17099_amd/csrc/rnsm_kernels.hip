@@ -513,7 +513,7 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     u64* lkeys = (u64*)psm + (int64_t)wib * (2 * a.wcap + a.R);
     u64* lsort = lkeys + a.wcap;
     int* kept_ids = (int*)(lsort + a.wcap);
-    const int64_t p = a.items ? (int64_t)a.items[i] : a.item_base + i;
+    const int64_t p = a.item_base + (a.items ? (int64_t)a.items[i] : i);
     const int64_t e = p - a.extra_index_base;
     const int R = a.R;
     const int G = a.G, RPP = WAVE >> a.lgG;
@@ -732,16 +732,19 @@ __global__ void k_pad_adjacency(const int64_t* offs, const int32_t* nbrs, int64_
     out[t] = j < e - b ? nbrs[b + j] : -1;
 }
 
+// one thread per row slot, so that consecutive threads write consecutive ids
 __global__ void k_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
                             int R, int32_t* rows, int32_t* deg, float* rdist) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * R) return;
+    const int64_t v = t / R;
+    const int j = (int)(t - v * R);
     const int64_t b = offs[v], e = offs[v + 1];
     const int64_t g = base + v;
-    deg[g] = (int32_t)(e - b);
-    for (int64_t j = b; j < e; ++j) {
-        rows[g * R + (j - b)] = (int32_t)(base + nbrs[j]);
-        rdist[g * R + (j - b)] = __int_as_float(0x7fc00000);  // NaN: not computed yet
+    if (j == 0) deg[g] = (int32_t)(e - b);
+    if (j < e - b) {
+        rows[g * R + j] = (int32_t)(base + nbrs[b + j]);
+        rdist[g * R + j] = __int_as_float(0x7fc00000);  // NaN: not computed yet
     }
 }
 
@@ -881,33 +884,53 @@ __global__ void k_max_i32(const int32_t* v, int64_t n, int32_t* out) {
     if (t < n) atomicMax(out, v[t]);
 }
 
-__global__ void k_compact(const int32_t* rows, const int32_t* deg, const float* rdist,
-                          const int64_t* off, int64_t N, int R, const float* X, int dim,
-                          int metric, const float* norms, int32_t* out_nbrs, float* out_dists) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N * R) return;
-    const int64_t v = t / R;
-    const int j = (int)(t - v * R);
-    if (j >= deg[v]) return;
-    const int32_t u = rows[t];
-    out_nbrs[off[v] + j] = u;
-    if (out_dists) {
-        float d = rdist[t];
-        if (d != d) {  // not computed by a prune: input edge left as it was
-            float acc = 0.0f;
-            for (int c = 0; c < dim; ++c) {
-                const float a = X[v * dim + c], b = X[(int64_t)u * dim + c];
-                if (metric == 0) {
-                    const float x = a - b;
-                    acc = fmaf(x, x, acc);
-                } else {
-                    acc = fmaf(a, b, acc);
-                }
-            }
-            d = finalize_dist(acc, metric, metric == 2 ? norms[v] : 1.0f,
-                              metric == 2 ? norms[u] : 1.0f);
-        }
-        out_dists[off[v] + j] = d;
+// One wavefront per vertex (R <= 64: one lane per slot). Distances a prune
+// did not compute (input edges of rows no operation touched) are computed
+// here with the prune's lane-group layout and summation order.
+template <int CPL>
+__global__ __launch_bounds__(256) void k_compact(const int32_t* rows, const int32_t* deg,
+                                                 const float* rdist, const int64_t* off, int64_t N,
+                                                 int R, const float* X, int nch, int G, int lgG,
+                                                 int metric, const float* norms, int32_t* out_nbrs,
+                                                 float* out_dists) {
+    __shared__ int slots[4][WAVE];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int64_t v = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    if (v >= N) return;
+    const int dg = deg[v];
+    const int64_t o = off[v];
+    int32_t u = -1;
+    float d = 0.0f;
+    if (lane < dg) {
+        u = rows[v * R + lane];
+        d = rdist[v * R + lane];
+        out_nbrs[o + lane] = u;
+    }
+    if (!out_dists) return;
+    const bool miss = lane < dg && d != d;
+    if (lane < dg && !miss) out_dists[o + lane] = d;
+    const u64 need = __ballot(miss);
+    if (need == 0ull) return;
+    const int cnt = __popcll(need);
+    if (miss) slots[wib][__popcll(need & lanemask_lt(lane))] = lane;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int group = lane >> lgG, sub = lane & (G - 1), RPP = WAVE >> lgG;
+    const int rowf = nch * 4;
+    float4 pv[CPL];
+    load_row_f32<CPL>(X, v, rowf, sub, G, pv);
+    const float vn = metric == 2 ? norms[v] : 1.0f;
+    for (int c0 = 0; c0 < cnt; c0 += RPP) {
+        const int c = c0 + group;
+        const int sl = c < cnt ? slots[wib][c] : 0;
+        const int32_t uu = __shfl(u, sl);
+        float4 ux[CPL];
+        load_row_f32<CPL>(X, c < cnt ? (int64_t)uu : -1, rowf, sub, G, ux);
+        const float acc = dist_rows<CPL>(ux, pv, metric, G);
+        if (c < cnt && sub == G - 1)
+            out_dists[o + sl] = finalize_dist(acc, metric, vn, metric == 2 ? norms[uu] : 1.0f);
     }
 }
 
@@ -1044,8 +1067,8 @@ hipError_t launch_pad_adjacency(const int64_t* offs, const int32_t* nbrs, int64_
 hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
                             int R, int32_t* rows, int32_t* deg, float* rdist, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_init_rows, dim3(nblk(n, 256)), dim3(256), 0, st, offs, nbrs, n, base, R,
-                       rows, deg, rdist);
+    hipLaunchKernelGGL(k_init_rows, dim3(nblk(n * R, 256)), dim3(256), 0, st, offs, nbrs, n, base,
+                       R, rows, deg, rdist);
     return hipGetLastError();
 }
 
@@ -1182,8 +1205,17 @@ hipError_t launch_compact(const int32_t* rows, const int32_t* deg, const float* 
                           int metric, const float* norms, int32_t* out_nbrs, float* out_dists,
                           hipStream_t st) {
     if (N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact, dim3(nblk(N * R, 256)), dim3(256), 0, st, rows, deg, rdist, off,
-                       N, R, X, dim, metric, norms, out_nbrs, out_dists);
+    if (R > WAVE) return hipErrorInvalidValue;
+    const int nch = dim / 4, G = lanes_per_row(nch);
+    if (dim % 4 != 0 || G < 0) return hipErrorInvalidValue;
+    const int cpl = nch / G, lgG = ilog2i(G);
+    const dim3 grid(nblk(N, 4)), block(256);
+    switch (cpl) {
+        case 1: hipLaunchKernelGGL(k_compact<1>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists); break;
+        case 2: hipLaunchKernelGGL(k_compact<2>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists); break;
+        case 3: hipLaunchKernelGGL(k_compact<3>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists); break;
+        default: hipLaunchKernelGGL(k_compact<4>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists); break;
+    }
     return hipGetLastError();
 }
 

@@ -151,15 +151,14 @@ int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int 
 // gain; otherwise make it a pivot whose followers are its uncovered R_k.
 // A vertex is only ever moved to a lower gain while a higher one is
 // processed, so every gain level is a bitmap over vertex ids scanned once in
-// ascending order.
-void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, Pivots& out) {
-    out.pivots.clear();
-    out.followers.clear();
-    out.follower_pivot.clear();
-    std::vector<unsigned char> covered((size_t)n, 0);
+// ascending order; Covered is a bitmap too, so covered vertices of a level
+// are dropped 64 at a time.
+void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivots,
+                   int32_t* followers, int32_t* follower_pivot, int64_t chunk, const Emit& emit) {
+    const int64_t words = (n + 63) / 64;
+    std::vector<uint64_t> cov((size_t)words, 0ull);
     int64_t gmax = 0;
     for (int64_t x = 0; x < n; ++x) gmax = std::max<int64_t>(gmax, rk_off[x + 1] - rk_off[x]);
-    const int64_t words = (n + 63) / 64;
     std::vector<std::vector<uint64_t>> level(gmax + 1);
     auto mark = [&](int64_t g, int64_t x) {
         std::vector<uint64_t>& b = level[g];
@@ -167,38 +166,48 @@ void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, Pivo
         b[x >> 6] |= 1ull << (x & 63);
     };
     for (int64_t x = 0; x < n; ++x) mark(rk_off[x + 1] - rk_off[x], x);
-    out.pivots.reserve(n / 4);
-    out.followers.reserve(n);
-    out.follower_pivot.reserve(n);
+    int64_t np = 0, nf = 0, sent = 0;
+    chunk = std::max<int64_t>(chunk, 1);
     for (int64_t g = gmax; g >= 0; --g) {
         std::vector<uint64_t>& b = level[g];
         if (b.empty()) continue;
         for (int64_t w = 0; w < words; ++w) {
-            uint64_t bits = b[w];
+            uint64_t bits = b[w] & ~cov[w];
             while (bits) {
                 const int32_t x = (int32_t)(w * 64 + __builtin_ctzll(bits));
                 bits &= bits - 1;
-                if (covered[x]) continue;
+                const int64_t o0 = rk_off[x], o1 = rk_off[x + 1];
                 int64_t cur = 0;
-                for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) cur += !covered[rk_ids[j]];
+                for (int64_t j = o0; j < o1; ++j) {
+                    const int32_t y = rk_ids[j];
+                    cur += (int64_t)(~cov[y >> 6] >> (y & 63) & 1ull);
+                }
                 if (cur < g) {
                     mark(cur, x);
                     continue;
                 }
-                out.pivots.push_back(x);
-                covered[x] = 1;
-                for (int64_t j = rk_off[x]; j < rk_off[x + 1]; ++j) {
+                pivots[np++] = x;
+                cov[w] |= 1ull << (x & 63);
+                for (int64_t j = o0; j < o1; ++j) {
                     const int32_t y = rk_ids[j];
-                    if (!covered[y]) {
-                        covered[y] = 1;
-                        out.followers.push_back(y);
-                        out.follower_pivot.push_back(x);
+                    const uint64_t bit = 1ull << (y & 63);
+                    if (!(cov[y >> 6] & bit)) {
+                        cov[y >> 6] |= bit;
+                        followers[nf] = y;
+                        follower_pivot[nf++] = x;
                     }
+                }
+                bits &= ~cov[w];
+                if (np + nf - sent >= chunk) {
+                    emit(np, nf);
+                    sent = np + nf;
+                    chunk *= 2;
                 }
             }
         }
         std::vector<uint64_t>().swap(b);
     }
+    if (np + nf > sent || sent == 0) emit(np, nf);
 }
 
 }  // namespace rnsm

@@ -2,6 +2,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <functional>
 #include <utility>
 #include <vector>
 
@@ -16,14 +17,16 @@ int mos_edges(int m, const std::vector<double>& cost, int R, int delta,
 int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int R, int delta,
              std::vector<std::pair<int, int>>& ops, int* fallbacks);
 
-struct Pivots {
-    std::vector<int32_t> pivots;          // selection order
-    std::vector<int32_t> followers;       // grouped by pivot (selection order), ids ascending
-    std::vector<int32_t> follower_pivot;  // pivot of each follower
-};
-
-// lazy greedy over reverse k-NN lists R_k (CSR; the order inside a list only
-// changes the order of the follower list, not the pivots or their followers)
-void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, Pivots& out);
+// Lazy greedy over reverse k-NN lists R_k (CSR). Writes the pivots in
+// selection order, and the followers grouped by pivot (selection order) with
+// the pivot of each follower; the order inside an R_k list only changes the
+// order of a pivot's followers, not the pivots or their follower sets.
+// `emit(np, nf)` is called with the running counts each time at least
+// `chunk` vertices (pivots plus followers, doubling after every call) were
+// added since the last call, and once at the end; a caller can start work
+// on every group emitted so far while the selection goes on.
+using Emit = std::function<void(int64_t np, int64_t nf)>;
+void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivots,
+                   int32_t* followers, int32_t* follower_pivot, int64_t chunk, const Emit& emit);
 
 }  // namespace rnsm

@@ -169,6 +169,20 @@ def test_merge_tiny_bit_exact(dev, orc, pkg, tiny):
     assert st["n_pivots"] + st["n_followers"] == 5000
 
 
+@pytest.mark.parametrize("chunk", ["1", "700"])
+def test_merge_tiny_pivot_chunks_bit_exact(dev, orc, pkg, tiny, monkeypatch, chunk):
+    # the searches start on pivot groups while the greedy still runs; many
+    # small chunks must give the same graph and counts as one
+    X, subs = tiny
+    ref = orc.merge(subs, X, R=16, L=32, alpha=1.2, trace=True)
+    monkeypatch.setenv("RNSM_PIVOT_CHUNK", chunk)
+    got = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=16, L=32, alpha=1.2)
+    _assert_same_merge(got, ref)
+    st = pkg.stats()
+    assert st["n_pivots"] == ref["trace"]["n_pivots"]
+    assert st["launches"][1] >= 3 and st["queries"][1] + st["queries"][2] == 5000
+
+
 def test_merge_simple_entry_point(dev, orc, pkg, tiny):
     X, subs = tiny
     ref = orc.merge(subs, X, R=16, L=32, alpha=1.2)
