@@ -147,7 +147,9 @@ typedef struct {
     double ms_total;        /* host wall time of the call */
     double ms_search[3];    /* search kernels of each phase (device events) */
     double ms_invert;       /* reverse k-NN inversion (device events) */
-    double ms_plan;         /* host: MOS, reverse k-NN transfer, lazy greedy */
+    double ms_plan;         /* host: MOS, reverse k-NN transfer, lazy greedy (the greedy
+                               overlaps the device searches of the pivot groups it has
+                               handed over) */
     double ms_prune;        /* source and target prunes with the reverse edges (device events) */
     double ms_compact;      /* CSR compaction (device events) */
     int64_t n_ops, n_source_vertices, n_pivots, n_followers, n_reverse_edges;
@@ -163,6 +165,9 @@ typedef struct {
                                again, which adds to ndc but never changes a result */
     int32_t row_bytes;      /* bytes of one row of the searched copy */
     int32_t exact_visited;  /* 1 when the searches ran with the probing visited table */
+    int32_t prune_path;     /* prune arithmetic: 0 float32 walk, 1 bfloat16 MFMA Gram with
+                               exact products (rows exact in bfloat16, integer sums below
+                               2^24), 3 MFMA Gram with a hi/lo bfloat16 split of each row */
 } rnsm_stats;
 
 /*

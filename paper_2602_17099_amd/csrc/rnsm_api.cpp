@@ -209,6 +209,42 @@ struct Events {
     }
 };
 
+// Prune arithmetic for float32 rows X (n x dim): the bfloat16 MFMA Gram
+// when the dimension fits it; exact products (mode 1) when every value is an
+// integer of magnitude at most 256 (exact in bfloat16) and every Gram and
+// squared-norm sum stays below 2^24; the hi/lo split (mode 3) otherwise; the
+// float32 walk (mode 0) for other dimensions. RNSM_PRUNE=walk|split forces
+// mode 0 / 3 where allowed.
+hipError_t choose_prune(const float* X, int64_t n, int dim, int R, unsigned* scratch3,
+                        hipStream_t st, int* mode) {
+    *mode = 0;
+    const char* env = getenv("RNSM_PRUNE");
+    if (env && !strcmp(env, "walk")) return hipSuccess;
+    if (!prune_mfma_supported(dim) || R > 64) return hipSuccess;
+    if (env && !strcmp(env, "split")) {
+        *mode = 3;
+        return hipSuccess;
+    }
+    hipError_t e = launch_value_range(X, n * dim, scratch3, st);
+    if (e != hipSuccess) return e;
+    unsigned h[3];
+    e = hipMemcpyAsync(h, scratch3, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    const double lo = key_to_float(h[1]), hi = key_to_float(h[2]);
+    const double bound = std::max(std::fabs(lo), std::fabs(hi));
+    const bool exact = h[0] == 1u && std::isfinite(bound) && bound <= 256.0 &&
+                       (double)dim * bound * bound < 16777216.0;
+    *mode = exact ? 1 : 3;
+    return hipSuccess;
+}
+
+hipError_t run_prune(const PruneArgs& a, int mode, hipStream_t st) {
+    if (mode != 0 && prune_mfma_fits(a, mode)) return launch_prune_mfma(a, mode, st);
+    return launch_prune(a, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -338,6 +374,12 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     WS(rdist, "rdist", sizeof(float) * N * R);
     WS(cnt, "counters", sizeof(u64) * 3 * CNT_SLOTS * CNT_N);
     WS(errf, "errf", sizeof(int));
+    int pmode = 0;
+    {
+        unsigned* vr;
+        WS(vr, "value_range", sizeof(unsigned) * 3);
+        HIPCHK(choose_prune(vecs->f32, N, vecs->dim, R, vr, st, &pmode));
+    }
     HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * 3 * CNT_SLOTS * CNT_N, st));
     HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
     if (p->metric == RNSM_COSINE) {
@@ -658,7 +700,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         q.dist_out = rdist;
         q.wcap = R + RES;
         q.err = errf;
-        HIPCHK(launch_prune(q, st));
+        HIPCHK(run_prune(q, pmode, st));
         // reverse edges into the target, then prune every target that got some
         int32_t *rc, *rcur, *rev;
         int64_t *roff, *stmp;
@@ -690,7 +732,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         r.skip_empty_extra = 1;
         r.scratch = scratch;
         r.wcap = 256;
-        HIPCHK(launch_prune(r, st));
+        HIPCHK(run_prune(r, pmode, st));
         HIPCHK(E.record(st, &pe[1]));
         ev_prune.push_back(pe);
         HIPCHK(hipMemcpyAsync(h_nrev + oi, roff + nt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -744,6 +786,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     S.ms_prune = ms_prune;
     S.ms_compact = E.between(c0, c1);
     S.n_ops = (int64_t)ops.size();
+    S.prune_path = pmode;
     S.row_bytes = vi.row_bytes;
     const double rb = vi.row_bytes;
     for (int ph = 0; ph < 3; ++ph) {
@@ -882,6 +925,12 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
     WS(deg1, "b_deg1", sizeof(int32_t) * n);
     WS(d1, "b_d1", sizeof(float) * n * R);
     WS(errf, "b_err", sizeof(int));
+    int pmode = 0;
+    {
+        unsigned* vr;
+        WS(vr, "value_range", sizeof(unsigned) * 3);
+        HIPCHK(choose_prune(X, n, dim, R, vr, st, &pmode));
+    }
     HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
     if (metric == RNSM_COSINE) {
         WS(norms, "b_norms", sizeof(float) * n);
@@ -909,7 +958,7 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
     q.dist_out = d1;
     q.wcap = K;
     q.err = errf;
-    HIPCHK(launch_prune(q, st));
+    HIPCHK(run_prune(q, pmode, st));
     int32_t *rows = rows1, *deg = deg1;
     if (reverse) {
         WS(rows2, "b_rows2", sizeof(int32_t) * n * R);
@@ -944,7 +993,7 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
         r.dist_out = d2;
         r.scratch = scratch;
         r.wcap = 256;
-        HIPCHK(launch_prune(r, st));
+        HIPCHK(run_prune(r, pmode, st));
         HIPCHK(launch_copy_rows(rows1, deg1, d1, rc, n, R, rows2, deg2, d2, st));
         rows = rows2;
         deg = deg2;

@@ -95,6 +95,16 @@ hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStrea
 hipError_t launch_search(int tt, const SearchArgs& a, int waves_per_block, hipStream_t st);
 size_t search_lds_bytes(int hbits, int waves_per_block);
 hipError_t launch_prune(const PruneArgs& a, hipStream_t st);
+// the same rule with the Gram products on bfloat16 MFMA (dims 32, 64, 96,
+// 128; R <= 64): nt = 1 for rows exact in bfloat16 with exact float32 sums,
+// nt = 3 (hi/lo split) otherwise
+bool prune_mfma_supported(int dim);
+bool prune_mfma_fits(const PruneArgs& a, int nt);  // dimension, R and LDS size
+hipError_t launch_prune_mfma(const PruneArgs& a, int nt, hipStream_t st);
+// out[0] = 1 if every value is an integer, out[1] / out[2] = order-preserving
+// bits of min / max (key_to_float gives the value back)
+hipError_t launch_value_range(const float* X, int64_t total, unsigned* out, hipStream_t st);
+float key_to_float(unsigned k);
 hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* off, int64_t* tmp_blocks,
                        hipStream_t st);
 size_t scan_tmp_elems(int64_t n);

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "rnsm_internal.h"
 
@@ -496,28 +497,17 @@ __device__ __forceinline__ void load_row_f32(const float* X, int64_t id, int row
     }
 }
 
-// Prune(p, W): W = current row of p plus the extra candidates; keys (d, id)
-// are computed, sorted by rank, and walked in order; a candidate is kept
-// unless alpha * d(w, v) < d(p, v) for a kept w (strict, in double); stop at
-// R kept. Kept rows stay in registers (KS slots per lane group) or are
-// re-read (KS == 0).
-template <int CPL, int KS>
-__global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
-    extern __shared__ unsigned char psm[];
-    const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    const int64_t i = xcd_block() * wpb + wib;
-    if (i >= a.n_items) return;
-    // per wavefront: keys[wcap], sorted[wcap], kept ids[R]
-    u64* lkeys = (u64*)psm + (int64_t)wib * (2 * a.wcap + a.R);
-    u64* lsort = lkeys + a.wcap;
-    int* kept_ids = (int*)(lsort + a.wcap);
-    const int64_t p = a.item_base + (a.items ? (int64_t)a.items[i] : i);
-    const int64_t e = p - a.extra_index_base;
+// Candidate list W of the prune of p (Section 2.2): the current row of p
+// plus the extra candidates, minus p itself. Keys (d(p, w), w) go to wk;
+// the ones whose float32 distance is already known (search results, reverse
+// edges, pruned rows) take it, the others are computed here with the lane
+// group layout. Then the keys are placed in (d, id) order into *ws_out.
+// Returns |W|, or -1 when the wavefront has nothing to do.
+template <int CPL>
+__device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int64_t e, int lane,
+                                             u64* lkeys, u64** wk_out, u64** ws_out) {
     const int R = a.R;
     const int G = a.G, RPP = WAVE >> a.lgG;
-
     const int nrow = a.rows_in ? a.deg_in[p] : 0;
     int next = 0;
     int64_t xo = 0;
@@ -528,21 +518,18 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
         xo = a.extra_off[e];
         next = (int)(a.extra_off[e + 1] - xo);
     }
-    if (a.skip_empty_extra && next == 0) return;
+    if (a.skip_empty_extra && next == 0) return -1;
     const int nW = nrow + next;
     u64* wk = lkeys;
-    u64* ws = lsort;
+    u64* ws = lkeys + a.wcap;
     if (nW > a.wcap) {
         if (a.extra_mode != 2 || !a.scratch) {
             if (lane == 0) atomicOr(a.err, 2);
-            return;
+            return -1;
         }
         wk = a.scratch + 2 * ((int64_t)R * e + xo);
         ws = wk + nW;
     }
-    // candidate ids; a candidate whose float32 distance to p is already known
-    // (its search result, a reverse edge, a pruned row) gets its key now,
-    // the others hold their id (< 2^32) until their distance is computed
     for (int t = lane; t < nW; t += WAVE) {
         int64_t id;
         float d = __int_as_float(0x7fc00000);
@@ -558,6 +545,7 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
             atomicOr(a.err, 4);
             id = -1;
         }
+        // a key with the id alone (< 2^32) marks a distance still to compute
         wk[t] = (id < 0 || id == p) ? EMPTY_KEY : (d == d ? make_key(d, (int)id) : (u64)id);
     }
     __builtin_amdgcn_wave_barrier();
@@ -569,7 +557,6 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     float4 pq[CPL];
     load_row_f32<CPL>(a.X, p, rowf, sub, G, pq);
     const float pn = a.metric == 2 ? a.norms[p] : 1.0f;
-    // keys (d(p, w), w) of the candidates still without one
     constexpr int UNR = 2;
     for (int c0 = 0; c0 < nW; c0 += RPP * UNR) {
         float4 raw[UNR][CPL];
@@ -598,15 +585,45 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     for (int t = lane; t < nW; t += WAVE) {
         const u64 kt = wk[t];
         int r = 0;
-        for (int s = 0; s < nW; ++s) {
-            const u64 ks = wk[s];
-            r += (ks < kt || (ks == kt && s < t)) ? 1 : 0;
+        for (int s2 = 0; s2 < nW; ++s2) {
+            const u64 ks = wk[s2];
+            r += (ks < kt || (ks == kt && s2 < t)) ? 1 : 0;
         }
         ws[r] = kt;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    *wk_out = wk;
+    *ws_out = ws;
+    return nW;
+}
+
+// Prune(p, W) with float32 vector arithmetic: candidates are walked in
+// (d, id) order; a candidate is kept unless alpha * d(w, v) < d(p, v) for a
+// kept w (strict, in double); stop at R kept. Kept rows stay in registers
+// (KS slots per lane group) or are re-read (KS == 0).
+template <int CPL, int KS>
+__global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
+    extern __shared__ unsigned char psm[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int64_t i = xcd_block() * wpb + wib;
+    if (i >= a.n_items) return;
+    // per wavefront: keys[wcap], sorted[wcap], kept ids[R]
+    u64* lkeys = (u64*)psm + (int64_t)wib * (2 * a.wcap + a.R);
+    int* kept_ids = (int*)(lkeys + 2 * a.wcap);
+    const int64_t p = a.item_base + (a.items ? (int64_t)a.items[i] : i);
+    const int64_t e = p - a.extra_index_base;
+    const int R = a.R;
+    const int G = a.G, RPP = WAVE >> a.lgG;
+    u64 *wk, *ws;
+    const int nW = prune_collect<CPL>(a, p, e, lane, lkeys, &wk, &ws);
+    if (nW < 0) return;
+    (void)wk;
+    const int group = lane >> a.lgG, sub = lane & (G - 1);
+    const int rowf = a.nch * 4;
 
     // walk the candidates in (d, id) order
     float4 kept[KS > 0 ? KS : 1][CPL];
@@ -678,6 +695,267 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         ++nk;
+    }
+    if (lane == 0) a.deg_out[p] = nk;
+}
+
+// ------------------------------------------------------------ MFMA prune
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// bfloat16 bits of a finite float, round to nearest even
+__device__ __forceinline__ unsigned bf16_bits(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// eight floats -> packed bfloat16 hi = bf16(v) and, with NT == 3, the
+// remainder lo = bf16(v - hi), so that hi + lo carries about 16 bits
+template <int NT>
+__device__ __forceinline__ void split8(const float* v, uint4& hi, uint4& lo) {
+    unsigned h[8], l[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        h[e] = bf16_bits(v[e]);
+        l[e] = NT > 1 ? bf16_bits(v[e] - __uint_as_float(h[e] << 16)) : 0u;
+    }
+    hi = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16);
+    lo = make_uint4(l[0] | l[1] << 16, l[2] | l[3] << 16, l[4] | l[5] << 16, l[6] | l[7] << 16);
+}
+
+// D += A B for 16x32 A and 32x16 B; lane l holds row (A) / column (B) l % 16,
+// k = 8 (l / 16) + 0..7; D: lane l, element r is D[4 (l / 16) + r][l % 16]
+__device__ __forceinline__ floatx4_t mfma16(uint4 a, uint4 b, floatx4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                  __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+}
+
+// d(w_i, w_j) from the Gram entry g of the two rows: squared L2 as
+// u_i + u_j - 2 g, with u = |w|^2 for plain rows or u = |w - p|^2 = d(p, w)
+// (the key distance) for rows centred at p; inner product and cosine on the
+// rows themselves
+__device__ __forceinline__ double gram_dist(float g, int metric, float ui, float uj, float ni,
+                                            float nj) {
+    if (metric == 0) return (double)ui + (double)uj - 2.0 * (double)g;
+    if (metric == 1) return (double)(1.0f - g);
+    return (double)(1.0f - g / (ni * nj));
+}
+
+// LDS bytes per wavefront of k_prune_mfma: keys and sorted keys, kept ids,
+// distances and squared norms, kept-row fragments (R rounded up to whole
+// 16-row tiles; hi, then lo with the split)
+__host__ __device__ inline int mfma_row_stride(int kd) { return 64 * kd + 16; }
+__host__ __device__ inline int mfma_kept_rows(int R) { return (R + 15) & ~15; }
+__host__ __device__ inline size_t mfma_kept_bytes(int R) { return ((size_t)R * 12 + 15) / 16 * 16; }
+__host__ __device__ inline size_t mfma_prune_lds(int wcap, int R, int kd, int nt) {
+    return (size_t)2 * wcap * sizeof(u64) + mfma_kept_bytes(R) +
+           (size_t)mfma_kept_rows(R) * mfma_row_stride(kd) * (nt > 1 ? 2 : 1);
+}
+
+// Prune(p, W) with the candidate x kept-row Gram products on bfloat16 MFMA.
+// Candidates are taken 16 at a time in (d, id) order (tile J). Each lane
+// holds the 8 KD dimensions [q * 8 KD, (q + 1) * 8 KD) of row l % 16 of the
+// tile, q = l / 16, as KD fragments of 8. One MFMA chain gives the 16 x 16
+// Gram of the tile with itself; one per 16 kept rows (bfloat16 fragments in
+// LDS) gives kept x tile. A pair (w, v) is decided by
+// alpha * d(w, v) < d(p, v) as in the walk; then the 16 candidates are
+// resolved in order with ballot bit masks, and the kept ones are appended
+// to the kept rows.
+//  NT == 1: rows exact in bfloat16 and every Gram and squared-norm sum
+//           exact in float32 (integers of magnitude <= 256, dim <= 256):
+//           every d(w, v) is exact, so every decision equals the walk's.
+//  NT == 3: rows split as hi + lo bfloat16, products hi*hi + hi*lo + lo*hi;
+//           squared L2 works on rows centred at p.
+template <int KD, int NT, int CPL>
+__global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
+    extern __shared__ unsigned char psm[];
+    constexpr bool CENTER = NT > 1;
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int64_t i = xcd_block() * wpb + wib;
+    if (i >= a.n_items) return;
+    const int R = a.R;
+    unsigned char* base = psm + (size_t)wib * mfma_prune_lds(a.wcap, R, KD, NT);
+    u64* lkeys = (u64*)base;
+    int* kept_ids = (int*)(base + (size_t)2 * a.wcap * sizeof(u64));
+    float* kept_d = (float*)(kept_ids + R);
+    float* kept_u = kept_d + R;
+    unsigned char* khi = base + (size_t)2 * a.wcap * sizeof(u64) + mfma_kept_bytes(R);
+    const int rs = mfma_row_stride(KD);
+    const size_t klo_off = (size_t)mfma_kept_rows(R) * rs;  // lo fragments follow the hi ones
+    const int64_t p = a.item_base + (a.items ? (int64_t)a.items[i] : i);
+    const int64_t e = p - a.extra_index_base;
+    u64 *wk, *ws;
+    const int nW = prune_collect<CPL>(a, p, e, lane, lkeys, &wk, &ws);
+    if (nW < 0) return;
+    (void)wk;
+
+    constexpr int DL = 8 * KD;  // dimensions per lane
+    const int dim = 32 * KD;
+    const int jr = lane & 15, q = lane >> 4;
+    const int metric = a.metric;
+    const double alpha = (double)a.alpha;
+    float pf[CENTER ? DL : 1];
+    if constexpr (CENTER) {
+#pragma unroll
+        for (int t = 0; t < DL; ++t) pf[t] = 0.0f;
+        if (metric == 0) {
+            const float4* pr = (const float4*)(a.X + p * dim + q * DL);
+#pragma unroll
+            for (int t = 0; t < DL / 4; ++t) {
+                const float4 x = pr[t];
+                pf[4 * t] = x.x;
+                pf[4 * t + 1] = x.y;
+                pf[4 * t + 2] = x.z;
+                pf[4 * t + 3] = x.w;
+            }
+        }
+    }
+    // this lane's DL floats of sorted candidate J * 16 + l % 16 (zeros past the end)
+    auto load_tile = [&](int J, float* raw) {
+        const int c = J * 16 + jr;
+        const u64 kk = c < nW ? ws[c] : EMPTY_KEY;
+        if (kk != EMPTY_KEY) {
+            const float4* r = (const float4*)(a.X + (int64_t)(unsigned)(kk & 0xffffffffu) * dim + q * DL);
+#pragma unroll
+            for (int t = 0; t < DL / 4; ++t) {
+                const float4 x = r[t];
+                raw[4 * t] = x.x;
+                raw[4 * t + 1] = x.y;
+                raw[4 * t + 2] = x.z;
+                raw[4 * t + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < DL; ++t) raw[t] = 0.0f;
+        }
+    };
+    float raw[DL];
+    load_tile(0, raw);
+    int nk = 0;
+    u64 prev = EMPTY_KEY;
+    const int ntiles = (nW + 15) >> 4;
+    for (int J = 0; J < ntiles && nk < R; ++J) {
+        const int c = J * 16 + jr;
+        const u64 key = c < nW ? ws[c] : EMPTY_KEY;
+        const int idj = key == EMPTY_KEY ? -1 : (int)(unsigned)(key & 0xffffffffu);
+        const float dj = key == EMPTY_KEY ? INFINITY : fval((unsigned)(key >> 32));
+        const float nj = (metric == 2 && idj >= 0) ? a.norms[idj] : 1.0f;
+        uint4 hi[KD], lo[KD];
+        float sq = 0.0f;  // squared norm of the plain row (exact for NT == 1)
+#pragma unroll
+        for (int s2 = 0; s2 < KD; ++s2) {
+            float v[8];
+#pragma unroll
+            for (int e2 = 0; e2 < 8; ++e2) {
+                v[e2] = CENTER ? raw[8 * s2 + e2] - pf[CENTER ? 8 * s2 + e2 : 0] : raw[8 * s2 + e2];
+                if constexpr (!CENTER) sq = fmaf(v[e2], v[e2], sq);
+            }
+            split8<NT>(v, hi[s2], lo[s2]);
+        }
+        float uj = dj;
+        if constexpr (!CENTER) {
+            sq += __shfl_xor(sq, 16);
+            sq += __shfl_xor(sq, 32);
+            uj = sq;
+        }
+        if (J + 1 < ntiles) load_tile(J + 1, raw);  // next tile's rows in flight
+
+        // the tile with itself: pairs (i, j), i = 4 q + r, j = l % 16, i < j
+        floatx4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s2 = 0; s2 < KD; ++s2) {
+            acc = mfma16(hi[s2], hi[s2], acc);
+            if constexpr (NT > 1) {
+                acc = mfma16(hi[s2], lo[s2], acc);
+                acc = mfma16(lo[s2], hi[s2], acc);
+            }
+        }
+        u64 bt[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = 4 * q + r;
+            const float ui = __shfl(uj, ii);
+            const float ni = __shfl(nj, ii);
+            const bool pred = ii < jr && alpha * gram_dist(acc[r], metric, ui, uj, ni, nj) < (double)dj;
+            bt[r] = __ballot(pred);
+        }
+        // kept rows of earlier tiles against the tile
+        const int nk0 = nk;
+        u64 bk = 0ull;
+        for (int kt = 0; kt * 16 < nk0; ++kt) {
+            floatx4_t ak = {0.0f, 0.0f, 0.0f, 0.0f};
+            const unsigned char* krow = khi + (size_t)(kt * 16 + jr) * rs + q * KD * 16;
+#pragma unroll
+            for (int s2 = 0; s2 < KD; ++s2) {
+                const uint4 kh = *(const uint4*)(krow + s2 * 16);
+                ak = mfma16(kh, hi[s2], ak);
+                if constexpr (NT > 1) {
+                    const uint4 kl = *(const uint4*)(krow + klo_off + s2 * 16);
+                    ak = mfma16(kh, lo[s2], ak);
+                    ak = mfma16(kl, hi[s2], ak);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ki = kt * 16 + 4 * q + r;
+                bool pred = false;
+                if (ki < nk0) {
+                    const float nkk = metric == 2 ? a.norms[kept_ids[ki]] : 1.0f;
+                    pred = alpha * gram_dist(ak[r], metric, kept_u[ki], uj, nkk, nj) < (double)dj;
+                }
+                bk |= __ballot(pred);
+            }
+        }
+        const unsigned domk = (unsigned)((bk | (bk >> 16) | (bk >> 32) | (bk >> 48)) & 0xffffull);
+        // mask of the earlier tile candidates that would dominate candidate l % 16
+        unsigned mj = 0;
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) mj |= (unsigned)((bt[ii & 3] >> (16 * (ii >> 2) + jr)) & 1ull) << ii;
+        // resolve the 16 candidates in order (wavefront-uniform)
+        unsigned keptj = 0;
+        bool stop = false;
+        for (int j = 0; j < 16; ++j) {
+            const u64 kj = readlane64(key, j);
+            if (kj == EMPTY_KEY) {  // past the end, or no more valid candidates
+                stop = true;
+                break;
+            }
+            if (kj == prev) continue;  // the same vertex twice in W
+            prev = kj;
+            if ((domk >> j) & 1u) continue;
+            const unsigned mjj = (unsigned)__builtin_amdgcn_readlane((int)mj, j);
+            if (mjj & keptj) continue;
+            keptj |= 1u << j;
+            if (nk + __popc(keptj) == R) {
+                stop = true;
+                break;
+            }
+        }
+        // append the kept candidates (rows, ids, distances, outputs)
+        if ((keptj >> jr) & 1u) {
+            const int kr = nk + __popc(keptj & ((1u << jr) - 1u));
+            unsigned char* dst = khi + (size_t)kr * rs + q * KD * 16;
+#pragma unroll
+            for (int s2 = 0; s2 < KD; ++s2) {
+                *(uint4*)(dst + s2 * 16) = hi[s2];
+                if constexpr (NT > 1) *(uint4*)(dst + klo_off + s2 * 16) = lo[s2];
+            }
+            if (q == 0) {
+                kept_ids[kr] = idj;
+                kept_d[kr] = dj;
+                kept_u[kr] = uj;
+                a.rows_out[p * R + kr] = idj;
+                a.dist_out[p * R + kr] = dj;
+            }
+        }
+        nk += __popc(keptj);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (stop) break;
     }
     if (lane == 0) a.deg_out[p] = nk;
 }
@@ -949,6 +1227,52 @@ __global__ void k_copy_rows(const int32_t* rows_a, const int32_t* deg_a, const f
     }
 }
 
+// value summary of X for the choice of the prune arithmetic: out[0] stays 1
+// while every value is an integer, out[1] / out[2] are the order-preserving
+// bits (fkey) of the minimum / maximum
+__global__ void k_value_range(const float* X, int64_t total, unsigned* out) {
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool frac = false;
+    unsigned lo = ~0u, hi = 0u;
+    for (int64_t t = t0; t < total; t += stride) {
+        const float x = X[t];
+        frac |= !(x == floorf(x));
+        const unsigned k = fkey(x);
+        lo = k < lo ? k : lo;
+        hi = k > hi ? k : hi;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+    }
+    const bool anyfrac = __ballot(frac) != 0ull;
+    if (lane_id() == 0) {
+        if (anyfrac) atomicAnd(&out[0], 0u);
+        atomicMin(&out[1], lo);
+        atomicMax(&out[2], hi);
+    }
+}
+
+hipError_t launch_value_range(const float* X, int64_t total, unsigned* out, hipStream_t st) {
+    const unsigned init[3] = {1u, ~0u, 0u};
+    hipError_t e = hipMemcpyAsync(out, init, sizeof init, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess || total <= 0) return e;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_value_range, dim3((unsigned)blocks), dim3(256), 0, st, X, total, out);
+    return hipGetLastError();
+}
+
+float key_to_float(unsigned k) {
+    const unsigned u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    float f;
+    memcpy(&f, &u, sizeof f);
+    return f;
+}
+
 // builder entry point: vertex closest to the centroid
 __global__ void k_check_integral(const float* X, int64_t total, int* flag) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1129,6 +1453,42 @@ static void launch_prune_c(const PruneArgs& a, int need, dim3 grid, dim3 block, 
         hipLaunchKernelGGL((k_prune<CPL, 4>), grid, block, lds, st, a);
     else
         hipLaunchKernelGGL((k_prune<CPL, 0>), grid, block, lds, st, a);
+}
+
+template <int KD, int CPL>
+static void launch_prune_mfma_c(const PruneArgs& a, int nt, dim3 grid, dim3 block, size_t lds,
+                                hipStream_t st) {
+    if (nt == 1)
+        hipLaunchKernelGGL((k_prune_mfma<KD, 1, CPL>), grid, block, lds, st, a);
+    else
+        hipLaunchKernelGGL((k_prune_mfma<KD, 3, CPL>), grid, block, lds, st, a);
+}
+
+bool prune_mfma_supported(int dim) { return dim % 32 == 0 && dim >= 32 && dim <= 128; }
+
+bool prune_mfma_fits(const PruneArgs& a, int nt) {
+    const int dim = a.nch * 4;
+    return prune_mfma_supported(dim) && a.R <= 64 &&
+           mfma_prune_lds(a.wcap, a.R, dim / 32, nt) <= 64 * 1024;
+}
+
+hipError_t launch_prune_mfma(const PruneArgs& a, int nt, hipStream_t st) {
+    if (a.n_items <= 0) return hipSuccess;
+    const int dim = a.nch * 4;
+    if (!prune_mfma_fits(a, nt) || (nt != 1 && nt != 3)) return hipErrorInvalidValue;
+    const int kd = dim / 32;
+    const size_t per = mfma_prune_lds(a.wcap, a.R, kd, nt);
+    const int wpb = per <= 32 * 1024 ? 2 : 1;
+    const size_t lds = (size_t)wpb * per;
+    const dim3 grid(nblk(a.n_items, wpb)), block(wpb * WAVE);
+    // the candidate-distance layout of prune_collect for dim = 32 kd
+    switch (kd) {
+        case 1: launch_prune_mfma_c<1, 4>(a, nt, grid, block, lds, st); break;
+        case 2: launch_prune_mfma_c<2, 4>(a, nt, grid, block, lds, st); break;
+        case 3: launch_prune_mfma_c<3, 3>(a, nt, grid, block, lds, st); break;
+        default: launch_prune_mfma_c<4, 4>(a, nt, grid, block, lds, st); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_prune(const PruneArgs& a, hipStream_t st) {

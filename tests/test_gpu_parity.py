@@ -260,28 +260,61 @@ def medium(orc):
     return X, subs
 
 
-def test_merge_medium_bit_exact(dev, orc, pkg, medium):
+@pytest.fixture(scope="module")
+def medium_ref(orc, medium):
     X, subs = medium
-    ref = orc.merge(subs, X, R=32, L=64, alpha=1.2)
+    return orc.merge(subs, X, R=32, L=64, alpha=1.2)
+
+
+# prune arithmetic: default (bfloat16 MFMA Gram, exact products on these
+# integers), forced float32 walk, forced hi/lo split MFMA
+PRUNE_PATHS = [(None, 1), ("walk", 0), ("split", 3)]
+
+
+@pytest.mark.parametrize("mode,path", PRUNE_PATHS)
+def test_merge_medium_bit_exact(dev, orc, pkg, medium, medium_ref, monkeypatch, mode, path):
+    X, subs = medium
+    if mode:
+        monkeypatch.setenv("RNSM_PRUNE", mode)
     got = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=32, L=64, alpha=1.2)
+    assert pkg.stats()["prune_path"] == path
+    _assert_same_merge(got, medium_ref)
+
+
+@pytest.mark.parametrize("mode,path", PRUNE_PATHS)
+@pytest.mark.parametrize("dim,R,L", [(96, 24, 48), (128, 64, 32), (64, 12, 24)])
+def test_merge_prune_shapes_bit_exact(dev, orc, pkg, monkeypatch, dim, R, L, mode, path):
+    # every MFMA fragment count (dim 64, 96, 128), R not a multiple of 16,
+    # and R = 64 (one wavefront per block for the split form's LDS)
+    X = inputs.mixture_u8(3000, dim, comps=16, seed=700 + dim)
+    subs = [orc.build_graph(X[:1300], 2 * R, R, alpha=1.2, reverse=True),
+            orc.build_graph(X[1300:], 2 * R, R, alpha=1.2, reverse=True)]
+    ref = orc.merge(subs, X, R=R, L=L, alpha=1.2)
+    if mode:
+        monkeypatch.setenv("RNSM_PRUNE", mode)
+    got = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=R, L=L, alpha=1.2)
+    assert pkg.stats()["prune_path"] == path
     _assert_same_merge(got, ref)
 
 
-def test_merge_medium_bf16_search_bit_exact(dev, orc, pkg, medium):
+def test_merge_medium_bf16_search_bit_exact(dev, orc, pkg, medium, medium_ref):
     # 0..255 integers are exact in bfloat16: the reduced-precision search
     # reads different bytes but must reach the same graph
     import torch
     X, subs = medium
-    ref = orc.merge(subs, X, R=32, L=64, alpha=1.2)
+    ref = medium_ref
     Xd = _t(X, dev)
     got = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2, search=Xd.to(torch.bfloat16))
     _assert_same_merge(got, ref)
 
 
-@pytest.mark.parametrize("metric", [1, 2])
-def test_merge_float_data_tolerances(dev, orc, pkg, metric):
-    # L2-normalised float vectors, inner product / cosine: float32 on the GPU
-    # against float64 in the oracle
+@pytest.mark.parametrize("mode,path", [(None, 3), ("walk", 0)])
+@pytest.mark.parametrize("metric", [0, 1, 2])
+def test_merge_float_data_tolerances(dev, orc, pkg, monkeypatch, metric, mode, path):
+    # L2-normalised float vectors: float32 (walk) or hi/lo bfloat16 Gram
+    # (MFMA) on the GPU against float64 in the oracle
+    if mode:
+        monkeypatch.setenv("RNSM_PRUNE", mode)
     X = inputs.mixture_unit(6000, 32, comps=32, seed=401 + metric)
     Q = inputs.mixture_unit(200, 32, comps=32, seed=401 + metric, stream=1)
     subs = [orc.build_graph(X[:2500], 32, 16, alpha=1.2, metric=metric, reverse=True),
@@ -289,6 +322,7 @@ def test_merge_float_data_tolerances(dev, orc, pkg, metric):
     ref = orc.merge(subs, X, R=16, L=32, alpha=1.2, metric=metric)
     off, nb, ds, entry = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=16, L=32, alpha=1.2,
                                    metric=metric)
+    assert pkg.stats()["prune_path"] == path
     off, nb, ds = off.cpu().numpy(), nb.cpu().numpy(), ds.cpu().numpy()
     assert entry == ref["entry"]
     E_gpu = {(v, int(u)) for v in range(len(X)) for u in nb[off[v]:off[v + 1]]}
@@ -308,8 +342,11 @@ def test_merge_float_data_tolerances(dev, orc, pkg, metric):
 
 # --------------------------------------------------------------- builder
 
+@pytest.mark.parametrize("mode", [None, "walk", "split"])
 @pytest.mark.parametrize("reverse", [False, True])
-def test_build_graph_bit_exact(dev, orc, pkg, reverse):
+def test_build_graph_bit_exact(dev, orc, pkg, monkeypatch, reverse, mode):
+    if mode:
+        monkeypatch.setenv("RNSM_PRUNE", mode)
     X = inputs.mixture_u8(4000, 64, seed=501)
     knn = orc.knn_fast(X, 40)
     ref = orc.build_graph(X, 40, 20, alpha=1.2, reverse=reverse, alpha_rev=1.2, knn_ids=knn)
