@@ -26,6 +26,36 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of the k_beam_search launches of one timed merge, from two
+# rocprofv3 --pmc passes over `bench.py --steps 1 --warmup 0 --no-cpu-baseline
+# --no-bf16 --no-recall` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
+# each scaled by what the counter reads for a plain 1 GiB device copy
+# (FETCH_SIZE 0.5 GiB: factor 2.0; WRITE_SIZE 1 GiB: factor 1.0). The figures
+# hold for the sources they were taken on only (sha256 of the files below).
+COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
+                   "paper_2602_17099_amd/csrc/rnsm_api.cpp")
+SEARCH_COUNTERS = None  # {"sources_sha256": ..., "fetch_kib": [...], "write_kib": [...]}
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in COUNTER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def search_traffic():
+    """Measured HBM bytes per k_beam_search launch, or None when the counters
+    were taken on other sources."""
+    c = SEARCH_COUNTERS
+    if not c or c["sources_sha256"] != sources_sha256():
+        return None
+    tot = sum(c["fetch_kib"]) * FETCH_FACTOR + sum(c["write_kib"]) * WRITE_FACTOR
+    return tot * 1024.0 / len(c["fetch_kib"])
+
 WORKLOADS = {
     "fp32-2x500k": dict(n=500_000, dim=128, R=32, L=64, alpha=1.2, K=64, nq=10_000,
                         gen="mixture_u8", build_alpha=1.2, reverse=True),
@@ -88,12 +118,14 @@ def time_merges(pkg, subs, Xd, wl, steps, warmup, search=None):
     for _ in range(warmup):
         pkg.merge(subs, Xd, **kw)
     torch.cuda.synchronize()
-    agg = {"ms": [0.0] * 3, "bytes": [0.0] * 3, "ndc": [0] * 3, "launches": [0] * 3}
+    agg = {"ms": [0.0] * 3, "bytes": [0.0] * 3, "ndc": [0] * 3, "launches": [0] * 3,
+           "span_ms": 0.0}
     st = None
     t0 = time.perf_counter()
     for _ in range(steps):
         res = pkg.merge(subs, Xd, **kw)
         st = pkg.stats()
+        agg["span_ms"] += st["ms_search_span"]
         for ph in range(3):
             agg["ms"][ph] += st["ms_search"][ph]
             agg["bytes"][ph] += st["bytes"][ph]
@@ -120,13 +152,17 @@ def exact_ndc(pkg, subs, Xd, wl, search=None):
 def search_roofline(agg, st, ndc_exact, steps):
     """Algorithmic bytes of the k_beam_search launches (expansion, naive,
     sliding) over their event-timed durations; re-evaluations caused by the
-    forgetful visited table are not counted as algorithmic bytes."""
+    forgetful visited table are not counted as algorithmic bytes. Naive and
+    sliding launches overlap on two streams, so their event durations add up
+    to more than the device time they take together (span_gbs uses that)."""
     rb = st["row_bytes"]
     tot_b = tot_ms = 0.0
     per = {}
+    b_ph = []
     for ph in range(3):
         extra = agg["ndc"][ph] - steps * ndc_exact[ph]
         b = agg["bytes"][ph] - extra * rb
+        b_ph.append(b)
         per[PHASES[ph]] = {"gbs": b / (agg["ms"][ph] * 1e6) if agg["ms"][ph] else None,
                            "ms_per_launch": agg["ms"][ph] / max(1, agg["launches"][ph]),
                            "ndc_inflation": agg["ndc"][ph] / max(1, steps * ndc_exact[ph])}
@@ -134,10 +170,15 @@ def search_roofline(agg, st, ndc_exact, steps):
         tot_ms += agg["ms"][ph]
     launches = sum(agg["launches"])
     achieved = tot_b / (tot_ms * 1e6)
+    span = agg["span_ms"]
+    tr = search_traffic()
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": round(tr) if tr is not None else None,
             "kernel": "k_beam_search (expansion, naive and sliding launches)",
             "bytes_per_launch": tot_b / launches, "ms_per_launch": tot_ms / launches,
+            "launches_per_step": launches / steps,
+            "span_gbs": round((b_ph[1] + b_ph[2]) / (span * 1e6), 1) if span else None,
             "per_phase": per}
 
 

@@ -168,6 +168,10 @@ typedef struct {
     int32_t prune_path;     /* prune arithmetic: 0 float32 walk, 1 bfloat16 MFMA Gram with
                                exact products (rows exact in bfloat16, integer sums below
                                2^24), 3 MFMA Gram with a hi/lo bfloat16 split of each row */
+    double ms_search_span;  /* device time from the first naive search to the last sliding
+                               search of each operation, summed over operations: naive and
+                               sliding launches overlap on two streams, so this is below
+                               ms_search[1] + ms_search[2] */
 } rnsm_stats;
 
 /*

@@ -70,6 +70,9 @@ def _setup(L):
     L.orc_prune.restype = C.c_int
     L.orc_prune.argtypes = [C.c_int64, P, C.c_int, P, C.c_int, C.c_int, P, C.c_float, C.c_int,
                             P, P]
+    L.orc_expand_range.restype = C.c_int
+    L.orc_expand_range.argtypes = [C.c_int64, P, P, C.c_int64, P, C.c_int, C.c_int, P, C.c_int,
+                                   C.c_int, C.c_int64, C.c_int64, P]
     L.orc_expand.restype = C.c_int
     L.orc_expand.argtypes = [C.c_int64, P, P, C.c_int64, P, C.c_int, C.c_int, P, C.c_int,
                              C.c_int, P]
@@ -150,13 +153,30 @@ def prune(p, W, X, alpha, R, metric=L2SQ):
     return ids[:c].copy(), ds[:c].copy()
 
 
-def expand(offsets, nbrs, X, k, kplus, metric=L2SQ, base=0):
+def expand(offsets, nbrs, X, k, kplus, metric=L2SQ, base=0, threads=1):
+    """N_k of every vertex ([n x k], -1 padded). With threads > 1 the vertex
+    range is split over that many threads (the C calls release the GIL;
+    every vertex's search is independent)."""
     offsets, nbrs, X = _i64(offsets), _i32(nbrs), _f32(X)
     n = len(offsets) - 1
     nrm = norms(X) if metric == COSINE else None
     out = np.empty((n, k), dtype=np.int32)
-    lib().orc_expand(n, _p(offsets), _p(nbrs), base, _p(X), X.shape[1], metric, _p(nrm), k, kplus,
-                     _p(out))
+    if threads <= 1:
+        lib().orc_expand(n, _p(offsets), _p(nbrs), base, _p(X), X.shape[1], metric, _p(nrm), k,
+                         kplus, _p(out))
+        return out
+    from concurrent.futures import ThreadPoolExecutor
+    step = (n + 4 * threads - 1) // (4 * threads)
+    ranges = [(v, min(n, v + step)) for v in range(0, n, step)]
+
+    def run(r):
+        rc = lib().orc_expand_range(n, _p(offsets), _p(nbrs), base, _p(X), X.shape[1], metric,
+                                    _p(nrm), k, kplus, r[0], r[1], _p(out))
+        if rc != 0:
+            raise RuntimeError(f"orc_expand_range failed on {r}")
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, ranges))
     return out
 
 

@@ -287,12 +287,12 @@ int orc_prune(int64_t p, const int32_t* W, int nW, const float* X, int dim, int 
  */
 static int expand_neighbors(const space_t* S, int64_t n, const int64_t* offsets,
                             const int32_t* nbrs, int64_t base, int k, int kplus,
-                            int32_t* nk_out, int64_t* ndc) {
+                            int32_t* nk_out, int64_t* ndc, int64_t v0, int64_t v1) {
     visited_t vis;
     if (!visited_init(&vis, n)) return -1;
     int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)kplus);
     double* ds = (double*)malloc(sizeof(double) * (size_t)kplus);
-    for (int64_t v = 0; v < n; ++v) {
+    for (int64_t v = v0; v < v1; ++v) {
         int32_t seed = (int32_t)v;
         const float* q = S->X + (base + v) * S->dim;
         double qn = S->norms ? S->norms[base + v] : 1.0;
@@ -313,7 +313,17 @@ int orc_expand(int64_t n, const int64_t* offsets, const int32_t* nbrs, int64_t b
                const float* X, int dim, int metric, const double* norms, int k, int kplus,
                int32_t* nk_out) {
     space_t S = {X, dim, metric, norms};
-    return expand_neighbors(&S, n, offsets, nbrs, base, k, kplus, nk_out, NULL);
+    return expand_neighbors(&S, n, offsets, nbrs, base, k, kplus, nk_out, NULL, 0, n);
+}
+
+/* rows v0..v1-1 of N_k only (independent per vertex: callers may run ranges
+   on separate threads; nk_out is still indexed by vertex) */
+int orc_expand_range(int64_t n, const int64_t* offsets, const int32_t* nbrs, int64_t base,
+                     const float* X, int dim, int metric, const double* norms, int k, int kplus,
+                     int64_t v0, int64_t v1, int32_t* nk_out) {
+    space_t S = {X, dim, metric, norms};
+    if (v0 < 0 || v1 > n || v0 > v1) return -1;
+    return expand_neighbors(&S, n, offsets, nbrs, base, k, kplus, nk_out, NULL, v0, v1);
 }
 
 /* R_k(x) = { y : x in N_k(y) }, each list in ascending id order. */
@@ -792,7 +802,7 @@ int orc_merge(int m, const int64_t* sizes, const int64_t* offsets_cat, const int
         piv_of[si] = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->n > 0 ? s->n : 1));
         piv_ord[si] = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->n > 0 ? s->n : 1));
         if (expand_neighbors(&S, s->n, s->offsets, s->nbrs, s->base, P->k, P->kplus, nk,
-                             &g_ndc_expand) != 0)
+                             &g_ndc_expand, 0, s->n) != 0)
             rc = -4;
         orc_invert(s->n, nk, P->k, rko, rki);
         if (P->all_pivots) {

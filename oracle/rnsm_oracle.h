@@ -43,6 +43,9 @@ int orc_prune(int64_t p, const int32_t* W, int nW, const float* X, int dim, int 
 int orc_expand(int64_t n, const int64_t* offsets, const int32_t* nbrs, int64_t base,
                const float* X, int dim, int metric, const double* norms, int k, int kplus,
                int32_t* nk_out);
+int orc_expand_range(int64_t n, const int64_t* offsets, const int32_t* nbrs, int64_t base,
+                     const float* X, int dim, int metric, const double* norms, int k, int kplus,
+                     int64_t v0, int64_t v1, int32_t* nk_out);
 int orc_invert(int64_t n, const int32_t* nk, int k, int64_t* rk_off, int32_t* rk_ids);
 int orc_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivot_of,
                int32_t* order, int64_t* n_piv);

@@ -59,7 +59,8 @@ class Stats(C.Structure):
                 ("queries", C.c_int64 * 3), ("ndc", C.c_int64 * 3), ("expansions", C.c_int64 * 3),
                 ("adjacency", C.c_int64 * 3), ("launches", C.c_int64 * 3), ("bytes", C.c_double * 3),
                 ("hash_evictions", C.c_int64), ("row_bytes", C.c_int32),
-                ("exact_visited", C.c_int32), ("prune_path", C.c_int32)]
+                ("exact_visited", C.c_int32), ("prune_path", C.c_int32),
+                ("ms_search_span", C.c_double)]
 
 
 def lib():

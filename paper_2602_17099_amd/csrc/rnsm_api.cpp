@@ -445,6 +445,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     std::vector<int64_t> cached_np(m, 0), cached_nf(m, 0);
     std::vector<std::array<int, 3>> ev_exp;
     std::vector<std::array<int, 4>> ev_chunk;
+    std::vector<std::array<int, 2>> ev_span;  // first / last chunk of each operation
     std::vector<std::array<int, 2>> ev_prune;
     int64_t* h_nrev;
     HS(h_nrev, "h_nrev", sizeof(int64_t) * ops.size());
@@ -614,6 +615,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             pa = np;
             fa = nf;
         };
+        const size_t chunk0 = ev_chunk.size();
         const auto tg = std::chrono::steady_clock::now();
         int64_t np = 0, nf = 0;
         if (p->flags & RNSM_FLAG_ALL_PIVOTS) {
@@ -642,6 +644,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             emit(np, nf);
         }
         ms_plan += ms_since(tg);
+        if (!ev_chunk.empty() && ev_chunk.size() > chunk0)
+            ev_span.push_back({ev_chunk[chunk0][0], ev_chunk.back()[3]});
         if (cerr != hipSuccess) {
             (void)hipStreamSynchronize(sd);
             return fail(cerr == hipErrorOutOfMemory ? RNSM_ENOMEM : RNSM_EDEVICE,
@@ -770,6 +774,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         g_stats.ms_search[2] += E.between(ce[2], ce[3]);
     }
     for (auto& pe : ev_prune) ms_prune += E.between(pe[0], pe[1]);
+    for (auto& sp : ev_span) g_stats.ms_search_span += E.between(sp[0], sp[1]);
     for (size_t oi = 0; oi < ops.size(); ++oi) g_stats.n_reverse_edges += h_nrev[oi];
     if (herr & 1) return fail(RNSM_EINTERNAL, "rnsm_merge: a search exceeded its iteration bound");
     if (herr & 2) return fail(RNSM_EINTERNAL, "rnsm_merge: prune candidate list over capacity");

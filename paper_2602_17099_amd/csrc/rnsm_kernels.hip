@@ -1230,18 +1230,29 @@ __global__ void k_copy_rows(const int32_t* rows_a, const int32_t* deg_a, const f
 // value summary of X for the choice of the prune arithmetic: out[0] stays 1
 // while every value is an integer, out[1] / out[2] are the order-preserving
 // bits (fkey) of the minimum / maximum
-__global__ void k_value_range(const float* X, int64_t total, unsigned* out) {
+__device__ __forceinline__ void value_acc(float x, bool& frac, unsigned& lo, unsigned& hi) {
+    frac |= !(x == floorf(x));
+    const unsigned k = fkey(x);
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+}
+
+// total4 float4 values (16-byte loads), then the total % 4 tail
+__global__ __launch_bounds__(256) void k_value_range(const float* X, int64_t total, unsigned* out) {
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t total4 = total >> 2;
     bool frac = false;
     unsigned lo = ~0u, hi = 0u;
-    for (int64_t t = t0; t < total; t += stride) {
-        const float x = X[t];
-        frac |= !(x == floorf(x));
-        const unsigned k = fkey(x);
-        lo = k < lo ? k : lo;
-        hi = k > hi ? k : hi;
+    const float4* X4 = (const float4*)X;
+    for (int64_t t = t0; t < total4; t += stride) {
+        const float4 x = X4[t];
+        value_acc(x.x, frac, lo, hi);
+        value_acc(x.y, frac, lo, hi);
+        value_acc(x.z, frac, lo, hi);
+        value_acc(x.w, frac, lo, hi);
     }
+    for (int64_t t = 4 * total4 + t0; t < total; t += stride) value_acc(X[t], frac, lo, hi);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         const unsigned l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
@@ -1260,8 +1271,9 @@ hipError_t launch_value_range(const float* X, int64_t total, unsigned* out, hipS
     const unsigned init[3] = {1u, ~0u, 0u};
     hipError_t e = hipMemcpyAsync(out, init, sizeof init, hipMemcpyHostToDevice, st);
     if (e != hipSuccess || total <= 0) return e;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
+    int64_t blocks = (total / 4 + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_value_range, dim3((unsigned)blocks), dim3(256), 0, st, X, total, out);
     return hipGetLastError();
 }

@@ -124,3 +124,44 @@ def random_graph(n: int, deg: int, seed: int, ring: bool = True) -> tuple[np.nda
         nbrs[v] = row
     offsets = np.arange(0, n * deg + 1, deg, dtype=np.int64)
     return offsets, nbrs.reshape(-1)
+
+
+def projection_graph(X: np.ndarray, deg: int, n_proj: int = 8, seed: int = SEED_BASE + 50
+                     ) -> tuple[np.ndarray, np.ndarray]:
+    """Cheap locality-structured graph as CSR (int64 offsets, int32 local ids).
+
+    For each of ``n_proj`` seeded random directions the vertices are ordered
+    by their projection, and every vertex is linked to the
+    ``deg // (2 n_proj)`` vertices on either side of it in that order. A row
+    is the union over directions, ascending ids, without self-loops or
+    duplicates (so its degree is at most ``deg``). Used as an input graph at
+    sizes where building a proximity graph on the CPU would take too long;
+    it computes no distance.
+    """
+    n = X.shape[0]
+    w = max(1, deg // (2 * n_proj))
+    g = rng(seed)
+    cols = []
+    for _ in range(n_proj):
+        d = g.standard_normal(X.shape[1])
+        order = np.argsort(X.astype(np.float64) @ d, kind="stable")
+        pos = np.empty(n, dtype=np.int64)
+        pos[order] = np.arange(n)
+        for o in list(range(-w, 0)) + list(range(1, w + 1)):
+            q = pos + o
+            ok = (q >= 0) & (q < n)
+            c = np.full(n, -1, dtype=np.int64)
+            c[ok] = order[q[ok]]
+            cols.append(c)
+    C = np.sort(np.stack(cols, axis=1), axis=1)
+    dup = np.zeros_like(C, dtype=bool)
+    dup[:, 1:] = C[:, 1:] == C[:, :-1]
+    C[dup] = -1
+    C[C == np.arange(n)[:, None]] = -1
+    C = np.sort(np.where(C < 0, np.iinfo(np.int64).max, C), axis=1)
+    valid = C != np.iinfo(np.int64).max
+    valid[:, deg:] = False
+    cnt = valid.sum(axis=1)
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(cnt, out=offsets[1:])
+    return offsets, C[valid].astype(np.int32)

@@ -422,3 +422,24 @@ def test_builder_entry_and_rows(orc):
 def test_recall_definition(orc):
     assert orc.recall_at_k([[1, 2, 3]], [[1, 2, 4]], k=3) == pytest.approx(2 / 3)
     assert orc.recall_at_k([[5, 6], [1, 2]], [[6, 5], [3, 4]], k=2) == pytest.approx(0.5)
+
+
+def test_expansion_threaded_equals_serial(orc):
+    # the vertex-range form run on several threads writes the same N_k rows
+    X = inputs.mixture_u8(3000, 32, comps=8, seed=91)
+    off, nb = inputs.projection_graph(X, 16, seed=92)
+    a = orc.expand(off, nb, X, 5, 16)
+    b = orc.expand(off, nb, X, 5, 16, threads=4)
+    assert np.array_equal(a, b)
+
+
+def test_projection_graph_is_a_valid_input(orc):
+    # degree <= deg, no self-loop, no duplicate, ids in range (the merge
+    # rejects anything else)
+    X = inputs.mixture_u8(4000, 16, comps=8, seed=93)
+    off, nb = inputs.projection_graph(X, 24, seed=94)
+    deg = np.diff(off)
+    assert off[0] == 0 and deg.max() <= 24 and deg.min() >= 1
+    owner = np.repeat(np.arange(len(X)), deg)
+    assert nb.min() >= 0 and nb.max() < len(X) and not np.any(nb == owner)
+    assert len(np.unique(owner * len(X) + nb)) == len(nb)
