@@ -270,7 +270,7 @@ def main():
 
     bf16 = None
     if not args.no_bf16:
-        Xb = Xd.to(torch.bfloat16)
+        Xb = pkg.convert(Xd, torch.bfloat16)  # library staging conversion (RNE)
         ndc_b = exact_ndc(pkg, subs, Xd, wl, search=Xb)
         dtb, aggb, stb, resb = time_merges(pkg, subs, Xd, wl, args.steps, args.warmup, search=Xb)
         vb = args.steps * stb["n_source_vertices"] / dtb
@@ -278,6 +278,10 @@ def main():
         same = bool(torch.equal(resb[0], off) and torch.equal(resb[1], nb))
         rb = search_roofline(aggb, stb, ndc_b, args.steps)
         bf16 = {"value": vb, "ms_per_step": 1000.0 * dtb / args.steps, "recall_at_10": recb,
+                "phase_ms": {"expansion_search": stb["ms_search"][0],
+                             "search_span": stb["ms_search_span"],
+                             "prune_and_reverse": stb["ms_prune"], "compact": stb["ms_compact"],
+                             "total": stb["ms_total"]},
                 "speedup_vs_fp32": vb / value, "same_graph_as_fp32": same,
                 "search_ms_per_launch": rb["ms_per_launch"], "search_gbs": rb["achieved"],
                 "search_frac": rb["frac"]}

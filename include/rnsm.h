@@ -54,8 +54,8 @@ typedef enum {
 
 typedef enum { RNSM_L2SQ = 0, RNSM_IP = 1, RNSM_COSINE = 2 } rnsm_metric;
 
-/* storage type of the vectors the searches read */
-typedef enum { RNSM_F32 = 0, RNSM_BF16 = 1, RNSM_F16 = 2 } rnsm_dtype;
+/* storage type of the vectors the searches read (RNSM_U8: conversion input only) */
+typedef enum { RNSM_F32 = 0, RNSM_BF16 = 1, RNSM_F16 = 2, RNSM_U8 = 3 } rnsm_dtype;
 
 /* flags of rnsm_params */
 #define RNSM_FLAG_ALL_PIVOTS 1u     /* every source vertex runs a naive search (cross-query merge) */
@@ -234,6 +234,21 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
                              const int32_t* knn, int32_t K, int32_t R, float alpha,
                              int32_t reverse, float alpha_rev, int64_t* out_offsets,
                              int32_t* out_nbrs, int32_t* out_entry, void* stream);
+
+/*
+ * Staging conversion of vectors on the device (the inputs of the merge: the
+ * 16-bit search copy of float32 rows, or float32 / float16 rows from uint8
+ * data). count elements from src (src_type) to dst (dst_type), both device
+ * pointers, caller-owned, not overlapping. Supported:
+ *   F32 -> BF16, F32 -> F16: round to nearest, ties to even (the rounding of
+ *        the IEEE 754 conversions); NaN stays NaN (quiet), infinities and
+ *        values past the largest finite value become infinities;
+ *   U8 -> F16, U8 -> F32, U8 -> BF16: exact (every 0..255 is representable).
+ * Asynchronous on `stream` (NULL: the null stream). RNSM_EINVAL for NULL
+ * pointers with count > 0, count < 0 or an unsupported pair.
+ */
+rnsm_status rnsm_convert(const void* src, rnsm_dtype src_type, void* dst, rnsm_dtype dst_type,
+                         int64_t count, void* stream);
 
 /* Stats of the last rnsm_merge on the calling thread. */
 rnsm_status rnsm_get_stats(rnsm_stats* out);

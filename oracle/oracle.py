@@ -391,3 +391,35 @@ def recall_at_k(found, truth, k=10):
     for f, t in zip(found, truth):
         tot += len(set(int(v) for v in f[:k] if v >= 0) & set(int(v) for v in t[:k]))
     return tot / (k * len(found))
+
+
+def to_bf16_bits(x):
+    """float32 -> bfloat16 bit patterns (uint16) by the definition of round to
+    nearest, ties to even: of the two bfloat16 values that bracket |x| (x
+    with its low 16 bits cleared, and that value plus one bfloat16 ulp, the
+    ulp taken past the largest finite value too), take the nearer in exact
+    float64 arithmetic, on a tie the one whose last bit is 0. A value nearer
+    2^128 than the largest finite bfloat16 becomes infinity; NaN gives a NaN
+    pattern (0x7fc0 with the sign)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    sign = (u >> 31) & 1
+    lo_mag = (u & 0x7FFFFFFF) & 0x7FFF0000
+    lo_val = lo_mag.astype(np.uint32).view(np.float32).astype(np.float64)
+    e = (lo_mag >> 23) & 0xFF
+    ulp = np.where(e == 0, 2.0 ** -133, np.exp2(e.astype(np.float64) - 134.0))
+    with np.errstate(invalid="ignore"):
+        xv = np.abs(x.astype(np.float64))
+        d_lo = xv - lo_val
+        d_hi = (lo_val + ulp) - xv
+        lo16 = lo_mag >> 16
+        up = (d_hi < d_lo) | ((d_hi == d_lo) & ((lo16 & 1) == 1))
+    r = (lo16 + up.astype(np.uint64)) | (sign << 15)
+    r = np.where(np.isnan(x), 0x7FC0 | (sign << 15), r)
+    return r.astype(np.uint16)
+
+
+def bf16_bits_to_f32(b):
+    """bfloat16 bit patterns -> float32 values (exact)."""
+    b = np.ascontiguousarray(b, dtype=np.uint16)
+    return (b.astype(np.uint32) << 16).view(np.float32)

@@ -18,7 +18,7 @@ FLAG_ALL_PIVOTS = 1
 FLAG_CENTROID_COSTS = 2
 
 SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_search", "rnsm_build_graph",
-           "rnsm_get_stats", "rnsm_last_error"]
+           "rnsm_convert", "rnsm_get_stats", "rnsm_last_error"]
 
 _lib = None
 
@@ -84,6 +84,8 @@ def lib():
         L.rnsm_build_graph.restype = C.c_int
         L.rnsm_build_graph.argtypes = [C.c_int64, P, C.c_int32, C.c_int, P, C.c_int32, C.c_int32,
                                        C.c_float, C.c_int32, C.c_float, P, P, P, P]
+        L.rnsm_convert.restype = C.c_int
+        L.rnsm_convert.argtypes = [P, C.c_int, P, C.c_int, C.c_int64, P]
         L.rnsm_get_stats.restype = C.c_int
         L.rnsm_get_stats.argtypes = [P]
         L.rnsm_last_error.restype = C.c_char_p
@@ -233,3 +235,20 @@ def build_graph(X, knn, R, alpha=1.0, reverse=False, alpha_rev=1.2, metric=L2SQ,
                                   C.c_void_p(nb.data_ptr()), C.byref(entry), _stream(stream)))
     ne = int(off[-1].item())
     return off, nb[:ne].clone(), entry.value
+
+
+_DT = {"float32": 0, "bfloat16": 1, "float16": 2, "uint8": 3}
+
+
+def convert(src, dtype, stream=None):
+    """Device conversion (rnsm_convert) of a contiguous float32 or uint8
+    tensor to `dtype` (torch.bfloat16, torch.float16 or torch.float32);
+    returns a new tensor of the same shape."""
+    import torch
+    assert src.is_cuda and src.is_contiguous()
+    out = torch.empty(src.shape, dtype=dtype, device=src.device)
+    st = _DT[str(src.dtype).replace("torch.", "")]
+    dt = _DT[str(dtype).replace("torch.", "")]
+    _check(lib().rnsm_convert(C.c_void_p(src.data_ptr()), st, C.c_void_p(out.data_ptr()), dt,
+                              src.numel(), _stream(stream)))
+    return out

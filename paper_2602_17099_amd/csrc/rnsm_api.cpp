@@ -209,22 +209,14 @@ struct Events {
     }
 };
 
-// Prune arithmetic for float32 rows X (n x dim): the bfloat16 MFMA Gram
-// when the dimension fits it; exact products (mode 1) when every value is an
-// integer of magnitude at most 256 (exact in bfloat16) and every Gram and
-// squared-norm sum stays below 2^24; the hi/lo split (mode 3) otherwise; the
-// float32 walk (mode 0) for other dimensions. RNSM_PRUNE=walk|split forces
-// mode 0 / 3 where allowed.
-hipError_t choose_prune(const float* X, int64_t n, int dim, int R, unsigned* scratch3,
-                        hipStream_t st, int* mode) {
-    *mode = 0;
-    const char* env = getenv("RNSM_PRUNE");
-    if (env && !strcmp(env, "walk")) return hipSuccess;
-    if (!prune_mfma_supported(dim) || R > 64) return hipSuccess;
-    if (env && !strcmp(env, "split")) {
-        *mode = 3;
-        return hipSuccess;
-    }
+// Value summary of float32 rows X (n x dim): whether every value is an
+// integer, the largest magnitude and the spread (max - min).
+struct ValueInfo {
+    bool integral = false;
+    double bound = INFINITY, range = INFINITY;
+};
+hipError_t value_info(const float* X, int64_t n, int dim, unsigned* scratch3, hipStream_t st,
+                      ValueInfo* out) {
     hipError_t e = launch_value_range(X, n * dim, scratch3, st);
     if (e != hipSuccess) return e;
     unsigned h[3];
@@ -233,11 +225,34 @@ hipError_t choose_prune(const float* X, int64_t n, int dim, int R, unsigned* scr
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
     const double lo = key_to_float(h[1]), hi = key_to_float(h[2]);
-    const double bound = std::max(std::fabs(lo), std::fabs(hi));
-    const bool exact = h[0] == 1u && std::isfinite(bound) && bound <= 256.0 &&
-                       (double)dim * bound * bound < 16777216.0;
-    *mode = exact ? 1 : 3;
+    out->integral = h[0] == 1u;
+    out->bound = std::max(std::fabs(lo), std::fabs(hi));
+    out->range = hi - lo;
+    if (!std::isfinite(out->bound)) out->integral = false;
     return hipSuccess;
+}
+
+// Integer rows of magnitude <= maxmag (exact in a 16-bit float type with
+// that many integers) whose distance sums are all exact in float32: every
+// inner-product partial sum (dim * bound^2) and every squared-L2 partial sum
+// (dim * range^2) below 2^24. Then every distance is the same number in any
+// summation order, whichever copy it is computed from.
+bool int_exact(const ValueInfo& v, int dim, double maxmag) {
+    const double lim = 16777216.0;
+    return v.integral && v.bound <= maxmag && (double)dim * v.bound * v.bound < lim &&
+           (double)dim * v.range * v.range < lim;
+}
+
+// Prune arithmetic: the bfloat16 MFMA Gram when the dimension fits it, with
+// exact products (mode 1) on rows exact in bfloat16 with exact sums, the
+// hi/lo split (mode 3) otherwise; the float32 walk (mode 0) for other
+// dimensions. RNSM_PRUNE=walk|split forces mode 0 / 3 where allowed.
+int choose_prune(const ValueInfo& v, int dim, int R) {
+    const char* env = getenv("RNSM_PRUNE");
+    if (env && !strcmp(env, "walk")) return 0;
+    if (!prune_mfma_supported(dim) || R > 64) return 0;
+    if (env && !strcmp(env, "split")) return 3;
+    return int_exact(v, dim, 256.0) ? 1 : 3;
 }
 
 hipError_t run_prune(const PruneArgs& a, int mode, hipStream_t st) {
@@ -250,6 +265,21 @@ hipError_t run_prune(const PruneArgs& a, int mode, hipStream_t st) {
 extern "C" {
 
 const char* rnsm_last_error(void) { return g_err.c_str(); }
+
+rnsm_status rnsm_convert(const void* src, rnsm_dtype src_type, void* dst, rnsm_dtype dst_type,
+                         int64_t count, void* stream) {
+    g_err.clear();
+    if (count < 0) return fail(RNSM_EINVAL, "rnsm_convert: count < 0");
+    if (count > 0 && (!src || !dst)) return fail(RNSM_EINVAL, "rnsm_convert: NULL pointer");
+    const bool ok = (src_type == RNSM_F32 && (dst_type == RNSM_BF16 || dst_type == RNSM_F16)) ||
+                    (src_type == RNSM_U8 &&
+                     (dst_type == RNSM_F16 || dst_type == RNSM_F32 || dst_type == RNSM_BF16));
+    if (!ok)
+        return fail(RNSM_EINVAL, "rnsm_convert: unsupported conversion %d -> %d", (int)src_type,
+                    (int)dst_type);
+    HIPCHK(launch_convert(src, (int)src_type, dst, (int)dst_type, count, (hipStream_t)stream));
+    return RNSM_OK;
+}
 
 rnsm_status rnsm_get_stats(rnsm_stats* out) {
     if (!out) return fail(RNSM_EINVAL, "rnsm_get_stats: NULL");
@@ -374,12 +404,18 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     WS(rdist, "rdist", sizeof(float) * N * R);
     WS(cnt, "counters", sizeof(u64) * 3 * CNT_SLOTS * CNT_N);
     WS(errf, "errf", sizeof(int));
-    int pmode = 0;
+    ValueInfo vinfo;
     {
         unsigned* vr;
         WS(vr, "value_range", sizeof(unsigned) * 3);
-        HIPCHK(choose_prune(vecs->f32, N, vecs->dim, R, vr, st, &pmode));
+        HIPCHK(value_info(vecs->f32, N, vecs->dim, vr, st, &vinfo));
     }
+    const int pmode = choose_prune(vinfo, vecs->dim, R);
+    // search distances usable as prune keys: a float32 copy computes them
+    // with the prune's own lane layout and order; a 16-bit copy only when
+    // every distance is exact (integers exact in that type, exact sums)
+    const bool search_d_exact =
+        vi.tt == 0 || int_exact(vinfo, vecs->dim, vi.tt == 1 ? 256.0 : 2048.0);
     HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * 3 * CNT_SLOTS * CNT_N, st));
     HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
     if (p->metric == RNSM_COSINE) {
@@ -690,9 +726,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         q.rows_d = rdist;
         q.extra_mode = 1;
         q.extra_ids = res;
-        // a float32 search copy gives exactly the distances the prune would
-        // compute (same rows, same lane layout and order); a 16-bit copy does not
-        q.extra_d = vi.tt == 0 ? res_d : nullptr;
+        q.extra_d = search_d_exact ? res_d : nullptr;
         q.extra_stride = RES;
         q.extra_cnt = RES;
         q.extra_index_base = bases[s];
@@ -930,12 +964,13 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
     WS(deg1, "b_deg1", sizeof(int32_t) * n);
     WS(d1, "b_d1", sizeof(float) * n * R);
     WS(errf, "b_err", sizeof(int));
-    int pmode = 0;
+    ValueInfo vinfo;
     {
         unsigned* vr;
         WS(vr, "value_range", sizeof(unsigned) * 3);
-        HIPCHK(choose_prune(X, n, dim, R, vr, st, &pmode));
+        HIPCHK(value_info(X, n, dim, vr, st, &vinfo));
     }
+    const int pmode = choose_prune(vinfo, dim, R);
     HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
     if (metric == RNSM_COSINE) {
         WS(norms, "b_norms", sizeof(float) * n);

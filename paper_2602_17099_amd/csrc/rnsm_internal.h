@@ -105,6 +105,9 @@ hipError_t launch_prune_mfma(const PruneArgs& a, int nt, hipStream_t st);
 // bits of min / max (key_to_float gives the value back)
 hipError_t launch_value_range(const float* X, int64_t total, unsigned* out, hipStream_t st);
 float key_to_float(unsigned k);
+// src_type 0: float32, 3: uint8; dst_type 0: float32, 1: bfloat16, 2: float16
+hipError_t launch_convert(const void* src, int src_type, void* dst, int dst_type, int64_t count,
+                          hipStream_t st);
 hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* off, int64_t* tmp_blocks,
                        hipStream_t st);
 size_t scan_tmp_elems(int64_t n);

@@ -18,6 +18,7 @@
 //    which stay in registers.
 //  - reverse-edge count/scatter, reverse k-NN inversion, scans, compaction,
 //    input validation and the builder's entry point.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -1283,6 +1284,50 @@ float key_to_float(unsigned k) {
     float f;
     memcpy(&f, &u, sizeof f);
     return f;
+}
+
+// ------------------------------------------------------------ conversion
+
+// float32 -> bfloat16 / float16 bits, round to nearest, ties to even
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float x) {
+    const unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return (unsigned short)((u >> 16) | 0x0040u);  // NaN stays a (quiet) NaN
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ unsigned short f32_to_f16_rne(float x) {
+    return __half_as_ushort(__float2half_rn(x));
+}
+
+// count elements, 4 per thread (src and dst are read / written in 4-element
+// groups where the count allows)
+__global__ void k_convert(const void* src, int st, void* dst, int dt, int64_t count) {
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (t >= count) return;
+    const int m = count - t < 4 ? (int)(count - t) : 4;
+    float v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (e >= m) { v[e] = 0.0f; continue; }
+        v[e] = st == 0 ? ((const float*)src)[t + e] : (float)((const unsigned char*)src)[t + e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (e >= m) continue;
+        if (dt == 0) ((float*)dst)[t + e] = v[e];
+        else if (dt == 1) ((unsigned short*)dst)[t + e] = f32_to_bf16_rne(v[e]);
+        else ((unsigned short*)dst)[t + e] = f32_to_f16_rne(v[e]);
+    }
+}
+
+hipError_t launch_convert(const void* src, int src_type, void* dst, int dst_type, int64_t count,
+                          hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int s = src_type == 0 ? 0 : 1;  // 0: float32, 1: uint8
+    const int64_t threads = (count + 3) / 4;
+    hipLaunchKernelGGL(k_convert, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, src, s,
+                       dst, dst_type, count);
+    return hipGetLastError();
 }
 
 // builder entry point: vertex closest to the centroid

@@ -80,3 +80,16 @@ def test_mos_plan_rejects(pkg):
         pkg.mos_plan([10, 20], 2, 1)
     with pytest.raises(pkg.RnsmError):
         pkg.mos_plan([10, 0], 2, 2)
+
+
+def test_convert_rejects_on_host(pkg):
+    # argument errors come back before any device work
+    L = pkg.lib()
+    buf = C.create_string_buffer(64)
+    p = C.cast(buf, C.c_void_p)
+    assert L.rnsm_convert(p, 1, p, 0, 4, None) == 1          # bf16 -> f32: unsupported
+    assert L.rnsm_convert(p, 3, p, 3, 4, None) == 1          # u8 -> u8
+    assert L.rnsm_convert(None, 0, p, 1, 4, None) == 1       # NULL source
+    assert L.rnsm_convert(p, 0, p, 1, -1, None) == 1         # negative count
+    assert "unsupported" in pkg.last_error() or "count" in pkg.last_error()
+    assert L.rnsm_convert(None, 0, None, 1, 0, None) == 0    # nothing to do

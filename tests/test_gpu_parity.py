@@ -297,14 +297,17 @@ def test_merge_prune_shapes_bit_exact(dev, orc, pkg, monkeypatch, dim, R, L, mod
     _assert_same_merge(got, ref)
 
 
-def test_merge_medium_bf16_search_bit_exact(dev, orc, pkg, medium, medium_ref):
-    # 0..255 integers are exact in bfloat16: the reduced-precision search
-    # reads different bytes but must reach the same graph
+@pytest.mark.parametrize("dtype", ["bfloat16", "float16"])
+def test_merge_medium_16bit_search_bit_exact(dev, orc, pkg, medium, medium_ref, dtype):
+    # 0..255 integers are exact in bfloat16 and float16: the reduced-precision
+    # search reads different bytes but must reach the same graph (its
+    # distances are exact, so the prune reuses them)
     import torch
     X, subs = medium
     ref = medium_ref
     Xd = _t(X, dev)
-    got = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2, search=Xd.to(torch.bfloat16))
+    got = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2,
+                    search=Xd.to(getattr(torch, dtype)))
     _assert_same_merge(got, ref)
 
 
@@ -385,3 +388,37 @@ def test_merge_rejects_malformed_graphs(dev, orc, pkg, kind, msg):
     with pytest.raises(pkg.RnsmError) as ei:
         pkg.merge(_dsubs(subs, dev), _t(X, dev), R=R, L=16, alpha=1.2)
     assert ei.value.status == 1 and msg in str(ei.value)
+
+
+# ------------------------------------------------------ staging conversion
+
+def test_convert_float32_to_16bit(dev, orc, pkg):
+    # bfloat16 against the oracle's round-to-nearest-even definition, float16
+    # against numpy's IEEE conversion; exact ties, subnormals, overflow,
+    # infinities, NaN and a ragged count (not a multiple of 4)
+    import torch
+    g = inputs.rng(901)
+    x = (g.standard_normal(100003) * np.exp2(g.integers(-150, 130, 100003))).astype(np.float32)
+    ties = (g.integers(0, 1 << 16, 4000).astype(np.uint32) << 16 | 0x8000).view(np.float32)
+    special = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 3.4028235e38, 65504.0, 65520.0,
+                        6e-8, 1e-45, -1e-40, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8], dtype=np.float32)
+    x = np.concatenate([x, ties, special])
+    xd = _t(x, dev)
+    b = pkg.convert(xd, torch.bfloat16).view(torch.int16).cpu().numpy().view(np.uint16)
+    want = orc.to_bf16_bits(x)
+    nan = np.isnan(x)
+    assert np.array_equal(b[~nan], want[~nan])
+    assert np.all(np.isnan(orc.bf16_bits_to_f32(b[nan])))
+    h = pkg.convert(xd, torch.float16).view(torch.int16).cpu().numpy().view(np.uint16)
+    with np.errstate(over="ignore"):
+        hw = x.astype(np.float16).view(np.uint16)
+    assert np.array_equal(h[~nan], hw[~nan])
+    assert np.all(np.isnan(h[nan].view(np.float16)))
+
+
+@pytest.mark.parametrize("dtype", ["float16", "bfloat16", "float32"])
+def test_convert_uint8_exact(dev, pkg, dtype):
+    import torch
+    u = inputs.rng(902).integers(0, 256, 77777).astype(np.uint8)
+    got = pkg.convert(_t(u, dev), getattr(torch, dtype)).float().cpu().numpy()
+    assert np.array_equal(got, u.astype(np.float32))

@@ -443,3 +443,37 @@ def test_projection_graph_is_a_valid_input(orc):
     owner = np.repeat(np.arange(len(X)), deg)
     assert nb.min() >= 0 and nb.max() < len(X) and not np.any(nb == owner)
     assert len(np.unique(owner * len(X) + nb)) == len(nb)
+
+
+# ------------------------------------------------------ staging conversion
+
+def test_bf16_rounding_hand_values(orc):
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: ties to even (0x3f80);
+    # 1 + 3 * 2^-8 is halfway between 0x3f81 and 0x3f82: even is 0x3f82
+    x = np.array([1.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -8 + 2.0 ** -20, -2.0,
+                  0.0, -0.0, np.inf, -np.inf, 3.4028235e38, 3.3895314e38], dtype=np.float32)
+    want = [0x3F80, 0x3F80, 0x3F82, 0x3F81, 0xC000, 0x0000, 0x8000, 0x7F80, 0xFF80, 0x7F80, 0x7F7F]
+    assert orc.to_bf16_bits(x).tolist() == want
+    assert np.isnan(orc.bf16_bits_to_f32(orc.to_bf16_bits(np.array([np.nan], np.float32))))[0]
+
+
+def test_bf16_rounding_is_nearest(orc):
+    # brute force: no bfloat16 value is nearer than the chosen one, and among
+    # equally near ones the chosen has an even last bit
+    g = inputs.rng(95)
+    x = (g.standard_normal(20000) * np.exp2(g.integers(-140, 120, 20000))).astype(np.float32)
+    x = np.concatenate([x, (g.integers(0, 1 << 16, 2000) << 16 | 0x8000).astype(np.uint32)
+                        .view(np.float32)])  # exact ties
+    x = x[np.isfinite(x)]
+    b = orc.to_bf16_bits(x).astype(np.int64)
+    xv = x.astype(np.float64)
+    for dlt in (-1, 1):
+        nb = np.clip(b + dlt, 0, 0xFFFF)
+        same_sign = (nb >> 15) == (b >> 15)
+        v0 = orc.bf16_bits_to_f32(b).astype(np.float64)
+        v1 = orc.bf16_bits_to_f32(nb).astype(np.float64)
+        ok = np.isfinite(v1) & np.isfinite(v0) & same_sign
+        d0, d1 = np.abs(xv - v0), np.abs(xv - v1)
+        assert np.all(d0[ok] <= d1[ok])
+        tie = ok & (d0 == d1)
+        assert np.all((b[tie] & 1) == 0)
