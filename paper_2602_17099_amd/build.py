@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "librnsm.so")
 SOURCES = ["rnsm_kernels.hip", "rnsm_api.cpp", "rnsm_plan.cpp"]
 ARCH = os.environ.get("RNSM_OFFLOAD_ARCH", "gfx950")
 # packed FP32 instructions are kept out of every kernel
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "-pthread", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 

@@ -10,6 +10,9 @@
 #include <chrono>
 #include <cmath>
 #include <map>
+#include <thread>
+#include <deque>
+#include <condition_variable>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -485,6 +488,10 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     std::vector<std::array<int, 2>> ev_prune;
     int64_t* h_nrev;
     HS(h_nrev, "h_nrev", sizeof(int64_t) * ops.size());
+    const bool use_bfs = !getenv("RNSM_NO_BFS_ORDER");
+    std::vector<int32_t> rank, fbeg, fcnt;
+    std::vector<uint64_t> rbits;
+    int32_t* h_bfs = nullptr;
     for (size_t oi = 0; oi < ops.size(); ++oi) {
         const int s = ops[oi].first, t = ops[oi].second;
         const int64_t ns = sizes[s], nt = sizes[t];
@@ -495,10 +502,17 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         WS(d_folp, "follower_pivot", sizeof(int32_t) * ns);
         WS(res, "res", sizeof(int32_t) * ns * RES);
         WS(res_d, "res_d", sizeof(float) * ns * RES);
+        // selection lists (the greedy's output) and launch lists (the same
+        // groups, each chunk's groups ordered by the pivot's breadth-first rank)
+        int32_t* h_launch;
         HS(h_lists, "h_lists", sizeof(int32_t) * 3 * ns);
+        HS(h_launch, "h_launch", sizeof(int32_t) * 3 * ns);
         int32_t* h_piv = h_lists;
         int32_t* h_fol = h_lists + ns;
         int32_t* h_folp = h_lists + 2 * ns;
+        int32_t* h_lp = h_launch;
+        int32_t* h_lf = h_launch + ns;
+        int32_t* h_lfp = h_launch + 2 * ns;
         int64_t *h_off = nullptr;
         int32_t* h_ids = nullptr;
         const bool fresh = cached[s].empty() && !(p->flags & RNSM_FLAG_ALL_PIVOTS);
@@ -510,6 +524,23 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             WS(rk_off, "rk_off", sizeof(int64_t) * (ns + 1));
             WS(rk_ids, "rk_ids", sizeof(int32_t) * ns * k);
             WS(stmp, "scan_tmp", sizeof(int64_t) * scan_tmp_elems(ns));
+            // breadth-first order of the source graph from its entry: the
+            // expansion runs its queries in that order, and pivot groups are
+            // launched by the rank of their pivot in it (locality in L2 only)
+            int32_t *bfs_order = nullptr, *bfs_level;
+            int ev_order = -1;
+            if (use_bfs) {
+                unsigned *bfs_tail, *h_tail;
+                WS(bfs_order, "bfs_order", sizeof(int32_t) * ns);
+                WS(bfs_level, "bfs_level", sizeof(int32_t) * ns);
+                WS(bfs_tail, "bfs_tail", sizeof(unsigned));
+                HS(h_tail, "h_bfs_tail", sizeof(unsigned));
+                HS(h_bfs, "h_bfs_order", sizeof(int32_t) * ns);
+                HIPCHK(launch_bfs_order(padj + bases[s] * R, R, ns, graphs[s].entry, bfs_level,
+                                        bfs_order, bfs_tail, h_tail, st));
+                HIPCHK(hipMemcpyAsync(h_bfs, bfs_order, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+                HIPCHK(E.record(st, &ev_order));
+            }
             std::array<int, 3> ex;
             HIPCHK(E.record(st, &ex[0]));
             SearchArgs a = {};
@@ -522,7 +553,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             a.rp = R;
             a.n = ns;
             a.qvec = a.base;
-            a.qidx = nullptr;
+            a.qidx = bfs_order;
+            a.out_row = bfs_order;
             a.nq = ns;
             a.seed_mode = 1;
             a.metric = p->metric;
@@ -553,6 +585,17 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             HS(h_ids, "h_rk_ids", sizeof(int32_t) * ns * k);
             HIPCHK(hipMemcpyAsync(h_off, rk_off, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, st));
             HIPCHK(hipMemcpyAsync(h_ids, rk_ids, sizeof(int32_t) * ns * k, hipMemcpyDeviceToHost, st));
+            if (use_bfs) {
+                // ranks on the host while the expansion runs
+                HIPCHK(hipEventSynchronize(E.ev[ev_order]));
+                rank.assign(ns, -1);
+                for (int64_t r = 0; r < ns; ++r) {
+                    const int32_t v = h_bfs[r];
+                    if (v < 0 || v >= ns || rank[v] >= 0)
+                        return fail(RNSM_EINTERNAL, "rnsm_merge: breadth-first order is not a permutation");
+                    rank[v] = (int32_t)r;
+                }
+            }
         }
         // also drains the previous operation, whose copies read h_lists
         HIPCHK(hipStreamSynchronize(st));
@@ -613,21 +656,62 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         HIPCHK(E.record(st, &ev_go));
         HIPCHK(hipStreamWaitEvent(sd, E.ev[ev_go], 0));
         int64_t pa = 0, fa = 0;  // list prefixes already handed to the device
+        int64_t n_launch_a = 0, n_launch_b = 0;
         hipError_t cerr = hipSuccess;
+        bool reorder = false;  // set when the lists come from the greedy and ranks exist
+        // launch lists for pivots [pa, np) and followers [fa, nf)
+        auto stage = [&](int64_t np, int64_t nf) {
+            if (!reorder) {
+                memcpy(h_lp + pa, h_piv + pa, sizeof(int32_t) * (np - pa));
+                memcpy(h_lf + fa, h_fol + fa, sizeof(int32_t) * (nf - fa));
+                memcpy(h_lfp + fa, h_folp + fa, sizeof(int32_t) * (nf - fa));
+                return;
+            }
+            // followers of each new pivot: one contiguous run
+            for (int64_t i = pa; i < np; ++i) fcnt[h_piv[i]] = 0;
+            for (int64_t f = fa; f < nf; ++f) {
+                const int32_t pv = h_folp[f];
+                if (fcnt[pv]++ == 0) fbeg[pv] = (int32_t)f;
+            }
+            int64_t lo = INT64_MAX, hi = -1;
+            for (int64_t i = pa; i < np; ++i) {
+                const int64_t r = rank[h_piv[i]];
+                rbits[r >> 6] |= 1ull << (r & 63);
+                lo = std::min(lo, r >> 6);
+                hi = std::max(hi, r >> 6);
+            }
+            int64_t o = pa, fo = fa;
+            for (int64_t w = lo; w <= hi; ++w) {
+                uint64_t b = rbits[w];
+                rbits[w] = 0;
+                while (b) {
+                    const int32_t pv = h_bfs[w * 64 + __builtin_ctzll(b)];
+                    b &= b - 1;
+                    h_lp[o++] = pv;
+                    const int32_t c = fcnt[pv];
+                    if (c) {
+                        memcpy(h_lf + fo, h_fol + fbeg[pv], sizeof(int32_t) * c);
+                        for (int32_t t2 = 0; t2 < c; ++t2) h_lfp[fo + t2] = pv;
+                        fo += c;
+                    }
+                }
+            }
+        };
         auto emit = [&](int64_t np, int64_t nf) {
             if (cerr != hipSuccess) return;
+            stage(np, nf);
             std::array<int, 4> ce;
             auto chk = [&](hipError_t e) {
                 if (e != hipSuccess && cerr == hipSuccess) cerr = e;
                 return e == hipSuccess;
             };
-            if (np > pa && !chk(hipMemcpyAsync(d_piv + pa, h_piv + pa, sizeof(int32_t) * (np - pa),
+            if (np > pa && !chk(hipMemcpyAsync(d_piv + pa, h_lp + pa, sizeof(int32_t) * (np - pa),
                                                hipMemcpyHostToDevice, sd)))
                 return;
             if (nf > fa) {
-                if (!chk(hipMemcpyAsync(d_fol + fa, h_fol + fa, sizeof(int32_t) * (nf - fa),
+                if (!chk(hipMemcpyAsync(d_fol + fa, h_lf + fa, sizeof(int32_t) * (nf - fa),
                                         hipMemcpyHostToDevice, sd)) ||
-                    !chk(hipMemcpyAsync(d_folp + fa, h_folp + fa, sizeof(int32_t) * (nf - fa),
+                    !chk(hipMemcpyAsync(d_folp + fa, h_lfp + fa, sizeof(int32_t) * (nf - fa),
                                         hipMemcpyHostToDevice, sd)))
                     return;
             }
@@ -646,38 +730,79 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             y.nq = nf - fa;
             if (!chk(launch_search(vi.tt, y, shB.wpb, st)) || !chk(E.record(st, &ce[3]))) return;
             ev_chunk.push_back(ce);
-            g_stats.launches[1] += np > pa;
-            g_stats.launches[2] += nf > fa;
+            n_launch_a += np > pa;  // the stats are thread-local: added after the join
+            n_launch_b += nf > fa;
             pa = np;
             fa = nf;
         };
         const size_t chunk0 = ev_chunk.size();
         const auto tg = std::chrono::steady_clock::now();
+        // the greedy (this thread) posts (np, nf) marks; a launcher thread
+        // stages each chunk's groups and queues its copies and searches
+        std::mutex qm;
+        std::condition_variable qcv;
+        std::deque<std::pair<int64_t, int64_t>> qmarks;
+        bool qdone = false;
+        std::thread launcher([&] {
+            if (hipSetDevice(dev) != hipSuccess && cerr == hipSuccess) cerr = hipErrorInvalidDevice;
+            for (;;) {
+                std::pair<int64_t, int64_t> it;
+                {
+                    std::unique_lock<std::mutex> l(qm);
+                    qcv.wait(l, [&] { return !qmarks.empty() || qdone; });
+                    if (qmarks.empty()) return;
+                    it = qmarks.front();
+                    qmarks.pop_front();
+                }
+                emit(it.first, it.second);
+            }
+        });
+        auto post = [&](int64_t a1, int64_t b1) {
+            {
+                std::lock_guard<std::mutex> l(qm);
+                qmarks.emplace_back(a1, b1);
+            }
+            qcv.notify_one();
+        };
         int64_t np = 0, nf = 0;
         if (p->flags & RNSM_FLAG_ALL_PIVOTS) {
             // every vertex is a pivot (no sliding)
             for (int64_t v = 0; v < ns; ++v) h_piv[v] = (int32_t)v;
             np = ns;
-            emit(np, 0);
+            post(np, 0);
         } else if (fresh) {
+            reorder = use_bfs && (int64_t)rank.size() == ns;
+            if (reorder) {
+                fbeg.resize(ns);
+                fcnt.resize(ns);
+                rbits.assign((size_t)((ns + 63) / 64), 0ull);
+            }
             int64_t chunk = std::max<int64_t>(4096, ns / 64);
             if (const char* c = getenv("RNSM_PIVOT_CHUNK")) chunk = std::max(1ll, atoll(c));
             select_pivots(ns, h_off, h_ids, h_piv, h_fol, h_folp, chunk,
-                          [&](int64_t a1, int64_t b1) {
+                          std::max<int64_t>(chunk, ns / 8), [&](int64_t a1, int64_t b1) {
                               np = a1;
                               nf = b1;
-                              emit(a1, b1);
+                              post(a1, b1);
                           });
-            if (last_use[s] > (int)oi) {
-                cached[s].assign(h_lists, h_lists + 3 * ns);
-                cached_np[s] = np;
-                cached_nf[s] = nf;
-            }
         } else {
             memcpy(h_lists, cached[s].data(), sizeof(int32_t) * 3 * ns);
             np = cached_np[s];
             nf = cached_nf[s];
-            emit(np, nf);
+            post(np, nf);
+        }
+        {
+            std::lock_guard<std::mutex> l(qm);
+            qdone = true;
+        }
+        qcv.notify_one();
+        launcher.join();
+        g_stats.launches[1] += n_launch_a;
+        g_stats.launches[2] += n_launch_b;
+        if (fresh && last_use[s] > (int)oi) {
+            cached[s].assign(h_launch, h_launch + 3 * ns);
+            cached_np[s] = np;
+            cached_nf[s] = nf;
         }
         ms_plan += ms_since(tg);
         if (!ev_chunk.empty() && ev_chunk.size() > chunk0)
@@ -697,9 +822,9 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         {
             int64_t o = 0, f = 0;
             for (int64_t i = 0; i < np; ++i) {
-                const int32_t pv = h_piv[i];
+                const int32_t pv = h_lp[i];
                 h_order[o++] = pv;
-                while (f < nf && h_folp[f] == pv) h_order[o++] = h_fol[f++];
+                while (f < nf && h_lfp[f] == pv) h_order[o++] = h_lf[f++];
             }
             if (o != ns || f != nf)
                 return fail(RNSM_EINTERNAL, "rnsm_merge: pivot groups do not cover the source");

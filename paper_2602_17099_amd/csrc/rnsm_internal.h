@@ -131,6 +131,11 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
                         unsigned long long* colsum_i, u64* block_best, int64_t nblocks,
                         hipStream_t st);
 int64_t entry_blocks(int64_t n);
+// breadth-first vertex order of a padded-adjacency graph from root (a
+// processing order only); level: n ints of scratch, tail: one device
+// counter, h_tail: pinned host word; synchronises st once per level
+hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, int32_t* level,
+                            int32_t* order, unsigned* tail, unsigned* h_tail, hipStream_t st);
 
 // lanes per row for rows of nch 16-byte chunks: the smallest power of two G
 // with 4*G >= nch that divides nch, so that every lane holds nch/G <= 4 whole

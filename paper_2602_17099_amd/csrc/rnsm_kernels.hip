@@ -239,16 +239,44 @@ __device__ __forceinline__ int hash_visit(int* tab, int hbits, int v) {
     }
 }
 
+// the query row in the searched copy's layout: float32 values, or the packed
+// 16-bit chunks (consumed two at a time by v_dot2)
 template <int TT, int CPL>
 struct Query {
-    float q[CPL][Elt<TT>::EPC];
+    float q[CPL][TT == 0 ? 4 : 1];
+    uint4 r[TT == 0 ? 1 : CPL];
 };
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 halfx2_t __attribute__((ext_vector_type(2)));
+
+// acc + a.lo * b.lo + a.hi * b.hi over two packed 16-bit values
+template <int TT>
+__device__ __forceinline__ float dot2(unsigned a, unsigned b, float acc) {
+    if constexpr (TT == 1)
+        return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a),
+                                               __builtin_bit_cast(bf16x2_t, b), acc, false);
+    else
+        return __builtin_amdgcn_fdot2(__builtin_bit_cast(halfx2_t, a), __builtin_bit_cast(halfx2_t, b),
+                                      acc, false);
+}
+template <int TT>
+__device__ __forceinline__ float dot2x4(uint4 a, uint4 b, float acc) {
+    acc = dot2<TT>(a.x, b.x, acc);
+    acc = dot2<TT>(a.y, b.y, acc);
+    acc = dot2<TT>(a.z, b.z, acc);
+    return dot2<TT>(a.w, b.w, acc);
+}
 
 __host__ __device__ constexpr int search_lds_words(int hbits) { return (1 << hbits) + 64; }
 
 // evaluate the per-lane candidates v (-1: none): visited filter, distances,
 // beam insertion. Rows are read by groups of G lanes, CPL 16-byte chunks per
 // lane at a stride of G chunks, UNR rows per group per batch.
+// Distances: float32 copies sum (q - x)^2 (or q x) per element; 16-bit
+// copies use v_dot2 on the packed values, squared L2 as |q|^2 + |x|^2 - 2 q.x
+// combined in double (exact whenever the three sums are, e.g. small integers).
+// qn: the query's norm (cosine) or squared norm (squared L2, 16-bit copies).
 template <int TT, int EFS, int CPL, bool EXACT>
 __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS>& B,
                                                    const Query<TT, CPL>& Q, float qn, int* tab,
@@ -284,26 +312,35 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
                 for (int j = 0; j < CPL; ++j) raw[u][j] = *(const uint4*)(rp + j * gstride);
             }
         }
-        float acc[UNR];
+        float acc[UNR], xx[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-            float s = 0.0f;
+            float s = 0.0f, s2 = 0.0f;
+            if constexpr (TT == 0) {
 #pragma unroll
-            for (int j = 0; j < CPL; ++j) {
-                float x[EPC];
-                cvt_chunk<TT>(raw[u][j], x);
-                if (a.metric == 0) {
+                for (int j = 0; j < CPL; ++j) {
+                    float x[EPC];
+                    cvt_chunk<TT>(raw[u][j], x);
+                    if (a.metric == 0) {
 #pragma unroll
-                    for (int t = 0; t < EPC; ++t) {
-                        const float d = Q.q[j][t] - x[t];
-                        s = fmaf(d, d, s);
+                        for (int t = 0; t < EPC; ++t) {
+                            const float d = Q.q[j][t] - x[t];
+                            s = fmaf(d, d, s);
+                        }
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < EPC; ++t) s = fmaf(Q.q[j][t], x[t], s);
                     }
-                } else {
+                }
+            } else {
 #pragma unroll
-                    for (int t = 0; t < EPC; ++t) s = fmaf(Q.q[j][t], x[t], s);
+                for (int j = 0; j < CPL; ++j) {
+                    s = dot2x4<TT>(Q.r[j], raw[u][j], s);
+                    if (a.metric == 0) s2 = dot2x4<TT>(raw[u][j], raw[u][j], s2);
                 }
             }
             acc[u] = group_sum_last(s, G);
+            xx[u] = (TT != 0 && a.metric == 0) ? group_sum_last(s2, G) : 0.0f;
         }
         const u64 worst = beam_worst(B, a.ef);
 #pragma unroll
@@ -312,7 +349,12 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
             if (sub == G - 1 && cid[u] >= 0) {
                 float nb = 1.0f;
                 if (a.metric == 2) nb = a.base_norm[cid[u]];
-                key = make_key(finalize_dist(acc[u], a.metric, qn, nb), cid[u]);
+                float d;
+                if (TT != 0 && a.metric == 0)
+                    d = (float)((double)qn + (double)xx[u] - 2.0 * (double)acc[u]);
+                else
+                    d = finalize_dist(acc[u], a.metric, qn, nb);
+                key = make_key(d, cid[u]);
             }
             u64 mm = __ballot(key < worst);
             while (mm) {
@@ -343,10 +385,23 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     const int sub = lane & (a.G - 1);
     const char* qrow = a.qvec + (int64_t)u * a.row_bytes + sub * 16;
     Query<TT, CPL> Q;
+    float qn = a.metric == 2 ? a.q_norm[u] : 1.0f;
+    if constexpr (TT == 0) {
 #pragma unroll
-    for (int j = 0; j < CPL; ++j)
-        cvt_chunk<TT>(*(const uint4*)(qrow + (int64_t)j * a.G * 16), Q.q[j]);
-    const float qn = a.metric == 2 ? a.q_norm[u] : 1.0f;
+        for (int j = 0; j < CPL; ++j)
+            cvt_chunk<TT>(*(const uint4*)(qrow + (int64_t)j * a.G * 16), Q.q[j]);
+    } else {
+        float s2 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            Q.r[j] = *(const uint4*)(qrow + (int64_t)j * a.G * 16);
+            s2 = dot2x4<TT>(Q.r[j], Q.r[j], s2);
+        }
+        // squared norm of the query (valid in the last lane of each group,
+        // the lanes that form the keys)
+        const float qq = group_sum_last(s2, a.G);
+        if (a.metric == 0) qn = qq;
+    }
 
     Beam<EFS> B;
 #pragma unroll
@@ -1011,6 +1066,57 @@ __global__ void k_pad_adjacency(const int64_t* offs, const int32_t* nbrs, int64_
     out[t] = j < e - b ? nbrs[b + j] : -1;
 }
 
+// Breadth-first order of a graph given as padded adjacency [n x rp] (-1
+// filled) from `root`, used only as a processing order: searches of vertices
+// close in the graph then run in neighbouring wavefronts and share L2. Within
+// a level the order follows atomics and is not deterministic; no result
+// depends on it. order[0..n) receives every vertex once; level[] is scratch.
+__global__ void k_bfs_init(int64_t n, int32_t root, int32_t* level, int32_t* order,
+                           unsigned* tail) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    level[t] = t == root ? 0 : -1;
+    if (t == 0) {
+        order[0] = root;
+        *tail = 1u;
+    }
+}
+
+// frontier order[s, e) at level lvl: one thread per (vertex, slot)
+__global__ void k_bfs_level(const int32_t* padj, int rp, int64_t n, int32_t* order, int64_t s,
+                            int64_t e, int32_t lvl, int32_t* level, unsigned* tail) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool found = false;
+    int32_t w = -1;
+    if (t < (e - s) * rp) {
+        const int32_t u = order[s + t / rp];
+        w = padj[(int64_t)u * rp + (int)(t % rp)];
+        found = w >= 0 && w < n && atomicCAS(&level[w], -1, lvl + 1) == -1;
+    }
+    const u64 m = __ballot(found);
+    if (m == 0ull) return;
+    const int lane = lane_id();
+    unsigned base = 0;
+    const int lead = __ffsll((long long)m) - 1;
+    if (lane == lead) base = atomicAdd(tail, (unsigned)__popcll(m));
+    base = (unsigned)__shfl((int)base, lead);
+    if (found) order[base + __popcll(m & lanemask_lt(lane))] = w;
+}
+
+// vertices no level reached, after the others
+__global__ void k_bfs_rest(int64_t n, const int32_t* level, int32_t* order, unsigned* tail) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool miss = t < n && level[t] == -1;
+    const u64 m = __ballot(miss);
+    if (m == 0ull) return;
+    const int lane = lane_id();
+    unsigned base = 0;
+    const int lead = __ffsll((long long)m) - 1;
+    if (lane == lead) base = atomicAdd(tail, (unsigned)__popcll(m));
+    base = (unsigned)__shfl((int)base, lead);
+    if (miss) order[base + __popcll(m & lanemask_lt(lane))] = (int32_t)t;
+}
+
 // one thread per row slot, so that consecutive threads write consecutive ids
 __global__ void k_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
                             int R, int32_t* rows, int32_t* deg, float* rdist) {
@@ -1429,6 +1535,31 @@ __global__ __launch_bounds__(ENTRY_T) void k_entry_crit(const float* X, int64_t 
 // ---------------------------------------------------------------- launchers
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, int32_t* level,
+                            int32_t* order, unsigned* tail, unsigned* h_tail, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (root < 0 || root >= n) root = 0;
+    hipLaunchKernelGGL(k_bfs_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, root, level, order, tail);
+    hipError_t e = hipGetLastError();
+    int64_t s0 = 0, e0 = 1;
+    for (int32_t lvl = 0; e0 > s0 && e0 < n; ++lvl) {
+        hipLaunchKernelGGL(k_bfs_level, dim3(nblk((e0 - s0) * rp, 256)), dim3(256), 0, st, padj, rp, n,
+                           order, s0, e0, lvl, level, tail);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(h_tail, tail, sizeof(unsigned), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        s0 = e0;
+        e0 = (int64_t)*h_tail;
+    }
+    if (e0 < n) {
+        hipLaunchKernelGGL(k_bfs_rest, dim3(nblk(n, 256)), dim3(256), 0, st, n, level, order, tail);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
 
 hipError_t launch_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t nnz,
                            int R, int* flags, hipStream_t st) {

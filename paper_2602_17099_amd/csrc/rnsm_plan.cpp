@@ -154,7 +154,8 @@ int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int 
 // ascending order; Covered is a bitmap too, so covered vertices of a level
 // are dropped 64 at a time.
 void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivots,
-                   int32_t* followers, int32_t* follower_pivot, int64_t chunk, const Emit& emit) {
+                   int32_t* followers, int32_t* follower_pivot, int64_t chunk, int64_t chunk_max,
+                   const Emit& emit) {
     const int64_t words = (n + 63) / 64;
     std::vector<uint64_t> cov((size_t)words, 0ull);
     int64_t gmax = 0;
@@ -201,7 +202,7 @@ void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int3
                 if (np + nf - sent >= chunk) {
                     emit(np, nf);
                     sent = np + nf;
-                    chunk *= 2;
+                    chunk = std::max(chunk, std::min(2 * chunk, chunk_max));
                 }
             }
         }

@@ -22,11 +22,13 @@ int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int 
 // the pivot of each follower; the order inside an R_k list only changes the
 // order of a pivot's followers, not the pivots or their follower sets.
 // `emit(np, nf)` is called with the running counts each time at least
-// `chunk` vertices (pivots plus followers, doubling after every call) were
-// added since the last call, and once at the end; a caller can start work
-// on every group emitted so far while the selection goes on.
+// `chunk` vertices (pivots plus followers; the chunk doubles after every call
+// up to chunk_max) were added since the last call, and once at the end; a
+// caller can start work on every group emitted so far while the selection
+// goes on.
 using Emit = std::function<void(int64_t np, int64_t nf)>;
 void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivots,
-                   int32_t* followers, int32_t* follower_pivot, int64_t chunk, const Emit& emit);
+                   int32_t* followers, int32_t* follower_pivot, int64_t chunk, int64_t chunk_max,
+                   const Emit& emit);
 
 }  // namespace rnsm
