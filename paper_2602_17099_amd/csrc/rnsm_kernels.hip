@@ -770,6 +770,15 @@ __device__ __forceinline__ unsigned bf16_bits(float x) {
 // remainder lo = bf16(v - hi), so that hi + lo carries about 16 bits
 template <int NT>
 __device__ __forceinline__ void split8(const float* v, uint4& hi, uint4& lo) {
+    if constexpr (NT == 1) {
+        // values exact in bfloat16: the upper halves, two per word
+        auto pk = [](float a, float b) {
+            return (__float_as_uint(b) & 0xffff0000u) | (__float_as_uint(a) >> 16);
+        };
+        hi = make_uint4(pk(v[0], v[1]), pk(v[2], v[3]), pk(v[4], v[5]), pk(v[6], v[7]));
+        lo = make_uint4(0u, 0u, 0u, 0u);
+        return;
+    }
     unsigned h[8], l[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -796,6 +805,19 @@ __device__ __forceinline__ double gram_dist(float g, int metric, float ui, float
     if (metric == 0) return (double)ui + (double)uj - 2.0 * (double)g;
     if (metric == 1) return (double)(1.0f - g);
     return (double)(1.0f - g / (ni * nj));
+}
+
+// largest integer D with alpha * D < d (double products, exact for |D| < 2^29)
+__device__ __forceinline__ int dom_threshold(double alpha, float d) {
+    const double dd = (double)d;
+    if (!(dd < 1.0e18) || !(dd > -1.0e18)) return dd > 0.0 ? 0x7fffffff : -0x7fffffff;
+    double t = floor(dd / alpha);
+    if (!(t < 1.0e9)) t = 1.0e9;
+    if (t < -1.0e9) t = -1.0e9;
+    int ti = (int)t;
+    while (alpha * (double)ti >= dd) --ti;
+    while (alpha * (double)(ti + 1) < dd) ++ti;
+    return ti;
 }
 
 // LDS bytes per wavefront of k_prune_mfma: keys and sorted keys, kept ids,
@@ -917,6 +939,11 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
             sq += __shfl_xor(sq, 32);
             uj = sq;
         }
+        // exact rows, squared L2 or inner product: every d(w, v) is an exact
+        // integer, so alpha * d(w, v) < d(p, v) is d(w, v) <= T (integer)
+        const bool intd = NT == 1 && metric != 2;
+        const int tj = intd ? dom_threshold(alpha, dj) : 0;
+        const int uji = intd && metric == 0 ? (int)uj : 0;
         if (J + 1 < ntiles) load_tile(J + 1, raw);  // next tile's rows in flight
 
         // the tile with itself: pairs (i, j), i = 4 q + r, j = l % 16, i < j
@@ -933,9 +960,16 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ii = 4 * q + r;
-            const float ui = __shfl(uj, ii);
-            const float ni = __shfl(nj, ii);
-            const bool pred = ii < jr && alpha * gram_dist(acc[r], metric, ui, uj, ni, nj) < (double)dj;
+            bool pred;
+            if (intd) {
+                const int g = (int)acc[r];
+                const int dij = metric == 0 ? __shfl(uji, ii) + uji - 2 * g : 1 - g;
+                pred = ii < jr && dij <= tj;
+            } else {
+                const float ui = __shfl(uj, ii);
+                const float ni = __shfl(nj, ii);
+                pred = ii < jr && alpha * gram_dist(acc[r], metric, ui, uj, ni, nj) < (double)dj;
+            }
             bt[r] = __ballot(pred);
         }
         // kept rows of earlier tiles against the tile
@@ -959,8 +993,14 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
                 const int ki = kt * 16 + 4 * q + r;
                 bool pred = false;
                 if (ki < nk0) {
-                    const float nkk = metric == 2 ? a.norms[kept_ids[ki]] : 1.0f;
-                    pred = alpha * gram_dist(ak[r], metric, kept_u[ki], uj, nkk, nj) < (double)dj;
+                    if (intd) {
+                        const int g = (int)ak[r];
+                        const int dkj = metric == 0 ? (int)kept_u[ki] + uji - 2 * g : 1 - g;
+                        pred = dkj <= tj;
+                    } else {
+                        const float nkk = metric == 2 ? a.norms[kept_ids[ki]] : 1.0f;
+                        pred = alpha * gram_dist(ak[r], metric, kept_u[ki], uj, nkk, nj) < (double)dj;
+                    }
                 }
                 bk |= __ballot(pred);
             }
@@ -970,18 +1010,21 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
         unsigned mj = 0;
 #pragma unroll
         for (int ii = 0; ii < 16; ++ii) mj |= (unsigned)((bt[ii & 3] >> (16 * (ii >> 2) + jr)) & 1ull) << ii;
-        // resolve the 16 candidates in order (wavefront-uniform)
+        // resolve the candidates in order (wavefront-uniform). Lanes 0..15
+        // hold candidates 0..15 of the tile. Skipped outright: past the end
+        // (EMPTY keys sort last), the same vertex as the candidate before it
+        // (equal keys are adjacent), dominated by a kept row of an earlier
+        // tile; the rest are tested against this tile's kept candidates.
+        const unsigned valid16 = (unsigned)(__ballot(key != EMPTY_KEY) & 0xffffull);
+        u64 kb = __shfl(key, (jr + 15) & 15);
+        if (jr == 0) kb = prev;
+        const unsigned dup16 = (unsigned)(__ballot(key == kb) & 0xffffull);
+        unsigned cand = valid16 & ~dup16 & ~domk;
         unsigned keptj = 0;
-        bool stop = false;
-        for (int j = 0; j < 16; ++j) {
-            const u64 kj = readlane64(key, j);
-            if (kj == EMPTY_KEY) {  // past the end, or no more valid candidates
-                stop = true;
-                break;
-            }
-            if (kj == prev) continue;  // the same vertex twice in W
-            prev = kj;
-            if ((domk >> j) & 1u) continue;
+        bool stop = valid16 != 0xffffu;
+        while (cand) {
+            const int j = __builtin_ctz(cand);
+            cand &= cand - 1u;
             const unsigned mjj = (unsigned)__builtin_amdgcn_readlane((int)mj, j);
             if (mjj & keptj) continue;
             keptj |= 1u << j;
@@ -990,6 +1033,7 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
                 break;
             }
         }
+        prev = readlane64(key, 15);
         // append the kept candidates (rows, ids, distances, outputs)
         if ((keptj >> jr) & 1u) {
             const int kr = nk + __popc(keptj & ((1u << jr) - 1u));
