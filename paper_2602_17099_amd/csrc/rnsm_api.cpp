@@ -117,20 +117,19 @@ int ilog2_ceil(int64_t x) {
     return b;
 }
 
-// LDS visited-table size and wavefronts per block for a search of beam ef
-// over rows of degree <= maxdeg. RNSM_HASH_BITS / RNSM_WPB override.
 // LDS visited-table size, wavefronts per block and table mode of a search of
-// beam ef over rows of degree <= maxdeg. The fast table is lossy (a forgotten
-// vertex is evaluated again and dropped by key), so it is sized for
-// occupancy rather than for the whole visited set: 2048 slots measured best
-// for the L=64, R=32 searches. RNSM_EXACT_VISITED=1 selects an 8192-slot
-// probing table that holds every visited vertex (distance counts then equal
-// the method's own). RNSM_HASH_BITS / RNSM_WPB override the sizes.
+// beam ef over a graph of n vertices with rows of degree <= maxdeg. The fast
+// table is lossy (a forgotten vertex is evaluated again and dropped by key),
+// so it is sized for occupancy rather than for the whole visited set: 8 KB
+// (4096 16-bit slots) for the L=64, R=32 searches. RNSM_EXACT_VISITED=1, or a
+// graph too large for 16-bit tags, selects an 8192-slot probing table that
+// holds every visited vertex (distance counts then equal the method's own).
+// RNSM_HASH_BITS / RNSM_WPB override the sizes.
 struct SearchShape {
     int hbits, wpb, mode;
 };
 
-SearchShape search_shape(int ef, int maxdeg) {
+SearchShape search_shape(int ef, int maxdeg, int64_t n) {
     SearchShape s;
     int hb = ilog2_ceil((int64_t)ef * (maxdeg > 0 ? maxdeg : 16));
     hb = hb < 8 ? 8 : (hb > 11 ? 11 : hb);
@@ -142,6 +141,10 @@ SearchShape search_shape(int ef, int maxdeg) {
     }
     const char* e = getenv("RNSM_HASH_BITS");
     if (e && atoi(e) >= 6 && atoi(e) <= 14) hb = atoi(e);
+    if (s.mode == 0 && n >= ((int64_t)0xffff << (hb + 1))) {
+        s.mode = 1;  // ids do not fit the 16-bit tags
+        hb = 13;
+    }
     int w = 1;
     const char* ew = getenv("RNSM_WPB");
     if (ew && atoi(ew) >= 1 && atoi(ew) <= 4) w = atoi(ew);
@@ -489,6 +492,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     int64_t* h_nrev;
     HS(h_nrev, "h_nrev", sizeof(int64_t) * ops.size());
     const bool use_bfs = !getenv("RNSM_NO_BFS_ORDER");
+    std::vector<char> touched(m, 0);  // rows changed by an earlier operation
     std::vector<int32_t> rank, fbeg, fcnt;
     std::vector<uint64_t> rbits;
     int32_t* h_bfs = nullptr;
@@ -527,16 +531,17 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             // breadth-first order of the source graph from its entry: the
             // expansion runs its queries in that order, and pivot groups are
             // launched by the rank of their pivot in it (locality in L2 only)
-            int32_t *bfs_order = nullptr, *bfs_level;
+            int32_t* bfs_order = nullptr;
+            unsigned* bfs_vis;
             int ev_order = -1;
             if (use_bfs) {
                 unsigned *bfs_tail, *h_tail;
                 WS(bfs_order, "bfs_order", sizeof(int32_t) * ns);
-                WS(bfs_level, "bfs_level", sizeof(int32_t) * ns);
+                WS(bfs_vis, "bfs_visited", sizeof(unsigned) * ((ns + 31) / 32));
                 WS(bfs_tail, "bfs_tail", sizeof(unsigned));
                 HS(h_tail, "h_bfs_tail", sizeof(unsigned));
                 HS(h_bfs, "h_bfs_order", sizeof(int32_t) * ns);
-                HIPCHK(launch_bfs_order(padj + bases[s] * R, R, ns, graphs[s].entry, bfs_level,
+                HIPCHK(launch_bfs_order(padj + bases[s] * R, R, ns, graphs[s].entry, bfs_vis,
                                         bfs_order, bfs_tail, h_tail, st));
                 HIPCHK(hipMemcpyAsync(h_bfs, bfs_order, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
                 HIPCHK(E.record(st, &ev_order));
@@ -564,7 +569,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             a.G = vi.G;
             a.lgG = ilog2i(vi.G);
             a.cpl = vi.cpl;
-            const SearchShape sh = search_shape(kp, R);
+            const SearchShape sh = search_shape(kp, R, ns);
             a.hbits = sh.hbits;
             a.hash_mode = sh.mode;
             a.out_mode = 1;
@@ -573,6 +578,13 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             a.out_k = k;
             a.counters = cnt + 0 * CNT_SLOTS * CNT_N;
             a.err = errf;
+            if (!touched[s] && search_d_exact) {
+                // the source rows are still the input rows: the expansion's
+                // first step gives their distances, which the prune reuses
+                a.row_d = rdist;
+                a.row_d_base = bases[s];
+                a.row_d_stride = R;
+            }
             HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
             HIPCHK(E.record(st, &ex[1]));
             HIPCHK(launch_invert(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
@@ -630,7 +642,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         aA.ef = efN;
         aA.out_k = efN;
         aA.counters = cnt + 1 * CNT_SLOTS * CNT_N;
-        const SearchShape shA = search_shape(efN, R);
+        const SearchShape shA = search_shape(efN, R, nt);
         aA.hbits = shA.hbits;
         aA.hash_mode = shA.mode;
         // wave B: followers, local sliding from their pivot's results
@@ -642,7 +654,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         aB.ef = efS;
         aB.out_k = efS;
         aB.counters = cnt + 2 * CNT_SLOTS * CNT_N;
-        const SearchShape shB = search_shape(efS, R);
+        const SearchShape shB = search_shape(efS, R, nt);
         aB.hbits = shB.hbits;
         aB.hash_mode = shB.mode;
         g_stats.exact_visited = shB.mode;
@@ -902,6 +914,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         g_stats.n_followers += nf;
         g_stats.n_pivots += np;
         g_stats.n_source_vertices += ns;
+        touched[s] = touched[t] = 1;
     }
 
     // ----------------------------------------------------------- compaction
@@ -1044,7 +1057,7 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     a.G = vi.G;
     a.lgG = ilog2i(vi.G);
     a.cpl = vi.cpl;
-    const SearchShape sh = search_shape(ef, 32);
+    const SearchShape sh = search_shape(ef, 32, g->n);
     a.hbits = sh.hbits;
     a.hash_mode = sh.mode;
     a.out_mode = 0;

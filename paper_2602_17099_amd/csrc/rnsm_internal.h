@@ -48,6 +48,11 @@ struct SearchArgs {
     const int32_t* out_row;   // output row of query i (NULL: i)
     u64* counters;            // CNT_SLOTS x CNT_N entries
     int* err;
+    float* row_d;             // optional (seed mode 1): the distances of the query's own
+                              // neighbours, from its first expansion, go to
+                              // row_d[(row_d_base + u) * row_d_stride + slot]
+    int64_t row_d_base;
+    int row_d_stride;
 };
 
 struct PruneArgs {
@@ -132,9 +137,9 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
                         hipStream_t st);
 int64_t entry_blocks(int64_t n);
 // breadth-first vertex order of a padded-adjacency graph from root (a
-// processing order only); level: n ints of scratch, tail: one device
-// counter, h_tail: pinned host word; synchronises st once per level
-hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, int32_t* level,
+// processing order only); vis: (n + 31) / 32 words of scratch, tail: one
+// device counter, h_tail: pinned host word; synchronises st once per level
+hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, unsigned* vis,
                             int32_t* order, unsigned* tail, unsigned* h_tail, hipStream_t st);
 
 // lanes per row for rows of nch 16-byte chunks: the smallest power of two G

@@ -222,13 +222,27 @@ __device__ __forceinline__ void beam_insert(Beam<EFS>& B, u64 key, int ef, int l
 // held its slot. Mode 1 (exact while the table has room): linear probing.
 // 0: seen, 1: not seen, 2: not seen (or forgotten) and another vertex was
 // evicted / the probe path was full
+// Visited set in LDS (4 << hbits bytes). Forgetful form: 2 << hbits slots of
+// 16 bits; vertex v goes to slot (v ^ (v >> b)) mod 2^b and stores the tag
+// v >> b, so (slot, tag) identifies v while v < 0xffff << b (0xffff marks an
+// empty slot). A plain read then a write: two lanes that meet in one slot in
+// the same instruction are both treated as new, which only re-evaluates a
+// vertex. Exact form: 32-bit ids with linear probing (up to 64 probes).
+// Returns 0 if v was already there, 1 if it went into an empty slot, 2 if it
+// replaced another vertex (or found no slot).
 template <bool EXACT>
 __device__ __forceinline__ int hash_visit(int* tab, int hbits, int v) {
-    const unsigned h = ((unsigned)v * 2654435761u) >> (32 - hbits);
     if constexpr (!EXACT) {
-        const int old = atomicExch(&tab[h], v);
-        return old == v ? 0 : (old == -1 ? 1 : 2);
+        const unsigned b = (unsigned)hbits + 1u;
+        const unsigned hi = (unsigned)v >> b;
+        const unsigned slot = ((unsigned)v ^ hi) & ((1u << b) - 1u);
+        unsigned short* t16 = (unsigned short*)tab;
+        const unsigned old = t16[slot];
+        if (old == hi) return 0;
+        t16[slot] = (unsigned short)hi;
+        return old == 0xffffu ? 1 : 2;
     } else {
+        const unsigned h = ((unsigned)v * 2654435761u) >> (32 - hbits);
         const unsigned mask = (1u << hbits) - 1u;
         for (int p = 0; p < 64; ++p) {
             const int old = atomicCAS(&tab[(h + p) & mask], -1, v);
@@ -268,7 +282,9 @@ __device__ __forceinline__ float dot2x4(uint4 a, uint4 b, float acc) {
     return dot2<TT>(a.w, b.w, acc);
 }
 
-__host__ __device__ constexpr int search_lds_words(int hbits) { return (1 << hbits) + 64; }
+// per wavefront: the visited table, the compacted candidate list and the
+// adjacency slot of each compacted candidate
+__host__ __device__ constexpr int search_lds_words(int hbits) { return (1 << hbits) + 128; }
 
 // evaluate the per-lane candidates v (-1: none): visited filter, distances,
 // beam insertion. Rows are read by groups of G lanes, CPL 16-byte chunks per
@@ -281,7 +297,7 @@ template <int TT, int EFS, int CPL, bool EXACT>
 __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS>& B,
                                                    const Query<TT, CPL>& Q, float qn, int* tab,
                                                    int* cl, int v, int lane, u64& ndc,
-                                                   u64& nevict) {
+                                                   u64& nevict, float* rec = nullptr) {
     constexpr int EPC = Elt<TT>::EPC;
     constexpr int UNR = 2;
     int st = 0;
@@ -291,7 +307,11 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
     const u64 m = __ballot(st != 0);
     const int nc = __popcll(m);
     if (nc == 0) return;
-    if (st != 0) cl[__popcll(m & lanemask_lt(lane))] = v;
+    if (st != 0) {
+        const int rk = __popcll(m & lanemask_lt(lane));
+        cl[rk] = v;
+        cl[WAVE + rk] = lane;  // adjacency slot, for rec
+    }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -355,6 +375,7 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
                 else
                     d = finalize_dist(acc[u], a.metric, qn, nb);
                 key = make_key(d, cid[u]);
+                if (rec) rec[cl[WAVE + c0 + u * RPP + group]] = d;
             }
             u64 mm = __ballot(key < worst);
             while (mm) {
@@ -459,7 +480,11 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
             // padded adjacency: one load, no offsets lookup
             const int v = lane < a.rp ? a.padj[(int64_t)uid * a.rp + lane] : -1;
             nadj += (u64)__popcll(__ballot(v >= 0));
-            process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
+            // the seed's own first expansion evaluates every neighbour of u
+            float* rec = (a.row_d && it == 0 && uid == u)
+                             ? a.row_d + (a.row_d_base + u) * a.row_d_stride
+                             : nullptr;
+            process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict, rec);
         } else {
             const int64_t b = a.offs[uid], en = a.offs[uid + 1];
             nadj += (u64)(en - b);
@@ -1114,51 +1139,69 @@ __global__ void k_pad_adjacency(const int64_t* offs, const int32_t* nbrs, int64_
 // filled) from `root`, used only as a processing order: searches of vertices
 // close in the graph then run in neighbouring wavefronts and share L2. Within
 // a level the order follows atomics and is not deterministic; no result
-// depends on it. order[0..n) receives every vertex once; level[] is scratch.
-__global__ void k_bfs_init(int64_t n, int32_t root, int32_t* level, int32_t* order,
-                           unsigned* tail) {
+// depends on it. order[0..n) receives every vertex once. The visited set is a
+// bitmap of n bits (small enough to stay in L2); a plain read filters out
+// most visited neighbours before the atomic.
+__global__ void k_bfs_init(int64_t n, int32_t root, unsigned* vis, int32_t* order, unsigned* tail) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    level[t] = t == root ? 0 : -1;
+    const int64_t words = (n + 31) >> 5;
+    if (t >= words) return;
+    vis[t] = t == (root >> 5) ? 1u << (root & 31) : 0u;
     if (t == 0) {
         order[0] = root;
         *tail = 1u;
     }
 }
 
-// frontier order[s, e) at level lvl: one thread per (vertex, slot)
-__global__ void k_bfs_level(const int32_t* padj, int rp, int64_t n, int32_t* order, int64_t s,
-                            int64_t e, int32_t lvl, int32_t* level, unsigned* tail) {
+// appends the flagged values of a block to order[tail...]: one global atomic
+// per block (BFS_T threads), offsets from wavefront ballots and LDS
+#define BFS_T 1024
+__device__ __forceinline__ void block_append(bool flag, int32_t val, int32_t* order,
+                                             unsigned* tail) {
+    __shared__ unsigned wcount[BFS_T / WAVE];
+    __shared__ unsigned bbase;
+    const int lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const u64 m = __ballot(flag);
+    if (lane == 0) wcount[wid] = (unsigned)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int w2 = 0; w2 < nw; ++w2) {
+            const unsigned c = wcount[w2];
+            wcount[w2] = tot;
+            tot += c;
+        }
+        bbase = tot ? atomicAdd(tail, tot) : 0u;
+    }
+    __syncthreads();
+    if (flag) order[bbase + wcount[wid] + __popcll(m & lanemask_lt(lane))] = val;
+}
+
+// frontier order[s, e): one thread per (vertex, slot)
+__global__ __launch_bounds__(BFS_T) void k_bfs_level(const int32_t* padj, int rp, int64_t n,
+                                                     int32_t* order, int64_t s, int64_t e,
+                                                     unsigned* vis, unsigned* tail) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool found = false;
     int32_t w = -1;
     if (t < (e - s) * rp) {
         const int32_t u = order[s + t / rp];
         w = padj[(int64_t)u * rp + (int)(t % rp)];
-        found = w >= 0 && w < n && atomicCAS(&level[w], -1, lvl + 1) == -1;
+        if (w >= 0 && w < n) {
+            const unsigned bit = 1u << (w & 31);
+            if (!(__atomic_load_n(&vis[w >> 5], __ATOMIC_RELAXED) & bit))
+                found = !(atomicOr(&vis[w >> 5], bit) & bit);
+        }
     }
-    const u64 m = __ballot(found);
-    if (m == 0ull) return;
-    const int lane = lane_id();
-    unsigned base = 0;
-    const int lead = __ffsll((long long)m) - 1;
-    if (lane == lead) base = atomicAdd(tail, (unsigned)__popcll(m));
-    base = (unsigned)__shfl((int)base, lead);
-    if (found) order[base + __popcll(m & lanemask_lt(lane))] = w;
+    block_append(found, w, order, tail);
 }
 
 // vertices no level reached, after the others
-__global__ void k_bfs_rest(int64_t n, const int32_t* level, int32_t* order, unsigned* tail) {
+__global__ __launch_bounds__(BFS_T) void k_bfs_rest(int64_t n, const unsigned* vis, int32_t* order,
+                                                    unsigned* tail) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool miss = t < n && level[t] == -1;
-    const u64 m = __ballot(miss);
-    if (m == 0ull) return;
-    const int lane = lane_id();
-    unsigned base = 0;
-    const int lead = __ffsll((long long)m) - 1;
-    if (lane == lead) base = atomicAdd(tail, (unsigned)__popcll(m));
-    base = (unsigned)__shfl((int)base, lead);
-    if (miss) order[base + __popcll(m & lanemask_lt(lane))] = (int32_t)t;
+    const bool miss = t < n && !((vis[t >> 5] >> (t & 31)) & 1u);
+    block_append(miss, (int32_t)t, order, tail);
 }
 
 // one thread per row slot, so that consecutive threads write consecutive ids
@@ -1580,16 +1623,17 @@ __global__ __launch_bounds__(ENTRY_T) void k_entry_crit(const float* X, int64_t 
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, int32_t* level,
+hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, unsigned* vis,
                             int32_t* order, unsigned* tail, unsigned* h_tail, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (root < 0 || root >= n) root = 0;
-    hipLaunchKernelGGL(k_bfs_init, dim3(nblk(n, 256)), dim3(256), 0, st, n, root, level, order, tail);
+    hipLaunchKernelGGL(k_bfs_init, dim3(nblk((n + 31) >> 5, 256)), dim3(256), 0, st, n, root, vis,
+                       order, tail);
     hipError_t e = hipGetLastError();
     int64_t s0 = 0, e0 = 1;
-    for (int32_t lvl = 0; e0 > s0 && e0 < n; ++lvl) {
-        hipLaunchKernelGGL(k_bfs_level, dim3(nblk((e0 - s0) * rp, 256)), dim3(256), 0, st, padj, rp, n,
-                           order, s0, e0, lvl, level, tail);
+    while (e0 > s0 && e0 < n) {
+        hipLaunchKernelGGL(k_bfs_level, dim3(nblk((e0 - s0) * rp, BFS_T)), dim3(BFS_T), 0, st, padj, rp,
+                           n, order, s0, e0, vis, tail);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(h_tail, tail, sizeof(unsigned), hipMemcpyDeviceToHost, st)) != hipSuccess)
             return e;
@@ -1598,7 +1642,7 @@ hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root
         e0 = (int64_t)*h_tail;
     }
     if (e0 < n) {
-        hipLaunchKernelGGL(k_bfs_rest, dim3(nblk(n, 256)), dim3(256), 0, st, n, level, order, tail);
+        hipLaunchKernelGGL(k_bfs_rest, dim3(nblk(n, BFS_T)), dim3(BFS_T), 0, st, n, vis, order, tail);
         e = hipGetLastError();
     }
     return e;
