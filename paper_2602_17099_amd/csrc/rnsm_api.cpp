@@ -404,6 +404,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     // ------------------------------------------------------------ workspace
     int32_t *rows, *deg, *errf;
     float *rdist, *norms = nullptr;
+    double* norms64 = nullptr;  // inner product and cosine: for the stored distances
     u64* cnt;
     WS(rows, "rows", sizeof(int32_t) * N * R);
     WS(deg, "deg", sizeof(int32_t) * N);
@@ -426,7 +427,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
     if (p->metric == RNSM_COSINE) {
         WS(norms, "norms", sizeof(float) * N);
-        HIPCHK(launch_norms(vecs->f32, N, vecs->dim, norms, st));
+        WS(norms64, "norms64", sizeof(double) * N);
+        HIPCHK(launch_norms(vecs->f32, N, vecs->dim, norms, st, norms64));
     }
     for (int i = 0; i < m; ++i)
         HIPCHK(launch_init_rows(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, bases[i], R, rows,
@@ -923,8 +925,12 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     int64_t* stmp3;
     WS(stmp3, "scan_tmp3", sizeof(int64_t) * scan_tmp_elems(N));
     HIPCHK(launch_scan(deg, N, out->offsets, stmp3, st));
+    if (p->metric != RNSM_L2SQ && !norms64) {
+        WS(norms64, "norms64", sizeof(double) * N);
+        HIPCHK(launch_norms(vecs->f32, N, vecs->dim, nullptr, st, norms64));
+    }
     HIPCHK(launch_compact(rows, deg, rdist, out->offsets, N, R, vecs->f32, vecs->dim, p->metric,
-                          norms, out->nbrs, out->dists, st));
+                          norms, out->nbrs, out->dists, st, norms64));
     HIPCHK(E.record(st, &c1));
     int64_t nedges = 0;
     std::vector<u64> hslots(3 * CNT_SLOTS * CNT_N);

@@ -96,7 +96,9 @@ hipError_t launch_pad_adjacency(const int64_t* offs, const int32_t* nbrs, int64_
                                 int32_t* out, hipStream_t st);
 hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
                             int R, int32_t* rows, int32_t* deg, float* rdist, hipStream_t st);
-hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st);
+// row norms summed in double; out64 (optional) keeps the double values
+hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st,
+                        double* out64 = nullptr);
 hipError_t launch_search(int tt, const SearchArgs& a, int waves_per_block, hipStream_t st);
 size_t search_lds_bytes(int hbits, int waves_per_block);
 hipError_t launch_prune(const PruneArgs& a, hipStream_t st);
@@ -125,10 +127,12 @@ hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, const flo
                               const int64_t* off, int32_t* cur, int32_t* rev, float* rev_d,
                               hipStream_t st);
 hipError_t launch_max_i32(const int32_t* v, int64_t n, int32_t* out, hipStream_t st);
+// CSR output; for inner product and cosine (norms64 required then) every
+// stored distance is recomputed with float64 sums
 hipError_t launch_compact(const int32_t* rows, const int32_t* deg, const float* rdist,
                           const int64_t* off, int64_t N, int R, const float* X, int dim,
                           int metric, const float* norms, int32_t* out_nbrs, float* out_dists,
-                          hipStream_t st);
+                          hipStream_t st, const double* norms64 = nullptr);
 hipError_t launch_copy_rows(const int32_t* rows_a, const int32_t* deg_a, const float* dist_a,
                             const int32_t* cnt, int64_t n, int R, int32_t* rows_b,
                             int32_t* deg_b, float* dist_b, hipStream_t st);

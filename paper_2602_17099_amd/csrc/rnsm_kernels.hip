@@ -1220,12 +1220,18 @@ __global__ void k_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n,
     }
 }
 
-__global__ void k_norms(const float* X, int64_t n, int dim, float* out) {
+// row norms, summed in double (the float32 copy is the double result rounded)
+__global__ void k_norms(const float* X, int64_t n, int dim, float* out, double* out64) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    float s = 0.0f;
-    for (int j = 0; j < dim; ++j) s = fmaf(X[v * dim + j], X[v * dim + j], s);
-    out[v] = sqrtf(s);
+    double s = 0.0;
+    for (int j = 0; j < dim; ++j) {
+        const double x = (double)X[v * dim + j];
+        s = fma(x, x, s);
+    }
+    const double r = sqrt(s);
+    if (out) out[v] = (float)r;
+    if (out64) out64[v] = r;
 }
 
 // exclusive scan of int32 counts into int64 offsets (n+1 entries)
@@ -1359,12 +1365,16 @@ __global__ void k_max_i32(const int32_t* v, int64_t n, int32_t* out) {
 // One wavefront per vertex (R <= 64: one lane per slot). Distances a prune
 // did not compute (input edges of rows no operation touched) are computed
 // here with the prune's lane-group layout and summation order.
+// One wavefront per vertex. With norms64 (inner product, cosine) every
+// stored distance is recomputed with float64 sums and norms: 1 - <x, y> and
+// 1 - <x, y> / (|x| |y|) lose digits to cancellation in float32 when the
+// distance is small.
 template <int CPL>
 __global__ __launch_bounds__(256) void k_compact(const int32_t* rows, const int32_t* deg,
                                                  const float* rdist, const int64_t* off, int64_t N,
                                                  int R, const float* X, int nch, int G, int lgG,
                                                  int metric, const float* norms, int32_t* out_nbrs,
-                                                 float* out_dists) {
+                                                 float* out_dists, const double* norms64) {
     __shared__ int slots[4][WAVE];
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
@@ -1380,7 +1390,7 @@ __global__ __launch_bounds__(256) void k_compact(const int32_t* rows, const int3
         out_nbrs[o + lane] = u;
     }
     if (!out_dists) return;
-    const bool miss = lane < dg && d != d;
+    const bool miss = lane < dg && (d != d || norms64 != nullptr);
     if (lane < dg && !miss) out_dists[o + lane] = d;
     const u64 need = __ballot(miss);
     if (need == 0ull) return;
@@ -1400,9 +1410,25 @@ __global__ __launch_bounds__(256) void k_compact(const int32_t* rows, const int3
         const int32_t uu = __shfl(u, sl);
         float4 ux[CPL];
         load_row_f32<CPL>(X, c < cnt ? (int64_t)uu : -1, rowf, sub, G, ux);
-        const float acc = dist_rows<CPL>(ux, pv, metric, G);
-        if (c < cnt && sub == G - 1)
-            out_dists[o + sl] = finalize_dist(acc, metric, vn, metric == 2 ? norms[uu] : 1.0f);
+        if (norms64) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                s = fma((double)ux[j].x, (double)pv[j].x, s);
+                s = fma((double)ux[j].y, (double)pv[j].y, s);
+                s = fma((double)ux[j].z, (double)pv[j].z, s);
+                s = fma((double)ux[j].w, (double)pv[j].w, s);
+            }
+            for (int off2 = 1; off2 < G; off2 <<= 1) s += __shfl_xor(s, off2);
+            if (c < cnt && sub == G - 1) {
+                const double dd = metric == 1 ? 1.0 - s : 1.0 - s / (norms64[v] * norms64[uu]);
+                out_dists[o + sl] = (float)dd;
+            }
+        } else {
+            const float acc = dist_rows<CPL>(ux, pv, metric, G);
+            if (c < cnt && sub == G - 1)
+                out_dists[o + sl] = finalize_dist(acc, metric, vn, metric == 2 ? norms[uu] : 1.0f);
+        }
     }
 }
 
@@ -1672,9 +1698,10 @@ hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n,
     return hipGetLastError();
 }
 
-hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st) {
+hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st,
+                        double* out64) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_norms, dim3(nblk(n, 256)), dim3(256), 0, st, X, n, dim, out);
+    hipLaunchKernelGGL(k_norms, dim3(nblk(n, 256)), dim3(256), 0, st, X, n, dim, out, out64);
     return hipGetLastError();
 }
 
@@ -1839,18 +1866,20 @@ hipError_t launch_max_i32(const int32_t* v, int64_t n, int32_t* out, hipStream_t
 hipError_t launch_compact(const int32_t* rows, const int32_t* deg, const float* rdist,
                           const int64_t* off, int64_t N, int R, const float* X, int dim,
                           int metric, const float* norms, int32_t* out_nbrs, float* out_dists,
-                          hipStream_t st) {
+                          hipStream_t st, const double* norms64) {
     if (N <= 0) return hipSuccess;
     if (R > WAVE) return hipErrorInvalidValue;
     const int nch = dim / 4, G = lanes_per_row(nch);
     if (dim % 4 != 0 || G < 0) return hipErrorInvalidValue;
     const int cpl = nch / G, lgG = ilog2i(G);
+    const double* n64 = metric == 0 ? nullptr : norms64;
+    if (metric != 0 && !n64 && out_dists) return hipErrorInvalidValue;
     const dim3 grid(nblk(N, 4)), block(256);
     switch (cpl) {
-        case 1: hipLaunchKernelGGL(k_compact<1>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists); break;
-        case 2: hipLaunchKernelGGL(k_compact<2>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists); break;
-        case 3: hipLaunchKernelGGL(k_compact<3>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists); break;
-        default: hipLaunchKernelGGL(k_compact<4>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists); break;
+        case 1: hipLaunchKernelGGL(k_compact<1>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists, n64); break;
+        case 2: hipLaunchKernelGGL(k_compact<2>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists, n64); break;
+        case 3: hipLaunchKernelGGL(k_compact<3>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists, n64); break;
+        default: hipLaunchKernelGGL(k_compact<4>, grid, block, 0, st, rows, deg, rdist, off, N, R, X, nch, G, lgG, metric, norms, out_nbrs, out_dists, n64); break;
     }
     return hipGetLastError();
 }

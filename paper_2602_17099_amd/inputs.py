@@ -165,3 +165,24 @@ def projection_graph(X: np.ndarray, deg: int, n_proj: int = 8, seed: int = SEED_
     offsets = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(cnt, out=offsets[1:])
     return offsets, C[valid].astype(np.int32)
+
+
+def dirichlet_sizes(m: int, total: int, min_size: int, seed: int) -> list[int]:
+    """m sizes: min_size each plus a Dirichlet(1, ..., 1) share of the rest,
+    rounded by largest remainder so that they sum to ``total``."""
+    assert total >= m * min_size
+    g = rng(seed)
+    w = g.dirichlet(np.ones(m))
+    extra = w * (total - m * min_size)
+    base = np.floor(extra).astype(np.int64)
+    rem = int(total - m * min_size - base.sum())
+    order = np.argsort(-(extra - base), kind="stable")
+    base[order[:rem]] += 1
+    return [int(min_size + b) for b in base]
+
+
+def slab_order(X: np.ndarray, seed: int) -> np.ndarray:
+    """Row order by the projection on a seeded random unit direction (a slab
+    partition when the rows are then cut into consecutive sub-indexes)."""
+    d = rng(seed).standard_normal(X.shape[1])
+    return np.argsort(X.astype(np.float64) @ (d / np.linalg.norm(d)), kind="stable")

@@ -1,0 +1,123 @@
+"""Parity on small inputs shaped like the other workload configurations
+(many uneven sub-indexes with inner product; 768-d cosine with a bfloat16
+search copy; uint8 data converted to float16 on the device with many
+sub-indexes), through the C ABI, against the float64 oracle."""
+import numpy as np
+import pytest
+
+from paper_2602_17099_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2602_17099_amd as p
+    p.lib()
+    return p
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _dsubs(subs, dev):
+    return [(_t(o, dev), _t(nb, dev), e) for o, nb, e in subs]
+
+
+def _build(orc, X, sizes, K, R, metric):
+    subs, b = [], 0
+    for n in sizes:
+        subs.append(orc.build_graph(X[b:b + n], K, R, alpha=1.2, metric=metric, reverse=True))
+        b += n
+    return subs
+
+
+def _edges(off, nb):
+    return {(v, int(u)) for v in range(len(off) - 1) for u in nb[off[v]:off[v + 1]]}
+
+
+def _float_checks(orc, got, ref, X, Q, metric, ef, overlap=0.995):
+    # precision contract on float data: edge overlap, recall@10 within 0.002
+    # of the oracle's graph, stored distances within 1e-5 of float64
+    off, nb, ds, entry = got
+    off, nb, ds = off.cpu().numpy(), nb.cpu().numpy(), ds.cpu().numpy()
+    assert entry == ref["entry"]
+    e_gpu, e_ref = _edges(off, nb), _edges(ref["offsets"], ref["nbrs"])
+    frac = len(e_gpu & e_ref) / len(e_ref)
+    if overlap is not None:
+        assert frac >= overlap, f"edge overlap {frac:.4f}"
+    for v in range(0, len(X), max(1, len(X) // 300)):
+        for j in range(off[v], off[v + 1]):
+            d64 = orc.dist(X[v], X[nb[j]], metric)
+            assert abs(ds[j] - d64) <= 1e-5 * max(abs(d64), 1e-3)
+    gt, _ = orc.knn_queries(X, Q, 10, metric)
+    r_gpu = orc.recall_at_k(orc.search_graph(off, nb, X, Q, entry, ef, metric=metric), gt)
+    r_ref = orc.recall_at_k(orc.search_graph(ref["offsets"], ref["nbrs"], X, Q, ref["entry"], ef,
+                                             metric=metric), gt)
+    assert abs(r_gpu - r_ref) <= 0.002, f"recall {r_gpu:.4f} vs oracle {r_ref:.4f}"
+    return frac, r_gpu, r_ref
+
+
+def test_many_uneven_subindexes_inner_product(dev, orc, pkg):
+    # ten uneven sub-indexes (log-uniform sizes), L2-normalised 96-d mixture,
+    # inner product, slab partition so that centroid costs differ, MOS order
+    sizes = inputs.uneven_sizes(10, 300, 2400, 9000, seed=1101)
+    X = inputs.mixture_unit(sum(sizes), 96, comps=64, seed=1102)
+    X = np.ascontiguousarray(X[inputs.slab_order(X, 1103)])
+    Q = inputs.mixture_unit(500, 96, comps=64, seed=1102, stream=1)
+    subs = _build(orc, X, sizes, 32, 16, 1)
+    ref = orc.merge(subs, X, R=16, L=32, alpha=1.2, metric=1, use_centroids=True)
+    got = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=16, L=32, alpha=1.2, metric=1, flags=2)
+    st = pkg.stats()
+    assert st["n_ops"] == len(ref["ops"]) and st["prune_path"] == 3
+    _float_checks(orc, got, ref, X, Q, 1, 32)
+
+
+@pytest.mark.parametrize("form", ["float32", "bfloat16"])
+def test_768d_cosine(dev, orc, pkg, form):
+    # 768-d, per-dimension scale 1/sqrt(i), L2-normalised, cosine; four
+    # sub-indexes; R=48, L=96; the bfloat16 copy made by the library
+    import torch
+    X = inputs.mixture_unit(4 * 450, 768, comps=32, decay=True, seed=1201)
+    Q = inputs.mixture_unit(1000, 768, comps=32, decay=True, seed=1201, stream=1)
+    subs = _build(orc, X, [450] * 4, 96, 48, 2)
+    ref = orc.merge(subs, X, R=48, L=96, alpha=1.2, metric=2)
+    Xd = _t(X, dev)
+    search = pkg.convert(Xd, torch.bfloat16) if form == "bfloat16" else None
+    got = pkg.merge(_dsubs(subs, dev), Xd, R=48, L=96, alpha=1.2, metric=2, search=search)
+    assert pkg.stats()["prune_path"] == 0  # dim 768: the float32 walk
+    # the contract's edge overlap is for the float32 form; the bfloat16 form
+    # is held to recall@10 and to the float32 distances
+    _float_checks(orc, got, ref, X, Q, 2, 96, overlap=0.995 if form == "float32" else None)
+
+
+def test_uint8_many_subindexes_float16_search(dev, orc, pkg):
+    # uint8 data converted on the device (to float32 rows and a float16
+    # search copy), twelve Dirichlet-sized sub-indexes, MOS degree bound 8:
+    # integers exact in float16, so the merge is bit-exact
+    import torch
+    sizes = inputs.dirichlet_sizes(12, 7200, 200, seed=1301)
+    U = inputs.mixture_u8(sum(sizes), 96, comps=64, seed=1302).astype(np.uint8)
+    X = U.astype(np.float32)
+    subs = _build(orc, X, sizes, 48, 32, 0)
+    ref = orc.merge(subs, X, R=32, L=64, alpha=1.2, mos_degree=8)
+    Ud = _t(U, dev)
+    Xd = pkg.convert(Ud, torch.float32)
+    H = pkg.convert(Ud, torch.float16)
+    off, nb, ds, entry = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2, mos_degree=8,
+                                   search=H)
+    st = pkg.stats()
+    assert st["n_ops"] == len(ref["ops"]) and st["prune_path"] == 1
+    assert entry == ref["entry"]
+    assert np.array_equal(off.cpu().numpy(), ref["offsets"])
+    assert np.array_equal(nb.cpu().numpy(), ref["nbrs"])
+    assert np.array_equal(ds.cpu().numpy().astype(np.float64), ref["dists"])
