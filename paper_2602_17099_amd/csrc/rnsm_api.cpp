@@ -522,6 +522,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         int64_t *h_off = nullptr;
         int32_t* h_ids = nullptr;
         const bool fresh = cached[s].empty() && !(p->flags & RNSM_FLAG_ALL_PIVOTS);
+        int ev_rk_off = -1, ev_rk_ids = -1;
         if (fresh) {
             int32_t *nk, *rcnt, *rk_ids;
             int64_t *rk_off, *stmp;
@@ -598,7 +599,9 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             HS(h_off, "h_rk_off", sizeof(int64_t) * (ns + 1));
             HS(h_ids, "h_rk_ids", sizeof(int32_t) * ns * k);
             HIPCHK(hipMemcpyAsync(h_off, rk_off, sizeof(int64_t) * (ns + 1), hipMemcpyDeviceToHost, st));
+            HIPCHK(E.record(st, &ev_rk_off));
             HIPCHK(hipMemcpyAsync(h_ids, rk_ids, sizeof(int32_t) * ns * k, hipMemcpyDeviceToHost, st));
+            HIPCHK(E.record(st, &ev_rk_ids));
             if (use_bfs) {
                 // ranks on the host while the expansion runs
                 HIPCHK(hipEventSynchronize(E.ev[ev_order]));
@@ -611,8 +614,13 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
                 }
             }
         }
-        // also drains the previous operation, whose copies read h_lists
-        HIPCHK(hipStreamSynchronize(st));
+        // also drains the previous operation, whose copies read h_lists (the
+        // stream waited for every one of them before its prunes); a fresh
+        // source waits for the R_k offsets only, the ids follow
+        if (fresh)
+            HIPCHK(hipEventSynchronize(E.ev[ev_rk_off]));
+        else
+            HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));
 
         // search arguments shared by the chunks
@@ -779,6 +787,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             qcv.notify_one();
         };
         int64_t np = 0, nf = 0;
+        hipError_t wait_err = hipSuccess;  // the R_k ids transfer (greedy thread)
         if (p->flags & RNSM_FLAG_ALL_PIVOTS) {
             // every vertex is a pivot (no sliding)
             for (int64_t v = 0; v < ns; ++v) h_piv[v] = (int32_t)v;
@@ -794,11 +803,13 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             int64_t chunk = std::max<int64_t>(4096, ns / 64);
             if (const char* c = getenv("RNSM_PIVOT_CHUNK")) chunk = std::max(1ll, atoll(c));
             select_pivots(ns, h_off, h_ids, h_piv, h_fol, h_folp, chunk,
-                          std::max<int64_t>(chunk, ns / 8), [&](int64_t a1, int64_t b1) {
+                          std::max<int64_t>(chunk, ns / 8),
+                          [&](int64_t a1, int64_t b1) {
                               np = a1;
                               nf = b1;
                               post(a1, b1);
-                          });
+                          },
+                          [&] { wait_err = hipEventSynchronize(E.ev[ev_rk_ids]); });
         } else {
             memcpy(h_lists, cached[s].data(), sizeof(int32_t) * 3 * ns);
             np = cached_np[s];
@@ -811,6 +822,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         }
         qcv.notify_one();
         launcher.join();
+        if (wait_err != hipSuccess && cerr == hipSuccess) cerr = wait_err;
         g_stats.launches[1] += n_launch_a;
         g_stats.launches[2] += n_launch_b;
         if (fresh && last_use[s] > (int)oi) {

@@ -449,6 +449,7 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
 
     // expand the nearest unexpanded entry until every entry is expanded
     const int64_t maxit = a.n + 2;
+    int pf_uid = -1, pf_v = -1;  // adjacency fetched ahead for the runner-up entry
     for (int64_t it = 0;; ++it) {
         u64 m0 = __ballot(B.k[0] != EMPTY_KEY && B.e[0] == 0u);
         int s;
@@ -477,8 +478,30 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
         }
         ++nexp;
         if (a.padj) {
-            // padded adjacency: one load, no offsets lookup
-            const int v = lane < a.rp ? a.padj[(int64_t)uid * a.rp + lane] : -1;
+            // padded adjacency: one load, no offsets lookup (already in flight
+            // when the entry was the runner-up of the previous expansion)
+            const int v = uid == pf_uid ? pf_v : (lane < a.rp ? a.padj[(int64_t)uid * a.rp + lane] : -1);
+            // the next unexpanded entry of the sorted beam is expanded next
+            // unless this expansion inserts a nearer one: fetch its adjacency
+            // now, so that its latency overlaps this expansion's row loads
+            pf_uid = -1;
+            {
+                const u64 mA = __ballot(B.k[0] != EMPTY_KEY && B.e[0] == 0u);
+                int s2 = -1;
+                if (mA) {
+                    s2 = __ffsll((long long)mA) - 1;
+                    pf_uid = __builtin_amdgcn_readlane((int)(unsigned)(B.k[0] & 0xffffffffu), s2);
+                } else {
+                    if constexpr (EFS == 2) {
+                        const u64 mB = __ballot(B.k[1] != EMPTY_KEY && B.e[1] == 0u);
+                        if (mB) {
+                            s2 = __ffsll((long long)mB) - 1;
+                            pf_uid = __builtin_amdgcn_readlane((int)(unsigned)(B.k[1] & 0xffffffffu), s2);
+                        }
+                    }
+                }
+                if (pf_uid >= 0) pf_v = lane < a.rp ? a.padj[(int64_t)pf_uid * a.rp + lane] : -1;
+            }
             nadj += (u64)__popcll(__ballot(v >= 0));
             // the seed's own first expansion evaluates every neighbour of u
             float* rec = (a.row_d && it == 0 && uid == u)
@@ -1479,11 +1502,26 @@ __global__ __launch_bounds__(256) void k_value_range(const float* X, int64_t tot
         lo = l2 < lo ? l2 : lo;
         hi = h2 > hi ? h2 : hi;
     }
+    // one set of atomics per block: the wavefronts' results meet in LDS
+    __shared__ unsigned blo[4], bhi[4], bfr[4];
+    const int w = threadIdx.x >> 6;
     const bool anyfrac = __ballot(frac) != 0ull;
     if (lane_id() == 0) {
-        if (anyfrac) atomicAnd(&out[0], 0u);
-        atomicMin(&out[1], lo);
-        atomicMax(&out[2], hi);
+        blo[w] = lo;
+        bhi[w] = hi;
+        bfr[w] = anyfrac ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned l = blo[0], h = bhi[0], f = bfr[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            l = blo[i] < l ? blo[i] : l;
+            h = bhi[i] > h ? bhi[i] : h;
+            f |= bfr[i];
+        }
+        if (f) atomicAnd(&out[0], 0u);
+        atomicMin(&out[1], l);
+        atomicMax(&out[2], h);
     }
 }
 
@@ -1492,7 +1530,7 @@ hipError_t launch_value_range(const float* X, int64_t total, unsigned* out, hipS
     hipError_t e = hipMemcpyAsync(out, init, sizeof init, hipMemcpyHostToDevice, st);
     if (e != hipSuccess || total <= 0) return e;
     int64_t blocks = (total / 4 + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > 2048) blocks = 2048;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_value_range, dim3((unsigned)blocks), dim3(256), 0, st, X, total, out);
     return hipGetLastError();

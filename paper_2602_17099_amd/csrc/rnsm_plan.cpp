@@ -155,7 +155,7 @@ int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int 
 // are dropped 64 at a time.
 void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivots,
                    int32_t* followers, int32_t* follower_pivot, int64_t chunk, int64_t chunk_max,
-                   const Emit& emit) {
+                   const Emit& emit, const std::function<void()>& ids_ready) {
     const int64_t words = (n + 63) / 64;
     std::vector<uint64_t> cov((size_t)words, 0ull);
     int64_t gmax = 0;
@@ -167,6 +167,7 @@ void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int3
         b[x >> 6] |= 1ull << (x & 63);
     };
     for (int64_t x = 0; x < n; ++x) mark(rk_off[x + 1] - rk_off[x], x);
+    if (ids_ready) ids_ready();
     int64_t np = 0, nf = 0, sent = 0;
     chunk = std::max<int64_t>(chunk, 1);
     for (int64_t g = gmax; g >= 0; --g) {

@@ -26,9 +26,12 @@ int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int 
 // up to chunk_max) were added since the last call, and once at the end; a
 // caller can start work on every group emitted so far while the selection
 // goes on.
+// `ids_ready` (optional) is called after the gain levels are built from
+// rk_off and before rk_ids is first read, so that the ids may still be in
+// transit while the levels are built.
 using Emit = std::function<void(int64_t np, int64_t nf)>;
 void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivots,
                    int32_t* followers, int32_t* follower_pivot, int64_t chunk, int64_t chunk_max,
-                   const Emit& emit);
+                   const Emit& emit, const std::function<void()>& ids_ready = {});
 
 }  // namespace rnsm
