@@ -878,6 +878,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         q.extra_mode = 1;
         q.extra_ids = res;
         q.extra_d = search_d_exact ? res_d : nullptr;
+        q.extra_sorted = search_d_exact && RES <= 128;  // beams in key order
         q.extra_stride = RES;
         q.extra_cnt = RES;
         q.extra_index_base = bases[s];
@@ -919,6 +920,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         r.extra_index_base = bases[t];
         r.extra_id_add = 0;
         r.skip_empty_extra = 1;
+        r.extra_sorted = 0;
         r.scratch = scratch;
         r.wcap = 256;
         HIPCHK(run_prune(r, pmode, st));
@@ -1183,6 +1185,7 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
         r.extra_off = roff;
         r.extra_index_base = 0;
         r.skip_empty_extra = 1;
+        r.extra_sorted = 0;
         r.alpha = alpha_rev;
         r.rows_out = rows2;
         r.deg_out = deg2;

@@ -79,6 +79,8 @@ struct PruneArgs {
     int64_t extra_index_base; // extra row of vertex p is p - extra_index_base
     int64_t extra_id_add;     // added to every extra id (-1 entries skipped)
     int skip_empty_extra;     // leave rows without extra candidates untouched
+    int extra_sorted;         // mode 1 with extra_d: each extra row is in ascending
+                              // (d, id) order, -1 ids last (a search's final beam)
     float alpha;
     int R;
     int32_t* rows_out;

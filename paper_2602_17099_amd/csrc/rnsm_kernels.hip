@@ -685,15 +685,66 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // sort by rank: position = #smaller keys + #equal keys earlier
-    for (int t = lane; t < nW; t += WAVE) {
-        const u64 kt = wk[t];
-        int r = 0;
-        for (int s2 = 0; s2 < nW; ++s2) {
-            const u64 ks = wk[s2];
-            r += (ks < kt || (ks == kt && s2 < t)) ? 1 : 0;
+    // order: position = #smaller keys + #equal keys earlier in W
+    if (a.extra_sorted && a.extra_mode == 1 && a.extra_d && nrow <= WAVE && nW <= a.wcap) {
+        // the extras (wk[nrow..nW)) are already in key order: rank the row
+        // part among itself, then merge the two lists by binary search (row
+        // keys before equal extra keys, as their index is lower)
+        const int nb = nW - nrow;
+        u64 ka = EMPTY_KEY;
+        int ra = 0;
+        if (lane < nrow) {
+            ka = wk[lane];
+            for (int s2 = 0; s2 < nrow; ++s2) {
+                const u64 ks = wk[s2];
+                ra += (ks < ka || (ks == ka && s2 < lane)) ? 1 : 0;
+            }
+            ws[ra] = ka;  // the row part in order, for the extras' searches
         }
-        ws[r] = kt;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const u64* xb = wk + nrow;
+        int pa = 0;
+        if (lane < nrow) {  // extras below ka
+            int lo = 0, hi = nb;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (xb[mid] < ka) lo = mid + 1; else hi = mid;
+            }
+            pa = ra + lo;
+        }
+        constexpr int XPL = 2;  // extras per lane (nb <= 128)
+        u64 kb[XPL];
+        int pb[XPL];
+#pragma unroll
+        for (int x = 0; x < XPL; ++x) {
+            const int j = lane + x * WAVE;
+            kb[x] = j < nb ? xb[j] : EMPTY_KEY;
+            int lo = 0, hi = nrow;  // row keys <= kb
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ws[mid] <= kb[x]) lo = mid + 1; else hi = mid;
+            }
+            pb[x] = j + lo;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < nrow) ws[pa] = ka;
+#pragma unroll
+        for (int x = 0; x < XPL; ++x)
+            if (lane + x * WAVE < nb) ws[pb[x]] = kb[x];
+    } else {
+        for (int t = lane; t < nW; t += WAVE) {
+            const u64 kt = wk[t];
+            int r = 0;
+            for (int s2 = 0; s2 < nW; ++s2) {
+                const u64 ks = wk[s2];
+                r += (ks < kt || (ks == kt && s2 < t)) ? 1 : 0;
+            }
+            ws[r] = kt;
+        }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
