@@ -54,6 +54,7 @@ struct Workspace {
         size_t bytes = 0;
     };
     std::map<std::string, Buf> bufs, hbufs;
+    GainLevels levels;  // lazy-greedy gain levels, storage kept between calls
     // second stream (default priority) for the naive searches of the pivot
     // chunks, which then overlap the sliding searches of earlier chunks
     hipStream_t side = nullptr;
@@ -494,6 +495,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     int64_t* h_nrev;
     HS(h_nrev, "h_nrev", sizeof(int64_t) * ops.size());
     const bool use_bfs = !getenv("RNSM_NO_BFS_ORDER");
+    GainLevels& levels = ws.levels;
     std::vector<char> touched(m, 0);  // rows changed by an earlier operation
     std::vector<int32_t> rank, fbeg, fcnt;
     std::vector<uint64_t> rbits;
@@ -522,7 +524,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         int64_t *h_off = nullptr;
         int32_t* h_ids = nullptr;
         const bool fresh = cached[s].empty() && !(p->flags & RNSM_FLAG_ALL_PIVOTS);
-        int ev_rk_off = -1, ev_rk_ids = -1;
+        int ev_rk_off = -1, ev_rk_ids = -1, ev_rk_cnt = -1;
+        int32_t* h_cnt = nullptr;
         if (fresh) {
             int32_t *nk, *rcnt, *rk_ids;
             int64_t *rk_off, *stmp;
@@ -590,7 +593,13 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             }
             HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
             HIPCHK(E.record(st, &ex[1]));
-            HIPCHK(launch_invert(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
+            // list lengths to the host first: the greedy's gain levels are
+            // built from them while offsets and ids are made and copied
+            HIPCHK(launch_count_ids(nk, ns, k, rcnt, st));
+            HS(h_cnt, "h_rk_cnt", sizeof(int32_t) * ns);
+            HIPCHK(hipMemcpyAsync(h_cnt, rcnt, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+            HIPCHK(E.record(st, &ev_rk_cnt));
+            HIPCHK(launch_invert_lists(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
             HIPCHK(E.record(st, &ex[2]));
             ev_exp.push_back(ex);
             g_stats.queries[0] += ns;
@@ -617,10 +626,14 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         // also drains the previous operation, whose copies read h_lists (the
         // stream waited for every one of them before its prunes); a fresh
         // source waits for the R_k offsets only, the ids follow
+        const auto th0 = std::chrono::steady_clock::now();
         if (fresh)
-            HIPCHK(hipEventSynchronize(E.ev[ev_rk_off]));
+            HIPCHK(hipEventSynchronize(E.ev[ev_rk_cnt]));
         else
             HIPCHK(hipStreamSynchronize(st));
+        const auto th1 = std::chrono::steady_clock::now();
+        if (fresh) build_levels(ns, h_cnt, levels);
+        double th_levels = 0, th_ids = 0, th_first_post = -1, th_first_launch = -1;
         HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));
 
         // search arguments shared by the chunks
@@ -752,6 +765,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             y.nq = nf - fa;
             if (!chk(launch_search(vi.tt, y, shB.wpb, st)) || !chk(E.record(st, &ce[3]))) return;
             ev_chunk.push_back(ce);
+            if (th_first_launch < 0) th_first_launch = ms_since(th1);
             n_launch_a += np > pa;  // the stats are thread-local: added after the join
             n_launch_b += nf > fa;
             pa = np;
@@ -780,6 +794,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             }
         });
         auto post = [&](int64_t a1, int64_t b1) {
+            if (th_first_post < 0) th_first_post = ms_since(th1);
             {
                 std::lock_guard<std::mutex> l(qm);
                 qmarks.emplace_back(a1, b1);
@@ -802,14 +817,18 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             }
             int64_t chunk = std::max<int64_t>(4096, ns / 64);
             if (const char* c = getenv("RNSM_PIVOT_CHUNK")) chunk = std::max(1ll, atoll(c));
-            select_pivots(ns, h_off, h_ids, h_piv, h_fol, h_folp, chunk,
+            select_pivots(levels, h_off, h_ids, h_piv, h_fol, h_folp, chunk,
                           std::max<int64_t>(chunk, ns / 8),
                           [&](int64_t a1, int64_t b1) {
                               np = a1;
                               nf = b1;
                               post(a1, b1);
                           },
-                          [&] { wait_err = hipEventSynchronize(E.ev[ev_rk_ids]); });
+                          [&] {
+                              th_levels = ms_since(th1);
+                              wait_err = hipEventSynchronize(E.ev[ev_rk_ids]);
+                              th_ids = ms_since(th1);
+                          });  // the ids are copied after the offsets
         } else {
             memcpy(h_lists, cached[s].data(), sizeof(int32_t) * 3 * ns);
             np = cached_np[s];
@@ -831,6 +850,12 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             cached_nf[s] = nf;
         }
         ms_plan += ms_since(tg);
+        if (getenv("RNSM_HOST_TRACE"))
+            fprintf(stderr,
+                    "[rnsm host] op %zu: wait R_k offsets %.3f ms; after it: levels %.3f, ids %.3f, "
+                    "first chunk posted %.3f, first chunk queued %.3f, greedy + queueing %.3f ms\n",
+                    oi, std::chrono::duration<double, std::milli>(th1 - th0).count(), th_levels,
+                    th_ids, th_first_post, th_first_launch, ms_since(th1));
         if (!ev_chunk.empty() && ev_chunk.size() > chunk0)
             ev_span.push_back({ev_chunk[chunk0][0], ev_chunk.back()[3]});
         if (cerr != hipSuccess) {

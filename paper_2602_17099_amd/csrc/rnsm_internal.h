@@ -122,6 +122,12 @@ hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* off, int64_t* tmp
 size_t scan_tmp_elems(int64_t n);
 hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int64_t* rk_off,
                          int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st);
+// the two halves of launch_invert: list lengths into cnt, then offsets and
+// ids (cnt is overwritten)
+hipError_t launch_count_ids(const int32_t* nk, int64_t n, int k, int32_t* cnt, hipStream_t st);
+hipError_t launch_invert_lists(const int32_t* nk, int64_t n, int k, int32_t* cnt,
+                               int64_t* rk_off, int32_t* rk_ids, int64_t* scan_tmp,
+                               hipStream_t st);
 hipError_t launch_rev_count(const int32_t* rows, const int32_t* deg, int64_t s_base, int64_t n_s,
                             int R, int64_t t_base, int64_t n_t, int32_t* cnt, hipStream_t st);
 hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, const float* rdist,

@@ -1911,13 +1911,25 @@ hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* off, int64_t* tmp
     return hipGetLastError();
 }
 
-hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int64_t* rk_off,
-                         int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st) {
+hipError_t launch_count_ids(const int32_t* nk, int64_t n, int k, int32_t* cnt, hipStream_t st) {
     hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)n, st);
     if (e != hipSuccess) return e;
     if (n > 0)
         hipLaunchKernelGGL(k_count_ids, dim3(nblk(n * k, 256)), dim3(256), 0, st, nk, n * k, cnt);
-    e = launch_scan(cnt, n, rk_off, scan_tmp, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int64_t* rk_off,
+                         int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st) {
+    hipError_t e = launch_count_ids(nk, n, k, cnt, st);
+    if (e != hipSuccess) return e;
+    return launch_invert_lists(nk, n, k, cnt, rk_off, rk_ids, scan_tmp, st);
+}
+
+hipError_t launch_invert_lists(const int32_t* nk, int64_t n, int k, int32_t* cnt,
+                               int64_t* rk_off, int32_t* rk_ids, int64_t* scan_tmp,
+                               hipStream_t st) {
+    hipError_t e = launch_scan(cnt, n, rk_off, scan_tmp, st);
     if (e != hipSuccess) return e;
     e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)n, st);
     if (e != hipSuccess) return e;

@@ -145,71 +145,116 @@ int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int 
 
 // ------------------------------------------------------ lazy greedy pivots
 
+void build_levels(int64_t n, const int32_t* counts, GainLevels& L) {
+    L.n = n;
+    L.words = (n + 63) / 64;
+    int32_t gmax = 0;
+    for (int64_t x = 0; x < n; ++x) gmax = std::max(gmax, counts[x]);
+    L.nlev = std::min(gmax + 1, GainLevels::LCAP);
+    if ((int64_t)L.bits.size() < (int64_t)L.nlev * L.words) L.bits.resize((size_t)L.nlev * L.words);
+    L.high.clear();
+    // one word of every level at a time: the 64 vertices' bits meet in a
+    // small array, then each level's word is stored
+    uint64_t loc[GainLevels::LCAP];
+    for (int l = 0; l < L.nlev; ++l) loc[l] = 0ull;
+    for (int64_t w = 0; w < L.words; ++w) {
+        const int64_t x0 = w * 64, x1 = std::min<int64_t>(n, x0 + 64);
+        for (int64_t x = x0; x < x1; ++x) {
+            const int32_t g = counts[x];
+            if (g < GainLevels::LCAP)
+                loc[g] |= 1ull << (x - x0);
+            else
+                L.high.emplace_back((int64_t)g, (int32_t)x);
+        }
+        for (int l = 0; l < L.nlev; ++l) {
+            L.bits[(size_t)l * L.words + w] = loc[l];
+            loc[l] = 0ull;
+        }
+    }
+}
+
 // The lazy greedy of Algorithm 2: repeatedly take the vertex with the largest
 // stored gain (ties: smallest id); drop it if covered; if its gain
 // |R_k(x) minus Covered| fell below the stored one, store it under the new
 // gain; otherwise make it a pivot whose followers are its uncovered R_k.
 // A vertex is only ever moved to a lower gain while a higher one is
 // processed, so every gain level is a bitmap over vertex ids scanned once in
-// ascending order; Covered is a bitmap too, so covered vertices of a level
-// are dropped 64 at a time.
-void select_pivots(int64_t n, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivots,
+// ascending order (gains of LCAP and more: a heap with the same order);
+// Covered is a bitmap too, so covered vertices of a level are dropped 64 at
+// a time.
+void select_pivots(GainLevels& L, const int64_t* rk_off, const int32_t* rk_ids, int32_t* pivots,
                    int32_t* followers, int32_t* follower_pivot, int64_t chunk, int64_t chunk_max,
-                   const Emit& emit, const std::function<void()>& ids_ready) {
-    const int64_t words = (n + 63) / 64;
+                   const Emit& emit, const std::function<void()>& lists_ready) {
+    if (lists_ready) lists_ready();
+    const int64_t n = L.n, words = L.words;
     std::vector<uint64_t> cov((size_t)words, 0ull);
-    int64_t gmax = 0;
-    for (int64_t x = 0; x < n; ++x) gmax = std::max<int64_t>(gmax, rk_off[x + 1] - rk_off[x]);
-    std::vector<std::vector<uint64_t>> level(gmax + 1);
-    auto mark = [&](int64_t g, int64_t x) {
-        std::vector<uint64_t>& b = level[g];
-        if (b.empty()) b.assign((size_t)words, 0ull);
-        b[x >> 6] |= 1ull << (x & 63);
-    };
-    for (int64_t x = 0; x < n; ++x) mark(rk_off[x + 1] - rk_off[x], x);
-    if (ids_ready) ids_ready();
     int64_t np = 0, nf = 0, sent = 0;
     chunk = std::max<int64_t>(chunk, 1);
-    for (int64_t g = gmax; g >= 0; --g) {
-        std::vector<uint64_t>& b = level[g];
-        if (b.empty()) continue;
+    auto mark = [&](int64_t g, int64_t x) {
+        if (g < GainLevels::LCAP) {
+            L.bits[(size_t)g * words + (x >> 6)] |= 1ull << (x & 63);
+        } else {
+            L.high.emplace_back(g, (int32_t)x);
+            std::push_heap(L.high.begin(), L.high.end(), [](const std::pair<int64_t, int32_t>& a,
+                                                            const std::pair<int64_t, int32_t>& b) {
+                return a.first < b.first || (a.first == b.first && a.second > b.second);
+            });
+        }
+    };
+    // take x at stored gain g: 0 dropped (covered), 1 moved down, 2 pivot
+    auto visit = [&](int32_t x, int64_t g) {
+        const int64_t o0 = rk_off[x], o1 = rk_off[x + 1];
+        int64_t cur = 0;
+        for (int64_t j = o0; j < o1; ++j) {
+            const int32_t y = rk_ids[j];
+            cur += (int64_t)(~cov[y >> 6] >> (y & 63) & 1ull);
+        }
+        if (cur < g) {
+            mark(cur, x);
+            return;
+        }
+        pivots[np++] = x;
+        cov[x >> 6] |= 1ull << (x & 63);
+        for (int64_t j = o0; j < o1; ++j) {
+            const int32_t y = rk_ids[j];
+            const uint64_t bit = 1ull << (y & 63);
+            if (!(cov[y >> 6] & bit)) {
+                cov[y >> 6] |= bit;
+                followers[nf] = y;
+                follower_pivot[nf++] = x;
+            }
+        }
+        if (np + nf - sent >= chunk) {
+            emit(np, nf);
+            sent = np + nf;
+            chunk = std::max(chunk, std::min(2 * chunk, chunk_max));
+        }
+    };
+    // gains of LCAP and more first, largest gain then smallest id
+    auto hcmp = [](const std::pair<int64_t, int32_t>& a, const std::pair<int64_t, int32_t>& b) {
+        return a.first < b.first || (a.first == b.first && a.second > b.second);
+    };
+    std::make_heap(L.high.begin(), L.high.end(), hcmp);
+    while (!L.high.empty()) {
+        std::pop_heap(L.high.begin(), L.high.end(), hcmp);
+        const auto e = L.high.back();
+        L.high.pop_back();
+        if (!((cov[e.second >> 6] >> (e.second & 63)) & 1ull)) visit(e.second, e.first);
+    }
+    for (int64_t g = L.nlev - 1; g >= 0; --g) {
+        uint64_t* b = L.bits.data() + (size_t)g * words;
         for (int64_t w = 0; w < words; ++w) {
             uint64_t bits = b[w] & ~cov[w];
             while (bits) {
                 const int32_t x = (int32_t)(w * 64 + __builtin_ctzll(bits));
                 bits &= bits - 1;
-                const int64_t o0 = rk_off[x], o1 = rk_off[x + 1];
-                int64_t cur = 0;
-                for (int64_t j = o0; j < o1; ++j) {
-                    const int32_t y = rk_ids[j];
-                    cur += (int64_t)(~cov[y >> 6] >> (y & 63) & 1ull);
-                }
-                if (cur < g) {
-                    mark(cur, x);
-                    continue;
-                }
-                pivots[np++] = x;
-                cov[w] |= 1ull << (x & 63);
-                for (int64_t j = o0; j < o1; ++j) {
-                    const int32_t y = rk_ids[j];
-                    const uint64_t bit = 1ull << (y & 63);
-                    if (!(cov[y >> 6] & bit)) {
-                        cov[y >> 6] |= bit;
-                        followers[nf] = y;
-                        follower_pivot[nf++] = x;
-                    }
-                }
+                visit(x, g);
                 bits &= ~cov[w];
-                if (np + nf - sent >= chunk) {
-                    emit(np, nf);
-                    sent = np + nf;
-                    chunk = std::max(chunk, std::min(2 * chunk, chunk_max));
-                }
             }
         }
-        std::vector<uint64_t>().swap(b);
     }
     if (np + nf > sent || sent == 0) emit(np, nf);
+    (void)n;
 }
 
 }  // namespace rnsm

@@ -234,6 +234,26 @@ def test_merge_ragged_multi_op_bit_exact(dev, orc, pkg, flags):
     _assert_same_merge(got, ref)
 
 
+def test_merge_hub_source_bit_exact(dev, orc, pkg):
+    # a source sub-index whose every vertex has the origin as its nearest
+    # neighbour (sign vectors scaled by 2: |x|^2 = 128 < |x - y|^2 ~ 256),
+    # so the origin's reverse k-NN list is far longer than the greedy's
+    # bitmap levels (its high-gain heap path)
+    g = inputs.rng(1401)
+    S = (2 * (2 * g.integers(0, 2, (700, 32)) - 1)).astype(np.float32)
+    S[0] = 0.0
+    T = inputs.tiny_int(900, 32, seed=1402)
+    X = np.ascontiguousarray(np.concatenate([S, T]))
+    subs = [orc.build_graph(X[:700], 24, 12, alpha=1.0), orc.build_graph(X[700:], 24, 12, alpha=1.0)]
+    ref = orc.merge(subs, X, R=12, L=24, alpha=1.2, trace=True)
+    got = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=12, L=24, alpha=1.2)
+    _assert_same_merge(got, ref)
+    st = pkg.stats()
+    assert st["n_pivots"] == ref["trace"]["n_pivots"]
+    nk = orc.expand(*subs[0][:2], X[:700], 5, 16)
+    assert (nk == 0).any(axis=1).sum() > 256  # the hub is in more than 256 N_k lists
+
+
 def test_merge_centroid_costs_bit_exact(dev, orc, pkg):
     sizes = [700, 1500, 900, 1100, 600, 1300]
     # slab partition along a random direction: centroids differ
