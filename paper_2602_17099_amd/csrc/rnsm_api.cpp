@@ -419,6 +419,13 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         HIPCHK(value_info(vecs->f32, N, vecs->dim, vr, st, &vinfo));
     }
     const int pmode = choose_prune(vinfo, vecs->dim, R);
+    // exact-mode prune: a bfloat16 copy of the rows (exact in it), half the
+    // bytes for the prune's gathers
+    char* xb16 = nullptr;
+    if (pmode == 1) {
+        WS(xb16, "prune_bf16", (size_t)2 * N * vecs->dim);
+        HIPCHK(launch_convert(vecs->f32, RNSM_F32, xb16, RNSM_BF16, N * vecs->dim, st));
+    }
     // search distances usable as prune keys: a float32 copy computes them
     // with the prune's own lane layout and order; a 16-bit copy only when
     // every distance is exact (integers exact in that type, exact sums)
@@ -897,6 +904,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         // source rows: current row + search results, pruned to R
         PruneArgs q = {};
         q.X = vecs->f32;
+        q.xb = xb16;
         q.n_total = N;
         q.nch = vi.nch32;
         q.G = vi.G32;
@@ -1164,6 +1172,11 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
         HIPCHK(value_info(X, n, dim, vr, st, &vinfo));
     }
     const int pmode = choose_prune(vinfo, dim, R);
+    char* xb16 = nullptr;
+    if (pmode == 1) {
+        WS(xb16, "b_prune_bf16", (size_t)2 * n * dim);
+        HIPCHK(launch_convert(X, RNSM_F32, xb16, RNSM_BF16, n * (int64_t)dim, st));
+    }
     HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
     if (metric == RNSM_COSINE) {
         WS(norms, "b_norms", sizeof(float) * n);
@@ -1171,6 +1184,7 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
     }
     PruneArgs q = {};
     q.X = X;
+    q.xb = xb16;
     q.n_total = n;
     q.nch = nch;
     q.G = G;

@@ -59,6 +59,9 @@ struct SearchArgs {
 
 struct PruneArgs {
     const float* X;           // float32 rows of every vertex (global ids)
+    const char* xb;           // bfloat16 copy of X (dim * 2 bytes a row): the MFMA prune in
+                              // exact mode (rows exact in bfloat16) reads this one
+    int G16, lgG16;           // lanes per row of the copy in the candidate distances
     int64_t n_total;          // number of rows of X (ids >= n_total are rejected)
     int nch;
     int G;                    // lanes per row (power of two)

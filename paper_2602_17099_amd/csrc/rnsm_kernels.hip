@@ -592,11 +592,14 @@ __device__ __forceinline__ void load_row_f32(const float* X, int64_t id, int row
 // plus the extra candidates, minus p itself. Keys (d(p, w), w) go to wk;
 // the ones whose float32 distance is already known (search results, reverse
 // edges, pruned rows) take it, the others are computed here with the lane
-// group layout. Then the keys are placed in (d, id) order into *ws_out.
+// group layout: from the float32 rows, or (B16) from the bfloat16 copy of
+// rows that are exact in it, with v_dot2 and squared L2 as |p|^2 + |w|^2 -
+// 2 p.w in double; every sum is then an exact integer, so both give the same
+// float. Then the keys are placed in (d, id) order into *ws_out.
 // Returns |W|, or -1 when the wavefront has nothing to do.
-template <int CPL>
+template <int CPL, bool B16>
 __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int64_t e, int lane,
-                                             u64* lkeys, u64** wk_out, u64** ws_out) {
+                                             u64* lws, u64* lwk, u64** wk_out, u64** ws_out) {
     const int R = a.R;
     const int G = a.G, RPP = WAVE >> a.lgG;
     const int nrow = a.rows_in ? a.deg_in[p] : 0;
@@ -611,8 +614,8 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
     }
     if (a.skip_empty_extra && next == 0) return -1;
     const int nW = nrow + next;
-    u64* wk = lkeys;
-    u64* ws = lkeys + a.wcap;
+    u64* wk = lwk;  // wcap keys each in LDS
+    u64* ws = lws;
     if (nW > a.wcap) {
         if (a.extra_mode != 2 || !a.scratch) {
             if (lane == 0) atomicOr(a.err, 2);
@@ -643,13 +646,66 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+    const float pn = a.metric == 2 ? a.norms[p] : 1.0f;
+    constexpr int UNR = 2;
+    if constexpr (B16) {
+        const int G16 = a.G16, RPP16 = WAVE >> a.lgG16;
+        const int group16 = lane >> a.lgG16, sub16 = lane & (G16 - 1);
+        const int64_t rowb = (int64_t)a.nch * 8;  // bytes of a bfloat16 row
+        const int64_t gs = (int64_t)G16 * 16;
+        uint4 pq[CPL];
+        float pp = 0.0f;
+        {
+            const char* r = a.xb + p * rowb + sub16 * 16;
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                pq[j] = *(const uint4*)(r + j * gs);
+                pp = dot2x4<1>(pq[j], pq[j], pp);
+            }
+        }
+        pp = group_sum_last(pp, G16);
+        for (int c0 = 0; c0 < nW; c0 += RPP16 * UNR) {
+            uint4 raw[UNR][CPL];
+            int cid[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int c = c0 + u * RPP16 + group16;
+                const u64 kk = c < nW ? wk[c] : EMPTY_KEY;
+                cid[u] = kk < (1ull << 32) ? (int)kk : -1;
+                if (cid[u] >= 0) {
+                    const char* r = a.xb + (int64_t)cid[u] * rowb + sub16 * 16;
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) raw[u][j] = *(const uint4*)(r + j * gs);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                float acc = 0.0f, xx = 0.0f;
+                if (cid[u] >= 0) {
+#pragma unroll
+                    for (int j = 0; j < CPL; ++j) {
+                        acc = dot2x4<1>(pq[j], raw[u][j], acc);
+                        xx = dot2x4<1>(raw[u][j], raw[u][j], xx);
+                    }
+                }
+                acc = group_sum_last(acc, G16);
+                xx = group_sum_last(xx, G16);
+                const int c = c0 + u * RPP16 + group16;
+                if (sub16 == G16 - 1 && cid[u] >= 0) {
+                    const float nb = a.metric == 2 ? a.norms[cid[u]] : 1.0f;
+                    const float d = a.metric == 0
+                                        ? (float)((double)pp + (double)xx - 2.0 * (double)acc)
+                                        : finalize_dist(acc, a.metric, pn, nb);
+                    wk[c] = make_key(d, cid[u]);
+                }
+            }
+        }
+    }
     const int group = lane >> a.lgG, sub = lane & (G - 1);
     const int rowf = a.nch * 4;
     float4 pq[CPL];
-    load_row_f32<CPL>(a.X, p, rowf, sub, G, pq);
-    const float pn = a.metric == 2 ? a.norms[p] : 1.0f;
-    constexpr int UNR = 2;
-    for (int c0 = 0; c0 < nW; c0 += RPP * UNR) {
+    if (!B16) load_row_f32<CPL>(a.X, p, rowf, sub, G, pq);
+    for (int c0 = 0; c0 < (B16 ? 0 : nW); c0 += RPP * UNR) {
         float4 raw[UNR][CPL];
         int cid[UNR];
 #pragma unroll
@@ -761,7 +817,7 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     const int R = a.R;
     const int G = a.G, RPP = WAVE >> a.lgG;
     u64 *wk, *ws;
-    const int nW = prune_collect<CPL>(a, p, e, lane, lkeys, &wk, &ws);
+    const int nW = prune_collect<CPL, false>(a, p, e, lane, lkeys + a.wcap, lkeys, &wk, &ws);
     if (nW < 0) return;
     (void)wk;
     const int group = lane >> a.lgG, sub = lane & (G - 1);
@@ -906,15 +962,16 @@ __device__ __forceinline__ int dom_threshold(double alpha, float d) {
     return ti;
 }
 
-// LDS bytes per wavefront of k_prune_mfma: keys and sorted keys, kept ids,
-// distances and squared norms, kept-row fragments (R rounded up to whole
-// 16-row tiles; hi, then lo with the split)
+// LDS bytes per wavefront of k_prune_mfma: sorted keys, kept ids, distances
+// and squared norms, then kept-row fragments (R rounded up to whole 16-row
+// tiles; hi, then lo with the split), whose space first holds the unsorted keys
 __host__ __device__ inline int mfma_row_stride(int kd) { return 64 * kd + 16; }
 __host__ __device__ inline int mfma_kept_rows(int R) { return (R + 15) & ~15; }
 __host__ __device__ inline size_t mfma_kept_bytes(int R) { return ((size_t)R * 12 + 15) / 16 * 16; }
 __host__ __device__ inline size_t mfma_prune_lds(int wcap, int R, int kd, int nt) {
-    return (size_t)2 * wcap * sizeof(u64) + mfma_kept_bytes(R) +
-           (size_t)mfma_kept_rows(R) * mfma_row_stride(kd) * (nt > 1 ? 2 : 1);
+    const size_t rows = (size_t)mfma_kept_rows(R) * mfma_row_stride(kd) * (nt > 1 ? 2 : 1);
+    const size_t keys = (size_t)wcap * sizeof(u64);
+    return keys + mfma_kept_bytes(R) + (rows > keys ? rows : keys);
 }
 
 // Prune(p, W) with the candidate x kept-row Gram products on bfloat16 MFMA.
@@ -929,6 +986,8 @@ __host__ __device__ inline size_t mfma_prune_lds(int wcap, int R, int kd, int nt
 //  NT == 1: rows exact in bfloat16 and every Gram and squared-norm sum
 //           exact in float32 (integers of magnitude <= 256, dim <= 256):
 //           every d(w, v) is exact, so every decision equals the walk's.
+//           The fragments are read from the bfloat16 copy (half the bytes
+//           of the float32 rows, the same values).
 //  NT == 3: rows split as hi + lo bfloat16, products hi*hi + hi*lo + lo*hi;
 //           squared L2 works on rows centred at p.
 template <int KD, int NT, int CPL>
@@ -943,16 +1002,17 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
     const int R = a.R;
     unsigned char* base = psm + (size_t)wib * mfma_prune_lds(a.wcap, R, KD, NT);
     u64* lkeys = (u64*)base;
-    int* kept_ids = (int*)(base + (size_t)2 * a.wcap * sizeof(u64));
+    int* kept_ids = (int*)(base + (size_t)a.wcap * sizeof(u64));
     float* kept_d = (float*)(kept_ids + R);
     float* kept_u = kept_d + R;
-    unsigned char* khi = base + (size_t)2 * a.wcap * sizeof(u64) + mfma_kept_bytes(R);
+    unsigned char* khi = base + (size_t)a.wcap * sizeof(u64) + mfma_kept_bytes(R);
     const int rs = mfma_row_stride(KD);
     const size_t klo_off = (size_t)mfma_kept_rows(R) * rs;  // lo fragments follow the hi ones
     const int64_t p = a.item_base + (a.items ? (int64_t)a.items[i] : i);
     const int64_t e = p - a.extra_index_base;
     u64 *wk, *ws;
-    const int nW = prune_collect<CPL>(a, p, e, lane, lkeys, &wk, &ws);
+    // the unsorted keys share the kept rows' space: they are dead once sorted
+    const int nW = prune_collect<CPL, NT == 1>(a, p, e, lane, lkeys, (u64*)khi, &wk, &ws);
     if (nW < 0) return;
     (void)wk;
 
@@ -981,7 +1041,7 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
     auto load_tile = [&](int J, float* raw) {
         const int c = J * 16 + jr;
         const u64 kk = c < nW ? ws[c] : EMPTY_KEY;
-        if (kk != EMPTY_KEY) {
+        if (NT != 1 && kk != EMPTY_KEY) {
             const float4* r = (const float4*)(a.X + (int64_t)(unsigned)(kk & 0xffffffffu) * dim + q * DL);
 #pragma unroll
             for (int t = 0; t < DL / 4; ++t) {
@@ -996,8 +1056,28 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
             for (int t = 0; t < DL; ++t) raw[t] = 0.0f;
         }
     };
-    float raw[DL];
-    load_tile(0, raw);
+    // exact mode: the same DL dimensions as KD packed bfloat16 fragments,
+    // read from the bfloat16 copy
+    const int64_t rowb = (int64_t)dim * 2;
+    auto load_frag = [&](int J, uint4* fr) {
+        const int c = J * 16 + jr;
+        const u64 kk = c < nW ? ws[c] : EMPTY_KEY;
+        if (kk != EMPTY_KEY) {
+            const uint4* r = (const uint4*)(a.xb + (int64_t)(unsigned)(kk & 0xffffffffu) * rowb +
+                                            q * DL * 2);
+#pragma unroll
+            for (int t = 0; t < KD; ++t) fr[t] = r[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < KD; ++t) fr[t] = make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    float raw[NT == 1 ? 1 : DL];
+    uint4 frag[NT == 1 ? KD : 1];
+    if constexpr (NT == 1)
+        load_frag(0, frag);
+    else
+        load_tile(0, raw);
     int nk = 0;
     u64 prev = EMPTY_KEY;
     const int ntiles = (nW + 15) >> 4;
@@ -1009,15 +1089,24 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
         const float nj = (metric == 2 && idj >= 0) ? a.norms[idj] : 1.0f;
         uint4 hi[KD], lo[KD];
         float sq = 0.0f;  // squared norm of the plain row (exact for NT == 1)
+        if constexpr (NT == 1) {
 #pragma unroll
-        for (int s2 = 0; s2 < KD; ++s2) {
-            float v[8];
-#pragma unroll
-            for (int e2 = 0; e2 < 8; ++e2) {
-                v[e2] = CENTER ? raw[8 * s2 + e2] - pf[CENTER ? 8 * s2 + e2 : 0] : raw[8 * s2 + e2];
-                if constexpr (!CENTER) sq = fmaf(v[e2], v[e2], sq);
+            for (int s2 = 0; s2 < KD; ++s2) {
+                hi[s2] = frag[s2];
+                lo[s2] = make_uint4(0u, 0u, 0u, 0u);
+                sq = dot2x4<1>(hi[s2], hi[s2], sq);
             }
-            split8<NT>(v, hi[s2], lo[s2]);
+        } else {
+#pragma unroll
+            for (int s2 = 0; s2 < KD; ++s2) {
+                float v[8];
+#pragma unroll
+                for (int e2 = 0; e2 < 8; ++e2) {
+                    v[e2] = CENTER ? raw[8 * s2 + e2] - pf[CENTER ? 8 * s2 + e2 : 0] : raw[8 * s2 + e2];
+                    if constexpr (!CENTER) sq = fmaf(v[e2], v[e2], sq);
+                }
+                split8<NT>(v, hi[s2], lo[s2]);
+            }
         }
         float uj = dj;
         if constexpr (!CENTER) {
@@ -1030,7 +1119,12 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
         const bool intd = NT == 1 && metric != 2;
         const int tj = intd ? dom_threshold(alpha, dj) : 0;
         const int uji = intd && metric == 0 ? (int)uj : 0;
-        if (J + 1 < ntiles) load_tile(J + 1, raw);  // next tile's rows in flight
+        if (J + 1 < ntiles) {  // next tile's rows in flight
+            if constexpr (NT == 1)
+                load_frag(J + 1, frag);
+            else
+                load_tile(J + 1, raw);
+        }
 
         // the tile with itself: pairs (i, j), i = 4 q + r, j = l % 16, i < j
         floatx4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -1888,17 +1982,24 @@ hipError_t launch_prune_mfma(const PruneArgs& a, int nt, hipStream_t st) {
     if (a.n_items <= 0) return hipSuccess;
     const int dim = a.nch * 4;
     if (!prune_mfma_fits(a, nt) || (nt != 1 && nt != 3)) return hipErrorInvalidValue;
+    if (nt == 1 && !a.xb) return hipErrorInvalidValue;
     const int kd = dim / 32;
+    PruneArgs b = a;
+    // bfloat16 layout of prune_collect: dim / 8 chunks, as many per lane as
+    // the float32 layout has (kd = 1, 2, 4: 4; kd = 3: 3)
+    b.G16 = lanes_per_row(dim / 8);
+    b.lgG16 = ilog2i(b.G16);
     const size_t per = mfma_prune_lds(a.wcap, a.R, kd, nt);
     const int wpb = per <= 32 * 1024 ? 2 : 1;
     const size_t lds = (size_t)wpb * per;
     const dim3 grid(nblk(a.n_items, wpb)), block(wpb * WAVE);
     // the candidate-distance layout of prune_collect for dim = 32 kd
+    if (b.G16 < 1 || (dim / 8) / b.G16 != (kd == 3 ? 3 : 4)) return hipErrorInvalidValue;
     switch (kd) {
-        case 1: launch_prune_mfma_c<1, 4>(a, nt, grid, block, lds, st); break;
-        case 2: launch_prune_mfma_c<2, 4>(a, nt, grid, block, lds, st); break;
-        case 3: launch_prune_mfma_c<3, 3>(a, nt, grid, block, lds, st); break;
-        default: launch_prune_mfma_c<4, 4>(a, nt, grid, block, lds, st); break;
+        case 1: launch_prune_mfma_c<1, 4>(b, nt, grid, block, lds, st); break;
+        case 2: launch_prune_mfma_c<2, 4>(b, nt, grid, block, lds, st); break;
+        case 3: launch_prune_mfma_c<3, 3>(b, nt, grid, block, lds, st); break;
+        default: launch_prune_mfma_c<4, 4>(b, nt, grid, block, lds, st); break;
     }
     return hipGetLastError();
 }
