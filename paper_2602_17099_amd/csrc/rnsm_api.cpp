@@ -267,6 +267,12 @@ hipError_t run_prune(const PruneArgs& a, int mode, hipStream_t st) {
     return launch_prune(a, st);
 }
 
+// run_prune(a, mode) takes its candidate distances from the bfloat16 copy
+bool prune_reads_b16(const PruneArgs& a, int mode) { return mode == 1 && prune_mfma_fits(a, 1); }
+
+// LDS key capacity of a merge's target prune (longer candidate lists use scratch)
+constexpr int TARGET_WCAP = 256;
+
 }  // namespace
 
 extern "C" {
@@ -541,6 +547,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         int32_t* h_ids = nullptr;
         const bool fresh = cached[s].empty() && !(p->flags & RNSM_FLAG_ALL_PIVOTS);
         int ev_rk_off = -1, ev_rk_ids = -1, ev_rk_cnt = -1;
+        int ev_go = -1;  // st: result rows cleared; the side stream starts after it
         int32_t* h_cnt = nullptr;
         if (fresh) {
             int32_t *nk, *rcnt, *rk_ids;
@@ -560,8 +567,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
                 unsigned *bfs_tail, *h_tail;
                 WS(bfs_order, "bfs_order", sizeof(int32_t) * ns);
                 WS(bfs_vis, "bfs_visited", sizeof(unsigned) * ((ns + 31) / 32));
-                WS(bfs_tail, "bfs_tail", sizeof(unsigned));
-                HS(h_tail, "h_bfs_tail", sizeof(unsigned));
+                WS(bfs_tail, "bfs_ctl", 4 * sizeof(unsigned));
+                HS(h_tail, "h_bfs_ctl", 4 * sizeof(unsigned));
                 HS(h_bfs, "h_bfs_order", sizeof(int32_t) * ns);
                 HIPCHK(launch_bfs_order(padj + bases[s] * R, R, ns, graphs[s].entry, bfs_vis,
                                         bfs_order, bfs_tail, h_tail, st));
@@ -627,6 +634,32 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             HIPCHK(E.record(st, &ev_rk_off));
             HIPCHK(hipMemcpyAsync(h_ids, rk_ids, sizeof(int32_t) * ns * k, hipMemcpyDeviceToHost, st));
             HIPCHK(E.record(st, &ev_rk_ids));
+            HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));
+            HIPCHK(E.record(st, &ev_go));
+            if (!touched[t]) {
+                // the target rows are still the input rows: their distances,
+                // which the target prune needs, are computed while the host
+                // selects the first pivots (the side stream does not wait)
+                PruneArgs rd = {};
+                rd.X = vecs->f32;
+                rd.xb = xb16;
+                rd.n_total = N;
+                rd.nch = vi.nch32;
+                rd.G = vi.G32;
+                rd.lgG = ilog2i(vi.G32);
+                rd.cpl = vi.cpl32;
+                rd.metric = p->metric;
+                rd.norms = norms;
+                rd.n_items = nt;
+                rd.item_base = bases[t];
+                rd.rows_in = rows;
+                rd.deg_in = deg;
+                rd.rows_d = rdist;
+                rd.R = R;
+                rd.wcap = TARGET_WCAP;
+                rd.err = errf;
+                HIPCHK(launch_row_dists(rd, prune_reads_b16(rd, pmode), st));
+            }
             if (use_bfs) {
                 // ranks on the host while the expansion runs
                 HIPCHK(hipEventSynchronize(E.ev[ev_order]));
@@ -650,7 +683,10 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         const auto th1 = std::chrono::steady_clock::now();
         if (fresh) build_levels(ns, h_cnt, levels);
         double th_levels = 0, th_ids = 0, th_first_post = -1, th_first_launch = -1;
-        HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));
+        if (!fresh) {
+            HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));
+            HIPCHK(E.record(st, &ev_go));
+        }
 
         // search arguments shared by the chunks
         SearchArgs a = {};
@@ -704,9 +740,45 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         // search of chunk c+1 overlaps the sliding search of chunk c
         hipStream_t sd;
         HIPCHK(ws.side_stream(&sd));
-        int ev_go;
-        HIPCHK(E.record(st, &ev_go));
         HIPCHK(hipStreamWaitEvent(sd, E.ev[ev_go], 0));
+        // source rows: current row + search results, pruned to R after the
+        // searches, each pivot group together (order staged with the chunks).
+        // (Pruning each chunk on a third stream as soon as its searches end
+        // measured no faster: the prune waves take the LDS and CU slots the
+        // searches of later chunks would use.)
+        int32_t *h_order, *d_order;
+        HS(h_order, "h_order", sizeof(int32_t) * ns);
+        WS(d_order, "prune_order", sizeof(int32_t) * ns);
+        PruneArgs qs = {};
+        qs.X = vecs->f32;
+        qs.xb = xb16;
+        qs.n_total = N;
+        qs.nch = vi.nch32;
+        qs.G = vi.G32;
+        qs.lgG = ilog2i(vi.G32);
+        qs.cpl = vi.cpl32;
+        qs.metric = p->metric;
+        qs.norms = norms;
+        qs.item_base = bases[s];
+        qs.rows_in = rows;
+        qs.deg_in = deg;
+        qs.rows_d = rdist;
+        qs.extra_mode = 1;
+        qs.extra_ids = res;
+        qs.extra_d = search_d_exact ? res_d : nullptr;
+        qs.extra_sorted = search_d_exact && RES <= 128;  // beams in key order
+        qs.extra_stride = RES;
+        qs.extra_cnt = RES;
+        qs.extra_index_base = bases[s];
+        qs.extra_id_add = bases[t];
+        qs.alpha = p->alpha;
+        qs.R = R;
+        qs.rows_out = rows;
+        qs.deg_out = deg;
+        qs.dist_out = rdist;
+        qs.wcap = R + RES;
+        qs.err = errf;
+        bool groups_ok = true;
         int64_t pa = 0, fa = 0;  // list prefixes already handed to the device
         int64_t n_launch_a = 0, n_launch_b = 0;
         hipError_t cerr = hipSuccess;
@@ -752,6 +824,22 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         auto emit = [&](int64_t np, int64_t nf) {
             if (cerr != hipSuccess) return;
             stage(np, nf);
+            // prune order of the chunk: each pivot followed by its followers,
+            // so that neighbouring wavefronts share most candidate rows in L2
+            const int64_t o0 = pa + fa;
+            {
+                int64_t o = o0, f = fa;
+                for (int64_t i = pa; i < np; ++i) {
+                    const int32_t pv = h_lp[i];
+                    h_order[o++] = pv;
+                    while (f < nf && h_lfp[f] == pv) h_order[o++] = h_lf[f++];
+                }
+                if (f != nf) {
+                    groups_ok = false;
+                    if (cerr == hipSuccess) cerr = hipErrorInvalidValue;
+                    return;
+                }
+            }
             std::array<int, 4> ce;
             auto chk = [&](hipError_t e) {
                 if (e != hipSuccess && cerr == hipSuccess) cerr = e;
@@ -767,6 +855,9 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
                                         hipMemcpyHostToDevice, sd)))
                     return;
             }
+            if (!chk(hipMemcpyAsync(d_order + o0, h_order + o0, sizeof(int32_t) * (np + nf - o0),
+                                    hipMemcpyHostToDevice, sd)))
+                return;
             if (!chk(E.record(sd, &ce[0]))) return;
             SearchArgs x = aA;
             x.qidx = d_piv + pa;
@@ -877,62 +968,23 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             ev_span.push_back({ev_chunk[chunk0][0], ev_chunk.back()[3]});
         if (cerr != hipSuccess) {
             (void)hipStreamSynchronize(sd);
+            (void)hipStreamSynchronize(st);
+            if (!groups_ok)
+                return fail(RNSM_EINTERNAL, "rnsm_merge: pivot groups do not cover the source");
             return fail(cerr == hipErrorOutOfMemory ? RNSM_ENOMEM : RNSM_EDEVICE,
                         "rnsm_merge: queueing searches: %s", hipGetErrorString(cerr));
         }
+        if (pa + fa != ns)
+            return fail(RNSM_EINTERNAL, "rnsm_merge: pivot groups do not cover the source");
         g_stats.queries[1] += np;
         g_stats.queries[2] += nf;
-        // source prune order: each pivot followed by its followers, so that
-        // neighbouring wavefronts share most candidate rows in L2
-        int32_t *h_order, *d_order;
-        HS(h_order, "h_order", sizeof(int32_t) * ns);
-        WS(d_order, "prune_order", sizeof(int32_t) * ns);
-        {
-            int64_t o = 0, f = 0;
-            for (int64_t i = 0; i < np; ++i) {
-                const int32_t pv = h_lp[i];
-                h_order[o++] = pv;
-                while (f < nf && h_lfp[f] == pv) h_order[o++] = h_lf[f++];
-            }
-            if (o != ns || f != nf)
-                return fail(RNSM_EINTERNAL, "rnsm_merge: pivot groups do not cover the source");
-            HIPCHK(hipMemcpyAsync(d_order, h_order, sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
-        }
-
+        // source prune, in the order staged with the chunks (the copies on
+        // the side stream precede the last sliding search, which st waited for)
         std::array<int, 2> pe;
         HIPCHK(E.record(st, &pe[0]));
-        // source rows: current row + search results, pruned to R
-        PruneArgs q = {};
-        q.X = vecs->f32;
-        q.xb = xb16;
-        q.n_total = N;
-        q.nch = vi.nch32;
-        q.G = vi.G32;
-        q.lgG = ilog2i(vi.G32);
-        q.cpl = vi.cpl32;
-        q.metric = p->metric;
-        q.norms = norms;
-        q.n_items = ns;
+        PruneArgs q = qs;
         q.items = d_order;
-        q.item_base = bases[s];
-        q.rows_in = rows;
-        q.deg_in = deg;
-        q.rows_d = rdist;
-        q.extra_mode = 1;
-        q.extra_ids = res;
-        q.extra_d = search_d_exact ? res_d : nullptr;
-        q.extra_sorted = search_d_exact && RES <= 128;  // beams in key order
-        q.extra_stride = RES;
-        q.extra_cnt = RES;
-        q.extra_index_base = bases[s];
-        q.extra_id_add = bases[t];
-        q.alpha = p->alpha;
-        q.R = R;
-        q.rows_out = rows;
-        q.deg_out = deg;
-        q.dist_out = rdist;
-        q.wcap = R + RES;
-        q.err = errf;
+        q.n_items = ns;
         HIPCHK(run_prune(q, pmode, st));
         // reverse edges into the target, then prune every target that got some
         int32_t *rc, *rcur, *rev;
@@ -965,7 +1017,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         r.skip_empty_extra = 1;
         r.extra_sorted = 0;
         r.scratch = scratch;
-        r.wcap = 256;
+        r.wcap = TARGET_WCAP;
         HIPCHK(run_prune(r, pmode, st));
         HIPCHK(E.record(st, &pe[1]));
         ev_prune.push_back(pe);

@@ -118,6 +118,9 @@ hipError_t launch_prune(const PruneArgs& a, hipStream_t st);
 // nt = 3 (hi/lo split) otherwise
 bool prune_mfma_supported(int dim);
 bool prune_mfma_fits(const PruneArgs& a, int nt);  // dimension, R and LDS size
+// missing distances of the rows of a prune's vertices, as that prune would
+// compute them (b16: the MFMA prune in exact mode, reading the bfloat16 copy)
+hipError_t launch_row_dists(const PruneArgs& a, bool b16, hipStream_t st);
 hipError_t launch_prune_mfma(const PruneArgs& a, int nt, hipStream_t st);
 // out[0] = 1 if every value is an integer, out[1] / out[2] = order-preserving
 // bits of min / max (key_to_float gives the value back)
@@ -158,10 +161,12 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
                         hipStream_t st);
 int64_t entry_blocks(int64_t n);
 // breadth-first vertex order of a padded-adjacency graph from root (a
-// processing order only); vis: (n + 31) / 32 words of scratch, tail: one
-// device counter, h_tail: pinned host word; synchronises st once per level
+// processing order only); vis: (n + 31) / 32 words of scratch, ctl: 4 device
+// words (order tail, frontier start and end, finished blocks), h_ctl: 4
+// pinned host words; synchronises st once per batch of BFS_BATCH levels
+#define BFS_BATCH 8
 hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, unsigned* vis,
-                            int32_t* order, unsigned* tail, unsigned* h_tail, hipStream_t st);
+                            int32_t* order, unsigned* ctl, unsigned* h_ctl, hipStream_t st);
 
 // lanes per row for rows of nch 16-byte chunks: the smallest power of two G
 // with 4*G >= nch that divides nch, so that every lane holds nch/G <= 4 whole

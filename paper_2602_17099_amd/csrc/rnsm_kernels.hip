@@ -588,64 +588,14 @@ __device__ __forceinline__ void load_row_f32(const float* X, int64_t id, int row
     }
 }
 
-// Candidate list W of the prune of p (Section 2.2): the current row of p
-// plus the extra candidates, minus p itself. Keys (d(p, w), w) go to wk;
-// the ones whose float32 distance is already known (search results, reverse
-// edges, pruned rows) take it, the others are computed here with the lane
-// group layout: from the float32 rows, or (B16) from the bfloat16 copy of
-// rows that are exact in it, with v_dot2 and squared L2 as |p|^2 + |w|^2 -
-// 2 p.w in double; every sum is then an exact integer, so both give the same
-// float. Then the keys are placed in (d, id) order into *ws_out.
-// Returns |W|, or -1 when the wavefront has nothing to do.
+// the distances still missing in the keys wk[0, nW) of vertex p (a key with
+// the id alone, < 2^32), computed with the lane-group layout: from the
+// float32 rows, or (B16) from the bfloat16 copy of rows that are exact in it,
+// with v_dot2 and squared L2 as |p|^2 + |w|^2 - 2 p.w in double; every sum is
+// then an exact integer, so both give the same float
 template <int CPL, bool B16>
-__device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int64_t e, int lane,
-                                             u64* lws, u64* lwk, u64** wk_out, u64** ws_out) {
-    const int R = a.R;
-    const int G = a.G, RPP = WAVE >> a.lgG;
-    const int nrow = a.rows_in ? a.deg_in[p] : 0;
-    int next = 0;
-    int64_t xo = 0;
-    if (a.extra_mode == 1) {
-        next = a.extra_cnt;
-        xo = e * a.extra_stride;
-    } else if (a.extra_mode == 2) {
-        xo = a.extra_off[e];
-        next = (int)(a.extra_off[e + 1] - xo);
-    }
-    if (a.skip_empty_extra && next == 0) return -1;
-    const int nW = nrow + next;
-    u64* wk = lwk;  // wcap keys each in LDS
-    u64* ws = lws;
-    if (nW > a.wcap) {
-        if (a.extra_mode != 2 || !a.scratch) {
-            if (lane == 0) atomicOr(a.err, 2);
-            return -1;
-        }
-        wk = a.scratch + 2 * ((int64_t)R * e + xo);
-        ws = wk + nW;
-    }
-    for (int t = lane; t < nW; t += WAVE) {
-        int64_t id;
-        float d = __int_as_float(0x7fc00000);
-        if (t < nrow) {
-            id = a.rows_in[p * R + t];
-            if (a.rows_d) d = a.rows_d[p * R + t];
-        } else {
-            const int32_t x = a.extra_ids[xo + (t - nrow)];
-            id = x < 0 ? -1 : (int64_t)x + a.extra_id_add;
-            if (a.extra_d) d = a.extra_d[xo + (t - nrow)];
-        }
-        if (id >= a.n_total) {  // ids from callers are range-checked
-            atomicOr(a.err, 4);
-            id = -1;
-        }
-        // a key with the id alone (< 2^32) marks a distance still to compute
-        wk[t] = (id < 0 || id == p) ? EMPTY_KEY : (d == d ? make_key(d, (int)id) : (u64)id);
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
+__device__ __forceinline__ void collect_dists(const PruneArgs& a, int64_t p, u64* wk, int nW,
+                                              int lane) {
     const float pn = a.metric == 2 ? a.norms[p] : 1.0f;
     constexpr int UNR = 2;
     if constexpr (B16) {
@@ -701,6 +651,7 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
             }
         }
     }
+    const int G = a.G, RPP = WAVE >> a.lgG;
     const int group = lane >> a.lgG, sub = lane & (G - 1);
     const int rowf = a.nch * 4;
     float4 pq[CPL];
@@ -725,6 +676,64 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
             }
         }
     }
+}
+
+// Candidate list W of the prune of p (Section 2.2): the current row of p
+// plus the extra candidates, minus p itself. Keys (d(p, w), w) go to wk;
+// the ones whose float32 distance is already known (search results, reverse
+// edges, pruned rows) take it, the others are computed here (collect_dists).
+// Then the keys are placed in (d, id) order into *ws_out.
+// Returns |W|, or -1 when the wavefront has nothing to do.
+template <int CPL, bool B16>
+__device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int64_t e, int lane,
+                                             u64* lws, u64* lwk, u64** wk_out, u64** ws_out) {
+    const int R = a.R;
+    const int G = a.G, RPP = WAVE >> a.lgG;
+    const int nrow = a.rows_in ? a.deg_in[p] : 0;
+    int next = 0;
+    int64_t xo = 0;
+    if (a.extra_mode == 1) {
+        next = a.extra_cnt;
+        xo = e * a.extra_stride;
+    } else if (a.extra_mode == 2) {
+        xo = a.extra_off[e];
+        next = (int)(a.extra_off[e + 1] - xo);
+    }
+    if (a.skip_empty_extra && next == 0) return -1;
+    const int nW = nrow + next;
+    u64* wk = lwk;  // wcap keys each in LDS
+    u64* ws = lws;
+    if (nW > a.wcap) {
+        if (a.extra_mode != 2 || !a.scratch) {
+            if (lane == 0) atomicOr(a.err, 2);
+            return -1;
+        }
+        wk = a.scratch + 2 * ((int64_t)R * e + xo);
+        ws = wk + nW;
+    }
+    for (int t = lane; t < nW; t += WAVE) {
+        int64_t id;
+        float d = __int_as_float(0x7fc00000);
+        if (t < nrow) {
+            id = a.rows_in[p * R + t];
+            if (a.rows_d) d = a.rows_d[p * R + t];
+        } else {
+            const int32_t x = a.extra_ids[xo + (t - nrow)];
+            id = x < 0 ? -1 : (int64_t)x + a.extra_id_add;
+            if (a.extra_d) d = a.extra_d[xo + (t - nrow)];
+        }
+        if (id >= a.n_total) {  // ids from callers are range-checked
+            atomicOr(a.err, 4);
+            id = -1;
+        }
+        // a key with the id alone (< 2^32) marks a distance still to compute
+        wk[t] = (id < 0 || id == p) ? EMPTY_KEY : (d == d ? make_key(d, (int)id) : (u64)id);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    collect_dists<CPL, B16>(a, p, wk, nW, lane);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -795,6 +804,40 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
     *wk_out = wk;
     *ws_out = ws;
     return nW;
+}
+
+// distances of the rows of vertices item_base + [0, n_items) to their entries
+// (rows_in / deg_in), written to rows_d where it holds NaN, computed by
+// collect_dists exactly as a later prune of these vertices would compute
+// them (same layout, same arithmetic), so that the prune finds them known.
+// One wavefront per vertex, rows of at most 64 entries.
+template <int CPL, bool B16>
+__global__ __launch_bounds__(256) void k_row_dists(PruneArgs a) {
+    __shared__ u64 keys[4][WAVE];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int64_t i = xcd_block() * (blockDim.x >> 6) + wib;
+    if (i >= a.n_items) return;
+    const int64_t p = a.item_base + i;
+    const int R = a.R;
+    const int nrow = a.deg_in[p];
+    float* rd = (float*)a.rows_d + p * R;
+    u64* wk = keys[wib];
+    bool todo = false;
+    if (lane < nrow) {
+        const int id = a.rows_in[p * R + lane];
+        todo = rd[lane] != rd[lane] && id >= 0 && id < a.n_total && id != p;
+        wk[lane] = todo ? (u64)(unsigned)id : EMPTY_KEY;
+    }
+    if (__ballot(todo) == 0ull) return;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    collect_dists<CPL, B16>(a, p, wk, nrow, lane);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (todo) rd[lane] = fval((unsigned)(wk[lane] >> 32));
 }
 
 // Prune(p, W) with float32 vector arithmetic: candidates are walked in
@@ -1297,14 +1340,19 @@ __global__ void k_pad_adjacency(const int64_t* offs, const int32_t* nbrs, int64_
 // depends on it. order[0..n) receives every vertex once. The visited set is a
 // bitmap of n bits (small enough to stay in L2); a plain read filters out
 // most visited neighbours before the atomic.
-__global__ void k_bfs_init(int64_t n, int32_t root, unsigned* vis, int32_t* order, unsigned* tail) {
+// ctl: [0] order tail, [1] [2] current frontier order[s, e), [3] blocks of
+// the running level that have finished
+__global__ void k_bfs_init(int64_t n, int32_t root, unsigned* vis, int32_t* order, unsigned* ctl) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t words = (n + 31) >> 5;
     if (t >= words) return;
     vis[t] = t == (root >> 5) ? 1u << (root & 31) : 0u;
     if (t == 0) {
         order[0] = root;
-        *tail = 1u;
+        ctl[0] = 1u;
+        ctl[1] = 0u;
+        ctl[2] = 1u;
+        ctl[3] = 0u;
     }
 }
 
@@ -1332,23 +1380,42 @@ __device__ __forceinline__ void block_append(bool flag, int32_t val, int32_t* or
     if (flag) order[bbase + wcount[wid] + __popcll(m & lanemask_lt(lane))] = val;
 }
 
-// frontier order[s, e): one thread per (vertex, slot)
+// one level: the frontier order[ctl[1], ctl[2]), one thread per (vertex,
+// slot) over a fixed grid (block-uniform strides, so every thread of a block
+// takes part in each append). The last block to finish makes the appended
+// vertices the next frontier, so levels follow one another on the stream
+// without the host; a level with an empty frontier does nothing.
 __global__ __launch_bounds__(BFS_T) void k_bfs_level(const int32_t* padj, int rp, int64_t n,
-                                                     int32_t* order, int64_t s, int64_t e,
-                                                     unsigned* vis, unsigned* tail) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool found = false;
-    int32_t w = -1;
-    if (t < (e - s) * rp) {
-        const int32_t u = order[s + t / rp];
-        w = padj[(int64_t)u * rp + (int)(t % rp)];
-        if (w >= 0 && w < n) {
-            const unsigned bit = 1u << (w & 31);
-            if (!(__atomic_load_n(&vis[w >> 5], __ATOMIC_RELAXED) & bit))
-                found = !(atomicOr(&vis[w >> 5], bit) & bit);
+                                                     int32_t* order, unsigned* vis, unsigned* ctl) {
+    const int64_t s = ctl[1], e = ctl[2];
+    const int64_t total = (e - s) * rp;
+    for (int64_t b0 = (int64_t)blockIdx.x * BFS_T; b0 < total; b0 += (int64_t)gridDim.x * BFS_T) {
+        const int64_t t = b0 + threadIdx.x;
+        bool found = false;
+        int32_t w = -1;
+        if (t < total) {
+            const int32_t u = order[s + t / rp];
+            w = padj[(int64_t)u * rp + (int)(t % rp)];
+            if (w >= 0 && w < n) {
+                const unsigned bit = 1u << (w & 31);
+                if (!(__atomic_load_n(&vis[w >> 5], __ATOMIC_RELAXED) & bit))
+                    found = !(atomicOr(&vis[w >> 5], bit) & bit);
+            }
+        }
+        block_append(found, w, order, ctl);
+        __syncthreads();  // bbase and wcount are reused by the next stride
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&ctl[3], 1u) == gridDim.x - 1) {
+            // every block has read the bounds and made its appends
+            __threadfence();
+            const unsigned t = atomicAdd(&ctl[0], 0u);
+            atomicExch(&ctl[1], (unsigned)e);
+            atomicExch(&ctl[2], t);
+            atomicExch(&ctl[3], 0u);
         }
     }
-    block_append(found, w, order, tail);
 }
 
 // vertices no level reached, after the others
@@ -1853,25 +1920,28 @@ __global__ __launch_bounds__(ENTRY_T) void k_entry_crit(const float* X, int64_t 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, unsigned* vis,
-                            int32_t* order, unsigned* tail, unsigned* h_tail, hipStream_t st) {
+                            int32_t* order, unsigned* ctl, unsigned* h_ctl, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (root < 0 || root >= n) root = 0;
     hipLaunchKernelGGL(k_bfs_init, dim3(nblk((n + 31) >> 5, 256)), dim3(256), 0, st, n, root, vis,
-                       order, tail);
+                       order, ctl);
     hipError_t e = hipGetLastError();
-    int64_t s0 = 0, e0 = 1;
-    while (e0 > s0 && e0 < n) {
-        hipLaunchKernelGGL(k_bfs_level, dim3(nblk((e0 - s0) * rp, BFS_T)), dim3(BFS_T), 0, st, padj, rp,
-                           n, order, s0, e0, vis, tail);
+    // at most one thread per (vertex, slot) of the largest possible frontier
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nblk(n * rp, BFS_T), 512));
+    for (;;) {
+        for (int l = 0; l < BFS_BATCH; ++l)
+            hipLaunchKernelGGL(k_bfs_level, dim3((unsigned)grid), dim3(BFS_T), 0, st, padj, rp, n,
+                               order, vis, ctl);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(h_tail, tail, sizeof(unsigned), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        if ((e = hipMemcpyAsync(h_ctl, ctl, 3 * sizeof(unsigned), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess)
             return e;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-        s0 = e0;
-        e0 = (int64_t)*h_tail;
+        // stop once the frontier is empty (every reachable vertex ordered)
+        if (h_ctl[2] <= h_ctl[1] || (int64_t)h_ctl[0] > n) break;
     }
-    if (e0 < n) {
-        hipLaunchKernelGGL(k_bfs_rest, dim3(nblk(n, BFS_T)), dim3(BFS_T), 0, st, n, vis, order, tail);
+    if ((int64_t)h_ctl[0] < n) {
+        hipLaunchKernelGGL(k_bfs_rest, dim3(nblk(n, BFS_T)), dim3(BFS_T), 0, st, n, vis, order, ctl);
         e = hipGetLastError();
     }
     return e;
@@ -2000,6 +2070,32 @@ hipError_t launch_prune_mfma(const PruneArgs& a, int nt, hipStream_t st) {
         case 2: launch_prune_mfma_c<2, 4>(b, nt, grid, block, lds, st); break;
         case 3: launch_prune_mfma_c<3, 3>(b, nt, grid, block, lds, st); break;
         default: launch_prune_mfma_c<4, 4>(b, nt, grid, block, lds, st); break;
+    }
+    return hipGetLastError();
+}
+
+template <int CPL>
+static void launch_row_dists_c(const PruneArgs& a, bool b16, dim3 grid, dim3 block, hipStream_t st) {
+    if (b16)
+        hipLaunchKernelGGL((k_row_dists<CPL, true>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_row_dists<CPL, false>), grid, block, 0, st, a);
+}
+
+hipError_t launch_row_dists(const PruneArgs& a, bool b16, hipStream_t st) {
+    if (a.n_items <= 0) return hipSuccess;
+    if (a.R > WAVE || !a.rows_d || (b16 && !a.xb)) return hipErrorInvalidValue;
+    PruneArgs b = a;
+    b.G16 = lanes_per_row(a.nch / 2);
+    b.lgG16 = ilog2i(b.G16);
+    // the bfloat16 layout takes as many chunks per lane as the float32 one
+    if (b16 && (b.G16 < 1 || (a.nch / 2) / b.G16 != a.cpl)) return hipErrorInvalidValue;
+    const dim3 grid(nblk(a.n_items, 4)), block(4 * WAVE);
+    switch (a.cpl) {
+        case 1: launch_row_dists_c<1>(b, b16, grid, block, st); break;
+        case 2: launch_row_dists_c<2>(b, b16, grid, block, st); break;
+        case 3: launch_row_dists_c<3>(b, b16, grid, block, st); break;
+        default: launch_row_dists_c<4>(b, b16, grid, block, st); break;
     }
     return hipGetLastError();
 }
