@@ -34,7 +34,11 @@ PEAK_HBM_GBS = 8000.0
 # hold for the sources they were taken on only (sha256 of the files below).
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
-SEARCH_COUNTERS = None  # {"sources_sha256": ..., "fetch_kib": [...], "write_kib": [...]}
+SEARCH_COUNTERS = {
+    "sources_sha256": "82a903fcc7f8134fa48d5f0f0e0593c485fa20efb27a924bf9aaf60018214a21",
+    "fetch_kib": [29544956.062, 6844.75, 609025.312, 16097.062, 1266767.5, 41078.375, 3073633.25, 140842.625, 6372472.938, 246179.5, 9138936.062, 432189.312, 10051725.188, 847324.938, 11609219.375, 1932155.562, 13012176.438, 6115432.812, 12696854.25, 21375242.25, 2140187.812, 2763733.0],
+    "write_kib": [177452.906, 8.125, 4910.625, 25.0, 9851.875, 72.5, 19501.875, 247.5, 38840.0, 435.0, 38661.25, 775.625, 38301.25, 1491.25, 37578.75, 3314.375, 35752.5, 10318.125, 28744.375, 34956.25, 4106.25, 4607.5],
+}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
