@@ -548,7 +548,17 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         const bool fresh = cached[s].empty() && !(p->flags & RNSM_FLAG_ALL_PIVOTS);
         int ev_rk_off = -1, ev_rk_ids = -1, ev_rk_cnt = -1;
         int ev_go = -1;  // st: result rows cleared; the side stream starts after it
-        int32_t* h_cnt = nullptr;
+        // gain levels of the greedy, made on the device from the list lengths
+        constexpr int LCAP = GainLevels::LCAP;
+        const int64_t lv_words = (ns + 63) / 64;
+        // long lists (gain >= LCAP) copied with the levels; more are fetched
+        // when the greedy starts (RNSM_GAIN_PREFIX sets the count, for tests)
+        int64_t hpre = std::min<int64_t>(ns, 1 << 16);
+        if (const char* c = getenv("RNSM_GAIN_PREFIX")) hpre = std::min<int64_t>(ns, std::max(1ll, atoll(c)));
+        unsigned long long* h_lv = nullptr;
+        int* h_lvctl = nullptr;
+        int2* h_high = nullptr;
+        int2* d_high = nullptr;
         if (fresh) {
             int32_t *nk, *rcnt, *rk_ids;
             int64_t *rk_off, *stmp;
@@ -616,11 +626,26 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             }
             HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
             HIPCHK(E.record(st, &ex[1]));
-            // list lengths to the host first: the greedy's gain levels are
-            // built from them while offsets and ids are made and copied
+            // the greedy's gain levels, made on the device from the list
+            // lengths, go to the host first; offsets and ids follow
             HIPCHK(launch_count_ids(nk, ns, k, rcnt, st));
-            HS(h_cnt, "h_rk_cnt", sizeof(int32_t) * ns);
-            HIPCHK(hipMemcpyAsync(h_cnt, rcnt, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
+            {
+                unsigned long long* d_lv;
+                int* d_lvctl;
+                const size_t lv_bytes =
+                    sizeof(unsigned long long) * LCAP * (size_t)std::max<int64_t>(lv_words, 1);
+                WS(d_lv, "gain_levels", lv_bytes);
+                WS(d_lvctl, "gain_ctl", sizeof(int));
+                WS(d_high, "gain_high", sizeof(int2) * std::max<int64_t>(ns, 1));
+                HS(h_lv, "h_gain_levels", lv_bytes);
+                HS(h_lvctl, "h_gain_ctl", sizeof(int));
+                HS(h_high, "h_gain_high", sizeof(int2) * std::max<int64_t>(hpre, 1));
+                HIPCHK(launch_gain_levels(rcnt, ns, LCAP, d_lv, d_lvctl, d_high, ns, st));
+                HIPCHK(hipMemcpyAsync(h_lv, d_lv, sizeof(unsigned long long) * LCAP * lv_words,
+                                      hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(h_lvctl, d_lvctl, sizeof(int), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(h_high, d_high, sizeof(int2) * hpre, hipMemcpyDeviceToHost, st));
+            }
             HIPCHK(E.record(st, &ev_rk_cnt));
             HIPCHK(launch_invert_lists(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
             HIPCHK(E.record(st, &ex[2]));
@@ -681,7 +706,34 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         else
             HIPCHK(hipStreamSynchronize(st));
         const auto th1 = std::chrono::steady_clock::now();
-        if (fresh) build_levels(ns, h_cnt, levels);
+        if (fresh) {
+            levels.n = ns;
+            levels.words = lv_words;
+            levels.ext = reinterpret_cast<uint64_t*>(h_lv);
+            const int64_t nh = h_lvctl[0];
+            // levels up to the highest one in use (all of them when some
+            // gains went to the heap)
+            levels.nlev = nh > 0 ? LCAP : 0;
+            for (int g = LCAP - 1; g >= 0 && levels.nlev == 0; --g) {
+                const unsigned long long* b = h_lv + (size_t)g * lv_words;
+                for (int64_t w = 0; w < lv_words; ++w)
+                    if (b[w]) {
+                        levels.nlev = g + 1;
+                        break;
+                    }
+            }
+            levels.high.resize((size_t)nh);
+            for (int64_t i = 0; i < std::min(nh, hpre); ++i)
+                levels.high[(size_t)i] = {(int64_t)h_high[i].x, (int32_t)h_high[i].y};
+            if (nh > hpre) {  // more long lists than the prefix copied ahead
+                std::vector<int2> rest((size_t)(nh - hpre));
+                HIPCHK(hipMemcpy(rest.data(), d_high + hpre, sizeof(int2) * (nh - hpre),
+                                 hipMemcpyDeviceToHost));
+                for (int64_t i = hpre; i < nh; ++i)
+                    levels.high[(size_t)i] = {(int64_t)rest[(size_t)(i - hpre)].x,
+                                              (int32_t)rest[(size_t)(i - hpre)].y};
+            }
+        }
         double th_levels = 0, th_ids = 0, th_first_post = -1, th_first_launch = -1;
         if (!fresh) {
             HIPCHK(hipMemsetAsync(res, 0xff, sizeof(int32_t) * ns * RES, st));

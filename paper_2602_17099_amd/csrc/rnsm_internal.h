@@ -132,6 +132,10 @@ hipError_t launch_convert(const void* src, int src_type, void* dst, int dst_type
 hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* off, int64_t* tmp_blocks,
                        hipStream_t st);
 size_t scan_tmp_elems(int64_t n);
+// lazy-greedy gain levels from list lengths (lcap levels of (n + 63) / 64
+// words, lists of lcap or more as (length, id) in high[0, min(ctl[0], cap)))
+hipError_t launch_gain_levels(const int32_t* cnt, int64_t n, int lcap, unsigned long long* bits,
+                              int* ctl, int2* high, int64_t cap, hipStream_t st);
 hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int64_t* rk_off,
                          int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st);
 // the two halves of launch_invert: list lengths into cnt, then offsets and

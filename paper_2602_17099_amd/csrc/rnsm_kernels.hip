@@ -2136,6 +2136,49 @@ hipError_t launch_count_ids(const int32_t* nk, int64_t n, int k, int32_t* cnt, h
     return hipGetLastError();
 }
 
+// Gain levels of the lazy greedy from the R_k list lengths, one wavefront
+// per 64 vertices: word w of level g (g < lcap <= 64) has bit i set when
+// vertex 64 w + i has length g. Longer lists go to high as (length, id)
+// pairs (any order: the host orders them in a heap); ctl[0] counts them,
+// with one atomic per wavefront that has any (all wavefronts run at once:
+// per-lane atomics on one address would queue).
+__global__ void k_gain_levels(const int32_t* cnt, int64_t n, int64_t words, int lcap,
+                              unsigned long long* bits, int* ctl, int2* high, int64_t cap) {
+    const int lane = lane_id();
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= words) return;  // whole wavefronts
+    const int64_t x = w * 64 + lane;
+    const int g = x < n ? cnt[x] : -1;
+    u64 mine = 0ull;
+    for (int l = 0; l < lcap; ++l) {
+        const u64 b = __ballot(g == l);
+        if (lane == l) mine = b;
+    }
+    if (lane < lcap) bits[(int64_t)lane * words + w] = mine;
+    const u64 mh = __ballot(g >= lcap);
+    if (mh != 0ull) {
+        const int leader = __ffsll((long long)mh) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&ctl[0], __popcll(mh));
+        base = __shfl(base, leader);
+        if (g >= lcap) {
+            const int64_t i = base + __popcll(mh & lanemask_lt(lane));
+            if (i < cap) high[i] = make_int2(g, (int)x);
+        }
+    }
+}
+
+hipError_t launch_gain_levels(const int32_t* cnt, int64_t n, int lcap, unsigned long long* bits,
+                              int* ctl, int2* high, int64_t cap, hipStream_t st) {
+    if (lcap < 1 || lcap > WAVE) return hipErrorInvalidValue;
+    hipError_t e = hipMemsetAsync(ctl, 0, sizeof(int), st);
+    if (e != hipSuccess || n <= 0) return e;
+    const int64_t words = (n + 63) / 64;
+    hipLaunchKernelGGL(k_gain_levels, dim3(nblk(words, 4)), dim3(4 * WAVE), 0, st, cnt, n, words,
+                       lcap, bits, ctl, high, cap);
+    return hipGetLastError();
+}
+
 hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int64_t* rk_off,
                          int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st) {
     hipError_t e = launch_count_ids(nk, n, k, cnt, st);

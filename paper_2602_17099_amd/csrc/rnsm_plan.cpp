@@ -151,6 +151,7 @@ void build_levels(int64_t n, const int32_t* counts, GainLevels& L) {
     int32_t gmax = 0;
     for (int64_t x = 0; x < n; ++x) gmax = std::max(gmax, counts[x]);
     L.nlev = std::min(gmax + 1, GainLevels::LCAP);
+    L.ext = nullptr;
     if ((int64_t)L.bits.size() < (int64_t)L.nlev * L.words) L.bits.resize((size_t)L.nlev * L.words);
     L.high.clear();
     // one word of every level at a time: the 64 vertices' bits meet in a
@@ -187,12 +188,13 @@ void select_pivots(GainLevels& L, const int64_t* rk_off, const int32_t* rk_ids, 
                    const Emit& emit, const std::function<void()>& lists_ready) {
     if (lists_ready) lists_ready();
     const int64_t n = L.n, words = L.words;
+    uint64_t* lv = L.data();
     std::vector<uint64_t> cov((size_t)words, 0ull);
     int64_t np = 0, nf = 0, sent = 0;
     chunk = std::max<int64_t>(chunk, 1);
     auto mark = [&](int64_t g, int64_t x) {
         if (g < GainLevels::LCAP) {
-            L.bits[(size_t)g * words + (x >> 6)] |= 1ull << (x & 63);
+            lv[(size_t)g * words + (x >> 6)] |= 1ull << (x & 63);
         } else {
             L.high.emplace_back(g, (int32_t)x);
             std::push_heap(L.high.begin(), L.high.end(), [](const std::pair<int64_t, int32_t>& a,
@@ -242,7 +244,7 @@ void select_pivots(GainLevels& L, const int64_t* rk_off, const int32_t* rk_ids, 
         if (!((cov[e.second >> 6] >> (e.second & 63)) & 1ull)) visit(e.second, e.first);
     }
     for (int64_t g = L.nlev - 1; g >= 0; --g) {
-        uint64_t* b = L.bits.data() + (size_t)g * words;
+        uint64_t* b = lv + (size_t)g * words;
         for (int64_t w = 0; w < words; ++w) {
             uint64_t bits = b[w] & ~cov[w];
             while (bits) {

@@ -25,9 +25,11 @@ int plan_ops(int m, const int64_t* sizes, const double* centroids, int dim, int 
 struct GainLevels {
     static constexpr int LCAP = 32;
     int64_t n = 0, words = 0;
-    int nlev = 0;                   // levels held in `bits`
+    int nlev = 0;                   // levels held in `bits` (or `ext`)
     std::vector<uint64_t> bits;     // nlev x words
+    uint64_t* ext = nullptr;        // the same layout in a caller's buffer, used instead
     std::vector<std::pair<int64_t, int32_t>> high;  // (gain, id) of gains >= LCAP
+    uint64_t* data() { return ext ? ext : bits.data(); }
 };
 void build_levels(int64_t n, const int32_t* counts, GainLevels& L);
 

@@ -254,6 +254,24 @@ def test_merge_hub_source_bit_exact(dev, orc, pkg):
     assert (nk == 0).any(axis=1).sum() > 256  # the hub is in more than 256 N_k lists
 
 
+def test_merge_many_long_lists_bit_exact(dev, orc, pkg, monkeypatch):
+    # k = 40 of k+ = 48: several hundred source vertices have reverse k-NN
+    # lists of 32 or more (the greedy's heap, not its bitmap levels); with a
+    # prefix of 8 such lists copied ahead, the rest is fetched when the
+    # greedy starts
+    X = inputs.mixture_u8(2600, 16, comps=4, seed=1411)
+    subs = [orc.build_graph(X[:1200], 48, 24, alpha=1.2, reverse=True),
+            orc.build_graph(X[1200:], 48, 24, alpha=1.2, reverse=True)]
+    nk = orc.expand(*subs[0][:2], X[:1200], 40, 48)
+    rk_len = np.bincount(nk[nk >= 0].ravel(), minlength=1200)
+    assert (rk_len >= 32).sum() > 64
+    ref = orc.merge(subs, X, R=24, L=48, alpha=1.2, k=40, kplus=48, trace=True)
+    monkeypatch.setenv("RNSM_GAIN_PREFIX", "8")
+    got = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=24, L=48, alpha=1.2, k=40, kplus=48)
+    _assert_same_merge(got, ref)
+    assert pkg.stats()["n_pivots"] == ref["trace"]["n_pivots"]
+
+
 def test_merge_centroid_costs_bit_exact(dev, orc, pkg):
     sizes = [700, 1500, 900, 1100, 600, 1300]
     # slab partition along a random direction: centroids differ
