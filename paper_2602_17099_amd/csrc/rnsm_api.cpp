@@ -119,10 +119,13 @@ int ilog2_ceil(int64_t x) {
 }
 
 // LDS visited-table size, wavefronts per block and table mode of a search of
-// beam ef over a graph of n vertices with rows of degree <= maxdeg. The fast
-// table is lossy (a forgotten vertex is evaluated again and dropped by key),
-// so it is sized for occupancy rather than for the whole visited set: 8 KB
-// (4096 16-bit slots) for the L=64, R=32 searches. RNSM_EXACT_VISITED=1, or a
+// beam ef over a graph of n vertices with rows of degree <= maxdeg, on the
+// copy of type tt. The fast table is lossy (a forgotten vertex is evaluated
+// again and dropped by key), so it is sized for occupancy rather than for
+// the whole visited set: 8 KB (4096 16-bit slots) for the L=64, R=32
+// searches on float32 rows; 4 KB on 16-bit rows, whose kernels need fewer
+// registers, so that LDS does not cap their occupancy below the registers'
+// 6 wavefronts per SIMD. RNSM_EXACT_VISITED=1, or a
 // graph too large for 16-bit tags, selects an 8192-slot probing table that
 // holds every visited vertex (distance counts then equal the method's own).
 // RNSM_HASH_BITS / RNSM_WPB override the sizes.
@@ -130,10 +133,11 @@ struct SearchShape {
     int hbits, wpb, mode;
 };
 
-SearchShape search_shape(int ef, int maxdeg, int64_t n) {
+SearchShape search_shape(int ef, int maxdeg, int64_t n, int tt) {
     SearchShape s;
+    const int hmax = tt == 0 ? 11 : 10;
     int hb = ilog2_ceil((int64_t)ef * (maxdeg > 0 ? maxdeg : 16));
-    hb = hb < 8 ? 8 : (hb > 11 ? 11 : hb);
+    hb = hb < 8 ? 8 : (hb > hmax ? hmax : hb);
     s.mode = 0;
     const char* x = getenv("RNSM_EXACT_VISITED");
     if (x && atoi(x) == 1) {
@@ -608,7 +612,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             a.G = vi.G;
             a.lgG = ilog2i(vi.G);
             a.cpl = vi.cpl;
-            const SearchShape sh = search_shape(kp, R, ns);
+            const SearchShape sh = search_shape(kp, R, ns, vi.tt);
             a.hbits = sh.hbits;
             a.hash_mode = sh.mode;
             a.out_mode = 1;
@@ -770,7 +774,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         aA.ef = efN;
         aA.out_k = efN;
         aA.counters = cnt + 1 * CNT_SLOTS * CNT_N;
-        const SearchShape shA = search_shape(efN, R, nt);
+        const SearchShape shA = search_shape(efN, R, nt, vi.tt);
         aA.hbits = shA.hbits;
         aA.hash_mode = shA.mode;
         // wave B: followers, local sliding from their pivot's results
@@ -782,7 +786,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         aB.ef = efS;
         aB.out_k = efS;
         aB.counters = cnt + 2 * CNT_SLOTS * CNT_N;
-        const SearchShape shB = search_shape(efS, R, nt);
+        const SearchShape shB = search_shape(efS, R, nt, vi.tt);
         aB.hbits = shB.hbits;
         aB.hash_mode = shB.mode;
         g_stats.exact_visited = shB.mode;
@@ -1224,7 +1228,7 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     a.G = vi.G;
     a.lgG = ilog2i(vi.G);
     a.cpl = vi.cpl;
-    const SearchShape sh = search_shape(ef, 32, g->n);
+    const SearchShape sh = search_shape(ef, 32, g->n, vi.tt);
     a.hbits = sh.hbits;
     a.hash_mode = sh.mode;
     a.out_mode = 0;

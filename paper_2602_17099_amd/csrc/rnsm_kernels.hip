@@ -281,7 +281,10 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
                                                    int* cl, int v, int lane, u64& ndc,
                                                    u64& nevict, float* rec = nullptr) {
     constexpr int EPC = Elt<TT>::EPC;
-    constexpr int UNR = 2;
+    // rows per lane group per batch: two for float32 rows (more loads in
+    // flight); one for 16-bit rows, whose 72-78 VGPRs then allow 6 resident
+    // wavefronts per SIMD (measured faster for them, slower for float32)
+    constexpr int UNR = TT == 0 ? 2 : 1;
     int st = 0;
     if (v >= a.n) v = -1;  // ids from callers are range-checked
     if (v >= 0) st = hash_visit<EXACT>(tab, a.hbits, v);
