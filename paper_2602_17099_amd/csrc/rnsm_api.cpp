@@ -1038,11 +1038,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         // the side stream precede the last sliding search, which st waited for)
         std::array<int, 2> pe;
         HIPCHK(E.record(st, &pe[0]));
-        PruneArgs q = qs;
-        q.items = d_order;
-        q.n_items = ns;
-        HIPCHK(run_prune(q, pmode, st));
-        // reverse edges into the target, then prune every target that got some
+        // reverse edges into the target (counted by the source prune), then
+        // prune every target that got some
         int32_t *rc, *rcur, *rev;
         int64_t *roff, *stmp;
         u64* scratch;
@@ -1056,7 +1053,13 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         WS(scratch, "prune_scratch", sizeof(u64) * 2 * (nt * R + ns * R));
         HIPCHK(hipMemsetAsync(rc, 0, sizeof(int32_t) * nt, st));
         HIPCHK(hipMemsetAsync(rcur, 0, sizeof(int32_t) * nt, st));
-        HIPCHK(launch_rev_count(rows, deg, bases[s], ns, R, bases[t], nt, rc, st));
+        PruneArgs q = qs;
+        q.items = d_order;
+        q.n_items = ns;
+        q.rev_cnt = rc;
+        q.rev_lo = bases[t];
+        q.rev_n = nt;
+        HIPCHK(run_prune(q, pmode, st));
         HIPCHK(launch_scan(rc, nt, roff, stmp, st));
         HIPCHK(launch_rev_scatter(rows, deg, rdist, bases[s], ns, R, bases[t], nt, roff, rcur, rev,
                                   rev_d, st));
@@ -1074,6 +1077,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         r.extra_sorted = 0;
         r.scratch = scratch;
         r.wcap = TARGET_WCAP;
+        r.rev_cnt = nullptr;
         HIPCHK(run_prune(r, pmode, st));
         HIPCHK(E.record(st, &pe[1]));
         ev_prune.push_back(pe);

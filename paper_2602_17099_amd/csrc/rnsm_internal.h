@@ -91,6 +91,8 @@ struct PruneArgs {
     int32_t* rows_out;
     int32_t* deg_out;
     float* dist_out;
+    int32_t* rev_cnt;         // optional: +1 at rev_cnt[v - rev_lo] for every kept v in
+    int64_t rev_lo, rev_n;    // [rev_lo, rev_lo + rev_n) (reverse-edge counts)
     u64* scratch;             // keys of candidate lists longer than wcap (mode 2)
     int wcap;
     int* err;

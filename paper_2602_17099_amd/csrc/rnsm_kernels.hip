@@ -681,6 +681,12 @@ __device__ __forceinline__ void collect_dists(const PruneArgs& a, int64_t p, u64
     }
 }
 
+// a kept edge p -> v into the target range offers p to v: counted here, so
+// that the reverse lists need no separate counting pass over the rows
+__device__ __forceinline__ void count_reverse(const PruneArgs& a, int64_t v) {
+    if (a.rev_cnt && v >= a.rev_lo && v < a.rev_lo + a.rev_n) atomicAdd(&a.rev_cnt[v - a.rev_lo], 1);
+}
+
 // Candidate list W of the prune of p (Section 2.2): the current row of p
 // plus the extra candidates, minus p itself. Keys (d(p, w), w) go to wk;
 // the ones whose float32 distance is already known (search results, reverse
@@ -934,6 +940,7 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
             kept_ids[nk] = v;
             a.rows_out[p * R + nk] = v;
             a.dist_out[p * R + nk] = dv;
+            count_reverse(a, v);
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1275,6 +1282,7 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
                 kept_u[kr] = uj;
                 a.rows_out[p * R + kr] = idj;
                 a.dist_out[p * R + kr] = dj;
+                count_reverse(a, idj);
             }
         }
         nk += __popc(keptj);
