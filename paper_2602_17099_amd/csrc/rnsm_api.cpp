@@ -122,7 +122,7 @@ int ilog2_ceil(int64_t x) {
 // beam ef over a graph of n vertices with rows of degree <= maxdeg, on the
 // copy of type tt. The fast table is lossy (a forgotten vertex is evaluated
 // again and dropped by key), so it is sized for occupancy rather than for
-// the whole visited set: 8 KB (4096 16-bit slots) for the L=64, R=32
+// the whole visited set: 8 KB (2048 two-way sets of 16-bit tags) for the L=64, R=32
 // searches on float32 rows; 4 KB on 16-bit rows, whose kernels need fewer
 // registers, so that LDS does not cap their occupancy below the registers'
 // 6 wavefronts per SIMD. RNSM_EXACT_VISITED=1, or a
@@ -146,7 +146,7 @@ SearchShape search_shape(int ef, int maxdeg, int64_t n, int tt) {
     }
     const char* e = getenv("RNSM_HASH_BITS");
     if (e && atoi(e) >= 6 && atoi(e) <= 14) hb = atoi(e);
-    if (s.mode == 0 && n >= ((int64_t)0xffff << (hb + 1))) {
+    if (s.mode == 0 && n >= ((int64_t)0xffff << hb)) {
         s.mode = 1;  // ids do not fit the 16-bit tags
         hb = 13;
     }

@@ -200,29 +200,26 @@ __device__ __forceinline__ void beam_insert(Beam<EFS>& B, u64 key, int ef, int l
     }
 }
 
-// visited table. Mode 0 (fast): direct-mapped, a vertex replaces whatever
-// held its slot. Mode 1 (exact while the table has room): linear probing.
-// 0: seen, 1: not seen, 2: not seen (or forgotten) and another vertex was
-// evicted / the probe path was full
-// Visited set in LDS (4 << hbits bytes). Forgetful form: 2 << hbits slots of
-// 16 bits; vertex v goes to slot (v ^ (v >> b)) mod 2^b and stores the tag
-// v >> b, so (slot, tag) identifies v while v < 0xffff << b (0xffff marks an
-// empty slot). A plain read then a write: two lanes that meet in one slot in
-// the same instruction are both treated as new, which only re-evaluates a
+// Visited set in LDS (4 << hbits bytes). Forgetful form: 2^hbits sets of two
+// 16-bit tags in one 32-bit word; vertex v goes to set (v ^ (v >> b)) mod
+// 2^b and its tag is v >> b (b = hbits), so (set, tag) identifies v while
+// v < 0xffff << b (0xffff marks an empty tag). A new vertex takes the low
+// half and moves the earlier one to the high half, whose vertex is
+// forgotten. A plain read then a write: two lanes that meet in one set in the
+// same instruction may lose one of their tags, which only re-evaluates a
 // vertex. Exact form: 32-bit ids with linear probing (up to 64 probes).
-// Returns 0 if v was already there, 1 if it went into an empty slot, 2 if it
-// replaced another vertex (or found no slot).
+// Returns 0 if v was already there, 1 if it went into an empty place, 2 if
+// it made the set forget another vertex (or found no slot).
 template <bool EXACT>
 __device__ __forceinline__ int hash_visit(int* tab, int hbits, int v) {
     if constexpr (!EXACT) {
-        const unsigned b = (unsigned)hbits + 1u;
+        const unsigned b = (unsigned)hbits;
         const unsigned hi = (unsigned)v >> b;
-        const unsigned slot = ((unsigned)v ^ hi) & ((1u << b) - 1u);
-        unsigned short* t16 = (unsigned short*)tab;
-        const unsigned old = t16[slot];
-        if (old == hi) return 0;
-        t16[slot] = (unsigned short)hi;
-        return old == 0xffffu ? 1 : 2;
+        const unsigned set = ((unsigned)v ^ hi) & ((1u << b) - 1u);
+        const unsigned old = (unsigned)tab[set];
+        if ((old & 0xffffu) == hi || (old >> 16) == hi) return 0;
+        tab[set] = (int)((old << 16) | hi);
+        return (old >> 16) == 0xffffu ? 1 : 2;
     } else {
         const unsigned h = ((unsigned)v * 2654435761u) >> (32 - hbits);
         const unsigned mask = (1u << hbits) - 1u;
