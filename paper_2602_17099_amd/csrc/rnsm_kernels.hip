@@ -678,6 +678,36 @@ __device__ __forceinline__ void collect_dists(const PruneArgs& a, int64_t p, u64
     }
 }
 
+// ws[r] = wk[t] with r = #smaller keys + #equal keys earlier in wk, for
+// nW <= KMAX * 64 keys: each lane holds keys t = j * 64 + lane in registers,
+// and every key is broadcast once with readlane (no memory reads in the
+// O(nW^2) part, which matters when wk is in global scratch)
+template <int KMAX>
+__device__ __forceinline__ void rank_keys(const u64* wk, u64* ws, int nW, int lane) {
+    u64 kv[KMAX];
+    int rk[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        const int t = j * WAVE + lane;
+        kv[j] = t < nW ? wk[t] : EMPTY_KEY;
+        rk[j] = 0;
+    }
+#pragma unroll
+    for (int j2 = 0; j2 < KMAX; ++j2) {
+        const int lim = min(WAVE, nW - j2 * WAVE);
+        for (int l = 0; l < lim; ++l) {
+            const u64 ks = readlane64(kv[j2], l);
+            const int s2 = j2 * WAVE + l;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                rk[j] += (ks < kv[j] || (ks == kv[j] && s2 < j * WAVE + lane)) ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+        if (j * WAVE + lane < nW) ws[rk[j]] = kv[j];
+}
+
 // a kept edge p -> v into the target range offers p to v: counted here, so
 // that the reverse lists need no separate counting pass over the rows
 __device__ __forceinline__ void count_reverse(const PruneArgs& a, int64_t v) {
@@ -793,6 +823,14 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
 #pragma unroll
         for (int x = 0; x < XPL; ++x)
             if (lane + x * WAVE < nb) ws[pb[x]] = kb[x];
+    } else if (nW <= 2 * WAVE) {
+        rank_keys<2>(wk, ws, nW, lane);
+    } else if (nW <= 4 * WAVE) {
+        rank_keys<4>(wk, ws, nW, lane);
+    } else if (nW <= 8 * WAVE) {
+        rank_keys<8>(wk, ws, nW, lane);
+    } else if (nW <= 16 * WAVE) {
+        rank_keys<16>(wk, ws, nW, lane);
     } else {
         for (int t = lane; t < nW; t += WAVE) {
             const u64 kt = wk[t];

@@ -127,7 +127,10 @@ def test_fullsize_sampled_target_rows(orc, case):
     g = inputs.rng(812)
     indeg = np.bincount(src_nb[src_nb >= N_SUB] - N_SUB, minlength=N_SUB)
     a, b = np.flatnonzero(indeg > 0), np.flatnonzero(indeg == 0)
-    with_rev = g.choice(a, min(48, len(a)), replace=False) + N_SUB
+    # the most offered targets too: candidate lists of several hundred keys
+    # (ordered in global scratch, not LDS)
+    heavy = np.argsort(indeg, kind="stable")[-4:]
+    with_rev = np.concatenate([g.choice(a, min(48, len(a)), replace=False), heavy]) + N_SUB
     without = g.choice(b, min(16, len(b)), replace=False) + N_SUB
     for v in list(with_rev) + list(without):
         v = int(v)
