@@ -272,7 +272,7 @@ __host__ __device__ constexpr int search_lds_words(int hbits) { return (1 << hbi
 // copies use v_dot2 on the packed values, squared L2 as |q|^2 + |x|^2 - 2 q.x
 // combined in double (exact whenever the three sums are, e.g. small integers).
 // qn: the query's norm (cosine) or squared norm (squared L2, 16-bit copies).
-template <int TT, int EFS, int CPL, bool EXACT>
+template <int TT, int EFS, int CPL, bool EXACT, int LG>
 __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS>& B,
                                                    const Query<TT, CPL>& Q, float qn, int* tab,
                                                    int* cl, int v, int lane, u64& ndc,
@@ -298,8 +298,10 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     ndc += nc;
-    const int G = a.G, RPP = WAVE >> a.lgG;
-    const int group = lane >> a.lgG, sub = lane & (G - 1);
+    // lanes per row: a constant in the instances for the common shapes
+    // (LG = log2 G), so that the group sums and indexing fold
+    const int lgG = LG >= 0 ? LG : a.lgG, G = 1 << lgG, RPP = WAVE >> lgG;
+    const int group = lane >> lgG, sub = lane & (G - 1);
     const int64_t gstride = (int64_t)G * 16;
     for (int c0 = 0; c0 < nc; c0 += RPP * UNR) {
         uint4 raw[UNR][CPL];
@@ -375,7 +377,7 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int TT, int EFS, int CPL, bool EXACT>
+template <int TT, int EFS, int CPL, bool EXACT, int LG>
 __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     extern __shared__ int smem[];
     const int lane = lane_id();
@@ -390,24 +392,25 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     __builtin_amdgcn_wave_barrier();
 
     const int u = a.qidx ? a.qidx[i] : (int)i;
-    const int sub = lane & (a.G - 1);
+    const int G = LG >= 0 ? (1 << LG) : a.G;
+    const int sub = lane & (G - 1);
     const char* qrow = a.qvec + (int64_t)u * a.row_bytes + sub * 16;
     Query<TT, CPL> Q;
     float qn = a.metric == 2 ? a.q_norm[u] : 1.0f;
     if constexpr (TT == 0) {
 #pragma unroll
         for (int j = 0; j < CPL; ++j)
-            cvt_chunk<TT>(*(const uint4*)(qrow + (int64_t)j * a.G * 16), Q.q[j]);
+            cvt_chunk<TT>(*(const uint4*)(qrow + (int64_t)j * G * 16), Q.q[j]);
     } else {
         float s2 = 0.0f;
 #pragma unroll
         for (int j = 0; j < CPL; ++j) {
-            Q.r[j] = *(const uint4*)(qrow + (int64_t)j * a.G * 16);
+            Q.r[j] = *(const uint4*)(qrow + (int64_t)j * G * 16);
             s2 = dot2x4<TT>(Q.r[j], Q.r[j], s2);
         }
         // squared norm of the query (valid in the last lane of each group,
         // the lanes that form the keys)
-        const float qq = group_sum_last(s2, a.G);
+        const float qq = group_sum_last(s2, G);
         if (a.metric == 0) qn = qq;
     }
 
@@ -422,7 +425,7 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     // seeds
     if (a.seed_mode == 0 || a.seed_mode == 1) {
         const int s0 = a.seed_mode == 0 ? a.entry : u;
-        process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, lane == 0 ? s0 : -1, lane, ndc,
+        process_candidates<TT, EFS, CPL, EXACT, LG>(a, B, Q, qn, tab, cl, lane == 0 ? s0 : -1, lane, ndc,
                                        nevict);
     } else {
         const int64_t srow = a.seed_row ? a.seed_row[i] : i;
@@ -430,7 +433,7 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
         for (int j0 = 0; j0 < a.n_seeds; j0 += WAVE) {
             const int j = j0 + lane;
             const int v = j < a.n_seeds ? sp[j] : -1;
-            process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
+            process_candidates<TT, EFS, CPL, EXACT, LG>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
         }
     }
 
@@ -494,14 +497,14 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
             float* rec = (a.row_d && it == 0 && uid == u)
                              ? a.row_d + (a.row_d_base + u) * a.row_d_stride
                              : nullptr;
-            process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict, rec);
+            process_candidates<TT, EFS, CPL, EXACT, LG>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict, rec);
         } else {
             const int64_t b = a.offs[uid], en = a.offs[uid + 1];
             nadj += (u64)(en - b);
             for (int64_t j0 = b; j0 < en; j0 += WAVE) {
                 const int64_t j = j0 + lane;
                 const int v = j < en ? a.nbrs[j] : -1;
-                process_candidates<TT, EFS, CPL, EXACT>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
+                process_candidates<TT, EFS, CPL, EXACT, LG>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
             }
         }
         if (it > maxit) {
@@ -2026,11 +2029,18 @@ hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStrea
 
 template <int TT, int EFS, bool EXACT>
 static void launch_search_c(const SearchArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+    // dim 128 (512-byte float32 rows over 8 lanes, 256-byte 16-bit rows over
+    // 4 lanes): lanes per row fixed at compile time
+    constexpr int LG128 = TT == 0 ? 3 : 2;
+    if (a.cpl == 4 && a.lgG == LG128) {
+        hipLaunchKernelGGL((k_beam_search<TT, EFS, 4, EXACT, LG128>), grid, block, lds, st, a);
+        return;
+    }
     switch (a.cpl) {
-        case 1: hipLaunchKernelGGL((k_beam_search<TT, EFS, 1, EXACT>), grid, block, lds, st, a); break;
-        case 2: hipLaunchKernelGGL((k_beam_search<TT, EFS, 2, EXACT>), grid, block, lds, st, a); break;
-        case 3: hipLaunchKernelGGL((k_beam_search<TT, EFS, 3, EXACT>), grid, block, lds, st, a); break;
-        default: hipLaunchKernelGGL((k_beam_search<TT, EFS, 4, EXACT>), grid, block, lds, st, a); break;
+        case 1: hipLaunchKernelGGL((k_beam_search<TT, EFS, 1, EXACT, -1>), grid, block, lds, st, a); break;
+        case 2: hipLaunchKernelGGL((k_beam_search<TT, EFS, 2, EXACT, -1>), grid, block, lds, st, a); break;
+        case 3: hipLaunchKernelGGL((k_beam_search<TT, EFS, 3, EXACT, -1>), grid, block, lds, st, a); break;
+        default: hipLaunchKernelGGL((k_beam_search<TT, EFS, 4, EXACT, -1>), grid, block, lds, st, a); break;
     }
 }
 
