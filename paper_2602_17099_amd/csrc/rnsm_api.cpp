@@ -226,6 +226,15 @@ struct ValueInfo {
     bool integral = false;
     double bound = INFINITY, range = INFINITY;
 };
+// the summary from launch_value_range's three words
+void decode_value_range(const unsigned* h, ValueInfo* out) {
+    const double lo = key_to_float(h[1]), hi = key_to_float(h[2]);
+    out->integral = h[0] == 1u;
+    out->bound = std::max(std::fabs(lo), std::fabs(hi));
+    out->range = hi - lo;
+    if (!std::isfinite(out->bound)) out->integral = false;
+}
+
 hipError_t value_info(const float* X, int64_t n, int dim, unsigned* scratch3, hipStream_t st,
                       ValueInfo* out) {
     hipError_t e = launch_value_range(X, n * dim, scratch3, st);
@@ -235,11 +244,7 @@ hipError_t value_info(const float* X, int64_t n, int dim, unsigned* scratch3, hi
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
-    const double lo = key_to_float(h[1]), hi = key_to_float(h[2]);
-    out->integral = h[0] == 1u;
-    out->bound = std::max(std::fabs(lo), std::fabs(hi));
-    out->range = hi - lo;
-    if (!std::isfinite(out->bound)) out->integral = false;
+    decode_value_range(h, out);
     return hipSuccess;
 }
 
@@ -412,62 +417,6 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         if (f & 2) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: degree above R = %d", i, R);
     }
 
-    // ------------------------------------------------------------ workspace
-    int32_t *rows, *deg, *errf;
-    float *rdist, *norms = nullptr;
-    double* norms64 = nullptr;  // inner product and cosine: for the stored distances
-    u64* cnt;
-    WS(rows, "rows", sizeof(int32_t) * N * R);
-    WS(deg, "deg", sizeof(int32_t) * N);
-    WS(rdist, "rdist", sizeof(float) * N * R);
-    WS(cnt, "counters", sizeof(u64) * 3 * CNT_SLOTS * CNT_N);
-    WS(errf, "errf", sizeof(int));
-    ValueInfo vinfo;
-    {
-        unsigned* vr;
-        WS(vr, "value_range", sizeof(unsigned) * 3);
-        HIPCHK(value_info(vecs->f32, N, vecs->dim, vr, st, &vinfo));
-    }
-    const int pmode = choose_prune(vinfo, vecs->dim, R);
-    // exact-mode prune: a bfloat16 copy of the rows (exact in it), half the
-    // bytes for the prune's gathers
-    char* xb16 = nullptr;
-    if (pmode == 1) {
-        WS(xb16, "prune_bf16", (size_t)2 * N * vecs->dim);
-        HIPCHK(launch_convert(vecs->f32, RNSM_F32, xb16, RNSM_BF16, N * vecs->dim, st));
-    }
-    // search distances usable as prune keys: a float32 copy computes them
-    // with the prune's own lane layout and order; a 16-bit copy only when
-    // every distance is exact (integers exact in that type, exact sums)
-    const bool search_d_exact =
-        vi.tt == 0 || int_exact(vinfo, vecs->dim, vi.tt == 1 ? 256.0 : 2048.0);
-    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * 3 * CNT_SLOTS * CNT_N, st));
-    HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
-    if (p->metric == RNSM_COSINE) {
-        WS(norms, "norms", sizeof(float) * N);
-        WS(norms64, "norms64", sizeof(double) * N);
-        HIPCHK(launch_norms(vecs->f32, N, vecs->dim, norms, st, norms64));
-    }
-    // squared L2 on a 16-bit copy: |x|^2 of every row once, in the search's
-    // own summation order, instead of once per distance evaluation (the
-    // cross-graph searches; the expansion measured faster without the extra
-    // gather per candidate)
-    float* sqn = nullptr;
-    if (vi.tt != 0 && p->metric == RNSM_L2SQ) {
-        WS(sqn, "sqnorm16", sizeof(float) * N);
-        HIPCHK(launch_sqnorm16(vi.tt, vi.search, N, vi.nch, vi.G, sqn, st));
-    }
-    for (int i = 0; i < m; ++i)
-        HIPCHK(launch_init_rows(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, bases[i], R, rows,
-                                deg, rdist, st));
-    // padded adjacency of every input graph (rows of R ids, -1 filled): the
-    // searches read a vertex's neighbours with one load, no offsets lookup
-    int32_t* padj;
-    WS(padj, "padj", sizeof(int32_t) * N * R);
-    for (int i = 0; i < m; ++i)
-        HIPCHK(launch_pad_adjacency(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, R,
-                                    padj + bases[i] * R, st));
-
     // ----------------------------------------------------------------- plan
     const auto tp = std::chrono::steady_clock::now();
     std::vector<std::pair<int, int>> ops;
@@ -501,6 +450,108 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         return fail(RNSM_EINTERNAL, "rnsm_merge: planner failed");
     double ms_plan = ms_since(tp);
 
+    // ------------------------------------------------------------ workspace
+    // Order of the set-up: the padded adjacency first, so that the first
+    // operation's breadth-first order (side stream, host-paced levels) runs
+    // while this stream makes the value summary, row copies, norms and the
+    // bfloat16 copy; the summary is read after that.
+    int32_t *rows, *deg, *errf;
+    float *rdist, *norms = nullptr;
+    double* norms64 = nullptr;  // inner product and cosine: for the stored distances
+    u64* cnt;
+    WS(rows, "rows", sizeof(int32_t) * N * R);
+    WS(deg, "deg", sizeof(int32_t) * N);
+    WS(rdist, "rdist", sizeof(float) * N * R);
+    WS(cnt, "counters", sizeof(u64) * 3 * CNT_SLOTS * CNT_N);
+    WS(errf, "errf", sizeof(int));
+    // padded adjacency of every input graph (rows of R ids, -1 filled): the
+    // searches read a vertex's neighbours with one load, no offsets lookup
+    int32_t* padj;
+    WS(padj, "padj", sizeof(int32_t) * N * R);
+    for (int i = 0; i < m; ++i)
+        HIPCHK(launch_pad_adjacency(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, R,
+                                    padj + bases[i] * R, st));
+    int ev_padj;
+    HIPCHK(E.record(st, &ev_padj));
+    // value summary, read once the breadth-first order is done
+    unsigned *vr, *h_vr;
+    WS(vr, "value_range", sizeof(unsigned) * 3);
+    HS(h_vr, "h_value_range", sizeof(unsigned) * 3);
+    HIPCHK(launch_value_range(vecs->f32, N * vecs->dim, vr, st));
+    HIPCHK(hipMemcpyAsync(h_vr, vr, sizeof(unsigned) * 3, hipMemcpyDeviceToHost, st));
+    int ev_vr;
+    HIPCHK(E.record(st, &ev_vr));
+    // bfloat16 copy of the rows for an exact-mode prune (half the bytes for
+    // its gathers), made before the summary says whether the rows are exact
+    // in it; unused when they are not
+    char* xb16 = nullptr;
+    if (prune_mfma_supported(vecs->dim) && R <= 64) {
+        WS(xb16, "prune_bf16", (size_t)2 * N * vecs->dim);
+        HIPCHK(launch_convert(vecs->f32, RNSM_F32, xb16, RNSM_BF16, N * vecs->dim, st));
+    }
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * 3 * CNT_SLOTS * CNT_N, st));
+    HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
+    if (p->metric == RNSM_COSINE) {
+        WS(norms, "norms", sizeof(float) * N);
+        WS(norms64, "norms64", sizeof(double) * N);
+        HIPCHK(launch_norms(vecs->f32, N, vecs->dim, norms, st, norms64));
+    }
+    // squared L2 on a 16-bit copy: |x|^2 of every row once, in the search's
+    // own summation order, instead of once per distance evaluation (the
+    // cross-graph searches; the expansion measured faster without the extra
+    // gather per candidate)
+    float* sqn = nullptr;
+    if (vi.tt != 0 && p->metric == RNSM_L2SQ) {
+        WS(sqn, "sqnorm16", sizeof(float) * N);
+        HIPCHK(launch_sqnorm16(vi.tt, vi.search, N, vi.nch, vi.G, sqn, st));
+    }
+    for (int i = 0; i < m; ++i)
+        HIPCHK(launch_init_rows(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, bases[i], R, rows,
+                                deg, rdist, st));
+    // breadth-first order of a source graph from its entry: the expansion
+    // runs its queries in that order, and pivot groups are launched by the
+    // rank of their pivot in it (locality in L2 only)
+    const bool use_bfs = !getenv("RNSM_NO_BFS_ORDER");
+    int32_t* h_bfs = nullptr;
+    auto bfs_order_of = [&](int s, hipStream_t strm, int32_t** order_out, int* ev_out) -> rnsm_status {
+        const int64_t ns = sizes[s];
+        int32_t* bfs_order;
+        unsigned *bfs_vis, *bfs_tail, *h_tail;
+        WS(bfs_order, "bfs_order", sizeof(int32_t) * ns);
+        WS(bfs_vis, "bfs_visited", sizeof(unsigned) * ((ns + 31) / 32));
+        WS(bfs_tail, "bfs_ctl", 4 * sizeof(unsigned));
+        HS(h_tail, "h_bfs_ctl", 4 * sizeof(unsigned));
+        HS(h_bfs, "h_bfs_order", sizeof(int32_t) * ns);
+        HIPCHK(launch_bfs_order(padj + bases[s] * R, R, ns, graphs[s].entry, bfs_vis, bfs_order,
+                                bfs_tail, h_tail, strm));
+        HIPCHK(hipMemcpyAsync(h_bfs, bfs_order, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, strm));
+        HIPCHK(E.record(strm, ev_out));
+        *order_out = bfs_order;
+        return RNSM_OK;
+    };
+    hipStream_t sd;
+    HIPCHK(ws.side_stream(&sd));
+    int32_t* bfs0 = nullptr;
+    int ev_bfs0 = -1;
+    const bool bfs_early =
+        use_bfs && !ops.empty() && !(p->flags & RNSM_FLAG_ALL_PIVOTS) && sizes[ops[0].first] > 0;
+    if (bfs_early) {
+        HIPCHK(hipStreamWaitEvent(sd, E.ev[ev_padj], 0));
+        const rnsm_status bs = bfs_order_of(ops[0].first, sd, &bfs0, &ev_bfs0);
+        if (bs != RNSM_OK) return bs;
+    }
+    ValueInfo vinfo;
+    HIPCHK(hipEventSynchronize(E.ev[ev_vr]));
+    decode_value_range(h_vr, &vinfo);
+    const int pmode = choose_prune(vinfo, vecs->dim, R);
+    if (pmode != 1) xb16 = nullptr;
+    // search distances usable as prune keys: a float32 copy computes them
+    // with the prune's own lane layout and order; a 16-bit copy only when
+    // every distance is exact (integers exact in that type, exact sums)
+    const bool search_d_exact =
+        vi.tt == 0 || int_exact(vinfo, vecs->dim, vi.tt == 1 ? 256.0 : 2048.0);
+
+
     // ------------------------------------------------------- the operations
     // Per operation (source s into target t): neighbour expansion of s in
     // its own graph and the reverse k-NN lists (device); R_k to the host and
@@ -520,12 +571,10 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     std::vector<std::array<int, 2>> ev_prune;
     int64_t* h_nrev;
     HS(h_nrev, "h_nrev", sizeof(int64_t) * ops.size());
-    const bool use_bfs = !getenv("RNSM_NO_BFS_ORDER");
     GainLevels& levels = ws.levels;
     std::vector<char> touched(m, 0);  // rows changed by an earlier operation
     std::vector<int32_t> rank, fbeg, fcnt;
     std::vector<uint64_t> rbits;
-    int32_t* h_bfs = nullptr;
     for (size_t oi = 0; oi < ops.size(); ++oi) {
         const int s = ops[oi].first, t = ops[oi].second;
         const int64_t ns = sizes[s], nt = sizes[t];
@@ -575,19 +624,14 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             // expansion runs its queries in that order, and pivot groups are
             // launched by the rank of their pivot in it (locality in L2 only)
             int32_t* bfs_order = nullptr;
-            unsigned* bfs_vis;
             int ev_order = -1;
-            if (use_bfs) {
-                unsigned *bfs_tail, *h_tail;
-                WS(bfs_order, "bfs_order", sizeof(int32_t) * ns);
-                WS(bfs_vis, "bfs_visited", sizeof(unsigned) * ((ns + 31) / 32));
-                WS(bfs_tail, "bfs_ctl", 4 * sizeof(unsigned));
-                HS(h_tail, "h_bfs_ctl", 4 * sizeof(unsigned));
-                HS(h_bfs, "h_bfs_order", sizeof(int32_t) * ns);
-                HIPCHK(launch_bfs_order(padj + bases[s] * R, R, ns, graphs[s].entry, bfs_vis,
-                                        bfs_order, bfs_tail, h_tail, st));
-                HIPCHK(hipMemcpyAsync(h_bfs, bfs_order, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, st));
-                HIPCHK(E.record(st, &ev_order));
+            if (oi == 0 && bfs_early) {  // made on the side stream during the set-up
+                bfs_order = bfs0;
+                ev_order = ev_bfs0;
+                HIPCHK(hipStreamWaitEvent(st, E.ev[ev_order], 0));
+            } else if (use_bfs) {
+                const rnsm_status bs = bfs_order_of(s, st, &bfs_order, &ev_order);
+                if (bs != RNSM_OK) return bs;
             }
             std::array<int, 3> ex;
             HIPCHK(E.record(st, &ex[0]));
@@ -794,8 +838,6 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         // chunk c: lists and naive search on the side stream, then the
         // sliding search on st after the naive one (event wait); the naive
         // search of chunk c+1 overlaps the sliding search of chunk c
-        hipStream_t sd;
-        HIPCHK(ws.side_stream(&sd));
         HIPCHK(hipStreamWaitEvent(sd, E.ev[ev_go], 0));
         // source rows: current row + search results, pruned to R after the
         // searches, each pivot group together (order staged with the chunks).
