@@ -1163,16 +1163,20 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
             for (int t = 0; t < KD; ++t) fr[t] = make_uint4(0u, 0u, 0u, 0u);
         }
     };
+    // exact mode keeps two tiles of fragments in flight (buffers A and B
+    // alternate: tile J reads buffer J % 2, then refills it with tile J + 2)
     float raw[NT == 1 ? 1 : DL];
-    uint4 frag[NT == 1 ? KD : 1];
-    if constexpr (NT == 1)
-        load_frag(0, frag);
-    else
-        load_tile(0, raw);
+    uint4 fragA[NT == 1 ? KD : 1], fragB[NT == 1 ? KD : 1];
     int nk = 0;
     u64 prev = EMPTY_KEY;
     const int ntiles = (nW + 15) >> 4;
-    for (int J = 0; J < ntiles && nk < R; ++J) {
+    if constexpr (NT == 1) {
+        load_frag(0, fragA);
+        if (ntiles > 1) load_frag(1, fragB);
+    } else {
+        load_tile(0, raw);
+    }
+    auto tile = [&](int J, uint4* cur) -> bool {
         const int c = J * 16 + jr;
         const u64 key = c < nW ? ws[c] : EMPTY_KEY;
         const int idj = key == EMPTY_KEY ? -1 : (int)(unsigned)(key & 0xffffffffu);
@@ -1183,7 +1187,7 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
         if constexpr (NT == 1) {
 #pragma unroll
             for (int s2 = 0; s2 < KD; ++s2) {
-                hi[s2] = frag[s2];
+                hi[s2] = cur[s2];
                 lo[s2] = make_uint4(0u, 0u, 0u, 0u);
                 sq = dot2x4<1>(hi[s2], hi[s2], sq);
             }
@@ -1210,11 +1214,10 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
         const bool intd = NT == 1 && metric != 2;
         const int tj = intd ? dom_threshold(alpha, dj) : 0;
         const int uji = intd && metric == 0 ? (int)uj : 0;
-        if (J + 1 < ntiles) {  // next tile's rows in flight
-            if constexpr (NT == 1)
-                load_frag(J + 1, frag);
-            else
-                load_tile(J + 1, raw);
+        if constexpr (NT == 1) {  // tile J + 2's rows in flight
+            if (J + 2 < ntiles) load_frag(J + 2, cur);
+        } else if (J + 1 < ntiles) {  // next tile's rows in flight
+            load_tile(J + 1, raw);
         }
 
         // the tile with itself: pairs (i, j), i = 4 q + r, j = l % 16, i < j
@@ -1327,7 +1330,14 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (stop) break;
+        return stop;
+    };
+    if constexpr (NT == 1) {
+        for (int J = 0; J < ntiles && nk < R; ++J)
+            if ((J & 1) ? tile(J, fragB) : tile(J, fragA)) break;
+    } else {
+        for (int J = 0; J < ntiles && nk < R; ++J)
+            if (tile(J, fragA)) break;
     }
     if (lane == 0) a.deg_out[p] = nk;
 }
