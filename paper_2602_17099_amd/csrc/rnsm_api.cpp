@@ -496,15 +496,6 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         WS(norms64, "norms64", sizeof(double) * N);
         HIPCHK(launch_norms(vecs->f32, N, vecs->dim, norms, st, norms64));
     }
-    // squared L2 on a 16-bit copy: |x|^2 of every row once, in the search's
-    // own summation order, instead of once per distance evaluation (the
-    // cross-graph searches; the expansion measured faster without the extra
-    // gather per candidate)
-    float* sqn = nullptr;
-    if (vi.tt != 0 && p->metric == RNSM_L2SQ) {
-        WS(sqn, "sqnorm16", sizeof(float) * N);
-        HIPCHK(launch_sqnorm16(vi.tt, vi.search, N, vi.nch, vi.G, sqn, st));
-    }
     for (int i = 0; i < m; ++i)
         HIPCHK(launch_init_rows(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, bases[i], R, rows,
                                 deg, rdist, st));
@@ -802,7 +793,6 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         a.metric = p->metric;
         a.base_norm = norms ? norms + bases[t] : nullptr;
         a.q_norm = norms ? norms + bases[s] : nullptr;
-        a.base_sqn = sqn ? sqn + bases[t] : nullptr;
         a.G = vi.G;
         a.lgG = ilog2i(vi.G);
         a.cpl = vi.cpl;

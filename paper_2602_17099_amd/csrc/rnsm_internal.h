@@ -33,8 +33,6 @@ struct SearchArgs {
     int n_seeds;
     int metric;
     const float* base_norm;   // cosine: norms of target rows
-    const float* base_sqn;    // squared L2 on a 16-bit copy: |x|^2 of the target rows
-                              // (from the copy's values; NULL: computed per candidate)
     const float* q_norm;      // cosine: norms of query rows (indexed like the query row)
     int ef;
     int G;                    // lanes per row (power of two)
@@ -108,10 +106,6 @@ hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n,
 // row norms summed in double; out64 (optional) keeps the double values
 hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st,
                         double* out64 = nullptr);
-// |x|^2 of rows of a bfloat16 (tt 1) or float16 (tt 2) copy, summed with
-// v_dot2 in the order the search uses
-hipError_t launch_sqnorm16(int tt, const void* X, int64_t n, int nch, int G, float* out,
-                           hipStream_t st);
 hipError_t launch_search(int tt, const SearchArgs& a, int waves_per_block, hipStream_t st);
 size_t search_lds_bytes(int hbits, int waves_per_block);
 hipError_t launch_prune(const PruneArgs& a, hipStream_t st);

@@ -306,17 +306,14 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
     for (int c0 = 0; c0 < nc; c0 += RPP * UNR) {
         uint4 raw[UNR][CPL];
         int cid[UNR];
-        float sq[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             const int c = c0 + u * RPP + group;
             cid[u] = c < nc ? cl[c] : -1;
-            sq[u] = 0.0f;
             if (cid[u] >= 0) {
                 const char* rp = a.base + (int64_t)cid[u] * a.row_bytes + sub * 16;
 #pragma unroll
                 for (int j = 0; j < CPL; ++j) raw[u][j] = *(const uint4*)(rp + j * gstride);
-                if (TT != 0 && a.base_sqn && sub == G - 1) sq[u] = a.base_sqn[cid[u]];
             }
         }
         float acc[UNR], xx[UNR];
@@ -343,13 +340,11 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
 #pragma unroll
                 for (int j = 0; j < CPL; ++j) {
                     s = dot2x4<TT>(Q.r[j], raw[u][j], s);
-                    if (a.metric == 0 && !a.base_sqn) s2 = dot2x4<TT>(raw[u][j], raw[u][j], s2);
+                    if (a.metric == 0) s2 = dot2x4<TT>(raw[u][j], raw[u][j], s2);
                 }
             }
             acc[u] = group_sum_last(s, G);
-            xx[u] = (TT != 0 && a.metric == 0)
-                        ? (a.base_sqn ? sq[u] : group_sum_last(s2, G))
-                        : 0.0f;
+            xx[u] = (TT != 0 && a.metric == 0) ? group_sum_last(s2, G) : 0.0f;
         }
         const u64 worst = beam_worst(B, a.ef);
 #pragma unroll
@@ -1499,39 +1494,6 @@ __global__ void k_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n,
         rows[g * R + j] = (int32_t)(base + nbrs[b + j]);
         rdist[g * R + j] = __int_as_float(0x7fc00000);  // NaN: not computed yet
     }
-}
-
-// |x|^2 of 16-bit rows, the search's lane-group layout and summation order
-template <int TT>
-__global__ void k_sqnorm16(const char* X, int64_t n, int nch, int G, int lgG, float* out) {
-    const int lane = lane_id();
-    const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int RPP = WAVE >> lgG, group = lane >> lgG, sub = lane & (G - 1);
-    const int64_t row = wv * RPP + group;
-    const int cpl = nch / G;
-    float s = 0.0f;
-    if (row < n) {
-        const char* r = X + row * (int64_t)nch * 16 + sub * 16;
-        for (int j = 0; j < cpl; ++j) {
-            const uint4 x = *(const uint4*)(r + (int64_t)j * G * 16);
-            s = dot2x4<TT>(x, x, s);
-        }
-    }
-    s = group_sum_last(s, G);
-    if (row < n && sub == G - 1) out[row] = s;
-}
-
-hipError_t launch_sqnorm16(int tt, const void* X, int64_t n, int nch, int G, float* out,
-                           hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    const int lgG = ilog2i(G), RPP = WAVE / G;
-    const int64_t waves = (n + RPP - 1) / RPP;
-    const dim3 grid((unsigned)((waves * WAVE + 255) / 256)), block(256);
-    if (tt == 1)
-        hipLaunchKernelGGL(k_sqnorm16<1>, grid, block, 0, st, (const char*)X, n, nch, G, lgG, out);
-    else
-        hipLaunchKernelGGL(k_sqnorm16<2>, grid, block, 0, st, (const char*)X, n, nch, G, lgG, out);
-    return hipGetLastError();
 }
 
 // row norms, summed in double (the float32 copy is the double result rounded)
