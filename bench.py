@@ -28,7 +28,7 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM traffic of the k_beam_search launches of one timed merge, from two
 # rocprofv3 --pmc passes over `bench.py --steps 1 --warmup 0 --no-cpu-baseline
-# --no-bf16 --no-recall` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
+# --no-bf16 --no-recall --no-cm` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
 # each scaled by what the counter reads for a plain 1 GiB device copy
 # (FETCH_SIZE 0.5 GiB: factor 2.0; WRITE_SIZE 1 GiB: factor 1.0). The figures
 # hold for the sources they were taken on only (sha256 of the files below).
@@ -109,7 +109,7 @@ def recall_at_10(pkg, off, nb, entry, Xd, Qd, gt, ef=64):
 PHASES = ("expansion", "naive", "sliding")
 
 
-def time_merges(pkg, subs, Xd, wl, steps, warmup, search=None):
+def time_merges(pkg, subs, Xd, wl, steps, warmup, search=None, flags=0):
     """Time `steps` whole merges after `warmup`; per-phase event times and
     counts are summed over the timed steps."""
     import torch
@@ -118,7 +118,7 @@ def time_merges(pkg, subs, Xd, wl, steps, warmup, search=None):
     out = (torch.empty(N + 1, dtype=torch.int64, device=Xd.device),
            torch.empty(N * R, dtype=torch.int32, device=Xd.device),
            torch.empty(N * R, dtype=torch.float32, device=Xd.device))
-    kw = dict(R=R, L=wl["L"], alpha=wl["alpha"], search=search, out=out)
+    kw = dict(R=R, L=wl["L"], alpha=wl["alpha"], search=search, out=out, flags=flags)
     for _ in range(warmup):
         pkg.merge(subs, Xd, **kw)
     torch.cuda.synchronize()
@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-cm", action="store_true",
+                    help="skip the cross-query merge (every vertex a pivot) comparison line")
     ap.add_argument("--calib-only", action="store_true",
                     help="only copy 1 GiB device to device (counter calibration) and exit")
     args = ap.parse_args()
@@ -291,6 +293,21 @@ def main():
                 "search_frac": rb["frac"]}
         log(f"bf16 search copy: {bf16}")
 
+    # cross-query merge (every source vertex a pivot: naive searches only, no
+    # expansion, greedy or sliding), the comparison the paper makes for RNSM;
+    # fewer steps, since each merge runs ~5x the naive searches
+    cm = None
+    if not args.no_cm:
+        cm_steps = max(1, min(args.steps, 2))
+        dtc, aggc, stc, resc = time_merges(pkg, subs, Xd, wl, cm_steps, 1,
+                                           flags=pkg.FLAG_ALL_PIVOTS)
+        vc = cm_steps * stc["n_source_vertices"] / dtc
+        recc = recall_at_10(pkg, resc[0], resc[1], resc[3], Xd, Qd, gt) if gt is not None else None
+        cm = {"value": vc, "ms_per_step": 1000.0 * dtc / cm_steps, "steps": cm_steps,
+              "recall_at_10": recc, "rnsm_speedup": value / vc,
+              "naive_searches": stc["queries"][1], "ndc": stc["ndc"][1]}
+        log(f"cross-query merge: {cm}")
+
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
@@ -311,6 +328,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "bf16_form": bf16,
+        "cross_query_merge": cm,
         "phase_ms": {"expansion_search": st["ms_search"][0], "invert": st["ms_invert"],
                      "host_plan": st["ms_plan"], "naive_search": st["ms_search"][1],
                      "sliding_search": st["ms_search"][2], "prune_and_reverse": st["ms_prune"],
