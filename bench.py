@@ -84,11 +84,11 @@ def make_inputs(wl, seed_off=0):
     return np.ascontiguousarray(X), np.ascontiguousarray(Q)
 
 
-def build_subs(pkg, Xd, wl):
+def build_subs(pkg, Xd, wl, parts=2):
     from paper_2602_17099_amd.prepare import knn_l2_exact
     subs = []
-    n = wl["n"]
-    for i in range(2):
+    n = Xd.shape[0] // parts
+    for i in range(parts):
         Xi = Xd[i * n:(i + 1) * n]
         knn = knn_l2_exact(Xi, None, wl["K"], exclude_self=True)
         off, nb, entry = pkg.build_graph(Xi, knn, wl["R"], alpha=wl["build_alpha"],
@@ -96,6 +96,35 @@ def build_subs(pkg, Xd, wl):
         del knn
         subs.append((off, nb, entry))
     return subs
+
+
+def incremental(pkg, Xd, Qd, gt, wl, parts=4):
+    """The incremental scenario: the same vectors split into `parts` equal
+    sub-indexes, merged one at a time into the growing index (a pairwise
+    merge per step, the new sub-index as source). Sub-index builds are
+    input preparation, outside the timed steps."""
+    import torch
+    subs = build_subs(pkg, Xd, wl, parts)
+    n = Xd.shape[0] // parts
+    torch.cuda.synchronize()
+    acc = subs[0]
+    steps = []
+    t_all = 0.0
+    for i in range(1, parts):
+        Xi = Xd[:(i + 1) * n]
+        t = time.perf_counter()
+        off, nb, _, entry = pkg.merge([acc, subs[i]], Xi, R=wl["R"], L=wl["L"],
+                                      alpha=wl["alpha"], dists=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        t_all += dt
+        st = pkg.stats()
+        steps.append({"index_size": int(i * n), "added": int(n), "ms": 1000.0 * dt,
+                      "source_vertices": st["n_source_vertices"]})
+        acc = (off, nb, entry)
+    rec = recall_at_10(pkg, acc[0], acc[1], acc[2], Xd[:parts * n], Qd, gt) if gt is not None else None
+    return {"parts": parts, "sub_index_size": int(n), "steps": steps, "ms_total": 1000.0 * t_all,
+            "merged_vertices_per_s": (parts - 1) * n / t_all, "recall_at_10": rec}
 
 
 def recall_at_10(pkg, off, nb, entry, Xd, Qd, gt, ef=64):
@@ -220,6 +249,8 @@ def main():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-cm", action="store_true",
                     help="skip the cross-query merge (every vertex a pivot) comparison line")
+    ap.add_argument("--incremental", action="store_true",
+                    help="also time the incremental scenario: 4 sub-indexes merged one at a time")
     ap.add_argument("--calib-only", action="store_true",
                     help="only copy 1 GiB device to device (counter calibration) and exit")
     args = ap.parse_args()
@@ -308,6 +339,11 @@ def main():
               "naive_searches": stc["queries"][1], "ndc": stc["ndc"][1]}
         log(f"cross-query merge: {cm}")
 
+    inc = None
+    if args.incremental:
+        inc = incremental(pkg, Xd, Qd, gt, wl)
+        log(f"incremental merge: {inc}")
+
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
@@ -329,6 +365,7 @@ def main():
         "cpu_baseline": cpu,
         "bf16_form": bf16,
         "cross_query_merge": cm,
+        "incremental": inc,
         "phase_ms": {"expansion_search": st["ms_search"][0], "invert": st["ms_invert"],
                      "host_plan": st["ms_plan"], "naive_search": st["ms_search"][1],
                      "sliding_search": st["ms_search"][2], "prune_and_reverse": st["ms_prune"],
