@@ -272,6 +272,26 @@ def test_merge_many_long_lists_bit_exact(dev, orc, pkg, monkeypatch):
     assert pkg.stats()["n_pivots"] == ref["trace"]["n_pivots"]
 
 
+def test_incremental_merges_bit_exact(dev, orc, pkg):
+    # the incremental scenario: sub-indexes merged one at a time into the
+    # growing index, each step's merged graph (rows in prune order, degree up
+    # to R) the next step's first input
+    parts, n = 3, 1100
+    X = inputs.mixture_u8(parts * n, 24, comps=6, seed=1421)
+    subs = [orc.build_graph(X[i * n:(i + 1) * n], 24, 12, alpha=1.2, reverse=True)
+            for i in range(parts)]
+    acc_ref = subs[0]
+    acc_got = _dsubs([subs[0]], dev)[0]
+    for i in range(1, parts):
+        Xi = np.ascontiguousarray(X[:(i + 1) * n])
+        ref = orc.merge([acc_ref, subs[i]], Xi, R=12, L=24, alpha=1.2)
+        got = pkg.merge([acc_got, _dsubs([subs[i]], dev)[0]], _t(Xi, dev), R=12, L=24,
+                        alpha=1.2)
+        _assert_same_merge(got, ref)
+        acc_ref = (ref["offsets"], ref["nbrs"].astype(np.int32), ref["entry"])
+        acc_got = (got[0], got[1], got[3])
+
+
 def test_merge_centroid_costs_bit_exact(dev, orc, pkg):
     sizes = [700, 1500, 900, 1100, 600, 1300]
     # slab partition along a random direction: centroids differ
