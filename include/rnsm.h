@@ -66,7 +66,8 @@ typedef enum { RNSM_F32 = 0, RNSM_BF16 = 1, RNSM_F16 = 2, RNSM_U8 = 3 } rnsm_dty
  * CSR in device memory: offsets[n+1] (int64, offsets[0] = 0, non-decreasing),
  * nbrs[offsets[n]] local ids in [0, n). Rows hold no self-loop and no
  * duplicate, and at most R entries (rnsm_merge rejects others with
- * RNSM_EINVAL). entry: local id of the default entry point.
+ * RNSM_EINVAL); nbrs may be NULL when offsets[n] = 0 (no edges).
+ * entry: local id of the default entry point.
  */
 typedef struct {
     int64_t n;

@@ -371,7 +371,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     for (int i = 0; i < m; ++i) {
         const rnsm_graph& g = graphs[i];
         if (g.n < 1) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d is empty", i);
-        if (!g.offsets || !g.nbrs) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d has a NULL CSR pointer", i);
+        // nbrs may be NULL for a sub-index without edges (checked with nnz below)
+        if (!g.offsets) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d has a NULL CSR pointer", i);
         if (g.entry < 0 || g.entry >= g.n)
             return fail(RNSM_EINVAL, "rnsm_merge: entry %d of sub-index %d out of range", g.entry, i);
         sizes[i] = g.n;
@@ -403,6 +404,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     for (int i = 0; i < m; ++i) {
         if (first[i] != 0 || nnz[i] < 0)
             return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: offsets[0] != 0 or offsets[n] < 0", i);
+        if (nnz[i] > 0 && !graphs[i].nbrs)
+            return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d has a NULL CSR pointer", i);
         HIPCHK(launch_validate(graphs[i].offsets, graphs[i].nbrs, graphs[i].n, nnz[i], R, vflags + i, st));
     }
     std::vector<int> hflags(m);

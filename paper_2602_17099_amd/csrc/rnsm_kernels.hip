@@ -1036,10 +1036,12 @@ __device__ __forceinline__ double gram_dist(float g, int metric, float ui, float
 }
 
 // largest integer D with alpha * D < d (double products, exact for |D| < 2^29)
-__device__ __forceinline__ int dom_threshold(double alpha, float d) {
+// (the estimate takes the reciprocal of alpha >= 1; the two loops make the
+// result exact whatever its rounding)
+__device__ __forceinline__ int dom_threshold(double alpha, double inv_alpha, float d) {
     const double dd = (double)d;
     if (!(dd < 1.0e18) || !(dd > -1.0e18)) return dd > 0.0 ? 0x7fffffff : -0x7fffffff;
-    double t = floor(dd / alpha);
+    double t = floor(dd * inv_alpha);
     if (!(t < 1.0e9)) t = 1.0e9;
     if (t < -1.0e9) t = -1.0e9;
     int ti = (int)t;
@@ -1106,7 +1108,7 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
     const int dim = 32 * KD;
     const int jr = lane & 15, q = lane >> 4;
     const int metric = a.metric;
-    const double alpha = (double)a.alpha;
+    const double alpha = (double)a.alpha, inv_alpha = 1.0 / alpha;
     float pf[CENTER ? DL : 1];
     if constexpr (CENTER) {
 #pragma unroll
@@ -1207,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
         // exact rows, squared L2 or inner product: every d(w, v) is an exact
         // integer, so alpha * d(w, v) < d(p, v) is d(w, v) <= T (integer)
         const bool intd = NT == 1 && metric != 2;
-        const int tj = intd ? dom_threshold(alpha, dj) : 0;
+        const int tj = intd ? dom_threshold(alpha, inv_alpha, dj) : 0;
         const int uji = intd && metric == 0 ? (int)uj : 0;
         if constexpr (NT == 1) {  // tile J + 2's rows in flight
             if (J + 2 < ntiles) load_frag(J + 2, cur);

@@ -292,6 +292,39 @@ def test_incremental_merges_bit_exact(dev, orc, pkg):
         acc_got = (got[0], got[1], got[3])
 
 
+def _drop_rows(g, every, at):
+    off, nb, e = g
+    n = len(off) - 1
+    rows = [np.zeros(0, np.int32) if v % every == at else nb[off[v]:off[v + 1]]
+            for v in range(n)]
+    off2 = np.zeros(n + 1, np.int64)
+    off2[1:] = np.cumsum([len(r) for r in rows])
+    return off2, np.concatenate(rows).astype(np.int32), e
+
+
+@pytest.mark.parametrize("case", ["one_vertex_source", "isolated_vertices"])
+def test_merge_degenerate_bit_exact(dev, orc, pkg, case):
+    # degenerate inputs the method allows (one sub-index alone is rejected:
+    # m >= 2): a one-vertex source with no edges, vertices without edges in
+    # both sub-indexes (their expansion and reverse lists are empty; the
+    # source's entry is one of them, so its breadth-first order is one vertex
+    # plus the unreached rest)
+    X = inputs.tiny_int(701, 32, seed=1431)
+    s0 = orc.build_graph(X[:400], 24, 12, alpha=1.0)
+    if case == "one_vertex_source":
+        subs = [(np.array([0, 0], np.int64), np.zeros(0, np.int32), 0), s0]
+        Xm = np.concatenate([X[400:401], X[:400]])
+    else:
+        s1 = orc.build_graph(X[401:701], 24, 12, alpha=1.0)
+        subs = [_drop_rows(s0, 7, 3), _drop_rows(s1, 5, 1)]
+        Xm = np.concatenate([X[:400], X[401:701]])
+    Xm = np.ascontiguousarray(Xm)
+    ref = orc.merge(subs, Xm, R=12, L=24, alpha=1.2)
+    got = pkg.merge(_dsubs(subs, dev), _t(Xm, dev), R=12, L=24, alpha=1.2)
+    _assert_same_merge(got, ref)
+    assert pkg.stats()["n_ops"] == len(ref["ops"])
+
+
 def test_merge_centroid_costs_bit_exact(dev, orc, pkg):
     sizes = [700, 1500, 900, 1100, 600, 1300]
     # slab partition along a random direction: centroids differ
