@@ -28,16 +28,25 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM traffic of the k_beam_search launches of one timed merge, from two
 # rocprofv3 --pmc passes over `bench.py --steps 1 --warmup 0 --no-cpu-baseline
-# --no-bf16 --no-recall --no-cm` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
+# --no-bf16 --no-recall` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
 # each scaled by what the counter reads for a plain 1 GiB device copy
 # (FETCH_SIZE 0.5 GiB: factor 2.0; WRITE_SIZE 1 GiB: factor 1.0). The figures
 # hold for the sources they were taken on only (sha256 of the files below).
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
-    "sources_sha256": "82a903fcc7f8134fa48d5f0f0e0593c485fa20efb27a924bf9aaf60018214a21",
-    "fetch_kib": [29544956.062, 6844.75, 609025.312, 16097.062, 1266767.5, 41078.375, 3073633.25, 140842.625, 6372472.938, 246179.5, 9138936.062, 432189.312, 10051725.188, 847324.938, 11609219.375, 1932155.562, 13012176.438, 6115432.812, 12696854.25, 21375242.25, 2140187.812, 2763733.0],
-    "write_kib": [177452.906, 8.125, 4910.625, 25.0, 9851.875, 72.5, 19501.875, 247.5, 38840.0, 435.0, 38661.25, 775.625, 38301.25, 1491.25, 37578.75, 3314.375, 35752.5, 10318.125, 28744.375, 34956.25, 4106.25, 4607.5],
+    "sources_sha256": "b78109fe6f6f6b5c0e2076320aa85eded230b6fa2743e6c5ad4b18c9f6329499",
+    "fetch_kib": [
+        28790264.188, 6806.938, 582936.5, 16504.75, 1180737.625, 41417.625, 2997121.312,
+        136588.75, 6147314.938, 239905.938, 8773057.688, 423163.0, 9731800.062, 827886.562,
+        11414106.812, 1886377.062, 12529370.562, 5967009.062, 12371332.125, 20835091.125,
+        2079773.688, 2692091.188
+    ],
+    "write_kib": [
+        174324.562, 8.125, 4910.625, 25.0, 9851.875, 72.5, 19501.875, 247.5, 38840.0, 435.0,
+        38661.25, 775.625, 38301.25, 1491.25, 37578.75, 3314.375, 35752.5, 10318.125, 28744.375,
+        34956.25, 4106.25, 4607.5
+    ],
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
@@ -247,8 +256,8 @@ def main():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
-    ap.add_argument("--no-cm", action="store_true",
-                    help="skip the cross-query merge (every vertex a pivot) comparison line")
+    ap.add_argument("--cm", action="store_true",
+                    help="also time the cross-query merge (every vertex a pivot) for comparison")
     ap.add_argument("--incremental", action="store_true",
                     help="also time the incremental scenario: 4 sub-indexes merged one at a time")
     ap.add_argument("--calib-only", action="store_true",
@@ -328,7 +337,7 @@ def main():
     # expansion, greedy or sliding), the comparison the paper makes for RNSM;
     # fewer steps, since each merge runs ~5x the naive searches
     cm = None
-    if not args.no_cm:
+    if args.cm:
         cm_steps = max(1, min(args.steps, 2))
         dtc, aggc, stc, resc = time_merges(pkg, subs, Xd, wl, cm_steps, 1,
                                            flags=pkg.FLAG_ALL_PIVOTS)
