@@ -38,8 +38,8 @@ struct SearchArgs {
     int G;                    // lanes per row (power of two)
     int lgG;                  // log2(G)
     int cpl;                  // 16-byte chunks per lane (nch = G * cpl)
-    int hbits;                // log2 of the LDS visited-table size per wavefront
-    int hash_mode;            // 0: direct-mapped (forgetful), 1: linear probing
+    int hbits;                // log2 of the LDS visited-table words (32-bit) per wavefront
+    int hash_mode;            // 0: two-way sets of 16-bit tags (forgetful), 1: linear probing
     int out_mode;             // 0: first out_k of the beam, 1: first out_k excluding the query's own id
     int32_t* out_ids;
     float* out_d;
