@@ -132,10 +132,8 @@ size_t scan_tmp_elems(int64_t n);
 // words, lists of lcap or more as (length, id) in high[0, min(ctl[0], cap)))
 hipError_t launch_gain_levels(const int32_t* cnt, int64_t n, int lcap, unsigned long long* bits,
                               int* ctl, int2* high, int64_t cap, hipStream_t st);
-hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int64_t* rk_off,
-                         int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st);
-// the two halves of launch_invert: list lengths into cnt, then offsets and
-// ids (cnt is overwritten)
+// reverse k-NN inversion (R_k) in two halves: list lengths into cnt, then
+// offsets and ids (cnt is overwritten)
 hipError_t launch_count_ids(const int32_t* nk, int64_t n, int k, int32_t* cnt, hipStream_t st);
 hipError_t launch_invert_lists(const int32_t* nk, int64_t n, int k, int32_t* cnt,
                                int64_t* rk_off, int32_t* rk_ids, int64_t* scan_tmp,
@@ -146,7 +144,6 @@ hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, const flo
                               int64_t s_base, int64_t n_s, int R, int64_t t_base, int64_t n_t,
                               const int64_t* off, int32_t* cur, int32_t* rev, float* rev_d,
                               hipStream_t st);
-hipError_t launch_max_i32(const int32_t* v, int64_t n, int32_t* out, hipStream_t st);
 // CSR output; for inner product and cosine (norms64 required then) every
 // stored distance is recomputed with float64 sums
 hipError_t launch_compact(const int32_t* rows, const int32_t* deg, const float* rdist,

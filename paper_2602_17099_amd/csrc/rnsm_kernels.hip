@@ -1635,11 +1635,6 @@ __global__ void k_rev_scatter(const int32_t* rows, const int32_t* deg, const flo
     if (rev_d) rev_d[off[v] + pos] = rdist[g * R + j];  // d(u, v) = d(v, u), same arithmetic
 }
 
-__global__ void k_max_i32(const int32_t* v, int64_t n, int32_t* out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) atomicMax(out, v[t]);
-}
-
 // One wavefront per vertex (R <= 64: one lane per slot). Distances a prune
 // did not compute (input edges of rows no operation touched) are computed
 // here with the prune's lane-group layout and summation order.
@@ -2209,13 +2204,6 @@ hipError_t launch_gain_levels(const int32_t* cnt, int64_t n, int lcap, unsigned 
     return hipGetLastError();
 }
 
-hipError_t launch_invert(const int32_t* nk, int64_t n, int k, int32_t* cnt, int64_t* rk_off,
-                         int32_t* rk_ids, int64_t* scan_tmp, hipStream_t st) {
-    hipError_t e = launch_count_ids(nk, n, k, cnt, st);
-    if (e != hipSuccess) return e;
-    return launch_invert_lists(nk, n, k, cnt, rk_off, rk_ids, scan_tmp, st);
-}
-
 hipError_t launch_invert_lists(const int32_t* nk, int64_t n, int k, int32_t* cnt,
                                int64_t* rk_off, int32_t* rk_ids, int64_t* scan_tmp,
                                hipStream_t st) {
@@ -2245,12 +2233,6 @@ hipError_t launch_rev_scatter(const int32_t* rows, const int32_t* deg, const flo
     if (n_s <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_rev_scatter, dim3(nblk(n_s * R, 256)), dim3(256), 0, st, rows, deg, rdist,
                        s_base, n_s, R, t_base, n_t, off, cur, rev, rev_d);
-    return hipGetLastError();
-}
-
-hipError_t launch_max_i32(const int32_t* v, int64_t n, int32_t* out, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_max_i32, dim3(nblk(n, 256)), dim3(256), 0, st, v, n, out);
     return hipGetLastError();
 }
 
