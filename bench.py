@@ -35,15 +35,15 @@ PEAK_HBM_GBS = 8000.0
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
-    "sources_sha256": "b78109fe6f6f6b5c0e2076320aa85eded230b6fa2743e6c5ad4b18c9f6329499",
+    "sources_sha256": "79261d7a362ad4de23daba9517a192062ea022ecc6a241c1e9d27eefc41d9cf5",
     "fetch_kib": [
-        28790264.188, 6806.938, 582936.5, 16504.75, 1180737.625, 41417.625, 2997121.312,
-        136588.75, 6147314.938, 239905.938, 8773057.688, 423163.0, 9731800.062, 827886.562,
-        11414106.812, 1886377.062, 12529370.562, 5967009.062, 12371332.125, 20835091.125,
-        2079773.688, 2692091.188
+        29035964.125, 6856.875, 589517.25, 16732.0, 1211585.688, 41940.188, 3020435.625,
+        137183.938, 6225472.625, 240314.562, 8839491.438, 424150.812, 9966703.75, 829687.688,
+        11468873.625, 1885424.0, 12733923.562, 5995736.188, 12533724.125, 20868629.125,
+        2088558.125, 2699729.625
     ],
     "write_kib": [
-        174324.562, 8.125, 4910.625, 25.0, 9851.875, 72.5, 19501.875, 247.5, 38840.0, 435.0,
+        174504.562, 8.125, 4910.625, 25.0, 9851.875, 72.5, 19501.875, 247.5, 38840.0, 435.0,
         38661.25, 775.625, 38301.25, 1491.25, 37578.75, 3314.375, 35752.5, 10318.125, 28744.375,
         34956.25, 4106.25, 4607.5
     ],
