@@ -35,17 +35,15 @@ PEAK_HBM_GBS = 8000.0
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
-    "sources_sha256": "79261d7a362ad4de23daba9517a192062ea022ecc6a241c1e9d27eefc41d9cf5",
+    "sources_sha256": "610081a2206bf5a9d00ce19bdbd63ab917395fcb6b5c2a8894f3d073be106a90",
     "fetch_kib": [
-        29035964.125, 6856.875, 589517.25, 16732.0, 1211585.688, 41940.188, 3020435.625,
-        137183.938, 6225472.625, 240314.562, 8839491.438, 424150.812, 9966703.75, 829687.688,
-        11468873.625, 1885424.0, 12733923.562, 5995736.188, 12533724.125, 20868629.125,
-        2088558.125, 2699729.625
+        29002735.125, 6830.562, 602755.75, 16303.25, 1200769.75, 41541.562, 3017312.938,
+        137748.938, 6348718.812, 657428.0, 15786893.75, 2732649.125, 20907616.688, 26702515.188,
+        14256735.875, 2724346.688
     ],
     "write_kib": [
-        174504.562, 8.125, 4910.625, 25.0, 9851.875, 72.5, 19501.875, 247.5, 38840.0, 435.0,
-        38661.25, 775.625, 38301.25, 1491.25, 37578.75, 3314.375, 35752.5, 10318.125, 28744.375,
-        34956.25, 4106.25, 4607.5
+        174244.062, 8.125, 4910.625, 25.0, 9851.875, 72.5, 19501.875, 247.5, 38840.0, 1209.375,
+        76917.5, 4800.0, 73328.125, 45226.25, 32898.75, 4662.5
     ],
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
