@@ -1014,10 +1014,11 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
                 fcnt.resize(ns);
                 rbits.assign((size_t)((ns + 63) / 64), 0ull);
             }
-            int64_t chunk = std::max<int64_t>(4096, ns / 64);
-            // chunks double up to ns / 4 with float32 rows (fewer, longer
-            // launches measured faster) and ns / 8 with 16-bit rows (their
-            // faster searches would otherwise wait on the greedy)
+            // chunks double from ns / 16 up to ns / 4 with float32 rows (fewer,
+            // longer launches measured faster), from ns / 64 up to ns / 8 with
+            // 16-bit rows (their faster searches would otherwise wait on the
+            // greedy)
+            int64_t chunk = std::max<int64_t>(4096, ns / (vi.tt == 0 ? 16 : 64));
             const int64_t chunk_div = vi.tt == 0 ? 4 : 8;
             if (const char* c = getenv("RNSM_PIVOT_CHUNK")) chunk = std::max(1ll, atoll(c));
             select_pivots(levels, h_off, h_ids, h_piv, h_fol, h_folp, chunk,
