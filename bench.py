@@ -35,15 +35,14 @@ PEAK_HBM_GBS = 8000.0
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
-    "sources_sha256": "610081a2206bf5a9d00ce19bdbd63ab917395fcb6b5c2a8894f3d073be106a90",
+    "sources_sha256": "67648f78b5de9374ce8812d0d960365980174a13a8fa0480f76a8630756c8f3b",
     "fetch_kib": [
-        29002735.125, 6830.562, 602755.75, 16303.25, 1200769.75, 41541.562, 3017312.938,
-        137748.938, 6348718.812, 657428.0, 15786893.75, 2732649.125, 20907616.688, 26702515.188,
-        14256735.875, 2724346.688
+        29083410.625, 30528.188, 2549921.562, 107318.188, 5803188.688, 528371.5, 14772689.812,
+        1986568.125, 19731532.625, 18862423.938, 18640794.875, 11675364.375
     ],
     "write_kib": [
-        174244.062, 8.125, 4910.625, 25.0, 9851.875, 72.5, 19501.875, 247.5, 38840.0, 1209.375,
-        76917.5, 4800.0, 73328.125, 45226.25, 32898.75, 4662.5
+        174437.594, 48.125, 19571.875, 193.125, 38870.0, 970.625, 77168.125, 3530.625, 74595.625,
+        32081.875, 46043.125, 19426.875
     ],
 }
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
