@@ -243,9 +243,27 @@ void select_pivots(GainLevels& L, const int64_t* rk_off, const int32_t* rk_ids, 
         L.high.pop_back();
         if (!((cov[e.second >> 6] >> (e.second & 63)) & 1ull)) visit(e.second, e.first);
     }
+    // A level is scanned in id order, but the lists of its vertices lie all
+    // over the offsets and ids, so each visit would wait on memory: the
+    // offsets of the vertices a few bitmap words ahead, and then their ids,
+    // are fetched early.
+    constexpr int64_t PF_OFF = 16, PF_IDS = 8;  // bitmap words ahead
+    auto prefetch_word = [&](const uint64_t* b, int64_t w, bool ids) {
+        uint64_t m = b[w] & ~cov[w];
+        while (m) {
+            const int64_t x = w * 64 + __builtin_ctzll(m);
+            m &= m - 1;
+            if (ids)
+                __builtin_prefetch(rk_ids + rk_off[x]);
+            else
+                __builtin_prefetch(rk_off + x);
+        }
+    };
     for (int64_t g = L.nlev - 1; g >= 0; --g) {
         uint64_t* b = lv + (size_t)g * words;
         for (int64_t w = 0; w < words; ++w) {
+            if (w + PF_OFF < words) prefetch_word(b, w + PF_OFF, false);
+            if (w + PF_IDS < words) prefetch_word(b, w + PF_IDS, true);
             uint64_t bits = b[w] & ~cov[w];
             while (bits) {
                 const int32_t x = (int32_t)(w * 64 + __builtin_ctzll(bits));
