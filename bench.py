@@ -35,13 +35,13 @@ PEAK_HBM_GBS = 8000.0
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
-    "sources_sha256": "67648f78b5de9374ce8812d0d960365980174a13a8fa0480f76a8630756c8f3b",
+    "sources_sha256": "8bbf3b47d241f6841946fcf019e772cc5af5c0df83a2458341ae0a0c747bd589",
     "fetch_kib": [
-        29083410.625, 30528.188, 2549921.562, 107318.188, 5803188.688, 528371.5, 14772689.812,
-        1986568.125, 19731532.625, 18862423.938, 18640794.875, 11675364.375
+        28993254.312, 29619.0, 2476405.188, 107578.938, 5840651.875, 527570.125, 14954279.875,
+        1975751.125, 19809539.125, 18831470.5, 18587521.312, 11636306.5
     ],
     "write_kib": [
-        174437.594, 48.125, 19571.875, 193.125, 38870.0, 970.625, 77168.125, 3530.625, 74595.625,
+        174299.5, 48.125, 19571.875, 193.125, 38870.0, 970.625, 77168.125, 3530.625, 74595.625,
         32081.875, 46043.125, 19426.875
     ],
 }

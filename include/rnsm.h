@@ -208,6 +208,28 @@ rnsm_status mos_plan(int32_t m, const int64_t* sizes, const double* centroids, i
                      int32_t* out_count, int32_t* out_fallbacks);
 
 /*
+ * Pivot and follower selection of RNSM (Algorithm 2, phase 2): the lazy
+ * greedy over the reverse k-NN lists R_k, the same host code the merge runs
+ * while its searches start. Host only: deterministic, thread-safe, no device
+ * work. Repeatedly takes the vertex with the largest gain |R_k(x) minus
+ * Covered| (ties: the smallest id); it becomes a pivot, and its uncovered
+ * R_k members become its followers; it and they are then covered.
+ * rk_offsets: host [n+1] int64, rk_offsets[0] = 0, non-decreasing;
+ * rk_ids: host [rk_offsets[n]] int32, R_k(x) = rk_ids[rk_offsets[x] ..
+ * rk_offsets[x+1]), ids in 0..n-1, not x itself, no repeats (may be NULL
+ * when rk_offsets[n] = 0). All borrowed, read-only.
+ * Outputs, host, caller-owned, capacity n each: pivots in selection order
+ * (*out_n_pivots of them); followers grouped by pivot in selection order,
+ * each group in its pivot's list order, with follower_pivot[i] the pivot of
+ * followers[i] (*out_n_followers of them). Every vertex is written once,
+ * as a pivot or as a follower: *out_n_pivots + *out_n_followers = n.
+ * RNSM_EINVAL: n < 0 or n > INT32_MAX, NULL pointers, malformed lists.
+ */
+rnsm_status rnsm_select_pivots(int64_t n, const int64_t* rk_offsets, const int32_t* rk_ids,
+                               int32_t* pivots, int64_t* out_n_pivots, int32_t* followers,
+                               int32_t* follower_pivot, int64_t* out_n_followers);
+
+/*
  * Beam search (Algorithm 1) of nq queries in one graph.
  * g: the graph (local ids 0..n-1, device CSR), base: its n vectors
  * (search_dtype/search/f32 as in rnsm_vectors; base->n == g->n).

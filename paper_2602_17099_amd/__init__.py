@@ -17,8 +17,8 @@ F32, BF16, F16 = 0, 1, 2
 FLAG_ALL_PIVOTS = 1
 FLAG_CENTROID_COSTS = 2
 
-SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_search", "rnsm_build_graph",
-           "rnsm_convert", "rnsm_get_stats", "rnsm_last_error"]
+SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_select_pivots", "rnsm_search",
+           "rnsm_build_graph", "rnsm_convert", "rnsm_get_stats", "rnsm_last_error"]
 
 _lib = None
 
@@ -78,6 +78,8 @@ def lib():
         L.rnsm_merge_simple.argtypes = [C.c_int32, P, P, C.c_int32, C.c_int32, C.c_float, P]
         L.mos_plan.restype = C.c_int
         L.mos_plan.argtypes = [C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_int32, P, P]
+        L.rnsm_select_pivots.restype = C.c_int
+        L.rnsm_select_pivots.argtypes = [C.c_int64, P, P, P, P, P, P, P]
         L.rnsm_search.restype = C.c_int
         L.rnsm_search.argtypes = [P, P, P, C.c_int64, P, C.c_int32, C.c_int32, C.c_int32, C.c_int,
                                   P, P, P]
@@ -199,6 +201,25 @@ def mos_plan(sizes, degree_bound, diameter=2, centroids=None):
                           0 if cen is None else cen.shape[1], degree_bound, diameter,
                           ops.ctypes.data_as(C.c_void_p), cap, C.byref(cnt), C.byref(fb)))
     return [tuple(int(x) for x in o) for o in ops[: cnt.value]], fb.value
+
+
+def select_pivots(rk_offsets, rk_ids):
+    """Host-only lazy greedy over reverse k-NN lists (CSR, numpy): pivots in
+    selection order, followers grouped by pivot, and each follower's pivot."""
+    import numpy as np
+    off = np.ascontiguousarray(rk_offsets, dtype=np.int64)
+    ids = np.ascontiguousarray(rk_ids, dtype=np.int32)
+    n = off.shape[0] - 1
+    piv = np.empty(max(n, 1), dtype=np.int32)
+    fol = np.empty(max(n, 1), dtype=np.int32)
+    fp = np.empty(max(n, 1), dtype=np.int32)
+    npv, nfl = C.c_int64(0), C.c_int64(0)
+    _check(lib().rnsm_select_pivots(n, off.ctypes.data_as(C.c_void_p),
+                                    ids.ctypes.data_as(C.c_void_p) if ids.size else None,
+                                    piv.ctypes.data_as(C.c_void_p), C.byref(npv),
+                                    fol.ctypes.data_as(C.c_void_p),
+                                    fp.ctypes.data_as(C.c_void_p), C.byref(nfl)))
+    return piv[: npv.value].copy(), fol[: nfl.value].copy(), fp[: nfl.value].copy()
 
 
 def search(offsets, nbrs, entry, base, queries, ef, k, seeds=None, metric=L2SQ,

@@ -334,6 +334,43 @@ rnsm_status mos_plan(int32_t m, const int64_t* sizes, const double* centroids, i
     return RNSM_OK;
 }
 
+rnsm_status rnsm_select_pivots(int64_t n, const int64_t* rk_offsets, const int32_t* rk_ids,
+                               int32_t* pivots, int64_t* out_n_pivots, int32_t* followers,
+                               int32_t* follower_pivot, int64_t* out_n_followers) {
+    g_err.clear();
+    if (n < 0 || n > INT32_MAX) return fail(RNSM_EINVAL, "rnsm_select_pivots: n out of range");
+    if (!rk_offsets || !out_n_pivots || !out_n_followers || (n > 0 && (!pivots || !followers ||
+                                                                       !follower_pivot)))
+        return fail(RNSM_EINVAL, "rnsm_select_pivots: NULL pointer");
+    if (rk_offsets[0] != 0) return fail(RNSM_EINVAL, "rnsm_select_pivots: rk_offsets[0] != 0");
+    for (int64_t x = 0; x < n; ++x)
+        if (rk_offsets[x + 1] < rk_offsets[x])
+            return fail(RNSM_EINVAL, "rnsm_select_pivots: rk_offsets decrease at %lld", (long long)x);
+    if (rk_offsets[n] > 0 && !rk_ids) return fail(RNSM_EINVAL, "rnsm_select_pivots: NULL rk_ids");
+    // a list names other vertices, each once (the gain counts distinct ids)
+    std::vector<int32_t> seen((size_t)n, -1);
+    std::vector<int32_t> counts((size_t)n);
+    for (int64_t x = 0; x < n; ++x) {
+        for (int64_t j = rk_offsets[x]; j < rk_offsets[x + 1]; ++j) {
+            const int32_t y = rk_ids[j];
+            if (y < 0 || y >= n || y == x || seen[(size_t)y] == (int32_t)x)
+                return fail(RNSM_EINVAL, "rnsm_select_pivots: list of %lld: id %d out of range, "
+                            "itself or repeated", (long long)x, (int)y);
+            seen[(size_t)y] = (int32_t)x;
+        }
+        counts[(size_t)x] = (int32_t)std::min<int64_t>(rk_offsets[x + 1] - rk_offsets[x], INT32_MAX);
+    }
+    GainLevels levels;
+    build_levels(n, counts.data(), levels);
+    int64_t np = 0, nf = 0;
+    select_pivots(levels, rk_offsets, rk_ids, pivots, followers, follower_pivot,
+                  std::max<int64_t>(n, 1), std::max<int64_t>(n, 1),
+                  [&](int64_t a, int64_t b) { np = a; nf = b; });
+    *out_n_pivots = np;
+    *out_n_followers = nf;
+    return RNSM_OK;
+}
+
 rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
                        const rnsm_params* p, rnsm_csr* out) {
     const auto t0 = std::chrono::steady_clock::now();

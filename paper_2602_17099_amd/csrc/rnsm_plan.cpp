@@ -259,7 +259,7 @@ void select_pivots(GainLevels& L, const int64_t* rk_off, const int32_t* rk_ids, 
                 __builtin_prefetch(rk_off + x);
         }
     };
-    for (int64_t g = L.nlev - 1; g >= 0; --g) {
+    for (int64_t g = L.nlev - 1; g >= 1; --g) {
         uint64_t* b = lv + (size_t)g * words;
         for (int64_t w = 0; w < words; ++w) {
             if (w + PF_OFF < words) prefetch_word(b, w + PF_OFF, false);
@@ -270,6 +270,21 @@ void select_pivots(GainLevels& L, const int64_t* rk_off, const int32_t* rk_ids, 
                 bits &= bits - 1;
                 visit(x, g);
                 bits &= ~cov[w];
+            }
+        }
+    }
+    // Gain 0 last: a gain never rises, so every vertex still uncovered here
+    // is a pivot whose reverse list is all covered (no followers, nothing
+    // newly covered), taken in ascending id order without reading its list.
+    for (int64_t w = 0; L.nlev > 0 && w < words; ++w) {
+        uint64_t bits = lv[w] & ~cov[w];
+        while (bits) {
+            pivots[np++] = (int32_t)(w * 64 + __builtin_ctzll(bits));
+            bits &= bits - 1;
+            if (np + nf - sent >= chunk) {
+                emit(np, nf);
+                sent = np + nf;
+                chunk = std::max(chunk, std::min(2 * chunk, chunk_max));
             }
         }
     }

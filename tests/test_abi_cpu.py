@@ -93,3 +93,99 @@ def test_convert_rejects_on_host(pkg):
     assert L.rnsm_convert(p, 0, p, 1, -1, None) == 1         # negative count
     assert "unsupported" in pkg.last_error() or "count" in pkg.last_error()
     assert L.rnsm_convert(None, 0, None, 1, 0, None) == 0    # nothing to do
+
+
+# ------------------------------------------------- lazy greedy on the host
+
+def _expected_groups(rk_off, rk_ids, pivot_of, order):
+    """Followers grouped by pivot (selection order), each group in its
+    pivot's list order, from the oracle's pivot assignment."""
+    fol, fp = [], []
+    for p in order.tolist():
+        for y in rk_ids[rk_off[p]:rk_off[p + 1]].tolist():
+            if pivot_of[y] == p:
+                fol.append(y)
+                fp.append(p)
+    return fol, fp
+
+
+def _skewed_knn(g, n, k, skew):
+    """N_k lists drawn with popularity ~ rank^-skew, so a few reverse lists
+    are long (well past 32, the greedy's bitmap levels) and many are empty."""
+    w = 1.0 / np.arange(1, n + 1) ** skew
+    perm = g.permutation(n)
+    p = np.empty(n)
+    p[perm] = w / w.sum()
+    nk = np.empty((n, k), np.int32)
+    for v in range(n):
+        q = p.copy()
+        q[v] = 0.0
+        nk[v] = g.choice(n, k, replace=False, p=q / q.sum())
+    return nk
+
+
+@pytest.mark.parametrize("n,k,skew,seed", [(1, 0, 0.0, 0), (2, 1, 0.0, 1), (64, 3, 0.0, 2),
+                                           (65, 3, 0.5, 3), (700, 5, 0.0, 4), (3000, 5, 0.8, 5),
+                                           (3000, 7, 1.1, 6), (5000, 3, 0.3, 7)])
+def test_select_pivots_matches_oracle(pkg, orc, n, k, skew, seed):
+    # the merge's own host greedy (Algorithm 2, phase 2) against the oracle's
+    # heap-based lazy greedy, itself pinned to an eager greedy
+    g = np.random.default_rng(seed)
+    if k == 0:
+        off, ids = np.zeros(n + 1, np.int64), np.zeros(0, np.int32)
+    else:
+        off, ids = orc.invert(_skewed_knn(g, n, k, skew))
+    piv, fol, fp = pkg.select_pivots(off, ids)
+    pivot_of, order = orc.pivots(off, ids)
+    assert piv.tolist() == order.tolist()
+    efol, efp = _expected_groups(off, ids, pivot_of, order)
+    assert fol.tolist() == efol and fp.tolist() == efp
+    assert len(piv) + len(fol) == n
+    assert sorted(piv.tolist() + fol.tolist()) == list(range(n))
+    if skew >= 0.8:
+        assert (np.diff(off) >= 32).any()  # the heap path ran
+
+
+def test_select_pivots_long_random_lists(pkg, orc):
+    # many bitmap words and every gain level, uniform random N_k
+    g = np.random.default_rng(11)
+    n, k = 100_000, 5
+    # v + 1 + (0..n-2) mod n never names v; rows with a repeated id are redrawn
+    nk = ((np.arange(n)[:, None] + 1 + g.integers(0, n - 1, size=(n, k))) % n).astype(np.int32)
+    s = np.sort(nk, axis=1)
+    for v in np.nonzero((s[:, 1:] == s[:, :-1]).any(axis=1))[0]:
+        nk[v] = (v + 1 + g.choice(n - 1, k, replace=False)) % n
+    off, ids = orc.invert(nk)
+    piv, fol, fp = pkg.select_pivots(off, ids)
+    pivot_of, order = orc.pivots(off, ids)
+    assert np.array_equal(piv, order)
+    efol, efp = _expected_groups(off, ids, pivot_of, order)
+    assert fol.tolist() == efol and fp.tolist() == efp
+
+
+def test_select_pivots_special_cases(pkg):
+    # no vertices; lists all empty (every vertex its own pivot, in id order);
+    # a star: the hub's list holds everyone else
+    piv, fol, fp = pkg.select_pivots(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    assert len(piv) == len(fol) == len(fp) == 0
+    piv, fol, _ = pkg.select_pivots(np.zeros(6, np.int64), np.zeros(0, np.int32))
+    assert piv.tolist() == [0, 1, 2, 3, 4] and len(fol) == 0
+    n = 40
+    off = np.array([0] * 8 + [n - 1] * (n - 7), np.int64)
+    ids = np.array([y for y in range(n) if y != 7], np.int32)
+    piv, fol, fp = pkg.select_pivots(off, ids)
+    assert piv.tolist() == [7] and fol.tolist() == ids.tolist() and set(fp.tolist()) == {7}
+
+
+def test_select_pivots_rejects(pkg):
+    L = pkg.lib()
+    for off, ids, msg in [([0, 1, 1], [0], "itself"), ([0, 2, 2], [1, 1], "repeated"),
+                          ([0, 1, 1], [5], "out of range"), ([0, 2, 1], [1, 0], "decrease"),
+                          ([1, 1, 1], [0], "rk_offsets[0]")]:
+        with pytest.raises(pkg.RnsmError, match=msg.replace("[", r"\[").replace("]", r"\]")):
+            pkg.select_pivots(np.array(off, np.int64), np.array(ids, np.int32))
+    assert L.rnsm_select_pivots(-1, None, None, None, None, None, None, None) == 1
+    z = np.zeros(3, np.int64)
+    assert L.rnsm_select_pivots(2, z.ctypes.data_as(C.c_void_p), None, None, None, None, None,
+                                None) == 1
+    assert "NULL" in pkg.last_error()
