@@ -35,13 +35,13 @@ PEAK_HBM_GBS = 8000.0
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
-    "sources_sha256": "8bbf3b47d241f6841946fcf019e772cc5af5c0df83a2458341ae0a0c747bd589",
+    "sources_sha256": "28343a6889b8eda2df4e95368fbd9069156738bcab3ac4c0733ac8bcabaf4184",
     "fetch_kib": [
-        28993254.312, 29619.0, 2476405.188, 107578.938, 5840651.875, 527570.125, 14954279.875,
-        1975751.125, 19809539.125, 18831470.5, 18587521.312, 11636306.5
+        28835337.125, 30323.375, 2582459.938, 108508.0, 5894143.875, 529428.688, 14815167.438,
+        1996925.062, 19778152.688, 18819444.938, 18382456.812, 11649019.625
     ],
     "write_kib": [
-        174299.5, 48.125, 19571.875, 193.125, 38870.0, 970.625, 77168.125, 3530.625, 74595.625,
+        174328.594, 48.125, 19571.875, 193.125, 38870.0, 970.625, 77168.125, 3530.625, 74595.625,
         32081.875, 46043.125, 19426.875
     ],
 }
@@ -144,7 +144,7 @@ def recall_at_10(pkg, off, nb, entry, Xd, Qd, gt, ef=64):
 PHASES = ("expansion", "naive", "sliding")
 
 
-def time_merges(pkg, subs, Xd, wl, steps, warmup, search=None, flags=0):
+def time_merges(pkg, subs, Xd, wl, steps, warmup, search=None, flags=0, shape=None):
     """Time `steps` whole merges after `warmup`; per-phase event times and
     counts are summed over the timed steps."""
     import torch
@@ -153,7 +153,8 @@ def time_merges(pkg, subs, Xd, wl, steps, warmup, search=None, flags=0):
     out = (torch.empty(N + 1, dtype=torch.int64, device=Xd.device),
            torch.empty(N * R, dtype=torch.int32, device=Xd.device),
            torch.empty(N * R, dtype=torch.float32, device=Xd.device))
-    kw = dict(R=R, L=wl["L"], alpha=wl["alpha"], search=search, out=out, flags=flags)
+    kw = dict(R=R, L=wl["L"], alpha=wl["alpha"], search=search, out=out, flags=flags,
+              search_shape=shape)
     for _ in range(warmup):
         pkg.merge(subs, Xd, **kw)
     torch.cuda.synchronize()
@@ -173,6 +174,30 @@ def time_merges(pkg, subs, Xd, wl, steps, warmup, search=None, flags=0):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return dt, agg, st, res
+
+
+def autotune(pkg, subs, Xd, wl, args, ms_default, off, nb, bf16):
+    """Search-shape autotuner on the target sub-index (its own rows as
+    queries, beam L), then whole merges under the shape it picks, against the
+    default shape's merges; the graph must not change."""
+    import torch
+    n0 = subs[0][0].shape[0] - 1
+    o, b, e = subs[1]
+    out = {}
+    forms = [("fp32", None, ms_default)]
+    if bf16 is not None:
+        forms.append(("bf16", bf16[0], bf16[1]))
+    for name, search, ms_def in forms:
+        t = pkg.tune_search(o, b, e, Xd[n0:], wl["L"], n_sample=65536,
+                            base_search=None if search is None else search[n0:])
+        dt, _, _, res = time_merges(pkg, subs, Xd, wl, args.steps, args.warmup, search=search,
+                                    shape=t["shape"])
+        out[name] = {"shape": list(t["shape"]), "default_shape": list(t["default_shape"]),
+                     "sample_ms": t["ms"], "default_sample_ms": t["default_ms"],
+                     "sample_queries": t["n_queries"], "shapes_tried": t["n_tried"],
+                     "ms_per_step": 1000.0 * dt / args.steps, "default_ms_per_step": ms_def,
+                     "same_graph": bool(torch.equal(res[0], off) and torch.equal(res[1], nb))}
+    return out
 
 
 def exact_ndc(pkg, subs, Xd, wl, search=None):
@@ -257,6 +282,9 @@ def main():
                     help="also time the cross-query merge (every vertex a pivot) for comparison")
     ap.add_argument("--incremental", action="store_true",
                     help="also time the incremental scenario: 4 sub-indexes merged one at a time")
+    ap.add_argument("--autotune", action="store_true",
+                    help="also tune the search shape on the target sub-index and time merges "
+                         "under the shape it picks (float32 and bfloat16 copies)")
     ap.add_argument("--calib-only", action="store_true",
                     help="only copy 1 GiB device to device (counter calibration) and exit")
     args = ap.parse_args()
@@ -345,6 +373,12 @@ def main():
               "naive_searches": stc["queries"][1], "ndc": stc["ndc"][1]}
         log(f"cross-query merge: {cm}")
 
+    tuned = None
+    if args.autotune:
+        tuned = autotune(pkg, subs, Xd, wl, args, ms_step, off, nb,
+                         None if args.no_bf16 else (Xb, bf16["ms_per_step"]))
+        log(f"autotuned search shape: {tuned}")
+
     inc = None
     if args.incremental:
         inc = incremental(pkg, Xd, Qd, gt, wl)
@@ -372,6 +406,7 @@ def main():
         "bf16_form": bf16,
         "cross_query_merge": cm,
         "incremental": inc,
+        "autotune": tuned,
         "phase_ms": {"expansion_search": st["ms_search"][0], "invert": st["ms_invert"],
                      "host_plan": st["ms_plan"], "naive_search": st["ms_search"][1],
                      "sliding_search": st["ms_search"][2], "prune_and_reverse": st["ms_prune"],

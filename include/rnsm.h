@@ -110,6 +110,12 @@ typedef struct {
  * mos_diameter MOS diameter bound (default 2, must be >= 2)
  * flags    RNSM_FLAG_*
  * stream   hipStream_t or NULL
+ * search_hash_bits, search_waves_per_block  shape of every beam search of
+ *          the merge: log2 of the LDS visited table's two-way sets (8..12)
+ *          and wavefronts per block (1..4, fewer when a block would need
+ *          over 64 KB of LDS); 0 = the library's default for the beam width,
+ *          degree and storage type. rnsm_tune_search measures them. Results
+ *          do not depend on the shape, only the speed does.
  */
 typedef struct {
     int32_t R, L;
@@ -119,6 +125,7 @@ typedef struct {
     int32_t mos_degree, mos_diameter;
     uint32_t flags;
     void* stream;
+    int32_t search_hash_bits, search_waves_per_block;
 } rnsm_params;
 
 /*
@@ -242,6 +249,32 @@ rnsm_status rnsm_select_pivots(int64_t n, const int64_t* rk_offsets, const int32
 rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const void* queries,
                         int64_t nq, const int32_t* seeds, int32_t n_seeds, int32_t ef, int32_t k,
                         rnsm_metric metric, int32_t* out_ids, float* out_dists, void* stream);
+
+/*
+ * Autotuner of the beam-search shape (the batched form's project-written
+ * tuner of wavefronts per block and LDS visited-table size; the beam width
+ * stays the caller's, since it sets recall). Times Algorithm 1 on the
+ * device for min(n_sample, n) of the graph's own rows as queries (ids
+ * i * n / n_sample), searched from g->entry with beam ef, under the
+ * default shape and every table size 2^8..2^12 sets x 1, 2, 4 wavefronts
+ * per block that fits 64 KB of LDS per block; each shape's time is the best
+ * of three launches after one untimed launch. g, base as in rnsm_search.
+ * Writes the fastest shape (pass it as rnsm_params.search_hash_bits /
+ * search_waves_per_block) and the default's, with their times; synchronises
+ * `stream` (NULL: the null stream). RNSM_EINVAL on bad arguments,
+ * RNSM_EUNSUPPORTED for cosine with a 16-bit copy.
+ */
+typedef struct {
+    int32_t hash_bits, waves_per_block;     /* fastest shape measured */
+    float ms;                               /* its time for the sample */
+    int32_t default_hash_bits, default_waves_per_block;
+    float default_ms;
+    int64_t n_queries;
+    int32_t n_tried;                        /* shapes timed, the default included */
+} rnsm_search_tuning;
+rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int32_t ef,
+                             rnsm_metric metric, int64_t n_sample, rnsm_search_tuning* out,
+                             void* stream);
 
 /*
  * Sub-index builder used to make inputs: row(v) = Prune(v, knn(v), alpha, R);

@@ -18,7 +18,8 @@ FLAG_ALL_PIVOTS = 1
 FLAG_CENTROID_COSTS = 2
 
 SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_select_pivots", "rnsm_search",
-           "rnsm_build_graph", "rnsm_convert", "rnsm_get_stats", "rnsm_last_error"]
+           "rnsm_tune_search", "rnsm_build_graph", "rnsm_convert", "rnsm_get_stats",
+           "rnsm_last_error"]
 
 _lib = None
 
@@ -43,7 +44,14 @@ class Params(C.Structure):
     _fields_ = [("R", C.c_int32), ("L", C.c_int32), ("alpha", C.c_float), ("metric", C.c_int),
                 ("k_reverse", C.c_int32), ("k_expand", C.c_int32), ("ef_naive", C.c_int32),
                 ("ef_slide", C.c_int32), ("mos_degree", C.c_int32), ("mos_diameter", C.c_int32),
-                ("flags", C.c_uint32), ("stream", C.c_void_p)]
+                ("flags", C.c_uint32), ("stream", C.c_void_p),
+                ("search_hash_bits", C.c_int32), ("search_waves_per_block", C.c_int32)]
+
+
+class SearchTuning(C.Structure):
+    _fields_ = [("hash_bits", C.c_int32), ("waves_per_block", C.c_int32), ("ms", C.c_float),
+                ("default_hash_bits", C.c_int32), ("default_waves_per_block", C.c_int32),
+                ("default_ms", C.c_float), ("n_queries", C.c_int64), ("n_tried", C.c_int32)]
 
 
 class Csr(C.Structure):
@@ -80,6 +88,8 @@ def lib():
         L.mos_plan.argtypes = [C.c_int32, P, P, C.c_int32, C.c_int32, C.c_int32, P, C.c_int32, P, P]
         L.rnsm_select_pivots.restype = C.c_int
         L.rnsm_select_pivots.argtypes = [C.c_int64, P, P, P, P, P, P, P]
+        L.rnsm_tune_search.restype = C.c_int
+        L.rnsm_tune_search.argtypes = [P, P, C.c_int32, C.c_int, C.c_int64, P, P]
         L.rnsm_search.restype = C.c_int
         L.rnsm_search.argtypes = [P, P, P, C.c_int64, P, C.c_int32, C.c_int32, C.c_int32, C.c_int,
                                   P, P, P]
@@ -129,11 +139,13 @@ def _vectors(X, search=None):
 
 def merge(subs, X, R, L, alpha, metric=L2SQ, search=None, k=0, kplus=0, ef_naive=0,
           ef_slide=0, mos_degree=0, mos_diameter=0, flags=0, dists=True, stream=None,
-          out=None):
+          out=None, search_shape=None):
     """Merge sub-indexes. subs: list of (offsets int64, nbrs int32, entry) device
     tensors with local ids, in global-id order over the rows of X (float32
     device [N, dim]). search: optional bf16/f16 copy of X that the searches
-    read. Returns (offsets, nbrs, dists, entry) device tensors (global ids)."""
+    read. search_shape: optional (hash_bits, waves_per_block) of the beam
+    searches, e.g. from tune_search. Returns (offsets, nbrs, dists, entry)
+    device tensors (global ids)."""
     import torch
     m = len(subs)
     gs = (Graph * m)()
@@ -153,6 +165,8 @@ def merge(subs, X, R, L, alpha, metric=L2SQ, search=None, k=0, kplus=0, ef_naive
     p = Params(R=R, L=L, alpha=float(alpha), metric=metric, k_reverse=k, k_expand=kplus,
                ef_naive=ef_naive, ef_slide=ef_slide, mos_degree=mos_degree,
                mos_diameter=mos_diameter, flags=flags, stream=_stream(stream))
+    if search_shape is not None:
+        p.search_hash_bits, p.search_waves_per_block = (int(x) for x in search_shape)
     _check(lib().rnsm_merge(m, gs, C.byref(v), C.byref(p), C.byref(csr)))
     ne = int(csr.n_edges)
     return o_off, o_nb[:ne], (None if o_d is None else o_d[:ne]), int(csr.entry)
@@ -240,6 +254,22 @@ def search(offsets, nbrs, entry, base, queries, ef, k, seeds=None, metric=L2SQ,
                              _ptr(seeds), ns, ef, k, metric, C.c_void_p(ids.data_ptr()),
                              C.c_void_p(ds.data_ptr()), _stream(stream)))
     return ids, ds
+
+
+def tune_search(offsets, nbrs, entry, base, ef, n_sample=65536, metric=L2SQ, base_search=None,
+                stream=None):
+    """Autotuner of the beam-search shape on one graph (its own rows as
+    queries): a dict with the fastest (hash_bits, waves_per_block), the
+    default's, and their times in ms."""
+    g = Graph(n=offsets.shape[0] - 1, offsets=offsets.data_ptr(), nbrs=nbrs.data_ptr(),
+              entry=int(entry))
+    v = _vectors(base, base_search)
+    t = SearchTuning()
+    _check(lib().rnsm_tune_search(C.byref(g), C.byref(v), ef, metric, int(n_sample), C.byref(t),
+                                  _stream(stream)))
+    return {"shape": (t.hash_bits, t.waves_per_block), "ms": t.ms,
+            "default_shape": (t.default_hash_bits, t.default_waves_per_block),
+            "default_ms": t.default_ms, "n_queries": t.n_queries, "n_tried": t.n_tried}
 
 
 def build_graph(X, knn, R, alpha=1.0, reverse=False, alpha_rev=1.2, metric=L2SQ, stream=None):

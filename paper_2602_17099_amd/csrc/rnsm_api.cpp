@@ -128,12 +128,18 @@ int ilog2_ceil(int64_t x) {
 // 6 wavefronts per SIMD. RNSM_EXACT_VISITED=1, or a
 // graph too large for 16-bit tags, selects an 8192-slot probing table that
 // holds every visited vertex (distance counts then equal the method's own).
-// RNSM_HASH_BITS / RNSM_WPB override the sizes.
+// RNSM_HASH_BITS / RNSM_WPB override the sizes (diagnostics); a caller's
+// hb_req / wpb_req (non-zero: the merge's search_hash_bits and
+// search_waves_per_block, say from rnsm_tune_search) override both. Blocks
+// are cut to at most 64 KB of LDS by using fewer wavefronts per block.
 struct SearchShape {
     int hbits, wpb, mode;
 };
 
-SearchShape search_shape(int ef, int maxdeg, int64_t n, int tt) {
+// visited-table sizes (log2 of the two-way sets) a caller may ask for
+constexpr int TUNE_HB_MIN = 8, TUNE_HB_MAX = 12;
+
+SearchShape search_shape(int ef, int maxdeg, int64_t n, int tt, int hb_req = 0, int wpb_req = 0) {
     SearchShape s;
     const int hmax = tt == 0 ? 11 : 10;
     int hb = ilog2_ceil((int64_t)ef * (maxdeg > 0 ? maxdeg : 16));
@@ -146,6 +152,7 @@ SearchShape search_shape(int ef, int maxdeg, int64_t n, int tt) {
     }
     const char* e = getenv("RNSM_HASH_BITS");
     if (e && atoi(e) >= 6 && atoi(e) <= 14) hb = atoi(e);
+    if (hb_req > 0 && s.mode == 0) hb = hb_req;
     if (s.mode == 0 && n >= ((int64_t)0xffff << hb)) {
         s.mode = 1;  // ids do not fit the 16-bit tags
         hb = 13;
@@ -153,6 +160,7 @@ SearchShape search_shape(int ef, int maxdeg, int64_t n, int tt) {
     int w = 1;
     const char* ew = getenv("RNSM_WPB");
     if (ew && atoi(ew) >= 1 && atoi(ew) <= 4) w = atoi(ew);
+    if (wpb_req > 0) w = wpb_req;
     while (w > 1 && search_lds_bytes(hb, w) > 64 * 1024) --w;
     s.hbits = hb;
     s.wpb = w;
@@ -399,6 +407,12 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     if (diam < 2) return fail(RNSM_EINVAL, "rnsm_merge: mos_diameter < 2");
     int rmos = p->mos_degree;
     if (rmos < 0) return fail(RNSM_EINVAL, "rnsm_merge: mos_degree < 0");
+    const int hb_req = p->search_hash_bits, wpb_req = p->search_waves_per_block;
+    if (hb_req != 0 && (hb_req < TUNE_HB_MIN || hb_req > TUNE_HB_MAX))
+        return fail(RNSM_EINVAL, "rnsm_merge: search_hash_bits = %d outside %d..%d", hb_req,
+                    TUNE_HB_MIN, TUNE_HB_MAX);
+    if (wpb_req < 0 || wpb_req > 4)
+        return fail(RNSM_EINVAL, "rnsm_merge: search_waves_per_block = %d outside 0..4", wpb_req);
     if (rmos == 0) rmos = std::max(2, (int)std::ceil(std::sqrt((double)m)));
     VecInfo vi;
     rnsm_status vs = vec_info(vecs, vi);
@@ -687,7 +701,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
             a.G = vi.G;
             a.lgG = ilog2i(vi.G);
             a.cpl = vi.cpl;
-            const SearchShape sh = search_shape(kp, R, ns, vi.tt);
+            const SearchShape sh = search_shape(kp, R, ns, vi.tt, hb_req, wpb_req);
             a.hbits = sh.hbits;
             a.hash_mode = sh.mode;
             a.out_mode = 1;
@@ -848,7 +862,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         aA.ef = efN;
         aA.out_k = efN;
         aA.counters = cnt + 1 * CNT_SLOTS * CNT_N;
-        const SearchShape shA = search_shape(efN, R, nt, vi.tt);
+        const SearchShape shA = search_shape(efN, R, nt, vi.tt, hb_req, wpb_req);
         aA.hbits = shA.hbits;
         aA.hash_mode = shA.mode;
         // wave B: followers, local sliding from their pivot's results
@@ -860,7 +874,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         aB.ef = efS;
         aB.out_k = efS;
         aB.counters = cnt + 2 * CNT_SLOTS * CNT_N;
-        const SearchShape shB = search_shape(efS, R, nt, vi.tt);
+        const SearchShape shB = search_shape(efS, R, nt, vi.tt, hb_req, wpb_req);
         aB.hbits = shB.hbits;
         aB.hash_mode = shB.mode;
         g_stats.exact_visited = shB.mode;
@@ -1324,6 +1338,139 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     HIPCHK(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (herr) return fail(RNSM_EINTERNAL, "rnsm_search: a search exceeded its iteration bound");
+    return RNSM_OK;
+}
+
+rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int32_t ef,
+                             rnsm_metric metric, int64_t n_sample, rnsm_search_tuning* out,
+                             void* stream) {
+    g_err.clear();
+    if (!g || !base || !out) return fail(RNSM_EINVAL, "rnsm_tune_search: NULL argument");
+    memset(out, 0, sizeof *out);
+    if (ef < 1 || ef > 128) return fail(RNSM_EINVAL, "rnsm_tune_search: ef outside 1..128");
+    if (metric < RNSM_L2SQ || metric > RNSM_COSINE)
+        return fail(RNSM_EINVAL, "rnsm_tune_search: metric");
+    if (n_sample < 1) return fail(RNSM_EINVAL, "rnsm_tune_search: n_sample < 1");
+    if (g->n < 1 || !g->offsets || !g->nbrs || base->n != g->n)
+        return fail(RNSM_EINVAL, "rnsm_tune_search: graph / base mismatch");
+    if (g->entry < 0 || g->entry >= g->n) return fail(RNSM_EINVAL, "rnsm_tune_search: entry");
+    VecInfo vi;
+    rnsm_status vs = vec_info(base, vi);
+    if (vs != RNSM_OK) return vs;
+    if (metric == RNSM_COSINE && base->search_dtype != RNSM_F32)
+        return fail(RNSM_EUNSUPPORTED, "rnsm_tune_search: cosine needs a float32 search copy here");
+    const int64_t nq = std::min<int64_t>(n_sample, g->n);
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    Workspace& ws = g_ws[dev];
+    u64* cnt;
+    int *errf, *qidx, *oid;
+    float* bn = nullptr;
+    WS(cnt, "search_counters", sizeof(u64) * CNT_SLOTS * CNT_N);
+    WS(errf, "search_err", sizeof(int));
+    WS(qidx, "tune_queries", sizeof(int) * nq);
+    WS(oid, "tune_ids", sizeof(int) * nq);
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * CNT_SLOTS * CNT_N, st));
+    HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
+    if (metric == RNSM_COSINE) {
+        WS(bn, "search_bnorm", sizeof(float) * g->n);
+        HIPCHK(launch_norms(base->f32, g->n, base->dim, bn, st));
+    }
+    // queries: the graph's own rows, spread evenly over its ids
+    std::vector<int> hq((size_t)nq);
+    for (int64_t i = 0; i < nq; ++i) hq[(size_t)i] = (int)(i * g->n / nq);
+    HIPCHK(hipMemcpyAsync(qidx, hq.data(), sizeof(int) * nq, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    SearchArgs a = {};
+    a.base = vi.search;
+    a.nch = vi.nch;
+    a.row_bytes = vi.row_bytes;
+    a.offs = g->offsets;
+    a.nbrs = g->nbrs;
+    a.n = g->n;
+    a.qvec = vi.search;
+    a.qidx = qidx;
+    a.nq = nq;
+    a.seed_mode = 0;
+    a.entry = g->entry;
+    a.metric = metric;
+    a.base_norm = bn;
+    a.q_norm = bn;
+    a.ef = ef;
+    a.G = vi.G;
+    a.lgG = ilog2i(vi.G);
+    a.cpl = vi.cpl;
+    a.out_mode = 0;
+    a.out_ids = oid;
+    a.out_stride = 1;
+    a.out_k = 1;
+    a.counters = cnt;
+    a.err = errf;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(RNSM_EDEVICE, "rnsm_tune_search: hipEventCreate failed");
+    }
+    // the best of three timed launches of one shape (after one untimed)
+    auto time_shape = [&](const SearchShape& sh, float* best) -> hipError_t {
+        SearchArgs b = a;
+        b.hbits = sh.hbits;
+        b.hash_mode = sh.mode;
+        hipError_t r = launch_search(vi.tt, b, sh.wpb, st);
+        *best = 0.0f;
+        for (int rep = 0; rep < 3 && r == hipSuccess; ++rep) {
+            float ms = 0.0f;
+            if ((r = hipEventRecord(e0, st)) != hipSuccess) break;
+            if ((r = launch_search(vi.tt, b, sh.wpb, st)) != hipSuccess) break;
+            if ((r = hipEventRecord(e1, st)) != hipSuccess) break;
+            if ((r = hipEventSynchronize(e1)) != hipSuccess) break;
+            if ((r = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (rep == 0 || ms < *best) *best = ms;
+        }
+        return r;
+    };
+    const SearchShape def = search_shape(ef, 32, g->n, vi.tt);
+    float def_ms = 0.0f;
+    hipError_t r = time_shape(def, &def_ms);
+    SearchShape best = def;
+    float best_ms = def_ms;
+    int tried = 1;
+    // every table size and block shape the fast table allows (an exact
+    // table, forced by the id range or for diagnostics, has one shape)
+    for (int hb = TUNE_HB_MIN; hb <= TUNE_HB_MAX && def.mode == 0 && r == hipSuccess; ++hb) {
+        for (int w : {1, 2, 4}) {
+            const SearchShape sh = search_shape(ef, 32, g->n, vi.tt, hb, w);
+            if (sh.mode != 0 || sh.wpb != w || (sh.hbits == def.hbits && sh.wpb == def.wpb))
+                continue;
+            float ms = 0.0f;
+            if ((r = time_shape(sh, &ms)) != hipSuccess) break;
+            ++tried;
+            if (ms < best_ms) {
+                best = sh;
+                best_ms = ms;
+            }
+        }
+    }
+    int herr = 0;
+    if (r == hipSuccess) r = hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (r == hipSuccess) r = hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != hipSuccess)
+        return fail(r == hipErrorOutOfMemory ? RNSM_ENOMEM : RNSM_EDEVICE, "rnsm_tune_search: %s",
+                    hipGetErrorString(r));
+    if (herr) return fail(RNSM_EINTERNAL, "rnsm_tune_search: a search exceeded its iteration bound");
+    out->hash_bits = best.hbits;
+    out->waves_per_block = best.wpb;
+    out->ms = best_ms;
+    out->default_hash_bits = def.hbits;
+    out->default_waves_per_block = def.wpb;
+    out->default_ms = def_ms;
+    out->n_queries = nq;
+    out->n_tried = tried;
     return RNSM_OK;
 }
 

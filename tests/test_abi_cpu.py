@@ -47,6 +47,12 @@ def test_merge_rejects_bad_arguments_on_host(pkg):
         setattr(q, field, val)
         assert L.rnsm_merge(2, g, C.byref(v), C.byref(q), C.byref(out)) == 1, field
         assert msg in pkg.last_error()
+    for field, val in [("search_hash_bits", 7), ("search_hash_bits", 13),
+                       ("search_waves_per_block", 5), ("search_waves_per_block", -1)]:
+        q = pkg.Params(R=16, L=32, alpha=1.2)
+        setattr(q, field, val)
+        assert L.rnsm_merge(2, g, C.byref(v), C.byref(q), C.byref(out)) == 1, field
+        assert field in pkg.last_error()
     # vectors
     assert L.rnsm_merge(2, g, C.byref(v), C.byref(p), C.byref(out)) == 1
     assert "f32 is NULL" in pkg.last_error()
@@ -189,3 +195,26 @@ def test_select_pivots_rejects(pkg):
     assert L.rnsm_select_pivots(2, z.ctypes.data_as(C.c_void_p), None, None, None, None, None,
                                 None) == 1
     assert "NULL" in pkg.last_error()
+
+
+def test_tune_search_rejects_on_host(pkg):
+    # argument errors come back before any device work
+    L = pkg.lib()
+    t = pkg.SearchTuning()
+    g = pkg.Graph(n=10, offsets=8, nbrs=8, entry=0)
+    v = pkg.Vectors(n=10, dim=32, f32=8)
+    ok = (C.byref(g), C.byref(v), 32, 0, 100, C.byref(t), None)
+    for i, bad, msg in [(0, None, "NULL"), (2, 0, "ef"), (2, 129, "ef"), (3, 5, "metric"),
+                        (4, 0, "n_sample"), (5, None, "NULL")]:
+        args = list(ok)
+        args[i] = bad
+        assert L.rnsm_tune_search(*args) == 1, (i, bad)
+        assert msg in pkg.last_error()
+    g2 = pkg.Graph(n=11, offsets=8, nbrs=8, entry=0)
+    assert L.rnsm_tune_search(C.byref(g2), *ok[1:]) == 1
+    assert "mismatch" in pkg.last_error()
+    g3 = pkg.Graph(n=10, offsets=8, nbrs=8, entry=10)
+    assert L.rnsm_tune_search(C.byref(g3), *ok[1:]) == 1
+    assert "entry" in pkg.last_error()
+    v2 = pkg.Vectors(n=10, dim=32, f32=8, search_dtype=1, search=8)
+    assert L.rnsm_tune_search(C.byref(g), C.byref(v2), 32, 2, 100, C.byref(t), None) == 4

@@ -388,6 +388,31 @@ def test_merge_prune_shapes_bit_exact(dev, orc, pkg, monkeypatch, dim, R, L, mod
     _assert_same_merge(got, ref)
 
 
+def test_tune_search_then_tuned_merge_bit_exact(dev, orc, pkg, medium, medium_ref):
+    # the autotuner times every visited-table size and block shape on the
+    # target graph; a merge under the shape it picks, or under the smallest
+    # and largest tables, reaches the oracle's graph all the same
+    X, subs = medium
+    Xd = _t(X, dev)
+    o, nb, e = _dsubs(subs, dev)[1]
+    n0 = subs[0][0].shape[0] - 1
+    t = pkg.tune_search(o, nb, e, Xd[n0:], 64, n_sample=8000)
+    hb, w = t["shape"]
+    assert 8 <= hb <= 12 and w in (1, 2, 4)
+    assert t["ms"] > 0 and t["default_ms"] > 0 and t["ms"] <= t["default_ms"]
+    assert t["n_queries"] == 8000 and 2 <= t["n_tried"] <= 16
+    assert t["default_shape"] == (11, 1)  # float32 rows, L = 64, R = 32
+    for shape in [t["shape"], (8, 4), (12, 1), (12, 2)]:
+        got = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2, search_shape=shape)
+        _assert_same_merge(got, medium_ref)
+    # a 16-bit search copy: its own default (a 4 KB table), same graph
+    t16 = pkg.tune_search(o, nb, e, Xd[n0:], 64, n_sample=3000, base_search=Xd[n0:].bfloat16())
+    assert t16["default_shape"] == (10, 1) and t16["n_queries"] == 3000
+    got = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2, search=Xd.bfloat16(),
+                    search_shape=t16["shape"])
+    _assert_same_merge(got, medium_ref)
+
+
 @pytest.mark.parametrize("dtype", ["bfloat16", "float16"])
 def test_merge_medium_16bit_search_bit_exact(dev, orc, pkg, medium, medium_ref, dtype):
     # 0..255 integers are exact in bfloat16 and float16: the reduced-precision
