@@ -200,6 +200,94 @@ def autotune(pkg, subs, Xd, wl, args, ms_default, off, nb, bf16):
     return out
 
 
+def multiway(pkg, scale, steps, warmup):
+    """The many-sub-index inner-product workload at `scale` of its 10,000,000
+    vectors: ten log-uniform sizes on [50,000, 2,000,000] x scale summing to
+    10,000,000 x scale, an L2-normalised 256-component mixture in dim 96 cut
+    into slabs along a seeded direction, sub-indexes from exact 64-NN pruned
+    to R = 32, then MOS-ordered pairwise merges (degree bound 4, centroid
+    costs) with R = 32, L = 64, alpha = 1.2. Reports merged vertices/s (source
+    vertices over all operations per second), recall@10 of the merged graph,
+    its invariants, and the search-shape autotuner against the default."""
+    import torch
+    from paper_2602_17099_amd import inputs
+    from paper_2602_17099_amd.prepare import knn_float_exact
+    IP = 1
+    total = int(round(10_000_000 * scale))
+    sizes = inputs.uneven_sizes(10, int(50_000 * scale), int(2_000_000 * scale), total,
+                                seed=inputs.SEED_BASE + 3)
+    t = time.perf_counter()
+    X = inputs.mixture_unit(total, 96, comps=256, seed=inputs.SEED_BASE + 3)
+    X = np.ascontiguousarray(X[inputs.slab_order(X, inputs.SEED_BASE + 33)])
+    Q = inputs.mixture_unit(10_000, 96, comps=256, seed=inputs.SEED_BASE + 3, stream=1)
+    log(f"multiway inputs {X.shape} sizes {sizes} in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    del X
+    t = time.perf_counter()
+    subs, b = [], 0
+    for n in sizes:
+        Xi = Xd[b:b + n]
+        knn = knn_float_exact(Xi, None, 64, metric=IP, exclude_self=True)
+        subs.append(pkg.build_graph(Xi, knn, 32, alpha=1.2, reverse=True, alpha_rev=1.2,
+                                    metric=IP))
+        del knn
+        b += n
+        torch.cuda.synchronize()
+        log(f"multiway sub-index of {n:,} built at {time.perf_counter() - t:.1f}s")
+    torch.cuda.synchronize()
+    log(f"multiway sub-indexes built in {time.perf_counter() - t:.1f}s")
+    N = Xd.shape[0]
+    kw = dict(R=32, L=64, alpha=1.2, metric=IP, mos_degree=4, flags=pkg.FLAG_CENTROID_COSTS,
+              out=(torch.empty(N + 1, dtype=torch.int64, device=dev),
+                   torch.empty(N * 32, dtype=torch.int32, device=dev),
+                   torch.empty(N * 32, dtype=torch.float32, device=dev)))
+
+    def run(shape=None):
+        for _ in range(warmup):
+            pkg.merge(subs, Xd, search_shape=shape, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = pkg.merge(subs, Xd, search_shape=shape, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, pkg.stats(), res
+
+    dt, st, (off, nb, ds, entry) = run()
+    off_c, nb_c = off.clone(), nb.clone()
+    # invariants: degree <= R, no self-loops, no repeated neighbour
+    deg = off[1:] - off[:-1]
+    row = torch.repeat_interleave(torch.arange(N, device=dev), deg)
+    keys = row * N + nb.to(torch.int64)
+    inv = {"max_degree": int(deg.max()), "self_loops": int((nb.to(torch.int64) == row).sum()),
+           "repeated": int(keys.numel() - torch.unique(keys).numel())}
+    del row, keys
+    gt = knn_float_exact(Xd, Qd, 10, metric=IP, block=1024)
+    ids, _ = pkg.search(off, nb, entry, Xd, Qd, 64, 10, metric=IP)
+    rec = (ids.to(torch.int64)[:, :, None] == gt.to(torch.int64)[:, None, :]).any(2).sum().item()
+    rec /= 10 * Qd.shape[0]
+    big = max(range(len(sizes)), key=lambda i: sizes[i])
+    b0 = sum(sizes[:big])
+    o, g, e = subs[big]
+    tune = pkg.tune_search(o, g, e, Xd[b0:b0 + sizes[big]], 64, n_sample=65536, metric=IP)
+    dtt, _, rt = run(tuple(tune["shape"]))
+    same = bool(torch.equal(rt[0], off_c) and torch.equal(rt[1], nb_c))
+    return {"workload": f"{len(sizes)} uneven slab sub-indexes, {N:,} L2-normalised vectors, "
+                        f"dim 96, inner product, R=32, L=64, alpha=1.2, MOS degree 4",
+            "scale_of_10M": scale, "sizes": sizes, "operations": st["n_ops"],
+            "source_vertices": st["n_source_vertices"], "ms_per_merge": 1000.0 * dt,
+            "value": st["n_source_vertices"] / dt, "unit": "merged vertices/s",
+            "steps": steps, "warmup": warmup, "recall_at_10": rec, "invariants": inv,
+            "phase_ms": {"expansion_search": st["ms_search"][0], "invert": st["ms_invert"],
+                         "host_plan": st["ms_plan"], "naive_search": st["ms_search"][1],
+                         "sliding_search": st["ms_search"][2], "prune_and_reverse": st["ms_prune"],
+                         "compact": st["ms_compact"], "total": st["ms_total"]},
+            "autotune": {"shape": list(tune["shape"]), "default_shape": list(tune["default_shape"]),
+                         "sample_ms": tune["ms"], "default_sample_ms": tune["default_ms"],
+                         "ms_per_merge": 1000.0 * dtt, "same_graph": same}}
+
+
 def exact_ndc(pkg, subs, Xd, wl, search=None):
     """Distance counts of one merge with the probing visited table, which
     evaluates every visited vertex exactly once (the method's own count)."""
@@ -285,6 +373,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="also tune the search shape on the target sub-index and time merges "
                          "under the shape it picks (float32 and bfloat16 copies)")
+    ap.add_argument("--multiway", type=float, default=0.0, metavar="SCALE",
+                    help="only run the ten-sub-index inner-product workload at SCALE of its "
+                         "10,000,000 vectors and print its JSON line")
     ap.add_argument("--calib-only", action="store_true",
                     help="only copy 1 GiB device to device (counter calibration) and exit")
     args = ap.parse_args()
@@ -302,6 +393,10 @@ def main():
         return
     import paper_2602_17099_amd as pkg
     pkg.lib()
+    if args.multiway > 0:
+        mw = multiway(pkg, args.multiway, max(1, min(args.steps, 3)), args.warmup)
+        print(json.dumps({"multiway": mw}), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
 

@@ -48,3 +48,38 @@ def knn_l2_exact(base: torch.Tensor, queries: torch.Tensor | None, K: int,
     finally:
         torch.backends.cuda.matmul.allow_tf32 = prev
     return out
+
+
+@torch.no_grad()
+def knn_float_exact(base: torch.Tensor, queries: torch.Tensor | None, K: int, metric: int = 0,
+                    exclude_self: bool = False, block: int = 4096) -> torch.Tensor:
+    """Top-K ids (int32, [nq, K]) of every query row by float32 distance:
+    squared L2 (metric 0) or 1 - <q, x> (metric 1), brute force. For
+    real-valued data, where equal distances practically never occur; the
+    order among exactly equal distances is topk's, not by id."""
+    assert base.dtype == torch.float32 and base.is_cuda and metric in (0, 1)
+    q_all = base if queries is None else queries
+    n = base.shape[0]
+    sq = (base * base).sum(1) if metric == 0 else None
+    out = torch.empty((q_all.shape[0], K), dtype=torch.int32, device=base.device)
+    kk = K + 1 if exclude_self else K
+    prev = torch.backends.cuda.matmul.allow_tf32
+    torch.backends.cuda.matmul.allow_tf32 = False
+    try:
+        for s in range(0, q_all.shape[0], block):
+            q = q_all[s:s + block]
+            if metric == 0:
+                d = torch.addmm((q * q).sum(1)[:, None] + sq[None, :], q, base.t(), beta=1.0,
+                                alpha=-2.0)
+            else:
+                d = torch.addmm(torch.ones((), device=base.device), q, base.t(), beta=1.0,
+                                alpha=-1.0)
+            if exclude_self:
+                r = torch.arange(s, s + q.shape[0], device=base.device)
+                d[torch.arange(q.shape[0], device=base.device), r] = float("inf")
+            top = torch.topk(d, kk, dim=1, largest=False, sorted=True).indices
+            del d
+            out[s:s + q.shape[0]] = top[:, :K].to(torch.int32)
+    finally:
+        torch.backends.cuda.matmul.allow_tf32 = prev
+    return out
