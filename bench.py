@@ -35,13 +35,13 @@ PEAK_HBM_GBS = 8000.0
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
-    "sources_sha256": "28343a6889b8eda2df4e95368fbd9069156738bcab3ac4c0733ac8bcabaf4184",
+    "sources_sha256": "bad3af8b4de8a677e0fa4f9a4d1a52dbe0c872326958ae09153a2e8e7e32c4b2",
     "fetch_kib": [
-        28835337.125, 30323.375, 2582459.938, 108508.0, 5894143.875, 529428.688, 14815167.438,
-        1996925.062, 19778152.688, 18819444.938, 18382456.812, 11649019.625
+        28927148.625, 30086.375, 2508022.312, 107937.25, 5778242.125, 531066.375, 14852761.375,
+        1991948.75, 19702611.188, 18858656.25, 18569737.562, 11661523.562
     ],
     "write_kib": [
-        174328.594, 48.125, 19571.875, 193.125, 38870.0, 970.625, 77168.125, 3530.625, 74595.625,
+        174345.312, 48.125, 19571.875, 193.125, 38870.0, 970.625, 77168.125, 3530.625, 74595.625,
         32081.875, 46043.125, 19426.875
     ],
 }

@@ -60,6 +60,11 @@ typedef enum { RNSM_F32 = 0, RNSM_BF16 = 1, RNSM_F16 = 2, RNSM_U8 = 3 } rnsm_dty
 /* flags of rnsm_params */
 #define RNSM_FLAG_ALL_PIVOTS 1u     /* every source vertex runs a naive search (cross-query merge) */
 #define RNSM_FLAG_CENTROID_COSTS 2u /* MOS costs = centroid distances (default: unit costs) */
+#define RNSM_FLAG_AUTOTUNE 4u       /* pick the search shape with rnsm_tune_search's measurement on
+                                       the largest sub-index (65,536 of its rows, beam ef_naive),
+                                       once per process for each device, storage type, row size,
+                                       beam, R, metric and power-of-two size class; ignored when
+                                       params fix search_hash_bits / search_waves_per_block */
 
 /*
  * One input sub-index: a flat proximity graph (Section 2.2) over n vectors.
@@ -114,8 +119,10 @@ typedef struct {
  *          the merge: log2 of the LDS visited table's two-way sets (8..12)
  *          and wavefronts per block (1..4, fewer when a block would need
  *          over 64 KB of LDS); 0 = the library's default for the beam width,
- *          degree and storage type. rnsm_tune_search measures them. Results
- *          do not depend on the shape, only the speed does.
+ *          degree and storage type (or, with RNSM_FLAG_AUTOTUNE, the shape
+ *          the merge measures itself; its first call of a kind includes the
+ *          tuning time). rnsm_tune_search measures them. Results do not
+ *          depend on the shape, only the speed does.
  */
 typedef struct {
     int32_t R, L;
@@ -180,6 +187,7 @@ typedef struct {
                                search of each operation, summed over operations: naive and
                                sliding launches overlap on two streams, so this is below
                                ms_search[1] + ms_search[2] */
+    int32_t search_hash_bits, search_waves_per_block;  /* shape of the operations' searches */
 } rnsm_stats;
 
 /*

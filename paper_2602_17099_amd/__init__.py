@@ -16,6 +16,7 @@ L2SQ, IP, COSINE = 0, 1, 2
 F32, BF16, F16 = 0, 1, 2
 FLAG_ALL_PIVOTS = 1
 FLAG_CENTROID_COSTS = 2
+FLAG_AUTOTUNE = 4
 
 SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_select_pivots", "rnsm_search",
            "rnsm_tune_search", "rnsm_build_graph", "rnsm_convert", "rnsm_get_stats",
@@ -68,7 +69,8 @@ class Stats(C.Structure):
                 ("adjacency", C.c_int64 * 3), ("launches", C.c_int64 * 3), ("bytes", C.c_double * 3),
                 ("hash_evictions", C.c_int64), ("row_bytes", C.c_int32),
                 ("exact_visited", C.c_int32), ("prune_path", C.c_int32),
-                ("ms_search_span", C.c_double)]
+                ("ms_search_span", C.c_double), ("search_hash_bits", C.c_int32),
+                ("search_waves_per_block", C.c_int32)]
 
 
 def lib():

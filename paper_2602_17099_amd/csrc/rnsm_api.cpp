@@ -379,6 +379,16 @@ rnsm_status rnsm_select_pivots(int64_t n, const int64_t* rk_offsets, const int32
     return RNSM_OK;
 }
 
+static rnsm_status tune_shape_locked(const rnsm_graph* g, const rnsm_vectors* base,
+                                     const VecInfo& vi, int32_t ef, rnsm_metric metric,
+                                     int64_t n_sample, int maxdeg, rnsm_search_tuning* out,
+                                     hipStream_t st);
+
+// shapes picked by the merge's own tuning (RNSM_FLAG_AUTOTUNE), per device,
+// storage type, row bytes, beam, degree bound, metric and log2 of the
+// largest sub-index; guarded by g_lock
+static std::map<std::array<int64_t, 7>, std::pair<int, int>> g_tuned;
+
 rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
                        const rnsm_params* p, rnsm_csr* out) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -407,7 +417,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     if (diam < 2) return fail(RNSM_EINVAL, "rnsm_merge: mos_diameter < 2");
     int rmos = p->mos_degree;
     if (rmos < 0) return fail(RNSM_EINVAL, "rnsm_merge: mos_degree < 0");
-    const int hb_req = p->search_hash_bits, wpb_req = p->search_waves_per_block;
+    int hb_req = p->search_hash_bits, wpb_req = p->search_waves_per_block;
     if (hb_req != 0 && (hb_req < TUNE_HB_MIN || hb_req > TUNE_HB_MAX))
         return fail(RNSM_EINVAL, "rnsm_merge: search_hash_bits = %d outside %d..%d", hb_req,
                     TUNE_HB_MIN, TUNE_HB_MAX);
@@ -469,6 +479,33 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         if (f & 8) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: self-loop", i);
         if (f & 16) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: duplicate neighbour", i);
         if (f & 2) return fail(RNSM_EINVAL, "rnsm_merge: sub-index %d: degree above R = %d", i, R);
+    }
+    // the merge's own search-shape tuning: once per kind of input, on the
+    // largest sub-index (its own rows as queries, beam ef_naive), unless the
+    // caller fixed the shape
+    if ((p->flags & RNSM_FLAG_AUTOTUNE) && hb_req == 0 && wpb_req == 0) {
+        int big = 0;
+        for (int i = 1; i < m; ++i)
+            if (sizes[i] > sizes[big]) big = i;
+        const std::array<int64_t, 7> key = {dev, vi.tt, vi.row_bytes, efN, R, (int64_t)p->metric,
+                                            (int64_t)ilog2_ceil(sizes[big])};
+        auto it = g_tuned.find(key);
+        if (it == g_tuned.end()) {
+            rnsm_vectors vb = *vecs;
+            vb.n = sizes[big];
+            vb.f32 = vecs->f32 + bases[big] * vecs->dim;
+            if (vecs->search_dtype != RNSM_F32)
+                vb.search = (const char*)vecs->search + bases[big] * vi.row_bytes;
+            VecInfo vib;  // the same layout, rows of sub-index `big`
+            rnsm_status ts = vec_info(&vb, vib);
+            if (ts != RNSM_OK) return ts;
+            rnsm_search_tuning tr;
+            ts = tune_shape_locked(&graphs[big], &vb, vib, efN, p->metric, 65536, R, &tr, st);
+            if (ts != RNSM_OK) return ts;
+            it = g_tuned.emplace(key, std::make_pair((int)tr.hash_bits, (int)tr.waves_per_block)).first;
+        }
+        hb_req = it->second.first;
+        wpb_req = it->second.second;
     }
 
     // ----------------------------------------------------------------- plan
@@ -878,6 +915,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         aB.hbits = shB.hbits;
         aB.hash_mode = shB.mode;
         g_stats.exact_visited = shB.mode;
+        g_stats.search_hash_bits = shB.hbits;
+        g_stats.search_waves_per_block = shB.wpb;
 
         // chunk c: lists and naive search on the side stream, then the
         // sliding search on st after the naive one (event wait); the naive
@@ -1341,27 +1380,12 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     return RNSM_OK;
 }
 
-rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int32_t ef,
-                             rnsm_metric metric, int64_t n_sample, rnsm_search_tuning* out,
-                             void* stream) {
-    g_err.clear();
-    if (!g || !base || !out) return fail(RNSM_EINVAL, "rnsm_tune_search: NULL argument");
-    memset(out, 0, sizeof *out);
-    if (ef < 1 || ef > 128) return fail(RNSM_EINVAL, "rnsm_tune_search: ef outside 1..128");
-    if (metric < RNSM_L2SQ || metric > RNSM_COSINE)
-        return fail(RNSM_EINVAL, "rnsm_tune_search: metric");
-    if (n_sample < 1) return fail(RNSM_EINVAL, "rnsm_tune_search: n_sample < 1");
-    if (g->n < 1 || !g->offsets || !g->nbrs || base->n != g->n)
-        return fail(RNSM_EINVAL, "rnsm_tune_search: graph / base mismatch");
-    if (g->entry < 0 || g->entry >= g->n) return fail(RNSM_EINVAL, "rnsm_tune_search: entry");
-    VecInfo vi;
-    rnsm_status vs = vec_info(base, vi);
-    if (vs != RNSM_OK) return vs;
-    if (metric == RNSM_COSINE && base->search_dtype != RNSM_F32)
-        return fail(RNSM_EUNSUPPORTED, "rnsm_tune_search: cosine needs a float32 search copy here");
+// The search-shape autotuner's measurement, with g_lock held: g and base
+// already checked, vi their layout. Default shape for rows of degree maxdeg.
+static rnsm_status tune_shape_locked(const rnsm_graph* g, const rnsm_vectors* base, const VecInfo& vi,
+                              int32_t ef, rnsm_metric metric, int64_t n_sample, int maxdeg,
+                              rnsm_search_tuning* out, hipStream_t st) {
     const int64_t nq = std::min<int64_t>(n_sample, g->n);
-    std::lock_guard<std::mutex> lk(g_lock);
-    hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     Workspace& ws = g_ws[dev];
@@ -1412,7 +1436,7 @@ rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int3
     HIPCHK(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
-        return fail(RNSM_EDEVICE, "rnsm_tune_search: hipEventCreate failed");
+        return fail(RNSM_EDEVICE, "search tuning: hipEventCreate failed");
     }
     // the best of three timed launches of one shape (after one untimed)
     auto time_shape = [&](const SearchShape& sh, float* best) -> hipError_t {
@@ -1432,7 +1456,7 @@ rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int3
         }
         return r;
     };
-    const SearchShape def = search_shape(ef, 32, g->n, vi.tt);
+    const SearchShape def = search_shape(ef, maxdeg, g->n, vi.tt);
     float def_ms = 0.0f;
     hipError_t r = time_shape(def, &def_ms);
     SearchShape best = def;
@@ -1442,7 +1466,7 @@ rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int3
     // table, forced by the id range or for diagnostics, has one shape)
     for (int hb = TUNE_HB_MIN; hb <= TUNE_HB_MAX && def.mode == 0 && r == hipSuccess; ++hb) {
         for (int w : {1, 2, 4}) {
-            const SearchShape sh = search_shape(ef, 32, g->n, vi.tt, hb, w);
+            const SearchShape sh = search_shape(ef, maxdeg, g->n, vi.tt, hb, w);
             if (sh.mode != 0 || sh.wpb != w || (sh.hbits == def.hbits && sh.wpb == def.wpb))
                 continue;
             float ms = 0.0f;
@@ -1460,9 +1484,9 @@ rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int3
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (r != hipSuccess)
-        return fail(r == hipErrorOutOfMemory ? RNSM_ENOMEM : RNSM_EDEVICE, "rnsm_tune_search: %s",
+        return fail(r == hipErrorOutOfMemory ? RNSM_ENOMEM : RNSM_EDEVICE, "search tuning: %s",
                     hipGetErrorString(r));
-    if (herr) return fail(RNSM_EINTERNAL, "rnsm_tune_search: a search exceeded its iteration bound");
+    if (herr) return fail(RNSM_EINTERNAL, "search tuning: a search exceeded its iteration bound");
     out->hash_bits = best.hbits;
     out->waves_per_block = best.wpb;
     out->ms = best_ms;
@@ -1472,6 +1496,29 @@ rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int3
     out->n_queries = nq;
     out->n_tried = tried;
     return RNSM_OK;
+}
+
+
+rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int32_t ef,
+                             rnsm_metric metric, int64_t n_sample, rnsm_search_tuning* out,
+                             void* stream) {
+    g_err.clear();
+    if (!g || !base || !out) return fail(RNSM_EINVAL, "rnsm_tune_search: NULL argument");
+    memset(out, 0, sizeof *out);
+    if (ef < 1 || ef > 128) return fail(RNSM_EINVAL, "rnsm_tune_search: ef outside 1..128");
+    if (metric < RNSM_L2SQ || metric > RNSM_COSINE)
+        return fail(RNSM_EINVAL, "rnsm_tune_search: metric");
+    if (n_sample < 1) return fail(RNSM_EINVAL, "rnsm_tune_search: n_sample < 1");
+    if (g->n < 1 || !g->offsets || !g->nbrs || base->n != g->n)
+        return fail(RNSM_EINVAL, "rnsm_tune_search: graph / base mismatch");
+    if (g->entry < 0 || g->entry >= g->n) return fail(RNSM_EINVAL, "rnsm_tune_search: entry");
+    VecInfo vi;
+    rnsm_status vs = vec_info(base, vi);
+    if (vs != RNSM_OK) return vs;
+    if (metric == RNSM_COSINE && base->search_dtype != RNSM_F32)
+        return fail(RNSM_EUNSUPPORTED, "rnsm_tune_search: cosine needs a float32 search copy here");
+    std::lock_guard<std::mutex> lk(g_lock);
+    return tune_shape_locked(g, base, vi, ef, metric, n_sample, 32, out, (hipStream_t)stream);
 }
 
 rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric metric,

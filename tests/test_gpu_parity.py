@@ -413,6 +413,32 @@ def test_tune_search_then_tuned_merge_bit_exact(dev, orc, pkg, medium, medium_re
     _assert_same_merge(got, medium_ref)
 
 
+def test_merge_autotune_flag_bit_exact(dev, orc, pkg, medium, medium_ref):
+    # the merge tunes its own search shape (on the larger sub-index) and keeps
+    # it for later merges of the same kind; the graph is the oracle's
+    X, subs = medium
+    Xd = _t(X, dev)
+    shapes = set()
+    for _ in range(2):
+        got = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2, flags=pkg.FLAG_AUTOTUNE)
+        _assert_same_merge(got, medium_ref)
+        st = pkg.stats()
+        shapes.add((st["search_hash_bits"], st["search_waves_per_block"]))
+    assert len(shapes) == 1
+    hb, w = shapes.pop()
+    assert 8 <= hb <= 12 and w in (1, 2, 4)
+    # a shape fixed by the caller wins over the flag
+    got = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2, flags=pkg.FLAG_AUTOTUNE,
+                    search_shape=(8, 2))
+    _assert_same_merge(got, medium_ref)
+    st = pkg.stats()
+    assert (st["search_hash_bits"], st["search_waves_per_block"]) == (8, 2)
+    # without either, the default shape (float32 rows, L = 64, R = 32)
+    pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2)
+    st = pkg.stats()
+    assert (st["search_hash_bits"], st["search_waves_per_block"]) == (11, 1)
+
+
 @pytest.mark.parametrize("dtype", ["bfloat16", "float16"])
 def test_merge_medium_16bit_search_bit_exact(dev, orc, pkg, medium, medium_ref, dtype):
     # 0..255 integers are exact in bfloat16 and float16: the reduced-precision
