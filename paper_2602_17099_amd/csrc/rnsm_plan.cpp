@@ -206,10 +206,17 @@ void select_pivots(GainLevels& L, const int64_t* rk_off, const int32_t* rk_ids, 
     // take x at stored gain g: 0 dropped (covered), 1 moved down, 2 pivot
     auto visit = [&](int32_t x, int64_t g) {
         const int64_t o0 = rk_off[x], o1 = rk_off[x + 1];
+        // one pass counts the uncovered members and, for lists of up to BUF,
+        // keeps them for the pivot case (the lists hold no repeated id)
+        constexpr int64_t BUF = 64;
+        int32_t unc[BUF];
         int64_t cur = 0;
+        const bool fits = o1 - o0 <= BUF;
         for (int64_t j = o0; j < o1; ++j) {
             const int32_t y = rk_ids[j];
-            cur += (int64_t)(~cov[y >> 6] >> (y & 63) & 1ull);
+            const int64_t u = (int64_t)(~cov[y >> 6] >> (y & 63) & 1ull);
+            if (fits) unc[cur] = y;
+            cur += u;
         }
         if (cur < g) {
             mark(cur, x);
@@ -217,13 +224,22 @@ void select_pivots(GainLevels& L, const int64_t* rk_off, const int32_t* rk_ids, 
         }
         pivots[np++] = x;
         cov[x >> 6] |= 1ull << (x & 63);
-        for (int64_t j = o0; j < o1; ++j) {
-            const int32_t y = rk_ids[j];
-            const uint64_t bit = 1ull << (y & 63);
-            if (!(cov[y >> 6] & bit)) {
-                cov[y >> 6] |= bit;
+        if (fits) {
+            for (int64_t t = 0; t < cur; ++t) {
+                const int32_t y = unc[t];
+                cov[y >> 6] |= 1ull << (y & 63);
                 followers[nf] = y;
                 follower_pivot[nf++] = x;
+            }
+        } else {
+            for (int64_t j = o0; j < o1; ++j) {
+                const int32_t y = rk_ids[j];
+                const uint64_t bit = 1ull << (y & 63);
+                if (!(cov[y >> 6] & bit)) {
+                    cov[y >> 6] |= bit;
+                    followers[nf] = y;
+                    follower_pivot[nf++] = x;
+                }
             }
         }
         if (np + nf - sent >= chunk) {
