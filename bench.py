@@ -288,6 +288,75 @@ def multiway(pkg, scale, steps, warmup):
                          "ms_per_merge": 1000.0 * dtt, "same_graph": same}}
 
 
+def precision768(pkg, scale, steps, warmup):
+    """The precision workload at `scale` of its 4,000,000 vectors: dim 768,
+    per-dimension scale 1/sqrt(i), 1,024 components, L2-normalised, cosine;
+    a random split into four equal sub-indexes (exact 96-NN pruned to
+    R = 48); merged with R = 48, L = 96, alpha = 1.2 (MOS degree 2) from the
+    float32 rows and from their bfloat16 copy (inexact here), each timed and
+    scored by recall@10 against exact cosine neighbours."""
+    import torch
+    from paper_2602_17099_amd import inputs
+    from paper_2602_17099_amd.prepare import knn_float_exact
+    COS = 2
+    n = int(round(1_000_000 * scale))
+    t = time.perf_counter()
+    X = inputs.mixture_unit(4 * n, 768, comps=1024, decay=True, seed=inputs.SEED_BASE + 4)
+    X = X[inputs.rng(inputs.SEED_BASE + 44).permutation(len(X))]
+    Q = inputs.mixture_unit(10_000, 768, comps=1024, decay=True, seed=inputs.SEED_BASE + 4,
+                            stream=1)
+    log(f"precision inputs {X.shape} in {time.perf_counter() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    del X
+    t = time.perf_counter()
+    subs = []
+    for i in range(4):
+        Xi = Xd[i * n:(i + 1) * n]
+        # unit rows: the inner-product order is the cosine order
+        knn = knn_float_exact(Xi, None, 96, metric=1, exclude_self=True)
+        subs.append(pkg.build_graph(Xi, knn, 48, alpha=1.2, reverse=True, alpha_rev=1.2,
+                                    metric=COS))
+        del knn
+        torch.cuda.synchronize()
+        log(f"precision sub-index {i} built at {time.perf_counter() - t:.1f}s")
+    N = Xd.shape[0]
+    gt = knn_float_exact(Xd, Qd, 10, metric=1, block=1024)
+    out = {"workload": f"4 random-split sub-indexes, {N:,} L2-normalised vectors, dim 768 "
+                       f"(scale 1/sqrt(i)), cosine, R=48, L=96, alpha=1.2, MOS degree 2",
+           "scale_of_4M": scale, "steps": steps, "warmup": warmup}
+    for name, search in [("fp32", None), ("bf16", pkg.convert(Xd, torch.bfloat16))]:
+        kw = dict(R=48, L=96, alpha=1.2, metric=COS, mos_degree=2, search=search,
+                  out=(torch.empty(N + 1, dtype=torch.int64, device=dev),
+                       torch.empty(N * 48, dtype=torch.int32, device=dev),
+                       torch.empty(N * 48, dtype=torch.float32, device=dev)))
+        for _ in range(warmup):
+            pkg.merge(subs, Xd, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            off, nb, _, entry = pkg.merge(subs, Xd, **kw)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = pkg.stats()
+        ids, _ = pkg.search(off, nb, entry, Xd, Qd, 96, 10, metric=COS)
+        rec = (ids.to(torch.int64)[:, :, None] == gt.to(torch.int64)[:, None, :]).any(2)
+        out[name] = {"ms_per_merge": 1000.0 * dt, "value": st["n_source_vertices"] / dt,
+                     "unit": "merged vertices/s", "operations": st["n_ops"],
+                     "source_vertices": st["n_source_vertices"],
+                     "recall_at_10": rec.sum().item() / (10 * Qd.shape[0]),
+                     "prune_path": st["prune_path"],
+                     "phase_ms": {"expansion_search": st["ms_search"][0],
+                                  "naive_search": st["ms_search"][1],
+                                  "sliding_search": st["ms_search"][2],
+                                  "prune_and_reverse": st["ms_prune"], "total": st["ms_total"]}}
+        log(f"precision {name}: {out[name]}")
+        del off, nb
+    out["bf16_speedup"] = out["bf16"]["value"] / out["fp32"]["value"]
+    return out
+
+
 def exact_ndc(pkg, subs, Xd, wl, search=None):
     """Distance counts of one merge with the probing visited table, which
     evaluates every visited vertex exactly once (the method's own count)."""
@@ -376,6 +445,9 @@ def main():
     ap.add_argument("--multiway", type=float, default=0.0, metavar="SCALE",
                     help="only run the ten-sub-index inner-product workload at SCALE of its "
                          "10,000,000 vectors and print its JSON line")
+    ap.add_argument("--precision768", type=float, default=0.0, metavar="SCALE",
+                    help="only run the 768-d cosine precision workload at SCALE of its "
+                         "4,000,000 vectors (float32 and bfloat16 search copies)")
     ap.add_argument("--calib-only", action="store_true",
                     help="only copy 1 GiB device to device (counter calibration) and exit")
     args = ap.parse_args()
@@ -393,6 +465,10 @@ def main():
         return
     import paper_2602_17099_amd as pkg
     pkg.lib()
+    if args.precision768 > 0:
+        pr = precision768(pkg, args.precision768, max(1, min(args.steps, 3)), args.warmup)
+        print(json.dumps({"precision768": pr}), flush=True)
+        return
     if args.multiway > 0:
         mw = multiway(pkg, args.multiway, max(1, min(args.steps, 3)), args.warmup)
         print(json.dumps({"multiway": mw}), flush=True)
