@@ -218,3 +218,30 @@ def test_tune_search_rejects_on_host(pkg):
     assert "entry" in pkg.last_error()
     v2 = pkg.Vectors(n=10, dim=32, f32=8, search_dtype=1, search=8)
     assert L.rnsm_tune_search(C.byref(g), C.byref(v2), 32, 2, 100, C.byref(t), None) == 4
+
+
+def test_header_is_plain_c(tmp_path):
+    # a C99 caller can include the header and name every entry point
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include "rnsm.h"\n'
+                   "int main(void) {\n"
+                   "    rnsm_params p = {0};\n"
+                   "    rnsm_search_tuning t;\n"
+                   "    rnsm_stats s;\n"
+                   "    typedef void (*fn)(void);\n"
+                   "    fn f[] = {(fn)rnsm_merge, (fn)rnsm_merge_simple, (fn)mos_plan,\n"
+                   "              (fn)rnsm_select_pivots, (fn)rnsm_search, (fn)rnsm_tune_search,\n"
+                   "              (fn)rnsm_build_graph, (fn)rnsm_convert, (fn)rnsm_get_stats,\n"
+                   "              (fn)rnsm_last_error};\n"
+                   "    (void)p; (void)t; (void)s; (void)f;\n"
+                   "    return RNSM_FLAG_AUTOTUNE == 4u ? 0 : 1;\n"
+                   "}\n")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                        "-fsyntax-only", "-I", os.path.join(ROOT, "include"), str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
