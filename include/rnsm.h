@@ -253,6 +253,11 @@ rnsm_status rnsm_select_pivots(int64_t n, const int64_t* rk_offsets, const int32
  * query from g->entry. ef in 1..128, k in 1..ef.
  * out_ids: device [nq x k] local ids (-1 when fewer than k found);
  * out_dists: device [nq x k] float32 or NULL.
+ * Cosine: base norms come from base->f32, query norms from the query rows as
+ * given (float32, or the 16-bit values); both summed in double.
+ * Synchronises `stream` (NULL: the null stream) before returning.
+ * RNSM_EINVAL on bad arguments; RNSM_EINTERNAL if a search exceeded its
+ * iteration bound.
  */
 rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const void* queries,
                         int64_t nq, const int32_t* seeds, int32_t n_seeds, int32_t ef, int32_t k,
@@ -269,8 +274,7 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
  * of three launches after one untimed launch. g, base as in rnsm_search.
  * Writes the fastest shape (pass it as rnsm_params.search_hash_bits /
  * search_waves_per_block) and the default's, with their times; synchronises
- * `stream` (NULL: the null stream). RNSM_EINVAL on bad arguments,
- * RNSM_EUNSUPPORTED for cosine with a 16-bit copy.
+ * `stream` (NULL: the null stream). RNSM_EINVAL on bad arguments.
  */
 typedef struct {
     int32_t hash_bits, waves_per_block;     /* fastest shape measured */

@@ -292,11 +292,9 @@ constexpr int TARGET_WCAP = 256;
 
 }  // namespace
 
-extern "C" {
-
 const char* rnsm_last_error(void) { return g_err.c_str(); }
 
-rnsm_status rnsm_convert(const void* src, rnsm_dtype src_type, void* dst, rnsm_dtype dst_type,
+static rnsm_status rnsm_convert_impl(const void* src, rnsm_dtype src_type, void* dst, rnsm_dtype dst_type,
                          int64_t count, void* stream) {
     g_err.clear();
     if (count < 0) return fail(RNSM_EINVAL, "rnsm_convert: count < 0");
@@ -311,13 +309,13 @@ rnsm_status rnsm_convert(const void* src, rnsm_dtype src_type, void* dst, rnsm_d
     return RNSM_OK;
 }
 
-rnsm_status rnsm_get_stats(rnsm_stats* out) {
+static rnsm_status rnsm_get_stats_impl(rnsm_stats* out) {
     if (!out) return fail(RNSM_EINVAL, "rnsm_get_stats: NULL");
     *out = g_stats;
     return RNSM_OK;
 }
 
-rnsm_status mos_plan(int32_t m, const int64_t* sizes, const double* centroids, int32_t dim,
+static rnsm_status mos_plan_impl(int32_t m, const int64_t* sizes, const double* centroids, int32_t dim,
                      int32_t degree_bound, int32_t diameter, int32_t* out_ops, int32_t cap,
                      int32_t* out_count, int32_t* out_fallbacks) {
     g_err.clear();
@@ -342,7 +340,7 @@ rnsm_status mos_plan(int32_t m, const int64_t* sizes, const double* centroids, i
     return RNSM_OK;
 }
 
-rnsm_status rnsm_select_pivots(int64_t n, const int64_t* rk_offsets, const int32_t* rk_ids,
+static rnsm_status rnsm_select_pivots_impl(int64_t n, const int64_t* rk_offsets, const int32_t* rk_ids,
                                int32_t* pivots, int64_t* out_n_pivots, int32_t* followers,
                                int32_t* follower_pivot, int64_t* out_n_followers) {
     g_err.clear();
@@ -389,7 +387,7 @@ static rnsm_status tune_shape_locked(const rnsm_graph* g, const rnsm_vectors* ba
 // largest sub-index; guarded by g_lock
 static std::map<std::array<int64_t, 7>, std::pair<int, int>> g_tuned;
 
-rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
+static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
                        const rnsm_params* p, rnsm_csr* out) {
     const auto t0 = std::chrono::steady_clock::now();
     g_err.clear();
@@ -1068,6 +1066,8 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
         std::condition_variable qcv;
         std::deque<std::pair<int64_t, int64_t>> qmarks;
         bool qdone = false;
+        // the greedy thread must not index E.ev while the launcher appends to it
+        const hipEvent_t rk_ids_event = ev_rk_ids >= 0 ? E.ev[ev_rk_ids] : nullptr;
         std::thread launcher([&] {
             if (hipSetDevice(dev) != hipSuccess && cerr == hipSuccess) cerr = hipErrorInvalidDevice;
             for (;;) {
@@ -1079,9 +1079,32 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
                     it = qmarks.front();
                     qmarks.pop_front();
                 }
-                emit(it.first, it.second);
+                try {
+                    emit(it.first, it.second);
+                } catch (const std::bad_alloc&) {
+                    if (cerr == hipSuccess) cerr = hipErrorOutOfMemory;
+                } catch (...) {
+                    if (cerr == hipSuccess) cerr = hipErrorUnknown;
+                }
             }
         });
+        // joins the launcher on every way out of this scope (an exception
+        // from the greedy included)
+        struct JoinLauncher {
+            std::thread& t;
+            std::mutex& m;
+            std::condition_variable& cv;
+            bool& done;
+            ~JoinLauncher() {
+                if (!t.joinable()) return;
+                {
+                    std::lock_guard<std::mutex> l(m);
+                    done = true;
+                }
+                cv.notify_one();
+                t.join();
+            }
+        } join_launcher{launcher, qm, qcv, qdone};
         auto post = [&](int64_t a1, int64_t b1) {
             if (th_first_post < 0) th_first_post = ms_since(th1);
             {
@@ -1120,7 +1143,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
                           },
                           [&] {
                               th_levels = ms_since(th1);
-                              wait_err = hipEventSynchronize(E.ev[ev_rk_ids]);
+                              wait_err = hipEventSynchronize(rk_ids_event);
                               th_ids = ms_since(th1);
                           });  // the ids are copied after the offsets
         } else {
@@ -1289,7 +1312,7 @@ rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* 
     return RNSM_OK;
 }
 
-rnsm_status rnsm_merge_simple(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
+static rnsm_status rnsm_merge_simple_impl(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
                               int32_t R, int32_t L, float alpha, rnsm_csr* out) {
     rnsm_params p;
     memset(&p, 0, sizeof p);
@@ -1304,42 +1327,50 @@ rnsm_status rnsm_merge_simple(int32_t m, const rnsm_graph* graphs, const rnsm_ve
     return rnsm_merge(m, graphs, &v, &p, out);
 }
 
-rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const void* queries,
-                        int64_t nq, const int32_t* seeds, int32_t n_seeds, int32_t ef, int32_t k,
-                        rnsm_metric metric, int32_t* out_ids, float* out_dists, void* stream) {
-    g_err.clear();
+// Device buffers of one beam-search call: counters (CNT_SLOTS x CNT_N), the
+// error flag, and for cosine the norms of the base rows and of the queries.
+struct SearchBufs {
+    u64* cnt = nullptr;
+    int* errf = nullptr;
+    float* bn = nullptr;
+    float* qn = nullptr;
+};
+
+// Argument checks of rnsm_search and its allocation-free variant.
+static rnsm_status search_check(const char* fn, const rnsm_graph* g, const rnsm_vectors* base,
+                                const void* queries, int64_t nq, const int32_t* seeds,
+                                int32_t n_seeds, int32_t ef, int32_t k, rnsm_metric metric,
+                                int32_t* out_ids, VecInfo& vi) {
     if (!g || !base || !out_ids || (nq > 0 && !queries))
-        return fail(RNSM_EINVAL, "rnsm_search: NULL argument");
-    if (ef < 1 || ef > 128) return fail(RNSM_EINVAL, "rnsm_search: ef outside 1..128");
-    if (k < 1 || k > ef) return fail(RNSM_EINVAL, "rnsm_search: k outside 1..ef");
-    if (metric < RNSM_L2SQ || metric > RNSM_COSINE) return fail(RNSM_EINVAL, "rnsm_search: metric");
-    if (seeds && n_seeds < 1) return fail(RNSM_EINVAL, "rnsm_search: n_seeds < 1");
+        return fail(RNSM_EINVAL, "%s: NULL argument", fn);
+    if (nq < 0) return fail(RNSM_EINVAL, "%s: nq < 0", fn);
+    if (ef < 1 || ef > 128) return fail(RNSM_EINVAL, "%s: ef outside 1..128", fn);
+    if (k < 1 || k > ef) return fail(RNSM_EINVAL, "%s: k outside 1..ef", fn);
+    if (metric < RNSM_L2SQ || metric > RNSM_COSINE) return fail(RNSM_EINVAL, "%s: metric", fn);
+    if (seeds && n_seeds < 1) return fail(RNSM_EINVAL, "%s: n_seeds < 1", fn);
     if (g->n < 1 || !g->offsets || !g->nbrs || base->n != g->n)
-        return fail(RNSM_EINVAL, "rnsm_search: graph / base mismatch");
-    if (!seeds && (g->entry < 0 || g->entry >= g->n)) return fail(RNSM_EINVAL, "rnsm_search: entry");
-    VecInfo vi;
-    rnsm_status vs = vec_info(base, vi);
-    if (vs != RNSM_OK) return vs;
-    if (nq == 0) return RNSM_OK;
-    std::lock_guard<std::mutex> lk(g_lock);
-    hipStream_t st = (hipStream_t)stream;
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
-    Workspace& ws = g_ws[dev];
-    u64* cnt;
-    int* errf;
-    float *bn = nullptr, *qn = nullptr;
-    WS(cnt, "search_counters", sizeof(u64) * CNT_SLOTS * CNT_N);
-    WS(errf, "search_err", sizeof(int));
-    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * CNT_SLOTS * CNT_N, st));
-    HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
+        return fail(RNSM_EINVAL, "%s: graph / base mismatch", fn);
+    if (!seeds && (g->entry < 0 || g->entry >= g->n)) return fail(RNSM_EINVAL, "%s: entry", fn);
+    return vec_info(base, vi);
+}
+
+// Algorithm 1 for nq queries on the given buffers (st ordered): clears the
+// counters and the error flag with a kernel, makes the cosine norms (base
+// rows from their float32 originals, queries from the rows as given, in the
+// searched copy's type), launches, and waits for the error flag.
+static rnsm_status search_run(const char* fn, const rnsm_graph* g, const rnsm_vectors* base,
+                              const VecInfo& vi, const void* queries, int64_t nq,
+                              const int32_t* seeds, int32_t n_seeds, int32_t ef, int32_t k,
+                              rnsm_metric metric, int32_t* out_ids, float* out_dists,
+                              hipStream_t st, const SearchBufs& b) {
+    HIPCHK(launch_zero(b.cnt, sizeof(u64) * CNT_SLOTS * CNT_N, st));
+    HIPCHK(launch_zero(b.errf, sizeof(int), st));
     if (metric == RNSM_COSINE) {
-        if (base->search_dtype != RNSM_F32)
-            return fail(RNSM_EUNSUPPORTED, "rnsm_search: cosine needs a float32 search copy here");
-        WS(bn, "search_bnorm", sizeof(float) * g->n);
-        WS(qn, "search_qnorm", sizeof(float) * nq);
-        HIPCHK(launch_norms(base->f32, g->n, base->dim, bn, st));
-        HIPCHK(launch_norms((const float*)queries, nq, base->dim, qn, st));
+        HIPCHK(launch_norms(base->f32, g->n, base->dim, b.bn, st));
+        if (vi.tt == 0)
+            HIPCHK(launch_norms((const float*)queries, nq, base->dim, b.qn, st));
+        else
+            HIPCHK(launch_norms16(queries, vi.tt, nq, base->dim, b.qn, st));
     }
     SearchArgs a = {};
     a.base = vi.search;
@@ -1356,8 +1387,8 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     a.seed_stride = n_seeds;
     a.n_seeds = seeds ? n_seeds : 0;
     a.metric = metric;
-    a.base_norm = bn;
-    a.q_norm = qn;
+    a.base_norm = b.bn;
+    a.q_norm = b.qn;
     a.ef = ef;
     a.G = vi.G;
     a.lgG = ilog2i(vi.G);
@@ -1370,14 +1401,38 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
     a.out_d = out_dists;
     a.out_stride = k;
     a.out_k = k;
-    a.counters = cnt;
-    a.err = errf;
+    a.counters = b.cnt;
+    a.err = b.errf;
     HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
     int herr = 0;
-    HIPCHK(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&herr, b.errf, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (herr) return fail(RNSM_EINTERNAL, "rnsm_search: a search exceeded its iteration bound");
+    if (herr) return fail(RNSM_EINTERNAL, "%s: a search exceeded its iteration bound", fn);
     return RNSM_OK;
+}
+
+static rnsm_status rnsm_search_impl(const rnsm_graph* g, const rnsm_vectors* base, const void* queries,
+                        int64_t nq, const int32_t* seeds, int32_t n_seeds, int32_t ef, int32_t k,
+                        rnsm_metric metric, int32_t* out_ids, float* out_dists, void* stream) {
+    g_err.clear();
+    VecInfo vi;
+    rnsm_status vs = search_check("rnsm_search", g, base, queries, nq, seeds, n_seeds, ef, k,
+                                  metric, out_ids, vi);
+    if (vs != RNSM_OK || nq == 0) return vs;
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    Workspace& ws = g_ws[dev];
+    SearchBufs b;
+    WS(b.cnt, "search_counters", sizeof(u64) * CNT_SLOTS * CNT_N);
+    WS(b.errf, "search_err", sizeof(int));
+    if (metric == RNSM_COSINE) {
+        WS(b.bn, "search_bnorm", sizeof(float) * g->n);
+        WS(b.qn, "search_qnorm", sizeof(float) * nq);
+    }
+    return search_run("rnsm_search", g, base, vi, queries, nq, seeds, n_seeds, ef, k, metric,
+                      out_ids, out_dists, st, b);
 }
 
 // The search-shape autotuner's measurement, with g_lock held: g and base
@@ -1498,8 +1553,7 @@ static rnsm_status tune_shape_locked(const rnsm_graph* g, const rnsm_vectors* ba
     return RNSM_OK;
 }
 
-
-rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int32_t ef,
+static rnsm_status rnsm_tune_search_impl(const rnsm_graph* g, const rnsm_vectors* base, int32_t ef,
                              rnsm_metric metric, int64_t n_sample, rnsm_search_tuning* out,
                              void* stream) {
     g_err.clear();
@@ -1515,13 +1569,11 @@ rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int3
     VecInfo vi;
     rnsm_status vs = vec_info(base, vi);
     if (vs != RNSM_OK) return vs;
-    if (metric == RNSM_COSINE && base->search_dtype != RNSM_F32)
-        return fail(RNSM_EUNSUPPORTED, "rnsm_tune_search: cosine needs a float32 search copy here");
     std::lock_guard<std::mutex> lk(g_lock);
     return tune_shape_locked(g, base, vi, ef, metric, n_sample, 32, out, (hipStream_t)stream);
 }
 
-rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric metric,
+static rnsm_status rnsm_build_graph_impl(int64_t n, const float* X, int32_t dim, rnsm_metric metric,
                              const int32_t* knn, int32_t K, int32_t R, float alpha,
                              int32_t reverse, float alpha_rev, int64_t* out_offsets,
                              int32_t* out_nbrs, int32_t* out_entry, void* stream) {
@@ -1663,6 +1715,80 @@ rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric
     }
     *out_entry = (int32_t)hb[3 * best + 2];
     return RNSM_OK;
+}
+
+// ------------------------------------------------------------- the C ABI
+// Every entry point runs its body under guard(): no C++ exception crosses the
+// boundary (std::bad_alloc becomes RNSM_ENOMEM, anything else RNSM_EINTERNAL).
+// After a failed merge the device is drained, so that no queued work still
+// reads the library's buffers when the next call reuses them.
+namespace {
+template <class F>
+rnsm_status guard(const char* fn, F&& body) {
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return fail(RNSM_ENOMEM, "%s: host allocation failed", fn);
+    } catch (const std::exception& e) {
+        return fail(RNSM_EINTERNAL, "%s: %s", fn, e.what());
+    } catch (...) {
+        return fail(RNSM_EINTERNAL, "%s: unexpected exception", fn);
+    }
+}
+}  // namespace
+
+extern "C" {
+
+rnsm_status rnsm_convert(const void* src, rnsm_dtype src_type, void* dst, rnsm_dtype dst_type,
+                         int64_t count, void* stream) {
+    return guard("rnsm_convert", [&] { return rnsm_convert_impl(src, src_type, dst, dst_type, count, stream); });
+}
+
+rnsm_status rnsm_get_stats(rnsm_stats* out) {
+    return guard("rnsm_get_stats", [&] { return rnsm_get_stats_impl(out); });
+}
+
+rnsm_status mos_plan(int32_t m, const int64_t* sizes, const double* centroids, int32_t dim,
+                     int32_t degree_bound, int32_t diameter, int32_t* out_ops, int32_t cap,
+                     int32_t* out_count, int32_t* out_fallbacks) {
+    return guard("mos_plan", [&] { return mos_plan_impl(m, sizes, centroids, dim, degree_bound, diameter, out_ops, cap, out_count, out_fallbacks); });
+}
+
+rnsm_status rnsm_select_pivots(int64_t n, const int64_t* rk_offsets, const int32_t* rk_ids,
+                               int32_t* pivots, int64_t* out_n_pivots, int32_t* followers,
+                               int32_t* follower_pivot, int64_t* out_n_followers) {
+    return guard("rnsm_select_pivots", [&] { return rnsm_select_pivots_impl(n, rk_offsets, rk_ids, pivots, out_n_pivots, followers, follower_pivot, out_n_followers); });
+}
+
+rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
+                       const rnsm_params* p, rnsm_csr* out) {
+    const rnsm_status r = guard("rnsm_merge", [&] { return rnsm_merge_impl(m, graphs, vecs, p, out); });
+    if (r == RNSM_EDEVICE || r == RNSM_ENOMEM || r == RNSM_EINTERNAL) (void)hipDeviceSynchronize();
+    return r;
+}
+
+rnsm_status rnsm_merge_simple(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
+                              int32_t R, int32_t L, float alpha, rnsm_csr* out) {
+    return guard("rnsm_merge_simple", [&] { return rnsm_merge_simple_impl(m, graphs, vecs, R, L, alpha, out); });
+}
+
+rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const void* queries,
+                        int64_t nq, const int32_t* seeds, int32_t n_seeds, int32_t ef, int32_t k,
+                        rnsm_metric metric, int32_t* out_ids, float* out_dists, void* stream) {
+    return guard("rnsm_search", [&] { return rnsm_search_impl(g, base, queries, nq, seeds, n_seeds, ef, k, metric, out_ids, out_dists, stream); });
+}
+
+rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int32_t ef,
+                             rnsm_metric metric, int64_t n_sample, rnsm_search_tuning* out,
+                             void* stream) {
+    return guard("rnsm_tune_search", [&] { return rnsm_tune_search_impl(g, base, ef, metric, n_sample, out, stream); });
+}
+
+rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric metric,
+                             const int32_t* knn, int32_t K, int32_t R, float alpha,
+                             int32_t reverse, float alpha_rev, int64_t* out_offsets,
+                             int32_t* out_nbrs, int32_t* out_entry, void* stream) {
+    return guard("rnsm_build_graph", [&] { return rnsm_build_graph_impl(n, X, dim, metric, knn, K, R, alpha, reverse, alpha_rev, out_offsets, out_nbrs, out_entry, stream); });
 }
 
 }  // extern "C"

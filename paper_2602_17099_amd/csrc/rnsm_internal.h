@@ -107,6 +107,10 @@ hipError_t launch_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n,
 hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStream_t st,
                         double* out64 = nullptr);
 hipError_t launch_search(int tt, const SearchArgs& a, int waves_per_block, hipStream_t st);
+// row norms of 16-bit rows (tt 1: bfloat16, 2: float16), summed in double
+hipError_t launch_norms16(const void* X, int tt, int64_t n, int dim, float* out, hipStream_t st);
+// zero bytes (a multiple of 4) at p with a kernel (no memset node in a captured graph)
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 size_t search_lds_bytes(int hbits, int waves_per_block);
 hipError_t launch_prune(const PruneArgs& a, hipStream_t st);
 // the same rule with the Gram products on bfloat16 MFMA (dims 32, 64, 96,

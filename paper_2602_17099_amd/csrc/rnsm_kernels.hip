@@ -24,6 +24,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "rnsm_internal.h"
 
 namespace rnsm {
@@ -1993,6 +1995,51 @@ hipError_t launch_norms(const float* X, int64_t n, int dim, float* out, hipStrea
                         double* out64) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_norms, dim3(nblk(n, 256)), dim3(256), 0, st, X, n, dim, out, out64);
+    return hipGetLastError();
+}
+
+// row norms of 16-bit rows (tt 1: bfloat16, 2: float16), summed in double
+__global__ void k_norms16(const unsigned short* X, int tt, int64_t n, int dim, float* out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < dim; ++j) {
+        const unsigned short h = X[v * dim + j];
+        float x;
+        if (tt == 1) {
+            x = __uint_as_float((unsigned)h << 16);
+        } else {
+            union { unsigned short s; _Float16 f; } c;
+            c.s = h;
+            x = (float)c.f;
+        }
+        s = fma((double)x, (double)x, s);
+    }
+    out[v] = (float)sqrt(s);
+}
+
+hipError_t launch_norms16(const void* X, int tt, int64_t n, int dim, float* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (tt != 1 && tt != 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_norms16, dim3(nblk(n, 256)), dim3(256), 0, st,
+                       (const unsigned short*)X, tt, n, dim, out);
+    return hipGetLastError();
+}
+
+// zero `bytes` bytes at p (a multiple of 4, p 4-byte aligned): a kernel
+// rather than hipMemsetAsync, so that code a caller captures into a HIP
+// graph records no memset node
+__global__ void k_zero_words(unsigned* p, int64_t words) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < words) p[t] = 0u;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if ((bytes & 3) != 0 || ((uintptr_t)p & 3) != 0) return hipErrorInvalidValue;
+    const int64_t words = (int64_t)(bytes >> 2);
+    hipLaunchKernelGGL(k_zero_words, dim3(nblk(words, 256)), dim3(256), 0, st, (unsigned*)p,
+                       words);
     return hipGetLastError();
 }
 

@@ -216,8 +216,26 @@ def test_tune_search_rejects_on_host(pkg):
     g3 = pkg.Graph(n=10, offsets=8, nbrs=8, entry=10)
     assert L.rnsm_tune_search(C.byref(g3), *ok[1:]) == 1
     assert "entry" in pkg.last_error()
-    v2 = pkg.Vectors(n=10, dim=32, f32=8, search_dtype=1, search=8)
-    assert L.rnsm_tune_search(C.byref(g), C.byref(v2), 32, 2, 100, C.byref(t), None) == 4
+
+
+def test_search_rejects_on_host(pkg):
+    # argument errors of the beam search come back before any device work
+    L = pkg.lib()
+    g = pkg.Graph(n=10, offsets=8, nbrs=8, entry=0)
+    v = pkg.Vectors(n=10, dim=32, f32=8)
+    ok = [C.byref(g), C.byref(v), C.c_void_p(8), 4, None, 0, 16, 10, 0, C.c_void_p(8), None, None]
+    for i, bad, msg in [(0, None, "NULL"), (1, None, "NULL"), (2, None, "NULL"), (3, -1, "nq"),
+                        (6, 0, "ef"), (6, 129, "ef"), (7, 0, "k"), (7, 17, "k"),
+                        (8, 7, "metric"), (9, None, "NULL")]:
+        args = list(ok)
+        args[i] = bad
+        assert L.rnsm_search(*args) == 1, (i, bad)
+        assert msg in pkg.last_error()
+    args = list(ok)
+    args[4], args[5] = C.c_void_p(8), 0
+    assert L.rnsm_search(*args) == 1 and "n_seeds" in pkg.last_error()
+    g2 = pkg.Graph(n=11, offsets=8, nbrs=8, entry=0)
+    assert L.rnsm_search(C.byref(g2), *ok[1:]) == 1 and "mismatch" in pkg.last_error()
 
 
 def test_header_is_plain_c(tmp_path):

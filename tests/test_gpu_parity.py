@@ -121,6 +121,29 @@ def test_search_16bit_copy_on_integers(dev, orc, pkg, search_case, dtype):
         assert ids[i, :len(rid)].tolist() == rid.tolist(), i
 
 
+@pytest.mark.parametrize("dtype", ["bfloat16", "float16"])
+def test_search_cosine_16bit_copy(dev, orc, pkg, search_case, dtype):
+    # cosine on a 16-bit copy of integer rows: the copy holds the values
+    # exactly and every dot2 sum is exact, so ids and distance bits equal the
+    # float32 search's; those match the oracle's float64 cosine search
+    import torch
+    X, Q, off, nb, entry = search_case
+    dt = getattr(torch, dtype)
+    Xd, Qd = _t(X, dev), _t(Q, dev)
+    i32, d32 = pkg.search(_t(off, dev), _t(nb, dev), entry, Xd, Qd, 40, 20, metric=2)
+    i16, d16 = pkg.search(_t(off, dev), _t(nb, dev), entry, Xd, Qd.to(dt), 40, 20, metric=2,
+                          base_search=Xd.to(dt))
+    assert torch.equal(i32, i16)
+    assert torch.equal(d32, d16)
+    i32 = i32.cpu().numpy()
+    same = tot = 0
+    for i in range(0, len(Q), 7):
+        rid, _, _ = orc.beam_search(off, nb, X, Q[i], [entry], 40, metric=2)
+        same += len(set(rid[:20].tolist()) & set(i32[i].tolist()))
+        tot += min(20, len(rid))
+    assert same >= 0.99 * tot
+
+
 def test_search_tiny_visited_table(dev, orc, pkg, search_case, monkeypatch):
     # a 64-slot visited table overflows: the beam must still be exact
     X, Q, off, nb, entry = search_case
