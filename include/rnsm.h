@@ -264,6 +264,25 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
                         rnsm_metric metric, int32_t* out_ids, float* out_dists, void* stream);
 
 /*
+ * rnsm_search for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results, but its counters, error flag and
+ * cosine norms live in a static device array of the library (16 MiB per
+ * device, held until the process ends) instead of library-allocated memory;
+ * it calls no hipMalloc, hipFree or other allocating routine. The caller
+ * still passes inputs and outputs. Every call on a device shares that
+ * device's array, so calls that overlap on one device (on different
+ * streams or threads) race; calls are otherwise serialised by the library's
+ * lock. RNSM_EINVAL when cosine norms do not fit the array (4 bytes per base
+ * row plus 4 per query, about 4.19 million rows together), besides the
+ * argument errors of rnsm_search.
+ */
+rnsm_status rnsm_search_noalloc(const rnsm_graph* g, const rnsm_vectors* base, const void* queries,
+                                int64_t nq, const int32_t* seeds, int32_t n_seeds, int32_t ef,
+                                int32_t k, rnsm_metric metric, int32_t* out_ids, float* out_dists,
+                                void* stream);
+
+/*
  * Autotuner of the beam-search shape (the batched form's project-written
  * tuner of wavefronts per block and LDS visited-table size; the beam width
  * stays the caller's, since it sets recall). Times Algorithm 1 on the

@@ -19,8 +19,8 @@ FLAG_CENTROID_COSTS = 2
 FLAG_AUTOTUNE = 4
 
 SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_select_pivots", "rnsm_search",
-           "rnsm_tune_search", "rnsm_build_graph", "rnsm_convert", "rnsm_get_stats",
-           "rnsm_last_error"]
+           "rnsm_search_noalloc", "rnsm_tune_search", "rnsm_build_graph", "rnsm_convert",
+           "rnsm_get_stats", "rnsm_last_error"]
 
 _lib = None
 
@@ -95,6 +95,8 @@ def lib():
         L.rnsm_search.restype = C.c_int
         L.rnsm_search.argtypes = [P, P, P, C.c_int64, P, C.c_int32, C.c_int32, C.c_int32, C.c_int,
                                   P, P, P]
+        L.rnsm_search_noalloc.restype = C.c_int
+        L.rnsm_search_noalloc.argtypes = L.rnsm_search.argtypes
         L.rnsm_build_graph.restype = C.c_int
         L.rnsm_build_graph.argtypes = [C.c_int64, P, C.c_int32, C.c_int, P, C.c_int32, C.c_int32,
                                        C.c_float, C.c_int32, C.c_float, P, P, P, P]
@@ -239,20 +241,27 @@ def select_pivots(rk_offsets, rk_ids):
 
 
 def search(offsets, nbrs, entry, base, queries, ef, k, seeds=None, metric=L2SQ,
-           base_search=None, stream=None):
-    """Beam search of every query row in one graph (local ids)."""
+           base_search=None, stream=None, noalloc=False, out=None):
+    """Beam search of every query row in one graph (local ids). noalloc: call
+    rnsm_search_noalloc (the library's static scratch, no device allocation).
+    out: optional (ids int32 [nq, k], dists float32 [nq, k]) device tensors."""
     import torch
     g = Graph(n=offsets.shape[0] - 1, offsets=offsets.data_ptr(), nbrs=nbrs.data_ptr(),
               entry=int(entry))
     v = _vectors(base, base_search)
     nq = queries.shape[0]
-    ids = torch.empty((nq, k), dtype=torch.int32, device=base.device)
-    ds = torch.empty((nq, k), dtype=torch.float32, device=base.device)
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int32, device=base.device)
+        ds = torch.empty((nq, k), dtype=torch.float32, device=base.device)
+    else:
+        ids, ds = out
+        assert ids.shape == (nq, k) and ds.shape == (nq, k)
     ns = 0
     if seeds is not None:
         assert seeds.dtype == torch.int32 and seeds.is_contiguous()
         ns = seeds.shape[1]
-    _check(lib().rnsm_search(C.byref(g), C.byref(v), C.c_void_p(queries.data_ptr()), nq,
+    fn = lib().rnsm_search_noalloc if noalloc else lib().rnsm_search
+    _check(fn(C.byref(g), C.byref(v), C.c_void_p(queries.data_ptr()), nq,
                              _ptr(seeds), ns, ef, k, metric, C.c_void_p(ids.data_ptr()),
                              C.c_void_p(ds.data_ptr()), _stream(stream)))
     return ids, ds

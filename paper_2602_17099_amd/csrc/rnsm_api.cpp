@@ -1553,6 +1553,57 @@ static rnsm_status tune_shape_locked(const rnsm_graph* g, const rnsm_vectors* ba
     return RNSM_OK;
 }
 
+// Layout of the static scratch in rnsm_search_noalloc: counters, error flag,
+// then (cosine) base norms and query norms, each 256-byte aligned.
+struct NoallocLayout {
+    size_t cnt = 0, err = 0, bn = 0, qn = 0, total = 0;
+};
+static NoallocLayout noalloc_layout(int64_t n, int64_t nq, rnsm_metric metric) {
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    NoallocLayout l;
+    l.cnt = 0;
+    l.err = up(sizeof(u64) * CNT_SLOTS * CNT_N);
+    l.bn = l.err + 256;
+    l.total = l.bn;
+    if (metric == RNSM_COSINE) {
+        l.qn = up(l.bn + sizeof(float) * (size_t)n);
+        l.total = l.qn + sizeof(float) * (size_t)nq;
+    }
+    return l;
+}
+
+static rnsm_status rnsm_search_noalloc_impl(const rnsm_graph* g, const rnsm_vectors* base,
+                                            const void* queries, int64_t nq, const int32_t* seeds,
+                                            int32_t n_seeds, int32_t ef, int32_t k,
+                                            rnsm_metric metric, int32_t* out_ids, float* out_dists,
+                                            void* stream) {
+    g_err.clear();
+    VecInfo vi;
+    rnsm_status vs = search_check("rnsm_search_noalloc", g, base, queries, nq, seeds, n_seeds, ef,
+                                  k, metric, out_ids, vi);
+    if (vs != RNSM_OK) return vs;
+    const NoallocLayout l = noalloc_layout(g->n, nq, metric);
+    if (l.total > NOALLOC_SCRATCH_BYTES)
+        return fail(RNSM_EINVAL,
+                    "rnsm_search_noalloc: cosine norms of %lld base rows and %lld queries need "
+                    "%zu bytes of scratch, above its %zu bytes",
+                    (long long)g->n, (long long)nq, l.total, NOALLOC_SCRATCH_BYTES);
+    if (nq == 0) return RNSM_OK;
+    std::lock_guard<std::mutex> lk(g_lock);
+    void* sp = nullptr;
+    HIPCHK(noalloc_scratch(&sp));
+    char* base_p = (char*)sp;
+    SearchBufs b;
+    b.cnt = (u64*)(base_p + l.cnt);
+    b.errf = (int*)(base_p + l.err);
+    if (metric == RNSM_COSINE) {
+        b.bn = (float*)(base_p + l.bn);
+        b.qn = (float*)(base_p + l.qn);
+    }
+    return search_run("rnsm_search_noalloc", g, base, vi, queries, nq, seeds, n_seeds, ef, k,
+                      metric, out_ids, out_dists, (hipStream_t)stream, b);
+}
+
 static rnsm_status rnsm_tune_search_impl(const rnsm_graph* g, const rnsm_vectors* base, int32_t ef,
                              rnsm_metric metric, int64_t n_sample, rnsm_search_tuning* out,
                              void* stream) {
@@ -1776,6 +1827,16 @@ rnsm_status rnsm_search(const rnsm_graph* g, const rnsm_vectors* base, const voi
                         int64_t nq, const int32_t* seeds, int32_t n_seeds, int32_t ef, int32_t k,
                         rnsm_metric metric, int32_t* out_ids, float* out_dists, void* stream) {
     return guard("rnsm_search", [&] { return rnsm_search_impl(g, base, queries, nq, seeds, n_seeds, ef, k, metric, out_ids, out_dists, stream); });
+}
+
+rnsm_status rnsm_search_noalloc(const rnsm_graph* g, const rnsm_vectors* base,
+                                const void* queries, int64_t nq, const int32_t* seeds,
+                                int32_t n_seeds, int32_t ef, int32_t k, rnsm_metric metric,
+                                int32_t* out_ids, float* out_dists, void* stream) {
+    return guard("rnsm_search_noalloc", [&] {
+        return rnsm_search_noalloc_impl(g, base, queries, nq, seeds, n_seeds, ef, k, metric,
+                                        out_ids, out_dists, stream);
+    });
 }
 
 rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int32_t ef,

@@ -111,6 +111,10 @@ hipError_t launch_search(int tt, const SearchArgs& a, int waves_per_block, hipSt
 hipError_t launch_norms16(const void* X, int tt, int64_t n, int dim, float* out, hipStream_t st);
 // zero bytes (a multiple of 4) at p with a kernel (no memset node in a captured graph)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// static device scratch of the allocation-free search (bytes per device) and
+// its address on the current device (looked up once per device)
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+hipError_t noalloc_scratch(void** out);
 size_t search_lds_bytes(int hbits, int waves_per_block);
 hipError_t launch_prune(const PruneArgs& a, hipStream_t st);
 // the same rule with the Gram products on bfloat16 MFMA (dims 32, 64, 96,

@@ -2331,4 +2331,34 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
     return hipGetLastError();
 }
 
+// ------------------------------------------- static scratch of rnsm_search_noalloc
+
+// The scratch memory of the allocation-free search entry point (counters,
+// error flag, cosine norms): a file-scope device array, so that the entry
+// point allocates nothing. Every GPU the library runs on holds its own copy
+// until the process ends. Host code must not use the array's name as a
+// device address (it names a host-side stand-in): noalloc_scratch() gives
+// the copy of the current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void** out) {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void* ptr[MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace rnsm

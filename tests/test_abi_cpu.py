@@ -263,3 +263,24 @@ def test_header_is_plain_c(tmp_path):
                         "-fsyntax-only", "-I", os.path.join(ROOT, "include"), str(src)],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_search_noalloc_rejects_on_host(pkg):
+    # argument errors, and cosine norms beyond the static scratch, come back
+    # before any device work
+    L = pkg.lib()
+    g = pkg.Graph(n=10, offsets=8, nbrs=8, entry=0)
+    v = pkg.Vectors(n=10, dim=32, f32=8)
+    ok = [C.byref(g), C.byref(v), C.c_void_p(8), 4, None, 0, 16, 10, 0, C.c_void_p(8), None, None]
+    for i, bad, msg in [(0, None, "NULL"), (3, -1, "nq"), (6, 0, "ef"), (7, 17, "k")]:
+        args = list(ok)
+        args[i] = bad
+        assert L.rnsm_search_noalloc(*args) == 1, (i, bad)
+        assert msg in pkg.last_error()
+    big = pkg.Graph(n=4_000_000, offsets=8, nbrs=8, entry=0)
+    vb = pkg.Vectors(n=4_000_000, dim=32, f32=8)
+    args = [C.byref(big), C.byref(vb), C.c_void_p(8), 500_000, None, 0, 16, 10, 2,
+            C.c_void_p(8), None, None]
+    assert L.rnsm_search_noalloc(*args) == 1
+    assert "scratch" in pkg.last_error()
+
