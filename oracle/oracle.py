@@ -86,6 +86,8 @@ def _setup(L):
     L.orc_mos.argtypes = [C.c_int, P, C.c_int, C.c_int, P, C.c_int, P, P]
     L.orc_plan.restype = C.c_int
     L.orc_plan.argtypes = [C.c_int, P, P, C.c_int, C.c_int, C.c_int, P, C.c_int, P, P]
+    L.orc_plan_cost.restype = C.c_int
+    L.orc_plan_cost.argtypes = [C.c_int, P, P, C.c_int, C.c_int, P, C.c_int, P, P]
     L.orc_merge.restype = C.c_int
     L.orc_merge.argtypes = [C.c_int, P, P, P, P, P, C.c_int, P, P, P, P, P, P, P, P]
     L.orc_knn.restype = C.c_int
@@ -231,6 +233,20 @@ def plan(sizes, R, delta=2, centroids=None):
                         _p(ops), m * m, _p(n), _p(nf))
     if rc != 0:
         raise ValueError(f"orc_plan failed: {rc}")
+    return [tuple(int(v) for v in o) for o in ops[: n[0]]], int(nf[0])
+
+
+def plan_cost(sizes, cost, R, delta=2):
+    """Operations (source, target) in execution order from a cost matrix."""
+    sizes = _i64(sizes)
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    m = len(sizes)
+    ops = np.zeros((max(1, m * m), 2), dtype=np.int32)
+    n = np.zeros(1, dtype=np.int32)
+    nf = np.zeros(1, dtype=np.int32)
+    rc = lib().orc_plan_cost(m, _p(sizes), _p(cost), R, delta, _p(ops), m * m, _p(n), _p(nf))
+    if rc != 0:
+        raise ValueError(f"orc_plan_cost failed: {rc}")
     return [tuple(int(v) for v in o) for o in ops[: n[0]]], int(nf[0])
 
 

@@ -678,13 +678,21 @@ int orc_plan(int m, const int64_t* sizes, const double* centroids, int dim, int 
              int32_t* out_ops, int cap, int* n_ops, int* n_fallback) {
     double* C = (double*)malloc(sizeof(double) * (size_t)m * m);
     orc_mos_cost(m, centroids, dim, C);
+    int r = orc_plan_cost(m, sizes, C, R, delta, out_ops, cap, n_ops, n_fallback);
+    free(C);
+    return r;
+}
+
+/* the same plan from a given cost matrix C [m x m] */
+int orc_plan_cost(int m, const int64_t* sizes, const double* C, int R, int delta,
+                  int32_t* out_ops, int cap, int* n_ops, int* n_fallback) {
     int ne = 0, nf = 0;
     int32_t* edges = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)(m * m + 1));
     if (m >= 2 && orc_mos(m, C, R, delta, edges, m * m, &ne, &nf) != 0) {
-        free(C); free(edges);
+        free(edges);
         return -1;
     }
-    if (ne > cap) { free(C); free(edges); return -2; }
+    if (ne > cap) { free(edges); return -2; }
     /* normalise every edge to (min, max) */
     for (int a = 0; a < ne; ++a) {
         int32_t e0 = edges[2 * a], e1 = edges[2 * a + 1];
@@ -717,7 +725,7 @@ int orc_plan(int m, const int64_t* sizes, const double* centroids, int dim, int 
     }
     *n_ops = ne;
     if (n_fallback) *n_fallback = nf;
-    free(C); free(edges);
+    free(edges);
     return 0;
 }
 

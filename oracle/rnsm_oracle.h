@@ -54,6 +54,8 @@ int orc_mos(int m, const double* C, int R, int delta, int32_t* out_edges, int ca
             int* n_fallback);
 int orc_plan(int m, const int64_t* sizes, const double* centroids, int dim, int R, int delta,
              int32_t* out_ops, int cap, int* n_ops, int* n_fallback);
+int orc_plan_cost(int m, const int64_t* sizes, const double* C, int R, int delta,
+                  int32_t* out_ops, int cap, int* n_ops, int* n_fallback);
 int orc_merge(int m, const int64_t* sizes, const int64_t* offsets_cat, const int32_t* nbrs_cat,
               const int32_t* entries, const float* X, int dim, const orc_params_t* P,
               int32_t* out_rows, double* out_dists, int32_t* out_deg, int32_t* out_entry,

@@ -30,6 +30,19 @@ MUTANTS = {
                            "(c1 == c0 && (i1 < i0 || (i1 == i0 && j1 < j0)))"),
     "larger_is_source": ("int src = (sizes[j] < sizes[i]) ? j : i;",
                          "int src = (sizes[j] > sizes[i]) ? j : i;"),
+    "ops_cost_order_reversed": ("int later = c1 > c0 ||", "int later = c1 < c0 ||"),
+    "follower_seeded_from_entry": ("res_ids + (int64_t)p * RES,\n                               res_n[p], EL",
+                                   "&t->entry,\n                               1, EL"),
+    "follower_seeded_from_top1": ("res_n[p], EL, &vis", "(res_n[p] > 0 ? 1 : 0), EL, &vis"),
+    "follower_beam_ef_naive": ("res_n[p], EL, &vis", "res_n[p], L, &vis"),
+    "follower_cosine_query_norm_dropped": ("double qn = S->norms ? S->norms[s->base + y] : 1.0;",
+                                           "double qn = 1.0;"),
+    "merged_entry_smallest": ("if (sizes[i] > sizes[big]) big = i;",
+                              "if (sizes[i] < sizes[big]) big = i;"),
+    "knn_queries_no_cosine_norm": ("un = sqrt(s);", "un = 1.0;"),
+    "knn_queries_unsorted": ("qsort(c, (size_t)n, sizeof(wkey_t), wkey_cmp);", ""),
+    "builder_reverse_with_alpha": ("deg2[w] = prune(&S, w, W2, nw, alpha_rev, R",
+                                   "deg2[w] = prune(&S, w, W2, nw, alpha, R"),
 }
 
 

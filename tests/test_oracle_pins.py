@@ -270,6 +270,24 @@ def test_mos_hand_traced_relay(orc, name):
     assert nf == gd["fallbacks"]
 
 
+@pytest.mark.parametrize("name", ["mos_relay_5.json", "mos_relay_7.json"])
+def test_mos_hand_traced_execution_order(orc, name):
+    # Section 5: operations run by ascending cost, then (min index, max index);
+    # with equal sizes the lower index is the source
+    gd = _gold(name)
+    C = np.array(gd["cost"], np.float64)
+    m = len(C)
+    ops, nf = orc.plan_cost([1] * m, C, gd["degree_bound"], gd["diameter"])
+    assert [list(o) for o in ops] == gd["execution_order"]
+    assert nf == gd["fallbacks"]
+    # unequal sizes flip the direction only: the smaller sub-index is the source
+    sizes = [10 + 7 * ((5 * i) % m) for i in range(m)]
+    ops2, _ = orc.plan_cost(sizes, C, gd["degree_bound"], gd["diameter"])
+    assert [tuple(sorted(o)) for o in ops2] == [tuple(o) for o in gd["execution_order"]]
+    for s, t in ops2:
+        assert sizes[s] < sizes[t] or (sizes[s] == sizes[t] and s < t)
+
+
 def test_mos_two_and_star(orc):
     assert orc.mos(orc.mos_cost(2), 2)[0] == [(0, 1)]
     for m in (3, 4, 5):
@@ -358,6 +376,133 @@ def test_multi_op_exhaustive_equals_sequential_cm(orc):
         assert got == rows[v], v
 
 
+def _merge_golden(orc, gd):
+    X = np.array(gd["X"], np.float32)
+    subs = [(*_csr(sub["adj"]), sub["entry"]) for sub in gd["subs"]]
+    P = gd["params"]
+    return X, subs, orc.merge(subs, X, R=P["R"], L=P["L"], alpha=P["alpha"], k=P["k"],
+                              kplus=P["kplus"], ef_slide=P["ef_slide"], trace=True)
+
+
+def test_pairwise_op_hand_traced_sliding(orc):
+    # Algorithm 2 end to end on a hand-traced instance where the follower's
+    # local sliding from its pivot's whole beam (ef_slide 1 < ef_naive 2)
+    # ends in another beam than a naive search or a top-1 seed would
+    gd = _gold("op_slide.json")
+    X, subs, out = _merge_golden(orc, gd)
+    tr = out["trace"]
+    assert tr["source"] == 0
+    assert tr["nk"].tolist() == gd["nk"]
+    assert tr["pivot_of"].tolist() == gd["pivot_of"]
+    assert tr["res_ids"].tolist() == gd["res_ids"]
+    want_d = [[np.inf if d is None else d for d in r] for r in gd["res_d"]]
+    assert tr["res_d"].tolist() == want_d
+    offs, nb, ds = out["offsets"], out["nbrs"], out["dists"]
+    rows = [nb[offs[v]:offs[v + 1]].tolist() for v in range(len(X))]
+    assert rows == gd["rows"]
+    assert [ds[offs[v]:offs[v + 1]].tolist() for v in range(len(X))] == gd["dists"]
+    assert out["entry"] == gd["entry"]
+    # the contrasts of the trace, with the pinned Algorithm 1
+    t_off, t_nb, _ = subs[1]
+    s1 = X[1]
+    naive, _, _ = orc.beam_search(t_off, t_nb, X, s1, [0], 1, base=3)
+    assert naive.tolist() == gd["naive_ef1_s1"]
+    top1, _, _ = orc.beam_search(t_off, t_nb, X, s1, [gd["res_ids"][0][0]], 1, base=3)
+    assert top1.tolist() == gd["top1_seed_ef1_s1"]
+
+
+def _nonzero_int(n, dim, seed):
+    X = inputs.tiny_int(n, dim, seed=seed, lo=-6, hi=6)
+    X[np.all(X == 0, axis=1), 0] = 1.0  # cosine needs non-zero rows
+    return X
+
+
+def test_beam_search_cosine_exhaustive_equals_brute_force(orc):
+    # cosine on rows that are not normalised: with ef >= n the search visits
+    # the whole connected graph, so its beam is the exact top-ef by (d, id)
+    X = _nonzero_int(70, 6, seed=45)
+    Q = _nonzero_int(5, 6, seed=46)
+    offs, nb = inputs.random_graph(70, 5, seed=47)
+    X64 = X.astype(np.float64)
+    nx = np.sqrt((X64 * X64).sum(1))
+    for q in Q:
+        ids, ds, _ = orc.beam_search(offs, nb, X, q, [0], 80, metric=orc.COSINE)
+        q64 = q.astype(np.float64)
+        d = 1.0 - (X64 @ q64) / (nx * np.sqrt(q64 @ q64))
+        want = np.lexsort((np.arange(70), d))
+        assert len(ids) == 70
+        # the orders agree wherever the float64 distances are not within rounding
+        gap = np.diff(d[want])
+        for i in range(69):
+            if gap[i] > 1e-12:
+                assert set(ids[:i + 1].tolist()) == set(want[:i + 1].tolist()), i
+        assert np.allclose(ds, d[ids], rtol=0, atol=1e-13)
+
+
+def test_op_searches_and_prune_compose_cosine(orc):
+    # one operation with cosine on unnormalised integer rows and beams far
+    # below the target size: every pivot's naive search is Algorithm 1 from the
+    # target's entry with ef_naive, every follower's sliding is Algorithm 1
+    # seeded with the ids of its pivot's beam with ef_slide, and each source row
+    # is Prune(row + results) (pinned primitives composed by hand)
+    sizes, R, L, EL = [150, 220], 8, 12, 5
+    X = _nonzero_int(sum(sizes), 6, seed=48)
+    subs, rows = _subs_random(sizes, 5, 1100)
+    out = orc.merge(subs, X, R=R, L=L, alpha=1.2, metric=orc.COSINE, ef_slide=EL, trace=True)
+    tr = out["trace"]
+    assert tr["source"] == 0
+    t_off, t_nb, t_entry = subs[1]
+    piv = tr["pivot_of"]
+    assert 0 < tr["n_pivots"] < sizes[0]
+    for u in range(sizes[0]):
+        p = piv[u]
+        if p < 0:
+            ids, ds, _ = orc.beam_search(t_off, t_nb, X, X[u], [t_entry], L, metric=orc.COSINE,
+                                         base=sizes[0])
+        else:
+            seeds = tr["res_ids"][p][tr["res_ids"][p] >= 0]
+            ids, ds, _ = orc.beam_search(t_off, t_nb, X, X[u], seeds, EL, metric=orc.COSINE,
+                                         base=sizes[0])
+        got = tr["res_ids"][u][:len(ids)].tolist()
+        assert got == ids.tolist(), u
+        assert (tr["res_ids"][u][len(ids):] == -1).all()
+        assert tr["res_d"][u][:len(ids)].tolist() == ds.tolist(), u
+        row = orc.prune(u, rows[u] + [sizes[0] + int(i) for i in ids], X, 1.2, R,
+                        metric=orc.COSINE)[0].tolist()
+        assert out["nbrs"][out["offsets"][u]:out["offsets"][u + 1]].tolist() == row, u
+
+
+def test_whole_op_exhaustive_cosine_equals_exact_cm(orc):
+    # P6 with cosine on rows that are not normalised (norms inside the prune)
+    sizes, R, alpha = [40, 55], 7, 1.2
+    X = _nonzero_int(sum(sizes), 5, seed=49)
+    subs, rows = _subs_random(sizes, 4, 1300)
+    out = orc.merge(subs, X, R=R, L=64, alpha=alpha, metric=orc.COSINE)
+    ref = {v: list(r) for v, r in rows.items()}
+    for u in range(40):
+        ref[u] = orc.prune(u, ref[u] + list(range(40, 95)), X, alpha, R, metric=orc.COSINE)[0].tolist()
+    rev = {}
+    for u in range(40):
+        for v in ref[u]:
+            if v >= 40:
+                rev.setdefault(v, []).append(u)
+    for v, r in rev.items():
+        ref[v] = orc.prune(v, ref[v] + r, X, alpha, R, metric=orc.COSINE)[0].tolist()
+    for v in range(95):
+        assert out["nbrs"][out["offsets"][v]:out["offsets"][v + 1]].tolist() == ref[v], v
+
+
+def test_merged_entry_is_largest_subindex(orc):
+    # the entry of the largest sub-index (ties: the lowest index), which is
+    # neither the first nor the last here
+    sizes = [30, 20, 50, 50, 10]
+    X = inputs.tiny_int(sum(sizes), 4, seed=52)
+    subs, _ = _subs_random(sizes, 3, 1500)
+    subs = [(o, nb, 7 + i) for i, (o, nb, _) in enumerate(subs)]
+    out = orc.merge(subs, X, R=6, L=8, alpha=1.2)
+    assert out["entry"] == 30 + 20 + 9
+
+
 def test_merge_output_invariants(orc):
     X = inputs.tiny_int(800, 32, seed=51)
     g0 = orc.build_graph(X[:400], 32, 16, alpha=1.0)
@@ -404,6 +549,54 @@ def test_knn_brute_force_and_fast_path(orc):
     assert np.array_equal(orc.knn_fast(X, 12, block=64), a)
     Y = np.random.default_rng(2).standard_normal((200, 7)).astype(np.float32)
     assert np.array_equal(orc.knn_fast(Y, 9, block=50), orc.knn(Y, 9))
+
+
+def test_knn_queries_brute_force(orc):
+    # squared L2 on integers: exact, ties by id; cosine on floats: the float64
+    # brute force order wherever distances are not within rounding
+    X = inputs.tiny_int(400, 6, seed=72, lo=-3, hi=3)
+    Q = inputs.tiny_int(15, 6, seed=73, lo=-3, hi=3)
+    ids, ds = orc.knn_queries(X, Q, 25)
+    for i, q in enumerate(Q):
+        d = ((X.astype(np.int64) - q.astype(np.int64)) ** 2).sum(1)
+        want = np.lexsort((np.arange(400), d))[:25]
+        assert ids[i].tolist() == want.tolist()
+        assert ds[i].tolist() == d[want].astype(np.float64).tolist()
+    g = np.random.default_rng(74)
+    Y = (g.standard_normal((300, 7)) * g.uniform(0.2, 5.0, (300, 1))).astype(np.float32)
+    QY = (g.standard_normal((12, 7)) * 3.0).astype(np.float32)
+    ids, ds = orc.knn_queries(Y, QY, 20, metric=orc.COSINE)
+    Y64 = Y.astype(np.float64)
+    for i, q in enumerate(QY):
+        q64 = q.astype(np.float64)
+        d = 1.0 - (Y64 @ q64) / (np.sqrt((Y64 * Y64).sum(1)) * np.sqrt(q64 @ q64))
+        order = np.argsort(d, kind="stable")
+        assert ids[i].tolist() == order[:20].tolist()
+        assert np.allclose(ds[i], d[order[:20]], rtol=0, atol=1e-13)
+
+
+def test_builder_reverse_pass_composes_prunes(orc):
+    # the builder with reverse offers: row1(v) = Prune(v, kNN(v), alpha);
+    # every kept v -> w offers v to w; each offered w becomes
+    # Prune(w, row1(w) + offers, alpha_rev); others keep row1
+    X = inputs.tiny_int(300, 6, seed=82, lo=-4, hi=4)
+    K, R, a, arev = 16, 6, 1.0, 1.3
+    knn = orc.knn(X, K)
+    offs, nb, _ = orc.build_graph(X, K, R, alpha=a, reverse=True, alpha_rev=arev, knn_ids=knn)
+    row1 = [orc.prune(v, knn[v], X, a, R)[0].tolist() for v in range(300)]
+    offers = {}
+    for v in range(300):
+        for w in row1[v]:
+            offers.setdefault(w, []).append(v)
+    changed = 0
+    for w in range(300):
+        want = row1[w]
+        if w in offers:
+            want = orc.prune(w, row1[w] + offers[w], X, arev, R)[0].tolist()
+            alt = orc.prune(w, row1[w] + offers[w], X, a, R)[0].tolist()
+            changed += want != alt
+        assert nb[offs[w]:offs[w + 1]].tolist() == want, w
+    assert changed > 0  # alpha_rev makes a difference on this input
 
 
 def test_builder_entry_and_rows(orc):
