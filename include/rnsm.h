@@ -24,10 +24,14 @@
  *    already kept w has alpha * d(w,v) < d(p,v) (strict; alpha as float32,
  *    product formed in double); stop at R kept; no backfill.
  *  - Memory: every pointer marked "device" is HIP device memory (for example
- *    torch.Tensor.data_ptr() of a CUDA/HIP tensor). Inputs are borrowed and
- *    read only; nothing is retained after a call returns. Outputs are
- *    caller-allocated. Work runs on `stream` (NULL: the default stream) and
- *    every call has finished on the device when it returns.
+ *    torch.Tensor.data_ptr() of a CUDA/HIP tensor). rnsm_merge, rnsm_search
+ *    and rnsm_tune_search also take graphs and vectors in host memory
+ *    (mem = RNSM_HOST), which they copy to the device first. Inputs are
+ *    borrowed and read only; nothing is retained after a call returns.
+ *    Outputs are caller-allocated device buffers, except a merge with
+ *    RNSM_FLAG_HOST_OUT, whose host arrays the library allocates and
+ *    rnsm_csr_free releases. Work runs on `stream` (NULL: the default stream)
+ *    and every call has finished on the device when it returns.
  *  - Errors: every entry point returns rnsm_status; no exception crosses the
  *    boundary. On error the outputs are unspecified and nothing leaks;
  *    rnsm_last_error() describes the failure (thread-local).
@@ -54,6 +58,9 @@ typedef enum {
 
 typedef enum { RNSM_L2SQ = 0, RNSM_IP = 1, RNSM_COSINE = 2 } rnsm_metric;
 
+/* where the memory of an input or output lives */
+typedef enum { RNSM_DEVICE = 0, RNSM_HOST = 1 } rnsm_memspace;
+
 /* storage type of the vectors the searches read (RNSM_U8: conversion input only) */
 typedef enum { RNSM_F32 = 0, RNSM_BF16 = 1, RNSM_F16 = 2, RNSM_U8 = 3 } rnsm_dtype;
 
@@ -65,20 +72,26 @@ typedef enum { RNSM_F32 = 0, RNSM_BF16 = 1, RNSM_F16 = 2, RNSM_U8 = 3 } rnsm_dty
                                        once per process for each device, storage type, row size,
                                        beam, R, metric and power-of-two size class; ignored when
                                        params fix search_hash_bits / search_waves_per_block */
+#define RNSM_FLAG_HOST_OUT 8u       /* the merged graph goes to host arrays that the library
+                                       allocates (out->mem = RNSM_HOST; free with rnsm_csr_free);
+                                       the caller's out pointers are ignored */
+#define RNSM_FLAG_NO_STATS 16u      /* skip the device timing events and counter read-back of
+                                       rnsm_get_stats (its times and counts stay zero) */
 
 /*
  * One input sub-index: a flat proximity graph (Section 2.2) over n vectors.
- * CSR in device memory: offsets[n+1] (int64, offsets[0] = 0, non-decreasing),
- * nbrs[offsets[n]] local ids in [0, n). Rows hold no self-loop and no
- * duplicate, and at most R entries (rnsm_merge rejects others with
- * RNSM_EINVAL); nbrs may be NULL when offsets[n] = 0 (no edges).
- * entry: local id of the default entry point.
+ * CSR: offsets[n+1] (int64, offsets[0] = 0, non-decreasing), nbrs[offsets[n]]
+ * local ids in [0, n), both in device memory, or both in host memory with
+ * mem = RNSM_HOST. Rows hold no self-loop and no duplicate, and at most R
+ * entries (rnsm_merge rejects others with RNSM_EINVAL); nbrs may be NULL when
+ * offsets[n] = 0 (no edges). entry: local id of the default entry point.
  */
 typedef struct {
     int64_t n;
     const int64_t* offsets;
     const int32_t* nbrs;
     int32_t entry;
+    rnsm_memspace mem;
 } rnsm_graph;
 
 /*
@@ -95,6 +108,11 @@ typedef struct {
  * must be 2^k times 1, 2, 3 or 4 and at most 256 (float32: dim 4, 8, 12,
  * 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024); otherwise
  * RNSM_EUNSUPPORTED.
+ * row_stride: elements from one row to the next in f32 and in search (0:
+ *      dim, rows packed; otherwise >= dim, e.g. a column slice of a wider
+ *      matrix). mem: RNSM_DEVICE, or RNSM_HOST for f32 and search in host
+ *      memory. Strided or host rows are first copied, packed, to the device
+ *      (rnsm_search_noalloc takes packed device rows only).
  */
 typedef struct {
     int64_t n;
@@ -102,6 +120,8 @@ typedef struct {
     const float* f32;
     rnsm_dtype search_dtype;
     const void* search;
+    int64_t row_stride;
+    rnsm_memspace mem;
 } rnsm_vectors;
 
 /*
@@ -123,6 +143,10 @@ typedef struct {
  *          the merge measures itself; its first call of a kind includes the
  *          tuning time). rnsm_tune_search measures them. Results do not
  *          depend on the shape, only the speed does.
+ * max_device_bytes  budget of the device memory the merge's own buffers
+ *          need (inputs copied from the host or from strided rows included,
+ *          the caller's inputs and outputs not); a call that would exceed it
+ *          returns RNSM_ENOMEM before allocating. 0: no budget.
  */
 typedef struct {
     int32_t R, L;
@@ -133,13 +157,17 @@ typedef struct {
     uint32_t flags;
     void* stream;
     int32_t search_hash_bits, search_waves_per_block;
+    int64_t max_device_bytes;
 } rnsm_params;
 
 /*
- * Merged graph, caller-allocated device buffers:
+ * Merged graph. By default caller-allocated device buffers:
  * offsets [N+1] int64; nbrs [N*R] int32 capacity (global ids, first
  * offsets[N] used); dists [N*R] float32 capacity or NULL (distance of each
- * edge, recomputed in float32 on the original vectors).
+ * edge, recomputed in float32 on the original vectors); mem = RNSM_DEVICE.
+ * With RNSM_FLAG_HOST_OUT the library allocates host arrays offsets [N+1],
+ * nbrs [n_edges] and dists [n_edges], sets mem = RNSM_HOST, and the caller
+ * releases them with rnsm_csr_free (on error nothing is left allocated).
  * Written by the call: entry (global id of the entry of the largest
  * sub-index, ties: lowest index) and n_edges.
  * Pruned rows are in (distance, id) order; rows no operation touched keep the
@@ -151,7 +179,13 @@ typedef struct {
     float* dists;
     int32_t entry;
     int64_t n_edges;
+    rnsm_memspace mem;
 } rnsm_csr;
+
+/* Releases the host arrays of a merged graph the library allocated
+ * (mem = RNSM_HOST) and zeroes the struct; does nothing for NULL or for
+ * caller-owned device buffers (mem = RNSM_DEVICE). */
+void rnsm_csr_free(rnsm_csr* g);
 
 /*
  * Counters and event timings of the last rnsm_merge on this thread. Arrays
@@ -200,6 +234,8 @@ typedef struct {
  * RNSM_EINVAL: m < 2, NULL pointers, vecs->n != N, R/L/alpha/k out of range,
  * an entry out of range, or a malformed input row (offsets not
  * non-decreasing, id out of range, self-loop, duplicate, degree > R).
+ * RNSM_ENOMEM: a device or host allocation failed, or params->max_device_bytes
+ * would be exceeded.
  */
 rnsm_status rnsm_merge(int32_t m, const rnsm_graph* graphs, const rnsm_vectors* vecs,
                        const rnsm_params* params, rnsm_csr* out);

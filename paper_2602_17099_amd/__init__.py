@@ -17,10 +17,13 @@ F32, BF16, F16 = 0, 1, 2
 FLAG_ALL_PIVOTS = 1
 FLAG_CENTROID_COSTS = 2
 FLAG_AUTOTUNE = 4
+FLAG_HOST_OUT = 8
+FLAG_NO_STATS = 16
+DEVICE, HOST = 0, 1
 
 SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_select_pivots", "rnsm_search",
            "rnsm_search_noalloc", "rnsm_tune_search", "rnsm_build_graph", "rnsm_convert",
-           "rnsm_get_stats", "rnsm_last_error"]
+           "rnsm_get_stats", "rnsm_last_error", "rnsm_csr_free"]
 
 _lib = None
 
@@ -33,12 +36,13 @@ class RnsmError(RuntimeError):
 
 class Graph(C.Structure):
     _fields_ = [("n", C.c_int64), ("offsets", C.c_void_p), ("nbrs", C.c_void_p),
-                ("entry", C.c_int32)]
+                ("entry", C.c_int32), ("mem", C.c_int)]
 
 
 class Vectors(C.Structure):
     _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("f32", C.c_void_p),
-                ("search_dtype", C.c_int), ("search", C.c_void_p)]
+                ("search_dtype", C.c_int), ("search", C.c_void_p), ("row_stride", C.c_int64),
+                ("mem", C.c_int)]
 
 
 class Params(C.Structure):
@@ -46,7 +50,8 @@ class Params(C.Structure):
                 ("k_reverse", C.c_int32), ("k_expand", C.c_int32), ("ef_naive", C.c_int32),
                 ("ef_slide", C.c_int32), ("mos_degree", C.c_int32), ("mos_diameter", C.c_int32),
                 ("flags", C.c_uint32), ("stream", C.c_void_p),
-                ("search_hash_bits", C.c_int32), ("search_waves_per_block", C.c_int32)]
+                ("search_hash_bits", C.c_int32), ("search_waves_per_block", C.c_int32),
+                ("max_device_bytes", C.c_int64)]
 
 
 class SearchTuning(C.Structure):
@@ -57,7 +62,7 @@ class SearchTuning(C.Structure):
 
 class Csr(C.Structure):
     _fields_ = [("offsets", C.c_void_p), ("nbrs", C.c_void_p), ("dists", C.c_void_p),
-                ("entry", C.c_int32), ("n_edges", C.c_int64)]
+                ("entry", C.c_int32), ("n_edges", C.c_int64), ("mem", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -80,6 +85,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run paper_2602_17099_amd/build.py "
                                "(or __graft_entry__.build()) first")
+        # torch first: its bundled HIP runtime carries the soname the library
+        # links against, so the library binds to that one copy; loaded the
+        # other way round, the process would hold two HIP runtimes and the
+        # second would find no device
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.rnsm_merge.restype = C.c_int
@@ -106,6 +116,8 @@ def lib():
         L.rnsm_get_stats.argtypes = [P]
         L.rnsm_last_error.restype = C.c_char_p
         L.rnsm_last_error.argtypes = []
+        L.rnsm_csr_free.restype = None
+        L.rnsm_csr_free.argtypes = [P]
         _lib = L
     return _lib
 
@@ -130,11 +142,14 @@ def _stream(stream):
 
 
 def _vectors(X, search=None):
+    """Device rows: contiguous, or rows with unit column stride and a row
+    stride (e.g. a column slice of a wider matrix), passed as row_stride."""
     import torch
-    assert X.is_cuda and X.dtype == torch.float32 and X.is_contiguous()
-    v = Vectors(n=X.shape[0], dim=X.shape[1], f32=X.data_ptr(), search_dtype=F32, search=None)
+    assert X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1
+    v = Vectors(n=X.shape[0], dim=X.shape[1], f32=X.data_ptr(), search_dtype=F32, search=None,
+                row_stride=X.stride(0) if X.shape[0] > 1 else 0, mem=DEVICE)
     if search is not None:
-        assert search.is_cuda and search.is_contiguous() and search.shape == X.shape
+        assert search.is_cuda and search.shape == X.shape and search.stride() == X.stride()
         v.search_dtype = BF16 if search.dtype == torch.bfloat16 else F16
         assert search.dtype in (torch.bfloat16, torch.float16)
         v.search = search.data_ptr()
@@ -143,7 +158,7 @@ def _vectors(X, search=None):
 
 def merge(subs, X, R, L, alpha, metric=L2SQ, search=None, k=0, kplus=0, ef_naive=0,
           ef_slide=0, mos_degree=0, mos_diameter=0, flags=0, dists=True, stream=None,
-          out=None, search_shape=None):
+          out=None, search_shape=None, max_device_bytes=0):
     """Merge sub-indexes. subs: list of (offsets int64, nbrs int32, entry) device
     tensors with local ids, in global-id order over the rows of X (float32
     device [N, dim]). search: optional bf16/f16 copy of X that the searches
@@ -168,12 +183,54 @@ def merge(subs, X, R, L, alpha, metric=L2SQ, search=None, k=0, kplus=0, ef_naive
               dists=None if o_d is None else o_d.data_ptr())
     p = Params(R=R, L=L, alpha=float(alpha), metric=metric, k_reverse=k, k_expand=kplus,
                ef_naive=ef_naive, ef_slide=ef_slide, mos_degree=mos_degree,
-               mos_diameter=mos_diameter, flags=flags, stream=_stream(stream))
+               mos_diameter=mos_diameter, flags=flags, stream=_stream(stream),
+               max_device_bytes=int(max_device_bytes))
     if search_shape is not None:
         p.search_hash_bits, p.search_waves_per_block = (int(x) for x in search_shape)
     _check(lib().rnsm_merge(m, gs, C.byref(v), C.byref(p), C.byref(csr)))
     ne = int(csr.n_edges)
     return o_off, o_nb[:ne], (None if o_d is None else o_d[:ne]), int(csr.entry)
+
+
+def merge_host(subs, X, R, L, alpha, metric=L2SQ, search=None, flags=0, **kw):
+    """Merge from host (numpy) inputs into library-allocated host output:
+    graphs and rows with mem = RNSM_HOST, RNSM_FLAG_HOST_OUT, the arrays
+    copied out and released with rnsm_csr_free. subs: list of (offsets int64,
+    nbrs int32, entry) numpy arrays; X: float32 [N, dim] (any row stride);
+    search: optional numpy bfloat16-bits (uint16) / float16 copy of X.
+    Returns (offsets, nbrs, dists, entry) numpy arrays (global ids)."""
+    import numpy as np
+    m = len(subs)
+    keep = []
+    gs = (Graph * m)()
+    for i, (o, nb, e) in enumerate(subs):
+        o = np.ascontiguousarray(o, dtype=np.int64)
+        nb = np.ascontiguousarray(nb, dtype=np.int32)
+        keep += [o, nb]
+        gs[i] = Graph(n=o.shape[0] - 1, offsets=o.ctypes.data, nbrs=nb.ctypes.data if nb.size else None,
+                      entry=int(e), mem=HOST)
+    assert X.dtype == np.float32 and X.ndim == 2 and X.strides[1] == 4
+    v = Vectors(n=X.shape[0], dim=X.shape[1], f32=X.ctypes.data, search_dtype=F32, search=None,
+                row_stride=X.strides[0] // 4, mem=HOST)
+    if search is not None:
+        assert search.shape == X.shape and search.strides[1] == 2
+        assert search.strides[0] // 2 == X.strides[0] // 4
+        v.search_dtype = F16 if search.dtype == np.float16 else BF16
+        v.search = search.ctypes.data
+    p = Params(R=R, L=L, alpha=float(alpha), metric=metric, flags=flags | FLAG_HOST_OUT,
+               stream=_stream(kw.pop("stream", None)), **kw)
+    csr = Csr()
+    _check(lib().rnsm_merge(m, gs, C.byref(v), C.byref(p), C.byref(csr)))
+    try:
+        assert csr.mem == HOST
+        N = X.shape[0]
+        ne = int(csr.n_edges)
+        off = np.ctypeslib.as_array((C.c_int64 * (N + 1)).from_address(csr.offsets)).copy()
+        nb = np.ctypeslib.as_array((C.c_int32 * max(ne, 1)).from_address(csr.nbrs))[:ne].copy()
+        ds = np.ctypeslib.as_array((C.c_float * max(ne, 1)).from_address(csr.dists))[:ne].copy()
+        return off, nb, ds, int(csr.entry)
+    finally:
+        lib().rnsm_csr_free(C.byref(csr))
 
 
 def merge_simple(subs, X, R, L, alpha, stream=None):

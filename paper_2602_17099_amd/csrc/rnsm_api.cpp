@@ -52,7 +52,27 @@ struct Workspace {
     struct Buf {
         void* p = nullptr;
         size_t bytes = 0;
+        uint64_t call = 0;  // the call that last requested it
+        size_t need = 0;    // the largest size that call requested
     };
+    // Per call (begin_call): the device bytes the call's own buffers need
+    // (each named buffer counted once, at the largest size the call asks
+    // for), checked against the caller's budget before any allocation; and
+    // the allocation-failure injector: with RNSM_FAIL_ALLOC=k the call's k-th
+    // buffer request (device or pinned host) fails as out of memory, before
+    // anything is allocated (for tests of the error paths).
+    uint64_t call_id = 0;
+    size_t call_bytes = 0, budget = 0;
+    int64_t requests = 0, fail_at = 0;
+    void begin_call(int64_t max_device_bytes) {
+        ++call_id;
+        call_bytes = 0;
+        budget = max_device_bytes > 0 ? (size_t)max_device_bytes : 0;
+        requests = 0;
+        const char* f = getenv("RNSM_FAIL_ALLOC");
+        fail_at = f ? atoll(f) : 0;
+    }
+    bool inject_failure() { return ++requests == fail_at; }
     std::map<std::string, Buf> bufs, hbufs;
     GainLevels levels;  // lazy-greedy gain levels, storage kept between calls
     // second stream (default priority) for the naive searches of the pivot
@@ -70,7 +90,8 @@ struct Workspace {
         return hipSuccess;
     }
     // pinned host staging buffers (hipHostMalloc), kept like the device ones
-    hipError_t hget(const char* name, size_t bytes, void** out) {
+    hipError_t hget(const std::string& name, size_t bytes, void** out) {
+        if (inject_failure()) return hipErrorOutOfMemory;
         Buf& b = hbufs[name];
         if (bytes == 0) bytes = 16;
         if (b.bytes < bytes) {
@@ -87,9 +108,16 @@ struct Workspace {
         *out = b.p;
         return hipSuccess;
     }
-    hipError_t get(const char* name, size_t bytes, void** out) {
+    hipError_t get(const std::string& name, size_t bytes, void** out) {
+        if (inject_failure()) return hipErrorOutOfMemory;
         Buf& b = bufs[name];
         if (bytes == 0) bytes = 16;
+        const size_t prev = b.call == call_id ? b.need : 0;
+        const size_t need = std::max(prev, bytes);
+        if (budget && call_bytes - prev + need > budget) return hipErrorOutOfMemory;
+        call_bytes = call_bytes - prev + need;
+        b.call = call_id;
+        b.need = need;
         if (b.bytes < bytes) {
             if (b.p) {
                 hipError_t e = hipFree(b.p);
@@ -204,14 +232,81 @@ rnsm_status vec_info(const rnsm_vectors* v, VecInfo& vi) {
     return RNSM_OK;
 }
 
+// Staging of inputs (the first step of the path): the kernels read device
+// CSR and packed device rows, so graphs in host memory, and rows in host
+// memory or with a row stride, are first copied into workspace buffers.
+rnsm_status stage_graph(Workspace& ws, const char* fn, int idx, const rnsm_graph& g,
+                        hipStream_t st, rnsm_graph& out) {
+    out = g;
+    out.mem = RNSM_DEVICE;
+    if (g.mem == RNSM_DEVICE) return RNSM_OK;
+    if (g.mem != RNSM_HOST) return fail(RNSM_EINVAL, "%s: graph %d: unknown memspace", fn, idx);
+    if (!g.offsets) return fail(RNSM_EINVAL, "%s: graph %d has a NULL CSR pointer", fn, idx);
+    const int64_t nnz = g.offsets[g.n];
+    if (g.offsets[0] != 0 || nnz < 0)
+        return fail(RNSM_EINVAL, "%s: graph %d: offsets[0] != 0 or offsets[n] < 0", fn, idx);
+    if (nnz > 0 && !g.nbrs) return fail(RNSM_EINVAL, "%s: graph %d has a NULL CSR pointer", fn, idx);
+    int64_t* o;
+    int32_t* nb;
+    const std::string tag = std::to_string(idx);
+    WS(o, "in_offsets_" + tag, sizeof(int64_t) * (g.n + 1));
+    WS(nb, "in_nbrs_" + tag, sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    HIPCHK(hipMemcpyAsync(o, g.offsets, sizeof(int64_t) * (g.n + 1), hipMemcpyHostToDevice, st));
+    if (nnz > 0)
+        HIPCHK(hipMemcpyAsync(nb, g.nbrs, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+    out.offsets = o;
+    out.nbrs = nnz > 0 ? nb : nullptr;
+    return RNSM_OK;
+}
+
+// rows of v packed on the device (out.row_stride = 0, out.mem = device);
+// v.dim, v.f32 and the search copy were checked by vec_info
+rnsm_status stage_vectors(Workspace& ws, const char* fn, const rnsm_vectors& v, hipStream_t st,
+                          rnsm_vectors& out) {
+    out = v;
+    out.mem = RNSM_DEVICE;
+    out.row_stride = 0;
+    if (v.mem != RNSM_DEVICE && v.mem != RNSM_HOST)
+        return fail(RNSM_EINVAL, "%s: vectors: unknown memspace", fn);
+    const int64_t stride = v.row_stride ? v.row_stride : v.dim;
+    if (stride < v.dim) return fail(RNSM_EINVAL, "%s: vectors: row_stride < dim", fn);
+    if (v.mem == RNSM_DEVICE && stride == v.dim) return RNSM_OK;
+    const hipMemcpyKind kind = v.mem == RNSM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    auto copy_rows = [&](void* dst, const void* src, size_t esz) -> hipError_t {
+        if (stride == v.dim)
+            return hipMemcpyAsync(dst, src, esz * v.dim * v.n, kind, st);
+        return hipMemcpy2DAsync(dst, esz * v.dim, src, esz * stride, esz * v.dim, v.n, kind, st);
+    };
+    float* f;
+    WS(f, "in_f32", sizeof(float) * v.n * v.dim);
+    HIPCHK(copy_rows(f, v.f32, sizeof(float)));
+    out.f32 = f;
+    if (v.search_dtype != RNSM_F32) {
+        void* sc;
+        WS(sc, "in_search", (size_t)2 * v.n * v.dim);
+        HIPCHK(copy_rows(sc, v.search, 2));
+        out.search = sc;
+    }
+    return RNSM_OK;
+}
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 struct Events {
     std::vector<hipEvent_t> ev;
+    bool no_stats = false;  // RNSM_FLAG_NO_STATS: stat() records nothing
     ~Events() {
         for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    // an event that only times a phase for rnsm_get_stats (index -1 when skipped)
+    hipError_t stat(hipStream_t st, int* idx) {
+        if (no_stats) {
+            *idx = -1;
+            return hipSuccess;
+        }
+        return record(st, idx);
     }
     hipError_t record(hipStream_t st, int* idx) {
         hipEvent_t e;
@@ -395,7 +490,10 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     // ---------------------------------------------------- host argument checks
     if (m < 2) return fail(RNSM_EINVAL, "rnsm_merge: m = %d < 2", m);
     if (!graphs || !vecs || !p || !out) return fail(RNSM_EINVAL, "rnsm_merge: NULL argument");
-    if (!out->offsets || !out->nbrs) return fail(RNSM_EINVAL, "rnsm_merge: NULL output buffer");
+    const bool host_out = (p->flags & RNSM_FLAG_HOST_OUT) != 0;
+    if (!host_out && (!out->offsets || !out->nbrs))
+        return fail(RNSM_EINVAL, "rnsm_merge: NULL output buffer");
+    if (p->max_device_bytes < 0) return fail(RNSM_EINVAL, "rnsm_merge: max_device_bytes < 0");
     const int R = p->R;
     if (R < 1 || R > 64) return fail(RNSM_EINVAL, "rnsm_merge: R = %d outside 1..64", R);
     if (p->L < 1 || p->L > 128) return fail(RNSM_EINVAL, "rnsm_merge: L = %d outside 1..128", p->L);
@@ -447,7 +545,29 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     Workspace& ws = g_ws[dev];
+    ws.begin_call(p->max_device_bytes);
     Events E;
+    E.no_stats = (p->flags & RNSM_FLAG_NO_STATS) != 0;
+
+    // ------------------------------------------------------ input staging
+    // host or strided inputs to packed device buffers; from here on the
+    // graphs and vectors are device memory
+    std::vector<rnsm_graph> gstaged(m);
+    for (int i = 0; i < m; ++i) {
+        const rnsm_status ss = stage_graph(ws, "rnsm_merge", i, graphs[i], st, gstaged[i]);
+        if (ss != RNSM_OK) return ss;
+    }
+    rnsm_vectors vstaged;
+    {
+        const rnsm_status ss = stage_vectors(ws, "rnsm_merge", *vecs, st, vstaged);
+        if (ss != RNSM_OK) return ss;
+    }
+    graphs = gstaged.data();
+    vecs = &vstaged;
+    {
+        const rnsm_status ss = vec_info(vecs, vi);
+        if (ss != RNSM_OK) return ss;
+    }
 
     // ------------------------------------------------ input graph validation
     int* vflags;
@@ -714,7 +834,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                 if (bs != RNSM_OK) return bs;
             }
             std::array<int, 3> ex;
-            HIPCHK(E.record(st, &ex[0]));
+            HIPCHK(E.stat(st, &ex[0]));
             SearchArgs a = {};
             a.base = vi.search + bases[s] * vi.row_bytes;
             a.nch = vi.nch;
@@ -753,7 +873,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                 a.row_d_stride = R;
             }
             HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
-            HIPCHK(E.record(st, &ex[1]));
+            HIPCHK(E.stat(st, &ex[1]));
             // the greedy's gain levels, made on the device from the list
             // lengths, go to the host first; offsets and ids follow
             HIPCHK(launch_count_ids(nk, ns, k, rcnt, st));
@@ -776,7 +896,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
             }
             HIPCHK(E.record(st, &ev_rk_cnt));
             HIPCHK(launch_invert_lists(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
-            HIPCHK(E.record(st, &ex[2]));
+            HIPCHK(E.stat(st, &ex[2]));
             ev_exp.push_back(ex);
             g_stats.queries[0] += ns;
             g_stats.launches[0] += 1;
@@ -1037,20 +1157,20 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
             if (!chk(hipMemcpyAsync(d_order + o0, h_order + o0, sizeof(int32_t) * (np + nf - o0),
                                     hipMemcpyHostToDevice, sd)))
                 return;
-            if (!chk(E.record(sd, &ce[0]))) return;
+            if (!chk(E.stat(sd, &ce[0]))) return;
             SearchArgs x = aA;
             x.qidx = d_piv + pa;
             x.out_row = x.qidx;
             x.nq = np - pa;
             if (!chk(launch_search(vi.tt, x, shA.wpb, sd)) || !chk(E.record(sd, &ce[1]))) return;
             if (!chk(hipStreamWaitEvent(st, E.ev[ce[1]], 0))) return;
-            if (!chk(E.record(st, &ce[2]))) return;
+            if (!chk(E.stat(st, &ce[2]))) return;
             SearchArgs y = aB;
             y.qidx = d_fol + fa;
             y.out_row = y.qidx;
             y.seed_row = d_folp + fa;
             y.nq = nf - fa;
-            if (!chk(launch_search(vi.tt, y, shB.wpb, st)) || !chk(E.record(st, &ce[3]))) return;
+            if (!chk(launch_search(vi.tt, y, shB.wpb, st)) || !chk(E.stat(st, &ce[3]))) return;
             ev_chunk.push_back(ce);
             if (th_first_launch < 0) th_first_launch = ms_since(th1);
             n_launch_a += np > pa;  // the stats are thread-local: added after the join
@@ -1190,7 +1310,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
         // source prune, in the order staged with the chunks (the copies on
         // the side stream precede the last sliding search, which st waited for)
         std::array<int, 2> pe;
-        HIPCHK(E.record(st, &pe[0]));
+        HIPCHK(E.stat(st, &pe[0]));
         // reverse edges into the target (counted by the source prune), then
         // prune every target that got some
         int32_t *rc, *rcur, *rev;
@@ -1232,7 +1352,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
         r.wcap = TARGET_WCAP;
         r.rev_cnt = nullptr;
         HIPCHK(run_prune(r, pmode, st));
-        HIPCHK(E.record(st, &pe[1]));
+        HIPCHK(E.stat(st, &pe[1]));
         ev_prune.push_back(pe);
         HIPCHK(hipMemcpyAsync(h_nrev + oi, roff + nt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         g_stats.n_followers += nf;
@@ -1242,26 +1362,74 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     }
 
     // ----------------------------------------------------------- compaction
+    // into the caller's device buffers, or (host output) into workspace
+    // buffers that are copied to library-allocated host arrays below
+    int64_t* o_off = out->offsets;
+    int32_t* o_nbrs = out->nbrs;
+    float* o_dists = out->dists;
+    if (host_out) {
+        WS(o_off, "out_offsets", sizeof(int64_t) * (N + 1));
+        WS(o_nbrs, "out_nbrs", sizeof(int32_t) * N * R);
+        WS(o_dists, "out_dists", sizeof(float) * N * R);
+    }
     int c0, c1;
-    HIPCHK(E.record(st, &c0));
+    HIPCHK(E.stat(st, &c0));
     int64_t* stmp3;
     WS(stmp3, "scan_tmp3", sizeof(int64_t) * scan_tmp_elems(N));
-    HIPCHK(launch_scan(deg, N, out->offsets, stmp3, st));
+    HIPCHK(launch_scan(deg, N, o_off, stmp3, st));
     if (p->metric != RNSM_L2SQ && !norms64) {
         WS(norms64, "norms64", sizeof(double) * N);
         HIPCHK(launch_norms(vecs->f32, N, vecs->dim, nullptr, st, norms64));
     }
-    HIPCHK(launch_compact(rows, deg, rdist, out->offsets, N, R, vecs->f32, vecs->dim, p->metric,
-                          norms, out->nbrs, out->dists, st, norms64));
-    HIPCHK(E.record(st, &c1));
+    HIPCHK(launch_compact(rows, deg, rdist, o_off, N, R, vecs->f32, vecs->dim, p->metric,
+                          norms, o_nbrs, o_dists, st, norms64));
+    HIPCHK(E.stat(st, &c1));
     int64_t nedges = 0;
     std::vector<u64> hslots(3 * CNT_SLOTS * CNT_N);
     u64 hc[3 * CNT_N] = {};
     int herr = 0;
-    HIPCHK(hipMemcpyAsync(&nedges, out->offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hslots.data(), cnt, sizeof(u64) * hslots.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&nedges, o_off + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (!E.no_stats)
+        HIPCHK(hipMemcpyAsync(hslots.data(), cnt, sizeof(u64) * hslots.size(),
+                              hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (host_out) {
+        // host arrays owned by the caller from here on (rnsm_csr_free);
+        // released again if anything below fails
+        struct HostCsr {
+            int64_t* off = nullptr;
+            int32_t* nb = nullptr;
+            float* d = nullptr;
+            ~HostCsr() {
+                free(off);
+                free(nb);
+                free(d);
+            }
+        } h;
+        h.off = (int64_t*)malloc(sizeof(int64_t) * (N + 1));
+        h.nb = (int32_t*)malloc(sizeof(int32_t) * std::max<int64_t>(nedges, 1));
+        h.d = (float*)malloc(sizeof(float) * std::max<int64_t>(nedges, 1));
+        if (!h.off || !h.nb || !h.d)
+            return fail(RNSM_ENOMEM, "rnsm_merge: host output allocation failed");
+        HIPCHK(hipMemcpyAsync(h.off, o_off, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost, st));
+        if (nedges > 0) {
+            HIPCHK(hipMemcpyAsync(h.nb, o_nbrs, sizeof(int32_t) * nedges, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(h.d, o_dists, sizeof(float) * nedges, hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (!(herr & 3)) {
+            out->offsets = h.off;
+            out->nbrs = h.nb;
+            out->dists = h.d;
+            out->mem = RNSM_HOST;
+            h.off = nullptr;
+            h.nb = nullptr;
+            h.d = nullptr;
+        }
+    } else {
+        out->mem = RNSM_DEVICE;
+    }
     for (int ph = 0; ph < 3; ++ph)
         for (int sl = 0; sl < CNT_SLOTS; ++sl)
             for (int c = 0; c < CNT_N; ++c) hc[ph * CNT_N + c] += hslots[(ph * CNT_SLOTS + sl) * CNT_N + c];
@@ -1424,6 +1592,14 @@ static rnsm_status rnsm_search_impl(const rnsm_graph* g, const rnsm_vectors* bas
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     Workspace& ws = g_ws[dev];
+    ws.begin_call(0);
+    rnsm_graph gs;
+    rnsm_vectors vs2;
+    if ((vs = stage_graph(ws, "rnsm_search", 0, *g, st, gs)) != RNSM_OK) return vs;
+    if ((vs = stage_vectors(ws, "rnsm_search", *base, st, vs2)) != RNSM_OK) return vs;
+    if ((vs = vec_info(&vs2, vi)) != RNSM_OK) return vs;
+    g = &gs;
+    base = &vs2;
     SearchBufs b;
     WS(b.cnt, "search_counters", sizeof(u64) * CNT_SLOTS * CNT_N);
     WS(b.errf, "search_err", sizeof(int));
@@ -1582,6 +1758,10 @@ static rnsm_status rnsm_search_noalloc_impl(const rnsm_graph* g, const rnsm_vect
     rnsm_status vs = search_check("rnsm_search_noalloc", g, base, queries, nq, seeds, n_seeds, ef,
                                   k, metric, out_ids, vi);
     if (vs != RNSM_OK) return vs;
+    if (g->mem != RNSM_DEVICE || base->mem != RNSM_DEVICE ||
+        (base->row_stride != 0 && base->row_stride != base->dim))
+        return fail(RNSM_EUNSUPPORTED,
+                    "rnsm_search_noalloc: graph and rows must be packed device memory");
     const NoallocLayout l = noalloc_layout(g->n, nq, metric);
     if (l.total > NOALLOC_SCRATCH_BYTES)
         return fail(RNSM_EINVAL,
@@ -1621,7 +1801,17 @@ static rnsm_status rnsm_tune_search_impl(const rnsm_graph* g, const rnsm_vectors
     rnsm_status vs = vec_info(base, vi);
     if (vs != RNSM_OK) return vs;
     std::lock_guard<std::mutex> lk(g_lock);
-    return tune_shape_locked(g, base, vi, ef, metric, n_sample, 32, out, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    Workspace& ws = g_ws[dev];
+    ws.begin_call(0);
+    rnsm_graph gs;
+    rnsm_vectors vs2;
+    if ((vs = stage_graph(ws, "rnsm_tune_search", 0, *g, st, gs)) != RNSM_OK) return vs;
+    if ((vs = stage_vectors(ws, "rnsm_tune_search", *base, st, vs2)) != RNSM_OK) return vs;
+    if ((vs = vec_info(&vs2, vi)) != RNSM_OK) return vs;
+    return tune_shape_locked(&gs, &vs2, vi, ef, metric, n_sample, 32, out, st);
 }
 
 static rnsm_status rnsm_build_graph_impl(int64_t n, const float* X, int32_t dim, rnsm_metric metric,
@@ -1643,6 +1833,7 @@ static rnsm_status rnsm_build_graph_impl(int64_t n, const float* X, int32_t dim,
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     Workspace& ws = g_ws[dev];
+    ws.begin_call(0);
     int32_t *rows1, *deg1, *rows2, *deg2, *rc, *rcur, *rev, *errf;
     float *d1, *d2, *norms = nullptr;
     int64_t *roff, *stmp;
@@ -1793,6 +1984,14 @@ extern "C" {
 rnsm_status rnsm_convert(const void* src, rnsm_dtype src_type, void* dst, rnsm_dtype dst_type,
                          int64_t count, void* stream) {
     return guard("rnsm_convert", [&] { return rnsm_convert_impl(src, src_type, dst, dst_type, count, stream); });
+}
+
+void rnsm_csr_free(rnsm_csr* g) {
+    if (!g || g->mem != RNSM_HOST) return;
+    free(g->offsets);
+    free(g->nbrs);
+    free(g->dists);
+    memset(g, 0, sizeof *g);
 }
 
 rnsm_status rnsm_get_stats(rnsm_stats* out) {

@@ -23,7 +23,7 @@ def pkg():
 
 def test_exports_every_declared_symbol(pkg):
     hdr = open(os.path.join(ROOT, "include", "rnsm.h")).read()
-    names = set(re.findall(r"^\s*(?:rnsm_status|const char\*)\s+(\w+)\s*\(", hdr, re.M))
+    names = set(re.findall(r"^\s*(?:rnsm_status|const char\*|void)\s+(\w+)\s*\(", hdr, re.M))
     assert names == set(pkg.SYMBOLS)
     L = C.CDLL(pkg.LIB_PATH)
     for n in names:
@@ -53,6 +53,13 @@ def test_merge_rejects_bad_arguments_on_host(pkg):
         setattr(q, field, val)
         assert L.rnsm_merge(2, g, C.byref(v), C.byref(q), C.byref(out)) == 1, field
         assert field in pkg.last_error()
+    q = pkg.Params(R=16, L=32, alpha=1.2, max_device_bytes=-1)
+    assert L.rnsm_merge(2, g, C.byref(v), C.byref(q), C.byref(out)) == 1
+    assert "max_device_bytes" in pkg.last_error()
+    # host output needs no output buffers; the other checks still run
+    q = pkg.Params(R=16, L=32, alpha=1.2, flags=pkg.FLAG_HOST_OUT)
+    assert L.rnsm_merge(2, g, C.byref(v), C.byref(q), C.byref(pkg.Csr())) == 1
+    assert "f32 is NULL" in pkg.last_error()
     # vectors
     assert L.rnsm_merge(2, g, C.byref(v), C.byref(p), C.byref(out)) == 1
     assert "f32 is NULL" in pkg.last_error()
@@ -283,4 +290,16 @@ def test_search_noalloc_rejects_on_host(pkg):
             C.c_void_p(8), None, None]
     assert L.rnsm_search_noalloc(*args) == 1
     assert "scratch" in pkg.last_error()
+
+
+def test_csr_free_only_releases_library_arrays(pkg):
+    # NULL and caller-owned device buffers are left alone
+    L = pkg.lib()
+    L.rnsm_csr_free(None)
+    dev = pkg.Csr(offsets=8, nbrs=16, dists=24, entry=3, n_edges=5, mem=pkg.DEVICE)
+    L.rnsm_csr_free(C.byref(dev))
+    assert (dev.offsets, dev.nbrs, dev.dists, dev.entry, dev.n_edges) == (8, 16, 24, 3, 5)
+    empty = pkg.Csr(mem=pkg.HOST)  # host arrays, all NULL: free(NULL) is a no-op
+    L.rnsm_csr_free(C.byref(empty))
+    assert empty.mem == pkg.DEVICE and not empty.offsets
 
