@@ -26,25 +26,17 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
-# HBM traffic of the k_beam_search launches of one timed merge, from two
-# rocprofv3 --pmc passes over `bench.py --steps 1 --warmup 0 --no-cpu-baseline
-# --no-bf16 --no-recall` (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
-# each scaled by what the counter reads for a plain 1 GiB device copy
-# (FETCH_SIZE 0.5 GiB: factor 2.0; WRITE_SIZE 1 GiB: factor 1.0). The figures
-# hold for the sources they were taken on only (sha256 of the files below).
+# HBM traffic of the k_beam_search launches of one merge, from two rocprofv3
+# --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch) over
+# `bench.py --one-stream --steps 1 --warmup 0 --no-cpu-baseline --no-recall`
+# with --no-bf16 (float32 rows) or --bf16-only (bfloat16 copy), each counter
+# scaled by what it reads for a plain 1 GiB device copy (FETCH_SIZE reads
+# 0.5 GiB: factor 2.0; WRITE_SIZE 1 GiB: factor 1.0). The figures hold for the
+# sources they were taken on only (sha256 of the files below); otherwise the
+# line's traffic is null and its roofline falls back to algorithmic bytes.
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
-SEARCH_COUNTERS = {
-    "sources_sha256": "bad3af8b4de8a677e0fa4f9a4d1a52dbe0c872326958ae09153a2e8e7e32c4b2",
-    "fetch_kib": [
-        28927148.625, 30086.375, 2508022.312, 107937.25, 5778242.125, 531066.375, 14852761.375,
-        1991948.75, 19702611.188, 18858656.25, 18569737.562, 11661523.562
-    ],
-    "write_kib": [
-        174345.312, 48.125, 19571.875, 193.125, 38870.0, 970.625, 77168.125, 3530.625, 74595.625,
-        32081.875, 46043.125, 19426.875
-    ],
-}
+SEARCH_COUNTERS = {}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
@@ -57,14 +49,46 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def search_traffic():
-    """Measured HBM bytes per k_beam_search launch, or None when the counters
-    were taken on other sources."""
-    c = SEARCH_COUNTERS
+def search_traffic(form="fp32"):
+    """Measured HBM bytes per k_beam_search launch of the form (fp32, bf16),
+    or None when the counters were taken on other sources."""
+    c = SEARCH_COUNTERS.get(form)
     if not c or c["sources_sha256"] != sources_sha256():
         return None
     tot = sum(c["fetch_kib"]) * FETCH_FACTOR + sum(c["write_kib"]) * WRITE_FACTOR
     return tot * 1024.0 / len(c["fetch_kib"])
+
+
+def roofline_line(alg_bytes_per_launch, ms_per_launch, launches_per_step, ms_per_step,
+                  traffic_per_launch, peak=None):
+    """The line's roofline of the search kernel. Time base: the exclusive
+    launch time (each launch alone on the stream, HIP events on that stream).
+    achieved / frac: measured HBM bytes (counters) per launch over that time
+    when the counters match the sources, else the algorithmic bytes (basis
+    says which). The algorithmic rate is reported beside it; it counts the
+    re-reads that L2 and the Infinity Cache serve, so where it passes the HBM
+    peak (per launch, or as algorithmic bytes per step over the whole step
+    time) the line says cache_served."""
+    peak = PEAK_HBM_GBS if peak is None else peak
+    alg_gbs = alg_bytes_per_launch / (ms_per_launch * 1e6)
+    step_gbs = alg_bytes_per_launch * launches_per_step / (ms_per_step * 1e6)
+    if traffic_per_launch is not None:
+        achieved, basis = traffic_per_launch / (ms_per_launch * 1e6), "hbm_counters"
+    else:
+        achieved, basis = alg_gbs, "algorithmic"
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": round(traffic_per_launch) if traffic_per_launch is not None else None,
+            "basis": basis,
+            "algorithmic_gbs": round(alg_gbs, 1), "algorithmic_frac": round(alg_gbs / peak, 4),
+            "algorithmic_step_gbs": round(step_gbs, 1),
+            "cache_served": bool(alg_gbs > peak or step_gbs > peak or
+                                 (traffic_per_launch is not None and
+                                  traffic_per_launch < alg_bytes_per_launch)),
+            "bytes_per_launch": alg_bytes_per_launch, "ms_per_launch": ms_per_launch,
+            "launches_per_step": launches_per_step,
+            "time_base": "exclusive launch time: every search launch alone on one stream "
+                         "(RNSM_ONE_STREAM=1 pass), HIP events on that stream"}
 
 WORKLOADS = {
     "fp32-2x500k": dict(n=500_000, dim=128, R=32, L=64, alpha=1.2, K=64, nq=10_000,
@@ -370,43 +394,57 @@ def exact_ndc(pkg, subs, Xd, wl, search=None):
     return st["ndc"]
 
 
-def search_roofline(agg, st, ndc_exact, steps):
-    """Algorithmic bytes of the k_beam_search launches (expansion, naive,
-    sliding) over their event-timed durations; re-evaluations caused by the
-    forgetful visited table are not counted as algorithmic bytes. Naive and
-    sliding launches overlap on two streams, so their event durations add up
-    to more than the device time they take together (span_gbs uses that)."""
+def search_roofline(agg, st, ndc_exact, steps, ms_per_step, form="fp32"):
+    """Roofline of the k_beam_search launches (expansion, naive, sliding) of
+    merges timed with every launch alone on one stream (agg from an
+    RNSM_ONE_STREAM=1 pass): algorithmic bytes (re-evaluations caused by the
+    forgetful visited table not counted) and, when the counters match the
+    sources, measured HBM bytes, over the exclusive launch time."""
     rb = st["row_bytes"]
     tot_b = tot_ms = 0.0
     per = {}
-    b_ph = []
     for ph in range(3):
         extra = agg["ndc"][ph] - steps * ndc_exact[ph]
         b = agg["bytes"][ph] - extra * rb
-        b_ph.append(b)
-        per[PHASES[ph]] = {"gbs": b / (agg["ms"][ph] * 1e6) if agg["ms"][ph] else None,
+        per[PHASES[ph]] = {"algorithmic_gbs": b / (agg["ms"][ph] * 1e6) if agg["ms"][ph] else None,
                            "ms_per_launch": agg["ms"][ph] / max(1, agg["launches"][ph]),
+                           "launches_per_step": agg["launches"][ph] / steps,
                            "ndc_inflation": agg["ndc"][ph] / max(1, steps * ndc_exact[ph])}
         tot_b += b
         tot_ms += agg["ms"][ph]
     launches = sum(agg["launches"])
-    achieved = tot_b / (tot_ms * 1e6)
-    span = agg["span_ms"]
-    tr = search_traffic()
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": round(tr) if tr is not None else None,
-            "kernel": "k_beam_search (expansion, naive and sliding launches)",
-            "bytes_per_launch": tot_b / launches, "ms_per_launch": tot_ms / launches,
-            "launches_per_step": launches / steps,
-            "span_gbs": round((b_ph[1] + b_ph[2]) / (span * 1e6), 1) if span else None,
-            "per_phase": per}
+    r = roofline_line(tot_b / launches, tot_ms / launches, launches / steps, ms_per_step,
+                      search_traffic(form))
+    r["kernel"] = "k_beam_search (expansion, naive and sliding launches)"
+    r["per_phase"] = per
+    return r
+
+
+def host_cores():
+    """Threads the oracle may use: OMP_NUM_THREADS where set (the CPU share of
+    the machine), else the CPUs this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(wl):
     """The oracle's full merge on a replica of the workload with 1/8 of the
     vectors per sub-index (same distribution, dim and parameters; sub-indexes
-    built by the oracle), single-threaded."""
+    built by the oracle), timed on one thread and on all the host cores it may
+    use (its searches and prunes of independent vertices spread over them)."""
     from oracle import oracle as O
     from paper_2602_17099_amd import inputs
     n = max(1000, wl["n"] // 8)
@@ -416,13 +454,23 @@ def cpu_baseline(wl):
         X = inputs.tiny_int(2 * n, wl["dim"], seed=inputs.SEED_BASE + 1)
     subs = [O.build_graph(X[i * n:(i + 1) * n], wl["K"], wl["R"], alpha=wl["build_alpha"],
                           reverse=wl["reverse"], alpha_rev=1.2) for i in range(2)]
-    t0 = time.perf_counter()
-    O.merge(subs, X, R=wl["R"], L=wl["L"], alpha=wl["alpha"])
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "merged vertices/s", "cores": 1, "kind": "oracle",
+    cores = host_cores()
+    times = {}
+    prev = O.get_threads()
+    try:
+        for t in (1, cores):
+            O.set_threads(t)
+            t0 = time.perf_counter()
+            O.merge(subs, X, R=wl["R"], L=wl["L"], alpha=wl["alpha"])
+            times[t] = time.perf_counter() - t0
+    finally:
+        O.set_threads(prev)
+    return {"value": n / times[cores], "unit": "merged vertices/s", "cores": cores,
+            "kind": "oracle", "value_1_core": n / times[1], "cpu_model": cpu_model(),
+            "nproc": os.cpu_count(),
             "sample": f"full oracle merge of a 2 x {n} replica (same distribution, dim "
-                      f"{wl['dim']}, R={wl['R']}, L={wl['L']}, alpha={wl['alpha']}), "
-                      f"{dt:.1f} s single-threaded"}
+                      f"{wl['dim']}, R={wl['R']}, L={wl['L']}, alpha={wl['alpha']}): "
+                      f"{times[cores]:.1f} s on {cores} threads, {times[1]:.1f} s on 1"}
 
 
 def main():
@@ -450,7 +498,14 @@ def main():
                          "4,000,000 vectors (float32 and bfloat16 search copies)")
     ap.add_argument("--calib-only", action="store_true",
                     help="only copy 1 GiB device to device (counter calibration) and exit")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="every search launch alone on one stream for the whole run (for "
+                         "profiles and counters: kernel times are then exclusive)")
+    ap.add_argument("--bf16-only", action="store_true",
+                    help="only the bfloat16 form's merges (profiles and counters of its kernels)")
     args = ap.parse_args()
+    if args.one_stream:
+        os.environ["RNSM_ONE_STREAM"] = "1"
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -493,20 +548,49 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read, 1 GiB written")
 
+    def exclusive(search, dt_main, agg_main, st_main, steps_main):
+        """Merges with every search launch alone on one stream, for the
+        roofline's exclusive launch times (the run's own merges when it is
+        one-stream already)."""
+        if args.one_stream:
+            return agg_main, st_main, steps_main
+        ex_steps = max(1, min(args.steps, 3))
+        os.environ["RNSM_ONE_STREAM"] = "1"
+        try:
+            _, agg_x, st_x, _ = time_merges(pkg, subs, Xd, wl, ex_steps, 1, search=search)
+        finally:
+            del os.environ["RNSM_ONE_STREAM"]
+        return agg_x, st_x, ex_steps
+
+    gt = None
+    if wl["nq"] and not args.no_recall:
+        from paper_2602_17099_amd.prepare import knn_l2_exact
+        gt = knn_l2_exact(Xd, Qd, 10)
+
+    if args.bf16_only:
+        Xb = pkg.convert(Xd, torch.bfloat16)
+        ndc_b = exact_ndc(pkg, subs, Xd, wl, search=Xb)
+        dtb, aggb, stb, _ = time_merges(pkg, subs, Xd, wl, args.steps, args.warmup, search=Xb)
+        ms_b = 1000.0 * dtb / args.steps
+        aggx, stx, sx = exclusive(Xb, dtb, aggb, stb, args.steps)
+        print(json.dumps({"bf16_form": {"value": args.steps * stb["n_source_vertices"] / dtb,
+                                        "ms_per_step": ms_b,
+                                        "roofline": search_roofline(aggx, stx, ndc_b, sx, ms_b,
+                                                                    "bf16")}}), flush=True)
+        return
+
     ndc_x = exact_ndc(pkg, subs, Xd, wl)
     dt, agg, st, res = time_merges(pkg, subs, Xd, wl, args.steps, args.warmup)
     n_src = st["n_source_vertices"]
     value = args.steps * n_src / dt
     ms_step = 1000.0 * dt / args.steps
     log(f"fp32: {ms_step:.2f} ms/step, {value / 1e6:.3f} M merged vertices/s; stats {st}")
-    roof = search_roofline(agg, st, ndc_x, args.steps)
+    aggx, stx, sx = exclusive(None, dt, agg, st, args.steps)
+    roof = search_roofline(aggx, stx, ndc_x, sx, ms_step, "fp32")
     log(f"fp32 search roofline {roof}")
     off, nb, ds, entry = res
-    gt = None
     rec32 = None
-    if wl["nq"] and not args.no_recall:
-        from paper_2602_17099_amd.prepare import knn_l2_exact
-        gt = knn_l2_exact(Xd, Qd, 10)
+    if gt is not None:
         rec32 = recall_at_10(pkg, off, nb, entry, Xd, Qd, gt)
         log(f"fp32 recall@10 (query ef 64) {rec32:.4f}")
 
@@ -516,17 +600,18 @@ def main():
         ndc_b = exact_ndc(pkg, subs, Xd, wl, search=Xb)
         dtb, aggb, stb, resb = time_merges(pkg, subs, Xd, wl, args.steps, args.warmup, search=Xb)
         vb = args.steps * stb["n_source_vertices"] / dtb
+        ms_b = 1000.0 * dtb / args.steps
         recb = recall_at_10(pkg, resb[0], resb[1], resb[3], Xd, Qd, gt) if gt is not None else None
         same = bool(torch.equal(resb[0], off) and torch.equal(resb[1], nb))
-        rb = search_roofline(aggb, stb, ndc_b, args.steps)
-        bf16 = {"value": vb, "ms_per_step": 1000.0 * dtb / args.steps, "recall_at_10": recb,
+        aggbx, stbx, sbx = exclusive(Xb, dtb, aggb, stb, args.steps)
+        rb = search_roofline(aggbx, stbx, ndc_b, sbx, ms_b, "bf16")
+        bf16 = {"value": vb, "ms_per_step": ms_b, "recall_at_10": recb,
                 "phase_ms": {"expansion_search": stb["ms_search"][0],
                              "search_span": stb["ms_search_span"],
                              "prune_and_reverse": stb["ms_prune"], "compact": stb["ms_compact"],
                              "total": stb["ms_total"]},
                 "speedup_vs_fp32": vb / value, "same_graph_as_fp32": same,
-                "search_ms_per_launch": rb["ms_per_launch"], "search_gbs": rb["achieved"],
-                "search_frac": rb["frac"]}
+                "roofline": rb}
         log(f"bf16 search copy: {bf16}")
 
     # cross-query merge (every source vertex a pivot: naive searches only, no

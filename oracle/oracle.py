@@ -26,8 +26,8 @@ _lib = None
 
 
 def build() -> str:
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
-           "-o", LIB + ".tmp", SRC, "-lm"]
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall",
+           "-Wno-unused-function", "-o", LIB + ".tmp", SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
@@ -62,6 +62,10 @@ class Trace(C.Structure):
 
 def _setup(L):
     P = C.c_void_p
+    L.orc_set_threads.restype = None
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_get_threads.restype = C.c_int
+    L.orc_get_threads.argtypes = []
     L.orc_dist_vec.restype = C.c_double
     L.orc_dist_vec.argtypes = [P, P, C.c_int, C.c_int, C.c_double, C.c_double]
     L.orc_beam_search.restype = C.c_int
@@ -117,6 +121,16 @@ def _i64(x):
     return np.ascontiguousarray(x, dtype=np.int64)
 
 
+def set_threads(n: int) -> None:
+    """Threads of the loops over independent vertices (searches, prunes,
+    k-NN rows); results do not depend on it."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
+
+
 def norms(X: np.ndarray) -> np.ndarray:
     X = _f32(X)
     out = np.empty(X.shape[0], dtype=np.float64)
@@ -156,29 +170,21 @@ def prune(p, W, X, alpha, R, metric=L2SQ):
 
 
 def expand(offsets, nbrs, X, k, kplus, metric=L2SQ, base=0, threads=1):
-    """N_k of every vertex ([n x k], -1 padded). With threads > 1 the vertex
-    range is split over that many threads (the C calls release the GIL;
-    every vertex's search is independent)."""
+    """N_k of every vertex ([n x k], -1 padded), its independent searches
+    spread over `threads` threads."""
     offsets, nbrs, X = _i64(offsets), _i32(nbrs), _f32(X)
     n = len(offsets) - 1
     nrm = norms(X) if metric == COSINE else None
     out = np.empty((n, k), dtype=np.int32)
-    if threads <= 1:
-        lib().orc_expand(n, _p(offsets), _p(nbrs), base, _p(X), X.shape[1], metric, _p(nrm), k,
-                         kplus, _p(out))
-        return out
-    from concurrent.futures import ThreadPoolExecutor
-    step = (n + 4 * threads - 1) // (4 * threads)
-    ranges = [(v, min(n, v + step)) for v in range(0, n, step)]
-
-    def run(r):
-        rc = lib().orc_expand_range(n, _p(offsets), _p(nbrs), base, _p(X), X.shape[1], metric,
-                                    _p(nrm), k, kplus, r[0], r[1], _p(out))
-        if rc != 0:
-            raise RuntimeError(f"orc_expand_range failed on {r}")
-
-    with ThreadPoolExecutor(threads) as ex:
-        list(ex.map(run, ranges))
+    prev = get_threads()
+    set_threads(max(1, threads))
+    try:
+        rc = lib().orc_expand(n, _p(offsets), _p(nbrs), base, _p(X), X.shape[1], metric, _p(nrm),
+                              k, kplus, _p(out))
+    finally:
+        set_threads(prev)
+    if rc != 0:
+        raise RuntimeError("orc_expand failed")
     return out
 
 

@@ -6,7 +6,10 @@
  * baseline leg of the benchmark do. It shares no code with the HIP path.
  *
  * All distances are computed in double precision from the original float32
- * values. Everything is single-threaded and deterministic. Functions follow
+ * values. Everything is deterministic. Loops over vertices whose work is
+ * independent (one search, or one prune, per vertex) may run on several
+ * threads (OpenMP, orc_set_threads); each vertex's arithmetic is the same
+ * either way, counts are summed, and everything else is sequential. Functions follow
  * the paper (arXiv 2602.17099) in its own order and notation:
  *
  *   beam search ............ Algorithm 1 (Section 2.2)
@@ -34,6 +37,27 @@
 #include <string.h>
 
 #include "rnsm_oracle.h"
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* threads for the loops over independent vertices (1: sequential) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* distances (the paper's delta; L2 is its default, Section 2.1)       */
@@ -288,25 +312,34 @@ int orc_prune(int64_t p, const int32_t* W, int nW, const float* X, int dim, int 
 static int expand_neighbors(const space_t* S, int64_t n, const int64_t* offsets,
                             const int32_t* nbrs, int64_t base, int k, int kplus,
                             int32_t* nk_out, int64_t* ndc, int64_t v0, int64_t v1) {
-    visited_t vis;
-    if (!visited_init(&vis, n)) return -1;
-    int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)kplus);
-    double* ds = (double*)malloc(sizeof(double) * (size_t)kplus);
-    for (int64_t v = v0; v < v1; ++v) {
-        int32_t seed = (int32_t)v;
-        const float* q = S->X + (base + v) * S->dim;
-        double qn = S->norms ? S->norms[base + v] : 1.0;
-        int c = beam_search(S, n, offsets, nbrs, base, q, qn, &seed, 1, kplus, &vis, ids, ds, ndc,
-                            NULL);
-        int t = 0;
-        for (int i = 0; i < c && t < k; ++i)
-            if (ids[i] != v) nk_out[v * k + t++] = ids[i];
-        for (; t < k; ++t) nk_out[v * k + t] = -1;
+    int64_t nd = 0;
+    int fail = 0;
+#pragma omp parallel reduction(+ : nd) reduction(| : fail)
+    {
+        visited_t vis;
+        int32_t* ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)kplus);
+        double* ds = (double*)malloc(sizeof(double) * (size_t)kplus);
+        const int ok = visited_init(&vis, n) && ids && ds;
+        fail |= !ok;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t v = v0; v < v1; ++v) {
+            if (!ok) continue;
+            int32_t seed = (int32_t)v;
+            const float* q = S->X + (base + v) * S->dim;
+            double qn = S->norms ? S->norms[base + v] : 1.0;
+            int c = beam_search(S, n, offsets, nbrs, base, q, qn, &seed, 1, kplus, &vis, ids, ds,
+                                &nd, NULL);
+            int t = 0;
+            for (int i = 0; i < c && t < k; ++i)
+                if (ids[i] != v) nk_out[v * k + t++] = ids[i];
+            for (; t < k; ++t) nk_out[v * k + t] = -1;
+        }
+        free(ids);
+        free(ds);
+        free(vis.stamp);
     }
-    free(ids);
-    free(ds);
-    free(vis.stamp);
-    return 0;
+    if (ndc) *ndc += nd;
+    return fail ? -1 : 0;
 }
 
 int orc_expand(int64_t n, const int64_t* offsets, const int32_t* nbrs, int64_t base,
@@ -588,26 +621,52 @@ static int pair_op(const space_t* S, const sub_t* s, const sub_t* t, const rows_
     int32_t* res_ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->n * RES));
     double* res_d = (double*)malloc(sizeof(double) * (size_t)(s->n * RES));
     int* res_n = (int*)calloc((size_t)s->n, sizeof(int));
-    visited_t vis;
-    if (!res_ids || !res_d || !res_n || !visited_init(&vis, t->n)) return -1;
+    if (!res_ids || !res_d || !res_n) return -1;
+    int64_t ndc_naive = 0, ndc_slide = 0;
+    int fail = 0;
 
-    /* naive search of every pivot from the target's default entry point */
-    for (int64_t i = 0; i < n_piv; ++i) {
-        int64_t p = piv_order[i];
-        const float* q = S->X + (s->base + p) * S->dim;
-        double qn = S->norms ? S->norms[s->base + p] : 1.0;
-        res_n[p] = beam_search(S, t->n, t->offsets, t->nbrs, t->base, q, qn, &t->entry, 1, L, &vis,
-                               res_ids + p * RES, res_d + p * RES, &g_ndc_naive, NULL);
+    /* naive search of every pivot from the target's default entry point
+     * (each search is independent: one visited set per thread) */
+#pragma omp parallel reduction(+ : ndc_naive) reduction(| : fail)
+    {
+        visited_t vis;
+        const int ok = visited_init(&vis, t->n);
+        fail |= !ok;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n_piv; ++i) {
+            if (!ok) continue;
+            int64_t p = piv_order[i];
+            const float* q = S->X + (s->base + p) * S->dim;
+            double qn = S->norms ? S->norms[s->base + p] : 1.0;
+            res_n[p] = beam_search(S, t->n, t->offsets, t->nbrs, t->base, q, qn, &t->entry, 1, L,
+                                   &vis, res_ids + p * RES, res_d + p * RES, &ndc_naive, NULL);
+        }
+        free(vis.stamp);
     }
-    /* local sliding of every follower from its pivot's results */
-    for (int64_t y = 0; y < s->n; ++y) {
-        int32_t p = pivot_of[y];
-        if (p < 0) continue;
-        const float* q = S->X + (s->base + y) * S->dim;
-        double qn = S->norms ? S->norms[s->base + y] : 1.0;
-        res_n[y] = beam_search(S, t->n, t->offsets, t->nbrs, t->base, q, qn, res_ids + (int64_t)p * RES,
-                               res_n[p], EL, &vis, res_ids + y * RES, res_d + y * RES,
-                               &g_ndc_slide, NULL);
+    /* local sliding of every follower from its pivot's results (every pivot
+     * is done: the loop above has ended) */
+#pragma omp parallel reduction(+ : ndc_slide) reduction(| : fail)
+    {
+        visited_t vis;
+        const int ok = visited_init(&vis, t->n);
+        fail |= !ok;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t y = 0; y < s->n; ++y) {
+            int32_t p = pivot_of[y];
+            if (p < 0 || !ok) continue;
+            const float* q = S->X + (s->base + y) * S->dim;
+            double qn = S->norms ? S->norms[s->base + y] : 1.0;
+            res_n[y] = beam_search(S, t->n, t->offsets, t->nbrs, t->base, q, qn, res_ids + (int64_t)p * RES,
+                                   res_n[p], EL, &vis, res_ids + y * RES, res_d + y * RES,
+                                   &ndc_slide, NULL);
+        }
+        free(vis.stamp);
+    }
+    g_ndc_naive += ndc_naive;
+    g_ndc_slide += ndc_slide;
+    if (fail) {
+        free(res_ids); free(res_d); free(res_n);
+        return -1;
     }
     if (trace_res_ids) {
         for (int64_t y = 0; y < s->n; ++y)
@@ -617,16 +676,21 @@ static int pair_op(const space_t* S, const sub_t* s, const sub_t* t, const rows_
             }
     }
 
-    /* source update: concatenate with the current row, prune to R */
-    int32_t* W = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + RES + 1));
-    for (int64_t u = 0; u < s->n; ++u) {
-        int64_t gu = s->base + u;
-        int nw = 0;
-        for (int j = 0; j < rows->deg[gu]; ++j) W[nw++] = rows->rows[gu * R + j];
-        for (int j = 0; j < res_n[u]; ++j) W[nw++] = (int32_t)(t->base + res_ids[u * RES + j]);
-        rows->deg[gu] = prune(S, gu, W, nw, P->alpha, R, rows->rows + gu * R, rows->dists + gu * R);
+    /* source update: concatenate with the current row, prune to R (each
+     * vertex reads and writes only its own row) */
+#pragma omp parallel
+    {
+        int32_t* W = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + RES + 1));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t u = 0; u < s->n; ++u) {
+            int64_t gu = s->base + u;
+            int nw = 0;
+            for (int j = 0; j < rows->deg[gu]; ++j) W[nw++] = rows->rows[gu * R + j];
+            for (int j = 0; j < res_n[u]; ++j) W[nw++] = (int32_t)(t->base + res_ids[u * RES + j]);
+            rows->deg[gu] = prune(S, gu, W, nw, P->alpha, R, rows->rows + gu * R, rows->dists + gu * R);
+        }
+        free(W);
     }
-    free(W);
 
     /* reverse edges: every kept u -> v with v in the target */
     int64_t* rcnt = (int64_t*)calloc((size_t)(t->n + 1), sizeof(int64_t));
@@ -651,17 +715,22 @@ static int pair_op(const space_t* S, const sub_t* s, const sub_t* t, const rows_
     int maxrev = 0;
     for (int64_t v = 0; v < t->n; ++v)
         if (rcnt[v + 1] - rcnt[v] > maxrev) maxrev = (int)(rcnt[v + 1] - rcnt[v]);
-    int32_t* W2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + maxrev + 1));
-    for (int64_t v = 0; v < t->n; ++v) {
-        if (rcnt[v + 1] == rcnt[v]) continue;
-        int64_t gv = t->base + v;
-        int nw = 0;
-        for (int j = 0; j < rows->deg[gv]; ++j) W2[nw++] = rows->rows[gv * R + j];
-        for (int64_t j = rcnt[v]; j < rcnt[v + 1]; ++j) W2[nw++] = rev[j];
-        rows->deg[gv] = prune(S, gv, W2, nw, P->alpha, R, rows->rows + gv * R, rows->dists + gv * R);
+#pragma omp parallel
+    {
+        int32_t* W2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + maxrev + 1));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t v = 0; v < t->n; ++v) {
+            if (rcnt[v + 1] == rcnt[v]) continue;
+            int64_t gv = t->base + v;
+            int nw = 0;
+            for (int j = 0; j < rows->deg[gv]; ++j) W2[nw++] = rows->rows[gv * R + j];
+            for (int64_t j = rcnt[v]; j < rcnt[v + 1]; ++j) W2[nw++] = rev[j];
+            rows->deg[gv] = prune(S, gv, W2, nw, P->alpha, R, rows->rows + gv * R, rows->dists + gv * R);
+        }
+        free(W2);
     }
-    free(W2); free(rev); free(fill); free(rcnt);
-    free(res_ids); free(res_d); free(res_n); free(vis.stamp);
+    free(rev); free(fill); free(rcnt);
+    free(res_ids); free(res_d); free(res_n);
     return 0;
 }
 
@@ -863,19 +932,23 @@ int orc_knn(int64_t n, const float* X, int dim, int metric, int K, int32_t* out)
         orc_norms(X, n, dim, norms);
     }
     space_t S = {X, dim, metric, norms};
-    wkey_t* c = (wkey_t*)malloc(sizeof(wkey_t) * (size_t)(n > 0 ? n : 1));
-    for (int64_t v = 0; v < n; ++v) {
-        int nc = 0;
-        for (int64_t u = 0; u < n; ++u) {
-            if (u == v) continue;
-            c[nc].id = (int32_t)u;
-            c[nc].d = dist_ids(&S, v, u);
-            ++nc;
+#pragma omp parallel
+    {
+        wkey_t* c = (wkey_t*)malloc(sizeof(wkey_t) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t v = 0; v < n; ++v) {
+            int nc = 0;
+            for (int64_t u = 0; u < n; ++u) {
+                if (u == v) continue;
+                c[nc].id = (int32_t)u;
+                c[nc].d = dist_ids(&S, v, u);
+                ++nc;
+            }
+            qsort(c, (size_t)nc, sizeof(wkey_t), wkey_cmp);
+            for (int j = 0; j < K; ++j) out[v * K + j] = j < nc ? c[j].id : -1;
         }
-        qsort(c, (size_t)nc, sizeof(wkey_t), wkey_cmp);
-        for (int j = 0; j < K; ++j) out[v * K + j] = j < nc ? c[j].id : -1;
+        free(c);
     }
-    free(c);
     free(norms);
     return 0;
 }
@@ -883,7 +956,10 @@ int orc_knn(int64_t n, const float* X, int dim, int metric, int K, int32_t* out)
 /* exact top-K of the rows of X for external queries Q, by (d, id) */
 int orc_knn_queries(int64_t n, const float* X, int64_t nq, const float* Q, int dim, int metric,
                     int K, int32_t* out_ids, double* out_d) {
+#pragma omp parallel
+    {
     wkey_t* c = (wkey_t*)malloc(sizeof(wkey_t) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 4)
     for (int64_t i = 0; i < nq; ++i) {
         const float* q = Q + i * dim;
         double qn = 1.0;
@@ -909,6 +985,7 @@ int orc_knn_queries(int64_t n, const float* X, int64_t nq, const float* Q, int d
         }
     }
     free(c);
+    }
     return 0;
 }
 

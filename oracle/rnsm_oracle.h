@@ -32,6 +32,9 @@ typedef struct {
     int64_t ndc_expand, ndc_naive, ndc_slide, n_pivots;
 } orc_trace_t;
 
+/* threads for the loops over independent vertices (OpenMP builds; 1 = sequential) */
+void orc_set_threads(int n);
+int orc_get_threads(void);
 double orc_dist_vec(const float* a, const float* b, int dim, int metric, double na, double nb);
 void orc_norms(const float* X, int64_t n, int dim, double* out);
 int orc_beam_search(int64_t n, const int64_t* offsets, const int32_t* nbrs, int64_t base,

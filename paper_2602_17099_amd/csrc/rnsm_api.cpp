@@ -712,6 +712,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     // runs its queries in that order, and pivot groups are launched by the
     // rank of their pivot in it (locality in L2 only)
     const bool use_bfs = !getenv("RNSM_NO_BFS_ORDER");
+    const bool one_stream = getenv("RNSM_ONE_STREAM") && atoi(getenv("RNSM_ONE_STREAM")) == 1;
     int32_t* h_bfs = nullptr;
     auto bfs_order_of = [&](int s, hipStream_t strm, int32_t** order_out, int* ev_out) -> rnsm_status {
         const int64_t ns = sizes[s];
@@ -1040,6 +1041,10 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
         // sliding search on st after the naive one (event wait); the naive
         // search of chunk c+1 overlaps the sliding search of chunk c
         HIPCHK(hipStreamWaitEvent(sd, E.ev[ev_go], 0));
+        // the pivots' copies and naive searches: on the side stream, or (the
+        // measurement switch RNSM_ONE_STREAM=1) on st, where every search
+        // launch then runs alone and its event time is its own
+        const hipStream_t sa = one_stream ? st : sd;
         // source rows: current row + search results, pruned to R after the
         // searches, each pivot group together (order staged with the chunks).
         // (Pruning each chunk on a third stream as soon as its searches end
@@ -1145,24 +1150,24 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                 return e == hipSuccess;
             };
             if (np > pa && !chk(hipMemcpyAsync(d_piv + pa, h_lp + pa, sizeof(int32_t) * (np - pa),
-                                               hipMemcpyHostToDevice, sd)))
+                                               hipMemcpyHostToDevice, sa)))
                 return;
             if (nf > fa) {
                 if (!chk(hipMemcpyAsync(d_fol + fa, h_lf + fa, sizeof(int32_t) * (nf - fa),
-                                        hipMemcpyHostToDevice, sd)) ||
+                                        hipMemcpyHostToDevice, sa)) ||
                     !chk(hipMemcpyAsync(d_folp + fa, h_lfp + fa, sizeof(int32_t) * (nf - fa),
-                                        hipMemcpyHostToDevice, sd)))
+                                        hipMemcpyHostToDevice, sa)))
                     return;
             }
             if (!chk(hipMemcpyAsync(d_order + o0, h_order + o0, sizeof(int32_t) * (np + nf - o0),
-                                    hipMemcpyHostToDevice, sd)))
+                                    hipMemcpyHostToDevice, sa)))
                 return;
-            if (!chk(E.stat(sd, &ce[0]))) return;
+            if (!chk(E.stat(sa, &ce[0]))) return;
             SearchArgs x = aA;
             x.qidx = d_piv + pa;
             x.out_row = x.qidx;
             x.nq = np - pa;
-            if (!chk(launch_search(vi.tt, x, shA.wpb, sd)) || !chk(E.record(sd, &ce[1]))) return;
+            if (!chk(launch_search(vi.tt, x, shA.wpb, sa)) || !chk(E.record(sa, &ce[1]))) return;
             if (!chk(hipStreamWaitEvent(st, E.ev[ce[1]], 0))) return;
             if (!chk(E.stat(st, &ce[2]))) return;
             SearchArgs y = aB;

@@ -31,8 +31,8 @@ MUTANTS = {
     "larger_is_source": ("int src = (sizes[j] < sizes[i]) ? j : i;",
                          "int src = (sizes[j] > sizes[i]) ? j : i;"),
     "ops_cost_order_reversed": ("int later = c1 > c0 ||", "int later = c1 < c0 ||"),
-    "follower_seeded_from_entry": ("res_ids + (int64_t)p * RES,\n                               res_n[p], EL",
-                                   "&t->entry,\n                               1, EL"),
+    "follower_seeded_from_entry": ("res_ids + (int64_t)p * RES,\n" + " " * 35 + "res_n[p], EL",
+                                   "&t->entry,\n" + " " * 35 + "1, EL"),
     "follower_seeded_from_top1": ("res_n[p], EL, &vis", "(res_n[p] > 0 ? 1 : 0), EL, &vis"),
     "follower_beam_ef_naive": ("res_n[p], EL, &vis", "res_n[p], L, &vis"),
     "follower_cosine_query_norm_dropped": ("double qn = S->norms ? S->norms[s->base + y] : 1.0;",

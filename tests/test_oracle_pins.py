@@ -626,6 +626,28 @@ def test_expansion_threaded_equals_serial(orc):
     assert np.array_equal(a, b)
 
 
+def test_merge_threads_equal_serial(orc):
+    # the loops over independent vertices give the same merge, trace and
+    # distance counts on any number of threads
+    X = inputs.mixture_u8(2400, 16, comps=6, seed=96)
+    subs = [orc.build_graph(X[:1000], 24, 12, alpha=1.2, reverse=True),
+            orc.build_graph(X[1000:], 24, 12, alpha=1.2, reverse=True)]
+    prev = orc.get_threads()
+    try:
+        orc.set_threads(1)
+        a = orc.merge(subs, X, R=12, L=24, alpha=1.2, ef_slide=16, trace=True)
+        orc.set_threads(4)
+        b = orc.merge(subs, X, R=12, L=24, alpha=1.2, ef_slide=16, trace=True)
+    finally:
+        orc.set_threads(prev)
+    for key in ("offsets", "nbrs", "dists"):
+        assert np.array_equal(a[key], b[key])
+    for key in ("nk", "pivot_of", "res_ids", "res_d"):
+        assert np.array_equal(a["trace"][key], b["trace"][key])
+    for key in ("ndc_expand", "ndc_naive", "ndc_slide", "n_pivots"):
+        assert a["trace"][key] == b["trace"][key]
+
+
 def test_projection_graph_is_a_valid_input(orc):
     # degree <= deg, no self-loop, no duplicate, ids in range (the merge
     # rejects anything else)
