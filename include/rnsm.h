@@ -216,12 +216,18 @@ typedef struct {
     int32_t exact_visited;  /* 1 when the searches ran with the probing visited table */
     int32_t prune_path;     /* prune arithmetic: 0 float32 walk, 1 bfloat16 MFMA Gram with
                                exact products (rows exact in bfloat16, integer sums below
-                               2^24), 3 MFMA Gram with a hi/lo bfloat16 split of each row */
+                               2^24), 3 MFMA Gram with a hi/lo bfloat16 split of each row,
+                               pairs near the alpha boundary decided in float32 as the walk
+                               does; the MFMA forms cover dims 32..128 (multiples of 32)
+                               and 256..1024 (multiples of 128) */
     double ms_search_span;  /* device time from the first naive search to the last sliding
                                search of each operation, summed over operations: naive and
                                sliding launches overlap on two streams, so this is below
                                ms_search[1] + ms_search[2] */
     int32_t search_hash_bits, search_waves_per_block;  /* shape of the operations' searches */
+    int64_t prune_rechecks; /* prune_path 3: vertex pairs whose split-Gram estimate lay near the
+                               alpha boundary and were decided with float32 arithmetic on
+                               the original rows instead */
 } rnsm_stats;
 
 /*

@@ -75,7 +75,7 @@ class Stats(C.Structure):
                 ("hash_evictions", C.c_int64), ("row_bytes", C.c_int32),
                 ("exact_visited", C.c_int32), ("prune_path", C.c_int32),
                 ("ms_search_span", C.c_double), ("search_hash_bits", C.c_int32),
-                ("search_waves_per_block", C.c_int32)]
+                ("search_waves_per_block", C.c_int32), ("prune_rechecks", C.c_int64)]
 
 
 def lib():

@@ -374,8 +374,29 @@ int choose_prune(const ValueInfo& v, int dim, int R) {
     return int_exact(v, dim, 256.0) ? 1 : 3;
 }
 
+// relative band of the float re-decision in the MFMA prune (RNSM_PRUNE_BAND:
+// log2 of the band, e.g. -4; "off" disables it, for measurement)
+double prune_band() {
+    const char* e = getenv("RNSM_PRUNE_BAND");
+    if (!e) return PRUNE_BAND;
+    if (!strcmp(e, "off")) return 0.0;
+    const int v = atoi(e);
+    return v < 0 && v > -60 ? std::ldexp(1.0, v) : PRUNE_BAND;
+}
+
 hipError_t run_prune(const PruneArgs& a, int mode, hipStream_t st) {
-    if (mode != 0 && prune_mfma_fits(a, mode)) return launch_prune_mfma(a, mode, st);
+    if (mode != 0 && prune_mfma_fits(a, mode)) {
+        if (a.extra_mode != 2) return launch_prune_mfma(a, mode, st);
+        // candidate lists of any length: the MFMA Gram takes those up to
+        // LONG_LIST, the float32 walk the longer ones (targets with thousands
+        // of reverse edges; the same decisions, see the band re-decision)
+        PruneArgs b = a;
+        b.list_filter = 1;
+        hipError_t e = launch_prune_mfma(b, mode, st);
+        if (e != hipSuccess) return e;
+        b.list_filter = 2;
+        return launch_prune(b, st);
+    }
     return launch_prune(a, st);
 }
 
@@ -693,11 +714,15 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     // bfloat16 copy of the rows for an exact-mode prune (half the bytes for
     // its gathers), made before the summary says whether the rows are exact
     // in it; unused when they are not
+    // (above dim 128 the copy is large: made only once the summary asks for it)
     char* xb16 = nullptr;
-    if (prune_mfma_supported(vecs->dim) && R <= 64) {
+    if (prune_mfma_supported(vecs->dim) && vecs->dim <= 128 && R <= 64) {
         WS(xb16, "prune_bf16", (size_t)2 * N * vecs->dim);
         HIPCHK(launch_convert(vecs->f32, RNSM_F32, xb16, RNSM_BF16, N * vecs->dim, st));
     }
+    u64* rechecks;
+    WS(rechecks, "prune_rechecks", sizeof(u64) * CNT_SLOTS);
+    HIPCHK(hipMemsetAsync(rechecks, 0, sizeof(u64) * CNT_SLOTS, st));
     HIPCHK(hipMemsetAsync(cnt, 0, sizeof(u64) * 3 * CNT_SLOTS * CNT_N, st));
     HIPCHK(hipMemsetAsync(errf, 0, sizeof(int), st));
     if (p->metric == RNSM_COSINE) {
@@ -746,6 +771,11 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     decode_value_range(h_vr, &vinfo);
     const int pmode = choose_prune(vinfo, vecs->dim, R);
     if (pmode != 1) xb16 = nullptr;
+    if (pmode == 1 && !xb16) {
+        WS(xb16, "prune_bf16", (size_t)2 * N * vecs->dim);
+        HIPCHK(launch_convert(vecs->f32, RNSM_F32, xb16, RNSM_BF16, N * vecs->dim, st));
+    }
+    const double band = prune_band();
     // search distances usable as prune keys: a float32 copy computes them
     // with the prune's own lane layout and order; a 16-bit copy only when
     // every distance is exact (integers exact in that type, exact sums)
@@ -932,6 +962,8 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                 rd.R = R;
                 rd.wcap = TARGET_WCAP;
                 rd.err = errf;
+                rd.band = band;
+                rd.rechecks = rechecks;
                 HIPCHK(launch_row_dists(rd, prune_reads_b16(rd, pmode), st));
             }
             if (use_bfs) {
@@ -1082,6 +1114,8 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
         qs.dist_out = rdist;
         qs.wcap = R + RES;
         qs.err = errf;
+        qs.band = band;
+        qs.rechecks = rechecks;
         bool groups_ok = true;
         int64_t pa = 0, fa = 0;  // list prefixes already handed to the device
         int64_t n_launch_a = 0, n_launch_b = 0;
@@ -1394,9 +1428,12 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     u64 hc[3 * CNT_N] = {};
     int herr = 0;
     HIPCHK(hipMemcpyAsync(&nedges, o_off + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    if (!E.no_stats)
+    u64 hrck[CNT_SLOTS] = {};
+    if (!E.no_stats) {
         HIPCHK(hipMemcpyAsync(hslots.data(), cnt, sizeof(u64) * hslots.size(),
                               hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hrck, rechecks, sizeof hrck, hipMemcpyDeviceToHost, st));
+    }
     HIPCHK(hipMemcpyAsync(&herr, errf, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (host_out) {
@@ -1465,6 +1502,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     S.ms_compact = E.between(c0, c1);
     S.n_ops = (int64_t)ops.size();
     S.prune_path = pmode;
+    for (int sl = 0; sl < CNT_SLOTS; ++sl) S.prune_rechecks += (int64_t)hrck[sl];
     S.row_bytes = vi.row_bytes;
     const double rb = vi.row_bytes;
     for (int ph = 0; ph < 3; ++ph) {
@@ -1887,6 +1925,7 @@ static rnsm_status rnsm_build_graph_impl(int64_t n, const float* X, int32_t dim,
     q.dist_out = d1;
     q.wcap = K;
     q.err = errf;
+    q.band = prune_band();
     HIPCHK(run_prune(q, pmode, st));
     int32_t *rows = rows1, *deg = deg1;
     if (reverse) {

@@ -94,7 +94,17 @@ struct PruneArgs {
     u64* scratch;             // keys of candidate lists longer than wcap (mode 2)
     int wcap;
     int* err;
+    // MFMA prune of float rows (hi/lo split): a pair whose estimate lies
+    // within band * scale of the alpha boundary is decided again with the
+    // float32 walk's own arithmetic (0: no re-decision); rechecks counts them
+    double band;
+    u64* rechecks;
+    // which vertices this launch prunes, by candidate count: 0 all, 1 those
+    // with at most LONG_LIST candidates, 2 the others (the float32 walk takes
+    // those, 16 at a time in key order, with no full sort)
+    int list_filter;
 };
+constexpr int LONG_LIST = 1024;
 
 // launchers (all asynchronous on `st`)
 hipError_t launch_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t nnz,
@@ -121,6 +131,8 @@ hipError_t launch_prune(const PruneArgs& a, hipStream_t st);
 // 128; R <= 64): nt = 1 for rows exact in bfloat16 with exact float32 sums,
 // nt = 3 (hi/lo split) otherwise
 bool prune_mfma_supported(int dim);
+// default relative band of the float re-decision (2^-10)
+constexpr double PRUNE_BAND = 1.0 / 1024.0;
 bool prune_mfma_fits(const PruneArgs& a, int nt);  // dimension, R and LDS size
 // missing distances of the rows of a prune's vertices, as that prune would
 // compute them (b16: the MFMA prune in exact mode, reading the bfloat16 copy)

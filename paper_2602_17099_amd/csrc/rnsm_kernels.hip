@@ -708,6 +708,42 @@ __device__ __forceinline__ void rank_keys(const u64* wk, u64* ws, int nW, int la
         if (j * WAVE + lane < nW) ws[rk[j]] = kv[j];
 }
 
+// The 16 smallest keys >= lo among wk[0, nW) in ascending order, EMPTY_KEY
+// past the last: lane l returns the (l % 16)-th. Each lane keeps the 16
+// smallest keys of its share in registers (an insertion network), then 16
+// rounds of wavefront minima merge the 64 lists. Equal keys (one vertex twice
+// in W) come out next to each other. O(nW / 64) reads per lane.
+__device__ __noinline__ u64 next16(const u64* wk, int nW, u64 lo, int lane) {
+    u64 s[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s[i] = EMPTY_KEY;
+    for (int t = lane; t < nW; t += WAVE) {
+        u64 x = wk[t];
+        if (x >= lo && x < s[15]) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const u64 m = s[i] < x ? s[i] : x;
+                x = s[i] < x ? x : s[i];
+                s[i] = m;
+            }
+        }
+    }
+    u64 out = EMPTY_KEY;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const u64 m = wave_min_u64(s[0]);
+        if (m == EMPTY_KEY) break;
+        const int src = __ffsll((long long)__ballot(s[0] == m)) - 1;
+        if (lane == src) {
+#pragma unroll
+            for (int i = 0; i < 15; ++i) s[i] = s[i + 1];
+            s[15] = EMPTY_KEY;
+        }
+        if ((lane & 15) == r) out = m;
+    }
+    return out;
+}
+
 // a kept edge p -> v into the target range offers p to v: counted here, so
 // that the reverse lists need no separate counting pass over the rows
 __device__ __forceinline__ void count_reverse(const PruneArgs& a, int64_t v) {
@@ -737,6 +773,9 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
     }
     if (a.skip_empty_extra && next == 0) return -1;
     const int nW = nrow + next;
+    // long candidate lists may go to a pass of their own (list_filter)
+    if ((a.list_filter == 1 && nW > LONG_LIST) || (a.list_filter == 2 && nW <= LONG_LIST))
+        return -1;
     u64* wk = lwk;  // wcap keys each in LDS
     u64* ws = lws;
     if (nW > a.wcap) {
@@ -829,18 +868,13 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
         rank_keys<4>(wk, ws, nW, lane);
     } else if (nW <= 8 * WAVE) {
         rank_keys<8>(wk, ws, nW, lane);
-    } else if (nW <= 16 * WAVE) {
+    } else if (nW <= LONG_LIST) {
         rank_keys<16>(wk, ws, nW, lane);
     } else {
-        for (int t = lane; t < nW; t += WAVE) {
-            const u64 kt = wk[t];
-            int r = 0;
-            for (int s2 = 0; s2 < nW; ++s2) {
-                const u64 ks = wk[s2];
-                r += (ks < kt || (ks == kt && s2 < t)) ? 1 : 0;
-            }
-            ws[r] = kt;
-        }
+        // longer lists (targets that collected thousands of reverse edges)
+        // are not sorted: the prune takes them 16 at a time in key order
+        // (next16), and stops once R are kept
+        ws = nullptr;
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -906,7 +940,6 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     u64 *wk, *ws;
     const int nW = prune_collect<CPL, false>(a, p, e, lane, lkeys + a.wcap, lkeys, &wk, &ws);
     if (nW < 0) return;
-    (void)wk;
     const int group = lane >> a.lgG, sub = lane & (G - 1);
     const int rowf = a.nch * 4;
 
@@ -916,7 +949,25 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     int nk = 0;
     u64 prev = EMPTY_KEY;
     float4 vx[CPL], nx[CPL];
-    u64 cur = nW > 0 ? ws[0] : EMPTY_KEY;
+    // candidate t in key order: the sorted list, or (long lists, ws NULL)
+    // 16 at a time from next16 into a buffer in the then unused LDS keys
+    int tbase = -16;
+    u64 lo = 0;
+    auto key_at = [&](int t) -> u64 {
+        if (ws) return t < nW ? ws[t] : EMPTY_KEY;
+        if (t >= tbase + 16) {
+            const u64 k = next16(wk, nW, lo, lane);
+            if (lane < 16) lkeys[lane] = k;
+            const u64 last = readlane64(k, 15);
+            lo = last == EMPTY_KEY ? EMPTY_KEY : last + 1;
+            tbase += 16;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        return lkeys[t - tbase];
+    };
+    u64 cur = nW > 0 ? key_at(0) : EMPTY_KEY;
     load_row_f32<CPL>(a.X, cur == EMPTY_KEY ? -1 : (int64_t)(unsigned)(cur & 0xffffffffu), rowf,
                       sub, G, nx);
     for (int t = 0; t < nW && nk < R; ++t) {
@@ -925,7 +976,7 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
         for (int j = 0; j < CPL; ++j) vx[j] = nx[j];
         const u64 kcur = cur;
         // prefetch the next candidate's row
-        cur = t + 1 < nW ? ws[t + 1] : EMPTY_KEY;
+        cur = t + 1 < nW ? key_at(t + 1) : EMPTY_KEY;
         load_row_f32<CPL>(a.X, cur == EMPTY_KEY ? -1 : (int64_t)(unsigned)(cur & 0xffffffffu),
                           rowf, sub, G, nx);
         if (kcur == prev) continue;  // the same vertex twice in W
@@ -1052,12 +1103,57 @@ __device__ __forceinline__ int dom_threshold(double alpha, double inv_alpha, flo
     return ti;
 }
 
-// LDS bytes per wavefront of k_prune_mfma: sorted keys, kept ids, distances
-// and squared norms, then kept-row fragments (R rounded up to whole 16-row
-// tiles; hi, then lo with the split), whose space first holds the unsorted keys
+// d(w, v) in float32 with the arithmetic of the float32 walk (k_prune): the
+// rows in its lane-group layout (G lanes, CPL 16-byte chunks per lane, w as
+// the kept row, v as the candidate), the same fma order and group sum, then
+// finalize_dist with the norms in the same order. Lane group 0 computes it;
+// the value is returned in every lane.
+template <int CPL>
+__device__ __forceinline__ float walk_pair_dist(const PruneArgs& a, int w, int v, int lane) {
+    const int G = a.G, sub = lane & (G - 1), group = lane >> a.lgG;
+    const int rowf = a.nch * 4;
+    float4 xw[CPL], xv[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        xw[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        xv[j] = xw[j];
+    }
+    load_row_f32<CPL>(a.X, group == 0 ? (int64_t)w : -1, rowf, sub, G, xw);
+    load_row_f32<CPL>(a.X, group == 0 ? (int64_t)v : -1, rowf, sub, G, xv);
+    const float acc = dist_rows<CPL>(xw, xv, a.metric, G);
+    const float wn = a.metric == 2 ? a.norms[w] : 1.0f, vn = a.metric == 2 ? a.norms[v] : 1.0f;
+    const float d = finalize_dist(acc, a.metric, wn, vn);
+    return __shfl(d, G - 1);
+}
+
+// Whether the alpha test of a pair decided from a hi/lo-split Gram estimate
+// dwv may differ from the walk's float32 decision: the estimate lies within
+// band * scale of the boundary, scale bounding the pair's distance terms
+// (squared L2 centred at p: (sqrt d(p,w) + sqrt d(p,v))^2; inner product:
+// |w| |v|; cosine: 1). Outside the band the split's error (about 2^-15 of the
+// scale) and the float32 sums' cannot move the decision.
+__device__ __forceinline__ bool near_boundary(double alpha, double dwv, float dv, double band,
+                                              int metric, float ui, float uj, float si,
+                                              float sj) {
+    double scale;
+    if (metric == 0) {
+        const double r = sqrt((double)fmaxf(ui, 0.f)) + sqrt((double)fmaxf(uj, 0.f));
+        scale = r * r;
+    } else if (metric == 1) {
+        scale = sqrt((double)si) * sqrt((double)sj);
+    } else {
+        scale = 1.0;
+    }
+    return fabs(alpha * dwv - (double)dv) <= alpha * band * scale;
+}
+
+// LDS bytes per wavefront of k_prune_mfma: sorted keys, kept ids, distances,
+// key terms and squared norms, then kept-row fragments (R rounded up to whole
+// 16-row tiles; hi, then lo with the split), whose space first holds the
+// unsorted keys
 __host__ __device__ inline int mfma_row_stride(int kd) { return 64 * kd + 16; }
 __host__ __device__ inline int mfma_kept_rows(int R) { return (R + 15) & ~15; }
-__host__ __device__ inline size_t mfma_kept_bytes(int R) { return ((size_t)R * 12 + 15) / 16 * 16; }
+__host__ __device__ inline size_t mfma_kept_bytes(int R) { return ((size_t)R * 16 + 15) / 16 * 16; }
 __host__ __device__ inline size_t mfma_prune_lds(int wcap, int R, int kd, int nt) {
     const size_t rows = (size_t)mfma_kept_rows(R) * mfma_row_stride(kd) * (nt > 1 ? 2 : 1);
     const size_t keys = (size_t)wcap * sizeof(u64);
@@ -1081,7 +1177,7 @@ __host__ __device__ inline size_t mfma_prune_lds(int wcap, int R, int kd, int nt
 //  NT == 3: rows split as hi + lo bfloat16, products hi*hi + hi*lo + lo*hi;
 //           squared L2 works on rows centred at p.
 template <int KD, int NT, int CPL>
-__global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
+__global__ __launch_bounds__(256, NT == 1 ? 4 : 1) void k_prune_mfma(PruneArgs a) {
     extern __shared__ unsigned char psm[];
     constexpr bool CENTER = NT > 1;
     const int lane = lane_id();
@@ -1095,7 +1191,9 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
     int* kept_ids = (int*)(base + (size_t)a.wcap * sizeof(u64));
     float* kept_d = (float*)(kept_ids + R);
     float* kept_u = kept_d + R;
+    float* kept_s = kept_u + R;  // squared norms (float rows: the re-decision band)
     unsigned char* khi = base + (size_t)a.wcap * sizeof(u64) + mfma_kept_bytes(R);
+    u64 nrecheck = 0;
     const int rs = mfma_row_stride(KD);
     const size_t klo_off = (size_t)mfma_kept_rows(R) * rs;  // lo fragments follow the hi ones
     const int64_t p = a.item_base + (a.items ? (int64_t)a.items[i] : i);
@@ -1105,6 +1203,10 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
     const int nW = prune_collect<CPL, NT == 1>(a, p, e, lane, lkeys, (u64*)khi, &wk, &ws);
     if (nW < 0) return;
     (void)wk;
+    if (!ws) {  // lists longer than 1024 are the walk's (run with list_filter 2)
+        if (lane == 0) atomicOr(a.err, 2);
+        return;
+    }
 
     constexpr int DL = 8 * KD;  // dimensions per lane
     const int dim = 32 * KD;
@@ -1197,17 +1299,15 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
 #pragma unroll
                 for (int e2 = 0; e2 < 8; ++e2) {
                     v[e2] = CENTER ? raw[8 * s2 + e2] - pf[CENTER ? 8 * s2 + e2 : 0] : raw[8 * s2 + e2];
-                    if constexpr (!CENTER) sq = fmaf(v[e2], v[e2], sq);
+                    sq = fmaf(raw[8 * s2 + e2], raw[8 * s2 + e2], sq);
                 }
                 split8<NT>(v, hi[s2], lo[s2]);
             }
         }
         float uj = dj;
-        if constexpr (!CENTER) {
-            sq += __shfl_xor(sq, 16);
-            sq += __shfl_xor(sq, 32);
-            uj = sq;
-        }
+        sq += __shfl_xor(sq, 16);
+        sq += __shfl_xor(sq, 32);
+        if constexpr (!CENTER) uj = sq;
         // exact rows, squared L2 or inner product: every d(w, v) is an exact
         // integer, so alpha * d(w, v) < d(p, v) is d(w, v) <= T (integer)
         const bool intd = NT == 1 && metric != 2;
@@ -1229,11 +1329,11 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
                 acc = mfma16(lo[s2], hi[s2], acc);
             }
         }
-        u64 bt[4];
+        u64 bt[4], ut[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ii = 4 * q + r;
-            bool pred;
+            bool pred, unc = false;
             if (intd) {
                 const int g = (int)acc[r];
                 const int dij = metric == 0 ? __shfl(uji, ii) + uji - 2 * g : 1 - g;
@@ -1241,9 +1341,33 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
             } else {
                 const float ui = __shfl(uj, ii);
                 const float ni = __shfl(nj, ii);
-                pred = ii < jr && alpha * gram_dist(acc[r], metric, ui, uj, ni, nj) < (double)dj;
+                const float si = __shfl(sq, ii);
+                const double gd = gram_dist(acc[r], metric, ui, uj, ni, nj);
+                pred = ii < jr && alpha * gd < (double)dj;
+                if constexpr (NT > 1)
+                    unc = ii < jr && idj >= 0 && a.band > 0.0 &&
+                          near_boundary(alpha, gd, dj, a.band, metric, ui, uj, si, sq);
             }
-            bt[r] = __ballot(pred);
+            bt[r] = __ballot(pred && !unc);
+            ut[r] = __ballot(unc);
+        }
+        if constexpr (NT > 1) {
+            // pairs near the boundary: the float32 walk's own decision
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                u64 m = ut[r];
+                while (m) {
+                    const int l = __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    const int ii = 4 * (l >> 4) + r, jj = l & 15;
+                    const int w = __builtin_amdgcn_readlane(idj, ii);
+                    const int v = __builtin_amdgcn_readlane(idj, jj);
+                    const float dv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dj), jj));
+                    const float dwv = walk_pair_dist<CPL>(a, w, v, lane);
+                    if (alpha * (double)dwv < (double)dv) bt[r] |= 1ull << l;
+                    ++nrecheck;
+                }
+            }
         }
         // kept rows of earlier tiles against the tile
         const int nk0 = nk;
@@ -1264,7 +1388,7 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int ki = kt * 16 + 4 * q + r;
-                bool pred = false;
+                bool pred = false, unc = false;
                 if (ki < nk0) {
                     if (intd) {
                         const int g = (int)ak[r];
@@ -1272,10 +1396,29 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
                         pred = dkj <= tj;
                     } else {
                         const float nkk = metric == 2 ? a.norms[kept_ids[ki]] : 1.0f;
-                        pred = alpha * gram_dist(ak[r], metric, kept_u[ki], uj, nkk, nj) < (double)dj;
+                        const double gd = gram_dist(ak[r], metric, kept_u[ki], uj, nkk, nj);
+                        pred = alpha * gd < (double)dj;
+                        if constexpr (NT > 1)
+                            unc = idj >= 0 && a.band > 0.0 &&
+                                  near_boundary(alpha, gd, dj, a.band, metric, kept_u[ki], uj,
+                                                kept_s[ki], sq);
                     }
                 }
-                bk |= __ballot(pred);
+                bk |= __ballot(pred && !unc);
+                if constexpr (NT > 1) {
+                    u64 m = __ballot(unc);
+                    while (m) {
+                        const int l = __ffsll((long long)m) - 1;
+                        m &= m - 1;
+                        const int w = kept_ids[kt * 16 + 4 * (l >> 4) + r];
+                        const int v = __builtin_amdgcn_readlane(idj, l & 15);
+                        const float dv =
+                            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dj), l & 15));
+                        const float dwv = walk_pair_dist<CPL>(a, w, v, lane);
+                        if (alpha * (double)dwv < (double)dv) bk |= 1ull << l;
+                        ++nrecheck;
+                    }
+                }
             }
         }
         const unsigned domk = (unsigned)((bk | (bk >> 16) | (bk >> 32) | (bk >> 48)) & 0xffffull);
@@ -1320,6 +1463,7 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
                 kept_ids[kr] = idj;
                 kept_d[kr] = dj;
                 kept_u[kr] = uj;
+                if constexpr (NT > 1) kept_s[kr] = sq;
                 a.rows_out[p * R + kr] = idj;
                 a.dist_out[p * R + kr] = dj;
                 count_reverse(a, idj);
@@ -1338,7 +1482,293 @@ __global__ __launch_bounds__(256) void k_prune_mfma(PruneArgs a) {
         for (int J = 0; J < ntiles && nk < R; ++J)
             if (tile(J, fragA)) break;
     }
-    if (lane == 0) a.deg_out[p] = nk;
+    if (lane == 0) {
+        a.deg_out[p] = nk;
+        if (nrecheck && a.rechecks)
+            atomicAdd(&a.rechecks[blockIdx.x & (CNT_SLOTS - 1)], (u64)nrecheck);
+    }
+}
+
+// ----------------------------------------------- MFMA prune, K-sliced (dim > 128)
+
+// LDS bytes per wavefront of k_prune_mfma_ks: sorted and unsorted keys, kept
+// ids, key terms and squared norms (no row fragments: they are re-read)
+__host__ __device__ inline size_t mfma_ks_lds(int wcap, int R) {
+    return (size_t)2 * wcap * sizeof(u64) + ((size_t)R * 12 + 15) / 16 * 16;
+}
+
+// this lane's 32 dimensions [d0, d0 + 32) of row id as four MFMA fragments:
+// NT == 1 the bfloat16 copy's values (exact), NT == 3 the float32 values
+// (minus the centre row's when pc >= 0) split as hi + lo; zeros for id < 0.
+// sq accumulates the squares of the row's own values.
+template <int NT>
+__device__ __forceinline__ void load_slice(const PruneArgs& a, int64_t id, int dim, int d0,
+                                           const float* pcv, uint4* hi, uint4* lo, float& sq) {
+    if (id < 0) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            hi[f] = make_uint4(0u, 0u, 0u, 0u);
+            lo[f] = hi[f];
+        }
+        return;
+    }
+    if constexpr (NT == 1) {
+        const uint4* r = (const uint4*)(a.xb + (id * dim + d0) * 2);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            hi[f] = r[f];
+            lo[f] = make_uint4(0u, 0u, 0u, 0u);
+            sq = dot2x4<1>(hi[f], hi[f], sq);
+        }
+    } else {
+        const float4* r = (const float4*)(a.X + id * dim + d0);
+        float4 x[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = r[t];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            float v[8] = {x[2 * f].x, x[2 * f].y, x[2 * f].z, x[2 * f].w,
+                          x[2 * f + 1].x, x[2 * f + 1].y, x[2 * f + 1].z, x[2 * f + 1].w};
+#pragma unroll
+            for (int e2 = 0; e2 < 8; ++e2) {
+                sq = fmaf(v[e2], v[e2], sq);
+                if (pcv) v[e2] -= pcv[8 * f + e2];
+            }
+            split8<NT>(v, hi[f], lo[f]);
+        }
+    }
+}
+
+// Prune(p, W) with the Gram products on bfloat16 MFMA for dim = 128 * nsl
+// (nsl = 2..8). As k_prune_mfma, but each 16-candidate tile's Grams (with
+// itself, then with each 16 kept rows in turn) accumulate in registers over
+// slices of 128 dimensions: per slice each lane loads 32 dimensions of its
+// row and of a kept row (read again from memory, where they stay in L2), so
+// no buffer grows with the dimension. NT == 1: rows exact in bfloat16 with
+// exact sums (the bfloat16 copy; every decision exact); NT == 3: hi/lo split
+// of the float rows (centred at p for squared L2: CENTER), pairs near the
+// boundary decided again with the float32 walk's arithmetic (CPL: the walk's
+// chunks per lane).
+template <int NT, bool CENTER, int CPL>
+__global__ __launch_bounds__(256) void k_prune_mfma_ks(PruneArgs a) {
+    extern __shared__ unsigned char psm[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int64_t i = xcd_block() * wpb + wib;
+    if (i >= a.n_items) return;
+    const int R = a.R;
+    unsigned char* base = psm + (size_t)wib * mfma_ks_lds(a.wcap, R);
+    u64* lkeys = (u64*)base;
+    u64* lraw = lkeys + a.wcap;
+    int* kept_ids = (int*)(lraw + a.wcap);
+    float* kept_u = (float*)(kept_ids + R);
+    float* kept_s = kept_u + R;
+    const int64_t p = a.item_base + (a.items ? (int64_t)a.items[i] : i);
+    const int64_t e = p - a.extra_index_base;
+    u64 *wk, *ws;
+    const int nW = prune_collect<CPL, NT == 1>(a, p, e, lane, lkeys, lraw, &wk, &ws);
+    if (nW < 0) return;
+    (void)wk;
+    if (!ws) {  // lists longer than 1024 are the walk's (run with list_filter 2)
+        if (lane == 0) atomicOr(a.err, 2);
+        return;
+    }
+    const int dim = a.nch * 4;
+    const int nsl = dim >> 7;
+    const int jr = lane & 15, q = lane >> 4;
+    const int metric = a.metric;
+    const double alpha = (double)a.alpha, inv_alpha = 1.0 / alpha;
+    int nk = 0;
+    u64 prev = EMPTY_KEY, nrecheck = 0;
+    const int ntiles = (nW + 15) >> 4;
+    // this lane's 32 dimensions of the centre row p in slice sl
+    auto centre = [&](int sl, float* pc) {
+        const float4* pr = (const float4*)(a.X + p * dim + sl * 128 + q * 32);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const float4 x = pr[t];
+            pc[4 * t] = x.x;
+            pc[4 * t + 1] = x.y;
+            pc[4 * t + 2] = x.z;
+            pc[4 * t + 3] = x.w;
+        }
+    };
+    for (int J = 0; J < ntiles && nk < R; ++J) {
+        const int c = J * 16 + jr;
+        const u64 key = c < nW ? ws[c] : EMPTY_KEY;
+        const int idj = key == EMPTY_KEY ? -1 : (int)(unsigned)(key & 0xffffffffu);
+        const float dj = key == EMPTY_KEY ? INFINITY : fval((unsigned)(key >> 32));
+        const float nj = (metric == 2 && idj >= 0) ? a.norms[idj] : 1.0f;
+        const int nk0 = nk, nkt = (nk0 + 15) >> 4;
+        // the tile with itself
+        floatx4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        float sq = 0.0f;
+        for (int sl = 0; sl < nsl; ++sl) {
+            float pc[CENTER ? 32 : 1];
+            if constexpr (CENTER) centre(sl, pc);
+            uint4 hi[4], lo[4];
+            load_slice<NT>(a, idj, dim, sl * 128 + q * 32, CENTER ? pc : nullptr, hi, lo, sq);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                acc = mfma16(hi[f], hi[f], acc);
+                if constexpr (NT > 1) {
+                    acc = mfma16(hi[f], lo[f], acc);
+                    acc = mfma16(lo[f], hi[f], acc);
+                }
+            }
+        }
+        sq += __shfl_xor(sq, 16);
+        sq += __shfl_xor(sq, 32);
+        // key terms: d(p, v) for float rows, |v|^2 for exact rows
+        const float uj = NT > 1 ? dj : sq;
+        const bool intd = NT == 1 && metric != 2;
+        const int tj = intd ? dom_threshold(alpha, inv_alpha, dj) : 0;
+        const int uji = intd && metric == 0 ? (int)uj : 0;
+        // pairs (ii, jr), ii = 4 q + r, ii < jr
+        u64 bt[4], ut[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ii = 4 * q + r;
+            bool pred, unc = false;
+            if (intd) {
+                const int g = (int)acc[r];
+                const int dij = metric == 0 ? __shfl(uji, ii) + uji - 2 * g : 1 - g;
+                pred = ii < jr && dij <= tj;
+            } else {
+                const float ui = __shfl(uj, ii);
+                const float ni = __shfl(nj, ii);
+                const float si = __shfl(sq, ii);
+                const double gd = gram_dist(acc[r], metric, ui, uj, ni, nj);
+                pred = ii < jr && alpha * gd < (double)dj;
+                if constexpr (NT > 1)
+                    unc = ii < jr && idj >= 0 && a.band > 0.0 &&
+                          near_boundary(alpha, gd, dj, a.band, metric, ui, uj, si, sq);
+            }
+            bt[r] = __ballot(pred && !unc);
+            ut[r] = __ballot(unc);
+        }
+        if constexpr (NT > 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                u64 m = ut[r];
+                while (m) {
+                    const int l = __ffsll((long long)m) - 1;
+                    m &= m - 1;
+                    const int w = __builtin_amdgcn_readlane(idj, 4 * (l >> 4) + r);
+                    const int v = __builtin_amdgcn_readlane(idj, l & 15);
+                    const float dv =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dj), l & 15));
+                    const float dwv = walk_pair_dist<CPL>(a, w, v, lane);
+                    if (alpha * (double)dwv < (double)dv) bt[r] |= 1ull << l;
+                    ++nrecheck;
+                }
+            }
+        }
+        // each 16 kept rows against the tile
+        u64 bk = 0ull;
+        for (int kt = 0; kt < nkt; ++kt) {
+            const int kr = kt * 16 + jr;
+            const int kid = kr < nk0 ? kept_ids[kr] : -1;
+            floatx4_t ak = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int sl = 0; sl < nsl; ++sl) {
+                float pc[CENTER ? 32 : 1];
+                if constexpr (CENTER) centre(sl, pc);
+                float dummy = 0.0f;
+                uint4 hi[4], lo[4], khi[4], klo[4];
+                load_slice<NT>(a, idj, dim, sl * 128 + q * 32, CENTER ? pc : nullptr, hi, lo,
+                               dummy);
+                load_slice<NT>(a, kid, dim, sl * 128 + q * 32, CENTER ? pc : nullptr, khi, klo,
+                               dummy);
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    ak = mfma16(khi[f], hi[f], ak);
+                    if constexpr (NT > 1) {
+                        ak = mfma16(khi[f], lo[f], ak);
+                        ak = mfma16(klo[f], hi[f], ak);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ki = kt * 16 + 4 * q + r;
+                bool pred = false, unc = false;
+                if (ki < nk0) {
+                    if (intd) {
+                        const int g = (int)ak[r];
+                        const int dkj = metric == 0 ? (int)kept_u[ki] + uji - 2 * g : 1 - g;
+                        pred = dkj <= tj;
+                    } else {
+                        const float nkk = metric == 2 ? a.norms[kept_ids[ki]] : 1.0f;
+                        const double gd = gram_dist(ak[r], metric, kept_u[ki], uj, nkk, nj);
+                        pred = alpha * gd < (double)dj;
+                        if constexpr (NT > 1)
+                            unc = idj >= 0 && a.band > 0.0 &&
+                                  near_boundary(alpha, gd, dj, a.band, metric, kept_u[ki], uj,
+                                                kept_s[ki], sq);
+                    }
+                }
+                bk |= __ballot(pred && !unc);
+                if constexpr (NT > 1) {
+                    u64 m = __ballot(unc);
+                    while (m) {
+                        const int l = __ffsll((long long)m) - 1;
+                        m &= m - 1;
+                        const int w = kept_ids[kt * 16 + 4 * (l >> 4) + r];
+                        const int v = __builtin_amdgcn_readlane(idj, l & 15);
+                        const float dv =
+                            __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dj), l & 15));
+                        const float dwv = walk_pair_dist<CPL>(a, w, v, lane);
+                        if (alpha * (double)dwv < (double)dv) bk |= 1ull << l;
+                        ++nrecheck;
+                    }
+                }
+            }
+        }
+        const unsigned domk = (unsigned)((bk | (bk >> 16) | (bk >> 32) | (bk >> 48)) & 0xffffull);
+        unsigned mj = 0;
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) mj |= (unsigned)((bt[ii & 3] >> (16 * (ii >> 2) + jr)) & 1ull) << ii;
+        // resolve the 16 candidates in order (as k_prune_mfma)
+        const unsigned valid16 = (unsigned)(__ballot(key != EMPTY_KEY) & 0xffffull);
+        u64 kb = __shfl(key, (jr + 15) & 15);
+        if (jr == 0) kb = prev;
+        const unsigned dup16 = (unsigned)(__ballot(key == kb) & 0xffffull);
+        unsigned cand = valid16 & ~dup16 & ~domk;
+        unsigned keptj = 0;
+        bool stop = valid16 != 0xffffu;
+        while (cand) {
+            const int j = __builtin_ctz(cand);
+            cand &= cand - 1u;
+            const unsigned mjj = (unsigned)__builtin_amdgcn_readlane((int)mj, j);
+            if (mjj & keptj) continue;
+            keptj |= 1u << j;
+            if (nk + __popc(keptj) == R) {
+                stop = true;
+                break;
+            }
+        }
+        prev = readlane64(key, 15);
+        if (((keptj >> jr) & 1u) && q == 0) {
+            const int kr = nk + __popc(keptj & ((1u << jr) - 1u));
+            kept_ids[kr] = idj;
+            kept_u[kr] = uj;
+            kept_s[kr] = sq;
+            a.rows_out[p * R + kr] = idj;
+            a.dist_out[p * R + kr] = dj;
+            count_reverse(a, idj);
+        }
+        nk += __popc(keptj);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (stop) break;
+    }
+    if (lane == 0) {
+        a.deg_out[p] = nk;
+        if (nrecheck && a.rechecks)
+            atomicAdd(&a.rechecks[blockIdx.x & (CNT_SLOTS - 1)], (u64)nrecheck);
+    }
 }
 
 // ------------------------------------------------------------ small kernels
@@ -2112,12 +2542,41 @@ static void launch_prune_mfma_c(const PruneArgs& a, int nt, dim3 grid, dim3 bloc
         hipLaunchKernelGGL((k_prune_mfma<KD, 3, CPL>), grid, block, lds, st, a);
 }
 
-bool prune_mfma_supported(int dim) { return dim % 32 == 0 && dim >= 32 && dim <= 128; }
+// dims whose Grams the K-sliced kernel takes (slices of 128)
+static bool prune_ks_dim(int dim) { return dim % 128 == 0 && dim >= 256 && dim <= 1024; }
+
+bool prune_mfma_supported(int dim) {
+    return (dim % 32 == 0 && dim >= 32 && dim <= 128) || prune_ks_dim(dim);
+}
 
 bool prune_mfma_fits(const PruneArgs& a, int nt) {
     const int dim = a.nch * 4;
-    return prune_mfma_supported(dim) && a.R <= 64 &&
-           mfma_prune_lds(a.wcap, a.R, dim / 32, nt) <= 64 * 1024;
+    if (!prune_mfma_supported(dim) || a.R > 64) return false;
+    if (prune_ks_dim(dim)) return mfma_ks_lds(a.wcap, a.R) <= 64 * 1024;
+    return mfma_prune_lds(a.wcap, a.R, dim / 32, nt) <= 64 * 1024;
+}
+
+static hipError_t launch_prune_mfma_ks(const PruneArgs& b, int nt, hipStream_t st) {
+    const size_t per = mfma_ks_lds(b.wcap, b.R);
+    int wpb = 4;
+    while (wpb > 1 && per * wpb > 64 * 1024) --wpb;
+    const size_t lds = (size_t)wpb * per;
+    const dim3 grid(nblk(b.n_items, wpb)), block(wpb * WAVE);
+    // the float32 walk's layout (collect_dists, the re-decided pairs);
+    // float rows are centred at p for squared L2
+    const bool ctr = nt != 1 && b.metric == 0;
+    if (b.cpl == 3) {
+        if (nt == 1) hipLaunchKernelGGL((k_prune_mfma_ks<1, false, 3>), grid, block, lds, st, b);
+        else if (ctr) hipLaunchKernelGGL((k_prune_mfma_ks<3, true, 3>), grid, block, lds, st, b);
+        else hipLaunchKernelGGL((k_prune_mfma_ks<3, false, 3>), grid, block, lds, st, b);
+    } else if (b.cpl == 4) {
+        if (nt == 1) hipLaunchKernelGGL((k_prune_mfma_ks<1, false, 4>), grid, block, lds, st, b);
+        else if (ctr) hipLaunchKernelGGL((k_prune_mfma_ks<3, true, 4>), grid, block, lds, st, b);
+        else hipLaunchKernelGGL((k_prune_mfma_ks<3, false, 4>), grid, block, lds, st, b);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_prune_mfma(const PruneArgs& a, int nt, hipStream_t st) {
@@ -2125,6 +2584,14 @@ hipError_t launch_prune_mfma(const PruneArgs& a, int nt, hipStream_t st) {
     const int dim = a.nch * 4;
     if (!prune_mfma_fits(a, nt) || (nt != 1 && nt != 3)) return hipErrorInvalidValue;
     if (nt == 1 && !a.xb) return hipErrorInvalidValue;
+    if (prune_ks_dim(dim)) {
+        PruneArgs b = a;
+        b.G16 = lanes_per_row(dim / 8);
+        b.lgG16 = ilog2i(b.G16);
+        // the bfloat16 layout of collect_dists takes as many chunks per lane
+        if (b.G16 < 1 || (dim / 8) / b.G16 != a.cpl) return hipErrorInvalidValue;
+        return launch_prune_mfma_ks(b, nt, st);
+    }
     const int kd = dim / 32;
     PruneArgs b = a;
     // bfloat16 layout of prune_collect: dim / 8 chunks, as many per lane as
