@@ -287,6 +287,23 @@ rnsm_status rnsm_select_pivots(int64_t n, const int64_t* rk_offsets, const int32
                                int32_t* follower_pivot, int64_t* out_n_followers);
 
 /*
+ * The same pivot and follower selection on the device (the batched form's
+ * phase 2): the lazy greedy in parallel rounds. Each round, every uncovered
+ * vertex whose key (gain, then the smaller id) is the largest at itself and
+ * at each of its uncovered followers, among the uncovered vertices listing
+ * that position, becomes a pivot and takes its uncovered followers. Such a
+ * vertex is also the sequential greedy's pick before any vertex it competes
+ * with, with the same followers, so the result equals rnsm_select_pivots'.
+ * rk_offsets device [n+1] int64, rk_ids device int32 (as rnsm_select_pivots,
+ * repeats not allowed); pivot_of device [n] int32 output: -1 for a pivot,
+ * else the follower's pivot; *out_n_pivots (host) the pivot count.
+ * Synchronises `stream`. RNSM_EINVAL for NULL pointers, n out of range, or
+ * an id out of range or naming its own list's vertex.
+ */
+rnsm_status rnsm_select_pivots_device(int64_t n, const int64_t* rk_offsets, const int32_t* rk_ids,
+                                      int32_t* pivot_of, int64_t* out_n_pivots, void* stream);
+
+/*
  * Beam search (Algorithm 1) of nq queries in one graph.
  * g: the graph (local ids 0..n-1, device CSR), base: its n vectors
  * (search_dtype/search/f32 as in rnsm_vectors; base->n == g->n).

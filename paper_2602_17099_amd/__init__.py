@@ -23,7 +23,7 @@ DEVICE, HOST = 0, 1
 
 SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_select_pivots", "rnsm_search",
            "rnsm_search_noalloc", "rnsm_tune_search", "rnsm_build_graph", "rnsm_convert",
-           "rnsm_get_stats", "rnsm_last_error", "rnsm_csr_free"]
+           "rnsm_get_stats", "rnsm_last_error", "rnsm_csr_free", "rnsm_select_pivots_device"]
 
 _lib = None
 
@@ -116,6 +116,8 @@ def lib():
         L.rnsm_get_stats.argtypes = [P]
         L.rnsm_last_error.restype = C.c_char_p
         L.rnsm_last_error.argtypes = []
+        L.rnsm_select_pivots_device.restype = C.c_int
+        L.rnsm_select_pivots_device.argtypes = [C.c_int64, P, P, P, P, P]
         L.rnsm_csr_free.restype = None
         L.rnsm_csr_free.argtypes = [P]
         _lib = L
@@ -295,6 +297,18 @@ def select_pivots(rk_offsets, rk_ids):
                                     fol.ctypes.data_as(C.c_void_p),
                                     fp.ctypes.data_as(C.c_void_p), C.byref(nfl)))
     return piv[: npv.value].copy(), fol[: nfl.value].copy(), fp[: nfl.value].copy()
+
+
+def select_pivots_device(rk_offsets, rk_ids, stream=None):
+    """Device pivot selection over reverse lists (device int64 offsets, int32
+    ids): pivot_of device tensor (-1 pivots, else the pivot) and the count."""
+    import torch
+    n = rk_offsets.shape[0] - 1
+    piv = torch.empty(max(n, 1), dtype=torch.int32, device=rk_offsets.device)
+    npv = C.c_int64(0)
+    _check(lib().rnsm_select_pivots_device(n, _ptr(rk_offsets), _ptr(rk_ids), _ptr(piv),
+                                           C.byref(npv), _stream(stream)))
+    return piv[:n], npv.value
 
 
 def search(offsets, nbrs, entry, base, queries, ef, k, seeds=None, metric=L2SQ,

@@ -493,6 +493,64 @@ static rnsm_status rnsm_select_pivots_impl(int64_t n, const int64_t* rk_offsets,
     return RNSM_OK;
 }
 
+// Pivot selection on the device over reverse lists (off, ids) of n vertices:
+// rounds of the parallel rule until every vertex is covered (the host checks
+// after every `batch` rounds). pivot_of receives -1 for pivots, else the
+// pivot. Workspace buffers; the caller holds g_lock.
+static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off,
+                                    const int32_t* ids, int32_t* pivot_of, hipStream_t st,
+                                    int64_t* n_pivots, int batch = 8) {
+    unsigned char *cov, *sel;
+    u64 *key, *best;
+    int64_t *ctl, *h_ctl;
+    WS(cov, "sel_cov", n);
+    WS(sel, "sel_pick", n);
+    WS(key, "sel_key", sizeof(u64) * n);
+    WS(best, "sel_best", sizeof(u64) * n);
+    WS(ctl, "sel_ctl", sizeof(int64_t) * 4);
+    HS(h_ctl, "h_sel_ctl", sizeof(int64_t) * 4);
+    HIPCHK(launch_select_init(n, cov, sel, pivot_of, ctl, st));
+    // every round covers at least the vertex with the largest key
+    for (int64_t done = 0; done <= n + batch; done += batch) {
+        HIPCHK(launch_select_rounds(n, off, ids, cov, sel, key, best, pivot_of, ctl, batch, st));
+        HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (h_ctl[0] == 0) {
+            *n_pivots = h_ctl[1];
+            return RNSM_OK;
+        }
+    }
+    return fail(RNSM_EINTERNAL, "pivot selection did not cover every vertex");
+}
+
+static rnsm_status rnsm_select_pivots_device_impl(int64_t n, const int64_t* rk_offsets,
+                                                  const int32_t* rk_ids, int32_t* pivot_of,
+                                                  int64_t* out_n_pivots, void* stream) {
+    g_err.clear();
+    if (n < 0 || n > INT32_MAX)
+        return fail(RNSM_EINVAL, "rnsm_select_pivots_device: n out of range");
+    if (!out_n_pivots || (n > 0 && (!rk_offsets || !rk_ids || !pivot_of)))
+        return fail(RNSM_EINVAL, "rnsm_select_pivots_device: NULL pointer");
+    *out_n_pivots = 0;
+    if (n == 0) return RNSM_OK;
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    Workspace& ws = g_ws[dev];
+    ws.begin_call(0);
+    int *flag, hflag = 0;
+    WS(flag, "sel_check", sizeof(int));
+    HIPCHK(launch_zero(flag, sizeof(int), st));
+    HIPCHK(launch_check_lists(n, rk_offsets, rk_ids, flag, st));
+    HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hflag)
+        return fail(RNSM_EINVAL, "rnsm_select_pivots_device: malformed lists (offsets, an id out "
+                    "of range or a list naming its owner)");
+    return select_on_device(ws, n, rk_offsets, rk_ids, pivot_of, st, out_n_pivots);
+}
+
 static rnsm_status tune_shape_locked(const rnsm_graph* g, const rnsm_vectors* base,
                                      const VecInfo& vi, int32_t ef, rnsm_metric metric,
                                      int64_t n_sample, int maxdeg, rnsm_search_tuning* out,
@@ -2079,6 +2137,14 @@ rnsm_status rnsm_search_noalloc(const rnsm_graph* g, const rnsm_vectors* base,
     return guard("rnsm_search_noalloc", [&] {
         return rnsm_search_noalloc_impl(g, base, queries, nq, seeds, n_seeds, ef, k, metric,
                                         out_ids, out_dists, stream);
+    });
+}
+
+rnsm_status rnsm_select_pivots_device(int64_t n, const int64_t* rk_offsets, const int32_t* rk_ids,
+                                      int32_t* pivot_of, int64_t* out_n_pivots, void* stream) {
+    return guard("rnsm_select_pivots_device", [&] {
+        return rnsm_select_pivots_device_impl(n, rk_offsets, rk_ids, pivot_of, out_n_pivots,
+                                              stream);
     });
 }
 

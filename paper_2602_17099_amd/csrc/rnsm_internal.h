@@ -121,6 +121,18 @@ hipError_t launch_search(int tt, const SearchArgs& a, int waves_per_block, hipSt
 hipError_t launch_norms16(const void* X, int tt, int64_t n, int dim, float* out, hipStream_t st);
 // zero bytes (a multiple of 4) at p with a kernel (no memset node in a captured graph)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// pivot selection on the device (the lazy greedy in parallel rounds, the same
+// pivots and groups): init, then `rounds` rounds (each a no-op once ctl[0],
+// the uncovered count, is 0); ctl[1] counts pivots. pivot_of: -1 pivot, else
+// the pivot's id
+hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids, int* flag,
+                              hipStream_t st);
+hipError_t launch_select_init(int64_t n, unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
+                              int64_t* ctl, hipStream_t st);
+hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* ids,
+                                unsigned char* cov, unsigned char* sel, unsigned long long* key,
+                                unsigned long long* best, int32_t* pivot_of, int64_t* ctl,
+                                int rounds, hipStream_t st);
 // static device scratch of the allocation-free search (bytes per device) and
 // its address on the current device (looked up once per device)
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;

@@ -2798,6 +2798,143 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
     return hipGetLastError();
 }
 
+// ------------------------------------------------- pivot selection on the device
+
+// The lazy greedy of Algorithm 2 (phase 2) in parallel rounds. Every
+// uncovered vertex x has the key (gain, smaller id first) with gain = |R_k(x)
+// minus Covered|; x becomes a pivot in a round when its key is the largest,
+// among the uncovered vertices, at x itself and at each of its uncovered
+// followers (positions whose best key comes from the vertex there and from
+// the vertices listing it). Such an x is also the sequential greedy's pick
+// before any vertex it competes with, with the same followers, and picks that
+// share no position commute, so the pivots and follower groups are the
+// greedy's. ctl[0]: uncovered vertices left (every kernel returns when 0),
+// ctl[1]: pivots, ctl[2]: rounds that picked something.
+__global__ void k_sel_init(int64_t n, unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
+                           int64_t* ctl) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) {
+        cov[x] = 0;
+        sel[x] = 0;
+        pivot_of[x] = -2;
+    }
+    if (x == 0) {
+        ctl[0] = n;
+        ctl[1] = 0;
+        ctl[2] = 0;
+    }
+}
+
+__global__ void k_sel_keys(int64_t n, const int64_t* off, const int32_t* ids,
+                           const unsigned char* cov, u64* key, u64* best, const int64_t* ctl) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n || ctl[0] == 0 || cov[x]) return;
+    int64_t g = 0;
+    for (int64_t j = off[x]; j < off[x + 1]; ++j) g += cov[ids[j]] ? 0 : 1;
+    const u64 k = ((u64)g << 32) | (u64)(0xffffffffu - (unsigned)x);
+    key[x] = k;
+    best[x] = k;
+}
+
+__global__ void k_sel_spread(int64_t n, const int64_t* off, const int32_t* ids,
+                             const unsigned char* cov, const u64* key, u64* best,
+                             const int64_t* ctl) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n || ctl[0] == 0 || cov[x]) return;
+    const u64 k = key[x];
+    for (int64_t j = off[x]; j < off[x + 1]; ++j) {
+        const int32_t y = ids[j];
+        if (!cov[y] && best[y] < k) atomicMax(&best[y], k);
+    }
+}
+
+__global__ void k_sel_pick(int64_t n, const int64_t* off, const int32_t* ids,
+                           const unsigned char* cov, const u64* key, const u64* best,
+                           unsigned char* sel, const int64_t* ctl) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n || ctl[0] == 0 || cov[x]) return;
+    const u64 k = key[x];
+    bool ok = best[x] == k;
+    for (int64_t j = off[x]; j < off[x + 1] && ok; ++j) {
+        const int32_t y = ids[j];
+        if (!cov[y] && best[y] != k) ok = false;
+    }
+    sel[x] = ok ? 1 : 0;
+}
+
+// the picks of the round take themselves and their uncovered followers; no
+// two picks share an uncovered follower and none is another's, so the
+// coverage each reads is the round's starting one where it matters
+__global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids,
+                            unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
+                            int64_t* ctl) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool pick = x < n && ctl[0] != 0 && sel[x];
+    int64_t taken = 0;
+    if (pick) {
+        sel[x] = 0;
+        for (int64_t j = off[x]; j < off[x + 1]; ++j) {
+            const int32_t y = ids[j];
+            if (!cov[y]) {
+                pivot_of[y] = (int32_t)x;
+                cov[y] = 1;
+                ++taken;
+            }
+        }
+        pivot_of[x] = -1;
+        cov[x] = 1;
+        ++taken;
+    }
+    // one atomic per wavefront for the counts
+    const u64 any = __ballot(pick);
+    if (any == 0ull) return;
+    int64_t t = taken;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+    if (lane_id() == __ffsll((long long)any) - 1) {
+        atomicAdd((unsigned long long*)&ctl[0], (unsigned long long)(-t));
+        atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)__popcll(any));
+    }
+}
+
+// reverse lists of a device caller: ids in range and not the list's owner
+__global__ void k_check_lists(int64_t n, const int64_t* off, const int32_t* ids, int* flag) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int64_t b = off[x], e = off[x + 1];
+    bool bad = b > e || b < 0 || e > off[n];
+    for (int64_t j = b; j < e && !bad; ++j) bad = ids[j] < 0 || ids[j] >= n || ids[j] == x;
+    if (bad) atomicOr(flag, 1);
+}
+
+hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids, int* flag,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_lists, dim3(nblk(n, 256)), dim3(256), 0, st, n, off, ids, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_init(int64_t n, unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
+                              int64_t* ctl, hipStream_t st) {
+    hipLaunchKernelGGL(k_sel_init, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, st, n, cov, sel,
+                       pivot_of, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* ids,
+                                unsigned char* cov, unsigned char* sel, u64* key, u64* best,
+                                int32_t* pivot_of, int64_t* ctl, int rounds, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const dim3 g(nblk(n, 256)), b(256);
+    for (int r = 0; r < rounds; ++r) {
+        hipLaunchKernelGGL(k_sel_keys, g, b, 0, st, n, off, ids, cov, key, best, ctl);
+        hipLaunchKernelGGL(k_sel_spread, g, b, 0, st, n, off, ids, cov, key, best, ctl);
+        hipLaunchKernelGGL(k_sel_pick, g, b, 0, st, n, off, ids, cov, key, best, sel, ctl);
+        hipLaunchKernelGGL(k_sel_apply, g, b, 0, st, n, off, ids, cov, sel, pivot_of, ctl);
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------- static scratch of rnsm_search_noalloc
 
 // The scratch memory of the allocation-free search entry point (counters,

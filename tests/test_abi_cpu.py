@@ -303,3 +303,14 @@ def test_csr_free_only_releases_library_arrays(pkg):
     L.rnsm_csr_free(C.byref(empty))
     assert empty.mem == pkg.DEVICE and not empty.offsets
 
+
+def test_select_pivots_device_rejects_on_host(pkg):
+    L = pkg.lib()
+    n = C.c_int64(0)
+    assert L.rnsm_select_pivots_device(-1, C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                                       C.byref(n), None) == 1
+    assert L.rnsm_select_pivots_device(4, None, C.c_void_p(8), C.c_void_p(8), C.byref(n),
+                                       None) == 1
+    assert "NULL" in pkg.last_error()
+    assert L.rnsm_select_pivots_device(0, None, None, None, C.byref(n), None) == 0
+

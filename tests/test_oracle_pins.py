@@ -234,6 +234,60 @@ def test_lazy_greedy_equals_eager(orc, seed):
             assert pivot_of[pivot_of[y]] == -1
 
 
+def _parallel_local_max(rk):
+    """The pivot rule in rounds: each uncovered x gets the key (gain, -x); x
+    is picked when its key is the largest at itself and at each of its
+    uncovered followers among the uncovered vertices whose list (or self)
+    holds that position; every pick takes its uncovered followers at once."""
+    n = len(rk)
+    cov = [False] * n
+    pivot_of = [None] * n
+    rounds = 0
+    while not all(cov):
+        rounds += 1
+        key = {x: (sum(1 for y in rk[x] if not cov[y]), -x) for x in range(n) if not cov[x]}
+        best = dict(key)
+        for x, kx in key.items():
+            for y in rk[x]:
+                if not cov[y] and kx > best[y]:
+                    best[y] = kx
+        picks = [x for x, kx in key.items()
+                 if best[x] == kx and all(best[y] == kx for y in rk[x] if not cov[y])]
+        assert picks
+        for x in picks:
+            for y in rk[x]:
+                if not cov[y]:
+                    pivot_of[y] = x
+            pivot_of[x] = -1
+        for x in picks:
+            cov[x] = True
+            for y in rk[x]:
+                cov[y] = True
+    return pivot_of, rounds
+
+
+@pytest.mark.parametrize("seed,n,k,hub", [(0, 60, 3, False), (1, 200, 5, False), (2, 400, 2, True),
+                                          (3, 300, 5, True), (4, 30, 8, False)])
+def test_parallel_local_max_rule_equals_greedy(orc, seed, n, k, hub):
+    # the rule the device runs in parallel rounds picks the same pivots and
+    # follower groups as the lazy greedy with its ties: a vertex whose key tops
+    # every competitor's (shared uncovered follower, or one in the other's
+    # list) is the greedy's pick before any of them, with the same gain, and
+    # picks that share nothing commute
+    g = np.random.default_rng(seed)
+    nk = np.array([g.choice([u for u in range(n) if u != v], k, replace=False) for v in range(n)],
+                  np.int32)
+    if hub:  # a vertex in most lists (ties and long lists)
+        nk[g.random(n) < 0.6, 0] = 0
+        nk[0, 0] = 1
+    off, ids = orc.invert(nk)
+    pivot_of, _ = orc.pivots(off, ids)
+    rk = [ids[off[x]:off[x + 1]].tolist() for x in range(n)]
+    par, rounds = _parallel_local_max(rk)
+    assert par == pivot_of.tolist()
+    assert rounds < n
+
+
 def test_pivots_dominate(orc):
     # the pivots dominate the undirected R_k graph, so they are no fewer than a
     # minimum dominating set (brute force on 12 vertices)
