@@ -268,13 +268,14 @@ def multiway(pkg, scale, steps, warmup):
                    torch.empty(N * 32, dtype=torch.int32, device=dev),
                    torch.empty(N * 32, dtype=torch.float32, device=dev)))
 
-    def run(shape=None):
+    def run(shape=None, extra_flags=0):
+        kw2 = dict(kw, flags=kw["flags"] | extra_flags)
         for _ in range(warmup):
-            pkg.merge(subs, Xd, search_shape=shape, **kw)
+            pkg.merge(subs, Xd, search_shape=shape, **kw2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            res = pkg.merge(subs, Xd, search_shape=shape, **kw)
+            res = pkg.merge(subs, Xd, search_shape=shape, **kw2)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, pkg.stats(), res
 
@@ -297,6 +298,16 @@ def multiway(pkg, scale, steps, warmup):
     tune = pkg.tune_search(o, g, e, Xd[b0:b0 + sizes[big]], 64, n_sample=65536, metric=IP)
     dtt, _, rt = run(tuple(tune["shape"]))
     same = bool(torch.equal(rt[0], off_c) and torch.equal(rt[1], nb_c))
+    # the batched form: operations sharing no sub-index in one round
+    dtq, stq, rq = run(extra_flags=pkg.FLAG_BATCHED)
+    batched = {"ms_per_merge": 1000.0 * dtq, "value": stq["n_source_vertices"] / dtq,
+               "speedup_vs_plain": dt / dtq, "rounds": stq["n_rounds"],
+               "same_graph": bool(torch.equal(rq[0], off_c) and torch.equal(rq[1], nb_c)),
+               "phase_ms": {"expansion_search": stq["ms_search"][0], "order": stq["ms_order"],
+                            "select": stq["ms_select"], "groups": stq["ms_groups"],
+                            "group_search": stq["ms_search"][1],
+                            "overflow_search": stq["ms_search"][2],
+                            "prune_and_reverse": stq["ms_prune"], "total": stq["ms_total"]}}
     return {"workload": f"{len(sizes)} uneven slab sub-indexes, {N:,} L2-normalised vectors, "
                         f"dim 96, inner product, R=32, L=64, alpha=1.2, MOS degree 4",
             "scale_of_10M": scale, "sizes": sizes, "operations": st["n_ops"],
@@ -309,7 +320,8 @@ def multiway(pkg, scale, steps, warmup):
                          "compact": st["ms_compact"], "total": st["ms_total"]},
             "autotune": {"shape": list(tune["shape"]), "default_shape": list(tune["default_shape"]),
                          "sample_ms": tune["ms"], "default_sample_ms": tune["default_ms"],
-                         "ms_per_merge": 1000.0 * dtt, "same_graph": same}}
+                         "ms_per_merge": 1000.0 * dtt, "same_graph": same},
+            "batched_form": batched}
 
 
 def precision768(pkg, scale, steps, warmup):
@@ -501,6 +513,9 @@ def main():
     ap.add_argument("--one-stream", action="store_true",
                     help="every search launch alone on one stream for the whole run (for "
                          "profiles and counters: kernel times are then exclusive)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched form (operations in rounds, device pivot selection, "
+                         "one persistent pivot-group search per round)")
     ap.add_argument("--bf16-only", action="store_true",
                     help="only the bfloat16 form's merges (profiles and counters of its kernels)")
     args = ap.parse_args()
@@ -614,6 +629,34 @@ def main():
                 "roofline": rb}
         log(f"bf16 search copy: {bf16}")
 
+    # the batched form on the same inputs: same graph, its own time
+    batched = None
+    if not args.no_batched:
+        batched = {}
+        forms = [("fp32", None, value)]
+        if bf16 is not None:
+            forms.append(("bf16", Xb, bf16["value"]))
+        for name, search, v_plain in forms:
+            dtq, _, stq, resq = time_merges(pkg, subs, Xd, wl, args.steps, args.warmup,
+                                            search=search, flags=pkg.FLAG_BATCHED)
+            vq = args.steps * stq["n_source_vertices"] / dtq
+            batched[name] = {"value": vq, "ms_per_step": 1000.0 * dtq / args.steps,
+                             "speedup_vs_plain": vq / v_plain,
+                             "same_graph": bool(torch.equal(resq[0], off) and
+                                                torch.equal(resq[1], nb)),
+                             "rounds": stq["n_rounds"],
+                             "group_blocks": stq["group_blocks"],
+                             "overflow_followers": stq["group_overflow"],
+                             "select_rounds": stq["select_rounds"],
+                             "phase_ms": {"expansion_search": stq["ms_search"][0],
+                                          "order": stq["ms_order"], "select": stq["ms_select"],
+                                          "groups": stq["ms_groups"],
+                                          "group_search": stq["ms_search"][1],
+                                          "overflow_search": stq["ms_search"][2],
+                                          "prune_and_reverse": stq["ms_prune"],
+                                          "total": stq["ms_total"]}}
+        log(f"batched form: {batched}")
+
     # cross-query merge (every source vertex a pivot: naive searches only, no
     # expansion, greedy or sliding), the comparison the paper makes for RNSM;
     # fewer steps, since each merge runs ~5x the naive searches
@@ -660,6 +703,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "bf16_form": bf16,
+        "batched_form": batched,
         "cross_query_merge": cm,
         "incremental": inc,
         "autotune": tuned,

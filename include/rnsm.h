@@ -77,6 +77,11 @@ typedef enum { RNSM_F32 = 0, RNSM_BF16 = 1, RNSM_F16 = 2, RNSM_U8 = 3 } rnsm_dty
                                        the caller's out pointers are ignored */
 #define RNSM_FLAG_NO_STATS 16u      /* skip the device timing events and counter read-back of
                                        rnsm_get_stats (its times and counts stay zero) */
+#define RNSM_FLAG_BATCHED 32u       /* the batched form: operations in rounds of the plan
+                                       (operations sharing no sub-index together), pivot selection
+                                       on the device, and one persistent launch per round that
+                                       searches every pivot group (pivot, then its followers) of
+                                       the round's operations; the same merged graph */
 
 /*
  * One input sub-index: a flat proximity graph (Section 2.2) over n vectors.
@@ -228,6 +233,15 @@ typedef struct {
     int64_t prune_rechecks; /* prune_path 3: vertex pairs whose split-Gram estimate lay near the
                                alpha boundary and were decided with float32 arithmetic on
                                the original rows instead */
+    int64_t n_rounds;       /* rounds of operations: the batched form runs the operations that
+                               share no sub-index together; the plain form one per round */
+    int64_t group_blocks;   /* batched form: blocks of the last round's persistent group search */
+    int64_t group_overflow; /* batched form: followers past the first 2 of their pivot's group,
+                               searched by a plain launch after the group search */
+    double ms_order;        /* batched form: breadth-first orders of the sources (device time) */
+    double ms_select;       /* batched form: pivot selection (device time) */
+    int64_t select_rounds;  /* batched form: rounds of the parallel pivot selection */
+    double ms_groups;       /* batched form: pivot groups, overflow lists and prune order */
 } rnsm_stats;
 
 /*

@@ -19,6 +19,7 @@ FLAG_CENTROID_COSTS = 2
 FLAG_AUTOTUNE = 4
 FLAG_HOST_OUT = 8
 FLAG_NO_STATS = 16
+FLAG_BATCHED = 32
 DEVICE, HOST = 0, 1
 
 SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_select_pivots", "rnsm_search",
@@ -75,7 +76,11 @@ class Stats(C.Structure):
                 ("hash_evictions", C.c_int64), ("row_bytes", C.c_int32),
                 ("exact_visited", C.c_int32), ("prune_path", C.c_int32),
                 ("ms_search_span", C.c_double), ("search_hash_bits", C.c_int32),
-                ("search_waves_per_block", C.c_int32), ("prune_rechecks", C.c_int64)]
+                ("search_waves_per_block", C.c_int32), ("prune_rechecks", C.c_int64),
+                ("n_rounds", C.c_int64), ("group_blocks", C.c_int64),
+                ("group_overflow", C.c_int64), ("ms_order", C.c_double),
+                ("ms_select", C.c_double), ("select_rounds", C.c_int64),
+                ("ms_groups", C.c_double)]
 
 
 def lib():

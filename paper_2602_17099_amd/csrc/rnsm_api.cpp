@@ -499,7 +499,7 @@ static rnsm_status rnsm_select_pivots_impl(int64_t n, const int64_t* rk_offsets,
 // pivot. Workspace buffers; the caller holds g_lock.
 static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off,
                                     const int32_t* ids, int32_t* pivot_of, hipStream_t st,
-                                    int64_t* n_pivots, int batch = 8) {
+                                    int64_t* n_pivots, int batch = 8, int64_t* rounds = nullptr) {
     unsigned char *cov, *sel;
     u64 *key, *best;
     int64_t *ctl, *h_ctl;
@@ -509,14 +509,22 @@ static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off
     WS(best, "sel_best", sizeof(u64) * n);
     WS(ctl, "sel_ctl", sizeof(int64_t) * 4);
     HS(h_ctl, "h_sel_ctl", sizeof(int64_t) * 4);
-    HIPCHK(launch_select_init(n, cov, sel, pivot_of, ctl, st));
+    int32_t* longv;
+    WS(longv, "sel_long", sizeof(int32_t) * std::max<int64_t>(n, 1));
+    HIPCHK(launch_select_init(n, off, cov, sel, pivot_of, longv, ctl, st));
+    HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t nlong = h_ctl[3];
+    if (nlong < 0 || nlong > n) return fail(RNSM_EINTERNAL, "pivot selection: bad long-list count");
     // every round covers at least the vertex with the largest key
     for (int64_t done = 0; done <= n + batch; done += batch) {
-        HIPCHK(launch_select_rounds(n, off, ids, cov, sel, key, best, pivot_of, ctl, batch, st));
-        HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 2, hipMemcpyDeviceToHost, st));
+        HIPCHK(launch_select_rounds(n, off, ids, cov, sel, key, best, pivot_of, ctl, longv, nlong,
+                                    batch, st));
+        HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (h_ctl[0] == 0) {
             *n_pivots = h_ctl[1];
+            if (rounds) *rounds = h_ctl[2];
             return RNSM_OK;
         }
     }
@@ -797,18 +805,24 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     const bool use_bfs = !getenv("RNSM_NO_BFS_ORDER");
     const bool one_stream = getenv("RNSM_ONE_STREAM") && atoi(getenv("RNSM_ONE_STREAM")) == 1;
     int32_t* h_bfs = nullptr;
-    auto bfs_order_of = [&](int s, hipStream_t strm, int32_t** order_out, int* ev_out) -> rnsm_status {
+    // (per_source: the batched form's order buffer of its own per source, no
+    // host copy; the plain form's one buffer and its host copy otherwise)
+    auto bfs_order_of = [&](int s, hipStream_t strm, int32_t** order_out, int* ev_out,
+                            bool per_source = false) -> rnsm_status {
         const int64_t ns = sizes[s];
         int32_t* bfs_order;
         unsigned *bfs_vis, *bfs_tail, *h_tail;
-        WS(bfs_order, "bfs_order", sizeof(int32_t) * ns);
-        WS(bfs_vis, "bfs_visited", sizeof(unsigned) * ((ns + 31) / 32));
-        WS(bfs_tail, "bfs_ctl", 4 * sizeof(unsigned));
-        HS(h_tail, "h_bfs_ctl", 4 * sizeof(unsigned));
-        HS(h_bfs, "h_bfs_order", sizeof(int32_t) * ns);
+        const std::string oname = per_source ? "bt_bfs_" + std::to_string(s) : "bfs_order";
+        WS(bfs_order, oname, sizeof(int32_t) * ns);
+        WS(bfs_vis, per_source ? "bt_bfs_visited" : "bfs_visited", sizeof(unsigned) * ((ns + 31) / 32));
+        WS(bfs_tail, per_source ? "bt_bfs_ctl" : "bfs_ctl", 4 * sizeof(unsigned));
+        HS(h_tail, per_source ? "h_bt_bfs_ctl" : "h_bfs_ctl", 4 * sizeof(unsigned));
         HIPCHK(launch_bfs_order(padj + bases[s] * R, R, ns, graphs[s].entry, bfs_vis, bfs_order,
                                 bfs_tail, h_tail, strm));
-        HIPCHK(hipMemcpyAsync(h_bfs, bfs_order, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, strm));
+        if (!per_source) {
+            HS(h_bfs, "h_bfs_order", sizeof(int32_t) * ns);
+            HIPCHK(hipMemcpyAsync(h_bfs, bfs_order, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, strm));
+        }
         HIPCHK(E.record(strm, ev_out));
         *order_out = bfs_order;
         return RNSM_OK;
@@ -817,12 +831,31 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     HIPCHK(ws.side_stream(&sd));
     int32_t* bfs0 = nullptr;
     int ev_bfs0 = -1;
-    const bool bfs_early =
-        use_bfs && !ops.empty() && !(p->flags & RNSM_FLAG_ALL_PIVOTS) && sizes[ops[0].first] > 0;
+    const bool batched = (p->flags & RNSM_FLAG_BATCHED) != 0;
+    const bool bfs_early = use_bfs && !batched && !ops.empty() &&
+                           !(p->flags & RNSM_FLAG_ALL_PIVOTS) && sizes[ops[0].first] > 0;
     if (bfs_early) {
         HIPCHK(hipStreamWaitEvent(sd, E.ev[ev_padj], 0));
         const rnsm_status bs = bfs_order_of(ops[0].first, sd, &bfs0, &ev_bfs0);
         if (bs != RNSM_OK) return bs;
+    }
+    // the batched form: orders of the first round's sources (operations that
+    // share no sub-index with an earlier one), made on the side stream during
+    // the set-up as well
+    std::vector<int> bt_ev_bfs(m, -1), bt_ev_bfs0(m, -1);
+    std::vector<int32_t*> bt_bfs(m, nullptr);
+    if (batched && use_bfs && !(p->flags & RNSM_FLAG_ALL_PIVOTS)) {
+        HIPCHK(hipStreamWaitEvent(sd, E.ev[ev_padj], 0));
+        std::vector<char> used(m, 0);
+        for (size_t a1 = 0; a1 < ops.size(); ++a1) {
+            const int s = ops[a1].first, t = ops[a1].second;
+            const bool first_round = !used[s] && !used[t];
+            used[s] = used[t] = 1;
+            if (!first_round || sizes[s] == 0 || bt_bfs[s]) continue;
+            HIPCHK(E.stat(sd, &bt_ev_bfs0[s]));
+            const rnsm_status bs = bfs_order_of(s, sd, &bt_bfs[s], &bt_ev_bfs[s], true);
+            if (bs != RNSM_OK) return bs;
+        }
     }
     ValueInfo vinfo;
     HIPCHK(hipEventSynchronize(E.ev[ev_vr]));
@@ -864,6 +897,414 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     std::vector<char> touched(m, 0);  // rows changed by an earlier operation
     std::vector<int32_t> rank, fbeg, fcnt;
     std::vector<uint64_t> rbits;
+
+    // The batched form (RNSM_FLAG_BATCHED). Operations run in rounds: an
+    // operation's round is one past the last earlier operation sharing a
+    // sub-index with it, so the operations of a round touch disjoint rows and
+    // commute. Per round: for each source not prepared yet, neighbour
+    // expansion, reverse inversion, pivot selection on the device (the same
+    // pivots and groups as the host greedy) and its pivot groups in
+    // breadth-first order; then one persistent launch searches every group of
+    // every operation of the round (k_group_search); then each operation's
+    // source prune, reverse edges and target prune, as in the plain form.
+    std::vector<std::array<int, 4>> ev_rounds;  // group search start / end, overflow end, prunes end
+    std::vector<std::array<int, 3>> sel_ev;     // selection start, groups start, groups end
+    std::vector<std::array<int, 2>> ord_ev;     // breadth-first order start / end
+    int64_t n_rounds_b = 0;
+    auto batched_ops = [&]() -> rnsm_status {
+        const int nops = (int)ops.size();
+        std::vector<int> round_of(nops, 0);
+        int nrounds = 0;
+        for (int a1 = 0; a1 < nops; ++a1) {
+            for (int b1 = 0; b1 < a1; ++b1) {
+                const bool share = ops[a1].first == ops[b1].first || ops[a1].first == ops[b1].second ||
+                                   ops[a1].second == ops[b1].first || ops[a1].second == ops[b1].second;
+                if (share) round_of[a1] = std::max(round_of[a1], round_of[b1] + 1);
+            }
+            nrounds = std::max(nrounds, round_of[a1] + 1);
+        }
+        n_rounds_b = nrounds;
+        const bool all_piv = (p->flags & RNSM_FLAG_ALL_PIVOTS) != 0;
+        std::vector<char> prepared(m, 0);
+        std::vector<int64_t> src_np(m, 0), src_nf(m, 0);
+        int64_t* gstmp;
+        WS(gstmp, "bt_scan_tmp", sizeof(int64_t) * scan_tmp_elems(N));
+        // followers per group work item; the rest of a larger group (a hub's
+        // reverse list can hold thousands) goes to a plain sliding launch
+        // after the group search, so no wavefront runs a long serial tail
+        int64_t fmax = 2;  // measured fastest of 2..32 on 2 x 500,000 (dim 128)
+        if (const char* c = getenv("RNSM_GROUP_FMAX")) fmax = std::max(1ll, atoll(c));
+        int64_t* h_novf;
+        HS(h_novf, "h_bt_novf", sizeof(int64_t) * m);
+        // rounds of the pivot selection between the host's checks
+        int select_batch = 16;
+        if (const char* c = getenv("RNSM_SELECT_BATCH")) select_batch = std::max(1, atoi(c));
+        // per-source buffers (a source's groups are read by a later round too)
+        auto src_buf = [&](const char* what, int s2, size_t bytes, void** out) -> rnsm_status {
+            HIPCHK(ws.get(std::string(what) + std::to_string(s2), bytes, out));
+            return RNSM_OK;
+        };
+        int op_slot = 0;
+        for (int rr = 0; rr < nrounds; ++rr) {
+            std::vector<int> rops;
+            for (int oi = 0; oi < nops; ++oi)
+                if (round_of[oi] == rr) rops.push_back(oi);
+            // ---- sources of the round: expansion, inversion, selection, groups
+            int ev_novf = -1;
+            for (int oi : rops) {
+                const int s = ops[oi].first;
+                if (prepared[s]) continue;
+                const int64_t ns = sizes[s];
+                int32_t *pivot_of, *gpiv, *fbeg_d, *fol, *porder;
+                int64_t* fbeg64;
+                rnsm_status rs;
+                if ((rs = src_buf("bt_pivot_of_", s, sizeof(int32_t) * ns, (void**)&pivot_of)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_gpiv_", s, sizeof(int32_t) * ns, (void**)&gpiv)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_fbeg_", s, sizeof(int64_t) * (ns + 1), (void**)&fbeg64)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_fol_", s, sizeof(int32_t) * ns, (void**)&fol)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_order_", s, sizeof(int32_t) * ns, (void**)&porder)) != RNSM_OK) return rs;
+                (void)fbeg_d;
+                int32_t* bfs_order = nullptr;
+                if (bt_bfs[s]) {  // made on the side stream during the set-up
+                    bfs_order = bt_bfs[s];
+                    HIPCHK(hipStreamWaitEvent(st, E.ev[bt_ev_bfs[s]], 0));
+                    ord_ev.push_back({bt_ev_bfs0[s], bt_ev_bfs[s]});
+                } else if (use_bfs && !all_piv) {
+                    int ev_a = -1, ev_b = -1;
+                    HIPCHK(E.stat(st, &ev_a));
+                    const rnsm_status bs = bfs_order_of(s, st, &bfs_order, &ev_b, true);
+                    if (bs != RNSM_OK) return bs;
+                    ord_ev.push_back({ev_a, ev_b});
+                }
+                int64_t np = ns;
+                int ev_sel0 = -1;
+                if (all_piv) {
+                    HIPCHK(launch_fill32(pivot_of, ns, -1, st));
+                } else {
+                    int32_t *nk, *rcnt, *rk_ids;
+                    int64_t *rk_off, *stmp;
+                    WS(nk, "nk", sizeof(int32_t) * ns * k);
+                    WS(rcnt, "rk_cnt", sizeof(int32_t) * ns);
+                    WS(rk_off, "rk_off", sizeof(int64_t) * (ns + 1));
+                    WS(rk_ids, "rk_ids", sizeof(int32_t) * std::max<int64_t>(ns * k, 1));
+                    WS(stmp, "scan_tmp", sizeof(int64_t) * scan_tmp_elems(ns));
+                    std::array<int, 3> ex;
+                    HIPCHK(E.stat(st, &ex[0]));
+                    SearchArgs a = {};
+                    a.base = vi.search + bases[s] * vi.row_bytes;
+                    a.nch = vi.nch;
+                    a.row_bytes = vi.row_bytes;
+                    a.offs = graphs[s].offsets;
+                    a.nbrs = graphs[s].nbrs;
+                    a.padj = padj + bases[s] * R;
+                    a.rp = R;
+                    a.n = ns;
+                    a.qvec = a.base;
+                    a.qidx = bfs_order;
+                    a.out_row = bfs_order;
+                    a.nq = ns;
+                    a.seed_mode = 1;
+                    a.metric = p->metric;
+                    a.base_norm = norms ? norms + bases[s] : nullptr;
+                    a.q_norm = a.base_norm;
+                    a.ef = kp;
+                    a.G = vi.G;
+                    a.lgG = ilog2i(vi.G);
+                    a.cpl = vi.cpl;
+                    const SearchShape sh = search_shape(kp, R, ns, vi.tt, hb_req, wpb_req);
+                    a.hbits = sh.hbits;
+                    a.hash_mode = sh.mode;
+                    a.out_mode = 1;
+                    a.out_ids = nk;
+                    a.out_stride = k;
+                    a.out_k = k;
+                    a.counters = cnt + 0 * CNT_SLOTS * CNT_N;
+                    a.err = errf;
+                    if (!touched[s] && search_d_exact) {
+                        a.row_d = rdist;
+                        a.row_d_base = bases[s];
+                        a.row_d_stride = R;
+                    }
+                    HIPCHK(launch_search(vi.tt, a, sh.wpb, st));
+                    HIPCHK(E.stat(st, &ex[1]));
+                    HIPCHK(launch_count_ids(nk, ns, k, rcnt, st));
+                    HIPCHK(launch_invert_lists(nk, ns, k, rcnt, rk_off, rk_ids, stmp, st));
+                    HIPCHK(E.stat(st, &ex[2]));
+                    ev_exp.push_back(ex);
+                    g_stats.queries[0] += ns;
+                    g_stats.launches[0] += 1;
+                    int64_t nrs = 0;
+                    HIPCHK(E.stat(st, &ev_sel0));
+                    const rnsm_status ss = select_on_device(ws, ns, rk_off, rk_ids, pivot_of, st, &np,
+                                                            select_batch, &nrs);
+                    if (ss != RNSM_OK) return ss;
+                    g_stats.select_rounds += nrs;
+                }
+                int ev_sel1 = -1;
+                HIPCHK(E.stat(st, &ev_sel1));
+                int32_t *gflag, *group_of, *gcnt;
+                int64_t* gpos;
+                WS(gflag, "bt_flag", sizeof(int32_t) * ns);
+                WS(gpos, "bt_gpos", sizeof(int64_t) * (ns + 1));
+                WS(group_of, "bt_group_of", sizeof(int32_t) * ns);
+                WS(gcnt, "bt_gcnt", sizeof(int32_t) * std::max<int64_t>(np, 1));
+                HIPCHK(launch_groups(bfs_order, ns, pivot_of, gflag, gpos, gpiv, group_of, gcnt,
+                                     fbeg64, fol, porder, gstmp, np, st));
+                int32_t *ofl, *oflp;
+                int64_t* ooff;
+                if ((rs = src_buf("bt_ofl_", s, sizeof(int32_t) * ns, (void**)&ofl)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_oflp_", s, sizeof(int32_t) * ns, (void**)&oflp)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_ooff_", s, sizeof(int64_t) * (np + 1), (void**)&ooff)) != RNSM_OK) return rs;
+                HIPCHK(launch_group_overflow(np, ns - np, gpiv, fbeg64, fol, pivot_of, group_of, fmax,
+                                             gcnt, ooff, ofl, oflp, gstmp, st));
+                HIPCHK(hipMemcpyAsync(h_novf + s, ooff + np, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+                HIPCHK(E.record(st, &ev_novf));
+                sel_ev.push_back({ev_sel0, ev_sel1, ev_novf});
+                src_np[s] = np;
+                src_nf[s] = ns - np;
+                prepared[s] = 1;
+            }
+            // ---- one persistent search over the round's pivot groups
+            std::vector<GroupOp> gops;
+            int64_t total_groups = 0;
+            int hb_max = 0, mode_max = 0, wpb_min = 4;
+            for (int oi : rops) {
+                const int s = ops[oi].first, t = ops[oi].second;
+                const SearchShape a1 = search_shape(efN, R, sizes[t], vi.tt, hb_req, wpb_req);
+                const SearchShape b1 = search_shape(efS, R, sizes[t], vi.tt, hb_req, wpb_req);
+                mode_max = std::max({mode_max, a1.mode, b1.mode});
+                hb_max = std::max({hb_max, a1.hbits, b1.hbits});
+                wpb_min = std::min({wpb_min, a1.wpb, b1.wpb});
+                (void)s;
+            }
+            if (mode_max) hb_max = 13;
+            while (wpb_min > 1 && search_lds_bytes(hb_max, wpb_min) > 64 * 1024) --wpb_min;
+            std::vector<int32_t*> res_of(rops.size());
+            std::vector<float*> resd_of(rops.size());
+            for (size_t q = 0; q < rops.size(); ++q) {
+                const int oi = rops[q];
+                const int s = ops[oi].first, t = ops[oi].second;
+                const int64_t ns = sizes[s], nt = sizes[t];
+                rnsm_status rs;
+                int32_t *gpiv, *fol, *resq;
+                int64_t* fbeg64;
+                float* resdq;
+                if ((rs = src_buf("bt_gpiv_", s, sizeof(int32_t) * ns, (void**)&gpiv)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_fbeg_", s, sizeof(int64_t) * (ns + 1), (void**)&fbeg64)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_fol_", s, sizeof(int32_t) * ns, (void**)&fol)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_res_", s, sizeof(int32_t) * ns * RES, (void**)&resq)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_resd_", s, sizeof(float) * ns * RES, (void**)&resdq)) != RNSM_OK) return rs;
+                res_of[q] = resq;
+                resd_of[q] = resdq;
+                // beams shorter than RES leave -1 behind them for the prune
+                HIPCHK(launch_fill32(resq, ns * RES, -1, st));
+                GroupOp go = {};
+                SearchArgs a = {};
+                a.base = vi.search + bases[t] * vi.row_bytes;
+                a.nch = vi.nch;
+                a.row_bytes = vi.row_bytes;
+                a.offs = graphs[t].offsets;
+                a.nbrs = graphs[t].nbrs;
+                a.padj = padj + bases[t] * R;
+                a.rp = R;
+                a.n = nt;
+                a.qvec = vi.search + bases[s] * vi.row_bytes;
+                a.metric = p->metric;
+                a.base_norm = norms ? norms + bases[t] : nullptr;
+                a.q_norm = norms ? norms + bases[s] : nullptr;
+                a.G = vi.G;
+                a.lgG = ilog2i(vi.G);
+                a.cpl = vi.cpl;
+                a.hbits = hb_max;
+                a.hash_mode = mode_max;
+                a.out_mode = 0;
+                a.out_ids = resq;
+                a.out_d = resdq;
+                a.out_stride = RES;
+                a.err = errf;
+                go.naive = a;
+                go.naive.seed_mode = 0;
+                go.naive.entry = graphs[t].entry;
+                go.naive.ef = efN;
+                go.naive.out_k = efN;
+                go.slide = a;
+                go.slide.seed_mode = 2;
+                go.slide.seed_ids = resq;
+                go.slide.seed_stride = RES;
+                go.slide.n_seeds = efN;
+                go.slide.ef = efS;
+                go.slide.out_k = efS;
+                go.gpiv = gpiv;
+                go.fbeg = fbeg64;
+                go.fol = fol;
+                go.group_base = total_groups;
+                go.n_groups = src_np[s];
+                total_groups += src_np[s];
+                gops.push_back(go);
+                g_stats.queries[1] += src_np[s];
+                g_stats.queries[2] += src_nf[s];
+            }
+            // each round's op table in slots of its own: the stream may not
+            // have copied an earlier round's table yet
+            GroupOp *d_ops, *h_ops;
+            unsigned* next;
+            WS(d_ops, "bt_ops", sizeof(GroupOp) * nops);
+            HS(h_ops, "h_bt_ops", sizeof(GroupOp) * nops);
+            WS(next, "bt_next", sizeof(unsigned) * 8 * nrounds);
+            d_ops += op_slot;
+            h_ops += op_slot;
+            next += 8 * rr;
+            op_slot += (int)gops.size();
+            memcpy(h_ops, gops.data(), sizeof(GroupOp) * gops.size());
+            HIPCHK(hipMemcpyAsync(d_ops, h_ops, sizeof(GroupOp) * gops.size(), hipMemcpyHostToDevice, st));
+            HIPCHK(launch_zero(next, sizeof(unsigned) * 8, st));
+            GroupArgs ga = {};
+            ga.ops = d_ops;
+            ga.n_ops = (int)gops.size();
+            ga.n_groups = total_groups;
+            ga.next = next;
+            ga.hbits = hb_max;
+            ga.fmax = fmax;
+            ga.counters = cnt + 1 * CNT_SLOTS * CNT_N;
+            SearchArgs shape = gops[0].naive;
+            shape.ef = std::max(efN, efS);
+            std::array<int, 4> er;
+            HIPCHK(E.stat(st, &er[0]));
+            HIPCHK(launch_group_search(vi.tt, shape, ga, wpb_min, st, &g_stats.group_blocks));
+            HIPCHK(E.stat(st, &er[1]));
+            g_stats.launches[1] += 1;
+            // the overflow followers, one wavefront each, seeded by their
+            // pivot's beam (written by the group search)
+            if (ev_novf >= 0) HIPCHK(hipEventSynchronize(E.ev[ev_novf]));
+            for (size_t q = 0; q < rops.size(); ++q) {
+                const int s = ops[rops[q]].first, t = ops[rops[q]].second;
+                const int64_t novf = h_novf[s];
+                if (novf <= 0) continue;
+                int32_t *ofl, *oflp;
+                rnsm_status rs;
+                if ((rs = src_buf("bt_ofl_", s, sizeof(int32_t) * sizes[s], (void**)&ofl)) != RNSM_OK) return rs;
+                if ((rs = src_buf("bt_oflp_", s, sizeof(int32_t) * sizes[s], (void**)&oflp)) != RNSM_OK) return rs;
+                SearchArgs b = gops[q].slide;
+                const SearchShape shB = search_shape(efS, R, sizes[t], vi.tt, hb_req, wpb_req);
+                b.hbits = shB.hbits;
+                b.hash_mode = shB.mode;
+                b.qidx = ofl;
+                b.out_row = ofl;
+                b.seed_row = oflp;
+                b.nq = novf;
+                b.counters = cnt + 2 * CNT_SLOTS * CNT_N;
+                HIPCHK(launch_search(vi.tt, b, shB.wpb, st));
+                g_stats.launches[2] += 1;
+                g_stats.group_overflow += novf;
+            }
+            HIPCHK(E.stat(st, &er[2]));
+            g_stats.exact_visited = mode_max;
+            g_stats.search_hash_bits = hb_max;
+            g_stats.search_waves_per_block = wpb_min;
+            // ---- the round's prunes and reverse edges, operation by operation
+            for (size_t q = 0; q < rops.size(); ++q) {
+                const int oi = rops[q];
+                const int s = ops[oi].first, t = ops[oi].second;
+                const int64_t ns = sizes[s], nt = sizes[t];
+                int32_t* porder;
+                rnsm_status rs;
+                if ((rs = src_buf("bt_order_", s, sizeof(int32_t) * ns, (void**)&porder)) != RNSM_OK) return rs;
+                PruneArgs qs = {};
+                qs.X = vecs->f32;
+                qs.xb = xb16;
+                qs.n_total = N;
+                qs.nch = vi.nch32;
+                qs.G = vi.G32;
+                qs.lgG = ilog2i(vi.G32);
+                qs.cpl = vi.cpl32;
+                qs.metric = p->metric;
+                qs.norms = norms;
+                qs.item_base = bases[s];
+                qs.rows_in = rows;
+                qs.deg_in = deg;
+                qs.rows_d = rdist;
+                qs.extra_mode = 1;
+                qs.extra_ids = res_of[q];
+                qs.extra_d = search_d_exact ? resd_of[q] : nullptr;
+                qs.extra_sorted = search_d_exact && RES <= 128;
+                qs.extra_stride = RES;
+                qs.extra_cnt = RES;
+                qs.extra_index_base = bases[s];
+                qs.extra_id_add = bases[t];
+                qs.alpha = p->alpha;
+                qs.R = R;
+                qs.rows_out = rows;
+                qs.deg_out = deg;
+                qs.dist_out = rdist;
+                qs.wcap = R + RES;
+                qs.err = errf;
+                qs.band = band;
+                qs.rechecks = rechecks;
+                if (!touched[t]) {
+                    PruneArgs rd = qs;
+                    rd.n_items = nt;
+                    rd.item_base = bases[t];
+                    rd.extra_mode = 0;
+                    rd.wcap = TARGET_WCAP;
+                    HIPCHK(launch_row_dists(rd, prune_reads_b16(rd, pmode), st));
+                }
+                int32_t *rc, *rcur, *rev;
+                int64_t *roff, *stmp2;
+                u64* scratch;
+                float* rev_d;
+                WS(rc, "rev_cnt", sizeof(int32_t) * nt);
+                WS(rcur, "rev_cur", sizeof(int32_t) * nt);
+                WS(roff, "rev_off", sizeof(int64_t) * (nt + 1));
+                WS(rev, "rev_ids", sizeof(int32_t) * std::max<int64_t>(ns * R, 1));
+                WS(rev_d, "rev_d", sizeof(float) * std::max<int64_t>(ns * R, 1));
+                WS(stmp2, "scan_tmp2", sizeof(int64_t) * scan_tmp_elems(nt));
+                WS(scratch, "prune_scratch", sizeof(u64) * 2 * (nt * R + ns * R));
+                HIPCHK(launch_zero(rc, sizeof(int32_t) * nt, st));
+                HIPCHK(launch_zero(rcur, sizeof(int32_t) * nt, st));
+                PruneArgs q1 = qs;
+                q1.items = porder;
+                q1.n_items = ns;
+                q1.rev_cnt = rc;
+                q1.rev_lo = bases[t];
+                q1.rev_n = nt;
+                HIPCHK(run_prune(q1, pmode, st));
+                HIPCHK(launch_scan(rc, nt, roff, stmp2, st));
+                HIPCHK(launch_rev_scatter(rows, deg, rdist, bases[s], ns, R, bases[t], nt, roff, rcur,
+                                          rev, rev_d, st));
+                PruneArgs r2 = q1;
+                r2.n_items = nt;
+                r2.items = nullptr;
+                r2.item_base = bases[t];
+                r2.extra_mode = 2;
+                r2.extra_ids = rev;
+                r2.extra_d = rev_d;
+                r2.extra_off = roff;
+                r2.extra_index_base = bases[t];
+                r2.extra_id_add = 0;
+                r2.skip_empty_extra = 1;
+                r2.extra_sorted = 0;
+                r2.scratch = scratch;
+                r2.wcap = TARGET_WCAP;
+                r2.rev_cnt = nullptr;
+                HIPCHK(run_prune(r2, pmode, st));
+                HIPCHK(hipMemcpyAsync(h_nrev + oi, roff + nt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+                g_stats.n_followers += src_nf[s];
+                g_stats.n_pivots += src_np[s];
+                g_stats.n_source_vertices += ns;
+                touched[s] = touched[t] = 1;
+            }
+            HIPCHK(E.stat(st, &er[3]));
+            ev_rounds.push_back(er);
+            // the next round's groups overwrite nothing this round reads
+            // (rows change only through the prunes above, on this stream)
+        }
+        return RNSM_OK;
+    };
+
+    if (batched) {
+        const rnsm_status bs = batched_ops();
+        if (bs != RNSM_OK) return bs;
+    } else
     for (size_t oi = 0; oi < ops.size(); ++oi) {
         const int s = ops[oi].first, t = ops[oi].second;
         const int64_t ns = sizes[s], nt = sizes[t];
@@ -1542,6 +1983,18 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
         g_stats.ms_search[2] += E.between(ce[2], ce[3]);
     }
     for (auto& pe : ev_prune) ms_prune += E.between(pe[0], pe[1]);
+    for (auto& er : ev_rounds) {  // batched form: group searches (naive and sliding together),
+                                  // then the overflow followers' sliding
+        g_stats.ms_search[1] += E.between(er[0], er[1]);
+        g_stats.ms_search[2] += E.between(er[1], er[2]);
+        g_stats.ms_search_span += E.between(er[0], er[2]);
+        ms_prune += E.between(er[2], er[3]);
+    }
+    for (auto& oe : ord_ev) g_stats.ms_order += E.between(oe[0], oe[1]);
+    for (auto& se : sel_ev) {
+        g_stats.ms_select += E.between(se[0], se[1]);
+        g_stats.ms_groups += E.between(se[1], se[2]);
+    }
     for (auto& sp : ev_span) g_stats.ms_search_span += E.between(sp[0], sp[1]);
     for (size_t oi = 0; oi < ops.size(); ++oi) g_stats.n_reverse_edges += h_nrev[oi];
     if (herr & 1) return fail(RNSM_EINTERNAL, "rnsm_merge: a search exceeded its iteration bound");
@@ -1559,6 +2012,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     S.ms_prune = ms_prune;
     S.ms_compact = E.between(c0, c1);
     S.n_ops = (int64_t)ops.size();
+    S.n_rounds = batched ? n_rounds_b : (int64_t)ops.size();
     S.prune_path = pmode;
     for (int sl = 0; sl < CNT_SLOTS; ++sl) S.prune_rechecks += (int64_t)hrck[sl];
     S.row_bytes = vi.row_bytes;

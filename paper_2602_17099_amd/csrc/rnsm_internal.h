@@ -55,6 +55,29 @@ struct SearchArgs {
     int row_d_stride;
 };
 
+// One operation of a round in the persistent pivot-group search: its naive
+// and sliding search arguments (target graph and rows, beams, outputs; the
+// sliding seeds are row p of slide.seed_ids for the group of pivot p), and its
+// groups g: pivot gpiv[g], followers fol[fbeg[g] .. fbeg[g+1]) (source-local
+// ids). Groups of all operations are numbered from group_base on.
+struct GroupOp {
+    SearchArgs naive, slide;
+    const int32_t* gpiv;
+    const int64_t* fbeg;
+    const int32_t* fol;
+    int64_t group_base, n_groups;
+};
+
+struct GroupArgs {
+    const GroupOp* ops;   // device array, ascending group_base
+    int n_ops;
+    int64_t n_groups;     // all operations together
+    unsigned* next;       // 8 range counters, zero at launch
+    int hbits;            // LDS visited table of every search
+    int64_t fmax;         // followers searched in a group's work item (the rest: overflow)
+    u64* counters;        // CNT_SLOTS x CNT_N for the pivots, then as many for the followers
+};
+
 struct PruneArgs {
     const float* X;           // float32 rows of every vertex (global ids)
     const char* xb;           // bfloat16 copy of X (dim * 2 bytes a row): the MFMA prune in
@@ -121,18 +144,42 @@ hipError_t launch_search(int tt, const SearchArgs& a, int waves_per_block, hipSt
 hipError_t launch_norms16(const void* X, int tt, int64_t n, int dim, float* out, hipStream_t st);
 // zero bytes (a multiple of 4) at p with a kernel (no memset node in a captured graph)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// the persistent pivot-group search of a round (every op with the same
+// search shape as `shape`: storage type tt, chunks per lane, lanes per row,
+// table mode, beam class)
+// blocks_out (may be NULL): the grid launched
+hipError_t launch_group_search(int tt, const SearchArgs& shape, const GroupArgs& g, int wpb,
+                               hipStream_t st, int64_t* blocks_out = nullptr);
+// pivot groups of one source from pivot_of (-1 pivots), pivots taken along
+// `order` (NULL: id order): gpiv[n_groups], fbeg[n_groups + 1] (offsets into
+// fol), fol (followers by group), prune_order (each pivot then its
+// followers); flag, gpos (n + 1), group_of, cnt: scratch
+hipError_t launch_groups(const int32_t* order, int64_t n, const int32_t* pivot_of, int32_t* flag,
+                         int64_t* gpos, int32_t* gpiv, int32_t* group_of, int32_t* cnt,
+                         int64_t* fbeg, int32_t* fol, int32_t* prune_order, int64_t* scan_tmp,
+                         int64_t n_groups, hipStream_t st);
+// followers past the first fmax of their group (the overflow, searched by a
+// plain launch after the group search): cnt[g] = excess of group g (scratch,
+// n_groups), ooff (n_groups + 1) its scan, ofl / oflp the overflow followers
+// and their pivots, group by group; nf followers in all
+hipError_t launch_group_overflow(int64_t n_groups, int64_t nf, const int32_t* gpiv,
+                                 const int64_t* fbeg, const int32_t* fol, const int32_t* pivot_of,
+                                 const int32_t* group_of, int64_t fmax, int32_t* cnt, int64_t* ooff,
+                                 int32_t* ofl, int32_t* oflp, int64_t* scan_tmp, hipStream_t st);
+hipError_t launch_fill32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // pivot selection on the device (the lazy greedy in parallel rounds, the same
 // pivots and groups): init, then `rounds` rounds (each a no-op once ctl[0],
 // the uncovered count, is 0); ctl[1] counts pivots. pivot_of: -1 pivot, else
 // the pivot's id
 hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids, int* flag,
                               hipStream_t st);
-hipError_t launch_select_init(int64_t n, unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
-                              int64_t* ctl, hipStream_t st);
+hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov,
+                              unsigned char* sel, int32_t* pivot_of, int32_t* longv, int64_t* ctl,
+                              hipStream_t st);
 hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* ids,
                                 unsigned char* cov, unsigned char* sel, unsigned long long* key,
                                 unsigned long long* best, int32_t* pivot_of, int64_t* ctl,
-                                int rounds, hipStream_t st);
+                                const int32_t* longv, int64_t nlong, int rounds, hipStream_t st);
 // static device scratch of the allocation-free search (bytes per device) and
 // its address on the current device (looked up once per device)
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;

@@ -374,21 +374,24 @@ __device__ __forceinline__ void process_candidates(const SearchArgs& a, Beam<EFS
     __builtin_amdgcn_wave_barrier();
 }
 
+// distance counts of a wavefront's searches
+struct SearchCounts {
+    u64 ndc = 0, nexp = 0, nadj = 0, nevict = 0;
+};
+
+// Algorithm 1 for one query, by one wavefront: query row u of a.qvec,
+// seeds by seed_mode (0: a.entry, 1: u itself, 2: the n_seeds ids at sp, -1
+// and out-of-range ids skipped), the final beam to output row orow. tab / cl:
+// this wavefront's LDS visited table and candidate list (the table is
+// cleared here).
 template <int TT, int EFS, int CPL, bool EXACT, int LG>
-__global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
-    extern __shared__ int smem[];
-    const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
-    const int wpb = blockDim.x >> 6;
-    const int64_t i = xcd_block() * wpb + wib;
-    if (i >= a.nq) return;
+__device__ __forceinline__ void search_one(const SearchArgs& a, int u, int seed_mode,
+                                           const int32_t* sp, int n_seeds, int64_t orow,
+                                           int* tab, int* cl, int lane, SearchCounts& cnt) {
     const int H = 1 << a.hbits;
-    int* tab = smem + (int64_t)wib * search_lds_words(a.hbits);
-    int* cl = tab + H;
     for (int t = lane; t < H; t += WAVE) tab[t] = -1;
     __builtin_amdgcn_wave_barrier();
 
-    const int u = a.qidx ? a.qidx[i] : (int)i;
     const int G = LG >= 0 ? (1 << LG) : a.G;
     const int sub = lane & (G - 1);
     const char* qrow = a.qvec + (int64_t)u * a.row_bytes + sub * 16;
@@ -420,20 +423,17 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     u64 ndc = 0, nexp = 0, nadj = 0, nevict = 0;
 
     // seeds
-    if (a.seed_mode == 0 || a.seed_mode == 1) {
-        const int s0 = a.seed_mode == 0 ? a.entry : u;
+    if (seed_mode == 0 || seed_mode == 1) {
+        const int s0 = seed_mode == 0 ? a.entry : u;
         process_candidates<TT, EFS, CPL, EXACT, LG>(a, B, Q, qn, tab, cl, lane == 0 ? s0 : -1, lane, ndc,
                                        nevict);
     } else {
-        const int64_t srow = a.seed_row ? a.seed_row[i] : i;
-        const int32_t* sp = a.seed_ids + srow * a.seed_stride;
-        for (int j0 = 0; j0 < a.n_seeds; j0 += WAVE) {
+        for (int j0 = 0; j0 < n_seeds; j0 += WAVE) {
             const int j = j0 + lane;
-            const int v = j < a.n_seeds ? sp[j] : -1;
+            const int v = j < n_seeds ? sp[j] : -1;
             process_candidates<TT, EFS, CPL, EXACT, LG>(a, B, Q, qn, tab, cl, v, lane, ndc, nevict);
         }
     }
-
     // expand the nearest unexpanded entry until every entry is expanded
     const int64_t maxit = a.n + 2;
     int pf_uid = -1, pf_v = -1;  // adjacency fetched ahead for the runner-up entry
@@ -511,7 +511,6 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
     }
 
     // write the result
-    const int64_t orow = a.out_row ? a.out_row[i] : i;
     int32_t* oi = a.out_ids + orow * a.out_stride;
     float* od = a.out_d ? a.out_d + orow * a.out_stride : nullptr;
     if (a.out_mode == 0) {
@@ -540,15 +539,104 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
             if (od) od[lane] = INFINITY;
         }
     }
+    cnt.ndc += ndc;
+    cnt.nexp += nexp;
+    cnt.nadj += nadj;
+    cnt.nevict += nevict;
+}
+
+// one wavefront's counts into a launch's counters, spread over CNT_SLOTS
+// copies to keep the atomics of hundreds of thousands of wavefronts from
+// meeting on one address
+__device__ __forceinline__ void add_counts(u64* counters, const SearchCounts& c, int lane) {
     if (lane == 0) {
-        // counters are spread over CNT_SLOTS copies to keep the atomics of
-        // hundreds of thousands of wavefronts from meeting on one address
-        u64* c = a.counters + (blockIdx.x & (CNT_SLOTS - 1)) * CNT_N;
-        atomicAdd(&c[CNT_NDC], ndc);
-        atomicAdd(&c[CNT_EXP], nexp);
-        atomicAdd(&c[CNT_ADJ], nadj);
-        atomicAdd(&c[CNT_HFULL], nevict);
+        u64* p = counters + (blockIdx.x & (CNT_SLOTS - 1)) * CNT_N;
+        atomicAdd(&p[CNT_NDC], c.ndc);
+        atomicAdd(&p[CNT_EXP], c.nexp);
+        atomicAdd(&p[CNT_ADJ], c.nadj);
+        atomicAdd(&p[CNT_HFULL], c.nevict);
     }
+}
+
+template <int TT, int EFS, int CPL, bool EXACT, int LG>
+__global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
+    extern __shared__ int smem[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int64_t i = xcd_block() * wpb + wib;
+    if (i >= a.nq) return;
+    int* tab = smem + (int64_t)wib * search_lds_words(a.hbits);
+    int* cl = tab + (1 << a.hbits);
+    const int u = a.qidx ? a.qidx[i] : (int)i;
+    const int32_t* sp = nullptr;
+    if (a.seed_mode == 2) sp = a.seed_ids + (a.seed_row ? a.seed_row[i] : i) * a.seed_stride;
+    const int64_t orow = a.out_row ? a.out_row[i] : i;
+    SearchCounts c;
+    search_one<TT, EFS, CPL, EXACT, LG>(a, u, a.seed_mode, sp, a.n_seeds, orow, tab, cl, lane, c);
+    add_counts(a.counters, c, lane);
+}
+
+// The searches of a round's operations in one persistent launch. A work item
+// is a pivot group: the pivot's naive search from the target's entry, then
+// each follower's local sliding seeded with the pivot's final beam, which the
+// same wavefront has just written (so no wavefront waits on another). The
+// groups (in breadth-first order of the pivots within each operation) are
+// cut into 8 contiguous ranges, one per XCD (blocks are dispatched to the
+// XCDs in turn): a wavefront takes the groups of its XCD's range, then those
+// of the other ranges, through one atomic counter per range. Every
+// wavefront ends when all ranges are drained.
+template <int TT, int EFS, int CPL, bool EXACT, int LG>
+__global__ __launch_bounds__(256) void k_group_search(GroupArgs g) {
+    extern __shared__ int smem[];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    int* tab = smem + (int64_t)wib * search_lds_words(g.hbits);
+    int* cl = tab + (1 << g.hbits);
+    const int xcd = blockIdx.x & 7;
+    SearchCounts cp, cf;
+    for (int r = 0; r < 8; ++r) {
+        const int rng = (xcd + r) & 7;
+        const int64_t lo = g.n_groups * rng / 8, hi = g.n_groups * (rng + 1) / 8;
+        for (;;) {
+            unsigned t = 0;
+            if (lane == 0) t = atomicAdd(&g.next[rng], 1u);
+            // wavefront-uniform (scalar) from here on: the op's arguments
+            // are then scalar loads
+            const int64_t gi = lo + (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)t);
+            if (gi >= hi) break;
+            // the op table through the constant address space: scalar loads
+            // (the host pass of this kernel, never run, reads it plainly)
+#if defined(__HIP_DEVICE_COMPILE__)
+            typedef const __attribute__((address_space(4))) GroupOp CGroupOp;
+            CGroupOp* ops = (CGroupOp*)g.ops;
+#else
+            const GroupOp* ops = g.ops;
+#endif
+            int k = 0;
+            while (k + 1 < g.n_ops && ops[k + 1].group_base <= gi) ++k;
+            const int64_t j = gi - ops[k].group_base;
+            const int p = ops[k].gpiv[j];
+            const int64_t f0 = ops[k].fbeg[j];
+            const int64_t f1 = min(ops[k].fbeg[j + 1], f0 + g.fmax);
+            const int32_t* fol = ops[k].fol;
+            {
+                const SearchArgs a = ops[k].naive;
+                search_one<TT, EFS, CPL, EXACT, LG>(a, p, 0, nullptr, 0, p, tab, cl, lane, cp);
+            }
+            // the pivot's beam, just stored by this wavefront, seeds its
+            // followers: stores complete before those loads
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            const SearchArgs b = ops[k].slide;
+            const int32_t* seeds = b.seed_ids + (int64_t)p * b.seed_stride;
+            for (int64_t f = f0; f < f1; ++f) {
+                const int y = fol[f];
+                search_one<TT, EFS, CPL, EXACT, LG>(b, y, 2, seeds, b.n_seeds, y, tab, cl, lane, cf);
+            }
+        }
+    }
+    add_counts(g.counters, cp, lane);
+    add_counts(g.counters + CNT_SLOTS * CNT_N, cf, lane);
 }
 
 // ------------------------------------------------------------------ prune
@@ -2520,6 +2608,195 @@ hipError_t launch_search(int tt, const SearchArgs& a, int wpb, hipStream_t st) {
     return hipGetLastError();
 }
 
+// the persistent pivot-group search: as many blocks as the device holds at
+// once (each wavefront loops over the queue), no more than the groups need.
+// Resident wavefronts per CU from the kernel's registers (512 VGPRs per SIMD
+// lane, 4 SIMDs, at most 8 per SIMD) and its LDS (160 KiB per CU). More
+// blocks than fit are harmless: they start as others end and drain the
+// queue (no block waits on another).
+template <int TT, int EFS, int CPL, bool EXACT, int LG>
+static hipError_t launch_group_c(const GroupArgs& g, int wpb, hipStream_t st, int64_t* out) {
+    const void* fn = reinterpret_cast<const void*>(&k_group_search<TT, EFS, CPL, EXACT, LG>);
+    const size_t lds = search_lds_bytes(g.hbits, wpb);
+    int cus = 0, dev = 0;
+    hipFuncAttributes fa;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess) return e;
+    const int vg = std::max(8, (fa.numRegs + 7) & ~7);
+    const int per_simd = std::min(8, 512 / vg);
+    int64_t per_cu = std::max(1, 4 * per_simd / wpb);
+    if (lds > 0) per_cu = std::min<int64_t>(per_cu, std::max<size_t>(1, (160 * 1024) / lds));
+    int64_t blocks = per_cu * std::max(cus, 1);
+    if (const char* c = getenv("RNSM_GROUP_BLOCKS")) blocks = std::max(8ll, atoll(c));
+    blocks = std::min<int64_t>(blocks, (g.n_groups + wpb - 1) / wpb);
+    blocks = std::max<int64_t>(blocks, 8);  // every XCD's range has wavefronts of its own
+    if (out) *out = blocks;
+    hipLaunchKernelGGL((k_group_search<TT, EFS, CPL, EXACT, LG>), dim3((unsigned)blocks),
+                       dim3(wpb * WAVE), lds, st, g);
+    return hipGetLastError();
+}
+
+template <int TT, int EFS, bool EXACT>
+static hipError_t launch_group_m(const SearchArgs& a, const GroupArgs& g, int wpb, hipStream_t st,
+                                 int64_t* out) {
+    constexpr int LG128 = TT == 0 ? 3 : 2;
+    if (a.cpl == 4 && a.lgG == LG128) return launch_group_c<TT, EFS, 4, EXACT, LG128>(g, wpb, st, out);
+    switch (a.cpl) {
+        case 1: return launch_group_c<TT, EFS, 1, EXACT, -1>(g, wpb, st, out);
+        case 2: return launch_group_c<TT, EFS, 2, EXACT, -1>(g, wpb, st, out);
+        case 3: return launch_group_c<TT, EFS, 3, EXACT, -1>(g, wpb, st, out);
+        default: return launch_group_c<TT, EFS, 4, EXACT, -1>(g, wpb, st, out);
+    }
+}
+
+template <int TT, int EFS>
+static hipError_t launch_group_e(const SearchArgs& a, const GroupArgs& g, int wpb, hipStream_t st,
+                                 int64_t* out) {
+    return a.hash_mode ? launch_group_m<TT, EFS, true>(a, g, wpb, st, out)
+                       : launch_group_m<TT, EFS, false>(a, g, wpb, st, out);
+}
+
+hipError_t launch_group_search(int tt, const SearchArgs& shape, const GroupArgs& g, int wpb,
+                               hipStream_t st, int64_t* out) {
+    if (g.n_groups <= 0) return hipSuccess;
+    const bool two = shape.ef > 64;
+    if (tt == 0)
+        return two ? launch_group_e<0, 2>(shape, g, wpb, st, out) : launch_group_e<0, 1>(shape, g, wpb, st, out);
+    if (tt == 1)
+        return two ? launch_group_e<1, 2>(shape, g, wpb, st, out) : launch_group_e<1, 1>(shape, g, wpb, st, out);
+    return two ? launch_group_e<2, 2>(shape, g, wpb, st, out) : launch_group_e<2, 1>(shape, g, wpb, st, out);
+}
+
+// ------------------------------------------------------ pivot groups (batched form)
+
+// pivot groups of one source in breadth-first order of the pivots: flags of
+// the pivots along the order (for a scan into their group numbers)
+__global__ void k_grp_flags(const int32_t* order, int64_t n, const int32_t* pivot_of,
+                            int32_t* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = order ? order[i] : (int32_t)i;
+    flag[i] = pivot_of[v] == -1 ? 1 : 0;
+}
+
+// group g = gpos of pivot order[i]: gpiv[g] and the pivot's group number
+__global__ void k_grp_place(const int32_t* order, int64_t n, const int32_t* flag,
+                            const int64_t* gpos, int32_t* gpiv, int32_t* group_of) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const int32_t v = order ? order[i] : (int32_t)i;
+    gpiv[gpos[i]] = v;
+    group_of[v] = (int32_t)gpos[i];
+}
+
+// followers per group
+__global__ void k_grp_count(int64_t n, const int32_t* pivot_of, const int32_t* group_of,
+                            int32_t* cnt) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n) return;
+    const int32_t p = pivot_of[y];
+    if (p >= 0) atomicAdd(&cnt[group_of[p]], 1);
+}
+
+// followers into their group's run (order within a run is free: each
+// follower's search depends on its pivot's beam only)
+__global__ void k_grp_scatter(int64_t n, const int32_t* pivot_of, const int32_t* group_of,
+                              const int64_t* fbeg, int32_t* cur, int32_t* fol) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n) return;
+    const int32_t p = pivot_of[y];
+    if (p < 0) return;
+    const int32_t g = group_of[p];
+    fol[fbeg[g] + atomicAdd(&cur[g], 1)] = (int32_t)y;
+}
+
+// the prune order of the source: each pivot followed by its followers, group
+// after group (group g starts at g + fbeg[g], so follower slot f of group g
+// lands at g + 1 + f); one thread per group head, one per follower slot
+__global__ void k_grp_order(int64_t ng, int64_t nf, const int32_t* gpiv, const int64_t* fbeg,
+                            const int32_t* fol, const int32_t* pivot_of, const int32_t* group_of,
+                            int32_t* order) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ng) {
+        order[t + fbeg[t]] = gpiv[t];
+    } else if (t - ng < nf) {
+        const int64_t f = t - ng;
+        const int32_t y = fol[f];
+        order[(int64_t)group_of[pivot_of[y]] + 1 + f] = y;
+    }
+}
+
+__global__ void k_grp_excess(int64_t ng, const int64_t* fbeg, int64_t fmax, int32_t* exc) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < ng) exc[g] = (int32_t)max<int64_t>(0, fbeg[g + 1] - fbeg[g] - fmax);
+}
+
+// follower slot f of the runs: its group from its pivot, its place in the run
+__global__ void k_grp_overflow(int64_t nf, const int32_t* gpiv, const int64_t* fbeg,
+                               const int32_t* fol, const int32_t* pivot_of, const int32_t* group_of,
+                               int64_t fmax, const int64_t* ooff, int32_t* ofl, int32_t* oflp) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const int32_t y = fol[f];
+    const int32_t g = group_of[pivot_of[y]];
+    const int64_t r = f - fbeg[g] - fmax;
+    if (r < 0) return;
+    ofl[ooff[g] + r] = y;
+    oflp[ooff[g] + r] = gpiv[g];
+}
+
+hipError_t launch_group_overflow(int64_t ng, int64_t nf, const int32_t* gpiv, const int64_t* fbeg,
+                                 const int32_t* fol, const int32_t* pivot_of,
+                                 const int32_t* group_of, int64_t fmax, int32_t* cnt, int64_t* ooff,
+                                 int32_t* ofl, int32_t* oflp, int64_t* scan_tmp, hipStream_t st) {
+    if (ng <= 0) return launch_zero(ooff, sizeof(int64_t), st);
+    hipLaunchKernelGGL(k_grp_excess, dim3(nblk(ng, 256)), dim3(256), 0, st, ng, fbeg, fmax, cnt);
+    hipError_t e = launch_scan(cnt, ng, ooff, scan_tmp, st);
+    if (e != hipSuccess) return e;
+    if (nf > 0)
+        hipLaunchKernelGGL(k_grp_overflow, dim3(nblk(nf, 256)), dim3(256), 0, st, nf, gpiv, fbeg,
+                           fol, pivot_of, group_of, fmax, ooff, ofl, oflp);
+    return hipGetLastError();
+}
+
+__global__ void k_fill32(int32_t* p, int64_t n, int32_t v) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+hipError_t launch_fill32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill32, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_groups(const int32_t* order, int64_t n, const int32_t* pivot_of, int32_t* flag,
+                         int64_t* gpos, int32_t* gpiv, int32_t* group_of, int32_t* cnt,
+                         int64_t* fbeg, int32_t* fol, int32_t* prune_order, int64_t* scan_tmp,
+                         int64_t n_groups, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const dim3 g(nblk(n, 256)), b(256);
+    hipLaunchKernelGGL(k_grp_flags, g, b, 0, st, order, n, pivot_of, flag);
+    hipError_t e = launch_scan(flag, n, gpos, scan_tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grp_place, g, b, 0, st, order, n, flag, gpos, gpiv, group_of);
+    if ((e = launch_zero(cnt, sizeof(int32_t) * (size_t)std::max<int64_t>(n_groups, 1), st)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_grp_count, g, b, 0, st, n, pivot_of, group_of, cnt);
+    if ((e = launch_scan(cnt, n_groups, fbeg, scan_tmp, st)) != hipSuccess) return e;
+    if ((e = launch_zero(cnt, sizeof(int32_t) * (size_t)std::max<int64_t>(n_groups, 1), st)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_grp_scatter, g, b, 0, st, n, pivot_of, group_of, fbeg, cnt, fol);
+    if (n_groups > 0)
+        hipLaunchKernelGGL(k_grp_order, dim3(nblk(n, 256)), b, 0, st, n_groups, n - n_groups, gpiv,
+                           fbeg, fol, pivot_of, group_of, prune_order);
+    return hipGetLastError();
+}
+
 template <int CPL>
 static void launch_prune_c(const PruneArgs& a, int need, dim3 grid, dim3 block, size_t lds,
                            hipStream_t st) {
@@ -2668,7 +2945,7 @@ hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* off, int64_t* tmp
 }
 
 hipError_t launch_count_ids(const int32_t* nk, int64_t n, int k, int32_t* cnt, hipStream_t st) {
-    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)n, st);
+    hipError_t e = launch_zero(cnt, sizeof(int32_t) * (size_t)n, st);
     if (e != hipSuccess) return e;
     if (n > 0)
         hipLaunchKernelGGL(k_count_ids, dim3(nblk(n * k, 256)), dim3(256), 0, st, nk, n * k, cnt);
@@ -2723,7 +3000,7 @@ hipError_t launch_invert_lists(const int32_t* nk, int64_t n, int k, int32_t* cnt
                                hipStream_t st) {
     hipError_t e = launch_scan(cnt, n, rk_off, scan_tmp, st);
     if (e != hipSuccess) return e;
-    e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)n, st);
+    e = launch_zero(cnt, sizeof(int32_t) * (size_t)n, st);
     if (e != hipSuccess) return e;
     if (n > 0) {
         hipLaunchKernelGGL(k_invert_scatter, dim3(nblk(n * k, 256)), dim3(256), 0, st, nk, n, k,
@@ -2809,7 +3086,7 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
 // before any vertex it competes with, with the same followers, and picks that
 // share no position commute, so the pivots and follower groups are the
 // greedy's. ctl[0]: uncovered vertices left (every kernel returns when 0),
-// ctl[1]: pivots, ctl[2]: rounds that picked something.
+// ctl[1]: pivots, ctl[2]: rounds run with vertices left.
 __global__ void k_sel_init(int64_t n, unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
                            int64_t* ctl) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2822,15 +3099,60 @@ __global__ void k_sel_init(int64_t n, unsigned char* cov, unsigned char* sel, in
         ctl[0] = n;
         ctl[1] = 0;
         ctl[2] = 0;
+        ctl[3] = 0;
     }
 }
 
-__global__ void k_sel_keys(int64_t n, const int64_t* off, const int32_t* ids,
-                           const unsigned char* cov, u64* key, u64* best, const int64_t* ctl) {
+// Lists longer than SEL_LONG (a hub can be in thousands of k-NN lists) are
+// read by a whole wavefront each; the rest by one thread per vertex. The
+// long ones are listed once per selection (ctl[3] counts them; any order).
+constexpr int SEL_LONG = 64;
+
+__global__ void k_sel_long(int64_t n, const int64_t* off, int32_t* longv, int64_t* ctl) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n || ctl[0] == 0 || cov[x]) return;
+    if (x < n && off[x + 1] - off[x] > SEL_LONG)
+        longv[atomicAdd((unsigned long long*)&ctl[3], 1ull)] = (int32_t)x;
+}
+
+// Every round kernel: blocks below nblk(n) take one vertex per thread
+// (skipping long lists), the blocks after them one long list per wavefront.
+// Returns the vertex and whether this lane works on a long list (lane l of
+// the list's wavefront reads entries l, l + 64, ...); x < 0: nothing to do.
+struct SelItem {
+    int64_t x;
+    bool wave;
+};
+__device__ __forceinline__ SelItem sel_item(int64_t n, const int64_t* off, const int32_t* longv,
+                                            int64_t nlong) {
+    const int64_t nbs = (n + 255) / 256;
+    if ((int64_t)blockIdx.x < nbs) {
+        const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (x >= n || off[x + 1] - off[x] > SEL_LONG) return {-1, false};
+        return {x, false};
+    }
+    const int64_t w = (((int64_t)blockIdx.x - nbs) * blockDim.x + threadIdx.x) >> 6;
+    if (w >= nlong) return {-1, true};
+    return {(int64_t)longv[w], true};
+}
+
+__global__ void k_sel_keys(int64_t n, const int64_t* off, const int32_t* ids,
+                           const unsigned char* cov, u64* key, u64* best, int64_t* ctl,
+                           const int32_t* longv, int64_t nlong) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl[0] != 0) ctl[2] += 1;  // a round with vertices left
+    if (ctl[0] == 0) return;
+    const SelItem it = sel_item(n, off, longv, nlong);
+    const int64_t x = it.x;
+    if (x < 0 || cov[x]) return;  // wavefront-uniform on the long path
     int64_t g = 0;
-    for (int64_t j = off[x]; j < off[x + 1]; ++j) g += cov[ids[j]] ? 0 : 1;
+    const int64_t b = off[x], e = off[x + 1];
+    if (!it.wave) {
+        for (int64_t j = b; j < e; ++j) g += cov[ids[j]] ? 0 : 1;
+    } else {
+        for (int64_t j = b + lane_id(); j < e; j += WAVE) g += cov[ids[j]] ? 0 : 1;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) g += __shfl_xor(g, o);
+        if (lane_id() != 0) return;
+    }
     const u64 k = ((u64)g << 32) | (u64)(0xffffffffu - (unsigned)x);
     key[x] = k;
     best[x] = k;
@@ -2838,11 +3160,14 @@ __global__ void k_sel_keys(int64_t n, const int64_t* off, const int32_t* ids,
 
 __global__ void k_sel_spread(int64_t n, const int64_t* off, const int32_t* ids,
                              const unsigned char* cov, const u64* key, u64* best,
-                             const int64_t* ctl) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n || ctl[0] == 0 || cov[x]) return;
+                             const int64_t* ctl, const int32_t* longv, int64_t nlong) {
+    if (ctl[0] == 0) return;
+    const SelItem it = sel_item(n, off, longv, nlong);
+    const int64_t x = it.x;
+    if (x < 0 || cov[x]) return;
     const u64 k = key[x];
-    for (int64_t j = off[x]; j < off[x + 1]; ++j) {
+    const int64_t st = it.wave ? lane_id() : 0, step = it.wave ? WAVE : 1;
+    for (int64_t j = off[x] + st; j < off[x + 1]; j += step) {
         const int32_t y = ids[j];
         if (!cov[y] && best[y] < k) atomicMax(&best[y], k);
     }
@@ -2850,16 +3175,21 @@ __global__ void k_sel_spread(int64_t n, const int64_t* off, const int32_t* ids,
 
 __global__ void k_sel_pick(int64_t n, const int64_t* off, const int32_t* ids,
                            const unsigned char* cov, const u64* key, const u64* best,
-                           unsigned char* sel, const int64_t* ctl) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n || ctl[0] == 0 || cov[x]) return;
+                           unsigned char* sel, const int64_t* ctl, const int32_t* longv,
+                           int64_t nlong) {
+    if (ctl[0] == 0) return;
+    const SelItem it = sel_item(n, off, longv, nlong);
+    const int64_t x = it.x;
+    if (x < 0 || cov[x]) return;
     const u64 k = key[x];
     bool ok = best[x] == k;
-    for (int64_t j = off[x]; j < off[x + 1] && ok; ++j) {
+    const int64_t st = it.wave ? lane_id() : 0, step = it.wave ? WAVE : 1;
+    for (int64_t j = off[x] + st; j < off[x + 1] && ok; j += step) {
         const int32_t y = ids[j];
         if (!cov[y] && best[y] != k) ok = false;
     }
-    sel[x] = ok ? 1 : 0;
+    if (it.wave) ok = __ballot(!ok) == 0ull;
+    if (!it.wave || lane_id() == 0) sel[x] = ok ? 1 : 0;
 }
 
 // the picks of the round take themselves and their uncovered followers; no
@@ -2867,13 +3197,15 @@ __global__ void k_sel_pick(int64_t n, const int64_t* off, const int32_t* ids,
 // coverage each reads is the round's starting one where it matters
 __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids,
                             unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
-                            int64_t* ctl) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool pick = x < n && ctl[0] != 0 && sel[x];
+                            int64_t* ctl, const int32_t* longv, int64_t nlong) {
+    if (ctl[0] == 0) return;
+    const SelItem it = sel_item(n, off, longv, nlong);
+    const int64_t x = it.x;
+    const bool pick = x >= 0 && sel[x];
     int64_t taken = 0;
     if (pick) {
-        sel[x] = 0;
-        for (int64_t j = off[x]; j < off[x + 1]; ++j) {
+        const int64_t st = it.wave ? lane_id() : 0, step = it.wave ? WAVE : 1;
+        for (int64_t j = off[x] + st; j < off[x + 1]; j += step) {
             const int32_t y = ids[j];
             if (!cov[y]) {
                 pivot_of[y] = (int32_t)x;
@@ -2881,19 +3213,25 @@ __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids,
                 ++taken;
             }
         }
+    }
+    // the wavefront's counts in one atomic each; a long list's pick counts
+    // once (its lane 0)
+    const bool owner = pick && (!it.wave || lane_id() == 0);
+    if (owner) {
+        sel[x] = 0;
         pivot_of[x] = -1;
         cov[x] = 1;
         ++taken;
     }
-    // one atomic per wavefront for the counts
-    const u64 any = __ballot(pick);
-    if (any == 0ull) return;
+    const u64 anyp = __ballot(pick);
+    if (anyp == 0ull) return;
+    const u64 own = __ballot(owner);
     int64_t t = taken;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
-    if (lane_id() == __ffsll((long long)any) - 1) {
+    if (lane_id() == __ffsll((long long)anyp) - 1) {
         atomicAdd((unsigned long long*)&ctl[0], (unsigned long long)(-t));
-        atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)__popcll(any));
+        atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)__popcll(own));
     }
 }
 
@@ -2914,23 +3252,30 @@ hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids,
     return hipGetLastError();
 }
 
-hipError_t launch_select_init(int64_t n, unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
-                              int64_t* ctl, hipStream_t st) {
+hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov,
+                              unsigned char* sel, int32_t* pivot_of, int32_t* longv, int64_t* ctl,
+                              hipStream_t st) {
     hipLaunchKernelGGL(k_sel_init, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, st, n, cov, sel,
                        pivot_of, ctl);
+    if (n > 0)
+        hipLaunchKernelGGL(k_sel_long, dim3(nblk(n, 256)), dim3(256), 0, st, n, off, longv, ctl);
     return hipGetLastError();
 }
 
 hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* ids,
                                 unsigned char* cov, unsigned char* sel, u64* key, u64* best,
-                                int32_t* pivot_of, int64_t* ctl, int rounds, hipStream_t st) {
+                                int32_t* pivot_of, int64_t* ctl, const int32_t* longv,
+                                int64_t nlong, int rounds, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const dim3 g(nblk(n, 256)), b(256);
+    const dim3 g(nblk(n, 256) + nblk(nlong * WAVE, 256)), b(256);
     for (int r = 0; r < rounds; ++r) {
-        hipLaunchKernelGGL(k_sel_keys, g, b, 0, st, n, off, ids, cov, key, best, ctl);
-        hipLaunchKernelGGL(k_sel_spread, g, b, 0, st, n, off, ids, cov, key, best, ctl);
-        hipLaunchKernelGGL(k_sel_pick, g, b, 0, st, n, off, ids, cov, key, best, sel, ctl);
-        hipLaunchKernelGGL(k_sel_apply, g, b, 0, st, n, off, ids, cov, sel, pivot_of, ctl);
+        hipLaunchKernelGGL(k_sel_keys, g, b, 0, st, n, off, ids, cov, key, best, ctl, longv, nlong);
+        hipLaunchKernelGGL(k_sel_spread, g, b, 0, st, n, off, ids, cov, key, best, ctl, longv,
+                           nlong);
+        hipLaunchKernelGGL(k_sel_pick, g, b, 0, st, n, off, ids, cov, key, best, sel, ctl, longv,
+                           nlong);
+        hipLaunchKernelGGL(k_sel_apply, g, b, 0, st, n, off, ids, cov, sel, pivot_of, ctl, longv,
+                           nlong);
     }
     return hipGetLastError();
 }
