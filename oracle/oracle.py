@@ -103,6 +103,10 @@ def _setup(L):
                             C.c_int, C.c_float, P, P, P]
     L.orc_norms.restype = None
     L.orc_norms.argtypes = [P, C.c_int64, C.c_int, P]
+    L.orc_reachable.restype = C.c_int64
+    L.orc_reachable.argtypes = [C.c_int64, P, P, C.c_int32]
+    L.orc_repair.restype = C.c_int64
+    L.orc_repair.argtypes = [C.c_int64, P, C.c_int, C.c_int, C.c_int, P, P, C.c_int32]
 
 
 def _p(a: np.ndarray | None):
@@ -380,10 +384,13 @@ def knn_queries(X, Q, K, metric=L2SQ):
     return ids, ds
 
 
-def build_graph(X, K, R, alpha=1.0, reverse=False, alpha_rev=1.2, metric=L2SQ, knn_ids=None):
+def build_graph(X, K, R, alpha=1.0, reverse=False, alpha_rev=1.2, metric=L2SQ, knn_ids=None,
+                repair=False, return_links=False):
     """Sub-index builder: exact K-NN -> prune(alpha) to R [-> reverse edges
-    and prune(alpha_rev)] -> entry closest to the centroid.
-    Returns (offsets int64, nbrs int32 local, entry)."""
+    and prune(alpha_rev)] -> entry closest to the centroid [-> reachability
+    repair: every vertex the entry cannot reach is linked in from its
+    nearest reached vertex].
+    Returns (offsets int64, nbrs int32 local, entry) [, links added]."""
     X = _f32(X)
     n = X.shape[0]
     if knn_ids is None:
@@ -392,9 +399,33 @@ def build_graph(X, K, R, alpha=1.0, reverse=False, alpha_rev=1.2, metric=L2SQ, k
     offs = np.empty(n + 1, dtype=np.int64)
     nb = np.empty(max(1, n * R), dtype=np.int32)
     entry = np.zeros(1, dtype=np.int32)
-    lib().orc_build(n, _p(X), X.shape[1], metric, _p(knn_ids), knn_ids.shape[1], R, float(alpha),
-                    int(reverse), float(alpha_rev), _p(offs), _p(nb), _p(entry))
-    return offs, nb[: offs[-1]].copy(), int(entry[0])
+    links = lib().orc_build(n, _p(X), X.shape[1], metric, _p(knn_ids), knn_ids.shape[1], R,
+                            float(alpha), (1 if reverse else 0) | (2 if repair else 0),
+                            float(alpha_rev), _p(offs), _p(nb), _p(entry))
+    out = (offs, nb[: offs[-1]].copy(), int(entry[0]))
+    return out + (int(links),) if return_links else out
+
+
+def repair(X, rows, R, entry, metric=L2SQ):
+    """The builder's reachability repair applied to `rows` (lists of ids, at
+    most R each); returns (new rows, links added)."""
+    X = _f32(X)
+    n = X.shape[0]
+    pad = np.full((n, R), -1, dtype=np.int32)
+    deg = np.zeros(n, dtype=np.int32)
+    for v, r in enumerate(rows):
+        pad[v, :len(r)] = r
+        deg[v] = len(r)
+    links = lib().orc_repair(n, _p(X), X.shape[1], metric, R, _p(pad), _p(deg), int(entry))
+    return [pad[v, :deg[v]].tolist() for v in range(n)], int(links)
+
+
+def reachable(offsets, nbrs, entry):
+    """Vertices reachable from the entry along the graph's edges (entry included)."""
+    offsets, nbrs = _i64(offsets), _i32(nbrs)
+    n = len(offsets) - 1
+    return int(lib().orc_reachable(n, _p(offsets), _p(nbrs if len(nbrs) else np.zeros(1, np.int32)),
+                                   int(entry)))
 
 
 def search_graph(offsets, nbrs, X, Q, entry, ef, topk=10, metric=L2SQ):

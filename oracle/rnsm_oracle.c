@@ -997,9 +997,110 @@ int orc_knn_queries(int64_t n, const float* X, int64_t nq, const float* Q, int d
  * value is an integer, double precision otherwise), ties by id.
  * out_nbrs has room for n x R ids; out_offsets n+1.
  */
+/* Everything reachable from `start` along the rows (up to R ids per row,
+ * deg[v] used) that is not yet marked joins vis; returns how many joined. */
+static int64_t reach_from(int64_t n, int R, const int32_t* rows, const int32_t* deg, int64_t start,
+                          char* vis, int32_t* queue) {
+    if (vis[start]) return 0;
+    int64_t head = 0, tail = 0;
+    vis[start] = 1;
+    queue[tail++] = (int32_t)start;
+    while (head < tail) {
+        const int64_t v = queue[head++];
+        for (int j = 0; j < deg[v]; ++j) {
+            const int32_t w = rows[v * R + j];
+            if (w >= 0 && w < n && !vis[w]) {
+                vis[w] = 1;
+                queue[tail++] = w;
+            }
+        }
+    }
+    return tail;
+}
+
+int64_t orc_reachable(int64_t n, const int64_t* offsets, const int32_t* nbrs, int32_t entry) {
+    if (n <= 0 || entry < 0 || entry >= n) return 0;
+    char* vis = (char*)calloc((size_t)n, 1);
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t head = 0, tail = 0;
+    vis[entry] = 1;
+    queue[tail++] = entry;
+    while (head < tail) {
+        const int64_t v = queue[head++];
+        for (int64_t j = offsets[v]; j < offsets[v + 1]; ++j) {
+            const int32_t w = nbrs[j];
+            if (w >= 0 && w < n && !vis[w]) {
+                vis[w] = 1;
+                queue[tail++] = w;
+            }
+        }
+    }
+    free(vis);
+    free(queue);
+    return tail;
+}
+
+/* Reachability repair of a built graph: every vertex the entry cannot reach
+ * is linked in. The unreached vertex u of smallest id is linked from the
+ * reached vertex r nearest to it ((d, id) order over all vertices reached so
+ * far): u is appended to r's row, or replaces the row's last entry (its
+ * farthest, rows being in (d, id) order) when the row is full. Everything u
+ * reaches then counts as reached, and the next unreached vertex follows. A
+ * replaced edge can cut off vertices reached only through it, so passes
+ * repeat (at most 8) until one starts with every vertex reached. Returns the
+ * number of links added. */
+static int64_t repair_reach(const space_t* S, int64_t n, int R, int32_t* rows, int32_t* deg,
+                            int32_t entry) {
+    char* vis = (char*)malloc((size_t)n);
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t links = 0;
+    for (int pass = 0; pass < 8; ++pass) {
+        memset(vis, 0, (size_t)n);
+        int64_t got = reach_from(n, R, rows, deg, entry, vis, queue);
+        if (got == n) break;
+        for (int64_t u = 0; u < n && got < n; ++u) {
+            if (vis[u]) continue;
+            int64_t r = -1;
+            double dr = 0.0;
+            for (int64_t v = 0; v < n; ++v) {
+                if (!vis[v]) continue;
+                const double d = dist_ids(S, u, v);
+                if (r < 0 || key_less(d, v, dr, r)) {
+                    r = v;
+                    dr = d;
+                }
+            }
+            if (deg[r] < R)
+                rows[r * R + deg[r]++] = (int32_t)u;
+            else
+                rows[r * R + R - 1] = (int32_t)u;
+            ++links;
+            got += reach_from(n, R, rows, deg, u, vis, queue);
+        }
+    }
+    free(vis);
+    free(queue);
+    return links;
+}
+
+int64_t orc_repair(int64_t n, const float* X, int dim, int metric, int R, int32_t* rows,
+                   int32_t* deg, int32_t entry) {
+    if (n <= 0 || entry < 0 || entry >= n) return 0;
+    double* norms = NULL;
+    if (metric == ORC_COSINE) {
+        norms = (double*)malloc(sizeof(double) * (size_t)n);
+        orc_norms(X, n, dim, norms);
+    }
+    space_t S = {X, dim, metric, norms};
+    const int64_t links = repair_reach(&S, n, R, rows, deg, entry);
+    free(norms);
+    return links;
+}
+
 int orc_build(int64_t n, const float* X, int dim, int metric, const int32_t* knn, int K, int R,
-              float alpha, int reverse, float alpha_rev, int64_t* out_offsets, int32_t* out_nbrs,
+              float alpha, int options, float alpha_rev, int64_t* out_offsets, int32_t* out_nbrs,
               int32_t* out_entry) {
+    const int reverse = options & 1;
     double* norms = NULL;
     if (metric == ORC_COSINE) {
         norms = (double*)malloc(sizeof(double) * (size_t)n);
@@ -1049,11 +1150,6 @@ int orc_build(int64_t n, const float* X, int dim, int metric, const int32_t* knn
         memcpy(deg, deg2, sizeof(int32_t) * (size_t)n);
         free(rows2); free(deg2); free(W2); free(rev); free(fill); free(cnt);
     }
-    out_offsets[0] = 0;
-    for (int64_t v = 0; v < n; ++v) {
-        out_offsets[v + 1] = out_offsets[v] + deg[v];
-        memcpy(out_nbrs + out_offsets[v], rows + v * R, sizeof(int32_t) * (size_t)deg[v]);
-    }
     /* entry */
     int integral = 1;
     for (int64_t i = 0; i < n * dim && integral; ++i)
@@ -1090,6 +1186,13 @@ int orc_build(int64_t n, const float* X, int dim, int metric, const int32_t* knn
         free(mean);
     }
     *out_entry = (int32_t)best;
+    int64_t links = 0;
+    if (options & 2) links = repair_reach(&S, n, R, rows, deg, (int32_t)best);
+    out_offsets[0] = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        out_offsets[v + 1] = out_offsets[v] + deg[v];
+        memcpy(out_nbrs + out_offsets[v], rows + v * R, sizeof(int32_t) * (size_t)deg[v]);
+    }
     free(rows); free(rd); free(deg); free(norms);
-    return 0;
+    return (int)links;
 }

@@ -66,7 +66,15 @@ int orc_merge(int m, const int64_t* sizes, const int64_t* offsets_cat, const int
 int orc_knn(int64_t n, const float* X, int dim, int metric, int K, int32_t* out);
 int orc_knn_queries(int64_t n, const float* X, int64_t nq, const float* Q, int dim, int metric,
                     int K, int32_t* out_ids, double* out_d);
+/* options: 1 reverse edges with an alpha_rev re-prune, 2 reachability repair
+ * from the entry; returns the number of repair links added */
 int orc_build(int64_t n, const float* X, int dim, int metric, const int32_t* knn, int K, int R,
-              float alpha, int reverse, float alpha_rev, int64_t* out_offsets, int32_t* out_nbrs,
+              float alpha, int options, float alpha_rev, int64_t* out_offsets, int32_t* out_nbrs,
               int32_t* out_entry);
+/* the builder's reachability repair on rows of up to R ids (row v at rows +
+ * v R, deg[v] used), in place; returns the number of links added */
+int64_t orc_repair(int64_t n, const float* X, int dim, int metric, int R, int32_t* rows,
+                   int32_t* deg, int32_t entry);
+/* vertices reachable from entry along the CSR edges (entry included) */
+int64_t orc_reachable(int64_t n, const int64_t* offsets, const int32_t* nbrs, int32_t entry);
 #endif

@@ -746,3 +746,69 @@ def test_bf16_rounding_is_nearest(orc):
         assert np.all(d0[ok] <= d1[ok])
         tie = ok & (d0 == d1)
         assert np.all((b[tie] & 1) == 0)
+
+
+def test_repair_reach_golden(orc):
+    # hand-traced repairs: append, a link from a vertex reached earlier in
+    # the same pass, a distance tie, a full row's last entry replaced, and a
+    # cut-off vertex linked back by a second pass
+    for case in _gold("repair_reach.json")["cases"]:
+        X = np.array(case["points"], dtype=np.float32)
+        rows, links = orc.repair(X, case["rows"], case["R"], case["entry"])
+        assert rows == case["want_rows"], case["name"]
+        assert links == case["want_links"], case["name"]
+
+
+def test_builder_repair_two_clusters(orc):
+    # two far-apart clusters: the within-cluster k-NN graph leaves the other
+    # cluster unreachable from the entry; the repaired graph reaches every
+    # vertex, only rows that received a link change (by an append, or the
+    # last entry replaced), each link starts at a vertex the entry reached
+    # before the repair and the first goes to the smallest unreached id from
+    # its nearest reached vertex (brute force)
+    g = inputs.rng(1601)
+    A = g.integers(-3, 4, (70, 8))
+    B = g.integers(-3, 4, (50, 8)) + 60
+    X = np.concatenate([A, B]).astype(np.float32)
+    n, R = 120, 6
+    base = orc.build_graph(X, 10, R, alpha=1.0)
+    *fixed, links = orc.build_graph(X, 10, R, alpha=1.0, repair=True, return_links=True)
+    assert base[2] == fixed[2]
+    before = orc.reachable(*base)
+    assert before < n and orc.reachable(*fixed) == n and links >= 1
+    r0 = [base[1][base[0][v]:base[0][v + 1]].tolist() for v in range(n)]
+    r1 = [fixed[1][fixed[0][v]:fixed[0][v + 1]].tolist() for v in range(n)]
+    # the reached set before the repair, by a plain BFS here
+    seen, todo = {base[2]}, [base[2]]
+    while todo:
+        v = todo.pop()
+        for w in r0[v]:
+            if w not in seen:
+                seen.add(w)
+                todo.append(w)
+    assert len(seen) == before
+    changed = [v for v in range(n) if r0[v] != r1[v]]
+    assert 1 <= len(changed) <= links
+    for v in changed:
+        assert v in seen
+        a, b = r0[v], r1[v]
+        assert (len(b) == len(a) + 1 and b[:-1] == a) or (len(a) == R and b[:-1] == a[:-1])
+        assert b[-1] not in seen
+    u0 = min(set(range(n)) - seen)
+    d = ((X.astype(np.int64) - X[u0].astype(np.int64)) ** 2).sum(1)
+    r = min(seen, key=lambda v: (d[v], v))
+    assert r1[r][-1] == u0
+    # a graph the entry already reaches is left as it was
+    C = inputs.tiny_int(200, 8, seed=1602)
+    g0 = orc.build_graph(C, 16, 8, alpha=1.2, reverse=True)
+    *g1, l1 = orc.build_graph(C, 16, 8, alpha=1.2, reverse=True, repair=True, return_links=True)
+    if orc.reachable(*g0) == 200:
+        assert l1 == 0 and np.array_equal(g0[1], g1[1])
+
+
+def test_reachable_counts(orc):
+    # a hand-made graph: 0 -> 1 -> 2, 3 <-> 4, 5 alone
+    offs, nb = _csr([[1], [2], [], [4], [3], []])
+    assert orc.reachable(offs, nb, 0) == 3
+    assert orc.reachable(offs, nb, 3) == 2
+    assert orc.reachable(offs, nb, 5) == 1
