@@ -382,18 +382,41 @@ rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int3
 
 /*
  * Sub-index builder used to make inputs: row(v) = Prune(v, knn(v), alpha, R);
- * with reverse != 0, every kept v -> w offers v to w, and each w that got
- * offers is pruned again over row(w) + offers with alpha_rev. Entry: the
+ * with RNSM_BUILD_REVERSE, every kept v -> w offers v to w, and each w that
+ * got offers is pruned again over row(w) + offers with alpha_rev. Entry: the
  * vertex closest to the centroid (exact integer criterion when every value
- * is an integer, float64 otherwise), ties by id.
+ * is an integer, float64 otherwise), ties by id. With RNSM_BUILD_REPAIR,
+ * every vertex the entry cannot reach is linked in (the searches of
+ * Algorithm 1 start from the entry alone): the unreached vertex of smallest
+ * id gets an edge from the reached vertex nearest to it ((distance, id)
+ * order, float32 distances) among those with a free slot, appended there,
+ * or, every reached row being full, from the nearest reached vertex,
+ * replacing its row's last (farthest) entry; what it reaches then counts as
+ * reached; passes repeat (at most 8) until one starts with every vertex
+ * reached.
  * X: device [n x dim] float32. knn: device [n x K] local ids sorted by
  * (d, id), -1 padded, no self. out_offsets: device [n+1]; out_nbrs: device
- * [n x R] capacity. *out_entry written.
+ * [n x R] capacity. *out_entry written; *out_links (may be NULL): repair
+ * links added. Synchronises `stream`.
  */
+#define RNSM_BUILD_REVERSE 1
+#define RNSM_BUILD_REPAIR 2
 rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric metric,
                              const int32_t* knn, int32_t K, int32_t R, float alpha,
-                             int32_t reverse, float alpha_rev, int64_t* out_offsets,
-                             int32_t* out_nbrs, int32_t* out_entry, void* stream);
+                             int32_t options, float alpha_rev, int64_t* out_offsets,
+                             int32_t* out_nbrs, int32_t* out_entry, int64_t* out_links,
+                             void* stream);
+
+/*
+ * Vertices reachable from `entry` along the edges of a CSR graph (entry
+ * included): the fraction a search from the entry (Algorithm 1) can reach.
+ * offsets: device [n+1] int64, nbrs: device int32 ids (entries outside
+ * 0..n-1 are skipped). *out_count written. Synchronises `stream`.
+ * RNSM_EINVAL on a NULL pointer, an entry outside 0..n-1 or malformed
+ * offsets.
+ */
+rnsm_status rnsm_reachable(int64_t n, const int64_t* offsets, const int32_t* nbrs, int32_t entry,
+                           int64_t* out_count, void* stream);
 
 /*
  * Staging conversion of vectors on the device (the inputs of the merge: the

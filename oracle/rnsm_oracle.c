@@ -1042,13 +1042,14 @@ int64_t orc_reachable(int64_t n, const int64_t* offsets, const int32_t* nbrs, in
 
 /* Reachability repair of a built graph: every vertex the entry cannot reach
  * is linked in. The unreached vertex u of smallest id is linked from the
- * reached vertex r nearest to it ((d, id) order over all vertices reached so
- * far): u is appended to r's row, or replaces the row's last entry (its
- * farthest, rows being in (d, id) order) when the row is full. Everything u
- * reaches then counts as reached, and the next unreached vertex follows. A
- * replaced edge can cut off vertices reached only through it, so passes
- * repeat (at most 8) until one starts with every vertex reached. Returns the
- * number of links added. */
+ * reached vertex nearest to it ((d, id) order over all vertices reached so
+ * far) among those with a free slot in their row, u appended there; when
+ * every reached row is full, from the nearest reached vertex, u replacing
+ * its row's last entry (its farthest, rows being in (d, id) order).
+ * Everything u reaches then counts as reached, and the next unreached vertex
+ * follows. A replaced edge can cut off vertices reached only through it, so
+ * passes repeat (at most 8) until one starts with every vertex reached.
+ * Returns the number of links added. */
 static int64_t repair_reach(const space_t* S, int64_t n, int R, int32_t* rows, int32_t* deg,
                             int32_t entry) {
     char* vis = (char*)malloc((size_t)n);
@@ -1060,8 +1061,8 @@ static int64_t repair_reach(const space_t* S, int64_t n, int R, int32_t* rows, i
         if (got == n) break;
         for (int64_t u = 0; u < n && got < n; ++u) {
             if (vis[u]) continue;
-            int64_t r = -1;
-            double dr = 0.0;
+            int64_t r = -1, rf = -1;  /* nearest reached; nearest reached with a free slot */
+            double dr = 0.0, drf = 0.0;
             for (int64_t v = 0; v < n; ++v) {
                 if (!vis[v]) continue;
                 const double d = dist_ids(S, u, v);
@@ -1069,9 +1070,13 @@ static int64_t repair_reach(const space_t* S, int64_t n, int R, int32_t* rows, i
                     r = v;
                     dr = d;
                 }
+                if (deg[v] < R && (rf < 0 || key_less(d, v, drf, rf))) {
+                    rf = v;
+                    drf = d;
+                }
             }
-            if (deg[r] < R)
-                rows[r * R + deg[r]++] = (int32_t)u;
+            if (rf >= 0)
+                rows[rf * R + deg[rf]++] = (int32_t)u;
             else
                 rows[r * R + R - 1] = (int32_t)u;
             ++links;

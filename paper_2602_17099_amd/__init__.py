@@ -24,7 +24,8 @@ DEVICE, HOST = 0, 1
 
 SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_select_pivots", "rnsm_search",
            "rnsm_search_noalloc", "rnsm_tune_search", "rnsm_build_graph", "rnsm_convert",
-           "rnsm_get_stats", "rnsm_last_error", "rnsm_csr_free", "rnsm_select_pivots_device"]
+           "rnsm_get_stats", "rnsm_last_error", "rnsm_csr_free", "rnsm_select_pivots_device",
+           "rnsm_reachable"]
 
 _lib = None
 
@@ -114,7 +115,9 @@ def lib():
         L.rnsm_search_noalloc.argtypes = L.rnsm_search.argtypes
         L.rnsm_build_graph.restype = C.c_int
         L.rnsm_build_graph.argtypes = [C.c_int64, P, C.c_int32, C.c_int, P, C.c_int32, C.c_int32,
-                                       C.c_float, C.c_int32, C.c_float, P, P, P, P]
+                                       C.c_float, C.c_int32, C.c_float, P, P, P, P, P]
+        L.rnsm_reachable.restype = C.c_int
+        L.rnsm_reachable.argtypes = [C.c_int64, P, P, C.c_int32, P, P]
         L.rnsm_convert.restype = C.c_int
         L.rnsm_convert.argtypes = [P, C.c_int, P, C.c_int, C.c_int64, P]
         L.rnsm_get_stats.restype = C.c_int
@@ -359,20 +362,36 @@ def tune_search(offsets, nbrs, entry, base, ef, n_sample=65536, metric=L2SQ, bas
             "default_ms": t.default_ms, "n_queries": t.n_queries, "n_tried": t.n_tried}
 
 
-def build_graph(X, knn, R, alpha=1.0, reverse=False, alpha_rev=1.2, metric=L2SQ, stream=None):
-    """Sub-index builder from exact k-NN lists (device int32 [n, K])."""
+def build_graph(X, knn, R, alpha=1.0, reverse=False, alpha_rev=1.2, metric=L2SQ, stream=None,
+                repair=False, return_links=False):
+    """Sub-index builder from exact k-NN lists (device int32 [n, K]);
+    repair=True links in every vertex the entry cannot reach.
+    Returns (offsets, nbrs, entry) [, repair links added]."""
     import torch
     n, dim = X.shape
     K = knn.shape[1]
     off = torch.empty(n + 1, dtype=torch.int64, device=X.device)
     nb = torch.empty(n * R, dtype=torch.int32, device=X.device)
     entry = C.c_int32(0)
+    links = C.c_int64(0)
+    opts = (1 if reverse else 0) | (2 if repair else 0)
     _check(lib().rnsm_build_graph(n, C.c_void_p(X.data_ptr()), dim, metric,
-                                  C.c_void_p(knn.data_ptr()), K, R, float(alpha), int(reverse),
+                                  C.c_void_p(knn.data_ptr()), K, R, float(alpha), opts,
                                   float(alpha_rev), C.c_void_p(off.data_ptr()),
-                                  C.c_void_p(nb.data_ptr()), C.byref(entry), _stream(stream)))
+                                  C.c_void_p(nb.data_ptr()), C.byref(entry), C.byref(links),
+                                  _stream(stream)))
     ne = int(off[-1].item())
-    return off, nb[:ne].clone(), entry.value
+    out = (off, nb[:ne].clone(), entry.value)
+    return out + (links.value,) if return_links else out
+
+
+def reachable(off, nb, entry, stream=None):
+    """Vertices reachable from the entry of a device CSR graph (rnsm_reachable)."""
+    cnt = C.c_int64(0)
+    n = off.shape[0] - 1
+    _check(lib().rnsm_reachable(n, C.c_void_p(off.data_ptr()), C.c_void_p(nb.data_ptr()),
+                                int(entry), C.byref(cnt), _stream(stream)))
+    return cnt.value
 
 
 _DT = {"float32": 0, "bfloat16": 1, "float16": 2, "uint8": 3}

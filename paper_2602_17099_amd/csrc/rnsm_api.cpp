@@ -2371,9 +2371,14 @@ static rnsm_status rnsm_tune_search_impl(const rnsm_graph* g, const rnsm_vectors
 
 static rnsm_status rnsm_build_graph_impl(int64_t n, const float* X, int32_t dim, rnsm_metric metric,
                              const int32_t* knn, int32_t K, int32_t R, float alpha,
-                             int32_t reverse, float alpha_rev, int64_t* out_offsets,
-                             int32_t* out_nbrs, int32_t* out_entry, void* stream) {
+                             int32_t options, float alpha_rev, int64_t* out_offsets,
+                             int32_t* out_nbrs, int32_t* out_entry, int64_t* out_links,
+                             void* stream) {
     g_err.clear();
+    if (out_links) *out_links = 0;
+    if (options & ~(RNSM_BUILD_REVERSE | RNSM_BUILD_REPAIR))
+        return fail(RNSM_EINVAL, "rnsm_build_graph: unknown option bits");
+    const bool reverse = (options & RNSM_BUILD_REVERSE) != 0;
     if (n < 1 || !X || !knn || !out_offsets || !out_nbrs || !out_entry)
         return fail(RNSM_EINVAL, "rnsm_build_graph: bad argument");
     if (K < 1 || R < 1 || R > 64) return fail(RNSM_EINVAL, "rnsm_build_graph: K < 1 or R outside 1..64");
@@ -2479,10 +2484,6 @@ static rnsm_status rnsm_build_graph_impl(int64_t n, const float* X, int32_t dim,
         rows = rows2;
         deg = deg2;
     }
-    int64_t* stmp3;
-    WS(stmp3, "b_stmp3", sizeof(int64_t) * scan_tmp_elems(n));
-    HIPCHK(launch_scan(deg, n, out_offsets, stmp3, st));
-    HIPCHK(launch_compact(rows, deg, d1, out_offsets, n, R, X, dim, metric, norms, out_nbrs, nullptr, st));
     // entry: closest to the centroid
     int* flag;
     double* cs;
@@ -2511,7 +2512,80 @@ static rnsm_status rnsm_build_graph_impl(int64_t n, const float* X, int32_t dim,
         const u64* y = &hb[3 * best];
         if (x[0] < y[0] || (x[0] == y[0] && (x[1] < y[1] || (x[1] == y[1] && x[2] < y[2])))) best = b;
     }
-    *out_entry = (int32_t)hb[3 * best + 2];
+    const int32_t entry = (int32_t)hb[3 * best + 2];
+    *out_entry = entry;
+    if (options & RNSM_BUILD_REPAIR) {
+        // reachability repair on the -1 padded rows, host-paced: one link
+        // per unreached piece, each followed by the search of what it reaches
+        unsigned *vis, *ctl, *h_ctl;
+        int32_t* order;
+        unsigned long long* tmp;
+        WS(vis, "b_vis", sizeof(unsigned) * ((n + 31) / 32));
+        WS(order, "b_order", sizeof(int32_t) * n);
+        WS(ctl, "b_ctl", sizeof(unsigned) * 4);
+        WS(tmp, "b_repair", sizeof(unsigned long long) * 3);
+        HS(h_ctl, "h_b_ctl", sizeof(unsigned) * 4);
+        HIPCHK(launch_pad_tail(rows, deg, n, R, st));
+        int64_t links = 0;
+        for (int pass = 0; pass < 8; ++pass) {
+            HIPCHK(launch_bfs_init(n, entry, vis, order, ctl, st));
+            HIPCHK(launch_bfs_grow(rows, R, n, order, vis, ctl, h_ctl, st));
+            int64_t got = h_ctl[0];
+            if (got >= n) break;
+            while (got < n) {
+                HIPCHK(launch_repair_link(X, dim, metric, norms, n, rows, deg, R, vis, order, ctl,
+                                          tmp, st));
+                HIPCHK(launch_bfs_grow(rows, R, n, order, vis, ctl, h_ctl, st));
+                if ((int64_t)h_ctl[0] <= got)
+                    return fail(RNSM_EINTERNAL, "rnsm_build_graph: a repair link reached nothing");
+                got = h_ctl[0];
+                ++links;
+            }
+        }
+        if (out_links) *out_links = links;
+    }
+    int64_t* stmp3;
+    WS(stmp3, "b_stmp3", sizeof(int64_t) * scan_tmp_elems(n));
+    HIPCHK(launch_scan(deg, n, out_offsets, stmp3, st));
+    HIPCHK(launch_compact(rows, deg, d1, out_offsets, n, R, X, dim, metric, norms, out_nbrs, nullptr, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return RNSM_OK;
+}
+
+static rnsm_status rnsm_reachable_impl(int64_t n, const int64_t* offsets, const int32_t* nbrs,
+                                       int32_t entry, int64_t* out_count, void* stream) {
+    g_err.clear();
+    if (!out_count || n < 1 || !offsets || !nbrs || entry < 0 || entry >= n || n > INT32_MAX)
+        return fail(RNSM_EINVAL, "rnsm_reachable: bad argument");
+    *out_count = 0;
+    std::lock_guard<std::mutex> lk(g_lock);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    Workspace& ws = g_ws[dev];
+    ws.begin_call(0);
+    unsigned *md, *h_md;
+    int* bad;
+    WS(md, "r_shape", sizeof(unsigned) * 2);
+    HS(h_md, "h_r_shape", sizeof(unsigned) * 2);
+    bad = reinterpret_cast<int*>(md + 1);
+    HIPCHK(launch_zero(md, sizeof(unsigned) * 2, st));
+    HIPCHK(launch_csr_shape(offsets, n, md, bad, st));
+    HIPCHK(hipMemcpyAsync(h_md, md, sizeof(unsigned) * 2, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h_md[1]) return fail(RNSM_EINVAL, "rnsm_reachable: malformed offsets");
+    const int rp = std::max(1u, h_md[0]);
+    int32_t *padj, *order;
+    unsigned *vis, *ctl, *h_ctl;
+    WS(padj, "r_padj", sizeof(int32_t) * n * rp);
+    WS(order, "r_order", sizeof(int32_t) * n);
+    WS(vis, "r_vis", sizeof(unsigned) * ((n + 31) / 32));
+    WS(ctl, "r_ctl", sizeof(unsigned) * 4);
+    HS(h_ctl, "h_r_ctl", sizeof(unsigned) * 4);
+    HIPCHK(launch_pad_adjacency(offsets, nbrs, n, rp, padj, st));
+    HIPCHK(launch_bfs_init(n, entry, vis, order, ctl, st));
+    HIPCHK(launch_bfs_grow(padj, rp, n, order, vis, ctl, h_ctl, st));
+    *out_count = std::min<int64_t>(n, h_ctl[0]);
     return RNSM_OK;
 }
 
@@ -2610,9 +2684,15 @@ rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int3
 
 rnsm_status rnsm_build_graph(int64_t n, const float* X, int32_t dim, rnsm_metric metric,
                              const int32_t* knn, int32_t K, int32_t R, float alpha,
-                             int32_t reverse, float alpha_rev, int64_t* out_offsets,
-                             int32_t* out_nbrs, int32_t* out_entry, void* stream) {
-    return guard("rnsm_build_graph", [&] { return rnsm_build_graph_impl(n, X, dim, metric, knn, K, R, alpha, reverse, alpha_rev, out_offsets, out_nbrs, out_entry, stream); });
+                             int32_t options, float alpha_rev, int64_t* out_offsets,
+                             int32_t* out_nbrs, int32_t* out_entry, int64_t* out_links,
+                             void* stream) {
+    return guard("rnsm_build_graph", [&] { return rnsm_build_graph_impl(n, X, dim, metric, knn, K, R, alpha, options, alpha_rev, out_offsets, out_nbrs, out_entry, out_links, stream); });
+}
+
+rnsm_status rnsm_reachable(int64_t n, const int64_t* offsets, const int32_t* nbrs, int32_t entry,
+                           int64_t* out_count, void* stream) {
+    return guard("rnsm_reachable", [&] { return rnsm_reachable_impl(n, offsets, nbrs, entry, out_count, stream); });
 }
 
 }  // extern "C"

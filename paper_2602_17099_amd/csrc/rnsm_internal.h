@@ -243,6 +243,25 @@ int64_t entry_blocks(int64_t n);
 #define BFS_BATCH 8
 hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, unsigned* vis,
                             int32_t* order, unsigned* ctl, unsigned* h_ctl, hipStream_t st);
+// the same in steps: init from root; grow (levels until the frontier is
+// empty; h_ctl[0] = vertices reached, order[0, h_ctl[0]) the reached ones)
+hipError_t launch_bfs_init(int64_t n, int32_t root, unsigned* vis, int32_t* order, unsigned* ctl,
+                           hipStream_t st);
+hipError_t launch_bfs_grow(const int32_t* padj, int rp, int64_t n, int32_t* order, unsigned* vis,
+                           unsigned* ctl, unsigned* h_ctl, hipStream_t st);
+// one link of the reachability repair on rows (-1 padded, R per row): the
+// smallest unreached id u from the nearest reached vertex (distance key, id)
+// with a free slot, appended there, or, every reached row being full, over
+// the last entry of the nearest reached row; u becomes the next frontier
+// (launch_bfs_grow then adds what it reaches). tmp: 3 words
+hipError_t launch_repair_link(const float* X, int dim, int metric, const float* norms, int64_t n,
+                              int32_t* rows, int32_t* deg, int R, unsigned* vis, int32_t* order,
+                              unsigned* ctl, unsigned long long* tmp, hipStream_t st);
+hipError_t launch_pad_tail(int32_t* rows, const int32_t* deg, int64_t n, int R, hipStream_t st);
+// largest row length (atomicMax into *maxdeg, zeroed by the caller) and a
+// flag for malformed offsets
+hipError_t launch_csr_shape(const int64_t* offs, int64_t n, unsigned* maxdeg, int* bad,
+                            hipStream_t st);
 
 // lanes per row for rows of nch 16-byte chunks: the smallest power of two G
 // with 4*G >= nch that divides nch, so that every lane holds nch/G <= 4 whole

@@ -2002,6 +2002,99 @@ __global__ __launch_bounds__(BFS_T) void k_bfs_rest(int64_t n, const unsigned* v
     block_append(miss, (int32_t)t, order, tail);
 }
 
+// ------------------------------------------------ reachability and its repair
+
+// the vertex u = *ures joins the reached set as the next frontier by itself
+__global__ void k_bfs_push(const unsigned long long* ures, unsigned* vis, int32_t* order,
+                           unsigned* ctl) {
+    if (*ures >= 0x7fffffffull) return;  // nothing unreached
+    const int32_t u = (int32_t)*ures;
+    const unsigned t = ctl[0];
+    vis[u >> 5] |= 1u << (u & 31);
+    order[t] = u;
+    ctl[0] = t + 1;
+    ctl[1] = t;
+    ctl[2] = t + 1;
+    ctl[3] = 0;
+}
+
+// smallest id whose reached bit is clear (out starts at ~0)
+__global__ void k_first_unreached(const unsigned* vis, int64_t n, unsigned long long* out) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= (n + 31) >> 5) return;
+    unsigned miss = ~vis[w];
+    const int64_t valid = n - w * 32;
+    if (valid < 32) miss &= (1u << valid) - 1u;
+    if (miss) atomicMin(out, (unsigned long long)(w * 32 + __ffs(miss) - 1));
+}
+
+// the reached vertex nearest to u = *ures, as the least (distance key, id),
+// into best[0]; the nearest with a free slot in its row into best[1]: one
+// wavefront per vertex, lanes over the dimensions (float32, each lane's sum
+// then a butterfly: exact on integer rows)
+__global__ void k_nearest_reached(const float* X, int dim, int metric, const float* norms,
+                                  int64_t n, const unsigned* vis, const int32_t* deg, int R,
+                                  const unsigned long long* ures, unsigned long long* best) {
+    const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (v >= n || *ures >= (unsigned long long)n || !((vis[v >> 5] >> (v & 31)) & 1u)) return;
+    const int lane = lane_id();
+    const int64_t u = (int64_t)*ures;
+    const float* a = X + u * dim;
+    const float* b = X + v * dim;
+    float acc = 0.0f;
+    for (int j = lane; j < dim; j += WAVE) {
+        if (metric == 0) {
+            const float t = a[j] - b[j];
+            acc = fmaf(t, t, acc);
+        } else {
+            acc = fmaf(a[j], b[j], acc);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane != 0) return;
+    float d = acc;
+    if (metric == 1) d = 1.0f - acc;
+    if (metric == 2) d = 1.0f - acc / (norms[u] * norms[v]);
+    const unsigned long long key = ((unsigned long long)fkey(d) << 32) | (unsigned long long)v;
+    atomicMin(&best[0], key);
+    if (deg[v] < R) atomicMin(&best[1], key);
+}
+
+// the link to u: appended to the nearest reached row with a free slot, or,
+// when every reached row is full, over the last entry of the nearest one
+__global__ void k_repair_link(int32_t* rows, int32_t* deg, int R, const unsigned long long* ures,
+                              const unsigned long long* best) {
+    if (*ures >= 0x7fffffffull || best[0] == ~0ull) return;
+    const int32_t u = (int32_t)*ures;
+    if (best[1] != ~0ull) {
+        const int64_t r = (int64_t)(best[1] & 0xffffffffull);
+        rows[r * R + deg[r]++] = u;
+    } else {
+        const int64_t r = (int64_t)(best[0] & 0xffffffffull);
+        rows[r * R + R - 1] = u;
+    }
+}
+
+// -1 after each row's used entries (row v: rows + v R, deg[v] used)
+__global__ void k_pad_tail(int32_t* rows, const int32_t* deg, int64_t n, int R) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * R) return;
+    if ((int)(t % R) >= deg[t / R]) rows[t] = -1;
+}
+
+// largest row length of a CSR graph, and whether its offsets are well formed
+__global__ void k_csr_shape(const int64_t* offs, int64_t n, unsigned* maxdeg, int* bad) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int64_t d = offs[x + 1] - offs[x];
+    if (d < 0 || d > 0x7fffffff || offs[x] < 0) {
+        atomicOr(bad, 1);
+        return;
+    }
+    atomicMax(maxdeg, (unsigned)d);
+}
+
 // one thread per row slot, so that consecutive threads write consecutive ids
 __global__ void k_init_rows(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t base,
                             int R, int32_t* rows, int32_t* deg, float* rdist) {
@@ -2457,13 +2550,19 @@ __global__ __launch_bounds__(ENTRY_T) void k_entry_crit(const float* X, int64_t 
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, unsigned* vis,
-                            int32_t* order, unsigned* ctl, unsigned* h_ctl, hipStream_t st) {
+hipError_t launch_bfs_init(int64_t n, int32_t root, unsigned* vis, int32_t* order, unsigned* ctl,
+                           hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (root < 0 || root >= n) root = 0;
     hipLaunchKernelGGL(k_bfs_init, dim3(nblk((n + 31) >> 5, 256)), dim3(256), 0, st, n, root, vis,
                        order, ctl);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_bfs_grow(const int32_t* padj, int rp, int64_t n, int32_t* order, unsigned* vis,
+                           unsigned* ctl, unsigned* h_ctl, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipError_t e = hipSuccess;
     // at most one thread per (vertex, slot) of the largest possible frontier
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nblk(n * rp, BFS_T), 512));
     for (;;) {
@@ -2478,6 +2577,15 @@ hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root
         // stop once the frontier is empty (every reachable vertex ordered)
         if (h_ctl[2] <= h_ctl[1] || (int64_t)h_ctl[0] > n) break;
     }
+    return e;
+}
+
+hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root, unsigned* vis,
+                            int32_t* order, unsigned* ctl, unsigned* h_ctl, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipError_t e = launch_bfs_init(n, root, vis, order, ctl, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_bfs_grow(padj, rp, n, order, vis, ctl, h_ctl, st)) != hipSuccess) return e;
     if ((int64_t)h_ctl[0] < n) {
         hipLaunchKernelGGL(k_bfs_rest, dim3(nblk(n, BFS_T)), dim3(BFS_T), 0, st, n, vis, order, ctl);
         e = hipGetLastError();
@@ -2485,6 +2593,35 @@ hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root
     return e;
 }
 
+
+hipError_t launch_pad_tail(int32_t* rows, const int32_t* deg, int64_t n, int R, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pad_tail, dim3(nblk(n * R, 256)), dim3(256), 0, st, rows, deg, n, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_shape(const int64_t* offs, int64_t n, unsigned* maxdeg, int* bad,
+                            hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_csr_shape, dim3(nblk(n, 256)), dim3(256), 0, st, offs, n, maxdeg, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_repair_link(const float* X, int dim, int metric, const float* norms, int64_t n,
+                              int32_t* rows, int32_t* deg, int R, unsigned* vis, int32_t* order,
+                              unsigned* ctl, unsigned long long* tmp, hipStream_t st) {
+    // tmp[0]: the smallest unreached id, tmp[1], tmp[2]: the nearest reached
+    // key, the nearest with a free slot
+    hipError_t e = hipMemsetAsync(tmp, 0xff, 3 * sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_first_unreached, dim3(nblk((n + 31) >> 5, 256)), dim3(256), 0, st, vis, n,
+                       tmp);
+    hipLaunchKernelGGL(k_nearest_reached, dim3(nblk(n * WAVE, 256)), dim3(256), 0, st, X, dim,
+                       metric, norms, n, vis, deg, R, tmp, tmp + 1);
+    hipLaunchKernelGGL(k_repair_link, dim3(1), dim3(1), 0, st, rows, deg, R, tmp, tmp + 1);
+    hipLaunchKernelGGL(k_bfs_push, dim3(1), dim3(1), 0, st, tmp, vis, order, ctl);
+    return hipGetLastError();
+}
 
 hipError_t launch_validate(const int64_t* offs, const int32_t* nbrs, int64_t n, int64_t nnz,
                            int R, int* flags, hipStream_t st) {

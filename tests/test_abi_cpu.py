@@ -262,7 +262,7 @@ def test_header_is_plain_c(tmp_path):
                    "    fn f[] = {(fn)rnsm_merge, (fn)rnsm_merge_simple, (fn)mos_plan,\n"
                    "              (fn)rnsm_select_pivots, (fn)rnsm_search, (fn)rnsm_tune_search,\n"
                    "              (fn)rnsm_build_graph, (fn)rnsm_convert, (fn)rnsm_get_stats,\n"
-                   "              (fn)rnsm_last_error};\n"
+                   "              (fn)rnsm_last_error, (fn)rnsm_reachable};\n"
                    "    (void)p; (void)t; (void)s; (void)f;\n"
                    "    return RNSM_FLAG_AUTOTUNE == 4u ? 0 : 1;\n"
                    "}\n")

@@ -525,6 +525,61 @@ def test_build_graph_bit_exact(dev, orc, pkg, monkeypatch, reverse, mode):
     assert np.array_equal(nb.cpu().numpy(), ref[1])
 
 
+@pytest.mark.parametrize("case", ["two_clusters", "many_pieces", "reverse_connected"])
+def test_build_graph_repair_bit_exact(dev, orc, pkg, case):
+    # the builder's reachability repair: the same links as the oracle's
+    # (integer rows, so float32 distances are exact), every vertex reached
+    g = inputs.rng(1611)
+    if case == "two_clusters":
+        X = np.concatenate([g.integers(-3, 4, (700, 16)),
+                            g.integers(-3, 4, (500, 16)) + 40]).astype(np.float32)
+        K, R, a, rev = 10, 6, 1.0, False
+    elif case == "many_pieces":
+        # 40 tight clusters, few neighbours each: many unreached pieces
+        c = g.integers(0, 200, (40, 16))
+        X = (c[g.integers(0, 40, 3000)] + g.integers(-2, 3, (3000, 16))).astype(np.float32)
+        K, R, a, rev = 6, 4, 1.0, False
+    else:
+        X = inputs.mixture_u8(3000, 32, comps=12, seed=1612)
+        K, R, a, rev = 24, 12, 1.2, True
+    X = np.ascontiguousarray(X)
+    knn = orc.knn_fast(X, K)
+    base = orc.build_graph(X, K, R, alpha=a, reverse=rev, knn_ids=knn)
+    *ref, links = orc.build_graph(X, K, R, alpha=a, reverse=rev, knn_ids=knn, repair=True,
+                                  return_links=True)
+    off, nb, entry, glinks = pkg.build_graph(_t(X, dev), _t(knn, dev), R, alpha=a, reverse=rev,
+                                             repair=True, return_links=True)
+    assert entry == ref[2] and glinks == links
+    assert np.array_equal(off.cpu().numpy(), ref[0])
+    assert np.array_equal(nb.cpu().numpy(), ref[1])
+    n = X.shape[0]
+    assert pkg.reachable(off, nb, entry) == orc.reachable(*ref) == n
+    # the count before the repair, on the device and in the oracle
+    b_off, b_nb = _t(base[0], dev), _t(base[1] if len(base[1]) else np.zeros(1, np.int32), dev)
+    assert pkg.reachable(b_off, b_nb, base[2]) == orc.reachable(*base)
+    if case != "reverse_connected":
+        assert links >= 1 and orc.reachable(*base) < n
+
+
+def test_reachable_on_merged_graph(dev, orc, pkg, tiny):
+    X, subs = tiny
+    off, nb, _, entry = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=16, L=32, alpha=1.2)
+    ref = orc.merge(subs, X, R=16, L=32, alpha=1.2)
+    assert pkg.reachable(off, nb, entry) == orc.reachable(ref["offsets"], ref["nbrs"], ref["entry"])
+    for e in (0, 4999, 5000, 9999):
+        assert pkg.reachable(off, nb, e) == orc.reachable(ref["offsets"], ref["nbrs"], e)
+
+
+def test_reachable_rejects_bad_input(dev, pkg):
+    off = _t(np.array([0, 2, 1], np.int64), dev)  # decreasing offsets
+    nb = _t(np.array([1, 0], np.int32), dev)
+    with pytest.raises(pkg.RnsmError):
+        pkg.reachable(off, nb, 0)
+    ok = _t(np.array([0, 1, 2], np.int64), dev)
+    with pytest.raises(pkg.RnsmError):
+        pkg.reachable(ok, nb, 5)
+
+
 # ------------------------------------------------------------ bad inputs
 
 def _bad(orc, kind):

@@ -43,8 +43,9 @@ MUTANTS = {
     "knn_queries_unsorted": ("qsort(c, (size_t)n, sizeof(wkey_t), wkey_cmp);", ""),
     "builder_reverse_with_alpha": ("deg2[w] = prune(&S, w, W2, nw, alpha_rev, R",
                                    "deg2[w] = prune(&S, w, W2, nw, alpha, R"),
-    "repair_links_from_farthest": ("if (r < 0 || key_less(d, v, dr, r))",
-                                   "if (r < 0 || key_less(dr, r, d, v))"),
+    "repair_links_from_farthest": ("if (deg[v] < R && (rf < 0 || key_less(d, v, drf, rf)))",
+                                   "if (deg[v] < R && (rf < 0 || key_less(drf, rf, d, v)))"),
+    "repair_ignores_free_slots": ("            if (rf >= 0)\n", "            if (0)\n"),
     "repair_replaces_first_entry": ("rows[r * R + R - 1] = (int32_t)u;", "rows[r * R] = (int32_t)u;"),
     "repair_reach_not_updated": ("got += reach_from(n, R, rows, deg, u, vis, queue);", "got += 1;"),
     "repair_single_pass": ("for (int pass = 0; pass < 8; ++pass)", "for (int pass = 0; pass < 1; ++pass)"),

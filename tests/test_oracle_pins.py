@@ -796,7 +796,8 @@ def test_builder_repair_two_clusters(orc):
         assert b[-1] not in seen
     u0 = min(set(range(n)) - seen)
     d = ((X.astype(np.int64) - X[u0].astype(np.int64)) ** 2).sum(1)
-    r = min(seen, key=lambda v: (d[v], v))
+    free = [v for v in seen if len(r0[v]) < R]
+    r = min(free or seen, key=lambda v: (d[v], v))
     assert r1[r][-1] == u0
     # a graph the entry already reaches is left as it was
     C = inputs.tiny_int(200, 8, seed=1602)
