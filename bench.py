@@ -114,18 +114,60 @@ def make_inputs(wl, seed_off=0):
     return np.ascontiguousarray(X), np.ascontiguousarray(Q)
 
 
-def build_subs(pkg, Xd, wl, parts=2):
+def build_graph_checked(pkg, Xi, knn, wl, info=None):
+    """The builder with the reachability repair; with `info`, also the
+    vertices reachable from the entry before the repair and the links it
+    added."""
+    kw = dict(alpha=wl["build_alpha"], reverse=wl["reverse"], alpha_rev=1.2)
+    if info is not None:
+        o0, b0, e0 = pkg.build_graph(Xi, knn, wl["R"], **kw)
+        info.setdefault("reachable_before_repair", []).append(pkg.reachable(o0, b0, e0) / Xi.shape[0])
+        del o0, b0
+    off, nb, entry, links = pkg.build_graph(Xi, knn, wl["R"], repair=True, return_links=True, **kw)
+    if info is not None:
+        info.setdefault("repair_links", []).append(links)
+        info.setdefault("reachable_after_repair", []).append(pkg.reachable(off, nb, entry) /
+                                                              Xi.shape[0])
+    return off, nb, entry
+
+
+def build_subs(pkg, Xd, wl, parts=2, info=None):
     from paper_2602_17099_amd.prepare import knn_l2_exact
     subs = []
     n = Xd.shape[0] // parts
     for i in range(parts):
         Xi = Xd[i * n:(i + 1) * n]
         knn = knn_l2_exact(Xi, None, wl["K"], exclude_self=True)
-        off, nb, entry = pkg.build_graph(Xi, knn, wl["R"], alpha=wl["build_alpha"],
-                                         reverse=wl["reverse"], alpha_rev=1.2)
+        subs.append(build_graph_checked(pkg, Xi, knn, wl, info))
         del knn
-        subs.append((off, nb, entry))
     return subs
+
+
+RECALL_EFS = (10, 16, 32, 64, 128)
+
+
+def recall_sweep(pkg, off, nb, entry, Xd, Qd, gt):
+    """recall@10 (Section 2.1) of searches from the entry at each beam."""
+    return {str(ef): recall_at_10(pkg, off, nb, entry, Xd, Qd, gt, ef=ef) for ef in RECALL_EFS}
+
+
+def rebuild_baseline(pkg, Xd, Qd, gt, wl):
+    """The rebuild the merge replaces: the same builder (exact k-NN, prune,
+    reverse edges, repair) on the union of the sub-indexes' vectors."""
+    import torch
+    from paper_2602_17099_amd.prepare import knn_l2_exact
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    knn = knn_l2_exact(Xd, None, wl["K"], exclude_self=True)
+    info = {}
+    off, nb, entry = build_graph_checked(pkg, Xd, knn, wl, info)
+    del knn
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    return {"build_s": dt, "reachable_frac": info["reachable_after_repair"][0],
+            "reachable_before_repair": info["reachable_before_repair"][0],
+            "repair_links": info["repair_links"][0],
+            "recall_at_10_by_ef": recall_sweep(pkg, off, nb, entry, Xd, Qd, gt)}
 
 
 def incremental(pkg, Xd, Qd, gt, wl, parts=4):
@@ -255,7 +297,7 @@ def multiway(pkg, scale, steps, warmup):
         Xi = Xd[b:b + n]
         knn = knn_float_exact(Xi, None, 64, metric=IP, exclude_self=True)
         subs.append(pkg.build_graph(Xi, knn, 32, alpha=1.2, reverse=True, alpha_rev=1.2,
-                                    metric=IP))
+                                    metric=IP, repair=True))
         del knn
         b += n
         torch.cuda.synchronize()
@@ -353,7 +395,7 @@ def precision768(pkg, scale, steps, warmup):
         # unit rows: the inner-product order is the cosine order
         knn = knn_float_exact(Xi, None, 96, metric=1, exclude_self=True)
         subs.append(pkg.build_graph(Xi, knn, 48, alpha=1.2, reverse=True, alpha_rev=1.2,
-                                    metric=COS))
+                                    metric=COS, repair=True))
         del knn
         torch.cuda.synchronize()
         log(f"precision sub-index {i} built at {time.perf_counter() - t:.1f}s")
@@ -513,6 +555,8 @@ def main():
     ap.add_argument("--one-stream", action="store_true",
                     help="every search launch alone on one stream for the whole run (for "
                          "profiles and counters: kernel times are then exclusive)")
+    ap.add_argument("--no-rebuild", action="store_true",
+                    help="skip the rebuild baseline (the builder on the union) and its recall")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched form (operations in rounds, device pivot selection, "
                          "one persistent pivot-group search per round)")
@@ -552,7 +596,8 @@ def main():
     Qd = torch.from_numpy(Q).to(dev)
     log(f"inputs {X.shape} in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
-    subs = build_subs(pkg, Xd, wl)
+    sub_info = {}
+    subs = build_subs(pkg, Xd, wl, info=sub_info)
     torch.cuda.synchronize()
     log(f"sub-indexes built in {time.perf_counter() - t:.1f}s "
         f"(edges {[int(s[0][-1]) for s in subs]}, entries {[s[2] for s in subs]})")
@@ -608,6 +653,12 @@ def main():
     if gt is not None:
         rec32 = recall_at_10(pkg, off, nb, entry, Xd, Qd, gt)
         log(f"fp32 recall@10 (query ef 64) {rec32:.4f}")
+    graphs = {"sub_indexes": sub_info, "merged_reachable_frac": pkg.reachable(off, nb, entry) / Xd.shape[0]}
+    if gt is not None:
+        graphs["merged_recall_at_10_by_ef"] = recall_sweep(pkg, off, nb, entry, Xd, Qd, gt)
+        if not args.no_rebuild:
+            graphs["rebuild"] = rebuild_baseline(pkg, Xd, Qd, gt, wl)
+    log(f"graphs: {graphs}")
 
     bf16 = None
     if not args.no_bf16:
@@ -703,6 +754,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "bf16_form": bf16,
+        "graphs": graphs,
         "batched_form": batched,
         "cross_query_merge": cm,
         "incremental": inc,

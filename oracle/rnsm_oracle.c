@@ -1040,28 +1040,47 @@ int64_t orc_reachable(int64_t n, const int64_t* offsets, const int32_t* nbrs, in
     return tail;
 }
 
-/* Reachability repair of a built graph: every vertex the entry cannot reach
- * is linked in. The unreached vertex u of smallest id is linked from the
- * reached vertex nearest to it ((d, id) order over all vertices reached so
- * far) among those with a free slot in their row, u appended there; when
- * every reached row is full, from the nearest reached vertex, u replacing
- * its row's last entry (its farthest, rows being in (d, id) order).
- * Everything u reaches then counts as reached, and the next unreached vertex
- * follows. A replaced edge can cut off vertices reached only through it, so
- * passes repeat (at most 8) until one starts with every vertex reached.
- * Returns the number of links added. */
+/* Reachability repair of a built graph, in passes. A pass takes the
+ * vertices the entry reaches and the unreached rest. Its heads are the
+ * unreached vertices that no unreached vertex links to (when there are none,
+ * only cycles being left, the unreached vertex of smallest id alone). Each
+ * head proposes to the reached vertex nearest to it ((d, id) order) among
+ * those with a free slot in their row, or, when no reached row has one, to
+ * the nearest reached vertex. Each vertex with proposals accepts the nearest
+ * ((d, head id) order): the head is appended to its row, or replaces the
+ * row's last entry (its farthest, rows being in (d, id) order) when the row
+ * is full. Passes repeat until one starts with every vertex reached (at most
+ * 4096). Returns the number of links added. */
 static int64_t repair_reach(const space_t* S, int64_t n, int R, int32_t* rows, int32_t* deg,
                             int32_t entry) {
     char* vis = (char*)malloc((size_t)n);
+    char* inu = (char*)malloc((size_t)n);
     int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t* prop_u = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    double* prop_d = (double*)malloc(sizeof(double) * (size_t)n);
     int64_t links = 0;
-    for (int pass = 0; pass < 8; ++pass) {
+    for (int pass = 0; pass < 4096; ++pass) {
         memset(vis, 0, (size_t)n);
-        int64_t got = reach_from(n, R, rows, deg, entry, vis, queue);
-        if (got == n) break;
-        for (int64_t u = 0; u < n && got < n; ++u) {
-            if (vis[u]) continue;
-            int64_t r = -1, rf = -1;  /* nearest reached; nearest reached with a free slot */
+        if (reach_from(n, R, rows, deg, entry, vis, queue) == n) break;
+        /* unreached vertices some unreached vertex links to */
+        memset(inu, 0, (size_t)n);
+        for (int64_t v = 0; v < n; ++v) {
+            if (vis[v]) continue;
+            for (int j = 0; j < deg[v]; ++j) {
+                const int32_t w = rows[v * R + j];
+                if (w >= 0 && w < n && !vis[w]) inu[w] = 1;
+            }
+        }
+        int64_t nheads = 0, only = -1;
+        for (int64_t u = 0; u < n; ++u)
+            if (!vis[u] && !inu[u]) ++nheads;
+        if (nheads == 0)
+            for (int64_t u = 0; u < n && only < 0; ++u)
+                if (!vis[u]) only = u;
+        for (int64_t v = 0; v < n; ++v) prop_u[v] = -1;
+        for (int64_t u = 0; u < n; ++u) {
+            if (vis[u] || (only >= 0 ? u != only : inu[u])) continue;
+            int64_t r = -1, rf = -1; /* nearest reached; nearest reached with a free slot */
             double dr = 0.0, drf = 0.0;
             for (int64_t v = 0; v < n; ++v) {
                 if (!vis[v]) continue;
@@ -1075,16 +1094,27 @@ static int64_t repair_reach(const space_t* S, int64_t n, int R, int32_t* rows, i
                     drf = d;
                 }
             }
-            if (rf >= 0)
-                rows[rf * R + deg[rf]++] = (int32_t)u;
+            const int64_t t = rf >= 0 ? rf : r;
+            const double dt = rf >= 0 ? drf : dr;
+            if (prop_u[t] < 0 || key_less(dt, u, prop_d[t], prop_u[t])) {
+                prop_u[t] = u;
+                prop_d[t] = dt;
+            }
+        }
+        for (int64_t t = 0; t < n; ++t) {
+            if (prop_u[t] < 0) continue;
+            if (deg[t] < R)
+                rows[t * R + deg[t]++] = (int32_t)prop_u[t];
             else
-                rows[r * R + R - 1] = (int32_t)u;
+                rows[t * R + R - 1] = (int32_t)prop_u[t];
             ++links;
-            got += reach_from(n, R, rows, deg, u, vis, queue);
         }
     }
     free(vis);
+    free(inu);
     free(queue);
+    free(prop_u);
+    free(prop_d);
     return links;
 }
 

@@ -45,10 +45,13 @@ MUTANTS = {
                                    "deg2[w] = prune(&S, w, W2, nw, alpha, R"),
     "repair_links_from_farthest": ("if (deg[v] < R && (rf < 0 || key_less(d, v, drf, rf)))",
                                    "if (deg[v] < R && (rf < 0 || key_less(drf, rf, d, v)))"),
-    "repair_ignores_free_slots": ("            if (rf >= 0)\n", "            if (0)\n"),
-    "repair_replaces_first_entry": ("rows[r * R + R - 1] = (int32_t)u;", "rows[r * R] = (int32_t)u;"),
-    "repair_reach_not_updated": ("got += reach_from(n, R, rows, deg, u, vis, queue);", "got += 1;"),
-    "repair_single_pass": ("for (int pass = 0; pass < 8; ++pass)", "for (int pass = 0; pass < 1; ++pass)"),
+    "repair_ignores_free_slots": ("const int64_t t = rf >= 0 ? rf : r;", "const int64_t t = r;"),
+    "repair_replaces_first_entry": ("rows[t * R + R - 1] = (int32_t)prop_u[t];",
+                                    "rows[t * R] = (int32_t)prop_u[t];"),
+    "repair_accepts_farthest": ("if (prop_u[t] < 0 || key_less(dt, u, prop_d[t], prop_u[t]))",
+                                "if (prop_u[t] < 0 || key_less(prop_d[t], prop_u[t], dt, u))"),
+    "repair_every_unreached_proposes": ("(only >= 0 ? u != only : inu[u])", "(only >= 0 && u != only)"),
+    "repair_single_pass": ("for (int pass = 0; pass < 4096; ++pass)", "for (int pass = 0; pass < 1; ++pass)"),
 }
 
 
