@@ -387,13 +387,16 @@ rnsm_status rnsm_tune_search(const rnsm_graph* g, const rnsm_vectors* base, int3
  * vertex closest to the centroid (exact integer criterion when every value
  * is an integer, float64 otherwise), ties by id. With RNSM_BUILD_REPAIR,
  * every vertex the entry cannot reach is linked in (the searches of
- * Algorithm 1 start from the entry alone): the unreached vertex of smallest
- * id gets an edge from the reached vertex nearest to it ((distance, id)
- * order, float32 distances) among those with a free slot, appended there,
- * or, every reached row being full, from the nearest reached vertex,
- * replacing its row's last (farthest) entry; what it reaches then counts as
- * reached; passes repeat (at most 8) until one starts with every vertex
- * reached.
+ * Algorithm 1 start from the entry alone), in passes: the heads of the
+ * unreached part (unreached vertices no unreached vertex links to; when
+ * there are none, those no unreached vertex of smaller id links to) each
+ * propose to their
+ * nearest reached vertex ((distance, id) order, float32 distances) with a
+ * free slot in its row, else to their nearest reached vertex; every vertex
+ * accepts its nearest proposals, as many as it has free slots, appended (a
+ * full row accepts one, over its last, farthest entry); passes repeat (at
+ * most 4096) until everything is reached. The nearest free vertex is read from the head's k-NN list when
+ * the list holds one (exact for exact lists), else found by a full scan.
  * X: device [n x dim] float32. knn: device [n x K] local ids sorted by
  * (d, id), -1 padded, no self. out_offsets: device [n+1]; out_nbrs: device
  * [n x R] capacity. *out_entry written; *out_links (may be NULL): repair

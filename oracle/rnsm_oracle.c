@@ -1042,44 +1042,64 @@ int64_t orc_reachable(int64_t n, const int64_t* offsets, const int32_t* nbrs, in
 
 /* Reachability repair of a built graph, in passes. A pass takes the
  * vertices the entry reaches and the unreached rest. Its heads are the
- * unreached vertices that no unreached vertex links to (when there are none,
- * only cycles being left, the unreached vertex of smallest id alone). Each
+ * unreached vertices that no unreached vertex links to; when there are none
+ * (only cycles and what hangs off them are left), the unreached vertices
+ * that no unreached vertex of smaller id links to (following links backwards
+ * to ever smaller ids ends at one of them, so every unreached vertex hangs
+ * off a head). Each
  * head proposes to the reached vertex nearest to it ((d, id) order) among
  * those with a free slot in their row, or, when no reached row has one, to
  * the nearest reached vertex. Each vertex with proposals accepts the nearest
- * ((d, head id) order): the head is appended to its row, or replaces the
- * row's last entry (its farthest, rows being in (d, id) order) when the row
- * is full. Passes repeat until one starts with every vertex reached (at most
- * 4096). Returns the number of links added. */
+ * ((d, head id) order), as many as its row has free slots, each appended; a
+ * full row accepts one, which replaces its last entry (its farthest, rows
+ * being in (d, id) order). Passes repeat until one starts with every vertex
+ * reached (at most 4096). Returns the number of links added. */
+typedef struct {
+    int64_t t, u;
+    double d;
+} prop_t;
+
+static int prop_cmp(const void* a, const void* b) {
+    const prop_t* x = (const prop_t*)a;
+    const prop_t* y = (const prop_t*)b;
+    if (x->t != y->t) return x->t < y->t ? -1 : 1;
+    if (key_less(x->d, x->u, y->d, y->u)) return -1;
+    if (key_less(y->d, y->u, x->d, x->u)) return 1;
+    return 0;
+}
+
 static int64_t repair_reach(const space_t* S, int64_t n, int R, int32_t* rows, int32_t* deg,
                             int32_t entry) {
     char* vis = (char*)malloc((size_t)n);
     char* inu = (char*)malloc((size_t)n);
+    char* ins = (char*)malloc((size_t)n);
     int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    int64_t* prop_u = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
-    double* prop_d = (double*)malloc(sizeof(double) * (size_t)n);
+    prop_t* P = (prop_t*)malloc(sizeof(prop_t) * (size_t)n);
     int64_t links = 0;
     for (int pass = 0; pass < 4096; ++pass) {
         memset(vis, 0, (size_t)n);
         if (reach_from(n, R, rows, deg, entry, vis, queue) == n) break;
-        /* unreached vertices some unreached vertex links to */
+        /* unreached vertices some unreached vertex links to (inu), some
+         * unreached vertex of smaller id (ins) */
         memset(inu, 0, (size_t)n);
+        memset(ins, 0, (size_t)n);
         for (int64_t v = 0; v < n; ++v) {
             if (vis[v]) continue;
             for (int j = 0; j < deg[v]; ++j) {
                 const int32_t w = rows[v * R + j];
-                if (w >= 0 && w < n && !vis[w]) inu[w] = 1;
+                if (w >= 0 && w < n && !vis[w]) {
+                    inu[w] = 1;
+                    if (v < w) ins[w] = 1;
+                }
             }
         }
-        int64_t nheads = 0, only = -1;
+        int64_t nheads = 0;
         for (int64_t u = 0; u < n; ++u)
             if (!vis[u] && !inu[u]) ++nheads;
-        if (nheads == 0)
-            for (int64_t u = 0; u < n && only < 0; ++u)
-                if (!vis[u]) only = u;
-        for (int64_t v = 0; v < n; ++v) prop_u[v] = -1;
+        const char* excl = nheads > 0 ? inu : ins;
+        int64_t np = 0;
         for (int64_t u = 0; u < n; ++u) {
-            if (vis[u] || (only >= 0 ? u != only : inu[u])) continue;
+            if (vis[u] || excl[u]) continue;
             int64_t r = -1, rf = -1; /* nearest reached; nearest reached with a free slot */
             double dr = 0.0, drf = 0.0;
             for (int64_t v = 0; v < n; ++v) {
@@ -1094,27 +1114,32 @@ static int64_t repair_reach(const space_t* S, int64_t n, int R, int32_t* rows, i
                     drf = d;
                 }
             }
-            const int64_t t = rf >= 0 ? rf : r;
-            const double dt = rf >= 0 ? drf : dr;
-            if (prop_u[t] < 0 || key_less(dt, u, prop_d[t], prop_u[t])) {
-                prop_u[t] = u;
-                prop_d[t] = dt;
-            }
+            P[np].t = rf >= 0 ? rf : r;
+            P[np].d = rf >= 0 ? drf : dr;
+            P[np].u = u;
+            ++np;
         }
-        for (int64_t t = 0; t < n; ++t) {
-            if (prop_u[t] < 0) continue;
-            if (deg[t] < R)
-                rows[t * R + deg[t]++] = (int32_t)prop_u[t];
-            else
-                rows[t * R + R - 1] = (int32_t)prop_u[t];
-            ++links;
+        qsort(P, (size_t)np, sizeof(prop_t), prop_cmp);
+        for (int64_t i = 0; i < np;) {
+            const int64_t t = P[i].t;
+            int64_t e = i;
+            while (e < np && P[e].t == t) ++e;
+            const int64_t take = deg[t] < R ? R - deg[t] : 1;
+            for (int64_t k = i; k < e && k - i < take; ++k) {
+                if (deg[t] < R)
+                    rows[t * R + deg[t]++] = (int32_t)P[k].u;
+                else
+                    rows[t * R + R - 1] = (int32_t)P[k].u;
+                ++links;
+            }
+            i = e;
         }
     }
     free(vis);
     free(inu);
+    free(ins);
     free(queue);
-    free(prop_u);
-    free(prop_d);
+    free(P);
     return links;
 }
 

@@ -2515,34 +2515,75 @@ static rnsm_status rnsm_build_graph_impl(int64_t n, const float* X, int32_t dim,
     const int32_t entry = (int32_t)hb[3 * best + 2];
     *out_entry = entry;
     if (options & RNSM_BUILD_REPAIR) {
-        // reachability repair on the -1 padded rows, host-paced: one link
-        // per unreached piece, each followed by the search of what it reaches
+        // reachability repair in passes (host-paced: a search from the entry,
+        // the heads and their proposals, the acceptances)
+        if ((size_t)dim * 16 * sizeof(float) > 64 * 1024)
+            return fail(RNSM_EUNSUPPORTED, "rnsm_build_graph: the repair takes dim <= 1024");
         unsigned *vis, *ctl, *h_ctl;
-        int32_t* order;
-        unsigned long long* tmp;
+        int32_t *order, *fb, *cand, *pt, *cnt, *cur;
+        unsigned char* inu;
+        unsigned long long *pk, *seg, *rctl, *h_rctl;
+        int64_t *off, *rtmp;
         WS(vis, "b_vis", sizeof(unsigned) * ((n + 31) / 32));
         WS(order, "b_order", sizeof(int32_t) * n);
         WS(ctl, "b_ctl", sizeof(unsigned) * 4);
-        WS(tmp, "b_repair", sizeof(unsigned long long) * 3);
+        WS(inu, "b_inu", ((n + 3) & ~3ll) + 4);  // whole words: k_rep_mark ORs 32-bit words
+        WS(fb, "b_fb", sizeof(int32_t) * n);
+        WS(cand, "b_cand", sizeof(int32_t) * n);
+        WS(pt, "b_pt", sizeof(int32_t) * n);
+        WS(cnt, "b_pcnt", sizeof(int32_t) * n);
+        WS(cur, "b_pcur", sizeof(int32_t) * n);
+        WS(pk, "b_pk", sizeof(unsigned long long) * n);
+        WS(seg, "b_seg", sizeof(unsigned long long) * n);
+        WS(off, "b_poff", sizeof(int64_t) * (n + 1));
+        WS(rtmp, "b_pscan", sizeof(int64_t) * scan_tmp_elems(n));
+        WS(rctl, "b_rctl", sizeof(unsigned long long) * 5);
         HS(h_ctl, "h_b_ctl", sizeof(unsigned) * 4);
+        HS(h_rctl, "h_b_rctl", sizeof(unsigned long long) * 5);
         HIPCHK(launch_pad_tail(rows, deg, n, R, st));
-        int64_t links = 0;
-        for (int pass = 0; pass < 8; ++pass) {
+        HIPCHK(launch_zero(rctl + 3, sizeof(unsigned long long), st));  // links
+        for (int pass = 0; pass < 4096; ++pass) {
             HIPCHK(launch_bfs_init(n, entry, vis, order, ctl, st));
             HIPCHK(launch_bfs_grow(rows, R, n, order, vis, ctl, h_ctl, st));
-            int64_t got = h_ctl[0];
-            if (got >= n) break;
-            while (got < n) {
-                HIPCHK(launch_repair_link(X, dim, metric, norms, n, rows, deg, R, vis, order, ctl,
-                                          tmp, st));
-                HIPCHK(launch_bfs_grow(rows, R, n, order, vis, ctl, h_ctl, st));
-                if ((int64_t)h_ctl[0] <= got)
-                    return fail(RNSM_EINTERNAL, "rnsm_build_graph: a repair link reached nothing");
-                got = h_ctl[0];
-                ++links;
+            if ((int64_t)h_ctl[0] >= n) break;
+            HIPCHK(launch_repair_heads(n, rows, deg, R, vis, inu, cnt, cur, rctl, st));
+            HIPCHK(hipMemcpyAsync(h_rctl, rctl, sizeof(unsigned long long) * 2,
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            // heads: no unreached vertex links to them; when there are none,
+            // no unreached vertex of smaller id
+            const int64_t only = h_rctl[0] == 0 ? 1 : 0;
+            if (h_rctl[1] >= (unsigned long long)n)
+                return fail(RNSM_EINTERNAL, "rnsm_build_graph: repair found no unreached vertex");
+            HIPCHK(launch_repair_propose(n, X, dim, metric, norms, knn, K, vis, inu, deg, R, only,
+                                         pt, pk, fb, rctl, st));
+            // heads with no reached free vertex in their list: a scan over
+            // the reached vertices with a free slot (all reached ones when
+            // no reached row has one)
+            HIPCHK(launch_zero(rctl + 4, sizeof(unsigned long long), st));
+            HIPCHK(launch_repair_cands(n, vis, deg, R, 0, cand, rctl + 4, st));
+            HIPCHK(hipMemcpyAsync(h_rctl + 2, rctl + 2, sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(h_rctl + 4, rctl + 4, sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (h_rctl[2] > 0) {
+                if (h_rctl[4] == 0) {
+                    HIPCHK(launch_repair_cands(n, vis, deg, R, 1, cand, rctl + 4, st));
+                    HIPCHK(hipMemcpyAsync(h_rctl + 4, rctl + 4, sizeof(unsigned long long),
+                                          hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                }
+                HIPCHK(launch_repair_scan(n, X, dim, metric, norms, fb, (int64_t)h_rctl[2], cand,
+                                          (int64_t)h_rctl[4], pt, pk, st));
             }
+            HIPCHK(launch_repair_accept(n, vis, inu, only, pt, pk, cnt, cur, off, rtmp, seg, rows,
+                                        deg, R, rctl + 3, st));
         }
-        if (out_links) *out_links = links;
+        HIPCHK(hipMemcpyAsync(h_rctl + 3, rctl + 3, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (out_links) *out_links = (int64_t)h_rctl[3];
     }
     int64_t* stmp3;
     WS(stmp3, "b_stmp3", sizeof(int64_t) * scan_tmp_elems(n));

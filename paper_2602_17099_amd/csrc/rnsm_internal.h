@@ -249,14 +249,39 @@ hipError_t launch_bfs_init(int64_t n, int32_t root, unsigned* vis, int32_t* orde
                            hipStream_t st);
 hipError_t launch_bfs_grow(const int32_t* padj, int rp, int64_t n, int32_t* order, unsigned* vis,
                            unsigned* ctl, unsigned* h_ctl, hipStream_t st);
-// one link of the reachability repair on rows (-1 padded, R per row): the
-// smallest unreached id u from the nearest reached vertex (distance key, id)
-// with a free slot, appended there, or, every reached row being full, over
-// the last entry of the nearest reached row; u becomes the next frontier
-// (launch_bfs_grow then adds what it reaches). tmp: 3 words
-hipError_t launch_repair_link(const float* X, int dim, int metric, const float* norms, int64_t n,
-                              int32_t* rows, int32_t* deg, int R, unsigned* vis, int32_t* order,
-                              unsigned* ctl, unsigned long long* tmp, hipStream_t st);
+// one pass of the builder's reachability repair over rows of R ids (-1
+// padded) and the reached bits `vis` of a search from the entry. heads:
+// clears inu (n bytes), cnt and cur (n words each), marks unreached vertices
+// an unreached vertex links to, and counts the heads (ctl[0]) and the
+// smallest unreached id (ctl[1]); propose: each head (only = 0: no
+// unreached vertex links to it; 1: none of smaller id does) proposes
+// (target pt[u], key pk[u]) from its k-NN list (knn [n x K],
+// exact, sorted by (d, id)) or is listed in fb (ctl[2] of them) for scan;
+// cands + scan: the global scan of the listed heads over the reached
+// vertices with a free slot (every reached vertex when none has one), 16
+// heads a block (dim <= 1024); accept: proposals grouped by target (cnt,
+// off: n + 1, seg: n keys), each target taking its nearest ones (as many as
+// its free slots, appended; one over a full row's last entry), links
+// counted into *links
+hipError_t launch_repair_heads(int64_t n, const int32_t* rows, const int32_t* deg, int R,
+                               const unsigned* vis, unsigned char* inu, int32_t* cnt, int32_t* cur,
+                               unsigned long long* ctl, hipStream_t st);
+hipError_t launch_repair_propose(int64_t n, const float* X, int dim, int metric, const float* norms,
+                                 const int32_t* knn, int K, const unsigned* vis,
+                                 const unsigned char* inu, const int32_t* deg, int R, int64_t only,
+                                 int32_t* pt, unsigned long long* pk, int32_t* fb,
+                                 unsigned long long* ctl, hipStream_t st);
+hipError_t launch_repair_cands(int64_t n, const unsigned* vis, const int32_t* deg, int R,
+                               int all_reached, int32_t* cand, unsigned long long* cnt,
+                               hipStream_t st);
+hipError_t launch_repair_scan(int64_t n, const float* X, int dim, int metric, const float* norms,
+                              const int32_t* fb, int64_t nfb, const int32_t* cand, int64_t ncand,
+                              int32_t* pt, unsigned long long* pk, hipStream_t st);
+hipError_t launch_repair_accept(int64_t n, const unsigned* vis, const unsigned char* inu,
+                                int64_t only, const int32_t* pt, const unsigned long long* pk,
+                                int32_t* cnt, int32_t* cur, int64_t* off, int64_t* scan_tmp,
+                                unsigned long long* seg, int32_t* rows, int32_t* deg, int R,
+                                unsigned long long* links, hipStream_t st);
 hipError_t launch_pad_tail(int32_t* rows, const int32_t* deg, int64_t n, int R, hipStream_t st);
 // largest row length (atomicMax into *maxdeg, zeroed by the caller) and a
 // flag for malformed offsets

@@ -2004,76 +2004,235 @@ __global__ __launch_bounds__(BFS_T) void k_bfs_rest(int64_t n, const unsigned* v
 
 // ------------------------------------------------ reachability and its repair
 
-// the vertex u = *ures joins the reached set as the next frontier by itself
-__global__ void k_bfs_push(const unsigned long long* ures, unsigned* vis, int32_t* order,
-                           unsigned* ctl) {
-    if (*ures >= 0x7fffffffull) return;  // nothing unreached
-    const int32_t u = (int32_t)*ures;
-    const unsigned t = ctl[0];
-    vis[u >> 5] |= 1u << (u & 31);
-    order[t] = u;
-    ctl[0] = t + 1;
-    ctl[1] = t;
-    ctl[2] = t + 1;
-    ctl[3] = 0;
+// One pass of the builder's reachability repair, over rows of R ids (-1
+// padded, deg[v] used) and the reached bits of a search from the entry:
+// heads are the unreached vertices no unreached vertex links to (or, when
+// there are none, those no unreached vertex of smaller id links to); each
+// proposes to its
+// nearest reached vertex with a free slot, else to its nearest reached
+// vertex, and every vertex accepts its nearest proposals. Keys are (float32
+// distance key, id); distances summed in index order (exact on integers).
+__device__ __forceinline__ bool reached_bit(const unsigned* vis, int64_t v) {
+    return (vis[v >> 5] >> (v & 31)) & 1u;
 }
 
-// smallest id whose reached bit is clear (out starts at ~0)
-__global__ void k_first_unreached(const unsigned* vis, int64_t n, unsigned long long* out) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= (n + 31) >> 5) return;
-    unsigned miss = ~vis[w];
-    const int64_t valid = n - w * 32;
-    if (valid < 32) miss &= (1u << valid) - 1u;
-    if (miss) atomicMin(out, (unsigned long long)(w * 32 + __ffs(miss) - 1));
-}
-
-// the reached vertex nearest to u = *ures, as the least (distance key, id),
-// into best[0]; the nearest with a free slot in its row into best[1]: one
-// wavefront per vertex, lanes over the dimensions (float32, each lane's sum
-// then a butterfly: exact on integer rows)
-__global__ void k_nearest_reached(const float* X, int dim, int metric, const float* norms,
-                                  int64_t n, const unsigned* vis, const int32_t* deg, int R,
-                                  const unsigned long long* ures, unsigned long long* best) {
-    const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (v >= n || *ures >= (unsigned long long)n || !((vis[v >> 5] >> (v & 31)) & 1u)) return;
-    const int lane = lane_id();
-    const int64_t u = (int64_t)*ures;
-    const float* a = X + u * dim;
-    const float* b = X + v * dim;
+__device__ __forceinline__ float row_dist(const float* X, int dim, int metric, const float* norms,
+                                          int64_t a, int64_t b) {
+    const float* x = X + a * dim;
+    const float* y = X + b * dim;
     float acc = 0.0f;
-    for (int j = lane; j < dim; j += WAVE) {
-        if (metric == 0) {
-            const float t = a[j] - b[j];
+    if (metric == 0) {
+        for (int j = 0; j < dim; ++j) {
+            const float t = x[j] - y[j];
             acc = fmaf(t, t, acc);
-        } else {
-            acc = fmaf(a[j], b[j], acc);
+        }
+        return acc;
+    }
+    for (int j = 0; j < dim; ++j) acc = fmaf(x[j], y[j], acc);
+    return metric == 1 ? 1.0f - acc : 1.0f - acc / (norms[a] * norms[b]);
+}
+
+// ctl: [0] heads, [1] smallest unreached id, [2] heads left to the global scan
+// inu: bit 0 when an unreached vertex links to the vertex, bit 1 when one of
+// smaller id does
+__global__ void k_rep_clear(int64_t n, unsigned char* inu, int32_t* cnt, int32_t* cur,
+                            unsigned long long* ctl) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        inu[t] = 0;
+        cnt[t] = 0;
+        cur[t] = 0;
+    }
+    if (t == 0) {
+        ctl[0] = 0;
+        ctl[1] = ~0ull;
+        ctl[2] = 0;
+    }
+}
+
+__global__ void k_rep_mark(const int32_t* rows, const int32_t* deg, int R, int64_t n,
+                           const unsigned* vis, unsigned char* inu) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n || reached_bit(vis, v)) return;
+    for (int j = 0; j < deg[v]; ++j) {
+        const int32_t w = rows[v * R + j];
+        if (w >= 0 && w < n && !reached_bit(vis, w)) {
+            unsigned* word = reinterpret_cast<unsigned*>(inu + (w & ~3ll));
+            const unsigned bits = (v < w ? 3u : 1u) << (8 * (w & 3));
+            atomicOr(word, bits);
+        }
+    }
+}
+
+__global__ void k_rep_heads(int64_t n, const unsigned* vis, const unsigned char* inu,
+                            unsigned long long* ctl) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool un = u < n && !reached_bit(vis, u);
+    const bool head = un && !(inu[u] & 1u);
+    const u64 m = __ballot(head);
+    if (m && lane_id() == __ffsll((long long)m) - 1) atomicAdd(&ctl[0], (unsigned long long)__popcll(m));
+    if (un) atomicMin(&ctl[1], (unsigned long long)u);
+}
+
+// mode 0: no unreached vertex links to u; mode 1: none of smaller id does
+__device__ __forceinline__ bool rep_is_head(int64_t u, const unsigned* vis,
+                                            const unsigned char* inu, int64_t mode) {
+    if (reached_bit(vis, u)) return false;
+    return !(inu[u] & (mode ? 2u : 1u));
+}
+
+// a head's proposal from its exact k-NN list (sorted by (d, id)): the first
+// reached entry with a free slot is the nearest such vertex of all, since
+// every vertex nearer than the list's last lies in the list; heads without
+// one go to the global scan. Proposal of head u: target pt[u], key pk[u] =
+// (distance key, u)
+__global__ void k_rep_propose_knn(int64_t n, const float* X, int dim, int metric,
+                                  const float* norms, const int32_t* knn, int K,
+                                  const unsigned* vis, const unsigned char* inu,
+                                  const int32_t* deg, int R, int64_t only, int32_t* pt,
+                                  unsigned long long* pk, int32_t* fb, unsigned long long* ctl) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n || !rep_is_head(u, vis, inu, only)) return;
+    int64_t rf = -1;
+    for (int j = 0; j < K && rf < 0; ++j) {
+        const int32_t w = knn[u * K + j];
+        if (w >= 0 && w < n && reached_bit(vis, w) && deg[w] < R) rf = w;
+    }
+    if (rf < 0) {
+        fb[atomicAdd(&ctl[2], 1ull)] = (int32_t)u;
+        return;
+    }
+    const float d = row_dist(X, dim, metric, norms, u, rf);
+    pt[u] = (int32_t)rf;
+    pk[u] = ((unsigned long long)fkey(d) << 32) | (unsigned long long)u;
+}
+
+// the candidates of the global scan: reached vertices with a free slot
+// (all_reached: every reached vertex), appended in any order (*cnt of them)
+__global__ void k_rep_cands(int64_t n, const unsigned* vis, const int32_t* deg, int R,
+                            int all_reached, int32_t* cand, unsigned long long* cnt) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = v < n && reached_bit(vis, v) && (all_reached || deg[v] < R);
+    const u64 m = __ballot(in);
+    if (m == 0ull) return;
+    unsigned long long base = 0;
+    const int lead = __ffsll((long long)m) - 1;
+    if (lane_id() == lead) base = atomicAdd(cnt, (unsigned long long)__popcll(m));
+    base = __shfl(base, lead);
+    if (in) cand[base + __popcll(m & lanemask_lt(lane_id()))] = (int32_t)v;
+}
+
+// the global scan for REP_TILE heads per block (their rows staged in LDS):
+// each thread takes candidate rows in turn and keeps, per head, the least
+// (distance key, id); the block's least per head becomes its proposal
+constexpr int REP_TILE = 16;
+__global__ __launch_bounds__(256) void k_rep_propose_scan(int64_t n, const float* X, int dim,
+                                                          int metric, const float* norms,
+                                                          const int32_t* fb, int64_t nfb,
+                                                          const int32_t* cand, int64_t ncand,
+                                                          int32_t* pt, unsigned long long* pk) {
+    extern __shared__ float hrow[];  // REP_TILE x dim
+    __shared__ unsigned long long sbest[REP_TILE];
+    const int64_t h0 = (int64_t)blockIdx.x * REP_TILE;
+    const int nh = (int)min<int64_t>(REP_TILE, nfb - h0);
+    for (int t = threadIdx.x; t < REP_TILE * dim; t += blockDim.x) {
+        const int h = t / dim, j = t - h * dim;
+        hrow[t] = h < nh ? X[(int64_t)fb[h0 + h] * dim + j] : 0.0f;
+    }
+    if (threadIdx.x < REP_TILE) sbest[threadIdx.x] = ~0ull;
+    __syncthreads();
+    unsigned long long best[REP_TILE];
+#pragma unroll
+    for (int h = 0; h < REP_TILE; ++h) best[h] = ~0ull;
+    for (int64_t c = threadIdx.x; c < ncand; c += blockDim.x) {
+        const int64_t v = cand[c];
+        const float* y = X + v * dim;
+        float acc[REP_TILE];
+#pragma unroll
+        for (int h = 0; h < REP_TILE; ++h) acc[h] = 0.0f;
+        for (int j = 0; j < dim; ++j) {
+            const float yj = y[j];
+#pragma unroll
+            for (int h = 0; h < REP_TILE; ++h) {
+                if (metric == 0) {
+                    const float t = hrow[h * dim + j] - yj;
+                    acc[h] = fmaf(t, t, acc[h]);
+                } else {
+                    acc[h] = fmaf(hrow[h * dim + j], yj, acc[h]);
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < REP_TILE; ++h) {
+            if (h >= nh) break;
+            float d = acc[h];
+            if (metric == 1) d = 1.0f - acc[h];
+            if (metric == 2) d = 1.0f - acc[h] / (norms[fb[h0 + h]] * norms[v]);
+            const unsigned long long key = ((unsigned long long)fkey(d) << 32) | (unsigned long long)v;
+            best[h] = key < best[h] ? key : best[h];
         }
     }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane != 0) return;
-    float d = acc;
-    if (metric == 1) d = 1.0f - acc;
-    if (metric == 2) d = 1.0f - acc / (norms[u] * norms[v]);
-    const unsigned long long key = ((unsigned long long)fkey(d) << 32) | (unsigned long long)v;
-    atomicMin(&best[0], key);
-    if (deg[v] < R) atomicMin(&best[1], key);
+    for (int h = 0; h < REP_TILE; ++h)
+        if (h < nh && best[h] != ~0ull) atomicMin(&sbest[h], best[h]);
+    __syncthreads();
+    if (threadIdx.x >= nh) return;
+    const unsigned long long t = sbest[threadIdx.x];
+    if (t == ~0ull) return;
+    const int64_t u = fb[h0 + threadIdx.x];
+    pt[u] = (int32_t)(t & 0xffffffffull);
+    pk[u] = (t & 0xffffffff00000000ull) | (unsigned long long)u;
 }
 
-// the link to u: appended to the nearest reached row with a free slot, or,
-// when every reached row is full, over the last entry of the nearest one
-__global__ void k_repair_link(int32_t* rows, int32_t* deg, int R, const unsigned long long* ures,
-                              const unsigned long long* best) {
-    if (*ures >= 0x7fffffffull || best[0] == ~0ull) return;
-    const int32_t u = (int32_t)*ures;
-    if (best[1] != ~0ull) {
-        const int64_t r = (int64_t)(best[1] & 0xffffffffull);
-        rows[r * R + deg[r]++] = u;
-    } else {
-        const int64_t r = (int64_t)(best[0] & 0xffffffffull);
-        rows[r * R + R - 1] = u;
+// proposals grouped by target: counts, then (after a scan into off) the keys
+// of each target's proposals in its segment of seg, in any order
+__global__ void k_rep_count(int64_t n, const unsigned* vis, const unsigned char* inu, int64_t only,
+                            const int32_t* pt, int32_t* cnt) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n && rep_is_head(u, vis, inu, only)) atomicAdd(&cnt[pt[u]], 1);
+}
+
+__global__ void k_rep_scatter(int64_t n, const unsigned* vis, const unsigned char* inu,
+                              int64_t only, const int32_t* pt, const unsigned long long* pk,
+                              const int64_t* off, int32_t* cur, unsigned long long* seg) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n || !rep_is_head(u, vis, inu, only)) return;
+    const int32_t t = pt[u];
+    seg[off[t] + atomicAdd(&cur[t], 1)] = pk[u];
+}
+
+// each target takes its nearest proposals (least keys), as many as its row
+// has free slots, appended; a full row takes one, over its last entry
+__global__ void k_rep_accept(int64_t n, const int32_t* cnt, const int64_t* off,
+                             const unsigned long long* seg, int32_t* rows, int32_t* deg, int R,
+                             unsigned long long* links) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int taken = 0;
+    if (t < n && cnt[t] > 0) {
+        const unsigned long long* sg = seg + off[t];
+        const int c = cnt[t];
+        const int take = deg[t] < R ? R - deg[t] : 1;
+        unsigned long long prev = 0;
+        for (int k = 0; k < take && k < c; ++k) {
+            // the least key above the previous one (keys are distinct: they hold the head id)
+            unsigned long long m = ~0ull;
+            for (int i = 0; i < c; ++i) {
+                const unsigned long long x = sg[i];
+                if ((k == 0 || x > prev) && x < m) m = x;
+            }
+            prev = m;
+            const int32_t u = (int32_t)(m & 0xffffffffull);
+            if (deg[t] < R)
+                rows[t * R + deg[t]++] = u;
+            else
+                rows[t * R + R - 1] = u;
+            ++taken;
+        }
     }
+    int64_t tk = taken;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) tk += __shfl_xor(tk, o);
+    if (lane_id() == 0 && tk) atomicAdd(links, (unsigned long long)tk);
 }
 
 // -1 after each row's used entries (row v: rows + v R, deg[v] used)
@@ -2607,19 +2766,60 @@ hipError_t launch_csr_shape(const int64_t* offs, int64_t n, unsigned* maxdeg, in
     return hipGetLastError();
 }
 
-hipError_t launch_repair_link(const float* X, int dim, int metric, const float* norms, int64_t n,
-                              int32_t* rows, int32_t* deg, int R, unsigned* vis, int32_t* order,
-                              unsigned* ctl, unsigned long long* tmp, hipStream_t st) {
-    // tmp[0]: the smallest unreached id, tmp[1], tmp[2]: the nearest reached
-    // key, the nearest with a free slot
-    hipError_t e = hipMemsetAsync(tmp, 0xff, 3 * sizeof(unsigned long long), st);
+hipError_t launch_repair_heads(int64_t n, const int32_t* rows, const int32_t* deg, int R,
+                               const unsigned* vis, unsigned char* inu, int32_t* cnt, int32_t* cur,
+                               unsigned long long* ctl, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rep_clear, dim3(nblk(n, 256)), dim3(256), 0, st, n, inu, cnt, cur, ctl);
+    hipLaunchKernelGGL(k_rep_mark, dim3(nblk(n, 256)), dim3(256), 0, st, rows, deg, R, n, vis, inu);
+    hipLaunchKernelGGL(k_rep_heads, dim3(nblk(n, 256)), dim3(256), 0, st, n, vis, inu, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_repair_propose(int64_t n, const float* X, int dim, int metric, const float* norms,
+                                 const int32_t* knn, int K, const unsigned* vis,
+                                 const unsigned char* inu, const int32_t* deg, int R, int64_t only,
+                                 int32_t* pt, unsigned long long* pk, int32_t* fb,
+                                 unsigned long long* ctl, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rep_propose_knn, dim3(nblk(n, 256)), dim3(256), 0, st, n, X, dim, metric,
+                       norms, knn, K, vis, inu, deg, R, only, pt, pk, fb, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_repair_cands(int64_t n, const unsigned* vis, const int32_t* deg, int R,
+                               int all_reached, int32_t* cand, unsigned long long* cnt,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rep_cands, dim3(nblk(n, 256)), dim3(256), 0, st, n, vis, deg, R,
+                       all_reached, cand, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_repair_scan(int64_t n, const float* X, int dim, int metric, const float* norms,
+                              const int32_t* fb, int64_t nfb, const int32_t* cand, int64_t ncand,
+                              int32_t* pt, unsigned long long* pk, hipStream_t st) {
+    if (n <= 0 || nfb <= 0 || ncand <= 0) return hipSuccess;
+    const size_t lds = sizeof(float) * REP_TILE * (size_t)dim;
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rep_propose_scan, dim3(nblk(nfb, REP_TILE)), dim3(256), lds, st, n, X, dim,
+                       metric, norms, fb, nfb, cand, ncand, pt, pk);
+    return hipGetLastError();
+}
+
+hipError_t launch_repair_accept(int64_t n, const unsigned* vis, const unsigned char* inu,
+                                int64_t only, const int32_t* pt, const unsigned long long* pk,
+                                int32_t* cnt, int32_t* cur, int64_t* off, int64_t* scan_tmp,
+                                unsigned long long* seg, int32_t* rows, int32_t* deg, int R,
+                                unsigned long long* links, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rep_count, dim3(nblk(n, 256)), dim3(256), 0, st, n, vis, inu, only, pt, cnt);
+    hipError_t e = launch_scan(cnt, n, off, scan_tmp, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_first_unreached, dim3(nblk((n + 31) >> 5, 256)), dim3(256), 0, st, vis, n,
-                       tmp);
-    hipLaunchKernelGGL(k_nearest_reached, dim3(nblk(n * WAVE, 256)), dim3(256), 0, st, X, dim,
-                       metric, norms, n, vis, deg, R, tmp, tmp + 1);
-    hipLaunchKernelGGL(k_repair_link, dim3(1), dim3(1), 0, st, rows, deg, R, tmp, tmp + 1);
-    hipLaunchKernelGGL(k_bfs_push, dim3(1), dim3(1), 0, st, tmp, vis, order, ctl);
+    hipLaunchKernelGGL(k_rep_scatter, dim3(nblk(n, 256)), dim3(256), 0, st, n, vis, inu, only, pt,
+                       pk, off, cur, seg);
+    hipLaunchKernelGGL(k_rep_accept, dim3(nblk(n, 256)), dim3(256), 0, st, n, cnt, off, seg, rows,
+                       deg, R, links);
     return hipGetLastError();
 }
 

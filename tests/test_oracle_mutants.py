@@ -45,12 +45,15 @@ MUTANTS = {
                                    "deg2[w] = prune(&S, w, W2, nw, alpha, R"),
     "repair_links_from_farthest": ("if (deg[v] < R && (rf < 0 || key_less(d, v, drf, rf)))",
                                    "if (deg[v] < R && (rf < 0 || key_less(drf, rf, d, v)))"),
-    "repair_ignores_free_slots": ("const int64_t t = rf >= 0 ? rf : r;", "const int64_t t = r;"),
-    "repair_replaces_first_entry": ("rows[t * R + R - 1] = (int32_t)prop_u[t];",
-                                    "rows[t * R] = (int32_t)prop_u[t];"),
-    "repair_accepts_farthest": ("if (prop_u[t] < 0 || key_less(dt, u, prop_d[t], prop_u[t]))",
-                                "if (prop_u[t] < 0 || key_less(prop_d[t], prop_u[t], dt, u))"),
-    "repair_every_unreached_proposes": ("(only >= 0 ? u != only : inu[u])", "(only >= 0 && u != only)"),
+    "repair_ignores_free_slots": ("P[np].t = rf >= 0 ? rf : r;", "P[np].t = r;"),
+    "repair_replaces_first_entry": ("rows[t * R + R - 1] = (int32_t)P[k].u;",
+                                    "rows[t * R] = (int32_t)P[k].u;"),
+    "repair_accepts_farthest": ("    if (key_less(x->d, x->u, y->d, y->u)) return -1;",
+                                "    if (key_less(x->d, x->u, y->d, y->u)) return 1;"),
+    "repair_accepts_one_per_pass": ("const int64_t take = deg[t] < R ? R - deg[t] : 1;",
+                                    "const int64_t take = 1;"),
+    "repair_every_unreached_proposes": ("if (vis[u] || excl[u]) continue;", "if (vis[u]) continue;"),
+    "repair_cycles_by_larger_id": ("if (v < w) ins[w] = 1;", "if (v > w) ins[w] = 1;"),
     "repair_single_pass": ("for (int pass = 0; pass < 4096; ++pass)", "for (int pass = 0; pass < 1; ++pass)"),
 }
 
