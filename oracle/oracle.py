@@ -51,7 +51,8 @@ class Params(C.Structure):
     _fields_ = [("R", C.c_int), ("ef_naive", C.c_int), ("ef_slide", C.c_int),
                 ("alpha", C.c_float), ("metric", C.c_int), ("k", C.c_int), ("kplus", C.c_int),
                 ("mos_degree", C.c_int), ("mos_diameter", C.c_int),
-                ("use_centroids", C.c_int), ("all_pivots", C.c_int)]
+                ("use_centroids", C.c_int), ("all_pivots", C.c_int),
+                ("prune_rule", C.c_int), ("prune_param", C.c_float)]
 
 
 class Trace(C.Structure):
@@ -94,6 +95,9 @@ def _setup(L):
     L.orc_plan_cost.argtypes = [C.c_int, P, P, C.c_int, C.c_int, P, C.c_int, P, P]
     L.orc_merge.restype = C.c_int
     L.orc_merge.argtypes = [C.c_int, P, P, P, P, P, C.c_int, P, P, P, P, P, P, P, P]
+    L.orc_prune_rule.restype = C.c_int
+    L.orc_prune_rule.argtypes = [C.c_int64, P, C.c_int, P, C.c_int, C.c_int, P, C.c_int, C.c_float,
+                                 C.c_float, C.c_int, P, P]
     L.orc_knn.restype = C.c_int
     L.orc_knn.argtypes = [C.c_int64, P, C.c_int, C.c_int, C.c_int, P]
     L.orc_knn_queries.restype = C.c_int
@@ -170,6 +174,18 @@ def prune(p, W, X, alpha, R, metric=L2SQ):
     ds = np.empty(max(1, len(W)), dtype=np.float64)
     c = lib().orc_prune(p, _p(W), len(W), _p(X), X.shape[1], metric, _p(nrm), float(alpha), R,
                         _p(ids), _p(ds))
+    return ids[:c].copy(), ds[:c].copy()
+
+
+def prune_rule(p, W, X, rule, R, alpha=1.0, param=0.0, metric=L2SQ):
+    """Prune(p, W) under a proximity-graph rule: PRUNE_ALPHA (alpha), PRUNE_ANGLE
+    (SSG, param = theta in degrees), PRUNE_TAU (tau-MNG, param = tau)."""
+    W, X = _i32(W), _f32(X)
+    nrm = norms(X) if metric == COSINE else None
+    ids = np.empty(max(1, len(W)), dtype=np.int32)
+    ds = np.empty(max(1, len(W)), dtype=np.float64)
+    c = lib().orc_prune_rule(p, _p(W), len(W), _p(X), X.shape[1], metric, _p(nrm), int(rule),
+                             float(alpha), float(param), R, _p(ids), _p(ds))
     return ids[:c].copy(), ds[:c].copy()
 
 
@@ -260,8 +276,12 @@ def plan_cost(sizes, cost, R, delta=2):
     return [tuple(int(v) for v in o) for o in ops[: n[0]]], int(nf[0])
 
 
+PRUNE_ALPHA, PRUNE_ANGLE, PRUNE_TAU = 0, 1, 2
+
+
 def merge(subs, X, R, L, alpha, metric=L2SQ, k=5, kplus=16, ef_slide=None, mos_degree=0,
-          mos_diameter=2, use_centroids=False, all_pivots=False, trace=False):
+          mos_diameter=2, use_centroids=False, all_pivots=False, trace=False,
+          prune_rule=PRUNE_ALPHA, prune_param=0.0):
     """Whole merge. subs: list of (offsets, nbrs, entry) with local ids, in
     global-id order over the rows of X. Returns a dict with the merged CSR
     (global ids), FP64 edge distances, merged entry, operations and trace."""
@@ -274,7 +294,8 @@ def merge(subs, X, R, L, alpha, metric=L2SQ, k=5, kplus=16, ef_slide=None, mos_d
     entries = _i32([s[2] for s in subs])
     P = Params(R=R, ef_naive=L, ef_slide=L if ef_slide is None else ef_slide, alpha=float(alpha),
                metric=metric, k=k, kplus=kplus, mos_degree=mos_degree, mos_diameter=mos_diameter,
-               use_centroids=int(use_centroids), all_pivots=int(all_pivots))
+               use_centroids=int(use_centroids), all_pivots=int(all_pivots),
+               prune_rule=int(prune_rule), prune_param=float(prune_param))
     N = X.shape[0]
     rows = np.full((N, R), -1, dtype=np.int32)
     dists = np.full((N, R), np.inf, dtype=np.float64)

@@ -257,12 +257,66 @@ static int wkey_cmp(const void* a, const void* b) {
 }
 
 /*
- * Prune(p, W): sort the candidates by (d(p,.), id); walk them in order and
- * keep v unless some already kept w satisfies alpha * d(w, v) < d(p, v);
- * stop once R are kept. Duplicates and p itself are removed first.
+ * The rule by which an already kept w removes a later candidate v, from the
+ * distances d(p,v), d(p,w), d(w,v) (squared L2 for rules 1 and 2):
+ *   0  alpha (the RNG rule with a factor; alpha = 1 is NSG's MRNG):
+ *      alpha * d(w, v) < d(p, v);
+ *   1  angle (SSG): the angle at p between v and w is below theta, i.e.
+ *      cos = (d(p,v) + d(p,w) - d(w,v)) / (2 sqrt(d(p,v) d(p,w))) exceeds
+ *      cos(theta), decided as c > 0 and c^2 > 4 cos^2(theta) d(p,v) d(p,w)
+ *      with c the numerator (0 < theta <= 90 degrees);
+ *   2  tau (tau-MNG): w lies in the tau-lune of (p, v): sqrt(d(w, v)) <
+ *      sqrt(d(p, v)) - 3 tau (w precedes v, so d(p, w) <= d(p, v)).
+ * a: alpha, cos(theta) or 3 tau, formed once in double (prune_rule_param).
  */
+typedef struct {
+    int kind;
+    double a;
+} rule_t;
+
+static int rule_drops(const rule_t* r, double dpv, double dpw, double dwv) {
+    if (r->kind == 1) {
+        const double c = dpv + dpw - dwv;
+        return c > 0.0 && c * c > 4.0 * r->a * r->a * dpv * dpw;
+    }
+    if (r->kind == 2) {
+        const double t = sqrt(dpv) - r->a;
+        return t > 0.0 && sqrt(dwv) < t;
+    }
+    return r->a * dwv < dpv;
+}
+
+/* the rule's constant from the user's parameter: alpha as given (float32),
+ * cos(theta) for theta in degrees, 3 tau */
+static rule_t prune_rule_param(int kind, float alpha, float param) {
+    rule_t r;
+    r.kind = kind;
+    if (kind == 1)
+        r.a = cos((double)param * (3.14159265358979323846 / 180.0));
+    else if (kind == 2)
+        r.a = 3.0 * (double)param;
+    else
+        r.a = (double)alpha;
+    return r;
+}
+
+/*
+ * Prune(p, W): sort the candidates by (d(p,.), id); walk them in order and
+ * keep v unless some already kept w removes it by the rule (alpha: alpha *
+ * d(w, v) < d(p, v)); stop once R are kept. Duplicates and p itself are
+ * removed first.
+ */
+static int prune_rule(const space_t* S, int64_t p, const int32_t* W, int nW, const rule_t* rule,
+                      int R, int32_t* out_ids, double* out_d);
+
 static int prune(const space_t* S, int64_t p, const int32_t* W, int nW, float alpha, int R,
                  int32_t* out_ids, double* out_d) {
+    const rule_t r = prune_rule_param(0, alpha, 0.0f);
+    return prune_rule(S, p, W, nW, &r, R, out_ids, out_d);
+}
+
+static int prune_rule(const space_t* S, int64_t p, const int32_t* W, int nW, const rule_t* rule,
+                      int R, int32_t* out_ids, double* out_d) {
     wkey_t* c = (wkey_t*)malloc(sizeof(wkey_t) * (size_t)(nW > 0 ? nW : 1));
     int nc = 0;
     for (int i = 0; i < nW; ++i) {
@@ -277,13 +331,12 @@ static int prune(const space_t* S, int64_t p, const int32_t* W, int nW, float al
         ++nc;
     }
     qsort(c, (size_t)nc, sizeof(wkey_t), wkey_cmp);
-    const double a = (double)alpha; /* alpha already float32 */
     int nk = 0;
     for (int i = 0; i < nc && nk < R; ++i) {
         int dominated = 0;
         for (int j = 0; j < nk; ++j) {
             double dwv = dist_ids(S, out_ids[j], c[i].id);
-            if (a * dwv < c[i].d) { dominated = 1; break; }
+            if (rule_drops(rule, c[i].d, out_d[j], dwv)) { dominated = 1; break; }
         }
         if (!dominated) {
             out_ids[nk] = c[i].id;
@@ -293,6 +346,14 @@ static int prune(const space_t* S, int64_t p, const int32_t* W, int nW, float al
     }
     free(c);
     return nk;
+}
+
+int orc_prune_rule(int64_t p, const int32_t* W, int nW, const float* X, int dim, int metric,
+                   const double* norms, int rule, float alpha, float param, int R,
+                   int32_t* out_ids, double* out_d) {
+    space_t S = {X, dim, metric, norms};
+    const rule_t r = prune_rule_param(rule, alpha, param);
+    return prune_rule(&S, p, W, nW, &r, R, out_ids, out_d);
 }
 
 int orc_prune(int64_t p, const int32_t* W, int nW, const float* X, int dim, int metric,
@@ -618,6 +679,7 @@ static int pair_op(const space_t* S, const sub_t* s, const sub_t* t, const rows_
                    int64_t n_piv, int32_t* trace_res_ids, double* trace_res_d) {
     const int L = P->ef_naive, EL = P->ef_slide, R = P->R;
     const int RES = L > EL ? L : EL;
+    const rule_t rule = prune_rule_param(P->prune_rule, P->alpha, P->prune_param);
     int32_t* res_ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)(s->n * RES));
     double* res_d = (double*)malloc(sizeof(double) * (size_t)(s->n * RES));
     int* res_n = (int*)calloc((size_t)s->n, sizeof(int));
@@ -687,7 +749,8 @@ static int pair_op(const space_t* S, const sub_t* s, const sub_t* t, const rows_
             int nw = 0;
             for (int j = 0; j < rows->deg[gu]; ++j) W[nw++] = rows->rows[gu * R + j];
             for (int j = 0; j < res_n[u]; ++j) W[nw++] = (int32_t)(t->base + res_ids[u * RES + j]);
-            rows->deg[gu] = prune(S, gu, W, nw, P->alpha, R, rows->rows + gu * R, rows->dists + gu * R);
+            rows->deg[gu] = prune_rule(S, gu, W, nw, &rule, R, rows->rows + gu * R,
+                                       rows->dists + gu * R);
         }
         free(W);
     }
@@ -725,7 +788,8 @@ static int pair_op(const space_t* S, const sub_t* s, const sub_t* t, const rows_
             int nw = 0;
             for (int j = 0; j < rows->deg[gv]; ++j) W2[nw++] = rows->rows[gv * R + j];
             for (int64_t j = rcnt[v]; j < rcnt[v + 1]; ++j) W2[nw++] = rev[j];
-            rows->deg[gv] = prune(S, gv, W2, nw, P->alpha, R, rows->rows + gv * R, rows->dists + gv * R);
+            rows->deg[gv] = prune_rule(S, gv, W2, nw, &rule, R, rows->rows + gv * R,
+                                       rows->dists + gv * R);
         }
         free(W2);
     }
@@ -804,6 +868,10 @@ int orc_merge(int m, const int64_t* sizes, const int64_t* offsets_cat, const int
               int32_t* out_ops, int* out_nops, orc_trace_t* trace) {
     if (m < 1 || P->R < 1 || P->ef_naive < 1 || P->ef_slide < 1 || P->k < 1 || P->kplus < P->k)
         return -1;
+    if (P->prune_rule < 0 || P->prune_rule > 2 || (P->prune_rule != 0 && P->metric != ORC_L2SQ))
+        return -1;
+    if (P->prune_rule == 1 && !(P->prune_param > 0.0f && P->prune_param <= 90.0f)) return -1;
+    if (P->prune_rule == 2 && !(P->prune_param >= 0.0f)) return -1;
     const int R = P->R;
     int64_t N = 0;
     sub_t* subs = (sub_t*)malloc(sizeof(sub_t) * (size_t)m);
@@ -1098,26 +1166,33 @@ static int64_t repair_reach(const space_t* S, int64_t n, int R, int32_t* rows, i
             if (!vis[u] && !inu[u]) ++nheads;
         const char* excl = nheads > 0 ? inu : ins;
         int64_t np = 0;
-        for (int64_t u = 0; u < n; ++u) {
-            if (vis[u] || excl[u]) continue;
-            int64_t r = -1, rf = -1; /* nearest reached; nearest reached with a free slot */
-            double dr = 0.0, drf = 0.0;
-            for (int64_t v = 0; v < n; ++v) {
-                if (!vis[v]) continue;
+        for (int64_t u = 0; u < n; ++u)
+            if (!vis[u] && !excl[u]) P[np++].u = u;
+        /* the targets a head may propose to: the reached vertices with a free
+         * slot, or every reached vertex when none has one */
+        int64_t nc = 0;
+        for (int64_t v = 0; v < n; ++v)
+            if (vis[v] && deg[v] < R) queue[nc++] = (int32_t)v;
+        if (nc == 0)
+            for (int64_t v = 0; v < n; ++v)
+                if (vis[v]) queue[nc++] = (int32_t)v;
+        /* each head's proposal on its own (threads over heads): the nearest
+         * target */
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t h = 0; h < np; ++h) {
+            const int64_t u = P[h].u;
+            int64_t r = -1;
+            double dr = 0.0;
+            for (int64_t c = 0; c < nc; ++c) {
+                const int64_t v = queue[c];
                 const double d = dist_ids(S, u, v);
                 if (r < 0 || key_less(d, v, dr, r)) {
                     r = v;
                     dr = d;
                 }
-                if (deg[v] < R && (rf < 0 || key_less(d, v, drf, rf))) {
-                    rf = v;
-                    drf = d;
-                }
             }
-            P[np].t = rf >= 0 ? rf : r;
-            P[np].d = rf >= 0 ? drf : dr;
-            P[np].u = u;
-            ++np;
+            P[h].t = r;
+            P[h].d = dr;
         }
         qsort(P, (size_t)np, sizeof(prop_t), prop_cmp);
         for (int64_t i = 0; i < np;) {
@@ -1170,14 +1245,19 @@ int orc_build(int64_t n, const float* X, int dim, int metric, const int32_t* knn
     int32_t* rows = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n * R + 1));
     double* rd = (double*)malloc(sizeof(double) * (size_t)(n * R + 1));
     int32_t* deg = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-    int32_t* W = (int32_t*)malloc(sizeof(int32_t) * (size_t)(K + 1));
-    for (int64_t v = 0; v < n; ++v) {
-        int nw = 0;
-        for (int j = 0; j < K; ++j)
-            if (knn[v * K + j] >= 0) W[nw++] = knn[v * K + j];
-        deg[v] = prune(&S, v, W, nw, alpha, R, rows + v * R, rd + v * R);
+    /* rows on their own (threads over vertices) */
+#pragma omp parallel
+    {
+        int32_t* W = (int32_t*)malloc(sizeof(int32_t) * (size_t)(K + 1));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t v = 0; v < n; ++v) {
+            int nw = 0;
+            for (int j = 0; j < K; ++j)
+                if (knn[v * K + j] >= 0) W[nw++] = knn[v * K + j];
+            deg[v] = prune(&S, v, W, nw, alpha, R, rows + v * R, rd + v * R);
+        }
+        free(W);
     }
-    free(W);
     if (reverse) {
         int64_t* cnt = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
         for (int64_t v = 0; v < n; ++v)
@@ -1194,21 +1274,26 @@ int orc_build(int64_t n, const float* X, int dim, int metric, const int32_t* knn
         /* every offer is read from the rows of the first pass */
         int32_t* rows2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n * R + 1));
         int32_t* deg2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
-        int32_t* W2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + maxr + 1));
-        for (int64_t w = 0; w < n; ++w) {
-            if (cnt[w + 1] == cnt[w]) {
-                deg2[w] = deg[w];
-                memcpy(rows2 + w * R, rows + w * R, sizeof(int32_t) * (size_t)deg[w]);
-                continue;
+#pragma omp parallel
+        {
+            int32_t* W2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + maxr + 1));
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t w = 0; w < n; ++w) {
+                if (cnt[w + 1] == cnt[w]) {
+                    deg2[w] = deg[w];
+                    memcpy(rows2 + w * R, rows + w * R, sizeof(int32_t) * (size_t)deg[w]);
+                    continue;
+                }
+                int nw = 0;
+                for (int j = 0; j < deg[w]; ++j) W2[nw++] = rows[w * R + j];
+                for (int64_t j = cnt[w]; j < cnt[w + 1]; ++j) W2[nw++] = rev[j];
+                deg2[w] = prune(&S, w, W2, nw, alpha_rev, R, rows2 + w * R, rd + w * R);
             }
-            int nw = 0;
-            for (int j = 0; j < deg[w]; ++j) W2[nw++] = rows[w * R + j];
-            for (int64_t j = cnt[w]; j < cnt[w + 1]; ++j) W2[nw++] = rev[j];
-            deg2[w] = prune(&S, w, W2, nw, alpha_rev, R, rows2 + w * R, rd + w * R);
+            free(W2);
         }
         memcpy(rows, rows2, sizeof(int32_t) * (size_t)(n * R));
         memcpy(deg, deg2, sizeof(int32_t) * (size_t)n);
-        free(rows2); free(deg2); free(W2); free(rev); free(fill); free(cnt);
+        free(rows2); free(deg2); free(rev); free(fill); free(cnt);
     }
     /* entry */
     int integral = 1;

@@ -21,6 +21,9 @@ typedef struct {
     int mos_diameter; /* >= 2 */
     int use_centroids;/* MOS costs from centroids (1) or unit costs (0) */
     int all_pivots;   /* every source vertex runs a naive search (CM) */
+    int prune_rule;   /* 0 alpha, 1 angle (SSG, prune_param = theta in degrees), 2 tau-MNG
+                         (prune_param = tau); 1 and 2 take squared L2 */
+    float prune_param;
 } orc_params_t;
 
 typedef struct {
@@ -43,6 +46,9 @@ int orc_beam_search(int64_t n, const int64_t* offsets, const int32_t* nbrs, int6
                     int64_t* ndc);
 int orc_prune(int64_t p, const int32_t* W, int nW, const float* X, int dim, int metric,
               const double* norms, float alpha, int R, int32_t* out_ids, double* out_d);
+int orc_prune_rule(int64_t p, const int32_t* W, int nW, const float* X, int dim, int metric,
+                   const double* norms, int rule, float alpha, float param, int R,
+                   int32_t* out_ids, double* out_d);
 int orc_expand(int64_t n, const int64_t* offsets, const int32_t* nbrs, int64_t base,
                const float* X, int dim, int metric, const double* norms, int k, int kplus,
                int32_t* nk_out);

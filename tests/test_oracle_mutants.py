@@ -20,8 +20,15 @@ MUTANTS = {
     "beam_no_truncation": ("        if (size > ef) size = ef;\n    }\n    for (int i = 0; i < size; ++i) {",
                            "    }\n    for (int i = 0; i < size; ++i) {"),
     "beam_expands_farthest": ("if (!C[i].expanded) { u = i; break; }", "if (!C[i].expanded) { u = i; }"),
-    "prune_not_strict": ("if (a * dwv < c[i].d)", "if (a * dwv <= c[i].d)"),
-    "prune_alpha_wrong_side": ("if (a * dwv < c[i].d)", "if (dwv < a * c[i].d)"),
+    "prune_not_strict": ("return r->a * dwv < dpv;", "return r->a * dwv <= dpv;"),
+    "prune_alpha_wrong_side": ("return r->a * dwv < dpv;", "return dwv < r->a * dpv;"),
+    "angle_factor_four_dropped": ("c * c > 4.0 * r->a * r->a * dpv * dpw",
+                                  "c * c > r->a * r->a * dpv * dpw"),
+    "angle_obtuse_not_excluded": ("return c > 0.0 && c * c", "return c * c"),
+    "tau_without_factor_three": ("r.a = 3.0 * (double)param;", "r.a = (double)param;"),
+    "tau_on_squared_distances": ("return t > 0.0 && sqrt(dwv) < t;", "return t > 0.0 && dwv < t;"),
+    "rule_ignored_by_merge": ("const rule_t rule = prune_rule_param(P->prune_rule, P->alpha, P->prune_param);",
+                              "const rule_t rule = prune_rule_param(0, P->alpha, P->prune_param);"),
     "pivot_tie_reversed": ("(a.g == b.g && a.x < b.x)", "(a.g == b.g && a.x > b.x)"),
     "mos_relay_costliest": ("(best < 0 || C[c * m + v] < C[best * m + v])",
                             "(best < 0 || C[c * m + v] > C[best * m + v])"),
@@ -43,16 +50,18 @@ MUTANTS = {
     "knn_queries_unsorted": ("qsort(c, (size_t)n, sizeof(wkey_t), wkey_cmp);", ""),
     "builder_reverse_with_alpha": ("deg2[w] = prune(&S, w, W2, nw, alpha_rev, R",
                                    "deg2[w] = prune(&S, w, W2, nw, alpha, R"),
-    "repair_links_from_farthest": ("if (deg[v] < R && (rf < 0 || key_less(d, v, drf, rf)))",
-                                   "if (deg[v] < R && (rf < 0 || key_less(drf, rf, d, v)))"),
-    "repair_ignores_free_slots": ("P[np].t = rf >= 0 ? rf : r;", "P[np].t = r;"),
+    "repair_links_from_farthest": ("if (r < 0 || key_less(d, v, dr, r)) {\n                    r = v;\n                    dr = d;\n                }\n            }\n            P[h].t",
+                                   "if (r < 0 || key_less(dr, r, d, v)) {\n                    r = v;\n                    dr = d;\n                }\n            }\n            P[h].t"),
+    "repair_ignores_free_slots": ("if (vis[v] && deg[v] < R) queue[nc++] = (int32_t)v;",
+                                  "if (vis[v]) queue[nc++] = (int32_t)v;"),
     "repair_replaces_first_entry": ("rows[t * R + R - 1] = (int32_t)P[k].u;",
                                     "rows[t * R] = (int32_t)P[k].u;"),
     "repair_accepts_farthest": ("    if (key_less(x->d, x->u, y->d, y->u)) return -1;",
                                 "    if (key_less(x->d, x->u, y->d, y->u)) return 1;"),
     "repair_accepts_one_per_pass": ("const int64_t take = deg[t] < R ? R - deg[t] : 1;",
                                     "const int64_t take = 1;"),
-    "repair_every_unreached_proposes": ("if (vis[u] || excl[u]) continue;", "if (vis[u]) continue;"),
+    "repair_every_unreached_proposes": ("if (!vis[u] && !excl[u]) P[np++].u = u;",
+                                        "if (!vis[u]) P[np++].u = u;"),
     "repair_cycles_by_larger_id": ("if (v < w) ins[w] = 1;", "if (v > w) ins[w] = 1;"),
     "repair_single_pass": ("for (int pass = 0; pass < 4096; ++pass)", "for (int pass = 0; pass < 1; ++pass)"),
 }

@@ -811,3 +811,88 @@ def test_reachable_counts(orc):
     assert orc.reachable(offs, nb, 0) == 3
     assert orc.reachable(offs, nb, 3) == 2
     assert orc.reachable(offs, nb, 5) == 1
+
+
+def test_prune_rules_golden(orc):
+    # the alpha (NSG at alpha = 1), angle (SSG) and tau (tau-MNG) rules on a
+    # hand-traced 2-d example
+    g = _gold("prune_rules.json")
+    X = np.array(g["points"], dtype=np.float32)
+    for c in g["cases"]:
+        ids, _ = orc.prune_rule(g["p"], g["W"], X, c["rule"], g["R"], alpha=c["alpha"],
+                                param=c["param"])
+        assert ids.tolist() == c["want"], c
+
+
+def _angle_deg(p, v, w):
+    a, b = v - p, w - p
+    return np.degrees(np.arccos(np.clip(a @ b / np.sqrt((a @ a) * (b @ b)), -1.0, 1.0)))
+
+
+@pytest.mark.parametrize("theta", [30.0, 60.0, 75.0])
+def test_prune_angle_rule_definition(orc, theta):
+    # the angle rule against its geometric definition on random integer
+    # points: kept candidates pairwise at least theta apart (seen from p),
+    # every removed one (before R are kept) closer than theta to an earlier
+    # kept one; angles from normalised dot products in float64
+    g = np.random.default_rng(int(theta))
+    checked = 0
+    for trial in range(40):
+        X = g.integers(-20, 21, (60, 3)).astype(np.float32)
+        X[0] = 0
+        W = list(range(1, 60))
+        R = 12
+        ids, _ = orc.prune_rule(0, W, X, 1, R, param=theta)
+        X64 = X.astype(np.float64)
+        order = sorted(W, key=lambda v: (float(X64[v] @ X64[v]), v))
+        kept, boundary = [], False
+        for v in order:
+            if len(kept) == R:
+                break
+            angs = [_angle_deg(X64[0], X64[v], X64[w]) for w in kept]
+            boundary |= any(abs(a - theta) < 1e-7 for a in angs) or not X64[v].any()
+            if not any(a < theta for a in angs):
+                kept.append(v)
+        if boundary:  # an angle at theta itself: rounding decides, skip the draw
+            continue
+        checked += 1
+        assert ids.tolist() == kept, trial
+    assert checked >= 30
+
+
+@pytest.mark.parametrize("tau", [0.0, 1.5, 4.0])
+def test_prune_tau_rule_definition(orc, tau):
+    # tau-MNG against its definition with Euclidean lengths; tau = 0 is the
+    # RNG rule, i.e. the alpha rule at alpha = 1
+    g = np.random.default_rng(100 + int(tau * 10))
+    for trial in range(40):
+        X = g.integers(-20, 21, (60, 3)).astype(np.float32)
+        X[0] = 0
+        W = list(range(1, 60))
+        R = 12
+        ids, _ = orc.prune_rule(0, W, X, 2, R, param=tau)
+        X64 = X.astype(np.float64)
+        dist = lambda a, b: float(np.sqrt(((X64[a] - X64[b]) ** 2).sum()))
+        order = sorted(W, key=lambda v: (dist(0, v) ** 2, v))
+        kept = []
+        for v in order:
+            if len(kept) == R:
+                break
+            if not any(dist(w, v) < dist(0, v) - 3 * tau for w in kept):
+                kept.append(v)
+        assert ids.tolist() == kept, trial
+        if tau == 0.0:
+            assert ids.tolist() == orc.prune(0, W, X, 1.0, R)[0].tolist()
+
+
+def test_merge_with_prune_rules_differs_and_keeps_degree(orc):
+    # a merge under each rule: rows within R, and the rules give different
+    # graphs (the rule reaches the merge's source and target prunes)
+    X = inputs.tiny_int(1600, 8, seed=1651, lo=-6, hi=6)
+    subs = [orc.build_graph(X[:700], 24, 12, alpha=1.0), orc.build_graph(X[700:], 24, 12, alpha=1.0)]
+    outs = []
+    for rule, prm in [(0, 0.0), (1, 60.0), (2, 0.5)]:
+        r = orc.merge(subs, X, R=12, L=24, alpha=1.0, prune_rule=rule, prune_param=prm)
+        assert np.diff(r["offsets"]).max() <= 12
+        outs.append(r["nbrs"].tolist())
+    assert outs[0] != outs[1] and outs[0] != outs[2] and outs[1] != outs[2]
