@@ -152,7 +152,22 @@ typedef struct {
  *          need (inputs copied from the host or from strided rows included,
  *          the caller's inputs and outputs not); a call that would exceed it
  *          returns RNSM_ENOMEM before allocating. 0: no budget.
+ * prune_rule, prune_param  the edge-selection rule of the merge's prunes,
+ *          for graphs of other proximity-graph families (Section 6's
+ *          applicability experiment): RNSM_PRUNE_ALPHA (0, default; the RNG
+ *          rule with factor alpha, NSG's MRNG at alpha = 1): kept w removes
+ *          a later candidate v when alpha d(w,v) < d(p,v); RNSM_PRUNE_ANGLE
+ *          (SSG): when the angle at p between v and w is below prune_param
+ *          degrees (0 < theta <= 90); RNSM_PRUNE_TAU (tau-MNG): when
+ *          |w - v| < |p - v| - 3 prune_param (tau >= 0). The angle and tau
+ *          rules take RNSM_L2SQ (RNSM_EINVAL otherwise) and run on the
+ *          float32 prune; decisions are taken in double from the float32
+ *          distances, the rule's constant (cos theta, 3 tau) formed in
+ *          double on the host.
  */
+#define RNSM_PRUNE_ALPHA 0
+#define RNSM_PRUNE_ANGLE 1
+#define RNSM_PRUNE_TAU 2
 typedef struct {
     int32_t R, L;
     float alpha;
@@ -163,6 +178,8 @@ typedef struct {
     void* stream;
     int32_t search_hash_bits, search_waves_per_block;
     int64_t max_device_bytes;
+    int32_t prune_rule;
+    float prune_param;
 } rnsm_params;
 
 /*

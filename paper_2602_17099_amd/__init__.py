@@ -20,6 +20,7 @@ FLAG_AUTOTUNE = 4
 FLAG_HOST_OUT = 8
 FLAG_NO_STATS = 16
 FLAG_BATCHED = 32
+PRUNE_ALPHA, PRUNE_ANGLE, PRUNE_TAU = 0, 1, 2
 DEVICE, HOST = 0, 1
 
 SYMBOLS = ["rnsm_merge", "rnsm_merge_simple", "mos_plan", "rnsm_select_pivots", "rnsm_search",
@@ -53,7 +54,8 @@ class Params(C.Structure):
                 ("ef_slide", C.c_int32), ("mos_degree", C.c_int32), ("mos_diameter", C.c_int32),
                 ("flags", C.c_uint32), ("stream", C.c_void_p),
                 ("search_hash_bits", C.c_int32), ("search_waves_per_block", C.c_int32),
-                ("max_device_bytes", C.c_int64)]
+                ("max_device_bytes", C.c_int64), ("prune_rule", C.c_int32),
+                ("prune_param", C.c_float)]
 
 
 class SearchTuning(C.Structure):
@@ -168,7 +170,7 @@ def _vectors(X, search=None):
 
 def merge(subs, X, R, L, alpha, metric=L2SQ, search=None, k=0, kplus=0, ef_naive=0,
           ef_slide=0, mos_degree=0, mos_diameter=0, flags=0, dists=True, stream=None,
-          out=None, search_shape=None, max_device_bytes=0):
+          out=None, search_shape=None, max_device_bytes=0, prune_rule=0, prune_param=0.0):
     """Merge sub-indexes. subs: list of (offsets int64, nbrs int32, entry) device
     tensors with local ids, in global-id order over the rows of X (float32
     device [N, dim]). search: optional bf16/f16 copy of X that the searches
@@ -194,7 +196,8 @@ def merge(subs, X, R, L, alpha, metric=L2SQ, search=None, k=0, kplus=0, ef_naive
     p = Params(R=R, L=L, alpha=float(alpha), metric=metric, k_reverse=k, k_expand=kplus,
                ef_naive=ef_naive, ef_slide=ef_slide, mos_degree=mos_degree,
                mos_diameter=mos_diameter, flags=flags, stream=_stream(stream),
-               max_device_bytes=int(max_device_bytes))
+               max_device_bytes=int(max_device_bytes), prune_rule=int(prune_rule),
+               prune_param=float(prune_param))
     if search_shape is not None:
         p.search_hash_bits, p.search_waves_per_block = (int(x) for x in search_shape)
     _check(lib().rnsm_merge(m, gs, C.byref(v), C.byref(p), C.byref(csr)))

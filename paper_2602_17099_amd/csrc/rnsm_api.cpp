@@ -588,6 +588,18 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
         return fail(RNSM_EINVAL, "rnsm_merge: alpha must be finite and >= 1");
     if (p->metric < RNSM_L2SQ || p->metric > RNSM_COSINE)
         return fail(RNSM_EINVAL, "rnsm_merge: unknown metric %d", (int)p->metric);
+    if (p->prune_rule < RNSM_PRUNE_ALPHA || p->prune_rule > RNSM_PRUNE_TAU)
+        return fail(RNSM_EINVAL, "rnsm_merge: unknown prune_rule %d", (int)p->prune_rule);
+    if (p->prune_rule != RNSM_PRUNE_ALPHA && p->metric != RNSM_L2SQ)
+        return fail(RNSM_EINVAL, "rnsm_merge: the angle and tau rules take squared L2");
+    if (p->prune_rule == RNSM_PRUNE_ANGLE && !(p->prune_param > 0.0f && p->prune_param <= 90.0f))
+        return fail(RNSM_EINVAL, "rnsm_merge: prune_param (theta) outside (0, 90] degrees");
+    if (p->prune_rule == RNSM_PRUNE_TAU && !(p->prune_param >= 0.0f && std::isfinite(p->prune_param)))
+        return fail(RNSM_EINVAL, "rnsm_merge: prune_param (tau) must be finite and >= 0");
+    // the rule's constant, formed once in double
+    const double rule_a = p->prune_rule == RNSM_PRUNE_ANGLE
+                              ? cos((double)p->prune_param * (3.14159265358979323846 / 180.0))
+                              : 3.0 * (double)p->prune_param;
     const int k = p->k_reverse ? p->k_reverse : 5;
     const int kp = p->k_expand ? p->k_expand : 16;
     if (k < 1 || kp < k || kp > 64)
@@ -860,7 +872,8 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
     ValueInfo vinfo;
     HIPCHK(hipEventSynchronize(E.ev[ev_vr]));
     decode_value_range(h_vr, &vinfo);
-    const int pmode = choose_prune(vinfo, vecs->dim, R);
+    // the angle and tau rules run on the float32 walk
+    const int pmode = p->prune_rule != RNSM_PRUNE_ALPHA ? 0 : choose_prune(vinfo, vecs->dim, R);
     if (pmode != 1) xb16 = nullptr;
     if (pmode == 1 && !xb16) {
         WS(xb16, "prune_bf16", (size_t)2 * N * vecs->dim);
@@ -1232,6 +1245,8 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                 qs.extra_index_base = bases[s];
                 qs.extra_id_add = bases[t];
                 qs.alpha = p->alpha;
+                qs.rule = p->prune_rule;
+                qs.rule_a = rule_a;
                 qs.R = R;
                 qs.rows_out = rows;
                 qs.deg_out = deg;
@@ -1607,6 +1622,8 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
         qs.extra_index_base = bases[s];
         qs.extra_id_add = bases[t];
         qs.alpha = p->alpha;
+        qs.rule = p->prune_rule;
+        qs.rule_a = rule_a;
         qs.R = R;
         qs.rows_out = rows;
         qs.deg_out = deg;

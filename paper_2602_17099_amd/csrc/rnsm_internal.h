@@ -108,6 +108,10 @@ struct PruneArgs {
     int extra_sorted;         // mode 1 with extra_d: each extra row is in ascending
                               // (d, id) order, -1 ids last (a search's final beam)
     float alpha;
+    // the removal rule (float32 walk only): 0 alpha; 1 angle (SSG), rule_a =
+    // cos(theta); 2 tau-MNG, rule_a = 3 tau; 1 and 2 on squared L2
+    int rule;
+    double rule_a;
     int R;
     int32_t* rows_out;
     int32_t* deg_out;

@@ -1006,10 +1006,31 @@ __global__ __launch_bounds__(256) void k_row_dists(PruneArgs a) {
     if (todo) rd[lane] = fval((unsigned)(wk[lane] >> 32));
 }
 
+// Whether kept w removes candidate v under the rule, from d(p,v), d(p,w),
+// d(w,v): 0 alpha * d(w,v) < d(p,v); 1 (SSG) the angle at p between v and w
+// below theta: c = d(p,v) + d(p,w) - d(w,v) > 0 and c^2 > 4 cos^2(theta)
+// d(p,v) d(p,w); 2 (tau-MNG) sqrt(d(w,v)) < sqrt(d(p,v)) - 3 tau. In double,
+// each operation rounded on its own in this order (no contraction), so
+// exact distances give the same decision on any IEEE double machine.
+__device__ __forceinline__ bool rule_drops(int rule, double ra, double alpha, double dpv,
+                                           double dpw, double dwv) {
+    if (rule == 1) {
+        const double c = __dsub_rn(__dadd_rn(dpv, dpw), dwv);
+        return c > 0.0 &&
+               __dmul_rn(c, c) > __dmul_rn(__dmul_rn(__dmul_rn(__dmul_rn(4.0, ra), ra), dpv), dpw);
+    }
+    if (rule == 2) {
+        const double t = __dsub_rn(__dsqrt_rn(dpv), ra);
+        return t > 0.0 && __dsqrt_rn(dwv) < t;
+    }
+    return alpha * dwv < dpv;
+}
+
 // Prune(p, W) with float32 vector arithmetic: candidates are walked in
-// (d, id) order; a candidate is kept unless alpha * d(w, v) < d(p, v) for a
-// kept w (strict, in double); stop at R kept. Kept rows stay in registers
-// (KS slots per lane group) or are re-read (KS == 0).
+// (d, id) order; a candidate is kept unless a kept w removes it by the rule
+// (alpha: alpha * d(w, v) < d(p, v), strict, in double); stop at R kept.
+// Kept rows stay in registers (KS slots per lane group) or are re-read
+// (KS == 0); kept distances d(p, w) are read back from the output row.
 template <int CPL, int KS>
 __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
     extern __shared__ unsigned char psm[];
@@ -1083,7 +1104,9 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
                     if (jk < nk && sub == G - 1) {
                         const float kn = a.metric == 2 ? a.norms[kept_ids[jk]] : 1.0f;
                         const float dkv = finalize_dist(acc, a.metric, kn, vn);
-                        if (alpha * (double)dkv < (double)dv) dom = true;
+                        const double dpw = a.rule ? (double)a.dist_out[p * R + jk] : 0.0;
+                        if (rule_drops(a.rule, a.rule_a, alpha, (double)dv, dpw, (double)dkv))
+                            dom = true;
                     }
                 }
             }
@@ -1096,7 +1119,9 @@ __global__ __launch_bounds__(256) void k_prune(PruneArgs a) {
                 if (jk < nk && sub == G - 1) {
                     const float kn = a.metric == 2 ? a.norms[kept_ids[jk]] : 1.0f;
                     const float dkv = finalize_dist(acc, a.metric, kn, vn);
-                    if (alpha * (double)dkv < (double)dv) dom = true;
+                    const double dpw = a.rule ? (double)a.dist_out[p * R + jk] : 0.0;
+                    if (rule_drops(a.rule, a.rule_a, alpha, (double)dv, dpw, (double)dkv))
+                        dom = true;
                 }
             }
         }

@@ -37,14 +37,19 @@ def tiny_int(n: int, dim: int = 32, seed: int = SEED_BASE + 1, lo: int = -8, hi:
 
 def mixture_u8(n: int, dim: int = 128, comps: int = 64, sigma: float = 30.0,
                center_sd: float = 20.0, seed: int = SEED_BASE + 2,
-               stream: int = 0) -> np.ndarray:
+               stream: int = 0, centre_range: tuple[float, float] | None = None) -> np.ndarray:
     """Gaussian-mixture integers in [0, 255] stored as float32, shape (n, dim).
 
-    ``stream`` selects an independent draw (0: base vectors, 1: queries) from
-    the same mixture: the centres depend on ``seed`` only.
+    Centres are 128 + center_sd * N(0, I), or uniform on centre_range per
+    coordinate when given. ``stream`` selects an independent draw (0: base
+    vectors, 1: queries) from the same mixture: the centres depend on
+    ``seed`` only.
     """
     gc = rng(seed)
-    centres = 128.0 + center_sd * gc.standard_normal((comps, dim))
+    if centre_range is None:
+        centres = 128.0 + center_sd * gc.standard_normal((comps, dim))
+    else:
+        centres = gc.uniform(centre_range[0], centre_range[1], (comps, dim))
     g = rng(seed * 1000003 + 17 + stream)
     out = np.empty((n, dim), dtype=np.float32)
     chunk = 1 << 16
@@ -186,3 +191,11 @@ def slab_order(X: np.ndarray, seed: int) -> np.ndarray:
     partition when the rows are then cut into consecutive sub-indexes)."""
     d = rng(seed).standard_normal(X.shape[1])
     return np.argsort(X.astype(np.float64) @ (d / np.linalg.norm(d)), kind="stable")
+
+
+def paper_scale_u8(n: int, seed: int = SEED_BASE + 5, stream: int = 0) -> np.ndarray:
+    """The 100,000,000-vector uint8 workload's distribution (any n): dim 96,
+    4,096 components with centres uniform on [40, 215] per coordinate, noise
+    sigma 30, rounded and clipped to [0, 255]; uint8."""
+    return mixture_u8(n, 96, comps=4096, sigma=30.0, seed=seed, stream=stream,
+                      centre_range=(40.0, 215.0)).astype(np.uint8)

@@ -642,3 +642,35 @@ def test_convert_uint8_exact(dev, pkg, dtype):
     u = inputs.rng(902).integers(0, 256, 77777).astype(np.uint8)
     got = pkg.convert(_t(u, dev), getattr(torch, dtype)).float().cpu().numpy()
     assert np.array_equal(got, u.astype(np.float32))
+
+
+@pytest.mark.parametrize("rule,param", [(1, 60.0), (1, 45.0), (2, 0.0), (2, 0.5), (2, 2.0)])
+def test_merge_prune_rules_bit_exact(dev, orc, pkg, rule, param):
+    # the SSG angle rule and the tau-MNG rule in the merge's source and
+    # target prunes (the float32 walk), against the oracle: integer rows,
+    # so every distance is exact and the decisions in double agree
+    sizes = [1300, 2100, 900]
+    X = inputs.tiny_int(sum(sizes), 32, seed=1661)
+    subs, b = [], 0
+    for n in sizes:
+        subs.append(orc.build_graph(X[b:b + n], 24, 12, alpha=1.0))
+        b += n
+    ref = orc.merge(subs, X, R=12, L=24, alpha=1.2, prune_rule=rule, prune_param=param)
+    for flags in (0, pkg.FLAG_BATCHED):
+        got = pkg.merge(_dsubs(subs, dev), _t(X, dev), R=12, L=24, alpha=1.2, prune_rule=rule,
+                        prune_param=param, flags=flags)
+        assert pkg.stats()["prune_path"] == 0
+        _assert_same_merge(got, ref)
+
+
+def test_merge_prune_rules_rejected(dev, orc, pkg):
+    X = inputs.tiny_int(600, 32, seed=1662)
+    subs = _dsubs([orc.build_graph(X[:300], 16, 8, alpha=1.0),
+                   orc.build_graph(X[300:], 16, 8, alpha=1.0)], dev)
+    Xd = _t(X, dev)
+    for kw in (dict(prune_rule=3), dict(prune_rule=1, prune_param=0.0),
+               dict(prune_rule=1, prune_param=95.0), dict(prune_rule=2, prune_param=-1.0),
+               dict(prune_rule=1, prune_param=60.0, metric=1)):
+        with pytest.raises(pkg.RnsmError) as ei:
+            pkg.merge(subs, Xd, R=8, L=16, alpha=1.2, **kw)
+        assert ei.value.status == 1
