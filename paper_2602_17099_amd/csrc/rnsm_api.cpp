@@ -493,33 +493,37 @@ static rnsm_status rnsm_select_pivots_impl(int64_t n, const int64_t* rk_offsets,
     return RNSM_OK;
 }
 
-// Pivot selection on the device over reverse lists (off, ids) of n vertices:
-// rounds of the parallel rule until every vertex is covered (the host checks
-// after every `batch` rounds). pivot_of receives -1 for pivots, else the
-// pivot. Workspace buffers; the caller holds g_lock.
+// Pivot selection on the device over reverse lists (off, ids) of n vertices
+// and their forward lists (f_ids with CSR offsets f_off, or f_off NULL:
+// fixed stride fk, -1 padded, as N_k): rounds of the parallel rule until
+// every vertex is covered (the host checks after every `batch` rounds).
+// pivot_of receives -1 for pivots, else the pivot. Workspace buffers; the
+// caller holds g_lock.
 static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off,
-                                    const int32_t* ids, int32_t* pivot_of, hipStream_t st,
-                                    int64_t* n_pivots, int batch = 8, int64_t* rounds = nullptr) {
-    unsigned char *cov, *sel;
-    u64 *key, *best;
+                                    const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
+                                    int fk, int32_t* pivot_of, hipStream_t st, int64_t* n_pivots,
+                                    int batch = 8, int64_t* rounds = nullptr) {
+    unsigned char *cov, *lose;
+    int32_t* gain;
+    u64* best;
     int64_t *ctl, *h_ctl;
     WS(cov, "sel_cov", n);
-    WS(sel, "sel_pick", n);
-    WS(key, "sel_key", sizeof(u64) * n);
+    WS(lose, "sel_lose", n);
+    WS(gain, "sel_gain", sizeof(int32_t) * n);
     WS(best, "sel_best", sizeof(u64) * n);
     WS(ctl, "sel_ctl", sizeof(int64_t) * 4);
     HS(h_ctl, "h_sel_ctl", sizeof(int64_t) * 4);
     int32_t* longv;
     WS(longv, "sel_long", sizeof(int32_t) * std::max<int64_t>(n, 1));
-    HIPCHK(launch_select_init(n, off, cov, sel, pivot_of, longv, ctl, st));
+    HIPCHK(launch_select_init(n, off, cov, gain, pivot_of, longv, ctl, st));
     HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const int64_t nlong = h_ctl[3];
     if (nlong < 0 || nlong > n) return fail(RNSM_EINTERNAL, "pivot selection: bad long-list count");
     // every round covers at least the vertex with the largest key
     for (int64_t done = 0; done <= n + batch; done += batch) {
-        HIPCHK(launch_select_rounds(n, off, ids, cov, sel, key, best, pivot_of, ctl, longv, nlong,
-                                    batch, st));
+        HIPCHK(launch_select_rounds(n, off, ids, f_ids, f_off, fk, cov, lose, gain, best, pivot_of,
+                                    ctl, longv, nlong, batch, st));
         HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (h_ctl[0] == 0) {
@@ -556,7 +560,20 @@ static rnsm_status rnsm_select_pivots_device_impl(int64_t n, const int64_t* rk_o
     if (hflag)
         return fail(RNSM_EINVAL, "rnsm_select_pivots_device: malformed lists (offsets, an id out "
                     "of range or a list naming its owner)");
-    return select_on_device(ws, n, rk_offsets, rk_ids, pivot_of, st, out_n_pivots);
+    // forward lists of the caller's reverse lists
+    int32_t *fcnt, *fcur, *f_ids;
+    int64_t *f_off, *stmp;
+    int64_t nnz = 0;
+    HIPCHK(hipMemcpyAsync(&nnz, rk_offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    WS(fcnt, "sel_fcnt", sizeof(int32_t) * n);
+    WS(fcur, "sel_fcur", sizeof(int32_t) * n);
+    WS(f_off, "sel_foff", sizeof(int64_t) * (n + 1));
+    WS(f_ids, "sel_fids", sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    WS(stmp, "sel_scan", sizeof(int64_t) * scan_tmp_elems(n));
+    HIPCHK(launch_select_forward(n, rk_offsets, rk_ids, fcnt, fcur, f_off, f_ids, stmp, st));
+    return select_on_device(ws, n, rk_offsets, rk_ids, f_ids, f_off, 0, pivot_of, st,
+                            out_n_pivots);
 }
 
 static rnsm_status tune_shape_locked(const rnsm_graph* g, const rnsm_vectors* base,
@@ -1048,8 +1065,8 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                     g_stats.launches[0] += 1;
                     int64_t nrs = 0;
                     HIPCHK(E.stat(st, &ev_sel0));
-                    const rnsm_status ss = select_on_device(ws, ns, rk_off, rk_ids, pivot_of, st, &np,
-                                                            select_batch, &nrs);
+                    const rnsm_status ss = select_on_device(ws, ns, rk_off, rk_ids, nk, nullptr, k,
+                                                            pivot_of, st, &np, select_batch, &nrs);
                     if (ss != RNSM_OK) return ss;
                     g_stats.select_rounds += nrs;
                 }

@@ -3447,14 +3447,44 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
 // the vertices listing it). Such an x is also the sequential greedy's pick
 // before any vertex it competes with, with the same followers, and picks that
 // share no position commute, so the pivots and follower groups are the
-// greedy's. ctl[0]: uncovered vertices left (every kernel returns when 0),
-// ctl[1]: pivots, ctl[2]: rounds run with vertices left.
-__global__ void k_sel_init(int64_t n, unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
-                           int64_t* ctl) {
+// greedy's.
+//
+// The keys come from gains kept up to date: each newly covered y takes one
+// from the gain of every x whose list holds it, i.e. every x in y's forward
+// list F(y) = {x : y in R_k(x)} (N_k(y) in the merge). A round reads forward
+// lists only (short: k entries in the merge): spread, best[y] = the largest
+// key of y and of the uncovered x in F(y); mark, x loses when best[x] is not
+// its key or some uncovered y with x in F(y) has another best; apply, the
+// uncovered non-losers take their uncovered lists (a wavefront per list
+// longer than SEL_LONG). ctl[0]: uncovered vertices left (every kernel
+// returns when 0), ctl[1]: pivots, ctl[2]: rounds run with vertices left,
+// ctl[3]: long lists.
+struct SelFwd {
+    const int32_t* ids;   // forward lists
+    const int64_t* off;   // CSR offsets, or NULL: fixed stride fk, -1 padded
+    int fk;
+};
+
+__device__ __forceinline__ void fwd_range(const SelFwd& f, int64_t y, int64_t& b, int64_t& e) {
+    if (f.off) {
+        b = f.off[y];
+        e = f.off[y + 1];
+    } else {
+        b = y * f.fk;
+        e = b + f.fk;
+    }
+}
+
+__device__ __forceinline__ u64 sel_key(const int32_t* gain, int64_t x) {
+    return ((u64)(unsigned)gain[x] << 32) | (u64)(0xffffffffu - (unsigned)x);
+}
+
+__global__ void k_sel_init(int64_t n, const int64_t* rk_off, unsigned char* cov, int32_t* gain,
+                           int32_t* pivot_of, int64_t* ctl) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x < n) {
         cov[x] = 0;
-        sel[x] = 0;
+        gain[x] = (int32_t)(rk_off[x + 1] - rk_off[x]);
         pivot_of[x] = -2;
     }
     if (x == 0) {
@@ -3466,8 +3496,8 @@ __global__ void k_sel_init(int64_t n, unsigned char* cov, unsigned char* sel, in
 }
 
 // Lists longer than SEL_LONG (a hub can be in thousands of k-NN lists) are
-// read by a whole wavefront each; the rest by one thread per vertex. The
-// long ones are listed once per selection (ctl[3] counts them; any order).
+// taken by a whole wavefront each in the apply step; the rest by one thread
+// per vertex. The long ones are listed once per selection (any order).
 constexpr int SEL_LONG = 64;
 
 __global__ void k_sel_long(int64_t n, const int64_t* off, int32_t* longv, int64_t* ctl) {
@@ -3476,10 +3506,41 @@ __global__ void k_sel_long(int64_t n, const int64_t* off, int32_t* longv, int64_
         longv[atomicAdd((unsigned long long*)&ctl[3], 1ull)] = (int32_t)x;
 }
 
-// Every round kernel: blocks below nblk(n) take one vertex per thread
+__global__ void k_sel_spread(int64_t n, SelFwd f, const unsigned char* cov, const int32_t* gain,
+                             u64* best, unsigned char* lose, int64_t* ctl) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y == 0 && ctl[0] != 0) ctl[2] += 1;  // a round with vertices left
+    if (y >= n || ctl[0] == 0 || cov[y]) return;
+    u64 b = sel_key(gain, y);
+    int64_t j0, j1;
+    fwd_range(f, y, j0, j1);
+    for (int64_t j = j0; j < j1; ++j) {
+        const int32_t x = f.ids[j];
+        if (x >= 0 && x < n && !cov[x]) {
+            const u64 k = sel_key(gain, x);
+            b = k > b ? k : b;
+        }
+    }
+    best[y] = b;
+    lose[y] = 0;
+}
+
+__global__ void k_sel_mark(int64_t n, SelFwd f, const unsigned char* cov, const int32_t* gain,
+                           const u64* best, unsigned char* lose, const int64_t* ctl) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n || ctl[0] == 0 || cov[y]) return;
+    const u64 by = best[y];
+    if (by != sel_key(gain, y)) lose[y] = 1;
+    int64_t j0, j1;
+    fwd_range(f, y, j0, j1);
+    for (int64_t j = j0; j < j1; ++j) {
+        const int32_t x = f.ids[j];
+        if (x >= 0 && x < n && !cov[x] && by != sel_key(gain, x)) lose[x] = 1;
+    }
+}
+
+// Every apply item: blocks below nblk(n) take one vertex per thread
 // (skipping long lists), the blocks after them one long list per wavefront.
-// Returns the vertex and whether this lane works on a long list (lane l of
-// the list's wavefront reads entries l, l + 64, ...); x < 0: nothing to do.
 struct SelItem {
     int64_t x;
     bool wave;
@@ -3497,73 +3558,26 @@ __device__ __forceinline__ SelItem sel_item(int64_t n, const int64_t* off, const
     return {(int64_t)longv[w], true};
 }
 
-__global__ void k_sel_keys(int64_t n, const int64_t* off, const int32_t* ids,
-                           const unsigned char* cov, u64* key, u64* best, int64_t* ctl,
-                           const int32_t* longv, int64_t nlong) {
-    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl[0] != 0) ctl[2] += 1;  // a round with vertices left
-    if (ctl[0] == 0) return;
-    const SelItem it = sel_item(n, off, longv, nlong);
-    const int64_t x = it.x;
-    if (x < 0 || cov[x]) return;  // wavefront-uniform on the long path
-    int64_t g = 0;
-    const int64_t b = off[x], e = off[x + 1];
-    if (!it.wave) {
-        for (int64_t j = b; j < e; ++j) g += cov[ids[j]] ? 0 : 1;
-    } else {
-        for (int64_t j = b + lane_id(); j < e; j += WAVE) g += cov[ids[j]] ? 0 : 1;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) g += __shfl_xor(g, o);
-        if (lane_id() != 0) return;
+// a newly covered vertex z: one less gain for every x listing it
+__device__ __forceinline__ void sel_uncount(const SelFwd& f, int64_t n, int64_t z, int32_t* gain) {
+    int64_t j0, j1;
+    fwd_range(f, z, j0, j1);
+    for (int64_t j = j0; j < j1; ++j) {
+        const int32_t x = f.ids[j];
+        if (x >= 0 && x < n) atomicSub(&gain[x], 1);
     }
-    const u64 k = ((u64)g << 32) | (u64)(0xffffffffu - (unsigned)x);
-    key[x] = k;
-    best[x] = k;
-}
-
-__global__ void k_sel_spread(int64_t n, const int64_t* off, const int32_t* ids,
-                             const unsigned char* cov, const u64* key, u64* best,
-                             const int64_t* ctl, const int32_t* longv, int64_t nlong) {
-    if (ctl[0] == 0) return;
-    const SelItem it = sel_item(n, off, longv, nlong);
-    const int64_t x = it.x;
-    if (x < 0 || cov[x]) return;
-    const u64 k = key[x];
-    const int64_t st = it.wave ? lane_id() : 0, step = it.wave ? WAVE : 1;
-    for (int64_t j = off[x] + st; j < off[x + 1]; j += step) {
-        const int32_t y = ids[j];
-        if (!cov[y] && best[y] < k) atomicMax(&best[y], k);
-    }
-}
-
-__global__ void k_sel_pick(int64_t n, const int64_t* off, const int32_t* ids,
-                           const unsigned char* cov, const u64* key, const u64* best,
-                           unsigned char* sel, const int64_t* ctl, const int32_t* longv,
-                           int64_t nlong) {
-    if (ctl[0] == 0) return;
-    const SelItem it = sel_item(n, off, longv, nlong);
-    const int64_t x = it.x;
-    if (x < 0 || cov[x]) return;
-    const u64 k = key[x];
-    bool ok = best[x] == k;
-    const int64_t st = it.wave ? lane_id() : 0, step = it.wave ? WAVE : 1;
-    for (int64_t j = off[x] + st; j < off[x + 1] && ok; j += step) {
-        const int32_t y = ids[j];
-        if (!cov[y] && best[y] != k) ok = false;
-    }
-    if (it.wave) ok = __ballot(!ok) == 0ull;
-    if (!it.wave || lane_id() == 0) sel[x] = ok ? 1 : 0;
 }
 
 // the picks of the round take themselves and their uncovered followers; no
 // two picks share an uncovered follower and none is another's, so the
 // coverage each reads is the round's starting one where it matters
-__global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids,
-                            unsigned char* cov, unsigned char* sel, int32_t* pivot_of,
-                            int64_t* ctl, const int32_t* longv, int64_t nlong) {
+__global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids, SelFwd f,
+                            unsigned char* cov, const unsigned char* lose, int32_t* gain,
+                            int32_t* pivot_of, int64_t* ctl, const int32_t* longv, int64_t nlong) {
     if (ctl[0] == 0) return;
     const SelItem it = sel_item(n, off, longv, nlong);
     const int64_t x = it.x;
-    const bool pick = x >= 0 && sel[x];
+    const bool pick = x >= 0 && !cov[x] && !lose[x];
     int64_t taken = 0;
     if (pick) {
         const int64_t st = it.wave ? lane_id() : 0, step = it.wave ? WAVE : 1;
@@ -3572,6 +3586,7 @@ __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids,
             if (!cov[y]) {
                 pivot_of[y] = (int32_t)x;
                 cov[y] = 1;
+                sel_uncount(f, n, y, gain);
                 ++taken;
             }
         }
@@ -3580,9 +3595,9 @@ __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids,
     // once (its lane 0)
     const bool owner = pick && (!it.wave || lane_id() == 0);
     if (owner) {
-        sel[x] = 0;
         pivot_of[x] = -1;
         cov[x] = 1;
+        sel_uncount(f, n, x, gain);
         ++taken;
     }
     const u64 anyp = __ballot(pick);
@@ -3594,6 +3609,24 @@ __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids,
     if (lane_id() == __ffsll((long long)anyp) - 1) {
         atomicAdd((unsigned long long*)&ctl[0], (unsigned long long)(-t));
         atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)__popcll(own));
+    }
+}
+
+// forward lists of reverse lists given as CSR (the caller's R_k): a count per
+// vertex, then (after a scan into f_off) placement in any order
+__global__ void k_sel_fcount(int64_t n, const int64_t* off, const int32_t* ids, int32_t* cnt) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    for (int64_t j = off[x]; j < off[x + 1]; ++j) atomicAdd(&cnt[ids[j]], 1);
+}
+
+__global__ void k_sel_fplace(int64_t n, const int64_t* off, const int32_t* ids,
+                             const int64_t* f_off, int32_t* cur, int32_t* f_ids) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    for (int64_t j = off[x]; j < off[x + 1]; ++j) {
+        const int32_t y = ids[j];
+        f_ids[f_off[y] + atomicAdd(&cur[y], 1)] = (int32_t)x;
     }
 }
 
@@ -3614,30 +3647,42 @@ hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids,
     return hipGetLastError();
 }
 
-hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov,
-                              unsigned char* sel, int32_t* pivot_of, int32_t* longv, int64_t* ctl,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(k_sel_init, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, st, n, cov, sel,
-                       pivot_of, ctl);
+hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov, int32_t* gain,
+                              int32_t* pivot_of, int32_t* longv, int64_t* ctl, hipStream_t st) {
+    hipLaunchKernelGGL(k_sel_init, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, st, n, off, cov,
+                       gain, pivot_of, ctl);
     if (n > 0)
         hipLaunchKernelGGL(k_sel_long, dim3(nblk(n, 256)), dim3(256), 0, st, n, off, longv, ctl);
     return hipGetLastError();
 }
 
+hipError_t launch_select_forward(int64_t n, const int64_t* off, const int32_t* ids, int32_t* cnt,
+                                 int32_t* cur, int64_t* f_off, int32_t* f_ids, int64_t* scan_tmp,
+                                 hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipError_t e = launch_zero(cnt, sizeof(int32_t) * (size_t)n, st);
+    if (e == hipSuccess) e = launch_zero(cur, sizeof(int32_t) * (size_t)n, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sel_fcount, dim3(nblk(n, 256)), dim3(256), 0, st, n, off, ids, cnt);
+    if ((e = launch_scan(cnt, n, f_off, scan_tmp, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sel_fplace, dim3(nblk(n, 256)), dim3(256), 0, st, n, off, ids, f_off, cur,
+                       f_ids);
+    return hipGetLastError();
+}
+
 hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* ids,
-                                unsigned char* cov, unsigned char* sel, u64* key, u64* best,
+                                const int32_t* f_ids, const int64_t* f_off, int fk,
+                                unsigned char* cov, unsigned char* lose, int32_t* gain, u64* best,
                                 int32_t* pivot_of, int64_t* ctl, const int32_t* longv,
                                 int64_t nlong, int rounds, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const dim3 g(nblk(n, 256) + nblk(nlong * WAVE, 256)), b(256);
+    const SelFwd f = {f_ids, f_off, fk};
+    const dim3 gv(nblk(n, 256)), ga(nblk(n, 256) + nblk(nlong * WAVE, 256)), b(256);
     for (int r = 0; r < rounds; ++r) {
-        hipLaunchKernelGGL(k_sel_keys, g, b, 0, st, n, off, ids, cov, key, best, ctl, longv, nlong);
-        hipLaunchKernelGGL(k_sel_spread, g, b, 0, st, n, off, ids, cov, key, best, ctl, longv,
-                           nlong);
-        hipLaunchKernelGGL(k_sel_pick, g, b, 0, st, n, off, ids, cov, key, best, sel, ctl, longv,
-                           nlong);
-        hipLaunchKernelGGL(k_sel_apply, g, b, 0, st, n, off, ids, cov, sel, pivot_of, ctl, longv,
-                           nlong);
+        hipLaunchKernelGGL(k_sel_spread, gv, b, 0, st, n, f, cov, gain, best, lose, ctl);
+        hipLaunchKernelGGL(k_sel_mark, gv, b, 0, st, n, f, cov, gain, best, lose, ctl);
+        hipLaunchKernelGGL(k_sel_apply, ga, b, 0, st, n, off, ids, f, cov, lose, gain, pivot_of,
+                           ctl, longv, nlong);
     }
     return hipGetLastError();
 }
