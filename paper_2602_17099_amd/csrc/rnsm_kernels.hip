@@ -3456,7 +3456,8 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
 // key of y and of the uncovered x in F(y); mark, x loses when best[x] is not
 // its key or some uncovered y with x in F(y) has another best; apply, the
 // uncovered non-losers take their uncovered lists (a wavefront per list
-// longer than SEL_LONG). ctl[0]: uncovered vertices left (every kernel
+// longer than SEL_LONG), and a last pass takes the newly covered vertices
+// from the gains. ctl[0]: uncovered vertices left (every kernel
 // returns when 0), ctl[1]: pivots, ctl[2]: rounds run with vertices left,
 // ctl[3]: long lists.
 struct SelFwd {
@@ -3585,8 +3586,7 @@ __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids, S
             const int32_t y = ids[j];
             if (!cov[y]) {
                 pivot_of[y] = (int32_t)x;
-                cov[y] = 1;
-                sel_uncount(f, n, y, gain);
+                cov[y] = 2;  // newly covered: k_sel_uncount takes it from the gains
                 ++taken;
             }
         }
@@ -3596,8 +3596,7 @@ __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids, S
     const bool owner = pick && (!it.wave || lane_id() == 0);
     if (owner) {
         pivot_of[x] = -1;
-        cov[x] = 1;
-        sel_uncount(f, n, x, gain);
+        cov[x] = 2;
         ++taken;
     }
     const u64 anyp = __ballot(pick);
@@ -3610,6 +3609,15 @@ __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids, S
         atomicAdd((unsigned long long*)&ctl[0], (unsigned long long)(-t));
         atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)__popcll(own));
     }
+}
+
+// the round's newly covered vertices (cov 2), one thread each: one less gain
+// for every vertex listing it, then covered (cov 1)
+__global__ void k_sel_uncount(int64_t n, SelFwd f, unsigned char* cov, int32_t* gain) {
+    const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= n || cov[z] != 2) return;
+    sel_uncount(f, n, z, gain);
+    cov[z] = 1;
 }
 
 // forward lists of reverse lists given as CSR (the caller's R_k): a count per
@@ -3683,6 +3691,7 @@ hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* id
         hipLaunchKernelGGL(k_sel_mark, gv, b, 0, st, n, f, cov, gain, best, lose, ctl);
         hipLaunchKernelGGL(k_sel_apply, ga, b, 0, st, n, off, ids, f, cov, lose, gain, pivot_of,
                            ctl, longv, nlong);
+        hipLaunchKernelGGL(k_sel_uncount, gv, b, 0, st, n, f, cov, gain);
     }
     return hipGetLastError();
 }
