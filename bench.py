@@ -36,7 +36,92 @@ PEAK_HBM_GBS = 8000.0
 # line's traffic is null and its roofline falls back to algorithmic bytes.
 COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
-SEARCH_COUNTERS = {}
+SEARCH_COUNTERS = {
+    "fp32": {
+        "sources_sha256": "badb447ec90c7ec348f96088b8bc458566429670b82cf4902c9a9a872aedfb23",
+        "kernel": "k_beam_search<0, 1, 4, false, 3>",
+        "fetch_kib": [
+            28796563.438,
+            29690.062,
+            2568682.75,
+            107292.312,
+            5791900.938,
+            531358.375,
+            14746243.938,
+            1987979.375,
+            19460218.5,
+            18812010.625,
+            18493192.562,
+            11656004.438
+        ],
+        "write_kib": [
+            173959.5,
+            48.125,
+            19571.875,
+            193.125,
+            38870.0,
+            970.625,
+            77168.125,
+            3530.625,
+            74595.625,
+            32081.875,
+            46043.125,
+            19426.875
+        ]
+    },
+    "bf16": {
+        "sources_sha256": "badb447ec90c7ec348f96088b8bc458566429670b82cf4902c9a9a872aedfb23",
+        "kernel": "k_beam_search<1, 1, 4, false, 2>",
+        "fetch_kib": [
+            11050661.0,
+            3474.125,
+            187276.562,
+            8265.188,
+            358149.312,
+            20521.688,
+            900553.625,
+            63181.188,
+            1809459.25,
+            109902.375,
+            3082697.062,
+            190726.938,
+            3575524.812,
+            372752.688,
+            4530936.188,
+            839346.188,
+            5307769.625,
+            2654438.312,
+            5515956.875,
+            9339843.0,
+            979688.812,
+            1243561.438
+        ],
+        "write_kib": [
+            159409.125,
+            8.125,
+            4910.625,
+            25.0,
+            9851.875,
+            72.5,
+            19501.875,
+            247.5,
+            38840.0,
+            435.0,
+            38661.25,
+            775.625,
+            38301.25,
+            1491.25,
+            37578.75,
+            3314.375,
+            35752.5,
+            10318.125,
+            28744.375,
+            34956.25,
+            4106.25,
+            4607.5
+        ]
+    }
+}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
@@ -149,6 +234,79 @@ RECALL_EFS = (10, 16, 32, 64, 128)
 def recall_sweep(pkg, off, nb, entry, Xd, Qd, gt):
     """recall@10 (Section 2.1) of searches from the entry at each beam."""
     return {str(ef): recall_at_10(pkg, off, nb, entry, Xd, Qd, gt, ef=ef) for ef in RECALL_EFS}
+
+
+def slide_tradeoff(pkg, subs, Xd, Qd, gt, wl, steps=2):
+    """The local-sliding trade-off (Section 4.2: sliding saves about
+    (1 - |P|/|V|)(1 - ef_L/ef_N) of the naive search cost): RNSM with the
+    naive beam at L and sliding beams ef_L <= L, against the cross-query
+    merge (every source vertex a naive search) at beams up to L; each point
+    is whole-merge time and recall@10 (query beam 64). `equal_recall` names
+    the fastest RNSM point whose recall is within 0.002 of the cross-query
+    merge at L."""
+    import torch
+    L = wl["L"]
+    pts = []
+
+    def run(flags, ef_naive, ef_slide):
+        kw = dict(R=wl["R"], L=L, alpha=wl["alpha"], ef_naive=ef_naive, ef_slide=ef_slide,
+                  flags=flags, dists=False)
+        pkg.merge(subs, Xd, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            res = pkg.merge(subs, Xd, **kw)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        st = pkg.stats()
+        rec = recall_at_10(pkg, res[0], res[1], res[3], Xd, Qd, gt)
+        return {"ef_naive": ef_naive, "ef_slide": ef_slide, "ms_per_merge": 1000.0 * dt,
+                "recall_at_10": rec, "ndc": sum(st["ndc"]), "pivots": st["n_pivots"]}
+
+    for efs in sorted({16, 24, 32, 48, L}):
+        if efs <= L:
+            p = run(0, L, efs)
+            p["form"] = "rnsm"
+            pts.append(p)
+    for efn in sorted({32, 48, L}):
+        if efn <= L:
+            p = run(pkg.FLAG_ALL_PIVOTS, efn, efn)
+            p["form"] = "cross_query"
+            pts.append(p)
+    cm = [p for p in pts if p["form"] == "cross_query" and p["ef_naive"] == L][0]
+    ok = [p for p in pts if p["form"] == "rnsm" and p["recall_at_10"] >= cm["recall_at_10"] - 0.002]
+    best = min(ok, key=lambda p: p["ms_per_merge"]) if ok else None
+    return {"points": pts, "equal_recall": None if best is None else
+            {"rnsm": best, "cross_query": cm, "speedup": cm["ms_per_merge"] / best["ms_per_merge"]}}
+
+
+def prune_rules(pkg, subs, Xd, Qd, gt, wl, steps=2):
+    """The merge under each proximity-graph family's prune rule (Section 6's
+    applicability experiment): alpha (the headline rule), alpha = 1 (NSG's
+    MRNG), the SSG angle rule at 60 degrees and tau-MNG at tau = 5 (the angle
+    and tau rules on the float32 walk); whole-merge time and recall@10."""
+    import torch
+    out = {}
+    for name, kw in [("alpha_%g" % wl["alpha"], dict(alpha=wl["alpha"])),
+                     ("mrng_alpha_1", dict(alpha=1.0)),
+                     ("ssg_angle_60", dict(alpha=wl["alpha"], prune_rule=pkg.PRUNE_ANGLE,
+                                           prune_param=60.0)),
+                     ("tau_mng_5", dict(alpha=wl["alpha"], prune_rule=pkg.PRUNE_TAU,
+                                        prune_param=5.0))]:
+        args = dict(R=wl["R"], L=wl["L"], dists=False, **kw)
+        pkg.merge(subs, Xd, **args)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            res = pkg.merge(subs, Xd, **args)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        st = pkg.stats()
+        out[name] = {"ms_per_merge": 1000.0 * dt, "prune_ms": st["ms_prune"],
+                     "prune_path": st["prune_path"],
+                     "recall_at_10": recall_at_10(pkg, res[0], res[1], res[3], Xd, Qd, gt),
+                     "mean_degree": float(res[0][-1].item()) / Xd.shape[0]}
+    return out
 
 
 def rebuild_baseline(pkg, Xd, Qd, gt, wl):
@@ -404,34 +562,56 @@ def precision768(pkg, scale, steps, warmup):
     out = {"workload": f"4 random-split sub-indexes, {N:,} L2-normalised vectors, dim 768 "
                        f"(scale 1/sqrt(i)), cosine, R=48, L=96, alpha=1.2, MOS degree 2",
            "scale_of_4M": scale, "steps": steps, "warmup": warmup}
-    for name, search in [("fp32", None), ("bf16", pkg.convert(Xd, torch.bfloat16))]:
-        kw = dict(R=48, L=96, alpha=1.2, metric=COS, mos_degree=2, search=search,
-                  out=(torch.empty(N + 1, dtype=torch.int64, device=dev),
-                       torch.empty(N * 48, dtype=torch.int32, device=dev),
-                       torch.empty(N * 48, dtype=torch.float32, device=dev)))
+    bufs = (torch.empty(N + 1, dtype=torch.int64, device=dev),
+            torch.empty(N * 48, dtype=torch.int32, device=dev),
+            torch.empty(N * 48, dtype=torch.float32, device=dev))
+
+    def timed(search, L, reps):
+        kw = dict(R=48, L=L, alpha=1.2, metric=COS, mos_degree=2, search=search, out=bufs)
         for _ in range(warmup):
             pkg.merge(subs, Xd, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(reps):
             off, nb, _, entry = pkg.merge(subs, Xd, **kw)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
+        dt = (time.perf_counter() - t0) / reps
         st = pkg.stats()
         ids, _ = pkg.search(off, nb, entry, Xd, Qd, 96, 10, metric=COS)
         rec = (ids.to(torch.int64)[:, :, None] == gt.to(torch.int64)[:, None, :]).any(2)
+        return dt, st, rec.sum().item() / (10 * Qd.shape[0])
+
+    Xb = pkg.convert(Xd, torch.bfloat16)
+    for name, search in [("fp32", None), ("bf16", Xb)]:
+        dt, st, rec = timed(search, 96, steps)
         out[name] = {"ms_per_merge": 1000.0 * dt, "value": st["n_source_vertices"] / dt,
                      "unit": "merged vertices/s", "operations": st["n_ops"],
                      "source_vertices": st["n_source_vertices"],
-                     "recall_at_10": rec.sum().item() / (10 * Qd.shape[0]),
+                     "recall_at_10": rec,
                      "prune_path": st["prune_path"],
                      "phase_ms": {"expansion_search": st["ms_search"][0],
                                   "naive_search": st["ms_search"][1],
                                   "sliding_search": st["ms_search"][2],
                                   "prune_and_reverse": st["ms_prune"], "total": st["ms_total"]}}
         log(f"precision {name}: {out[name]}")
-        del off, nb
     out["bf16_speedup"] = out["bf16"]["value"] / out["fp32"]["value"]
+    # equal recall: the bfloat16 form's beam L swept around the float32
+    # form's 96; the smallest L whose recall is within 0.002 of float32's
+    target = out["fp32"]["recall_at_10"] - 0.002
+    sweep = {}
+    for L in (80, 88, 96, 104, 112, 128):
+        if L == 96:
+            sweep[L] = (out["bf16"]["ms_per_merge"], out["bf16"]["recall_at_10"])
+            continue
+        dt, _, rec = timed(Xb, L, max(1, steps - 1))
+        sweep[L] = (1000.0 * dt, rec)
+    ok = [L for L in sorted(sweep) if sweep[L][1] >= target]
+    Lq = ok[0] if ok else None
+    out["bf16_equal_recall"] = {
+        "sweep": {str(L): {"ms_per_merge": v[0], "recall_at_10": v[1]} for L, v in sweep.items()},
+        "L": Lq,
+        "speedup_vs_fp32": None if Lq is None else out["fp32"]["ms_per_merge"] / sweep[Lq][0]}
+    log(f"precision bf16 equal recall: {out['bf16_equal_recall']}")
     return out
 
 
@@ -507,7 +687,7 @@ def cpu_baseline(wl):
     else:
         X = inputs.tiny_int(2 * n, wl["dim"], seed=inputs.SEED_BASE + 1)
     subs = [O.build_graph(X[i * n:(i + 1) * n], wl["K"], wl["R"], alpha=wl["build_alpha"],
-                          reverse=wl["reverse"], alpha_rev=1.2) for i in range(2)]
+                          reverse=wl["reverse"], alpha_rev=1.2, repair=True) for i in range(2)]
     cores = host_cores()
     times = {}
     prev = O.get_threads()
@@ -555,6 +735,10 @@ def main():
     ap.add_argument("--one-stream", action="store_true",
                     help="every search launch alone on one stream for the whole run (for "
                          "profiles and counters: kernel times are then exclusive)")
+    ap.add_argument("--no-rules", action="store_true",
+                    help="skip the merges under the other proximity-graph prune rules")
+    ap.add_argument("--no-slide-sweep", action="store_true",
+                    help="skip the sliding-beam sweep against the cross-query merge")
     ap.add_argument("--no-rebuild", action="store_true",
                     help="skip the rebuild baseline (the builder on the union) and its recall")
     ap.add_argument("--no-batched", action="store_true",
@@ -658,6 +842,10 @@ def main():
         graphs["merged_recall_at_10_by_ef"] = recall_sweep(pkg, off, nb, entry, Xd, Qd, gt)
         if not args.no_rebuild:
             graphs["rebuild"] = rebuild_baseline(pkg, Xd, Qd, gt, wl)
+        if not args.no_slide_sweep:
+            graphs["slide_tradeoff"] = slide_tradeoff(pkg, subs, Xd, Qd, gt, wl)
+        if not args.no_rules:
+            graphs["prune_rules"] = prune_rules(pkg, subs, Xd, Qd, gt, wl)
     log(f"graphs: {graphs}")
 
     bf16 = None

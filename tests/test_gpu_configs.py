@@ -122,3 +122,90 @@ def test_uint8_many_subindexes_float16_search(dev, orc, pkg):
     assert np.array_equal(off.cpu().numpy(), ref["offsets"])
     assert np.array_equal(nb.cpu().numpy(), ref["nbrs"])
     assert np.array_equal(ds.cpu().numpy().astype(np.float64), ref["dists"])
+
+
+def test_inner_product_ten_subindexes_100k(dev, orc, pkg):
+    # the ten-sub-index inner-product workload's shape at 1/100 of its
+    # 10,000,000 vectors: log-uniform sizes summing to 100,000, 256-component
+    # L2-normalised 96-d mixture in slabs along a seeded direction, exact
+    # 64-NN sub-indexes pruned to R = 32 with reverse edges and the
+    # reachability repair, MOS degree 4 on centroid costs, R=32, L=64: the
+    # float precision contract against the oracle, and the batched form
+    # equal to the plain one
+    sizes = inputs.uneven_sizes(10, 1000, 40000, 100_000, seed=1501)
+    X = inputs.mixture_unit(100_000, 96, comps=256, seed=1502)
+    X = np.ascontiguousarray(X[inputs.slab_order(X, 1503)])
+    Q = inputs.mixture_unit(1000, 96, comps=256, seed=1502, stream=1)
+    subs, b = [], 0
+    for n in sizes:
+        subs.append(orc.build_graph(X[b:b + n], 64, 32, alpha=1.2, metric=1, reverse=True,
+                                    repair=True))
+        b += n
+    ref = orc.merge(subs, X, R=32, L=64, alpha=1.2, metric=1, mos_degree=4, use_centroids=True)
+    Xd = _t(X, dev)
+    got = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2, metric=1, mos_degree=4, flags=2)
+    st = pkg.stats()
+    assert st["n_ops"] == len(ref["ops"])
+    frac, r_gpu, r_ref = _float_checks(orc, got, ref, X, Q, 1, 64)
+    print(f"[ip 100k] ops {st['n_ops']}, edge overlap {frac:.5f}, recall {r_gpu:.4f} vs "
+          f"{r_ref:.4f}")
+    bat = pkg.merge(_dsubs(subs, dev), Xd, R=32, L=64, alpha=1.2, metric=1, mos_degree=4,
+                    flags=2 | pkg.FLAG_BATCHED)
+    assert pkg.stats()["n_rounds"] < st["n_ops"]
+    for a, c in zip(got[:3], bat[:3]):
+        assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
+    assert got[3] == bat[3]
+
+
+def _sha(*arrays):
+    import hashlib
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def test_paper_scale_replica_bit_exact(dev, pkg):
+    # the 100,000,000-vector uint8 workload at 1/100 scale: 50 Dirichlet-sized
+    # sub-indexes, uint8 rows converted on the device to float32 and a
+    # float16 search copy, MOS degree bound 8. The oracle's merge of the
+    # same replica is stored as digests (tests/golden, written by a script
+    # that runs only the oracle): the sub-indexes built here must be the
+    # oracle's inputs byte for byte, and the merged graph the oracle's
+    import json
+    import os
+    import torch
+    from paper_2602_17099_amd.prepare import knn_l2_exact
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_scale_replica.json")
+    gold = json.load(open(path))
+    sizes = gold["sizes"]
+    U = inputs.paper_scale_u8(sum(sizes))
+    assert _sha(U) == gold["inputs_sha256"]
+    Ud = _t(U, dev)
+    Xd = pkg.convert(Ud, torch.float32)
+    H = pkg.convert(Ud, torch.float16)
+    del U
+    subs, b = [], 0
+    for i, n in enumerate(sizes):
+        Xi = Xd[b:b + n]
+        knn = knn_l2_exact(Xi, None, gold["K"], exclude_self=True)
+        off, nb, e = pkg.build_graph(Xi, knn, gold["R"], alpha=gold["alpha"], reverse=True,
+                                     alpha_rev=gold["alpha"], repair=True)
+        del knn
+        assert _sha(off.cpu().numpy(), nb.cpu().numpy(), np.array([e], np.int32)) == \
+            gold["subindex_sha256"][i], f"sub-index {i} differs from the oracle's input"
+        subs.append((off, nb, e))
+        b += n
+    off, nb, ds, entry = pkg.merge(subs, Xd, R=gold["R"], L=gold["L"], alpha=gold["alpha"],
+                                   mos_degree=gold["mos_degree"], search=H)
+    st = pkg.stats()
+    assert st["n_ops"] == gold["n_ops"] and entry == gold["entry"]
+    off, nb, ds = off.cpu().numpy(), nb.cpu().numpy(), ds.cpu().numpy()
+    assert int(off[-1]) == gold["n_edges"]
+    for v, row in gold["sample_rows"].items():
+        v = int(v)
+        assert nb[off[v]:off[v + 1]].tolist() == row, v
+    assert _sha(off.astype(np.int64), nb.astype(np.int32), ds.astype(np.float64)) == \
+        gold["merged_sha256"]
+    print(f"[paper-scale replica] {st['n_ops']} operations, {gold['n_edges']} edges, "
+          f"{st['ms_total']:.1f} ms merge, bit-exact")
