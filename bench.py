@@ -38,24 +38,24 @@ COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
     "fp32": {
-        "sources_sha256": "badb447ec90c7ec348f96088b8bc458566429670b82cf4902c9a9a872aedfb23",
+        "sources_sha256": "6f20ea4ca54ce02a1b6a0f6d99f856ea638f100f0f182a7141f289b2fe236e6a",
         "kernel": "k_beam_search<0, 1, 4, false, 3>",
         "fetch_kib": [
-            28796563.438,
-            29690.062,
-            2568682.75,
-            107292.312,
-            5791900.938,
-            531358.375,
-            14746243.938,
-            1987979.375,
-            19460218.5,
-            18812010.625,
-            18493192.562,
-            11656004.438
+            28797917.375,
+            29826.125,
+            2489685.188,
+            108371.0,
+            6072374.125,
+            532023.312,
+            14981643.625,
+            1993439.875,
+            19848900.312,
+            18832093.562,
+            18548213.312,
+            11642208.938
         ],
         "write_kib": [
-            173959.5,
+            173846.188,
             48.125,
             19571.875,
             193.125,
@@ -70,34 +70,34 @@ SEARCH_COUNTERS = {
         ]
     },
     "bf16": {
-        "sources_sha256": "badb447ec90c7ec348f96088b8bc458566429670b82cf4902c9a9a872aedfb23",
+        "sources_sha256": "6f20ea4ca54ce02a1b6a0f6d99f856ea638f100f0f182a7141f289b2fe236e6a",
         "kernel": "k_beam_search<1, 1, 4, false, 2>",
         "fetch_kib": [
-            11050661.0,
-            3474.125,
-            187276.562,
-            8265.188,
-            358149.312,
-            20521.688,
-            900553.625,
-            63181.188,
-            1809459.25,
-            109902.375,
-            3082697.062,
-            190726.938,
-            3575524.812,
-            372752.688,
-            4530936.188,
-            839346.188,
-            5307769.625,
-            2654438.312,
-            5515956.875,
-            9339843.0,
-            979688.812,
-            1243561.438
+            11036055.688,
+            3496.75,
+            184749.688,
+            8335.062,
+            370508.062,
+            20351.312,
+            919289.562,
+            62201.125,
+            1733613.688,
+            108642.875,
+            3032567.438,
+            189421.25,
+            3501458.938,
+            372161.312,
+            4517531.812,
+            834351.875,
+            5217246.125,
+            2640640.812,
+            5470913.5,
+            9307221.938,
+            979381.0,
+            1241965.812
         ],
         "write_kib": [
-            159409.125,
+            159445.719,
             8.125,
             4910.625,
             25.0,
