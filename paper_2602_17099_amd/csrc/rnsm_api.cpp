@@ -500,9 +500,9 @@ static rnsm_status rnsm_select_pivots_impl(int64_t n, const int64_t* rk_offsets,
 // pivot_of receives -1 for pivots, else the pivot. Workspace buffers; the
 // caller holds g_lock.
 static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off,
-                                    const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
-                                    int fk, int32_t* pivot_of, hipStream_t st, int64_t* n_pivots,
-                                    int batch = 8, int64_t* rounds = nullptr) {
+                                    const int32_t* ids, int64_t nnz_bound, const int32_t* f_ids,
+                                    const int64_t* f_off, int fk, int32_t* pivot_of, hipStream_t st,
+                                    int64_t* n_pivots, int batch = 8, int64_t* rounds = nullptr) {
     unsigned char *cov, *lose;
     int32_t* gain;
     u64* best;
@@ -513,13 +513,15 @@ static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off
     WS(best, "sel_best", sizeof(u64) * n);
     WS(ctl, "sel_ctl", sizeof(int64_t) * 4);
     HS(h_ctl, "h_sel_ctl", sizeof(int64_t) * 4);
-    int32_t* longv;
-    WS(longv, "sel_long", sizeof(int32_t) * std::max<int64_t>(n, 1));
+    // chunks of the long lists: at most one per vertex plus one per 256 entries
+    const int64_t lcap = n + nnz_bound / 256 + 1;
+    int64_t* longv;
+    WS(longv, "sel_long", sizeof(int64_t) * lcap);
     HIPCHK(launch_select_init(n, off, cov, gain, pivot_of, longv, ctl, st));
     HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const int64_t nlong = h_ctl[3];
-    if (nlong < 0 || nlong > n) return fail(RNSM_EINTERNAL, "pivot selection: bad long-list count");
+    if (nlong < 0 || nlong > lcap) return fail(RNSM_EINTERNAL, "pivot selection: bad long-list count");
     // every round covers at least the vertex with the largest key
     for (int64_t done = 0; done <= n + batch; done += batch) {
         HIPCHK(launch_select_rounds(n, off, ids, f_ids, f_off, fk, cov, lose, gain, best, pivot_of,
@@ -572,7 +574,7 @@ static rnsm_status rnsm_select_pivots_device_impl(int64_t n, const int64_t* rk_o
     WS(f_ids, "sel_fids", sizeof(int32_t) * std::max<int64_t>(nnz, 1));
     WS(stmp, "sel_scan", sizeof(int64_t) * scan_tmp_elems(n));
     HIPCHK(launch_select_forward(n, rk_offsets, rk_ids, fcnt, fcur, f_off, f_ids, stmp, st));
-    return select_on_device(ws, n, rk_offsets, rk_ids, f_ids, f_off, 0, pivot_of, st,
+    return select_on_device(ws, n, rk_offsets, rk_ids, nnz, f_ids, f_off, 0, pivot_of, st,
                             out_n_pivots);
 }
 
@@ -979,6 +981,43 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
             std::vector<int> rops;
             for (int oi = 0; oi < nops; ++oi)
                 if (round_of[oi] == rr) rops.push_back(oi);
+            // ---- the round's untouched targets: their rows' distances (the
+            // target prunes read them) on the side stream, beside the
+            // selection's small kernels
+            int ev_rd = -1;
+            {
+                int ev_go = -1;
+                for (int oi : rops) {
+                    const int t = ops[oi].second;
+                    if (touched[t]) continue;
+                    if (ev_go < 0) {
+                        HIPCHK(E.record(st, &ev_go));
+                        HIPCHK(hipStreamWaitEvent(sd, E.ev[ev_go], 0));
+                    }
+                    PruneArgs rd = {};
+                    rd.X = vecs->f32;
+                    rd.xb = xb16;
+                    rd.n_total = N;
+                    rd.nch = vi.nch32;
+                    rd.G = vi.G32;
+                    rd.lgG = ilog2i(vi.G32);
+                    rd.cpl = vi.cpl32;
+                    rd.metric = p->metric;
+                    rd.norms = norms;
+                    rd.n_items = sizes[t];
+                    rd.item_base = bases[t];
+                    rd.rows_in = rows;
+                    rd.deg_in = deg;
+                    rd.rows_d = rdist;
+                    rd.R = R;
+                    rd.wcap = TARGET_WCAP;
+                    rd.err = errf;
+                    rd.band = band;
+                    rd.rechecks = rechecks;
+                    HIPCHK(launch_row_dists(rd, prune_reads_b16(rd, pmode), sd));
+                }
+                if (ev_go >= 0) HIPCHK(E.record(sd, &ev_rd));
+            }
             // ---- sources of the round: expansion, inversion, selection, groups
             int ev_novf = -1;
             for (int oi : rops) {
@@ -1065,8 +1104,9 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                     g_stats.launches[0] += 1;
                     int64_t nrs = 0;
                     HIPCHK(E.stat(st, &ev_sel0));
-                    const rnsm_status ss = select_on_device(ws, ns, rk_off, rk_ids, nk, nullptr, k,
-                                                            pivot_of, st, &np, select_batch, &nrs);
+                    const rnsm_status ss = select_on_device(ws, ns, rk_off, rk_ids, ns * k, nk,
+                                                            nullptr, k, pivot_of, st, &np,
+                                                            select_batch, &nrs);
                     if (ss != RNSM_OK) return ss;
                     g_stats.select_rounds += nrs;
                 }
@@ -1232,6 +1272,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
             g_stats.search_hash_bits = hb_max;
             g_stats.search_waves_per_block = wpb_min;
             // ---- the round's prunes and reverse edges, operation by operation
+            if (ev_rd >= 0) HIPCHK(hipStreamWaitEvent(st, E.ev[ev_rd], 0));
             for (size_t q = 0; q < rops.size(); ++q) {
                 const int oi = rops[q];
                 const int s = ops[oi].first, t = ops[oi].second;
@@ -1272,14 +1313,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                 qs.err = errf;
                 qs.band = band;
                 qs.rechecks = rechecks;
-                if (!touched[t]) {
-                    PruneArgs rd = qs;
-                    rd.n_items = nt;
-                    rd.item_base = bases[t];
-                    rd.extra_mode = 0;
-                    rd.wcap = TARGET_WCAP;
-                    HIPCHK(launch_row_dists(rd, prune_reads_b16(rd, pmode), st));
-                }
+                // (the untouched targets' row distances came from the side stream)
                 int32_t *rc, *rcur, *rev;
                 int64_t *roff, *stmp2;
                 u64* scratch;

@@ -177,8 +177,9 @@ hipError_t launch_fill32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // the pivot's id
 hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids, int* flag,
                               hipStream_t st);
+// longv: chunks of the long lists, at least n + off[n] / 256 + 1 entries
 hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov, int32_t* gain,
-                              int32_t* pivot_of, int32_t* longv, int64_t* ctl, hipStream_t st);
+                              int32_t* pivot_of, int64_t* longv, int64_t* ctl, hipStream_t st);
 // forward lists F(y) = {x : y in R_k(x)} of CSR reverse lists (off, ids):
 // cnt, cur n words of scratch, f_off n + 1, f_ids off[n]
 hipError_t launch_select_forward(int64_t n, const int64_t* off, const int32_t* ids, int32_t* cnt,
@@ -190,7 +191,7 @@ hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* id
                                 const int32_t* f_ids, const int64_t* f_off, int fk,
                                 unsigned char* cov, unsigned char* lose, int32_t* gain,
                                 unsigned long long* best, int32_t* pivot_of, int64_t* ctl,
-                                const int32_t* longv, int64_t nlong, int rounds, hipStream_t st);
+                                const int64_t* longv, int64_t nlong, int rounds, hipStream_t st);
 // static device scratch of the allocation-free search (bytes per device) and
 // its address on the current device (looked up once per device)
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;

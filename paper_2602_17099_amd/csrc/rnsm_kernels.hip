@@ -3497,14 +3497,20 @@ __global__ void k_sel_init(int64_t n, const int64_t* rk_off, unsigned char* cov,
 }
 
 // Lists longer than SEL_LONG (a hub can be in thousands of k-NN lists) are
-// taken by a whole wavefront each in the apply step; the rest by one thread
-// per vertex. The long ones are listed once per selection (any order).
+// taken in the apply step by wavefronts, one per SEL_CHUNK entries of the
+// list; the rest by one thread per vertex. The chunks of the long lists are
+// listed once per selection (any order) as (vertex << 32 | chunk).
 constexpr int SEL_LONG = 64;
+constexpr int SEL_CHUNK = 256;
 
-__global__ void k_sel_long(int64_t n, const int64_t* off, int32_t* longv, int64_t* ctl) {
+__global__ void k_sel_long(int64_t n, const int64_t* off, int64_t* longv, int64_t* ctl) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x < n && off[x + 1] - off[x] > SEL_LONG)
-        longv[atomicAdd((unsigned long long*)&ctl[3], 1ull)] = (int32_t)x;
+    if (x >= n) return;
+    const int64_t len = off[x + 1] - off[x];
+    if (len <= SEL_LONG) return;
+    const int64_t nc = (len + SEL_CHUNK - 1) / SEL_CHUNK;
+    const int64_t b = (int64_t)atomicAdd((unsigned long long*)&ctl[3], (unsigned long long)nc);
+    for (int64_t c = 0; c < nc; ++c) longv[b + c] = (x << 32) | c;
 }
 
 __global__ void k_sel_spread(int64_t n, SelFwd f, const unsigned char* cov, const int32_t* gain,
@@ -3541,22 +3547,29 @@ __global__ void k_sel_mark(int64_t n, SelFwd f, const unsigned char* cov, const 
 }
 
 // Every apply item: blocks below nblk(n) take one vertex per thread
-// (skipping long lists), the blocks after them one long list per wavefront.
+// (skipping long lists), the blocks after them one chunk of a long list per
+// wavefront (lane l reads entries l, l + 64, ... of the chunk). x < 0:
+// nothing to do; [j0, j1) the entries; first: the item that owns x's own
+// change (its thread, or the first chunk's lane 0).
 struct SelItem {
-    int64_t x;
-    bool wave;
+    int64_t x, j0, j1;
+    bool wave, first;
 };
-__device__ __forceinline__ SelItem sel_item(int64_t n, const int64_t* off, const int32_t* longv,
+__device__ __forceinline__ SelItem sel_item(int64_t n, const int64_t* off, const int64_t* longv,
                                             int64_t nlong) {
     const int64_t nbs = (n + 255) / 256;
     if ((int64_t)blockIdx.x < nbs) {
         const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (x >= n || off[x + 1] - off[x] > SEL_LONG) return {-1, false};
-        return {x, false};
+        if (x >= n || off[x + 1] - off[x] > SEL_LONG) return {-1, 0, 0, false, false};
+        return {x, off[x], off[x + 1], false, true};
     }
     const int64_t w = (((int64_t)blockIdx.x - nbs) * blockDim.x + threadIdx.x) >> 6;
-    if (w >= nlong) return {-1, true};
-    return {(int64_t)longv[w], true};
+    if (w >= nlong) return {-1, 0, 0, true, false};
+    const int64_t it = longv[w];
+    const int64_t x = it >> 32, c = it & 0xffffffffll;
+    const int64_t j0 = off[x] + c * SEL_CHUNK;
+    const int64_t j1 = min(off[x + 1], j0 + SEL_CHUNK);
+    return {x, j0 + lane_id(), j1, true, c == 0 && lane_id() == 0};
 }
 
 // a newly covered vertex z: one less gain for every x listing it
@@ -3574,15 +3587,17 @@ __device__ __forceinline__ void sel_uncount(const SelFwd& f, int64_t n, int64_t 
 // coverage each reads is the round's starting one where it matters
 __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids, SelFwd f,
                             unsigned char* cov, const unsigned char* lose, int32_t* gain,
-                            int32_t* pivot_of, int64_t* ctl, const int32_t* longv, int64_t nlong) {
+                            int32_t* pivot_of, int64_t* ctl, const int64_t* longv, int64_t nlong) {
     if (ctl[0] == 0) return;
     const SelItem it = sel_item(n, off, longv, nlong);
     const int64_t x = it.x;
-    const bool pick = x >= 0 && !cov[x] && !lose[x];
+    // a pick's own cov byte is changed only by its owner item, after this
+    // kernel's other items have read it (x is not another pick's follower)
+    const bool pick = x >= 0 && cov[x] != 1 && !lose[x] && (cov[x] == 0 || !it.first);
     int64_t taken = 0;
     if (pick) {
-        const int64_t st = it.wave ? lane_id() : 0, step = it.wave ? WAVE : 1;
-        for (int64_t j = off[x] + st; j < off[x + 1]; j += step) {
+        const int64_t step = it.wave ? WAVE : 1;
+        for (int64_t j = it.j0; j < it.j1; j += step) {
             const int32_t y = ids[j];
             if (!cov[y]) {
                 pivot_of[y] = (int32_t)x;
@@ -3592,8 +3607,8 @@ __global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids, S
         }
     }
     // the wavefront's counts in one atomic each; a long list's pick counts
-    // once (its lane 0)
-    const bool owner = pick && (!it.wave || lane_id() == 0);
+    // once (its first chunk's lane 0)
+    const bool owner = pick && it.first;
     if (owner) {
         pivot_of[x] = -1;
         cov[x] = 2;
@@ -3656,7 +3671,7 @@ hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids,
 }
 
 hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov, int32_t* gain,
-                              int32_t* pivot_of, int32_t* longv, int64_t* ctl, hipStream_t st) {
+                              int32_t* pivot_of, int64_t* longv, int64_t* ctl, hipStream_t st) {
     hipLaunchKernelGGL(k_sel_init, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, st, n, off, cov,
                        gain, pivot_of, ctl);
     if (n > 0)
@@ -3681,7 +3696,7 @@ hipError_t launch_select_forward(int64_t n, const int64_t* off, const int32_t* i
 hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* ids,
                                 const int32_t* f_ids, const int64_t* f_off, int fk,
                                 unsigned char* cov, unsigned char* lose, int32_t* gain, u64* best,
-                                int32_t* pivot_of, int64_t* ctl, const int32_t* longv,
+                                int32_t* pivot_of, int64_t* ctl, const int64_t* longv,
                                 int64_t nlong, int rounds, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const SelFwd f = {f_ids, f_off, fk};
