@@ -505,34 +505,40 @@ static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off
                                     int64_t* n_pivots, int batch = 8, int64_t* rounds = nullptr) {
     unsigned char *cov, *lose;
     int32_t* gain;
-    u64* best;
     int64_t *ctl, *h_ctl;
     WS(cov, "sel_cov", n);
     WS(lose, "sel_lose", n);
     WS(gain, "sel_gain", sizeof(int32_t) * n);
-    WS(best, "sel_best", sizeof(u64) * n);
-    WS(ctl, "sel_ctl", sizeof(int64_t) * 4);
-    HS(h_ctl, "h_sel_ctl", sizeof(int64_t) * 4);
-    // chunks of the long lists: at most one per vertex plus one per 256 entries
-    const int64_t lcap = n + nnz_bound / 256 + 1;
-    int64_t* longv;
-    WS(longv, "sel_long", sizeof(int64_t) * lcap);
-    HIPCHK(launch_select_init(n, off, cov, gain, pivot_of, longv, ctl, st));
-    HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    const int64_t nlong = h_ctl[3];
-    if (nlong < 0 || nlong > lcap) return fail(RNSM_EINTERNAL, "pivot selection: bad long-list count");
-    // every round covers at least the vertex with the largest key
+    WS(ctl, "sel_ctl", sizeof(int64_t) * 8);
+    HS(h_ctl, "h_sel_ctl", sizeof(int64_t) * 8);
+    int32_t *act_a, *act_b;
+    WS(act_a, "sel_act_a", sizeof(int32_t) * std::max<int64_t>(n, 1));
+    WS(act_b, "sel_act_b", sizeof(int32_t) * std::max<int64_t>(n, 1));
+    // a round's items: every pick's list in chunks of 16 entries
+    int64_t* items;
+    WS(items, "sel_items", sizeof(int64_t) * (n + nnz_bound / 16 + 1));
+    HIPCHK(launch_select_init(n, off, cov, lose, gain, pivot_of, ctl, st));
+    // every round with uncovered vertices picks at least the one with the
+    // largest key; after each check batch the rounds run over the vertices
+    // still uncovered only
+    const int32_t* act = nullptr;
+    int64_t nact = n;
     for (int64_t done = 0; done <= n + batch; done += batch) {
-        HIPCHK(launch_select_rounds(n, off, ids, f_ids, f_off, fk, cov, lose, gain, best, pivot_of,
-                                    ctl, longv, nlong, batch, st));
-        HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, st));
+        HIPCHK(launch_select_rounds(n, act, nact, off, ids, f_ids, f_off, fk, cov, lose, gain,
+                                    pivot_of, items, ctl, batch, st));
+        int32_t* act_next = act == act_a ? act_b : act_a;
+        HIPCHK(launch_select_compact(act, nact, cov, act_next, ctl, st));
+        HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (h_ctl[0] == 0) {
+        if (h_ctl[4] == 0) {
             *n_pivots = h_ctl[1];
             if (rounds) *rounds = h_ctl[2];
             return RNSM_OK;
         }
+        if (h_ctl[0] == 0 || h_ctl[4] < 0 || h_ctl[4] > nact)
+            return fail(RNSM_EINTERNAL, "pivot selection: inconsistent active counts");
+        act = act_next;
+        nact = h_ctl[4];
     }
     return fail(RNSM_EINTERNAL, "pivot selection did not cover every vertex");
 }
@@ -982,10 +988,14 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
             for (int oi = 0; oi < nops; ++oi)
                 if (round_of[oi] == rr) rops.push_back(oi);
             // ---- the round's untouched targets: their rows' distances (the
-            // target prunes read them) on the side stream, beside the
-            // selection's small kernels
+            // target prunes read them) on the side stream, queued once the
+            // round's first expansion search is (so that they run beside the
+            // selection's small kernels, not against the search)
             int ev_rd = -1;
-            {
+            bool rd_queued = false;
+            auto queue_row_dists = [&]() -> rnsm_status {
+                if (rd_queued) return RNSM_OK;
+                rd_queued = true;
                 int ev_go = -1;
                 for (int oi : rops) {
                     const int t = ops[oi].second;
@@ -1017,7 +1027,8 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                     HIPCHK(launch_row_dists(rd, prune_reads_b16(rd, pmode), sd));
                 }
                 if (ev_go >= 0) HIPCHK(E.record(sd, &ev_rd));
-            }
+                return RNSM_OK;
+            };
             // ---- sources of the round: expansion, inversion, selection, groups
             int ev_novf = -1;
             for (int oi : rops) {
@@ -1102,6 +1113,7 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                     ev_exp.push_back(ex);
                     g_stats.queries[0] += ns;
                     g_stats.launches[0] += 1;
+                    if ((rs = queue_row_dists()) != RNSM_OK) return rs;
                     int64_t nrs = 0;
                     HIPCHK(E.stat(st, &ev_sel0));
                     const rnsm_status ss = select_on_device(ws, ns, rk_off, rk_ids, ns * k, nk,
@@ -1133,6 +1145,10 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                 src_np[s] = np;
                 src_nf[s] = ns - np;
                 prepared[s] = 1;
+            }
+            {  // (a round whose sources were all prepared earlier)
+                const rnsm_status rs = queue_row_dists();
+                if (rs != RNSM_OK) return rs;
             }
             // ---- one persistent search over the round's pivot groups
             std::vector<GroupOp> gops;

@@ -172,26 +172,31 @@ hipError_t launch_group_overflow(int64_t n_groups, int64_t nf, const int32_t* gp
                                  int32_t* ofl, int32_t* oflp, int64_t* scan_tmp, hipStream_t st);
 hipError_t launch_fill32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // pivot selection on the device (the lazy greedy in parallel rounds, the same
-// pivots and groups): init, then `rounds` rounds (each a no-op once ctl[0],
-// the uncovered count, is 0); ctl[1] counts pivots. pivot_of: -1 pivot, else
-// the pivot's id
+// pivots and groups): init, then rounds (each a no-op once ctl[0] is 0: a
+// round picked nothing); ctl[1] counts pivots, ctl[2] rounds with picks.
+// pivot_of: -1 pivot, else the pivot's id
 hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids, int* flag,
                               hipStream_t st);
-// longv: chunks of the long lists, at least n + off[n] / 256 + 1 entries
-hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov, int32_t* gain,
-                              int32_t* pivot_of, int64_t* longv, int64_t* ctl, hipStream_t st);
+hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov,
+                              unsigned char* lose, int32_t* gain, int32_t* pivot_of, int64_t* ctl,
+                              hipStream_t st);
 // forward lists F(y) = {x : y in R_k(x)} of CSR reverse lists (off, ids):
 // cnt, cur n words of scratch, f_off n + 1, f_ids off[n]
 hipError_t launch_select_forward(int64_t n, const int64_t* off, const int32_t* ids, int32_t* cnt,
                                  int32_t* cur, int64_t* f_off, int32_t* f_ids, int64_t* scan_tmp,
                                  hipStream_t st);
-// `rounds` rounds over the reverse lists (off, ids) and the forward lists
-// (f_ids with CSR offsets f_off, or f_off NULL: fixed stride fk, -1 padded)
-hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* ids,
-                                const int32_t* f_ids, const int64_t* f_off, int fk,
-                                unsigned char* cov, unsigned char* lose, int32_t* gain,
-                                unsigned long long* best, int32_t* pivot_of, int64_t* ctl,
-                                const int64_t* longv, int64_t nlong, int rounds, hipStream_t st);
+// `rounds` rounds over the active vertices act[0, nact) (NULL: all n), the
+// reverse lists (off, ids) and the forward lists (f_ids with CSR offsets
+// f_off, or f_off NULL: fixed stride fk, -1 padded); items: a round's chunk
+// items, at least n + off[n] / 16 + 1 entries
+hipError_t launch_select_rounds(int64_t n, const int32_t* act, int64_t nact, const int64_t* off,
+                                const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
+                                int fk, unsigned char* cov, unsigned char* lose, int32_t* gain,
+                                int32_t* pivot_of, int64_t* items, int64_t* ctl, int rounds,
+                                hipStream_t st);
+// the still uncovered active vertices into act_out, their count into ctl[4]
+hipError_t launch_select_compact(const int32_t* act, int64_t nact, const unsigned char* cov,
+                                 int32_t* act_out, int64_t* ctl, hipStream_t st);
 // static device scratch of the allocation-free search (bytes per device) and
 // its address on the current device (looked up once per device)
 constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;

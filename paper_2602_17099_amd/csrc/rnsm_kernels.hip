@@ -1990,13 +1990,17 @@ __global__ __launch_bounds__(BFS_T) void k_bfs_level(const int32_t* padj, int rp
                                                      int32_t* order, unsigned* vis, unsigned* ctl) {
     const int64_t s = ctl[1], e = ctl[2];
     const int64_t total = (e - s) * rp;
+    const bool narrow = total <= 0xffffffffll;  // 32-bit division (block-uniform)
     for (int64_t b0 = (int64_t)blockIdx.x * BFS_T; b0 < total; b0 += (int64_t)gridDim.x * BFS_T) {
         const int64_t t = b0 + threadIdx.x;
         bool found = false;
         int32_t w = -1;
         if (t < total) {
-            const int32_t u = order[s + t / rp];
-            w = padj[(int64_t)u * rp + (int)(t % rp)];
+            int64_t q;
+            if (narrow) q = (int64_t)((uint32_t)t / (uint32_t)rp);
+            else q = t / rp;
+            const int32_t u = order[s + q];
+            w = padj[(int64_t)u * rp + (int)(t - q * rp)];
             if (w >= 0 && w < n) {
                 const unsigned bit = 1u << (w & 31);
                 if (!(__atomic_load_n(&vis[w >> 5], __ATOMIC_RELAXED) & bit))
@@ -2605,10 +2609,21 @@ __device__ __forceinline__ unsigned short f32_to_f16_rne(float x) {
 
 // count elements, 4 per thread (src and dst are read / written in 4-element
 // groups where the count allows)
-__global__ void k_convert(const void* src, int st, void* dst, int dt, int64_t count) {
+__global__ void k_convert(const void* src, int st, void* dst, int dt, int64_t count, int vec) {
     const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (t >= count) return;
     const int m = count - t < 4 ? (int)(count - t) : 4;
+    if (vec && m == 4 && st == 0 && dt != 0) {
+        // float32 to 16-bit, aligned: one 16-byte load and one 8-byte store
+        const float4 x = ((const float4*)src)[t >> 2];
+        const bool b = dt == 1;
+        const unsigned a0 = b ? f32_to_bf16_rne(x.x) : f32_to_f16_rne(x.x);
+        const unsigned a1 = b ? f32_to_bf16_rne(x.y) : f32_to_f16_rne(x.y);
+        const unsigned a2 = b ? f32_to_bf16_rne(x.z) : f32_to_f16_rne(x.z);
+        const unsigned a3 = b ? f32_to_bf16_rne(x.w) : f32_to_f16_rne(x.w);
+        ((uint2*)dst)[t >> 2] = make_uint2(a0 | (a1 << 16), a2 | (a3 << 16));
+        return;
+    }
     float v[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -2629,8 +2644,9 @@ hipError_t launch_convert(const void* src, int src_type, void* dst, int dst_type
     if (count <= 0) return hipSuccess;
     const int s = src_type == 0 ? 0 : 1;  // 0: float32, 1: uint8
     const int64_t threads = (count + 3) / 4;
+    const int vec = ((uintptr_t)src & 15) == 0 && ((uintptr_t)dst & 7) == 0;
     hipLaunchKernelGGL(k_convert, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, src, s,
-                       dst, dst_type, count);
+                       dst, dst_type, count, vec);
     return hipGetLastError();
 }
 
@@ -3451,20 +3467,27 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
 //
 // The keys come from gains kept up to date: each newly covered y takes one
 // from the gain of every x whose list holds it, i.e. every x in y's forward
-// list F(y) = {x : y in R_k(x)} (N_k(y) in the merge). A round reads forward
-// lists only (short: k entries in the merge): spread, best[y] = the largest
-// key of y and of the uncovered x in F(y); mark, x loses when best[x] is not
-// its key or some uncovered y with x in F(y) has another best; apply, the
-// uncovered non-losers take their uncovered lists (a wavefront per list
-// longer than SEL_LONG), and a last pass takes the newly covered vertices
-// from the gains. ctl[0]: uncovered vertices left (every kernel
-// returns when 0), ctl[1]: pivots, ctl[2]: rounds run with vertices left,
-// ctl[3]: long lists.
+// list F(y) = {x : y in R_k(x)} (N_k(y) in the merge). A round is three
+// kernels over the active vertices (those uncovered when the host last
+// checked): best, each uncovered y finds the largest key of y and of the
+// uncovered x in F(y) and marks as losers y and those x whose key it is not;
+// pick, each uncovered non-loser becomes a pivot (covered, its gains taken)
+// and appends its list to the round's items in chunks of SEL_CHUNK entries;
+// take, SEL_CHUNK lanes per item cover the chunk's uncovered entries and take
+// them from the gains at once. No two picks share an uncovered follower and
+// none is another's, so every cover byte read in a round is the round's
+// starting one where it matters; the claim on pivot_of (-2 while uncovered)
+// keeps the gains right even for a list that repeats an id.
+// ctl[0]: nonzero until a round picks nothing (every round kernel then
+// returns at once), ctl[1]: pivots, ctl[2]: rounds with picks, ctl[4]: active
+// vertices after a compaction, ctl[5]: the round's items.
 struct SelFwd {
     const int32_t* ids;   // forward lists
     const int64_t* off;   // CSR offsets, or NULL: fixed stride fk, -1 padded
     int fk;
 };
+
+constexpr int SEL_CHUNK = 16;  // list entries per take item (lanes per item)
 
 __device__ __forceinline__ void fwd_range(const SelFwd& f, int64_t y, int64_t& b, int64_t& e) {
     if (f.off) {
@@ -3480,96 +3503,23 @@ __device__ __forceinline__ u64 sel_key(const int32_t* gain, int64_t x) {
     return ((u64)(unsigned)gain[x] << 32) | (u64)(0xffffffffu - (unsigned)x);
 }
 
-__global__ void k_sel_init(int64_t n, const int64_t* rk_off, unsigned char* cov, int32_t* gain,
-                           int32_t* pivot_of, int64_t* ctl) {
+__global__ void k_sel_init(int64_t n, const int64_t* rk_off, unsigned char* cov,
+                           unsigned char* lose, int32_t* gain, int32_t* pivot_of, int64_t* ctl) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x < n) {
         cov[x] = 0;
+        lose[x] = 0;
         gain[x] = (int32_t)(rk_off[x + 1] - rk_off[x]);
         pivot_of[x] = -2;
     }
     if (x == 0) {
-        ctl[0] = n;
+        ctl[0] = 1;
         ctl[1] = 0;
         ctl[2] = 0;
         ctl[3] = 0;
+        ctl[4] = n;
+        ctl[5] = 0;
     }
-}
-
-// Lists longer than SEL_LONG (a hub can be in thousands of k-NN lists) are
-// taken in the apply step by wavefronts, one per SEL_CHUNK entries of the
-// list; the rest by one thread per vertex. The chunks of the long lists are
-// listed once per selection (any order) as (vertex << 32 | chunk).
-constexpr int SEL_LONG = 64;
-constexpr int SEL_CHUNK = 256;
-
-__global__ void k_sel_long(int64_t n, const int64_t* off, int64_t* longv, int64_t* ctl) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
-    const int64_t len = off[x + 1] - off[x];
-    if (len <= SEL_LONG) return;
-    const int64_t nc = (len + SEL_CHUNK - 1) / SEL_CHUNK;
-    const int64_t b = (int64_t)atomicAdd((unsigned long long*)&ctl[3], (unsigned long long)nc);
-    for (int64_t c = 0; c < nc; ++c) longv[b + c] = (x << 32) | c;
-}
-
-__global__ void k_sel_spread(int64_t n, SelFwd f, const unsigned char* cov, const int32_t* gain,
-                             u64* best, unsigned char* lose, int64_t* ctl) {
-    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (y == 0 && ctl[0] != 0) ctl[2] += 1;  // a round with vertices left
-    if (y >= n || ctl[0] == 0 || cov[y]) return;
-    u64 b = sel_key(gain, y);
-    int64_t j0, j1;
-    fwd_range(f, y, j0, j1);
-    for (int64_t j = j0; j < j1; ++j) {
-        const int32_t x = f.ids[j];
-        if (x >= 0 && x < n && !cov[x]) {
-            const u64 k = sel_key(gain, x);
-            b = k > b ? k : b;
-        }
-    }
-    best[y] = b;
-    lose[y] = 0;
-}
-
-__global__ void k_sel_mark(int64_t n, SelFwd f, const unsigned char* cov, const int32_t* gain,
-                           const u64* best, unsigned char* lose, const int64_t* ctl) {
-    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (y >= n || ctl[0] == 0 || cov[y]) return;
-    const u64 by = best[y];
-    if (by != sel_key(gain, y)) lose[y] = 1;
-    int64_t j0, j1;
-    fwd_range(f, y, j0, j1);
-    for (int64_t j = j0; j < j1; ++j) {
-        const int32_t x = f.ids[j];
-        if (x >= 0 && x < n && !cov[x] && by != sel_key(gain, x)) lose[x] = 1;
-    }
-}
-
-// Every apply item: blocks below nblk(n) take one vertex per thread
-// (skipping long lists), the blocks after them one chunk of a long list per
-// wavefront (lane l reads entries l, l + 64, ... of the chunk). x < 0:
-// nothing to do; [j0, j1) the entries; first: the item that owns x's own
-// change (its thread, or the first chunk's lane 0).
-struct SelItem {
-    int64_t x, j0, j1;
-    bool wave, first;
-};
-__device__ __forceinline__ SelItem sel_item(int64_t n, const int64_t* off, const int64_t* longv,
-                                            int64_t nlong) {
-    const int64_t nbs = (n + 255) / 256;
-    if ((int64_t)blockIdx.x < nbs) {
-        const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (x >= n || off[x + 1] - off[x] > SEL_LONG) return {-1, 0, 0, false, false};
-        return {x, off[x], off[x + 1], false, true};
-    }
-    const int64_t w = (((int64_t)blockIdx.x - nbs) * blockDim.x + threadIdx.x) >> 6;
-    if (w >= nlong) return {-1, 0, 0, true, false};
-    const int64_t it = longv[w];
-    const int64_t x = it >> 32, c = it & 0xffffffffll;
-    const int64_t j0 = off[x] + c * SEL_CHUNK;
-    const int64_t j1 = min(off[x + 1], j0 + SEL_CHUNK);
-    return {x, j0 + lane_id(), j1, true, c == 0 && lane_id() == 0};
 }
 
 // a newly covered vertex z: one less gain for every x listing it
@@ -3582,57 +3532,194 @@ __device__ __forceinline__ void sel_uncount(const SelFwd& f, int64_t n, int64_t 
     }
 }
 
-// the picks of the round take themselves and their uncovered followers; no
-// two picks share an uncovered follower and none is another's, so the
-// coverage each reads is the round's starting one where it matters
-__global__ void k_sel_apply(int64_t n, const int64_t* off, const int32_t* ids, SelFwd f,
-                            unsigned char* cov, const unsigned char* lose, int32_t* gain,
-                            int32_t* pivot_of, int64_t* ctl, const int64_t* longv, int64_t nlong) {
-    if (ctl[0] == 0) return;
-    const SelItem it = sel_item(n, off, longv, nlong);
-    const int64_t x = it.x;
-    // a pick's own cov byte is changed only by its owner item, after this
-    // kernel's other items have read it (x is not another pick's follower)
-    const bool pick = x >= 0 && cov[x] != 1 && !lose[x] && (cov[x] == 0 || !it.first);
-    int64_t taken = 0;
-    if (pick) {
-        const int64_t step = it.wave ? WAVE : 1;
-        for (int64_t j = it.j0; j < it.j1; j += step) {
-            const int32_t y = ids[j];
-            if (!cov[y]) {
-                pivot_of[y] = (int32_t)x;
-                cov[y] = 2;  // newly covered: k_sel_uncount takes it from the gains
-                ++taken;
+// best key at y and the losers it makes; a vertex's lose byte is cleared by
+// the pick kernel that reads it, so every set here is for this round. The
+// keys of up to SEL_KREG forward entries stay in registers between the two
+// passes.
+constexpr int SEL_KREG = 8;
+
+__global__ void k_sel_best(int64_t n, const int32_t* __restrict__ act, int64_t nact, SelFwd f,
+                           const unsigned char* __restrict__ cov, const int32_t* __restrict__ gain,
+                           unsigned char* __restrict__ lose, int64_t* ctl) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) ctl[5] = 0;  // the round's item count (the last reader was the previous take)
+    if (i >= nact || ctl[0] == 0) return;
+    const int64_t y = act ? act[i] : i;
+    if (cov[y]) return;
+    const u64 ky = sel_key(gain, y);
+    u64 b = ky;
+    int64_t j0, j1;
+    fwd_range(f, y, j0, j1);
+    if (j1 - j0 <= SEL_KREG) {
+        u64 kx[SEL_KREG];
+#pragma unroll
+        for (int u = 0; u < SEL_KREG; ++u) {
+            kx[u] = 0;  // no key: never the best (a real key is > 0 in its id half)
+            if (j0 + u < j1) {
+                const int32_t x = f.ids[j0 + u];
+                if (x >= 0 && x < n && !cov[x]) kx[u] = sel_key(gain, x);
             }
+            b = kx[u] > b ? kx[u] : b;
+        }
+        if (b != ky) lose[y] = 1;
+#pragma unroll
+        for (int u = 0; u < SEL_KREG; ++u)
+            if (kx[u] != 0 && kx[u] != b) lose[f.ids[j0 + u]] = 1;
+        return;
+    }
+    for (int64_t j = j0; j < j1; ++j) {
+        const int32_t x = f.ids[j];
+        if (x >= 0 && x < n && !cov[x]) {
+            const u64 k = sel_key(gain, x);
+            b = k > b ? k : b;
         }
     }
-    // the wavefront's counts in one atomic each; a long list's pick counts
-    // once (its first chunk's lane 0)
-    const bool owner = pick && it.first;
-    if (owner) {
-        pivot_of[x] = -1;
-        cov[x] = 2;
-        ++taken;
-    }
-    const u64 anyp = __ballot(pick);
-    if (anyp == 0ull) return;
-    const u64 own = __ballot(owner);
-    int64_t t = taken;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
-    if (lane_id() == __ffsll((long long)anyp) - 1) {
-        atomicAdd((unsigned long long*)&ctl[0], (unsigned long long)(-t));
-        atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)__popcll(own));
+    if (b != ky) lose[y] = 1;
+    for (int64_t j = j0; j < j1; ++j) {
+        const int32_t x = f.ids[j];
+        if (x >= 0 && x < n && !cov[x] && sel_key(gain, x) != b) lose[x] = 1;
     }
 }
 
-// the round's newly covered vertices (cov 2), one thread each: one less gain
-// for every vertex listing it, then covered (cov 1)
-__global__ void k_sel_uncount(int64_t n, SelFwd f, unsigned char* cov, int32_t* gain) {
-    const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (z >= n || cov[z] != 2) return;
-    sel_uncount(f, n, z, gain);
-    cov[z] = 1;
+constexpr int SEL_PICK_THREADS = 1024;
+
+// the round's picks: covered, taken from the gains, their lists appended to
+// the items (x << 32 | chunk). The block reserves its items with one atomic
+// and writes them together: item q of the block belongs to the last thread
+// whose first item is at most q (a search over the block's offsets), so a
+// hub's thousands of chunks are not one thread's serial loop.
+__global__ void __launch_bounds__(SEL_PICK_THREADS)
+k_sel_pick(int64_t n, const int32_t* act, int64_t nact, const int64_t* off, SelFwd f,
+           unsigned char* cov, unsigned char* lose, int32_t* gain, int32_t* pivot_of,
+           int64_t* items, int64_t* ctl) {
+    if (ctl[0] == 0) return;  // uniform: nothing writes ctl[0] during this kernel
+    __shared__ int64_t first[SEL_PICK_THREADS];  // block-local offset of each thread's items
+    __shared__ int32_t owner[SEL_PICK_THREADS];
+    __shared__ int64_t wtot[SEL_PICK_THREADS / WAVE];
+    __shared__ int64_t base, total;
+    __shared__ int npk;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    if (tid == 0) npk = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+    int64_t x = -1, nc = 0;
+    bool pick = false;
+    if (i < nact) {
+        x = act ? act[i] : i;
+        if (!cov[x]) {
+            pick = !lose[x];
+            lose[x] = 0;
+        }
+    }
+    if (pick) {
+        pivot_of[x] = -1;
+        cov[x] = 1;
+        sel_uncount(f, n, x, gain);
+        // one item at least: a round's picks make items even when their
+        // lists are empty (a round without items ends the selection)
+        nc = max((int64_t)1, (off[x + 1] - off[x] + SEL_CHUNK - 1) / SEL_CHUNK);
+    }
+    const u64 pm = __ballot(pick);
+    if (lane == 0 && pm) atomicAdd(&npk, __popcll(pm));
+    int64_t inc = nc;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int64_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == WAVE - 1) wtot[w] = inc;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t sum = 0;
+        for (int k = 0; k < SEL_PICK_THREADS / WAVE; ++k) {
+            const int64_t t = wtot[k];
+            wtot[k] = sum;
+            sum += t;
+        }
+        total = sum;
+        base = sum ? (int64_t)atomicAdd((unsigned long long*)&ctl[5], (unsigned long long)sum) : 0;
+        if (npk) atomicAdd((unsigned long long*)&ctl[1], (unsigned long long)npk);
+    }
+    __syncthreads();
+    first[tid] = wtot[w] + inc - nc;
+    owner[tid] = (int32_t)x;
+    __syncthreads();
+    for (int64_t q = tid; q < total; q += SEL_PICK_THREADS) {
+        int lo = 0, hi = SEL_PICK_THREADS - 1;  // last t with first[t] <= q
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        items[base + q] = ((int64_t)owner[lo] << 32) | (q - first[lo]);
+    }
+}
+
+// SEL_CHUNK lanes per item, grid-stride over the round's items; thread 0
+// ends the selection's rounds when the round picked nothing
+__global__ void k_sel_take(int64_t n, const int64_t* off, const int32_t* ids, SelFwd f,
+                           unsigned char* cov, int32_t* gain, int32_t* pivot_of,
+                           const int64_t* items, int64_t* ctl) {
+    const int64_t cnt = ctl[5];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        if (cnt == 0) ctl[0] = 0;
+        else ctl[2] += 1;
+    }
+    const int sub = threadIdx.x & (SEL_CHUNK - 1);
+    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / SEL_CHUNK;
+    for (int64_t w = t / SEL_CHUNK; w < cnt; w += stride) {
+        const int64_t it = items[w];
+        const int64_t x = it >> 32, c = it & 0xffffffffll;
+        const int64_t j = off[x] + c * SEL_CHUNK + sub;
+        if (j >= off[x + 1]) continue;
+        const int32_t y = ids[j];
+        if (cov[y]) continue;
+        if (atomicCAS(&pivot_of[y], -2, (int32_t)x) != -2) continue;
+        cov[y] = 1;
+        sel_uncount(f, n, y, gain);
+    }
+}
+
+// block-wide exclusive offset of v (a multiple of 64 threads, at most 1024)
+// after one atomic reservation of the block's total in *counter; every
+// thread of the block calls it
+__device__ __forceinline__ int64_t sel_block_reserve(int64_t v, int64_t* counter) {
+    __shared__ int64_t wtot[16];
+    __shared__ int64_t base;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    int64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int64_t t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == WAVE - 1) wtot[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t sum = 0;
+        const int nw = (int)(blockDim.x >> 6);
+        for (int k = 0; k < nw; ++k) {
+            const int64_t t = wtot[k];
+            wtot[k] = sum;
+            sum += t;
+        }
+        base = sum ? (int64_t)atomicAdd((unsigned long long*)counter, (unsigned long long)sum) : 0;
+    }
+    __syncthreads();
+    return base + wtot[w] + inc - v;
+}
+
+// after a check batch: the still uncovered active vertices into act_out
+// (ctl[4] counts them; zero at launch)
+__global__ void __launch_bounds__(SEL_PICK_THREADS)
+k_sel_compact(const int32_t* act, int64_t nact, const unsigned char* cov, int32_t* act_out,
+              int64_t* ctl) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t x = i < nact ? (act ? act[i] : i) : -1;
+    const bool keep = x >= 0 && !cov[x];
+    const int64_t at = sel_block_reserve(keep ? 1 : 0, &ctl[4]);
+    if (keep) act_out[at] = (int32_t)x;
 }
 
 // forward lists of reverse lists given as CSR (the caller's R_k): a count per
@@ -3670,12 +3757,11 @@ hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids,
     return hipGetLastError();
 }
 
-hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov, int32_t* gain,
-                              int32_t* pivot_of, int64_t* longv, int64_t* ctl, hipStream_t st) {
+hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov,
+                              unsigned char* lose, int32_t* gain, int32_t* pivot_of, int64_t* ctl,
+                              hipStream_t st) {
     hipLaunchKernelGGL(k_sel_init, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, st, n, off, cov,
-                       gain, pivot_of, ctl);
-    if (n > 0)
-        hipLaunchKernelGGL(k_sel_long, dim3(nblk(n, 256)), dim3(256), 0, st, n, off, longv, ctl);
+                       lose, gain, pivot_of, ctl);
     return hipGetLastError();
 }
 
@@ -3693,21 +3779,32 @@ hipError_t launch_select_forward(int64_t n, const int64_t* off, const int32_t* i
     return hipGetLastError();
 }
 
-hipError_t launch_select_rounds(int64_t n, const int64_t* off, const int32_t* ids,
-                                const int32_t* f_ids, const int64_t* f_off, int fk,
-                                unsigned char* cov, unsigned char* lose, int32_t* gain, u64* best,
-                                int32_t* pivot_of, int64_t* ctl, const int64_t* longv,
-                                int64_t nlong, int rounds, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
+hipError_t launch_select_rounds(int64_t n, const int32_t* act, int64_t nact, const int64_t* off,
+                                const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
+                                int fk, unsigned char* cov, unsigned char* lose, int32_t* gain,
+                                int32_t* pivot_of, int64_t* items, int64_t* ctl, int rounds,
+                                hipStream_t st) {
+    if (n <= 0 || nact <= 0) return hipSuccess;
     const SelFwd f = {f_ids, f_off, fk};
-    const dim3 gv(nblk(n, 256)), ga(nblk(n, 256) + nblk(nlong * WAVE, 256)), b(256);
+    const dim3 gb(nblk(nact, 256)), gp(nblk(nact, SEL_PICK_THREADS)), b(256), bp(SEL_PICK_THREADS);
+    // take: SEL_CHUNK lanes per item, at most 16 items in flight per active vertex
+    const int64_t tb = std::min<int64_t>(std::max<int64_t>(nblk(nact * SEL_CHUNK, 256), 1), 1024);
     for (int r = 0; r < rounds; ++r) {
-        hipLaunchKernelGGL(k_sel_spread, gv, b, 0, st, n, f, cov, gain, best, lose, ctl);
-        hipLaunchKernelGGL(k_sel_mark, gv, b, 0, st, n, f, cov, gain, best, lose, ctl);
-        hipLaunchKernelGGL(k_sel_apply, ga, b, 0, st, n, off, ids, f, cov, lose, gain, pivot_of,
-                           ctl, longv, nlong);
-        hipLaunchKernelGGL(k_sel_uncount, gv, b, 0, st, n, f, cov, gain);
+        hipLaunchKernelGGL(k_sel_best, gb, b, 0, st, n, act, nact, f, cov, gain, lose, ctl);
+        hipLaunchKernelGGL(k_sel_pick, gp, bp, 0, st, n, act, nact, off, f, cov, lose, gain,
+                           pivot_of, items, ctl);
+        hipLaunchKernelGGL(k_sel_take, dim3(tb), b, 0, st, n, off, ids, f, cov, gain, pivot_of,
+                           items, ctl);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_select_compact(const int32_t* act, int64_t nact, const unsigned char* cov,
+                                 int32_t* act_out, int64_t* ctl, hipStream_t st) {
+    hipError_t e = launch_zero(ctl + 4, sizeof(int64_t), st);
+    if (e != hipSuccess || nact <= 0) return e;
+    hipLaunchKernelGGL(k_sel_compact, dim3(nblk(nact, SEL_PICK_THREADS)), dim3(SEL_PICK_THREADS), 0,
+                       st, act, nact, cov, act_out, ctl);
     return hipGetLastError();
 }
 
