@@ -523,6 +523,8 @@ static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off
     // still uncovered only
     const int32_t* act = nullptr;
     int64_t nact = n;
+    int64_t tail_max = SELECT_TAIL_MAX;
+    if (const char* c = getenv("RNSM_SELECT_TAIL")) tail_max = atoll(c);
     for (int64_t done = 0; done <= n + batch; done += batch) {
         HIPCHK(launch_select_rounds(n, act, nact, off, ids, f_ids, f_off, fk, cov, lose, gain,
                                     pivot_of, items, ctl, batch, st));
@@ -539,6 +541,20 @@ static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off
             return fail(RNSM_EINTERNAL, "pivot selection: inconsistent active counts");
         act = act_next;
         nact = h_ctl[4];
+        if (nact <= tail_max) {
+            // the last rounds in one workgroup: no launch per round
+            HIPCHK(launch_select_tail(n, act, nact, off, ids, f_ids, f_off, fk, cov, lose, gain,
+                                      pivot_of, items, ctl, st));
+            int32_t* act_fin = act == act_a ? act_b : act_a;
+            HIPCHK(launch_select_compact(act, nact, cov, act_fin, ctl, st));
+            HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (h_ctl[4] != 0)
+                return fail(RNSM_EINTERNAL, "pivot selection: vertices left after the last rounds");
+            *n_pivots = h_ctl[1];
+            if (rounds) *rounds = h_ctl[2];
+            return RNSM_OK;
+        }
     }
     return fail(RNSM_EINTERNAL, "pivot selection did not cover every vertex");
 }
@@ -580,8 +596,10 @@ static rnsm_status rnsm_select_pivots_device_impl(int64_t n, const int64_t* rk_o
     WS(f_ids, "sel_fids", sizeof(int32_t) * std::max<int64_t>(nnz, 1));
     WS(stmp, "sel_scan", sizeof(int64_t) * scan_tmp_elems(n));
     HIPCHK(launch_select_forward(n, rk_offsets, rk_ids, fcnt, fcur, f_off, f_ids, stmp, st));
+    int batch = 8;
+    if (const char* c = getenv("RNSM_SELECT_BATCH")) batch = std::max(1, atoi(c));
     return select_on_device(ws, n, rk_offsets, rk_ids, nnz, f_ids, f_off, 0, pivot_of, st,
-                            out_n_pivots);
+                            out_n_pivots, batch);
 }
 
 static rnsm_status tune_shape_locked(const rnsm_graph* g, const rnsm_vectors* base,

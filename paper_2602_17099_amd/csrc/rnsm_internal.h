@@ -194,6 +194,12 @@ hipError_t launch_select_rounds(int64_t n, const int32_t* act, int64_t nact, con
                                 int fk, unsigned char* cov, unsigned char* lose, int32_t* gain,
                                 int32_t* pivot_of, int64_t* items, int64_t* ctl, int rounds,
                                 hipStream_t st);
+// the remaining rounds over act[0, nact) in one workgroup (few vertices left)
+hipError_t launch_select_tail(int64_t n, const int32_t* act, int64_t nact, const int64_t* off,
+                              const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
+                              int fk, unsigned char* cov, unsigned char* lose, int32_t* gain,
+                              int32_t* pivot_of, int64_t* items, int64_t* ctl, hipStream_t st);
+constexpr int64_t SELECT_TAIL_MAX = 8192;  // active vertices for the one-workgroup tail
 // the still uncovered active vertices into act_out, their count into ctl[4]
 hipError_t launch_select_compact(const int32_t* act, int64_t nact, const unsigned char* cov,
                                  int32_t* act_out, int64_t* ctl, hipStream_t st);

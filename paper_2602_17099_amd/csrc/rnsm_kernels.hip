@@ -3538,13 +3538,10 @@ __device__ __forceinline__ void sel_uncount(const SelFwd& f, int64_t n, int64_t 
 // passes.
 constexpr int SEL_KREG = 8;
 
-__global__ void k_sel_best(int64_t n, const int32_t* __restrict__ act, int64_t nact, SelFwd f,
-                           const unsigned char* __restrict__ cov, const int32_t* __restrict__ gain,
-                           unsigned char* __restrict__ lose, int64_t* ctl) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) ctl[5] = 0;  // the round's item count (the last reader was the previous take)
-    if (i >= nact || ctl[0] == 0) return;
-    const int64_t y = act ? act[i] : i;
+__device__ __forceinline__ void sel_best_one(int64_t n, int64_t y, const SelFwd& f,
+                                             const unsigned char* __restrict__ cov,
+                                             const int32_t* __restrict__ gain,
+                                             unsigned char* __restrict__ lose) {
     if (cov[y]) return;
     const u64 ky = sel_key(gain, y);
     u64 b = ky;
@@ -3579,6 +3576,15 @@ __global__ void k_sel_best(int64_t n, const int32_t* __restrict__ act, int64_t n
         const int32_t x = f.ids[j];
         if (x >= 0 && x < n && !cov[x] && sel_key(gain, x) != b) lose[x] = 1;
     }
+}
+
+__global__ void k_sel_best(int64_t n, const int32_t* __restrict__ act, int64_t nact, SelFwd f,
+                           const unsigned char* __restrict__ cov, const int32_t* __restrict__ gain,
+                           unsigned char* __restrict__ lose, int64_t* ctl) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) ctl[5] = 0;  // the round's item count (the last reader was the previous take)
+    if (i >= nact || ctl[0] == 0) return;
+    sel_best_one(n, act ? act[i] : i, f, cov, gain, lose);
 }
 
 constexpr int SEL_PICK_THREADS = 1024;
@@ -3655,6 +3661,21 @@ k_sel_pick(int64_t n, const int32_t* act, int64_t nact, const int64_t* off, SelF
     }
 }
 
+// entry `sub` of a take item: an uncovered follower joins the item's pick
+__device__ __forceinline__ void sel_take_one(int64_t n, int64_t it, int sub, const int64_t* off,
+                                             const int32_t* ids, const SelFwd& f,
+                                             unsigned char* cov, int32_t* gain,
+                                             int32_t* pivot_of) {
+    const int64_t x = it >> 32, c = it & 0xffffffffll;
+    const int64_t j = off[x] + c * SEL_CHUNK + sub;
+    if (j >= off[x + 1]) return;
+    const int32_t y = ids[j];
+    if (cov[y]) return;
+    if (atomicCAS(&pivot_of[y], -2, (int32_t)x) != -2) return;
+    cov[y] = 1;
+    sel_uncount(f, n, y, gain);
+}
+
 // SEL_CHUNK lanes per item, grid-stride over the round's items; thread 0
 // ends the selection's rounds when the round picked nothing
 __global__ void k_sel_take(int64_t n, const int64_t* off, const int32_t* ids, SelFwd f,
@@ -3668,17 +3689,8 @@ __global__ void k_sel_take(int64_t n, const int64_t* off, const int32_t* ids, Se
     }
     const int sub = threadIdx.x & (SEL_CHUNK - 1);
     const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / SEL_CHUNK;
-    for (int64_t w = t / SEL_CHUNK; w < cnt; w += stride) {
-        const int64_t it = items[w];
-        const int64_t x = it >> 32, c = it & 0xffffffffll;
-        const int64_t j = off[x] + c * SEL_CHUNK + sub;
-        if (j >= off[x + 1]) continue;
-        const int32_t y = ids[j];
-        if (cov[y]) continue;
-        if (atomicCAS(&pivot_of[y], -2, (int32_t)x) != -2) continue;
-        cov[y] = 1;
-        sel_uncount(f, n, y, gain);
-    }
+    for (int64_t w = t / SEL_CHUNK; w < cnt; w += stride)
+        sel_take_one(n, items[w], sub, off, ids, f, cov, gain, pivot_of);
 }
 
 // block-wide exclusive offset of v (a multiple of 64 threads, at most 1024)
@@ -3720,6 +3732,54 @@ k_sel_compact(const int32_t* act, int64_t nact, const unsigned char* cov, int32_
     const bool keep = x >= 0 && !cov[x];
     const int64_t at = sel_block_reserve(keep ? 1 : 0, &ctl[4]);
     if (keep) act_out[at] = (int32_t)x;
+}
+
+// The last rounds in one workgroup, once few vertices are left: the same
+// three steps per round over act[0, nact), separated by workgroup barriers
+// (the group's waves share one L1, so its global writes are visible to the
+// group after a barrier), until a round picks nothing; every round with an
+// uncovered vertex picks one, so at most nact + 1 rounds run.
+__global__ void __launch_bounds__(SEL_PICK_THREADS)
+k_sel_tail(int64_t n, const int32_t* act, int64_t nact, const int64_t* off, const int32_t* ids,
+           SelFwd f, unsigned char* cov, unsigned char* lose, int32_t* gain, int32_t* pivot_of,
+           int64_t* items, int64_t* ctl) {
+    __shared__ unsigned long long nitems;
+    __shared__ int npk;
+    const int tid = threadIdx.x;
+    for (int64_t r = 0; r <= nact; ++r) {
+        for (int64_t i = tid; i < nact; i += SEL_PICK_THREADS)
+            sel_best_one(n, act[i], f, cov, gain, lose);
+        if (tid == 0) {
+            nitems = 0;
+            npk = 0;
+        }
+        __syncthreads();
+        for (int64_t i = tid; i < nact; i += SEL_PICK_THREADS) {
+            const int64_t x = act[i];
+            if (cov[x]) continue;
+            const bool pick = !lose[x];
+            lose[x] = 0;
+            if (!pick) continue;
+            pivot_of[x] = -1;
+            cov[x] = 1;
+            sel_uncount(f, n, x, gain);
+            const int64_t nc = max((int64_t)1, (off[x + 1] - off[x] + SEL_CHUNK - 1) / SEL_CHUNK);
+            const int64_t at = (int64_t)atomicAdd(&nitems, (unsigned long long)nc);
+            for (int64_t c = 0; c < nc; ++c) items[at + c] = (x << 32) | c;
+            atomicAdd(&npk, 1);
+        }
+        __syncthreads();
+        const int64_t cnt = (int64_t)nitems;
+        if (cnt == 0) break;  // uniform
+        if (tid == 0) {
+            ctl[1] += npk;
+            ctl[2] += 1;
+        }
+        for (int64_t w = tid / SEL_CHUNK; w < cnt; w += SEL_PICK_THREADS / SEL_CHUNK)
+            sel_take_one(n, items[w], tid & (SEL_CHUNK - 1), off, ids, f, cov, gain, pivot_of);
+        __syncthreads();  // nitems and npk are reset by the next round
+    }
+    if (tid == 0) ctl[0] = 0;
 }
 
 // forward lists of reverse lists given as CSR (the caller's R_k): a count per
@@ -3796,6 +3856,17 @@ hipError_t launch_select_rounds(int64_t n, const int32_t* act, int64_t nact, con
         hipLaunchKernelGGL(k_sel_take, dim3(tb), b, 0, st, n, off, ids, f, cov, gain, pivot_of,
                            items, ctl);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_select_tail(int64_t n, const int32_t* act, int64_t nact, const int64_t* off,
+                              const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
+                              int fk, unsigned char* cov, unsigned char* lose, int32_t* gain,
+                              int32_t* pivot_of, int64_t* items, int64_t* ctl, hipStream_t st) {
+    if (n <= 0 || nact <= 0 || !act) return hipSuccess;
+    const SelFwd f = {f_ids, f_off, fk};
+    hipLaunchKernelGGL(k_sel_tail, dim3(1), dim3(SEL_PICK_THREADS), 0, st, n, act, nact, off, ids, f,
+                       cov, lose, gain, pivot_of, items, ctl);
     return hipGetLastError();
 }
 

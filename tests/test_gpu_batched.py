@@ -59,6 +59,28 @@ def test_device_pivot_selection_equals_greedy(dev, orc, pkg, n, k, skew, seed):
     assert np.array_equal(got.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("batch,tail", [(1, 0), (1, 1 << 30), (3, 8192), (16, 0)])
+def test_device_pivot_selection_rounds_and_tail(dev, orc, pkg, monkeypatch, batch, tail):
+    # many rounds (a skewed list-length mix): rounds checked after every
+    # `batch`, the last ones in one workgroup once at most `tail` vertices
+    # are uncovered (0: never; 1 << 30: from the first check on)
+    monkeypatch.setenv("RNSM_SELECT_BATCH", str(batch))
+    monkeypatch.setenv("RNSM_SELECT_TAIL", str(tail))
+    n, k = 20000, 5
+    g = np.random.default_rng(7)
+    p = 1.0 / np.arange(1, n + 1) ** 1.1
+    cand = g.choice(n, size=(n, 4 * k), p=p / p.sum())
+    nk = np.full((n, k), -1, np.int32)
+    for v in range(n):
+        row = [int(u) for u in dict.fromkeys(cand[v].tolist()) if u != v][:k]
+        nk[v, :len(row)] = row
+    off, ids = orc.invert(nk)
+    ref, order = orc.pivots(off, ids)
+    got, npv = pkg.select_pivots_device(_t(off, dev), _t(ids, dev))
+    assert npv == len(order)
+    assert np.array_equal(got.cpu().numpy(), ref)
+
+
 def test_device_pivot_selection_on_expansion_lists(dev, orc, pkg):
     # the reverse lists of a real neighbour expansion (Algorithm 2, phase 1)
     X = inputs.mixture_u8(6000, 32, comps=16, seed=1701)
