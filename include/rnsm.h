@@ -328,8 +328,9 @@ rnsm_status rnsm_select_pivots(int64_t n, const int64_t* rk_offsets, const int32
  * rk_offsets device [n+1] int64, rk_ids device int32 (as rnsm_select_pivots,
  * repeats not allowed); pivot_of device [n] int32 output: -1 for a pivot,
  * else the follower's pivot; *out_n_pivots (host) the pivot count.
- * Synchronises `stream`. RNSM_EINVAL for NULL pointers, n out of range, or
- * an id out of range or naming its own list's vertex.
+ * Synchronises `stream`. RNSM_EINVAL for NULL pointers, n out of range
+ * (0 <= n < 2^30: a gain word also carries the vertex's coverage), or an id
+ * out of range or naming its own list's vertex.
  */
 rnsm_status rnsm_select_pivots_device(int64_t n, const int64_t* rk_offsets, const int32_t* rk_ids,
                                       int32_t* pivot_of, int64_t* out_n_pivots, void* stream);

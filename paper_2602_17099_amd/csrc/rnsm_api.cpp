@@ -503,10 +503,11 @@ static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off
                                     const int32_t* ids, int64_t nnz_bound, const int32_t* f_ids,
                                     const int64_t* f_off, int fk, int32_t* pivot_of, hipStream_t st,
                                     int64_t* n_pivots, int batch = 8, int64_t* rounds = nullptr) {
-    unsigned char *cov, *lose;
+    // (a gain word holds coverage too: n < 2^30 keeps it from wrapping)
+    if (n >= (int64_t)1 << 30) return fail(RNSM_EINVAL, "pivot selection: n >= 2^30");
+    unsigned char* lose;
     int32_t* gain;
     int64_t *ctl, *h_ctl;
-    WS(cov, "sel_cov", n);
     WS(lose, "sel_lose", n);
     WS(gain, "sel_gain", sizeof(int32_t) * n);
     WS(ctl, "sel_ctl", sizeof(int64_t) * 8);
@@ -517,7 +518,7 @@ static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off
     // a round's items: every pick's list in chunks of 16 entries
     int64_t* items;
     WS(items, "sel_items", sizeof(int64_t) * (n + nnz_bound / 16 + 1));
-    HIPCHK(launch_select_init(n, off, cov, lose, gain, pivot_of, ctl, st));
+    HIPCHK(launch_select_init(n, off, lose, gain, pivot_of, ctl, st));
     // every round with uncovered vertices picks at least the one with the
     // largest key; after each check batch the rounds run over the vertices
     // still uncovered only
@@ -526,10 +527,10 @@ static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off
     int64_t tail_max = SELECT_TAIL_MAX;
     if (const char* c = getenv("RNSM_SELECT_TAIL")) tail_max = atoll(c);
     for (int64_t done = 0; done <= n + batch; done += batch) {
-        HIPCHK(launch_select_rounds(n, act, nact, off, ids, f_ids, f_off, fk, cov, lose, gain,
-                                    pivot_of, items, ctl, batch, st));
+        HIPCHK(launch_select_rounds(n, act, nact, off, ids, f_ids, f_off, fk, lose, gain, pivot_of,
+                                    items, ctl, batch, st));
         int32_t* act_next = act == act_a ? act_b : act_a;
-        HIPCHK(launch_select_compact(act, nact, cov, act_next, ctl, st));
+        HIPCHK(launch_select_compact(act, nact, gain, act_next, ctl, st));
         HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (h_ctl[4] == 0) {
@@ -543,10 +544,10 @@ static rnsm_status select_on_device(Workspace& ws, int64_t n, const int64_t* off
         nact = h_ctl[4];
         if (nact <= tail_max) {
             // the last rounds in one workgroup: no launch per round
-            HIPCHK(launch_select_tail(n, act, nact, off, ids, f_ids, f_off, fk, cov, lose, gain,
-                                      pivot_of, items, ctl, st));
+            HIPCHK(launch_select_tail(n, act, nact, off, ids, f_ids, f_off, fk, lose, gain, pivot_of,
+                                      items, ctl, st));
             int32_t* act_fin = act == act_a ? act_b : act_a;
-            HIPCHK(launch_select_compact(act, nact, cov, act_fin, ctl, st));
+            HIPCHK(launch_select_compact(act, nact, gain, act_fin, ctl, st));
             HIPCHK(hipMemcpyAsync(h_ctl, ctl, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             if (h_ctl[4] != 0)
@@ -563,8 +564,8 @@ static rnsm_status rnsm_select_pivots_device_impl(int64_t n, const int64_t* rk_o
                                                   const int32_t* rk_ids, int32_t* pivot_of,
                                                   int64_t* out_n_pivots, void* stream) {
     g_err.clear();
-    if (n < 0 || n > INT32_MAX)
-        return fail(RNSM_EINVAL, "rnsm_select_pivots_device: n out of range");
+    if (n < 0 || n >= ((int64_t)1 << 30))
+        return fail(RNSM_EINVAL, "rnsm_select_pivots_device: n out of range (0 <= n < 2^30)");
     if (!out_n_pivots || (n > 0 && (!rk_offsets || !rk_ids || !pivot_of)))
         return fail(RNSM_EINVAL, "rnsm_select_pivots_device: NULL pointer");
     *out_n_pivots = 0;
@@ -877,6 +878,16 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
         if (!per_source) {
             HS(h_bfs, "h_bfs_order", sizeof(int32_t) * ns);
             HIPCHK(hipMemcpyAsync(h_bfs, bfs_order, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, strm));
+        } else {
+            // the batched form keeps the order on the device: checked there
+            // (the host reads the flag at the round's first synchronisation)
+            int32_t* pcnt;
+            int *pflag, *h_pflag;
+            WS(pcnt, "bt_perm_cnt", sizeof(int32_t) * std::max<int64_t>(ns, 1));
+            WS(pflag, "bt_perm_flag", sizeof(int) * m);
+            HS(h_pflag, "h_bt_perm_flag", sizeof(int) * m);
+            HIPCHK(launch_perm_check(bfs_order, ns, pcnt, pflag + s, strm));
+            HIPCHK(hipMemcpyAsync(h_pflag + s, pflag + s, sizeof(int), hipMemcpyDeviceToHost, strm));
         }
         HIPCHK(E.record(strm, ev_out));
         *order_out = bfs_order;
@@ -1280,6 +1291,13 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
             // the overflow followers, one wavefront each, seeded by their
             // pivot's beam (written by the group search)
             if (ev_novf >= 0) HIPCHK(hipEventSynchronize(E.ev[ev_novf]));
+            if (use_bfs && !all_piv) {  // (the round's orders were made before ev_novf)
+                int* h_pflag;
+                HS(h_pflag, "h_bt_perm_flag", sizeof(int) * m);
+                for (int oi : rops)
+                    if (h_pflag[ops[oi].first])
+                        return fail(RNSM_EINTERNAL, "rnsm_merge: breadth-first order is not a permutation");
+            }
             for (size_t q = 0; q < rops.size(); ++q) {
                 const int s = ops[rops[q]].first, t = ops[rops[q]].second;
                 const int64_t novf = h_novf[s];

@@ -177,11 +177,14 @@ hipError_t launch_fill32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 // pivot_of: -1 pivot, else the pivot's id
 hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids, int* flag,
                               hipStream_t st);
-hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov,
-                              unsigned char* lose, int32_t* gain, int32_t* pivot_of, int64_t* ctl,
-                              hipStream_t st);
+hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* lose, int32_t* gain,
+                              int32_t* pivot_of, int64_t* ctl, hipStream_t st);
 // forward lists F(y) = {x : y in R_k(x)} of CSR reverse lists (off, ids):
 // cnt, cur n words of scratch, f_off n + 1, f_ids off[n]
+// flag (device int) set unless order[0, n) is a permutation of 0..n-1 (cnt:
+// n words of scratch)
+hipError_t launch_perm_check(const int32_t* order, int64_t n, int32_t* cnt, int* flag,
+                             hipStream_t st);
 hipError_t launch_select_forward(int64_t n, const int64_t* off, const int32_t* ids, int32_t* cnt,
                                  int32_t* cur, int64_t* f_off, int32_t* f_ids, int64_t* scan_tmp,
                                  hipStream_t st);
@@ -191,17 +194,16 @@ hipError_t launch_select_forward(int64_t n, const int64_t* off, const int32_t* i
 // items, at least n + off[n] / 16 + 1 entries
 hipError_t launch_select_rounds(int64_t n, const int32_t* act, int64_t nact, const int64_t* off,
                                 const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
-                                int fk, unsigned char* cov, unsigned char* lose, int32_t* gain,
-                                int32_t* pivot_of, int64_t* items, int64_t* ctl, int rounds,
-                                hipStream_t st);
+                                int fk, unsigned char* lose, int32_t* gain, int32_t* pivot_of,
+                                int64_t* items, int64_t* ctl, int rounds, hipStream_t st);
 // the remaining rounds over act[0, nact) in one workgroup (few vertices left)
 hipError_t launch_select_tail(int64_t n, const int32_t* act, int64_t nact, const int64_t* off,
                               const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
-                              int fk, unsigned char* cov, unsigned char* lose, int32_t* gain,
-                              int32_t* pivot_of, int64_t* items, int64_t* ctl, hipStream_t st);
+                              int fk, unsigned char* lose, int32_t* gain, int32_t* pivot_of,
+                              int64_t* items, int64_t* ctl, hipStream_t st);
 constexpr int64_t SELECT_TAIL_MAX = 8192;  // active vertices for the one-workgroup tail
 // the still uncovered active vertices into act_out, their count into ctl[4]
-hipError_t launch_select_compact(const int32_t* act, int64_t nact, const unsigned char* cov,
+hipError_t launch_select_compact(const int32_t* act, int64_t nact, const int32_t* gain,
                                  int32_t* act_out, int64_t* ctl, hipStream_t st);
 // static device scratch of the allocation-free search (bytes per device) and
 // its address on the current device (looked up once per device)

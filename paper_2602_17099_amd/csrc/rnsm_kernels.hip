@@ -2794,6 +2794,30 @@ hipError_t launch_bfs_order(const int32_t* padj, int rp, int64_t n, int32_t root
 }
 
 
+// order[0, n) a permutation of 0..n-1: counts per id, then every count one
+__global__ void k_perm_count(const int32_t* order, int64_t n, int32_t* cnt, int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = order[i];
+    if (v < 0 || v >= n) atomicOr(flag, 1);
+    else atomicAdd(&cnt[v], 1);
+}
+
+__global__ void k_perm_check(const int32_t* cnt, int64_t n, int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && cnt[i] != 1) atomicOr(flag, 1);
+}
+
+hipError_t launch_perm_check(const int32_t* order, int64_t n, int32_t* cnt, int* flag,
+                             hipStream_t st) {
+    hipError_t e = launch_zero(flag, sizeof(int), st);
+    if (e != hipSuccess || n <= 0) return e;
+    if ((e = launch_zero(cnt, sizeof(int32_t) * (size_t)n, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_perm_count, dim3(nblk(n, 256)), dim3(256), 0, st, order, n, cnt, flag);
+    hipLaunchKernelGGL(k_perm_check, dim3(nblk(n, 256)), dim3(256), 0, st, cnt, n, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_pad_tail(int32_t* rows, const int32_t* deg, int64_t n, int R, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pad_tail, dim3(nblk(n * R, 256)), dim3(256), 0, st, rows, deg, n, R);
@@ -3467,17 +3491,21 @@ hipError_t launch_entry(const float* X, int64_t n, int dim, int* flag, double* c
 //
 // The keys come from gains kept up to date: each newly covered y takes one
 // from the gain of every x whose list holds it, i.e. every x in y's forward
-// list F(y) = {x : y in R_k(x)} (N_k(y) in the merge). A round is three
-// kernels over the active vertices (those uncovered when the host last
-// checked): best, each uncovered y finds the largest key of y and of the
-// uncovered x in F(y) and marks as losers y and those x whose key it is not;
-// pick, each uncovered non-loser becomes a pivot (covered, its gains taken)
-// and appends its list to the round's items in chunks of SEL_CHUNK entries;
-// take, SEL_CHUNK lanes per item cover the chunk's uncovered entries and take
-// them from the gains at once. No two picks share an uncovered follower and
-// none is another's, so every cover byte read in a round is the round's
-// starting one where it matters; the claim on pivot_of (-2 while uncovered)
-// keeps the gains right even for a list that repeats an id.
+// list F(y) = {x : y in R_k(x)} (N_k(y) in the merge). Coverage lives in the
+// same word: covering a vertex takes SEL_COVER from its gain, so a vertex is
+// covered exactly when its word is negative (an uncovered gain never is, and
+// n < 2^30 keeps a covered one from wrapping), and one load gives both.
+// A round is three kernels over the active vertices (those uncovered when the
+// host last checked): best, each uncovered y finds the largest key of y and
+// of the uncovered x in F(y) and marks as losers y and those x whose key it
+// is not; pick, each uncovered non-loser becomes a pivot (covered, its gains
+// taken) and appends its list to the round's items in chunks of SEL_CHUNK
+// entries; take, SEL_CHUNK lanes per item cover the chunk's uncovered entries
+// and take them from the gains at once. No two picks share an uncovered
+// follower and none is another's, so the coverage read in a round is the
+// round's starting one where it matters (other decrements never change a
+// word's sign); the claim on pivot_of (-2 while uncovered) keeps the gains
+// right even for a list that repeats an id.
 // ctl[0]: nonzero until a round picks nothing (every round kernel then
 // returns at once), ctl[1]: pivots, ctl[2]: rounds with picks, ctl[4]: active
 // vertices after a compaction, ctl[5]: the round's items.
@@ -3487,7 +3515,8 @@ struct SelFwd {
     int fk;
 };
 
-constexpr int SEL_CHUNK = 16;  // list entries per take item (lanes per item)
+constexpr int SEL_CHUNK = 16;           // list entries per take item (lanes per item)
+constexpr int32_t SEL_COVER = 1 << 30;  // taken from a gain word on covering
 
 __device__ __forceinline__ void fwd_range(const SelFwd& f, int64_t y, int64_t& b, int64_t& e) {
     if (f.off) {
@@ -3499,15 +3528,15 @@ __device__ __forceinline__ void fwd_range(const SelFwd& f, int64_t y, int64_t& b
     }
 }
 
-__device__ __forceinline__ u64 sel_key(const int32_t* gain, int64_t x) {
-    return ((u64)(unsigned)gain[x] << 32) | (u64)(0xffffffffu - (unsigned)x);
+// key of an uncovered vertex from its gain word g >= 0
+__device__ __forceinline__ u64 sel_key_of(int32_t g, int64_t x) {
+    return ((u64)(unsigned)g << 32) | (u64)(0xffffffffu - (unsigned)x);
 }
 
-__global__ void k_sel_init(int64_t n, const int64_t* rk_off, unsigned char* cov,
-                           unsigned char* lose, int32_t* gain, int32_t* pivot_of, int64_t* ctl) {
+__global__ void k_sel_init(int64_t n, const int64_t* rk_off, unsigned char* lose, int32_t* gain,
+                           int32_t* pivot_of, int64_t* ctl) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x < n) {
-        cov[x] = 0;
         lose[x] = 0;
         gain[x] = (int32_t)(rk_off[x + 1] - rk_off[x]);
         pivot_of[x] = -2;
@@ -3539,11 +3568,11 @@ __device__ __forceinline__ void sel_uncount(const SelFwd& f, int64_t n, int64_t 
 constexpr int SEL_KREG = 8;
 
 __device__ __forceinline__ void sel_best_one(int64_t n, int64_t y, const SelFwd& f,
-                                             const unsigned char* __restrict__ cov,
                                              const int32_t* __restrict__ gain,
                                              unsigned char* __restrict__ lose) {
-    if (cov[y]) return;
-    const u64 ky = sel_key(gain, y);
+    const int32_t gy = gain[y];
+    if (gy < 0) return;
+    const u64 ky = sel_key_of(gy, y);
     u64 b = ky;
     int64_t j0, j1;
     fwd_range(f, y, j0, j1);
@@ -3554,7 +3583,10 @@ __device__ __forceinline__ void sel_best_one(int64_t n, int64_t y, const SelFwd&
             kx[u] = 0;  // no key: never the best (a real key is > 0 in its id half)
             if (j0 + u < j1) {
                 const int32_t x = f.ids[j0 + u];
-                if (x >= 0 && x < n && !cov[x]) kx[u] = sel_key(gain, x);
+                if (x >= 0 && x < n) {
+                    const int32_t g = gain[x];
+                    if (g >= 0) kx[u] = sel_key_of(g, x);
+                }
             }
             b = kx[u] > b ? kx[u] : b;
         }
@@ -3566,28 +3598,46 @@ __device__ __forceinline__ void sel_best_one(int64_t n, int64_t y, const SelFwd&
     }
     for (int64_t j = j0; j < j1; ++j) {
         const int32_t x = f.ids[j];
-        if (x >= 0 && x < n && !cov[x]) {
-            const u64 k = sel_key(gain, x);
-            b = k > b ? k : b;
+        if (x >= 0 && x < n) {
+            const int32_t g = gain[x];
+            if (g >= 0) {
+                const u64 k = sel_key_of(g, x);
+                b = k > b ? k : b;
+            }
         }
     }
     if (b != ky) lose[y] = 1;
     for (int64_t j = j0; j < j1; ++j) {
         const int32_t x = f.ids[j];
-        if (x >= 0 && x < n && !cov[x] && sel_key(gain, x) != b) lose[x] = 1;
+        if (x >= 0 && x < n) {
+            const int32_t g = gain[x];
+            if (g >= 0 && sel_key_of(g, x) != b) lose[x] = 1;
+        }
     }
 }
 
 __global__ void k_sel_best(int64_t n, const int32_t* __restrict__ act, int64_t nact, SelFwd f,
-                           const unsigned char* __restrict__ cov, const int32_t* __restrict__ gain,
-                           unsigned char* __restrict__ lose, int64_t* ctl) {
+                           const int32_t* __restrict__ gain, unsigned char* __restrict__ lose,
+                           int64_t* ctl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) ctl[5] = 0;  // the round's item count (the last reader was the previous take)
     if (i >= nact || ctl[0] == 0) return;
-    sel_best_one(n, act ? act[i] : i, f, cov, gain, lose);
+    sel_best_one(n, act ? act[i] : i, f, gain, lose);
 }
 
 constexpr int SEL_PICK_THREADS = 1024;
+
+// a pick x (uncovered, no loser): a pivot, covered, its gains taken; returns
+// its item count (one at least: a round's picks make items even when their
+// lists are empty, and a round without items ends the selection)
+__device__ __forceinline__ int64_t sel_pick_one(int64_t n, int64_t x, const int64_t* off,
+                                                const SelFwd& f, int32_t* gain,
+                                                int32_t* pivot_of) {
+    pivot_of[x] = -1;
+    atomicSub(&gain[x], SEL_COVER);
+    sel_uncount(f, n, x, gain);
+    return max((int64_t)1, (off[x + 1] - off[x] + SEL_CHUNK - 1) / SEL_CHUNK);
+}
 
 // the round's picks: covered, taken from the gains, their lists appended to
 // the items (x << 32 | chunk). The block reserves its items with one atomic
@@ -3596,8 +3646,7 @@ constexpr int SEL_PICK_THREADS = 1024;
 // hub's thousands of chunks are not one thread's serial loop.
 __global__ void __launch_bounds__(SEL_PICK_THREADS)
 k_sel_pick(int64_t n, const int32_t* act, int64_t nact, const int64_t* off, SelFwd f,
-           unsigned char* cov, unsigned char* lose, int32_t* gain, int32_t* pivot_of,
-           int64_t* items, int64_t* ctl) {
+           unsigned char* lose, int32_t* gain, int32_t* pivot_of, int64_t* items, int64_t* ctl) {
     if (ctl[0] == 0) return;  // uniform: nothing writes ctl[0] during this kernel
     __shared__ int64_t first[SEL_PICK_THREADS];  // block-local offset of each thread's items
     __shared__ int32_t owner[SEL_PICK_THREADS];
@@ -3612,19 +3661,12 @@ k_sel_pick(int64_t n, const int32_t* act, int64_t nact, const int64_t* off, SelF
     bool pick = false;
     if (i < nact) {
         x = act ? act[i] : i;
-        if (!cov[x]) {
+        if (gain[x] >= 0) {
             pick = !lose[x];
             lose[x] = 0;
         }
     }
-    if (pick) {
-        pivot_of[x] = -1;
-        cov[x] = 1;
-        sel_uncount(f, n, x, gain);
-        // one item at least: a round's picks make items even when their
-        // lists are empty (a round without items ends the selection)
-        nc = max((int64_t)1, (off[x + 1] - off[x] + SEL_CHUNK - 1) / SEL_CHUNK);
-    }
+    if (pick) nc = sel_pick_one(n, x, off, f, gain, pivot_of);
     const u64 pm = __ballot(pick);
     if (lane == 0 && pm) atomicAdd(&npk, __popcll(pm));
     int64_t inc = nc;
@@ -3663,24 +3705,22 @@ k_sel_pick(int64_t n, const int32_t* act, int64_t nact, const int64_t* off, SelF
 
 // entry `sub` of a take item: an uncovered follower joins the item's pick
 __device__ __forceinline__ void sel_take_one(int64_t n, int64_t it, int sub, const int64_t* off,
-                                             const int32_t* ids, const SelFwd& f,
-                                             unsigned char* cov, int32_t* gain,
+                                             const int32_t* ids, const SelFwd& f, int32_t* gain,
                                              int32_t* pivot_of) {
     const int64_t x = it >> 32, c = it & 0xffffffffll;
     const int64_t j = off[x] + c * SEL_CHUNK + sub;
     if (j >= off[x + 1]) return;
     const int32_t y = ids[j];
-    if (cov[y]) return;
+    if (gain[y] < 0) return;
     if (atomicCAS(&pivot_of[y], -2, (int32_t)x) != -2) return;
-    cov[y] = 1;
+    atomicSub(&gain[y], SEL_COVER);
     sel_uncount(f, n, y, gain);
 }
 
 // SEL_CHUNK lanes per item, grid-stride over the round's items; thread 0
 // ends the selection's rounds when the round picked nothing
 __global__ void k_sel_take(int64_t n, const int64_t* off, const int32_t* ids, SelFwd f,
-                           unsigned char* cov, int32_t* gain, int32_t* pivot_of,
-                           const int64_t* items, int64_t* ctl) {
+                           int32_t* gain, int32_t* pivot_of, const int64_t* items, int64_t* ctl) {
     const int64_t cnt = ctl[5];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t == 0) {
@@ -3690,7 +3730,7 @@ __global__ void k_sel_take(int64_t n, const int64_t* off, const int32_t* ids, Se
     const int sub = threadIdx.x & (SEL_CHUNK - 1);
     const int64_t stride = ((int64_t)gridDim.x * blockDim.x) / SEL_CHUNK;
     for (int64_t w = t / SEL_CHUNK; w < cnt; w += stride)
-        sel_take_one(n, items[w], sub, off, ids, f, cov, gain, pivot_of);
+        sel_take_one(n, items[w], sub, off, ids, f, gain, pivot_of);
 }
 
 // block-wide exclusive offset of v (a multiple of 64 threads, at most 1024)
@@ -3725,11 +3765,11 @@ __device__ __forceinline__ int64_t sel_block_reserve(int64_t v, int64_t* counter
 // after a check batch: the still uncovered active vertices into act_out
 // (ctl[4] counts them; zero at launch)
 __global__ void __launch_bounds__(SEL_PICK_THREADS)
-k_sel_compact(const int32_t* act, int64_t nact, const unsigned char* cov, int32_t* act_out,
+k_sel_compact(const int32_t* act, int64_t nact, const int32_t* gain, int32_t* act_out,
               int64_t* ctl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t x = i < nact ? (act ? act[i] : i) : -1;
-    const bool keep = x >= 0 && !cov[x];
+    const bool keep = x >= 0 && gain[x] >= 0;
     const int64_t at = sel_block_reserve(keep ? 1 : 0, &ctl[4]);
     if (keep) act_out[at] = (int32_t)x;
 }
@@ -3741,14 +3781,13 @@ k_sel_compact(const int32_t* act, int64_t nact, const unsigned char* cov, int32_
 // uncovered vertex picks one, so at most nact + 1 rounds run.
 __global__ void __launch_bounds__(SEL_PICK_THREADS)
 k_sel_tail(int64_t n, const int32_t* act, int64_t nact, const int64_t* off, const int32_t* ids,
-           SelFwd f, unsigned char* cov, unsigned char* lose, int32_t* gain, int32_t* pivot_of,
-           int64_t* items, int64_t* ctl) {
+           SelFwd f, unsigned char* lose, int32_t* gain, int32_t* pivot_of, int64_t* items,
+           int64_t* ctl) {
     __shared__ unsigned long long nitems;
     __shared__ int npk;
     const int tid = threadIdx.x;
     for (int64_t r = 0; r <= nact; ++r) {
-        for (int64_t i = tid; i < nact; i += SEL_PICK_THREADS)
-            sel_best_one(n, act[i], f, cov, gain, lose);
+        for (int64_t i = tid; i < nact; i += SEL_PICK_THREADS) sel_best_one(n, act[i], f, gain, lose);
         if (tid == 0) {
             nitems = 0;
             npk = 0;
@@ -3756,14 +3795,11 @@ k_sel_tail(int64_t n, const int32_t* act, int64_t nact, const int64_t* off, cons
         __syncthreads();
         for (int64_t i = tid; i < nact; i += SEL_PICK_THREADS) {
             const int64_t x = act[i];
-            if (cov[x]) continue;
+            if (gain[x] < 0) continue;
             const bool pick = !lose[x];
             lose[x] = 0;
             if (!pick) continue;
-            pivot_of[x] = -1;
-            cov[x] = 1;
-            sel_uncount(f, n, x, gain);
-            const int64_t nc = max((int64_t)1, (off[x + 1] - off[x] + SEL_CHUNK - 1) / SEL_CHUNK);
+            const int64_t nc = sel_pick_one(n, x, off, f, gain, pivot_of);
             const int64_t at = (int64_t)atomicAdd(&nitems, (unsigned long long)nc);
             for (int64_t c = 0; c < nc; ++c) items[at + c] = (x << 32) | c;
             atomicAdd(&npk, 1);
@@ -3776,7 +3812,7 @@ k_sel_tail(int64_t n, const int32_t* act, int64_t nact, const int64_t* off, cons
             ctl[2] += 1;
         }
         for (int64_t w = tid / SEL_CHUNK; w < cnt; w += SEL_PICK_THREADS / SEL_CHUNK)
-            sel_take_one(n, items[w], tid & (SEL_CHUNK - 1), off, ids, f, cov, gain, pivot_of);
+            sel_take_one(n, items[w], tid & (SEL_CHUNK - 1), off, ids, f, gain, pivot_of);
         __syncthreads();  // nitems and npk are reset by the next round
     }
     if (tid == 0) ctl[0] = 0;
@@ -3817,11 +3853,10 @@ hipError_t launch_check_lists(int64_t n, const int64_t* off, const int32_t* ids,
     return hipGetLastError();
 }
 
-hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* cov,
-                              unsigned char* lose, int32_t* gain, int32_t* pivot_of, int64_t* ctl,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(k_sel_init, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, st, n, off, cov,
-                       lose, gain, pivot_of, ctl);
+hipError_t launch_select_init(int64_t n, const int64_t* off, unsigned char* lose, int32_t* gain,
+                              int32_t* pivot_of, int64_t* ctl, hipStream_t st) {
+    hipLaunchKernelGGL(k_sel_init, dim3(nblk(n > 0 ? n : 1, 256)), dim3(256), 0, st, n, off, lose,
+                       gain, pivot_of, ctl);
     return hipGetLastError();
 }
 
@@ -3841,41 +3876,40 @@ hipError_t launch_select_forward(int64_t n, const int64_t* off, const int32_t* i
 
 hipError_t launch_select_rounds(int64_t n, const int32_t* act, int64_t nact, const int64_t* off,
                                 const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
-                                int fk, unsigned char* cov, unsigned char* lose, int32_t* gain,
-                                int32_t* pivot_of, int64_t* items, int64_t* ctl, int rounds,
-                                hipStream_t st) {
+                                int fk, unsigned char* lose, int32_t* gain, int32_t* pivot_of,
+                                int64_t* items, int64_t* ctl, int rounds, hipStream_t st) {
     if (n <= 0 || nact <= 0) return hipSuccess;
     const SelFwd f = {f_ids, f_off, fk};
     const dim3 gb(nblk(nact, 256)), gp(nblk(nact, SEL_PICK_THREADS)), b(256), bp(SEL_PICK_THREADS);
     // take: SEL_CHUNK lanes per item, at most 16 items in flight per active vertex
     const int64_t tb = std::min<int64_t>(std::max<int64_t>(nblk(nact * SEL_CHUNK, 256), 1), 1024);
     for (int r = 0; r < rounds; ++r) {
-        hipLaunchKernelGGL(k_sel_best, gb, b, 0, st, n, act, nact, f, cov, gain, lose, ctl);
-        hipLaunchKernelGGL(k_sel_pick, gp, bp, 0, st, n, act, nact, off, f, cov, lose, gain,
-                           pivot_of, items, ctl);
-        hipLaunchKernelGGL(k_sel_take, dim3(tb), b, 0, st, n, off, ids, f, cov, gain, pivot_of,
+        hipLaunchKernelGGL(k_sel_best, gb, b, 0, st, n, act, nact, f, gain, lose, ctl);
+        hipLaunchKernelGGL(k_sel_pick, gp, bp, 0, st, n, act, nact, off, f, lose, gain, pivot_of,
                            items, ctl);
+        hipLaunchKernelGGL(k_sel_take, dim3(tb), b, 0, st, n, off, ids, f, gain, pivot_of, items,
+                           ctl);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_select_tail(int64_t n, const int32_t* act, int64_t nact, const int64_t* off,
                               const int32_t* ids, const int32_t* f_ids, const int64_t* f_off,
-                              int fk, unsigned char* cov, unsigned char* lose, int32_t* gain,
-                              int32_t* pivot_of, int64_t* items, int64_t* ctl, hipStream_t st) {
+                              int fk, unsigned char* lose, int32_t* gain, int32_t* pivot_of,
+                              int64_t* items, int64_t* ctl, hipStream_t st) {
     if (n <= 0 || nact <= 0 || !act) return hipSuccess;
     const SelFwd f = {f_ids, f_off, fk};
     hipLaunchKernelGGL(k_sel_tail, dim3(1), dim3(SEL_PICK_THREADS), 0, st, n, act, nact, off, ids, f,
-                       cov, lose, gain, pivot_of, items, ctl);
+                       lose, gain, pivot_of, items, ctl);
     return hipGetLastError();
 }
 
-hipError_t launch_select_compact(const int32_t* act, int64_t nact, const unsigned char* cov,
+hipError_t launch_select_compact(const int32_t* act, int64_t nact, const int32_t* gain,
                                  int32_t* act_out, int64_t* ctl, hipStream_t st) {
     hipError_t e = launch_zero(ctl + 4, sizeof(int64_t), st);
     if (e != hipSuccess || nact <= 0) return e;
     hipLaunchKernelGGL(k_sel_compact, dim3(nblk(nact, SEL_PICK_THREADS)), dim3(SEL_PICK_THREADS), 0,
-                       st, act, nact, cov, act_out, ctl);
+                       st, act, nact, gain, act_out, ctl);
     return hipGetLastError();
 }
 
