@@ -1053,6 +1053,9 @@ static rnsm_status rnsm_merge_impl(int32_t m, const rnsm_graph* graphs, const rn
                     rd.err = errf;
                     rd.band = band;
                     rd.rechecks = rechecks;
+                    // two blocks a compute unit: the selection's kernels and
+                    // the group search run beside it
+                    rd.grid_cap = 512;
                     HIPCHK(launch_row_dists(rd, prune_reads_b16(rd, pmode), sd));
                 }
                 if (ev_go >= 0) HIPCHK(E.record(sd, &ev_rd));

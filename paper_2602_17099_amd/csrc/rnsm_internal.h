@@ -79,6 +79,7 @@ struct GroupArgs {
 };
 
 struct PruneArgs {
+    int grid_cap;             // row distances: at most this many blocks (0: one wave a vertex)
     const float* X;           // float32 rows of every vertex (global ids)
     const char* xb;           // bfloat16 copy of X (dim * 2 bytes a row): the MFMA prune in
                               // exact mode (rows exact in bfloat16) reads this one

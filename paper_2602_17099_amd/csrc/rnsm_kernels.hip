@@ -976,34 +976,41 @@ __device__ __forceinline__ int prune_collect(const PruneArgs& a, int64_t p, int6
 // (rows_in / deg_in), written to rows_d where it holds NaN, computed by
 // collect_dists exactly as a later prune of these vertices would compute
 // them (same layout, same arithmetic), so that the prune finds them known.
-// One wavefront per vertex, rows of at most 64 entries.
+// One wavefront per vertex, rows of at most 64 entries; a capped grid
+// (grid_cap) strides over the vertices, leaving the rest of the device to
+// work running beside it.
 template <int CPL, bool B16>
 __global__ __launch_bounds__(256) void k_row_dists(PruneArgs a) {
     __shared__ u64 keys[4][WAVE];
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
-    const int64_t i = xcd_block() * (blockDim.x >> 6) + wib;
-    if (i >= a.n_items) return;
-    const int64_t p = a.item_base + i;
-    const int R = a.R;
-    const int nrow = a.deg_in[p];
-    float* rd = (float*)a.rows_d + p * R;
-    u64* wk = keys[wib];
-    bool todo = false;
-    if (lane < nrow) {
-        const int id = a.rows_in[p * R + lane];
-        todo = rd[lane] != rd[lane] && id >= 0 && id < a.n_total && id != p;
-        wk[lane] = todo ? (u64)(unsigned)id : EMPTY_KEY;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t i = xcd_block() * (blockDim.x >> 6) + wib; i < a.n_items; i += waves) {
+        const int64_t p = a.item_base + i;
+        const int R = a.R;
+        const int nrow = a.deg_in[p];
+        float* rd = (float*)a.rows_d + p * R;
+        u64* wk = keys[wib];
+        bool todo = false;
+        if (lane < nrow) {
+            const int id = a.rows_in[p * R + lane];
+            todo = rd[lane] != rd[lane] && id >= 0 && id < a.n_total && id != p;
+            wk[lane] = todo ? (u64)(unsigned)id : EMPTY_KEY;
+        }
+        if (__ballot(todo) == 0ull) continue;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        collect_dists<CPL, B16>(a, p, wk, nrow, lane);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (todo) rd[lane] = fval((unsigned)(wk[lane] >> 32));
+        // the next vertex's keys reuse wk
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (__ballot(todo) == 0ull) return;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    collect_dists<CPL, B16>(a, p, wk, nrow, lane);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (todo) rd[lane] = fval((unsigned)(wk[lane] >> 32));
 }
 
 // Whether kept w removes candidate v under the rule, from d(p,v), d(p,w),
@@ -3308,7 +3315,9 @@ hipError_t launch_row_dists(const PruneArgs& a, bool b16, hipStream_t st) {
     b.lgG16 = ilog2i(b.G16);
     // the bfloat16 layout takes as many chunks per lane as the float32 one
     if (b16 && (b.G16 < 1 || (a.nch / 2) / b.G16 != a.cpl)) return hipErrorInvalidValue;
-    const dim3 grid(nblk(a.n_items, 4)), block(4 * WAVE);
+    const int64_t nb = nblk(a.n_items, 4);
+    const dim3 grid((unsigned)(a.grid_cap > 0 ? std::min<int64_t>(nb, a.grid_cap) : nb)),
+        block(4 * WAVE);
     switch (a.cpl) {
         case 1: launch_row_dists_c<1>(b, b16, grid, block, st); break;
         case 2: launch_row_dists_c<2>(b, b16, grid, block, st); break;
