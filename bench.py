@@ -38,24 +38,24 @@ COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
     "fp32": {
-        "sources_sha256": "6f20ea4ca54ce02a1b6a0f6d99f856ea638f100f0f182a7141f289b2fe236e6a",
+        "sources_sha256": "16fe945a43bac1962739f0a1c3f0cb67e33ebdd612ed33cb0526c3f1fe1519f6",
         "kernel": "k_beam_search<0, 1, 4, false, 3>",
         "fetch_kib": [
-            28797917.375,
-            29826.125,
-            2489685.188,
-            108371.0,
-            6072374.125,
-            532023.312,
-            14981643.625,
-            1993439.875,
-            19848900.312,
-            18832093.562,
-            18548213.312,
-            11642208.938
+            28664069.938,
+            30047.0,
+            2475055.375,
+            107783.875,
+            5689714.875,
+            530533.438,
+            14858110.875,
+            1981620.688,
+            19817920.75,
+            18795901.438,
+            18420032.375,
+            11638428.75
         ],
         "write_kib": [
-            173846.188,
+            174039.438,
             48.125,
             19571.875,
             193.125,
@@ -70,34 +70,34 @@ SEARCH_COUNTERS = {
         ]
     },
     "bf16": {
-        "sources_sha256": "6f20ea4ca54ce02a1b6a0f6d99f856ea638f100f0f182a7141f289b2fe236e6a",
+        "sources_sha256": "16fe945a43bac1962739f0a1c3f0cb67e33ebdd612ed33cb0526c3f1fe1519f6",
         "kernel": "k_beam_search<1, 1, 4, false, 2>",
         "fetch_kib": [
-            11036055.688,
-            3496.75,
-            184749.688,
-            8335.062,
-            370508.062,
-            20351.312,
-            919289.562,
-            62201.125,
-            1733613.688,
-            108642.875,
-            3032567.438,
-            189421.25,
-            3501458.938,
-            372161.312,
-            4517531.812,
-            834351.875,
-            5217246.125,
-            2640640.812,
-            5470913.5,
-            9307221.938,
-            979381.0,
-            1241965.812
+            11028975.5,
+            3473.562,
+            184231.438,
+            8289.812,
+            352937.5,
+            20495.312,
+            875122.562,
+            62007.375,
+            1842116.0,
+            108491.688,
+            2977753.25,
+            189361.125,
+            3621120.125,
+            372054.75,
+            4528672.125,
+            839051.688,
+            5261917.438,
+            2661829.0,
+            5496366.0,
+            9341974.688,
+            984126.875,
+            1243336.562
         ],
         "write_kib": [
-            159445.719,
+            159562.969,
             8.125,
             4910.625,
             25.0,
