@@ -586,8 +586,13 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
 // XCDs in turn): a wavefront takes the groups of its XCD's range, then those
 // of the other ranges, through one atomic counter per range. Every
 // wavefront ends when all ranges are drained.
+// (16-bit rows: at least 5 resident wavefronts per SIMD, 96 VGPRs and 52
+// bytes a lane spilled, against 4 at the 108 VGPRs it takes unbounded: 7.5
+// against 8.5 ms on 2 x 500,000; the float32 instance and the plain searches
+// measured slower under such bounds)
 template <int TT, int EFS, int CPL, bool EXACT, int LG>
-__global__ __launch_bounds__(256) void k_group_search(GroupArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TT == 0 ? 1 : 5)))
+void k_group_search(GroupArgs g) {
     extern __shared__ int smem[];
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
