@@ -38,24 +38,24 @@ COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
     "fp32": {
-        "sources_sha256": "16fe945a43bac1962739f0a1c3f0cb67e33ebdd612ed33cb0526c3f1fe1519f6",
+        "sources_sha256": "0ad84fefe47e14e0e036bd2417f6b6921b131e8c53b5c6261fe3a6b729183413",
         "kernel": "k_beam_search<0, 1, 4, false, 3>",
         "fetch_kib": [
-            28664069.938,
-            30047.0,
-            2475055.375,
-            107783.875,
-            5689714.875,
-            530533.438,
-            14858110.875,
-            1981620.688,
-            19817920.75,
-            18795901.438,
-            18420032.375,
-            11638428.75
+            28767364.875,
+            30095.312,
+            2599464.875,
+            107496.375,
+            5872935.062,
+            529785.0,
+            14929274.5,
+            1987541.875,
+            19900630.5,
+            18811204.0,
+            18573410.375,
+            11634850.062
         ],
         "write_kib": [
-            174039.438,
+            173903.156,
             48.125,
             19571.875,
             193.125,
@@ -70,34 +70,34 @@ SEARCH_COUNTERS = {
         ]
     },
     "bf16": {
-        "sources_sha256": "16fe945a43bac1962739f0a1c3f0cb67e33ebdd612ed33cb0526c3f1fe1519f6",
+        "sources_sha256": "0ad84fefe47e14e0e036bd2417f6b6921b131e8c53b5c6261fe3a6b729183413",
         "kernel": "k_beam_search<1, 1, 4, false, 2>",
         "fetch_kib": [
-            11028975.5,
-            3473.562,
-            184231.438,
-            8289.812,
-            352937.5,
-            20495.312,
-            875122.562,
-            62007.375,
-            1842116.0,
-            108491.688,
-            2977753.25,
-            189361.125,
-            3621120.125,
-            372054.75,
-            4528672.125,
-            839051.688,
-            5261917.438,
-            2661829.0,
-            5496366.0,
-            9341974.688,
-            984126.875,
-            1243336.562
+            10884681.875,
+            3478.062,
+            189753.25,
+            8250.875,
+            368367.375,
+            20183.812,
+            882360.562,
+            62255.25,
+            1778432.688,
+            110023.25,
+            2946071.188,
+            187636.625,
+            3533631.625,
+            370906.312,
+            4451750.562,
+            836439.75,
+            5231119.188,
+            2643413.375,
+            5435558.188,
+            9308803.062,
+            975919.938,
+            1240697.125
         ],
         "write_kib": [
-            159562.969,
+            159488.875,
             8.125,
             4910.625,
             25.0,
