@@ -586,12 +586,14 @@ __global__ __launch_bounds__(256) void k_beam_search(SearchArgs a) {
 // XCDs in turn): a wavefront takes the groups of its XCD's range, then those
 // of the other ranges, through one atomic counter per range. Every
 // wavefront ends when all ranges are drained.
-// (16-bit rows: at least 5 resident wavefronts per SIMD, 96 VGPRs and 52
-// bytes a lane spilled, against 4 at the 108 VGPRs it takes unbounded: 7.5
-// against 8.5 ms on 2 x 500,000; the float32 instance and the plain searches
-// measured slower under such bounds)
+// One call site of the search for the pivot and its followers, and the
+// wavefront's counts in LDS, keep the registers near the plain search's
+// (float32 rows 103 VGPRs, 4 wavefronts per SIMD; 16-bit rows 87). The
+// 16-bit instance is held to 6 wavefronts per SIMD (80 VGPRs, 36 bytes a lane
+// spilled): 7.0 against 7.5 ms at 5 and 8.5 ms at 4 on 2 x 500,000; a bound
+// of 5 on the float32 instance measured no faster.
 template <int TT, int EFS, int CPL, bool EXACT, int LG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TT == 0 ? 1 : 5)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TT == 0 ? 1 : 6)))
 void k_group_search(GroupArgs g) {
     extern __shared__ int smem[];
     const int lane = lane_id();
@@ -599,7 +601,8 @@ void k_group_search(GroupArgs g) {
     int* tab = smem + (int64_t)wib * search_lds_words(g.hbits);
     int* cl = tab + (1 << g.hbits);
     const int xcd = blockIdx.x & 7;
-    SearchCounts cp, cf;
+    __shared__ u64 wcnt[4][8];  // per wavefront: pivots' counts, followers' counts
+    if (lane < 8) wcnt[wib][lane] = 0;
     for (int r = 0; r < 8; ++r) {
         const int rng = (xcd + r) & 7;
         const int64_t lo = g.n_groups * rng / 8, hi = g.n_groups * (rng + 1) / 8;
@@ -625,20 +628,42 @@ void k_group_search(GroupArgs g) {
             const int64_t f0 = ops[k].fbeg[j];
             const int64_t f1 = min(ops[k].fbeg[j + 1], f0 + g.fmax);
             const int32_t* fol = ops[k].fol;
-            {
-                const SearchArgs a = ops[k].naive;
-                search_one<TT, EFS, CPL, EXACT, LG>(a, p, 0, nullptr, 0, p, tab, cl, lane, cp);
-            }
-            // the pivot's beam, just stored by this wavefront, seeds its
-            // followers: stores complete before those loads
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            const SearchArgs b = ops[k].slide;
-            const int32_t* seeds = b.seed_ids + (int64_t)p * b.seed_stride;
-            for (int64_t f = f0; f < f1; ++f) {
-                const int y = fol[f];
-                search_one<TT, EFS, CPL, EXACT, LG>(b, y, 2, seeds, b.n_seeds, y, tab, cl, lane, cf);
+            // the pivot's naive search, then its followers' slides, through
+            // one call site (one inlined search: fewer live registers)
+            for (int64_t f = f0 - 1; f < f1; ++f) {
+                const bool piv = f < f0;
+                const SearchArgs a = piv ? ops[k].naive : ops[k].slide;
+                const int v = piv ? p : fol[f];
+                const int32_t* seeds = piv ? nullptr : a.seed_ids + (int64_t)p * a.seed_stride;
+                SearchCounts c;
+                search_one<TT, EFS, CPL, EXACT, LG>(a, v, piv ? 0 : 2, seeds, piv ? 0 : a.n_seeds, v,
+                                                    tab, cl, lane, c);
+                // the wavefront's counts wait in LDS (no registers held
+                // across the loop)
+                if (lane == 0) {
+                    u64* w = wcnt[wib] + (piv ? 0 : 4);
+                    w[0] += c.ndc;
+                    w[1] += c.nexp;
+                    w[2] += c.nadj;
+                    w[3] += c.nevict;
+                }
+                // the pivot's beam, just stored by this wavefront, seeds its
+                // followers: stores complete before those loads
+                if (piv) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             }
         }
+    }
+    SearchCounts cp, cf;
+    if (lane == 0) {
+        const u64* w = wcnt[wib];
+        cp.ndc = w[0];
+        cp.nexp = w[1];
+        cp.nadj = w[2];
+        cp.nevict = w[3];
+        cf.ndc = w[4];
+        cf.nexp = w[5];
+        cf.nadj = w[6];
+        cf.nevict = w[7];
     }
     add_counts(g.counters, cp, lane);
     add_counts(g.counters + CNT_SLOTS * CNT_N, cf, lane);
