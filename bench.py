@@ -38,24 +38,24 @@ COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
     "fp32": {
-        "sources_sha256": "0ad84fefe47e14e0e036bd2417f6b6921b131e8c53b5c6261fe3a6b729183413",
+        "sources_sha256": "6c37c02529f38005c734d485c1bb9894a5aa74c9ec2278d604805656982f1acf",
         "kernel": "k_beam_search<0, 1, 4, false, 3>",
         "fetch_kib": [
-            28767364.875,
-            30095.312,
-            2599464.875,
-            107496.375,
-            5872935.062,
-            529785.0,
-            14929274.5,
-            1987541.875,
-            19900630.5,
-            18811204.0,
-            18573410.375,
-            11634850.062
+            28776538.438,
+            30043.688,
+            2508485.562,
+            108393.0,
+            5692748.25,
+            529308.0,
+            14860637.312,
+            1996491.438,
+            19566346.438,
+            18838910.5,
+            18549722.75,
+            11642355.562
         ],
         "write_kib": [
-            173903.156,
+            173853.688,
             48.125,
             19571.875,
             193.125,
@@ -70,34 +70,34 @@ SEARCH_COUNTERS = {
         ]
     },
     "bf16": {
-        "sources_sha256": "0ad84fefe47e14e0e036bd2417f6b6921b131e8c53b5c6261fe3a6b729183413",
+        "sources_sha256": "6c37c02529f38005c734d485c1bb9894a5aa74c9ec2278d604805656982f1acf",
         "kernel": "k_beam_search<1, 1, 4, false, 2>",
         "fetch_kib": [
-            10884681.875,
-            3478.062,
-            189753.25,
-            8250.875,
-            368367.375,
-            20183.812,
-            882360.562,
-            62255.25,
-            1778432.688,
-            110023.25,
-            2946071.188,
-            187636.625,
-            3533631.625,
-            370906.312,
-            4451750.562,
-            836439.75,
-            5231119.188,
-            2643413.375,
-            5435558.188,
-            9308803.062,
-            975919.938,
-            1240697.125
+            10879724.125,
+            3474.812,
+            188223.812,
+            8350.5,
+            342750.125,
+            20535.0,
+            911288.812,
+            61690.5,
+            1762166.375,
+            108809.688,
+            2953419.375,
+            187528.75,
+            3435932.875,
+            369339.25,
+            4421239.0,
+            829196.75,
+            5194934.438,
+            2629667.0,
+            5412754.188,
+            9287170.938,
+            972678.25,
+            1240035.5
         ],
         "write_kib": [
-            159488.875,
+            159249.406,
             8.125,
             4910.625,
             25.0,
