@@ -2047,6 +2047,11 @@ __global__ __launch_bounds__(BFS_T) void k_bfs_level(const int32_t* padj, int rp
         block_append(found, w, order, ctl);
         __syncthreads();  // bbase and wcount are reused by the next stride
     }
+    // every wavefront of the block has read the frontier bounds before the
+    // block counts as finished: a block whose loop ran no stride has had no
+    // barrier yet, and the last block's update of the bounds must not reach
+    // one of its wavefronts that has not started
+    __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         if (atomicAdd(&ctl[3], 1u) == gridDim.x - 1) {
