@@ -38,24 +38,24 @@ COUNTER_SOURCES = ("paper_2602_17099_amd/csrc/rnsm_kernels.hip",
                    "paper_2602_17099_amd/csrc/rnsm_api.cpp")
 SEARCH_COUNTERS = {
     "fp32": {
-        "sources_sha256": "6c37c02529f38005c734d485c1bb9894a5aa74c9ec2278d604805656982f1acf",
+        "sources_sha256": "ebc676544128a85c4cacf5c8e908c9205a352fd442f3a7c8578972837dd48749",
         "kernel": "k_beam_search<0, 1, 4, false, 3>",
         "fetch_kib": [
-            28776538.438,
-            30043.688,
-            2508485.562,
-            108393.0,
-            5692748.25,
-            529308.0,
-            14860637.312,
-            1996491.438,
-            19566346.438,
-            18838910.5,
-            18549722.75,
-            11642355.562
+            28591989.625,
+            30219.625,
+            2466223.5,
+            107478.062,
+            5587405.625,
+            532523.188,
+            14828072.562,
+            1995516.625,
+            19674610.438,
+            18806222.812,
+            18494874.688,
+            11644181.688
         ],
         "write_kib": [
-            173853.688,
+            174074.156,
             48.125,
             19571.875,
             193.125,
@@ -70,34 +70,34 @@ SEARCH_COUNTERS = {
         ]
     },
     "bf16": {
-        "sources_sha256": "6c37c02529f38005c734d485c1bb9894a5aa74c9ec2278d604805656982f1acf",
+        "sources_sha256": "ebc676544128a85c4cacf5c8e908c9205a352fd442f3a7c8578972837dd48749",
         "kernel": "k_beam_search<1, 1, 4, false, 2>",
         "fetch_kib": [
-            10879724.125,
-            3474.812,
-            188223.812,
-            8350.5,
-            342750.125,
-            20535.0,
-            911288.812,
-            61690.5,
-            1762166.375,
-            108809.688,
-            2953419.375,
-            187528.75,
-            3435932.875,
-            369339.25,
-            4421239.0,
-            829196.75,
-            5194934.438,
-            2629667.0,
-            5412754.188,
-            9287170.938,
-            972678.25,
-            1240035.5
+            10822339.812,
+            3457.062,
+            189460.0,
+            8418.188,
+            357927.562,
+            20570.375,
+            907637.875,
+            62804.812,
+            1749403.125,
+            107732.25,
+            2915054.812,
+            188262.625,
+            3539175.188,
+            369166.438,
+            4386432.875,
+            830340.375,
+            5137545.5,
+            2632710.75,
+            5386122.188,
+            9264504.0,
+            977815.562,
+            1240407.125
         ],
         "write_kib": [
-            159249.406,
+            159620.0,
             8.125,
             4910.625,
             25.0,
