@@ -881,6 +881,9 @@ def main():
             vq = args.steps * stq["n_source_vertices"] / dtq
             batched[name] = {"value": vq, "ms_per_step": 1000.0 * dtq / args.steps,
                              "speedup_vs_plain": vq / v_plain,
+                             # against the line's plain float32 form (the same
+                             # graph, so at equal recall@10)
+                             "speedup_vs_plain_fp32": vq / value,
                              "same_graph": bool(torch.equal(resq[0], off) and
                                                 torch.equal(resq[1], nb)),
                              "rounds": stq["n_rounds"],
