@@ -750,7 +750,7 @@ def main():
     if args.one_stream:
         os.environ["RNSM_ONE_STREAM"] = "1"
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
     if args.calib_only:
